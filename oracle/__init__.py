@@ -1,0 +1,301 @@
+"""CPU oracle for the 2D electrostatic PIC cycle (arXiv:1610.03918, Sec. II).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py``, never by the GPU library.  It
+shares no code with the HIP path.  Particle and grid loops are plain C
+(``pic_oracle.c``, built with ``-ffp-contract=off``); the Poisson solve is a
+direct sparse factorisation of the discrete operator (SciPy SuperLU), i.e.
+the exact discrete solution up to rounding.
+
+Functions and the passages they follow:
+  node_cond      Dirichlet nodes from the conductor map        Sec. II, III.A, III.C
+  deposit        area weighting, integer fixed point            (weighting not stated; see readings)
+  assemble       source of eq. (5) plus Dirichlet lifts          eq. (5), Sec. III.D
+  solve_direct   exact solution of the 5-point system           eq. (5)
+  cg             double-precision CG (independent check)       eq. (5)
+  field          E = -grad(phi), central / two-point at walls   Sec. II
+  push_f32/f64   gather + leapfrog + wall test                  eqs. (1)-(4), Sec. III
+  rewind_f32/f64 leapfrog start (half step back)                eqs. (1)-(2)
+  Sim            one step = deposit, solve, field, push          Sec. II ordering (reading Q1)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pic_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part of the oracle (gcc, -O2 -ffp-contract=off)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        P = C.c_void_p
+        i, i64, d = C.c_int, C.c_int64, C.c_double
+        L.or_node_cond.argtypes = [i, i, i, i, P, P, P]
+        L.or_node_cond.restype = i
+        L.or_deposit.argtypes = [i, i, i, i, i64, P, P, P, P]
+        L.or_deposit.restype = None
+        L.or_assemble.argtypes = [i, i, i, i, P, P, P, d, P, i, i, P, d, i, i, P]
+        L.or_assemble.restype = None
+        L.or_cg.argtypes = [i, i, i, i, P, P, P, d, i, P]
+        L.or_cg.restype = i
+        L.or_field.argtypes = [i, i, i, i, P, P, P, P]
+        L.or_field.restype = None
+        for nm in ("or_push_f32", "or_push_f64"):
+            f = getattr(L, nm)
+            f.argtypes = [i, i, i, i, P, i, i, i, d, d, P, P, i64, P, P, P, P, P, P, P]
+            f.restype = i64
+        for nm in ("or_rewind_f32", "or_rewind_f64"):
+            f = getattr(L, nm)
+            f.argtypes = [i, i, i, i, d, d, P, P, i64, P, P, P, P, P]
+            f.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags.c_contiguous
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------------------
+# grid
+# ---------------------------------------------------------------------------
+
+def node_cond(w) -> np.ndarray:
+    """uint8 (NX, NY): 0 free, k > 0 Dirichlet node of conductor k."""
+    out = np.zeros((w.NX, w.NY), np.uint8)
+    cc = _c(w.cell_cond, np.uint8)
+    ec = np.array(w.edge_cond, np.int32)
+    rc = lib().or_node_cond(w.nx, w.ny, int(w.periodic_x), int(w.periodic_y), _p(cc), _p(ec), _p(out))
+    if rc != 0:
+        raise ValueError("two different conductors meet at a node")
+    return out
+
+
+def deposit(w, p: dict, rho: np.ndarray | None = None) -> np.ndarray:
+    """int64 (NX, NY) node charge of one species in units of 2^-32 particle."""
+    if rho is None:
+        rho = np.zeros((w.NX, w.NY), np.int64)
+    cell = _c(p["cell"], np.int32)
+    ox = _c(p["ox"], np.float32)
+    oy = _c(p["oy"], np.float32)
+    lib().or_deposit(w.nx, w.ny, int(w.periodic_x), int(w.periodic_y), cell.size,
+                     _p(cell), _p(ox), _p(oy), _p(rho))
+    return rho
+
+
+def assemble(w, nc, rho_e, rho_i, t: float, surf=None) -> np.ndarray:
+    """float64 (NX, NY) right-hand side; Dirichlet nodes carry V(t).
+    Fully periodic grids get the mean removed (gauge: mean(phi) = 0)."""
+    b = np.zeros((w.NX, w.NY), np.float64)
+    V = w.voltages(t)
+    if surf is None:
+        surf = np.zeros(w.ny, np.int64)
+    lib().or_assemble(w.nx, w.ny, int(w.periodic_x), int(w.periodic_y), _p(_c(nc, np.uint8)),
+                      _p(_c(rho_e, np.int64)), _p(_c(rho_i, np.int64)), float(w.weight), _p(V),
+                      int(w.charge_mode), int(w.charge_row), _p(_c(surf, np.int64)),
+                      float(w.static_density), int(w.static_j_lo), int(w.static_j_hi), _p(b))
+    if w.periodic_x and w.periodic_y:
+        b -= b.mean()
+    return b
+
+
+# ---------------------------------------------------------------------------
+# Poisson (eq. 5): exact discrete solution
+# ---------------------------------------------------------------------------
+
+_fact_cache: dict = {}
+
+
+def operator(w, nc):
+    """Sparse matrix of the 5-point operator 4 phi - sum(neighbours) restricted
+    to the free nodes (Dirichlet neighbours moved to the right-hand side).
+    A fully periodic grid pins node (0, 0) to make the matrix regular."""
+    import scipy.sparse as sp
+    NX, NY = w.NX, w.NY
+    fixed = (nc.reshape(-1) != 0).copy()
+    if w.periodic_x and w.periodic_y:
+        fixed[0] = True
+    free = np.nonzero(~fixed)[0]
+    idx = -np.ones(NX * NY, np.int64)
+    idx[free] = np.arange(free.size)
+    I, J = np.divmod(free, NY)
+    rows = [np.arange(free.size)]
+    cols = [np.arange(free.size)]
+    vals = [np.full(free.size, 4.0)]
+    for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        a, b = I + di, J + dj
+        ok = np.ones(free.size, bool)
+        if w.periodic_x:
+            a = a % NX
+        else:
+            ok &= (a >= 0) & (a < NX)
+        if w.periodic_y:
+            b = b % NY
+        else:
+            ok &= (b >= 0) & (b < NY)
+        nb = np.where(ok, a * NY + np.where(ok, b, 0), 0)
+        k = np.where(ok, idx[nb], -1)
+        m = k >= 0
+        rows.append(np.arange(free.size)[m])
+        cols.append(k[m])
+        vals.append(np.full(m.sum(), -1.0))
+    A = sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(free.size, free.size))
+    return A, free, fixed
+
+
+def solve_direct(w, nc, b) -> np.ndarray:
+    """phi (NX, NY) float64 with A phi = b on free nodes, phi = b on Dirichlet
+    nodes; fully periodic grids return the zero-mean solution."""
+    from scipy.sparse.linalg import splu
+    key = (w.nx, w.ny, w.periodic_x, w.periodic_y, nc.tobytes())
+    if key not in _fact_cache:
+        A, free, fixed = operator(w, nc)
+        _fact_cache.clear()
+        _fact_cache[key] = (splu(A, permc_spec="COLAMD"), free, fixed)
+    lu, free, fixed = _fact_cache[key]
+    bf = b.reshape(-1)
+    phi = np.zeros(w.NX * w.NY, np.float64)
+    phi[nc.reshape(-1) != 0] = bf[nc.reshape(-1) != 0]
+    phi[free] = lu.solve(bf[free])
+    if w.periodic_x and w.periodic_y:
+        phi -= phi.mean()
+    return phi.reshape(w.NX, w.NY)
+
+
+def cg(w, nc, b, phi0=None, rtol=1e-13, maxit=200000):
+    phi = np.zeros((w.NX, w.NY)) if phi0 is None else np.array(phi0, np.float64, copy=True)
+    rr = np.zeros(1)
+    it = lib().or_cg(w.NX, w.NY, int(w.periodic_x), int(w.periodic_y), _p(_c(nc, np.uint8)),
+                     _p(_c(b, np.float64)), _p(phi), float(rtol), int(maxit), _p(rr))
+    return phi, it, float(rr[0])
+
+
+def residual(w, nc, b, phi) -> float:
+    """Relative residual ||b - A phi|| / ||b|| over the free nodes, double."""
+    A, free, fixed = operator(w, nc)
+    bf = b.reshape(-1)[free]
+    r = bf - A @ phi.reshape(-1)[free]
+    nb = np.linalg.norm(bf)
+    return float(np.linalg.norm(r) / (nb if nb > 0 else 1.0))
+
+
+def field(w, nc, phi):
+    Ex = np.zeros((w.NX, w.NY))
+    Ey = np.zeros((w.NX, w.NY))
+    lib().or_field(w.NX, w.NY, int(w.periodic_x), int(w.periodic_y), _p(_c(nc, np.uint8)),
+                   _p(_c(phi, np.float64)), _p(Ex), _p(Ey))
+    return Ex, Ey
+
+
+# ---------------------------------------------------------------------------
+# particles
+# ---------------------------------------------------------------------------
+
+def _state(p: dict, dt):
+    return {"cell": _c(p["cell"], np.int32).copy(),
+            **{k: _c(p[k], dt).copy() for k in ("ox", "oy", "vx", "vy")}}
+
+
+def push(w, s: int, p: dict, Ex, Ey, precision="f32", tally=None, surf=None) -> int:
+    """In-place push of species s.  precision 'f32' needs float32 state,
+    'f64' float64 state.  Returns the number of particles removed."""
+    sp = w.species[s]
+    f = lib().or_push_f32 if precision == "f32" else lib().or_push_f64
+    dt = np.float32 if precision == "f32" else np.float64
+    for k in ("ox", "oy", "vx", "vy"):
+        assert p[k].dtype == dt and p[k].flags.c_contiguous
+    if tally is None:
+        tally = np.zeros(9, np.int64)
+    surf_p = _p(surf) if surf is not None else None
+    return f(w.nx, w.ny, int(w.periodic_x), int(w.periodic_y), _p(_c(w.cell_cond, np.uint8)),
+             int(w.box_i_top), int(w.box_j_lo), int(w.box_j_hi), float(w.dt), float(sp.alpha),
+             _p(_c(Ex, np.float64)), _p(_c(Ey, np.float64)), p["cell"].size, _p(p["cell"]),
+             _p(p["ox"]), _p(p["oy"]), _p(p["vx"]), _p(p["vy"]), _p(tally), surf_p)
+
+
+def rewind(w, s: int, p: dict, Ex, Ey, precision="f32"):
+    sp = w.species[s]
+    f = lib().or_rewind_f32 if precision == "f32" else lib().or_rewind_f64
+    f(w.nx, w.ny, int(w.periodic_x), int(w.periodic_y), float(w.dt), float(sp.alpha),
+      _p(_c(Ex, np.float64)), _p(_c(Ey, np.float64)), p["cell"].size, _p(p["cell"]),
+      _p(p["ox"]), _p(p["oy"]), _p(p["vx"]), _p(p["vy"]))
+
+
+class Sim:
+    """Full cycle, one step (reading of the ordering in Sec. II):
+    deposit x^n -> assemble at t^n -> exact solve -> field -> push both
+    species (v^{n-1/2} -> v^{n+1/2}, x^n -> x^{n+1}) with wall tests.
+    ``start()`` performs the half step back of the velocities."""
+
+    def __init__(self, w, particles: list, precision="f32"):
+        self.w = w
+        self.prec = precision
+        dt = np.float32 if precision == "f32" else np.float64
+        self.p = [_state(q, dt) for q in particles]
+        self.nc = node_cond(w)
+        self.step_index = 0
+        self.tally = np.zeros((len(self.p), 9), np.int64)
+        self.surf = np.zeros(w.ny, np.int64)
+        self.phi = None
+        self.b = None
+        self.rho = None
+
+    @property
+    def t(self):
+        return self.step_index * self.w.dt
+
+    def deposit_assemble(self):
+        w = self.w
+        self.rho = [deposit(w, q) for q in self.p]
+        surf = self.surf if w.charge_mode == 2 else None
+        self.b = assemble(w, self.nc, self.rho[0], self.rho[1], self.t, surf)
+        return self.b
+
+    def solve(self):
+        self.phi = solve_direct(self.w, self.nc, self.b)
+        return self.phi
+
+    def start(self):
+        self.deposit_assemble()
+        self.solve()
+        Ex, Ey = field(self.w, self.nc, self.phi)
+        for s, q in enumerate(self.p):
+            rewind(self.w, s, q, Ex, Ey, self.prec)
+
+    def step(self):
+        w = self.w
+        self.deposit_assemble()
+        self.solve()
+        Ex, Ey = field(w, self.nc, self.phi)
+        for s, q in enumerate(self.p):
+            surf = self.surf if (w.charge_mode == 2 and w.species[s].sign > 0) else None
+            push(w, s, q, Ex, Ey, self.prec, self.tally[s], surf)
+        self.step_index += 1
+
+    def alive(self, s):
+        return int(np.count_nonzero(self.p[s]["cell"] >= 0))
