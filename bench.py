@@ -1,0 +1,147 @@
+"""Throughput of the PIC hot path on one MI355X.
+
+One step = solve (from the previous potential) + field + gather/push/wall
+test + deposit of the new positions + assembly (+ re-binning when due),
+over both species of the trench workload.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                  [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PARTICLE_STEP = 40      # 20 B read + 20 B written per particle (cell, ox, oy, vx, vy)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import synth
+    if name == "trench1024x512":
+        return synth.trench()
+    if name == "bounded256":
+        return synth.bounded_square()
+    if name == "periodic64":
+        return synth.periodic_square()
+    if name.startswith("trench_small"):
+        return synth.trench(nx=256, ny=128, width=8, depth=32, ppc=64)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, parts):
+    """The oracle as it stands, one full step of the same workload on the
+    host (single thread; the sparse LU factorisation happens in start())."""
+    import oracle
+    t0 = time.perf_counter()
+    sim = oracle.Sim(w, parts)
+    sim.start()
+    t1 = time.perf_counter()
+    n = sum(sim.alive(s) for s in range(2))
+    t2 = time.perf_counter()
+    sim.step()
+    t3 = time.perf_counter()
+    rate = n / (t3 - t2)
+    log(f"oracle: start {t1 - t0:.1f}s, one step {t3 - t2:.2f}s for {n} particles")
+    return {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full step of {w.name} ({n} particles, {w.nx}x{w.ny} cells) "
+                      f"after the oracle's start (sparse LU factorisation excluded), "
+                      f"{t3 - t2:.1f} s of CPU time"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="trench1024x512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sort", default="8,64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1610_03918_amd import Pic
+
+    w = workload(args.workload)
+    t = time.perf_counter()
+    parts = synth.load(w)
+    n0 = [p["cell"].size for p in parts]
+    log(f"loaded {n0} particles in {time.perf_counter() - t:.1f}s")
+    sort = tuple(int(x) for x in args.sort.split(","))
+    pic = Pic(w, parts, device="cuda:0", sort_interval=sort)
+    info0 = pic.start()
+    log(f"start solve: {info0}")
+    for _ in range(args.warmup):
+        pic.pic_step(1)
+    torch.cuda.synchronize()
+    d0 = pic.pic_diagnostics()
+    pic.pic_set_timing(True)
+    solve_t = 0.0
+    iters = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        info = pic.pic_solve(1)
+        solve_t += time.perf_counter() - a
+        iters += info["iterations"]
+        pic.pic_push()
+        torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d1 = pic.pic_diagnostics()
+    push_ms, _, launches = pic.pic_push_timing()
+    elapsed = t1 - t0
+    alive0, alive1 = sum(d0["alive"]), sum(d1["alive"])
+    particle_steps = 0.5 * (alive0 + alive1) * args.steps
+    value = particle_steps / elapsed
+    per_launch = 0.25 * (alive0 + alive1)          # mean particles of one species per launch
+    achieved = per_launch * BYTES_PER_PARTICLE_STEP / (push_ms * 1e-3) / 1e9
+    out = {
+        "metric": "particle-steps/s (push+deposit+solve)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cells": [w.nx, w.ny], "ppc": w.species[0].ppc,
+                   "particles": n0, "dt": w.dt, "rtol": w.rtol, "sort_interval": list(sort)},
+        "poisson_ms_per_step": 1e3 * solve_t / args.steps,
+        "poisson_iters_per_step": iters / args.steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_push<true>", "avg_launch_ms": push_ms, "launches": launches,
+                     "bytes_per_launch": per_launch * BYTES_PER_PARTICLE_STEP},
+    }
+    pic.close()
+    del pic
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, parts)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

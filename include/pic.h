@@ -1,0 +1,204 @@
+/*
+ * pic.h - C ABI of the MI355X (gfx950) 2D electrostatic particle-in-cell
+ * library for the trench geometry of Lin & Nishimura (arXiv:1610.03918).
+ *
+ * One step of the method (Sec. II, eqs. 1-5):
+ *   deposit   area-weighted charge of electrons and one ion species (int64
+ *             fixed point, 2^32 units per particle, exact and order-free)
+ *   solve     eq. (5), -lap(phi) = n_i - n_e on a 5-point grid, with the
+ *             grounded plate, the RF plate V = amp*sin(omega*t) (Sec. III.B)
+ *             and the trench conductor (Sec. III.C) as Dirichlet nodes
+ *   field     E = -grad(phi), central inside, two-point at walls (Sec. II)
+ *   push      leapfrog of eqs. (1)-(4), absorption at walls and conductors,
+ *             hit classification, ion charge build-up on the trench bottom
+ *             (Sec. III.D)
+ *
+ * Units are the paper's normalised ones: length lambda_e (mesh spacing 1),
+ * time 1/omega_e, potential T_e/e, density n_0, velocity lambda_e*omega_e.
+ *
+ * Layout (all arrays row-major in x, the plate-normal axis):
+ *   cells  nx * ny, cell (i, j) at i*ny + j
+ *   nodes  NX * NY, NX = nx (periodic x) or nx + 1, NY likewise; node (i, j)
+ *          at i*NY + j; cell (i, j) spans nodes i..i+1, j..j+1 (wrapping)
+ *   particles, one structure-of-arrays per species and per storage set:
+ *          cell int32 = (i << 16) | j, negative once removed (-1 - class);
+ *          ox, oy float32 in-cell offsets in [0, 1); vx, vy float32
+ *
+ * Ownership: the caller allocates every device buffer (particles, charge,
+ * potential, right-hand side and one workspace block whose size
+ * pic_workspace_size reports) and keeps it alive until pic_destroy.  The
+ * library never allocates or frees device memory; it owns only the context.
+ *
+ * Streams: every call is enqueued on the stream given to pic_init and
+ * returns without waiting, except where stated (pic_solve, pic_step and
+ * pic_diagnostics wait for the convergence test / copy-back).
+ *
+ * Errors: every call returns a pic_status; on failure pic_last_error gives
+ * a message.  No exception or abort crosses this boundary.  A context is not
+ * thread safe.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_ERR_ARG = -1,            /* invalid configuration or argument */
+    PIC_ERR_HIP = -3,            /* a HIP runtime call failed */
+    PIC_ERR_NOT_CONVERGED = -4,  /* solver hit max_iter; phi still written */
+    PIC_ERR_STATE = -7,          /* call out of order (e.g. step before init) */
+    PIC_ERR_CAPACITY = -8        /* particle count exceeds buffer capacity */
+} pic_status;
+
+#define PIC_MAX_COND 8           /* conductor ids 1..7; 0 = plasma / free */
+#define PIC_NCLASS 9             /* hit classes, see pic_diag */
+
+typedef struct {
+    int32_t nx, ny;              /* cells along x (plate normal) and y */
+    int32_t periodic_x, periodic_y;
+    double dt;                   /* time step (Sec. III.A: 0.1) */
+    const uint8_t *cell_cond;    /* host nx*ny: 0 plasma, k>0 solid conductor k; copied */
+    int32_t edge_cond[4];        /* conductor of the x-low, x-high, y-low, y-high edges (bounded axes) */
+    double v_amp[PIC_MAX_COND];  /* V_k(t) = v_amp[k] * sin(v_omega[k] * t)  (Sec. III.B) */
+    double v_omega[PIC_MAX_COND];
+    double weight;               /* density carried by one particle (1/ppc, n_0 units) */
+    double alpha[2];             /* eqs. (1)-(2): species 0 electrons (-1), 1 ions (m_e/m_i) */
+    int32_t box_i_top, box_j_lo, box_j_hi; /* trench box (cells) for hit classes 4..7 */
+    int32_t charge_mode;         /* 0 none, 1 static extra ion density, 2 accumulate ion bottom hits */
+    int32_t charge_row;          /* node row receiving the build-up charge */
+    double static_density;       /* mode 1: extra n_i on charge_row, static_j_lo..static_j_hi */
+    int32_t static_j_lo, static_j_hi;
+    double rtol;                 /* relative residual ||b - A phi|| / ||b|| of the solve */
+    int32_t max_iter;            /* cap on preconditioned CG iterations per solve */
+    int32_t solver;              /* 0 multigrid-preconditioned CG, 1 plain CG */
+    int32_t sort_interval[2];    /* steps between re-binnings per species (0 = at init only) */
+    int32_t tile_x, tile_y;      /* particle tile in cells (powers of two; 0 = 16) */
+    int32_t halo;                /* cells of drift a tile absorbs before a global fallback (0 = 4) */
+    int32_t chunk;               /* particles per thread block (0 = 8192) */
+    int64_t hitlog_capacity;     /* ring of wall-hit records in the workspace (0 = none) */
+    int32_t hitlog_species_mask; /* bit s logs species s */
+} pic_config;
+
+typedef struct {
+    int64_t capacity;            /* slots in each storage set */
+    int64_t count;               /* particles loaded in set 0 at pic_init */
+    int32_t *cell[2];            /* device, two storage sets (re-binning ping-pong) */
+    float *ox[2], *oy[2], *vx[2], *vy[2];
+} pic_species_buffers;
+
+typedef struct {
+    pic_species_buffers sp[2];   /* 0 electrons, 1 ions */
+    int64_t *rho[2];             /* device NX*NY per species: charge of the current positions */
+    double *phi;                 /* device NX*NY potential (float64) */
+    double *b;                   /* device NX*NY right-hand side; Dirichlet nodes hold V(t) */
+    void *workspace;             /* device, pic_workspace_size bytes, 256-byte aligned */
+    size_t workspace_bytes;
+} pic_buffers;
+
+typedef struct {
+    int32_t iterations;          /* preconditioned CG iterations (one V-cycle each) */
+    int32_t outer;               /* float64 refinement passes */
+    int32_t converged;
+    int32_t pad;
+    double relres0;              /* relative residual of the start */
+    double relres;               /* final relative residual (float64) */
+} pic_solve_info;
+
+typedef struct {
+    int64_t step;                /* completed pushes */
+    double t;                    /* step * dt */
+    int64_t alive[2];            /* particles per species */
+    int64_t loaded[2];
+    int64_t charge[2];           /* sum of rho over all nodes (2^-32 particle units / 2^32) */
+    int64_t tally[2][PIC_NCLASS];/* removals: class = direction (0 +x, 1 -x, 2 +y, 3 -y)
+                                    + 4 inside the trench box; 8 = non-finite/runaway */
+    int64_t surf_hits;           /* ions absorbed by the trench bottom (charge mode 2 sum) */
+    int64_t hits_logged;         /* records written to the hit ring (total) */
+    int64_t deposit_fallbacks;   /* particles deposited outside their tile window */
+    pic_solve_info last_solve;
+} pic_diag;
+
+typedef struct {
+    int32_t species_class;       /* species << 8 | class */
+    int32_t cell;                /* packed code of the last cell occupied */
+    float vx, vy;                /* velocity at the hit */
+    int32_t step;                /* step index of the push */
+    int32_t pad;
+} pic_hit;
+
+/* Bytes of device workspace a configuration needs for the given per-species
+ * particle capacities.  Pure host computation; validates the configuration.
+ * capacity: host int64[2]. */
+pic_status pic_workspace_size(const pic_config *cfg, const int64_t *capacity, size_t *bytes);
+
+/* Validates the configuration, derives the Dirichlet node map from the cell
+ * conductor map (Sec. II boundary conditions), builds the multigrid
+ * hierarchy, bins the loaded particles of set 0 into tiles and deposits
+ * them (state: t = 0, rho and b valid, phi Dirichlet nodes set).  The
+ * caller must have copied particles into set 0 of each species and zeroed
+ * nothing else.  stream: a hipStream_t (NULL = default stream). */
+pic_status pic_init(const pic_config *cfg, const pic_buffers *buf, void *stream, pic_ctx **out);
+
+/* Re-deposits every live particle (area weighting) into rho and assembles b
+ * at the current time (eq. 5 source plus Dirichlet lifts and build-up
+ * charge).  Idempotent; needed only after particles were changed outside. */
+pic_status pic_deposit(pic_ctx *ctx);
+
+/* Solves eq. (5) for phi from b.  guess_kind 0: start from zero on the free
+ * nodes; 1: from the current phi (previous step); 2: from the device float64
+ * array guess (NX*NY, free nodes used).  Waits for the stream.  info may be
+ * NULL.  Returns PIC_ERR_NOT_CONVERGED (phi written) at max_iter. */
+pic_status pic_solve(pic_ctx *ctx, int32_t guess_kind, const double *guess, pic_solve_info *info);
+
+/* Leapfrog start: v <- v - (alpha dt / 2) E(x) with E from the current phi
+ * (velocities become v^{-1/2}).  Call once after the first pic_solve. */
+pic_status pic_rewind(pic_ctx *ctx);
+
+/* One push of both species with the field of the current phi (eqs. 1-4),
+ * wall/conductor absorption and classification, deposit of the new
+ * positions, t += dt, assembly of b at the new time, and re-binning when the
+ * species' sort interval is due. */
+pic_status pic_push(pic_ctx *ctx);
+
+/* nsteps x (pic_solve from the previous phi; pic_push).  Stops at the first
+ * failing solve and returns its status. */
+pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
+
+/* Waits for the stream and copies counters to the host. */
+pic_status pic_diagnostics(pic_ctx *ctx, pic_diag *out);
+
+/* Which storage set (0/1) currently holds species s and how many slots of it
+ * are in use (live particles first after a re-binning).  Waits. */
+pic_status pic_particles(pic_ctx *ctx, int32_t species, int32_t *set, int64_t *slots);
+
+/* Copies up to max of the most recent wall-hit records (oldest first) into
+ * host memory out; *n receives the number copied.  Waits. */
+pic_status pic_read_hits(pic_ctx *ctx, pic_hit *out, int64_t max, int64_t *n);
+
+/* Re-bins species s now (tile sort; drops removed particles). */
+pic_status pic_sort(pic_ctx *ctx, int32_t species);
+
+/* Average device time per launch of the push kernel over the pushes since
+ * the last call, measured with HIP events on the library stream (ms), and
+ * the number of particles it processed per launch.  Resets the counters. */
+pic_status pic_push_timing(pic_ctx *ctx, double *avg_ms, double *avg_particles, int32_t *launches);
+
+/* Enables or disables HIP event timing of the push kernels (default off). */
+pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
+
+void pic_destroy(pic_ctx *ctx);
+const char *pic_last_error(const pic_ctx *ctx);
+const char *pic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -1,0 +1,1146 @@
+// gfx950 kernels of the 2D electrostatic PIC step (arXiv:1610.03918, Sec. II).
+//
+// Grid kernels work on the node grid (NX x NY, row-major in x) with 64x4
+// thread blocks; floating-point reductions are float64, summed per block in
+// a fixed tree and finished by the last block to arrive in block order, so
+// every result is reproducible bit for bit.  The particle kernel processes
+// one tile of cells per block, accumulating the area-weighting moments of
+// its particles in LDS as integers and flushing them to the int64 node
+// charge with atomics (exact, order-free).
+//
+// Compiled with -ffp-contract=off: every float operation of the push is
+// rounded in the order written.
+#include "pic_internal.h"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int wrap_lo(int a, int n) { return a < 0 ? a + n : a; }
+__device__ __forceinline__ int wrap_hi(int a, int n) { return a >= n ? a - n : a; }
+
+__device__ __forceinline__ void store_agent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sums NQ per-thread values over the whole grid.  Every block writes its
+// partial; the last block to arrive adds the partials in block order and
+// returns true (totals in tot[] of thread 0).  Deterministic.
+template <int NQ>
+__device__ bool grid_reduce(const double (&val)[NQ], double (&tot)[NQ], const Red &red)
+{
+    __shared__ double sh[NQ][16];
+    __shared__ int last;
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nt = blockDim.x * blockDim.y;
+    const int lane = tid & 63, wid = tid >> 6, nw = (nt + 63) >> 6;
+    const int bid = blockIdx.x + blockIdx.y * gridDim.x;
+    const int nb = gridDim.x * gridDim.y;
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        double v = wave_sum(val[q]);
+        if (lane == 0) sh[q][wid] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            double s = 0.0;
+            for (int w = 0; w < nw; w++) s += sh[q][w];
+            store_agent(&red.part[q * red.stride + bid], s);
+        }
+        __threadfence();
+        unsigned prev = atomicAdd(red.count, 1u);
+        last = (prev == (unsigned)(nb - 1));
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        double s = 0.0;
+        for (int k = tid; k < nb; k += nt) s += load_agent(&red.part[q * red.stride + k]);
+        s = wave_sum(s);
+        __syncthreads();
+        if (lane == 0) sh[q][wid] = s;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < nw; w++) t += sh[q][w];
+            tot[q] = t;
+        }
+    }
+    if (tid == 0) *red.count = 0u;
+    return true;
+}
+
+#define GRID_IDX                                                     \
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;             \
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;             \
+    const bool inb = (i < NX) && (j < NY);                           \
+    const long long n = (long long)i * NY + j;
+
+static inline dim3 grid_of(int NX, int NY)
+{
+    return dim3((NY + kGridBX - 1) / kGridBX, (NX + kGridBY - 1) / kGridBY);
+}
+static inline dim3 gblock() { return dim3(kGridBX, kGridBY); }
+
+__global__ void k_zero_u64(unsigned long long *p, long long n)
+{
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; k < n; k += st) p[k] = 0ull;
+}
+
+void launch_zero_u64(unsigned long long *p, long long n, hipStream_t s)
+{
+    if (n <= 0) return;
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)nb), dim3(256), 0, s, p, n);
+}
+
+// ---------------------------------------------------------------------------
+// field: E = -grad(phi) at the four corners of every cell (Sec. II)
+// ---------------------------------------------------------------------------
+
+// One axis of -grad(phi) at a node.  Inside: central difference.  At a
+// Dirichlet node: two-point difference toward the only free neighbour if
+// exactly one neighbour is free; central if both neighbours exist (zero along
+// an equipotential wall); two-point with the only neighbour at a domain edge.
+__device__ __forceinline__ double axis_field(double pm, double pc, double pp, bool hm, bool hp,
+                                             bool fm, bool fp, bool fixed)
+{
+    if (!fixed) return -(pp - pm) * 0.5;
+    if (hm && hp) {
+        if (fp && !fm) return -(pp - pc);
+        if (fm && !fp) return -(pc - pm);
+        return -(pp - pm) * 0.5;
+    }
+    if (hp) return -(pp - pc);
+    if (hm) return -(pc - pm);
+    return 0.0;
+}
+
+__device__ __forceinline__ float2 node_field(const Geom g, const uint8_t *nc, const double *phi,
+                                             int i, int j)
+{
+    const int NX = g.NX, NY = g.NY;
+    const long long n = (long long)i * NY + j;
+    const bool fixed = nc[n] != 0;
+    const double pc = phi[n];
+    bool hm = g.px || i > 0, hp = g.px || i < NX - 1;
+    int im = g.px ? wrap_lo(i - 1, NX) : i - 1, ip = g.px ? wrap_hi(i + 1, NX) : i + 1;
+    double pm = hm ? phi[(long long)im * NY + j] : 0.0;
+    double pp = hp ? phi[(long long)ip * NY + j] : 0.0;
+    bool fm = hm && nc[(long long)im * NY + j] == 0;
+    bool fp = hp && nc[(long long)ip * NY + j] == 0;
+    double ex = axis_field(pm, pc, pp, hm, hp, fm, fp, fixed);
+    bool gm = g.py || j > 0, gp = g.py || j < NY - 1;
+    int jm = g.py ? wrap_lo(j - 1, NY) : j - 1, jp = g.py ? wrap_hi(j + 1, NY) : j + 1;
+    double qm = gm ? phi[(long long)i * NY + jm] : 0.0;
+    double qp = gp ? phi[(long long)i * NY + jp] : 0.0;
+    bool em = gm && nc[(long long)i * NY + jm] == 0;
+    bool ep = gp && nc[(long long)i * NY + jp] == 0;
+    double ey = axis_field(qm, pc, qp, gm, gp, em, ep, fixed);
+    return make_float2((float)ex, (float)ey);
+}
+
+// One thread per cell; writes the cell's four corner fields (float32) and,
+// when requested, clears both species' node charge for the coming deposit.
+__global__ void k_field(Geom g, const uint8_t *nc, const double *phi, float4 *E4,
+                        unsigned long long *rho0, unsigned long long *rho1)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (rho0 && i < g.NX && j < g.NY) {
+        long long n = (long long)i * g.NY + j;
+        rho0[n] = 0ull;
+        rho1[n] = 0ull;
+    }
+    if (i >= g.nx || j >= g.ny) return;
+    const int i1 = g.px ? wrap_hi(i + 1, g.nx) : i + 1;
+    const int j1 = g.py ? wrap_hi(j + 1, g.ny) : j + 1;
+    float2 e00 = node_field(g, nc, phi, i, j);
+    float2 e10 = node_field(g, nc, phi, i1, j);
+    float2 e01 = node_field(g, nc, phi, i, j1);
+    float2 e11 = node_field(g, nc, phi, i1, j1);
+    long long c = (long long)i * g.ny + j;
+    E4[2 * c] = make_float4(e00.x, e00.y, e10.x, e10.y);
+    E4[2 * c + 1] = make_float4(e01.x, e01.y, e11.x, e11.y);
+}
+
+void launch_field(const Geom &g, const uint8_t *nc, const double *phi, float4 *E4,
+                  unsigned long long *rho0, unsigned long long *rho1, hipStream_t s)
+{
+    int rx = g.NX > g.nx ? g.NX : g.nx, ry = g.NY > g.ny ? g.NY : g.ny;
+    hipLaunchKernelGGL(k_field, grid_of(rx, ry), gblock(), 0, s, g, nc, phi, E4, rho0, rho1);
+}
+
+// ---------------------------------------------------------------------------
+// assemble: b = (N_i - N_e) w 2^-32 + Dirichlet lifts (eq. 5, unit spacing)
+// ---------------------------------------------------------------------------
+
+__global__ void k_assemble(Geom g, const uint8_t *nc, const uint8_t *fix0, const long long *re,
+                           const long long *ri, double q, VTab V, int mode, int row,
+                           const unsigned long long *surf, double sden, int sjl, int sjh,
+                           double *b, double *phi, Red red, int want_sum)
+{
+    const int NX = g.NX, NY = g.NY;
+    GRID_IDX
+    double bb = 0.0, sm = 0.0;
+    if (inb) {
+        const int c = nc[n];
+        if (c) {
+            b[n] = V.v[c];
+            phi[n] = V.v[c];
+        } else {
+            long long Ni = ri[n];
+            if (mode == 2 && i == row) {
+                int jl = g.py ? wrap_lo(j - 1, g.ny) : j - 1;
+                if (j < g.ny) Ni += (long long)surf[j] << 31;
+                if (jl >= 0) Ni += (long long)surf[jl] << 31;
+            }
+            double r = (double)(Ni - re[n]) * q;
+            if (mode == 1 && i == row && j >= sjl && j <= sjh) r += sden;
+            int im = g.px ? wrap_lo(i - 1, NX) : i - 1, ip = g.px ? wrap_hi(i + 1, NX) : i + 1;
+            int jm = g.py ? wrap_lo(j - 1, NY) : j - 1, jp = g.py ? wrap_hi(j + 1, NY) : j + 1;
+            int cn;
+            if ((cn = nc[(long long)im * NY + j])) r += V.v[cn];
+            if ((cn = nc[(long long)ip * NY + j])) r += V.v[cn];
+            if ((cn = nc[(long long)i * NY + jm])) r += V.v[cn];
+            if ((cn = nc[(long long)i * NY + jp])) r += V.v[cn];
+            b[n] = r;
+            if (!fix0[n]) bb = r * r;
+            sm = r;
+        }
+    }
+    double v[2] = {bb, sm}, t[2];
+    if (grid_reduce<2>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) {
+        if (!want_sum) red.S[S_BB] = t[0];
+        red.S[S_SUM] = t[1];
+    }
+}
+
+void launch_assemble(const Geom &g, const uint8_t *nc, const uint8_t *fix0, const long long *re,
+                     const long long *ri, double q, const VTab &V, int mode, int row,
+                     const unsigned long long *surf, double sden, int sjl, int sjh, double *b,
+                     double *phi, Red red, hipStream_t s)
+{
+    int want_sum = (g.px && g.py) ? 1 : 0;
+    hipLaunchKernelGGL(k_assemble, grid_of(g.NX, g.NY), gblock(), 0, s, g, nc, fix0, re, ri, q,
+                       V, mode, row, surf, sden, sjl, sjh, b, phi, red, want_sum);
+}
+
+// Fully periodic grid: the source must have zero mean (gauge); subtract it
+// and form ||b||^2 over the unknowns (the pinned node excluded).
+__global__ void k_project_mean(Geom g, const uint8_t *fix0, double *b, Red red)
+{
+    const int NX = g.NX, NY = g.NY;
+    GRID_IDX
+    const double mean = red.S[S_SUM] / ((double)NX * (double)NY);
+    double bb = 0.0;
+    if (inb) {
+        double r = b[n] - mean;
+        b[n] = r;
+        if (!fix0[n]) bb = r * r;
+    }
+    double v[1] = {bb}, t[1];
+    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) red.S[S_BB] = t[0];
+}
+
+void launch_project_mean(const Geom &g, const uint8_t *fix0, double *b, Red red, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_project_mean, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, b, red);
+}
+
+__global__ void k_sum_phi(Geom g, const double *phi, Red red)
+{
+    const int NX = g.NX, NY = g.NY;
+    GRID_IDX
+    double v[1] = {inb ? phi[n] : 0.0}, t[1];
+    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) red.S[S_SUM] = t[0];
+}
+
+__global__ void k_shift_phi(Geom g, double *phi, const double *S)
+{
+    const int NX = g.NX, NY = g.NY;
+    GRID_IDX
+    if (inb) phi[n] -= S[S_SUM] / ((double)NX * (double)NY);
+}
+
+void launch_shift_mean(const Geom &g, double *phi, Red red, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red);
+    hipLaunchKernelGGL(k_shift_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red.S);
+}
+
+__global__ void k_set_guess(Geom g, const uint8_t *fix0, int kind, const double *guess, double *phi)
+{
+    const int NX = g.NX, NY = g.NY;
+    GRID_IDX
+    if (!inb || fix0[n]) return;
+    phi[n] = (kind == 0) ? 0.0 : guess[n];
+}
+
+void launch_set_guess(const Geom &g, const uint8_t *fix0, int kind, const double *guess,
+                      double *phi, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_guess, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, kind, guess,
+                       phi);
+}
+
+// ---------------------------------------------------------------------------
+// float64 outer residual: r = b - A phi on the unknowns, ||r||^2 (float64),
+// r rounded to float32 for the inner preconditioned CG.
+// A = 4 - (sum of free neighbours); fixed neighbours sit in b already.
+// ---------------------------------------------------------------------------
+
+__global__ void k_resid64(Geom g, const uint8_t *fix, const double *b, const double *phi,
+                          float *r32, Red red)
+{
+    const int NX = g.NX, NY = g.NY;
+    GRID_IDX
+    double rr = 0.0;
+    if (inb) {
+        if (fix[n]) {
+            r32[n] = 0.0f;
+        } else {
+            int im = wrap_lo(i - 1, NX), ip = wrap_hi(i + 1, NX);
+            int jm = wrap_lo(j - 1, NY), jp = wrap_hi(j + 1, NY);
+            long long a = (long long)im * NY + j, c = (long long)ip * NY + j;
+            long long d = (long long)i * NY + jm, e = (long long)i * NY + jp;
+            double s = 4.0 * phi[n];
+            if (!fix[a]) s -= phi[a];
+            if (!fix[c]) s -= phi[c];
+            if (!fix[d]) s -= phi[d];
+            if (!fix[e]) s -= phi[e];
+            double r = b[n] - s;
+            r32[n] = (float)r;
+            rr = r * r;
+        }
+    }
+    double v[1] = {rr}, t[1];
+    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) red.S[S_RR64] = t[0];
+}
+
+void launch_resid64(const Geom &g, const uint8_t *fix0, const double *b, const double *phi,
+                    float *r, Red red, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resid64, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, b, phi, r, red);
+}
+
+__global__ void k_phi_update(Geom g, const uint8_t *fix, const float *e, double *phi)
+{
+    const int NX = g.NX, NY = g.NY;
+    GRID_IDX
+    if (inb && !fix[n]) phi[n] += (double)e[n];
+}
+
+void launch_phi_update(const Geom &g, const uint8_t *fix0, const float *e, double *phi,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_phi_update, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, e, phi);
+}
+
+// ---------------------------------------------------------------------------
+// multigrid pieces on any level (generic pointers: global or LDS)
+//   stencil per level: 4u - sum(free neighbours) = g   (h^2 folded into g)
+//   restriction g_c = P^T r (weights 1, 1/2, 1/4), prolongation bilinear P,
+//   red-black Gauss-Seidel: pre red->black, post black->red (symmetric)
+// ---------------------------------------------------------------------------
+
+struct Nb {
+    int im, ip, jm, jp;
+};
+
+__device__ __forceinline__ Nb nbs(int i, int j, int NX, int NY)
+{
+    Nb r;
+    r.im = wrap_lo(i - 1, NX);
+    r.ip = wrap_hi(i + 1, NX);
+    r.jm = wrap_lo(j - 1, NY);
+    r.jp = wrap_hi(j + 1, NY);
+    return r;
+}
+
+// Gauss-Seidel value of a free node from its neighbours.
+__device__ __forceinline__ float gs_value(const float *u, const float *gg, const uint8_t *fix,
+                                          int i, int j, int NX, int NY)
+{
+    Nb b = nbs(i, j, NX, NY);
+    long long a = (long long)b.im * NY + j, c = (long long)b.ip * NY + j;
+    long long d = (long long)i * NY + b.jm, e = (long long)i * NY + b.jp;
+    float s = gg[(long long)i * NY + j];
+    if (!fix[a]) s += u[a];
+    if (!fix[c]) s += u[c];
+    if (!fix[d]) s += u[d];
+    if (!fix[e]) s += u[e];
+    return s * 0.25f;
+}
+
+// Residual g - A u at a free fine node.
+__device__ __forceinline__ float node_resid(const float *u, const float *gg, const uint8_t *fix,
+                                            int i, int j, int NX, int NY)
+{
+    Nb b = nbs(i, j, NX, NY);
+    long long n = (long long)i * NY + j;
+    long long a = (long long)b.im * NY + j, c = (long long)b.ip * NY + j;
+    long long d = (long long)i * NY + b.jm, e = (long long)i * NY + b.jp;
+    float s = 4.0f * u[n];
+    if (!fix[a]) s -= u[a];
+    if (!fix[c]) s -= u[c];
+    if (!fix[d]) s -= u[d];
+    if (!fix[e]) s -= u[e];
+    return gg[n] - s;
+}
+
+// Restricted residual at coarse node (I, J): sum over the 3x3 fine stencil
+// around (2I, 2J) of weight * residual at free fine nodes.
+__device__ __forceinline__ float restrict_node(const float *u, const float *gg, const uint8_t *fix,
+                                               int NX, int NY, int px, int py, int I, int J)
+{
+    float acc = 0.0f;
+#pragma unroll
+    for (int di = -1; di <= 1; di++) {
+#pragma unroll
+        for (int dj = -1; dj <= 1; dj++) {
+            int a = 2 * I + di, c = 2 * J + dj;
+            if (px) a = wrap_hi(wrap_lo(a, NX), NX);
+            else if (a < 0 || a >= NX) continue;
+            if (py) c = wrap_hi(wrap_lo(c, NY), NY);
+            else if (c < 0 || c >= NY) continue;
+            if (fix[(long long)a * NY + c]) continue;
+            float w = (di == 0 ? 1.0f : 0.5f) * (dj == 0 ? 1.0f : 0.5f);
+            acc += w * node_resid(u, gg, fix, a, c, NX, NY);
+        }
+    }
+    return acc;
+}
+
+// Bilinear prolongation of the coarse correction e at a red fine node
+// (both indices even: coincident node; both odd: cell centre).
+__device__ __forceinline__ float prolong_red(const float *e, int NXc, int NYc, int a, int c)
+{
+    int I = a >> 1, J = c >> 1;
+    if (((a | c) & 1) == 0) return e[(long long)I * NYc + J];
+    int I1 = wrap_hi(I + 1, NXc), J1 = wrap_hi(J + 1, NYc);
+    return 0.25f * (e[(long long)I * NYc + J] + e[(long long)I1 * NYc + J] +
+                    e[(long long)I * NYc + J1] + e[(long long)I1 * NYc + J1]);
+}
+
+// Post-smoothing black update after the coarse correction: the red
+// neighbours enter with their correction, black values are overwritten.
+__device__ __forceinline__ float prolong_black_value(const float *u, const float *gg,
+                                                     const uint8_t *fix, const float *e, int NX,
+                                                     int NY, int NXc, int NYc, int i, int j)
+{
+    Nb b = nbs(i, j, NX, NY);
+    int ni[4] = {b.im, b.ip, i, i};
+    int nj[4] = {j, j, b.jm, b.jp};
+    float s = gg[(long long)i * NY + j];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        long long m = (long long)ni[k] * NY + nj[k];
+        if (!fix[m]) s += u[m] + prolong_red(e, NXc, NYc, ni[k], nj[k]);
+    }
+    return s * 0.25f;
+}
+
+// ---------------------------------------------------------------------------
+// preconditioned CG on level 0 (float32 vectors, float64 dot products)
+// ---------------------------------------------------------------------------
+
+// Inner start: e = 0, z = red-from-zero of M r (or z = r/4 when no MG),
+// ||r||^2 -> S_RR0, S_RR; iteration flag reset.
+__global__ void k_init_red0(Geom g, LevelDev L, float *e, double eta2, int mg, Red red)
+{
+    const int NX = L.NX, NY = L.NY;
+    GRID_IDX
+    double rr = 0.0, rz = 0.0;
+    if (inb) {
+        float r = L.g[n];
+        e[n] = 0.0f;
+        float z = 0.0f;
+        if (!L.fix[n]) {
+            rr = (double)r * (double)r;
+            if (!mg || (((i + j) & 1) == 0)) z = r * 0.25f;
+            rz = (double)r * (double)z;
+        }
+        L.u[n] = z;
+    }
+    double v[2] = {rr, rz}, t[2];
+    if (grid_reduce<2>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) {
+        red.S[S_RR0] = t[0];
+        red.S[S_RR] = t[0];
+        red.S[S_ETA2] = eta2;
+        red.F[F_DONE] = (t[0] == 0.0) ? 1 : 0;
+        if (!mg) {
+            red.S[S_RZOLD] = red.S[S_RZ];
+            red.S[S_RZ] = t[1];
+        }
+    }
+}
+
+void launch_init_red0(const Geom &g, const LevelDev &L0, float *e, double eta2, int mg, Red red,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_red0, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, e, eta2, mg,
+                       red);
+}
+
+// p_new = z + beta p_old, q = A p_new, p.q  (beta = rz / rz_old; 0 on the first)
+__global__ void k_pupdate_Ap(Geom g, LevelDev L, const float *p_old, float *p_new, float *q,
+                             int first, Red red)
+{
+    if (red.F[F_DONE]) return;
+    const int NX = L.NX, NY = L.NY;
+    GRID_IDX
+    const float beta = first ? 0.0f : (float)(red.S[S_RZ] / red.S[S_RZOLD]);
+    double pq = 0.0;
+    if (inb) {
+        if (L.fix[n]) {
+            p_new[n] = 0.0f;
+            q[n] = 0.0f;
+        } else {
+            Nb b = nbs(i, j, NX, NY);
+            long long m[4] = {(long long)b.im * NY + j, (long long)b.ip * NY + j,
+                              (long long)i * NY + b.jm, (long long)i * NY + b.jp};
+            float pc = first ? L.u[n] : L.u[n] + beta * p_old[n];
+            float s = 4.0f * pc;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                if (L.fix[m[k]]) continue;
+                float pn = first ? L.u[m[k]] : L.u[m[k]] + beta * p_old[m[k]];
+                s -= pn;
+            }
+            p_new[n] = pc;
+            q[n] = s;
+            pq = (double)pc * (double)s;
+        }
+    }
+    double v[1] = {pq}, t[1];
+    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) red.S[S_PQ] = t[0];
+}
+
+void launch_pupdate_Ap(const Geom &g, const LevelDev &L0, const float *p_old, float *p_new,
+                       float *q, int first, Red red, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pupdate_Ap, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, p_old, p_new,
+                       q, first, red);
+}
+
+// alpha = rz / pq; e += alpha p; r -= alpha q; ||r||^2; z = red-from-zero of
+// M r (or r/4 without MG, with r.z).  Marks the inner solve done when
+// ||r||^2 <= eta^2 ||r0||^2 and counts the iteration.
+__global__ void k_update_red0(Geom g, LevelDev L, const float *p, const float *q, float *e, int mg,
+                              Red red)
+{
+    if (red.F[F_DONE]) return;
+    const int NX = L.NX, NY = L.NY;
+    GRID_IDX
+    const float alpha = (float)(red.S[S_RZ] / red.S[S_PQ]);
+    double rr = 0.0, rz = 0.0;
+    if (inb) {
+        float z = 0.0f;
+        if (!L.fix[n]) {
+            e[n] = e[n] + alpha * p[n];
+            float r = L.g[n] - alpha * q[n];
+            L.g[n] = r;
+            rr = (double)r * (double)r;
+            if (!mg || (((i + j) & 1) == 0)) z = r * 0.25f;
+            rz = (double)r * (double)z;
+        }
+        L.u[n] = z;
+    }
+    double v[2] = {rr, rz}, t[2];
+    if (grid_reduce<2>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) {
+        red.S[S_RR] = t[0];
+        red.F[F_ITER] += 1;
+        if (t[0] <= red.S[S_ETA2] * red.S[S_RR0]) red.F[F_DONE] = 1;
+        if (!mg) {
+            red.S[S_RZOLD] = red.S[S_RZ];
+            red.S[S_RZ] = t[1];
+        }
+    }
+}
+
+void launch_update_red0(const Geom &g, const LevelDev &L0, const float *p, const float *q, float *e,
+                        int mg, Red red, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_update_red0, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, p, q, e, mg,
+                       red);
+}
+
+// One colour of red-black Gauss-Seidel on a level.  On level 0 with
+// level0_rz the kernel also forms r.z (after the final red sweep of the
+// V-cycle) and rotates rz -> rz_old.
+__global__ void k_smooth(Geom g, LevelDev L, int color, int level0_rz, Red red)
+{
+    if (red.F[F_DONE]) return;
+    const int NX = L.NX, NY = L.NY;
+    GRID_IDX
+    double rz = 0.0;
+    if (inb && !L.fix[n]) {
+        float z;
+        if (((i + j) & 1) == color) {
+            z = gs_value(L.u, L.g, L.fix, i, j, NX, NY);
+            L.u[n] = z;
+        } else {
+            z = L.u[n];
+        }
+        if (level0_rz) rz = (double)L.g[n] * (double)z;
+    }
+    if (!level0_rz) return;
+    double v[1] = {rz}, t[1];
+    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) {
+        red.S[S_RZOLD] = red.S[S_RZ];
+        red.S[S_RZ] = t[0];
+    }
+}
+
+void launch_smooth(const Geom &g, const LevelDev &L, int color, int level0_rz, Red red,
+                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_smooth, grid_of(L.NX, L.NY), gblock(), 0, s, g, L, color, level0_rz, red);
+}
+
+// g_c = P^T (g - A u) on the coarse level; u_c = red-from-zero.
+__global__ void k_restrict(Geom g, LevelDev F, LevelDev Cc, const int *done)
+{
+    if (*done) return;
+    const int NX = Cc.NX, NY = Cc.NY;
+    GRID_IDX
+    if (!inb) return;
+    float gv = 0.0f, uv = 0.0f;
+    if (!Cc.fix[n]) {
+        gv = restrict_node(F.u, F.g, F.fix, F.NX, F.NY, g.px, g.py, i, j);
+        if (((i + j) & 1) == 0) uv = gv * 0.25f;
+    }
+    Cc.g[n] = gv;
+    Cc.u[n] = uv;
+}
+
+void launch_restrict(const Geom &g, const LevelDev &F, const LevelDev &Cc, const int *done,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_restrict, grid_of(Cc.NX, Cc.NY), gblock(), 0, s, g, F, Cc, done);
+}
+
+__global__ void k_prolong_black(Geom g, LevelDev F, LevelDev Cc, const int *done)
+{
+    if (*done) return;
+    const int NX = F.NX, NY = F.NY;
+    GRID_IDX
+    if (!inb || F.fix[n] || ((i + j) & 1) != 1) return;
+    F.u[n] = prolong_black_value(F.u, F.g, F.fix, Cc.u, NX, NY, Cc.NX, Cc.NY, i, j);
+}
+
+void launch_prolong_black(const Geom &g, const LevelDev &F, const LevelDev &Cc, const int *done,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prolong_black, grid_of(F.NX, F.NY), gblock(), 0, s, g, F, Cc, done);
+}
+
+// ---------------------------------------------------------------------------
+// coarse levels: the rest of the V-cycle in one work-group, all in LDS
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_coarse(CoarseArgs a, const int *done)
+{
+    if (*done) return;
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int tab[5][kMaxLev];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid < a.nlev) {
+        tab[0][tid] = a.off_u[tid];
+        tab[1][tid] = a.off_g[tid];
+        tab[2][tid] = a.off_f[tid];
+    }
+    __syncthreads();
+#define u(l) ((float *)(lds + tab[0][l]))
+#define gg(l) ((float *)(lds + tab[1][l]))
+#define fx(l) ((uint8_t *)(lds + tab[2][l]))
+    for (int l = 0; l < a.nlev; l++) {
+        const int N = a.NX[l] * a.NY[l];
+        const uint8_t *src = a.fix[l];
+        for (int k = tid; k < N; k += nt) fx(l)[k] = src[k];
+    }
+    {
+        const int N = a.NX[0] * a.NY[0];
+        for (int k = tid; k < N; k += nt) {
+            float gv = a.g_top[k];
+            gg(0)[k] = gv;
+            int i = k / a.NY[0], j = k - i * a.NY[0];
+            u(0)[k] = (!a.fix[0][k] && ((i + j) & 1) == 0) ? gv * 0.25f : 0.0f;
+        }
+    }
+    __syncthreads();
+    // descend
+    for (int l = 0; l < a.nlev - 1; l++) {
+        const int NX = a.NX[l], NY = a.NY[l], N = NX * NY;
+        for (int k = tid; k < N; k += nt) {
+            int i = k / NY, j = k - i * NY;
+            if (!fx(l)[k] && ((i + j) & 1) == 1) u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+        }
+        __syncthreads();
+        const int NXc = a.NX[l + 1], NYc = a.NY[l + 1], Nc = NXc * NYc;
+        for (int k = tid; k < Nc; k += nt) {
+            int I = k / NYc, J = k - I * NYc;
+            float gv = 0.0f, uv = 0.0f;
+            if (!fx(l + 1)[k]) {
+                gv = restrict_node(u(l), gg(l), fx(l), NX, NY, a.px, a.py, I, J);
+                if (((I + J) & 1) == 0) uv = gv * 0.25f;
+            }
+            gg(l + 1)[k] = gv;
+            u(l + 1)[k] = uv;
+        }
+        __syncthreads();
+    }
+    // coarsest: red-black sweeps (first black completes the pre-smoothing)
+    {
+        const int l = a.nlev - 1, NX = a.NX[l], NY = a.NY[l], N = NX * NY;
+        for (int sw = 0; sw < a.sweeps; sw++) {
+            for (int col = 1; col >= 0; col--) {
+                for (int k = tid; k < N; k += nt) {
+                    int i = k / NY, j = k - i * NY;
+                    if (!fx(l)[k] && ((i + j) & 1) == col)
+                        u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+                }
+                __syncthreads();
+            }
+        }
+    }
+    // ascend
+    for (int l = a.nlev - 2; l >= 0; l--) {
+        const int NX = a.NX[l], NY = a.NY[l], N = NX * NY;
+        for (int k = tid; k < N; k += nt) {
+            int i = k / NY, j = k - i * NY;
+            if (!fx(l)[k] && ((i + j) & 1) == 1)
+                u(l)[k] = prolong_black_value(u(l), gg(l), fx(l), u(l + 1), NX, NY, a.NX[l + 1],
+                                              a.NY[l + 1], i, j);
+        }
+        __syncthreads();
+        for (int k = tid; k < N; k += nt) {
+            int i = k / NY, j = k - i * NY;
+            if (!fx(l)[k] && ((i + j) & 1) == 0) u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+        }
+        __syncthreads();
+    }
+    {
+        const int N = a.NX[0] * a.NY[0];
+        for (int k = tid; k < N; k += nt) a.u_top[k] = u(0)[k];
+    }
+#undef u
+#undef gg
+#undef fx
+}
+
+void launch_coarse(const CoarseArgs &a, const int *done, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_coarse, dim3(1), dim3(1024), a.lds_bytes, s, a, done);
+}
+
+// ---------------------------------------------------------------------------
+// particles: gather, leapfrog push, wall test, deposit (eqs. 1-4)
+// ---------------------------------------------------------------------------
+
+template <bool PUSH>
+__global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if ((long long)blockIdx.x >= a.info[1]) return;
+    const int4 ent = a.table[blockIdx.x];
+    const int tile = ent.x, start = ent.y, end = ent.z;
+    const int ti = tile / a.tiles_y, tj = tile - ti * a.tiles_y;
+    const int i0 = ti * a.TX - a.H, j0 = tj * a.TY - a.H;
+    const int WX = a.WX, WY = a.WY, WC = WX * WY;
+    unsigned long long *mA = (unsigned long long *)smem;
+    unsigned long long *mB = mA + WC;
+    unsigned *mC = (unsigned *)(mB + WC);
+    unsigned *tl = mC + WC;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < WC; k += kPushThreads) {
+        mA[k] = 0ull;
+        mB[k] = 0ull;
+        mC[k] = 0u;
+    }
+    if (tid < kNClass) tl[tid] = 0u;
+    __syncthreads();
+
+    const Geom g = a.g;
+    unsigned long long nfb = 0;
+    for (int p = start + tid; p < end; p += kPushThreads) {
+        int c = a.cell[p];
+        if (c < 0) continue;
+        float x0 = a.ox[p], y0 = a.oy[p];
+        int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
+        if (PUSH) {
+            const long long cc = (long long)ci * g.ny + cj;
+            const float4 ea = a.E4[2 * cc], eb = a.E4[2 * cc + 1];
+            const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
+            const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
+            float ex = w00 * ea.x;
+            ex = ex + w10 * ea.z;
+            ex = ex + w01 * eb.x;
+            ex = ex + w11 * eb.z;
+            float ey = w00 * ea.y;
+            ey = ey + w10 * ea.w;
+            ey = ey + w01 * eb.y;
+            ey = ey + w11 * eb.w;
+            const float ux = a.vx[p] + a.qdt * ex;
+            const float uy = a.vy[p] + a.qdt * ey;
+            const float Dx = ux * a.dtf, Dy = uy * a.dtf;
+            const float x1 = x0 + Dx, y1 = y0 + Dy;
+            const float fsx = floorf(x1), fsy = floorf(y1);
+            a.vx[p] = ux;
+            a.vy[p] = uy;
+            int dead = -1;
+            int ei = ci, ej = cj;
+            int sx = 0, sy = 0;
+            if (!(fabsf(fsx) < 1.0e6f && fabsf(fsy) < 1.0e6f)) {
+                dead = 8;
+            } else {
+                sx = (int)fsx;
+                sy = (int)fsy;
+                if (sx != 0 || sy != 0) {
+                    const float ax = fabsf(Dx), ay = fabsf(Dy);
+                    const float fx = sx > 0 ? 1.0f - x0 : x0, fy = sy > 0 ? 1.0f - y0 : y0;
+                    const int nxs = abs(sx), nys = abs(sy);
+                    const int di = sx > 0 ? 1 : -1, dj = sy > 0 ? 1 : -1;
+                    int kx = 0, ky = 0;
+                    while (kx < nxs || ky < nys) {
+                        bool gox;
+                        if (ky >= nys) gox = true;
+                        else if (kx >= nxs) gox = false;
+                        else gox = ((fx + (float)kx) * ay <= (fy + (float)ky) * ax);
+                        int ni = ei, nj = ej, dir;
+                        if (gox) { ni = ei + di; kx++; dir = di > 0 ? 0 : 1; }
+                        else { nj = ej + dj; ky++; dir = dj > 0 ? 2 : 3; }
+                        bool out = false;
+                        if (g.px) ni = wrap_hi(wrap_lo(ni, g.nx), g.nx);
+                        else if (ni < 0 || ni >= g.nx) out = true;
+                        if (g.py) nj = wrap_hi(wrap_lo(nj, g.ny), g.ny);
+                        else if (nj < 0 || nj >= g.ny) out = true;
+                        if (!out && a.cell_cond[(long long)ni * g.ny + nj]) out = true;
+                        if (out) {
+                            bool inbox = ei >= a.box_i_top && ej >= a.box_j_lo && ej < a.box_j_hi;
+                            dead = dir + (inbox ? 4 : 0);
+                            break;
+                        }
+                        ei = ni;
+                        ej = nj;
+                    }
+                }
+            }
+            if (dead >= 0) {
+                a.cell[p] = -1 - dead;
+                atomicAdd(&tl[dead], 1u);
+                if (a.surf && dead == 4) atomicAdd(&a.surf[ej], 1ull);
+                if (a.log.rec && ((a.log.species_mask >> a.species) & 1)) {
+                    unsigned long long k = atomicAdd(a.log.count, 1ull);
+                    long long slot = (long long)(k % (unsigned long long)a.log.capacity);
+                    int32_t *r = a.log.rec + 6 * slot;
+                    r[0] = (a.species << 8) | dead;
+                    r[1] = (int)(((unsigned)ei << 16) | (unsigned)ej);
+                    r[2] = __float_as_int(ux);
+                    r[3] = __float_as_int(uy);
+                    r[4] = a.step;
+                    r[5] = 0;
+                }
+                continue;
+            }
+            float nxo = x1 - (float)sx, nyo = y1 - (float)sy;
+            if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
+            if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
+            a.ox[p] = nxo;
+            a.oy[p] = nyo;
+            const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
+            if (nc != c) a.cell[p] = nc;
+            x0 = nxo;
+            y0 = nyo;
+            ci = ei;
+            cj = ej;
+        }
+        // area weighting, integer moments of the cell (exact, order-free)
+        const unsigned ux = (unsigned)floorf(x0 * 65536.0f);
+        const unsigned uy = (unsigned)floorf(y0 * 65536.0f);
+        int wi = ci - i0, wj = cj - j0;
+        if (g.px) { if (wi < 0) wi += g.nx; else if (wi >= g.nx) wi -= g.nx; }
+        if (g.py) { if (wj < 0) wj += g.ny; else if (wj >= g.ny) wj -= g.ny; }
+        if (wi >= 0 && wi < WX && wj >= 0 && wj < WY) {
+            const int k = wi * WY + wj;
+            const unsigned m3 = ux * uy;
+            atomicAdd(&mA[k], ((unsigned long long)ux << 32) | 1ull);
+            atomicAdd(&mB[k], ((unsigned long long)uy << 32) | (unsigned long long)(m3 >> 16));
+            atomicAdd(&mC[k], m3 & 0xFFFFu);
+        } else {
+            const unsigned long long S = 65536ull;
+            const int i1 = g.px ? wrap_hi(ci + 1, g.nx) : ci + 1;
+            const int j1 = g.py ? wrap_hi(cj + 1, g.ny) : cj + 1;
+            const unsigned long long X = ux, Y = uy;
+            atomicAdd(&a.rho[(long long)ci * g.NY + cj], (S - X) * (S - Y));
+            atomicAdd(&a.rho[(long long)i1 * g.NY + cj], X * (S - Y));
+            atomicAdd(&a.rho[(long long)ci * g.NY + j1], (S - X) * Y);
+            atomicAdd(&a.rho[(long long)i1 * g.NY + j1], X * Y);
+            nfb++;
+        }
+    }
+    if (nfb) atomicAdd(a.fallbacks, nfb);
+    __syncthreads();
+    // flush: node (wa, wb) of the window collects the four cells around it
+    const unsigned long long S = 65536ull;
+    const int WN = (WX + 1) * (WY + 1);
+    for (int k = tid; k < WN; k += kPushThreads) {
+        const int wa = k / (WY + 1), wb = k - wa * (WY + 1);
+        unsigned long long v = 0ull;
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int ca = wa - (q & 1), cb = wb - (q >> 1);
+            if (ca < 0 || ca >= WX || cb < 0 || cb >= WY) continue;
+            const int m = ca * WY + cb;
+            const unsigned long long A = mA[m];
+            if (A == 0ull) continue;
+            any = true;
+            const unsigned long long B = mB[m];
+            const unsigned long long M0 = A & 0xFFFFFFFFull, M1 = A >> 32, M2 = B >> 32;
+            const unsigned long long M3 = ((B & 0xFFFFFFFFull) << 16) + (unsigned long long)mC[m];
+            if (q == 0) v += S * S * M0 - S * M1 - S * M2 + M3;  // node is the cell's 00 corner
+            else if (q == 1) v += S * M1 - M3;                    // 10 corner of cell (wa-1, wb)
+            else if (q == 2) v += S * M2 - M3;                    // 01 corner of cell (wa, wb-1)
+            else v += M3;                                         // 11 corner of cell (wa-1, wb-1)
+        }
+        if (!any || v == 0ull) continue;
+        int gi = i0 + wa, gj = j0 + wb;
+        if (g.px) { gi = ((gi % g.NX) + g.NX) % g.NX; }
+        else if (gi < 0 || gi >= g.NX) continue;
+        if (g.py) { gj = ((gj % g.NY) + g.NY) % g.NY; }
+        else if (gj < 0 || gj >= g.NY) continue;
+        atomicAdd(&a.rho[(long long)gi * g.NY + gj], v);
+    }
+    if (PUSH && tid < kNClass && tl[tid]) atomicAdd(&a.tally[tid], (unsigned long long)tl[tid]);
+}
+
+void launch_push(const PushArgs &a, int max_blocks, bool push, hipStream_t s)
+{
+    const int WC = a.WX * a.WY;
+    const size_t lds = (size_t)WC * 20 + kNClass * 4 + 16;
+    if (push)
+        hipLaunchKernelGGL(k_push<true>, dim3(max_blocks), dim3(kPushThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_push<false>, dim3(max_blocks), dim3(kPushThreads), lds, s, a);
+}
+
+// Leapfrog start: v -= (alpha dt / 2) E(x), same gather as the push.
+__global__ void k_rewind(Geom g, const float4 *E4, const int32_t *cell, const float *ox,
+                         const float *oy, float *vx, float *vy, const long long *slots, float hq)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *slots) return;
+    const int c = cell[p];
+    if (c < 0) return;
+    const int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
+    const long long cc = (long long)ci * g.ny + cj;
+    const float4 ea = E4[2 * cc], eb = E4[2 * cc + 1];
+    const float x0 = ox[p], y0 = oy[p];
+    const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
+    const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
+    float ex = w00 * ea.x;
+    ex = ex + w10 * ea.z;
+    ex = ex + w01 * eb.x;
+    ex = ex + w11 * eb.z;
+    float ey = w00 * ea.y;
+    ey = ey + w10 * ea.w;
+    ey = ey + w01 * eb.y;
+    ey = ey + w11 * eb.w;
+    vx[p] = vx[p] - hq * ex;
+    vy[p] = vy[p] - hq * ey;
+}
+
+void launch_rewind(const Geom &g, const float4 *E4, const int32_t *cell, const float *ox,
+                   const float *oy, float *vx, float *vy, long long n, const long long *slots,
+                   float hq, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rewind, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, E4, cell,
+                       ox, oy, vx, vy, slots, hq);
+}
+
+// ---------------------------------------------------------------------------
+// re-binning: counting sort of live particles by tile (order inside a tile
+// is arbitrary; results never depend on particle order)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int tile_of(int c, int lx, int ly, int tiles_y)
+{
+    const int i = (int)((unsigned)c >> 16), j = c & 0xFFFF;
+    return (i >> lx) * tiles_y + (j >> ly);
+}
+
+// Adds 1 per active lane to counters[key], one atomic per distinct key in
+// the wavefront; returns the lane's slot (previous value + rank).
+__device__ __forceinline__ unsigned wave_add(unsigned *counters, int key, bool active)
+{
+    unsigned mine = 0;
+    const int lane = __lane_id();
+    unsigned long long pend = __ballot(active);
+    while (pend) {
+        const int leader = __builtin_ctzll(pend);
+        const int lk = __shfl(key, leader, 64);
+        const unsigned long long m = __ballot(active && key == lk) & pend;
+        unsigned base = 0;
+        if (lane == leader) base = atomicAdd(&counters[lk], (unsigned)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if ((m >> lane) & 1ull) mine = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+        pend &= ~m;
+    }
+    return mine;
+}
+
+// A slot is binned when its code is non-negative and names a cell of the
+// grid; a non-negative code outside the grid is counted in bad[0] and dropped.
+__device__ __forceinline__ bool live_code(int c, int nx, int ny)
+{
+    return c >= 0 && (int)((unsigned)c >> 16) < nx && (c & 0xFFFF) < ny;
+}
+
+__global__ void k_bin_count(BinArgs a)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = *a.slots;
+    int c = -1;
+    if (p < n) c = a.cell[p];
+    const bool act = live_code(c, a.nx, a.ny);
+    if (c >= 0 && !act) atomicAdd(a.bad, 1ull);
+    const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
+    wave_add(a.counts, key, act);
+}
+
+// Single work-group: exclusive scans of the tile counts and of the blocks
+// per tile; writes the cursor for the scatter and the totals.
+__global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
+{
+    __shared__ unsigned long long sp[1024], sb[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (a.ntiles + nt - 1) / nt;
+    const int lo = tid * per, hi = min(a.ntiles, lo + per);
+    unsigned long long s = 0, sbk = 0;
+    for (int t = lo; t < hi; t++) {
+        unsigned c = a.counts[t];
+        s += c;
+        sbk += (c + a.chunk - 1) / a.chunk;
+    }
+    sp[tid] = s;
+    sb[tid] = sbk;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {
+        unsigned long long x = tid >= o ? sp[tid - o] : 0, y = tid >= o ? sb[tid - o] : 0;
+        __syncthreads();
+        sp[tid] += x;
+        sb[tid] += y;
+        __syncthreads();
+    }
+    unsigned long long off = sp[tid] - s, boff = sb[tid] - sbk;
+    for (int t = lo; t < hi; t++) {
+        unsigned c = a.counts[t];
+        a.offsets[t] = (unsigned)off;
+        a.cursor[t] = (unsigned)off;
+        a.boff[t] = (unsigned)boff;
+        off += c;
+        boff += (c + a.chunk - 1) / a.chunk;
+    }
+    if (tid == nt - 1) {
+        a.info[0] = (long long)sp[tid];
+        a.info[1] = (long long)sb[tid];
+        a.info[2 + a.dst] = (long long)sp[tid];
+    }
+}
+
+__global__ void k_bin_table(BinArgs a)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.ntiles) return;
+    const unsigned c = a.counts[t], o = a.offsets[t], b0 = a.boff[t];
+    const unsigned nb = (c + a.chunk - 1) / a.chunk;
+    for (unsigned k = 0; k < nb; k++) {
+        unsigned s = o + k * a.chunk;
+        unsigned e = min(o + c, s + (unsigned)a.chunk);
+        a.table[b0 + k] = make_int4(t, (int)s, (int)e, 0);
+    }
+}
+
+__global__ void k_bin_scatter(BinArgs a)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = *a.slots;
+    int c = -1;
+    if (p < n) c = a.cell[p];
+    const bool act = live_code(c, a.nx, a.ny);
+    const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
+    const unsigned d = wave_add(a.cursor, key, act);
+    if (act) {
+        a.cell2[d] = c;
+        a.ox2[d] = a.ox[p];
+        a.oy2[d] = a.oy[p];
+        a.vx2[d] = a.vx[p];
+        a.vy2[d] = a.vy[p];
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p, int n)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0u;
+}
+
+void launch_bin(const BinArgs &a, long long max_slots, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3((a.ntiles + 255) / 256), dim3(256), 0, s, a.counts,
+                       a.ntiles);
+    const unsigned nb = (unsigned)((max_slots + 255) / 256);
+    if (nb) hipLaunchKernelGGL(k_bin_count, dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_bin_table, dim3((a.ntiles + 255) / 256), dim3(256), 0, s, a);
+    if (nb) hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(256), 0, s, a);
+}
+
+// Sum of a node charge array (exact integer sum).
+__global__ void k_rho_sum(const unsigned long long *rho, long long n, unsigned long long *out)
+{
+    __shared__ unsigned long long sh[4];
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    unsigned long long s = 0;
+    for (; k < n; k += st) s += rho[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
+void launch_rho_sum(const unsigned long long *rho, long long n, unsigned long long *out,
+                    hipStream_t s)
+{
+    long long nb = (n + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_rho_sum, dim3((unsigned)nb), dim3(256), 0, s, rho, n, out);
+}
+
+} // namespace pic
