@@ -465,7 +465,7 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess, pic_solve_info *i
     si.relres0 = relres;
     int total = 0, outer = 0;
     const int mg = c->L.mg ? 1 : 0;
-    while (relres > c->cfg.rtol && total < c->cfg.max_iter && std::isfinite(relres)) {
+    while (relres > c->cfg.rtol && total < c->cfg.max_iter && outer < 64 && std::isfinite(relres)) {
         double eta = 0.3 * c->cfg.rtol / relres;
         eta = std::min(0.5, std::max(eta, mg ? 2e-6 : 1e-5));
         launch_init_red0(c->g, L0, c->d_e, eta * eta, mg, r, c->stream);
