@@ -12,6 +12,7 @@ constexpr int kNClass = 9;
 constexpr int kGridBX = 64;      // grid kernels: 64 x 4 threads over (y, x) nodes
 constexpr int kGridBY = 4;
 constexpr int kPushThreads = 256;
+constexpr int kUnroll = 4;        // particles per thread per pass of the push loop
 
 struct Geom {
     int nx, ny;     // cells
@@ -30,6 +31,7 @@ enum {
     S_RR0,       // inner ||r0||^2
     S_ETA2,      // inner stop ratio (squared)
     S_SUM,       // scratch sum (mean projection)
+    S_PIN,       // value of the pinned node (fully periodic gauge)
     S_NSCAL = 16
 };
 enum { F_DONE = 0, F_ITER, F_NFLAG = 8 };
@@ -119,6 +121,7 @@ void launch_assemble(const Geom &g, const uint8_t *node_cond, const uint8_t *fix
                      int sj_hi, double *b, double *phi, Red red, hipStream_t s);
 void launch_project_mean(const Geom &g, const uint8_t *fix0, double *b, Red red, hipStream_t s);
 void launch_shift_mean(const Geom &g, double *phi, Red red, hipStream_t s);
+void launch_pin_shift(const Geom &g, double *phi, Red red, hipStream_t s);
 void launch_set_guess(const Geom &g, const uint8_t *fix0, int kind, const double *guess,
                       double *phi, hipStream_t s);
 void launch_resid64(const Geom &g, const uint8_t *fix0, const double *b, const double *phi,

@@ -21,15 +21,6 @@ namespace pic {
 __device__ __forceinline__ int wrap_lo(int a, int n) { return a < 0 ? a + n : a; }
 __device__ __forceinline__ int wrap_hi(int a, int n) { return a >= n ? a - n : a; }
 
-__device__ __forceinline__ void store_agent(double *p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double *p)
-{
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -37,19 +28,17 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sums NQ per-thread values over the whole grid.  Every block writes its
-// partial; the last block to arrive adds the partials in block order and
-// returns true (totals in tot[] of thread 0).  Deterministic.
+// Writes this block's sums of NQ per-thread values (fixed tree order) to
+// red.part[q * stride + block].  A one-block k_finalize launched next adds
+// the partials in block order, so every total is reproducible bit for bit.
 template <int NQ>
-__device__ bool grid_reduce(const double (&val)[NQ], double (&tot)[NQ], const Red &red)
+__device__ void block_partials(const double (&val)[NQ], const Red &red)
 {
     __shared__ double sh[NQ][16];
-    __shared__ int last;
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nt = blockDim.x * blockDim.y;
     const int lane = tid & 63, wid = tid >> 6, nw = (nt + 63) >> 6;
     const int bid = blockIdx.x + blockIdx.y * gridDim.x;
-    const int nb = gridDim.x * gridDim.y;
 #pragma unroll
     for (int q = 0; q < NQ; q++) {
         double v = wave_sum(val[q]);
@@ -61,31 +50,69 @@ __device__ bool grid_reduce(const double (&val)[NQ], double (&tot)[NQ], const Re
         for (int q = 0; q < NQ; q++) {
             double s = 0.0;
             for (int w = 0; w < nw; w++) s += sh[q][w];
-            store_agent(&red.part[q * red.stride + bid], s);
+            red.part[q * red.stride + bid] = s;
         }
-        __threadfence();
-        unsigned prev = atomicAdd(red.count, 1u);
-        last = (prev == (unsigned)(nb - 1));
+    }
+}
+
+// What k_finalize does with the totals.
+enum {
+    OP_BB = 0,      // S_BB = t0
+    OP_SUM,         // S_SUM = t0
+    OP_SUM2,        // S_SUM = t1 (second quantity)
+    OP_RR64,        // S_RR64 = t0
+    OP_INIT,        // inner start: S_RR0 = S_RR = t0, flags reset, (no MG) rz <- t1
+    OP_PQ,          // S_PQ = t0
+    OP_UPDATE,      // S_RR = t0, one more iteration, stop test, (no MG) rz <- t1
+    OP_RZ           // rz <- t0
+};
+
+__global__ __launch_bounds__(256) void k_finalize(Red red, int nb, int op, int mg, double eta2)
+{
+    const bool inner = op == OP_PQ || op == OP_UPDATE || op == OP_RZ;
+    if (inner && red.F[F_DONE]) return;
+    __shared__ double sh[2][4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nq = (op == OP_INIT || op == OP_UPDATE || op == OP_SUM2) ? 2 : 1;
+    double t[2] = {0.0, 0.0};
+    for (int q = 0; q < nq; q++) {
+        double s = 0.0;
+        for (int k = tid; k < nb; k += 256) s += red.part[q * red.stride + k];
+        s = wave_sum(s);
+        if (lane == 0) sh[q][wid] = s;
     }
     __syncthreads();
-    if (!last) return false;
-    __threadfence();
-#pragma unroll
-    for (int q = 0; q < NQ; q++) {
-        double s = 0.0;
-        for (int k = tid; k < nb; k += nt) s += load_agent(&red.part[q * red.stride + k]);
-        s = wave_sum(s);
-        __syncthreads();
-        if (lane == 0) sh[q][wid] = s;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < nw; w++) t += sh[q][w];
-            tot[q] = t;
-        }
+    if (tid != 0) return;
+    for (int q = 0; q < nq; q++) t[q] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
+    double *S = red.S;
+    int *F = red.F;
+    switch (op) {
+    case OP_BB: S[S_BB] = t[0]; break;
+    case OP_SUM: S[S_SUM] = t[0]; break;
+    case OP_SUM2: S[S_SUM] = t[1]; break;
+    case OP_RR64: S[S_RR64] = t[0]; break;
+    case OP_INIT:
+        S[S_RR0] = t[0];
+        S[S_RR] = t[0];
+        if (eta2 >= 0.0) S[S_ETA2] = eta2;   // negative: already stored by the host
+        F[F_DONE] = (t[0] == 0.0) ? 1 : 0;
+        F[F_ITER] = 0;
+        if (!mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t[1]; }
+        break;
+    case OP_PQ: S[S_PQ] = t[0]; break;
+    case OP_UPDATE:
+        S[S_RR] = t[0];
+        F[F_ITER] += 1;
+        if (t[0] <= S[S_ETA2] * S[S_RR0]) F[F_DONE] = 1;
+        if (!mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t[1]; }
+        break;
+    case OP_RZ: S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t[0]; break;
     }
-    if (tid == 0) *red.count = 0u;
-    return true;
+}
+
+static void finalize(const Red &red, int nb, int op, int mg, double eta2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, red, nb, op, mg, eta2);
 }
 
 #define GRID_IDX                                                     \
@@ -99,6 +126,7 @@ static inline dim3 grid_of(int NX, int NY)
     return dim3((NY + kGridBX - 1) / kGridBX, (NX + kGridBY - 1) / kGridBY);
 }
 static inline dim3 gblock() { return dim3(kGridBX, kGridBY); }
+static inline int nblk(int NX, int NY) { dim3 d = grid_of(NX, NY); return (int)(d.x * d.y); }
 
 __global__ void k_zero_u64(unsigned long long *p, long long n)
 {
@@ -230,11 +258,8 @@ __global__ void k_assemble(Geom g, const uint8_t *nc, const uint8_t *fix0, const
             sm = r;
         }
     }
-    double v[2] = {bb, sm}, t[2];
-    if (grid_reduce<2>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) {
-        if (!want_sum) red.S[S_BB] = t[0];
-        red.S[S_SUM] = t[1];
-    }
+    double v[2] = {bb, sm};
+    block_partials<2>(v, red);
 }
 
 void launch_assemble(const Geom &g, const uint8_t *nc, const uint8_t *fix0, const long long *re,
@@ -245,6 +270,7 @@ void launch_assemble(const Geom &g, const uint8_t *nc, const uint8_t *fix0, cons
     int want_sum = (g.px && g.py) ? 1 : 0;
     hipLaunchKernelGGL(k_assemble, grid_of(g.NX, g.NY), gblock(), 0, s, g, nc, fix0, re, ri, q,
                        V, mode, row, surf, sden, sjl, sjh, b, phi, red, want_sum);
+    finalize(red, nblk(g.NX, g.NY), want_sum ? OP_SUM2 : OP_BB, 0, 0.0, s);
 }
 
 // Fully periodic grid: the source must have zero mean (gauge); subtract it
@@ -260,41 +286,58 @@ __global__ void k_project_mean(Geom g, const uint8_t *fix0, double *b, Red red)
         b[n] = r;
         if (!fix0[n]) bb = r * r;
     }
-    double v[1] = {bb}, t[1];
-    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) red.S[S_BB] = t[0];
+    double v[1] = {bb};
+    block_partials<1>(v, red);
 }
 
 void launch_project_mean(const Geom &g, const uint8_t *fix0, double *b, Red red, hipStream_t s)
 {
     hipLaunchKernelGGL(k_project_mean, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, b, red);
+    finalize(red, nblk(g.NX, g.NY), OP_BB, 0, 0.0, s);
 }
 
 __global__ void k_sum_phi(Geom g, const double *phi, Red red)
 {
     const int NX = g.NX, NY = g.NY;
     GRID_IDX
-    double v[1] = {inb ? phi[n] : 0.0}, t[1];
-    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) red.S[S_SUM] = t[0];
+    double v[1] = {inb ? phi[n] : 0.0};
+    block_partials<1>(v, red);
 }
 
-__global__ void k_shift_phi(Geom g, double *phi, const double *S)
+// phi -= S[slot] * scale on every node
+__global__ void k_shift_phi(Geom g, double *phi, const double *S, int slot, double scale)
 {
     const int NX = g.NX, NY = g.NY;
     GRID_IDX
-    if (inb) phi[n] -= S[S_SUM] / ((double)NX * (double)NY);
+    if (inb) phi[n] -= S[slot] * scale;
 }
+
+__global__ void k_read_node0(const double *phi, double *S) { S[S_PIN] = phi[0]; }
 
 void launch_shift_mean(const Geom &g, double *phi, Red red, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sum_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red);
-    hipLaunchKernelGGL(k_shift_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red.S);
+    finalize(red, nblk(g.NX, g.NY), OP_SUM, 0, 0.0, s);
+    hipLaunchKernelGGL(k_shift_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red.S, (int)S_SUM,
+                       1.0 / ((double)g.NX * (double)g.NY));
 }
 
+// Fully periodic grid: node 0 is held at 0 during the solve (gauge); shift a
+// warm start so that it already satisfies that.
+void launch_pin_shift(const Geom &g, double *phi, Red red, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_read_node0, dim3(1), dim3(1), 0, s, phi, red.S);
+    hipLaunchKernelGGL(k_shift_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red.S, (int)S_PIN,
+                       1.0);
+}
+
+// Start of the solve on the unknowns; on a fully periodic grid also on the
+// pinned node (the gauge shift that follows moves it back to 0).
 __global__ void k_set_guess(Geom g, const uint8_t *fix0, int kind, const double *guess, double *phi)
 {
     const int NX = g.NX, NY = g.NY;
     GRID_IDX
-    if (!inb || fix0[n]) return;
+    if (!inb || (fix0[n] && !(g.px && g.py))) return;
     phi[n] = (kind == 0) ? 0.0 : guess[n];
 }
 
@@ -335,14 +378,15 @@ __global__ void k_resid64(Geom g, const uint8_t *fix, const double *b, const dou
             rr = r * r;
         }
     }
-    double v[1] = {rr}, t[1];
-    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) red.S[S_RR64] = t[0];
+    double v[1] = {rr};
+    block_partials<1>(v, red);
 }
 
 void launch_resid64(const Geom &g, const uint8_t *fix0, const double *b, const double *phi,
                     float *r, Red red, hipStream_t s)
 {
     hipLaunchKernelGGL(k_resid64, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, b, phi, r, red);
+    finalize(red, nblk(g.NX, g.NY), OP_RR64, 0, 0.0, s);
 }
 
 __global__ void k_phi_update(Geom g, const uint8_t *fix, const float *e, double *phi)
@@ -468,7 +512,7 @@ __device__ __forceinline__ float prolong_black_value(const float *u, const float
 
 // Inner start: e = 0, z = red-from-zero of M r (or z = r/4 when no MG),
 // ||r||^2 -> S_RR0, S_RR; iteration flag reset.
-__global__ void k_init_red0(Geom g, LevelDev L, float *e, double eta2, int mg, Red red)
+__global__ void k_init_red0(Geom g, LevelDev L, float *e, int mg, Red red)
 {
     const int NX = L.NX, NY = L.NY;
     GRID_IDX
@@ -484,24 +528,15 @@ __global__ void k_init_red0(Geom g, LevelDev L, float *e, double eta2, int mg, R
         }
         L.u[n] = z;
     }
-    double v[2] = {rr, rz}, t[2];
-    if (grid_reduce<2>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) {
-        red.S[S_RR0] = t[0];
-        red.S[S_RR] = t[0];
-        red.S[S_ETA2] = eta2;
-        red.F[F_DONE] = (t[0] == 0.0) ? 1 : 0;
-        if (!mg) {
-            red.S[S_RZOLD] = red.S[S_RZ];
-            red.S[S_RZ] = t[1];
-        }
-    }
+    double v[2] = {rr, rz};
+    block_partials<2>(v, red);
 }
 
 void launch_init_red0(const Geom &g, const LevelDev &L0, float *e, double eta2, int mg, Red red,
                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init_red0, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, e, eta2, mg,
-                       red);
+    hipLaunchKernelGGL(k_init_red0, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, e, mg, red);
+    finalize(red, nblk(L0.NX, L0.NY), OP_INIT, mg, eta2, s);
 }
 
 // p_new = z + beta p_old, q = A p_new, p.q  (beta = rz / rz_old; 0 on the first)
@@ -534,8 +569,8 @@ __global__ void k_pupdate_Ap(Geom g, LevelDev L, const float *p_old, float *p_ne
             pq = (double)pc * (double)s;
         }
     }
-    double v[1] = {pq}, t[1];
-    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) red.S[S_PQ] = t[0];
+    double v[1] = {pq};
+    block_partials<1>(v, red);
 }
 
 void launch_pupdate_Ap(const Geom &g, const LevelDev &L0, const float *p_old, float *p_new,
@@ -543,6 +578,7 @@ void launch_pupdate_Ap(const Geom &g, const LevelDev &L0, const float *p_old, fl
 {
     hipLaunchKernelGGL(k_pupdate_Ap, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, p_old, p_new,
                        q, first, red);
+    finalize(red, nblk(L0.NX, L0.NY), OP_PQ, 0, 0.0, s);
 }
 
 // alpha = rz / pq; e += alpha p; r -= alpha q; ||r||^2; z = red-from-zero of
@@ -568,16 +604,8 @@ __global__ void k_update_red0(Geom g, LevelDev L, const float *p, const float *q
         }
         L.u[n] = z;
     }
-    double v[2] = {rr, rz}, t[2];
-    if (grid_reduce<2>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) {
-        red.S[S_RR] = t[0];
-        red.F[F_ITER] += 1;
-        if (t[0] <= red.S[S_ETA2] * red.S[S_RR0]) red.F[F_DONE] = 1;
-        if (!mg) {
-            red.S[S_RZOLD] = red.S[S_RZ];
-            red.S[S_RZ] = t[1];
-        }
-    }
+    double v[2] = {rr, rz};
+    block_partials<2>(v, red);
 }
 
 void launch_update_red0(const Geom &g, const LevelDev &L0, const float *p, const float *q, float *e,
@@ -585,6 +613,7 @@ void launch_update_red0(const Geom &g, const LevelDev &L0, const float *p, const
 {
     hipLaunchKernelGGL(k_update_red0, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, p, q, e, mg,
                        red);
+    finalize(red, nblk(L0.NX, L0.NY), OP_UPDATE, mg, 0.0, s);
 }
 
 // One colour of red-black Gauss-Seidel on a level.  On level 0 with
@@ -607,17 +636,15 @@ __global__ void k_smooth(Geom g, LevelDev L, int color, int level0_rz, Red red)
         if (level0_rz) rz = (double)L.g[n] * (double)z;
     }
     if (!level0_rz) return;
-    double v[1] = {rz}, t[1];
-    if (grid_reduce<1>(v, t, red) && threadIdx.x == 0 && threadIdx.y == 0) {
-        red.S[S_RZOLD] = red.S[S_RZ];
-        red.S[S_RZ] = t[0];
-    }
+    double v[1] = {rz};
+    block_partials<1>(v, red);
 }
 
 void launch_smooth(const Geom &g, const LevelDev &L, int color, int level0_rz, Red red,
                    hipStream_t s)
 {
     hipLaunchKernelGGL(k_smooth, grid_of(L.NX, L.NY), gblock(), 0, s, g, L, color, level0_rz, red);
+    if (level0_rz) finalize(red, nblk(L.NX, L.NY), OP_RZ, 0, 0.0, s);
 }
 
 // g_c = P^T (g - A u) on the coarse level; u_c = red-from-zero.
@@ -785,14 +812,47 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
 
     const Geom g = a.g;
     unsigned long long nfb = 0;
-    for (int p = start + tid; p < end; p += kPushThreads) {
-        int c = a.cell[p];
+    // kUnroll particles per thread per pass: all their loads are issued
+    // before any is used, so each wave keeps several requests in flight.
+    for (int base = start + tid; base < end; base += kUnroll * kPushThreads) {
+    int cu[kUnroll];
+    float xu[kUnroll], yu[kUnroll], vxu[kUnroll], vyu[kUnroll];
+    float4 eau[kUnroll], ebu[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+        const int p = base + u * kPushThreads;
+        cu[u] = (p < end) ? a.cell[p] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+        const int p = base + u * kPushThreads;
+        if (p < end) {
+            xu[u] = a.ox[p];
+            yu[u] = a.oy[p];
+            if (PUSH) {
+                vxu[u] = a.vx[p];
+                vyu[u] = a.vy[p];
+            }
+        }
+    }
+    if (PUSH) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const int c = cu[u] < 0 ? 0 : cu[u];
+            const long long cc = (long long)((unsigned)c >> 16) * g.ny + (c & 0xFFFF);
+            eau[u] = a.E4[2 * cc];
+            ebu[u] = a.E4[2 * cc + 1];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+        const int p = base + u * kPushThreads;
+        int c = cu[u];
         if (c < 0) continue;
-        float x0 = a.ox[p], y0 = a.oy[p];
+        float x0 = xu[u], y0 = yu[u];
         int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
         if (PUSH) {
-            const long long cc = (long long)ci * g.ny + cj;
-            const float4 ea = a.E4[2 * cc], eb = a.E4[2 * cc + 1];
+            const float4 ea = eau[u], eb = ebu[u];
             const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
             const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
             float ex = w00 * ea.x;
@@ -803,8 +863,8 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
             ey = ey + w10 * ea.w;
             ey = ey + w01 * eb.y;
             ey = ey + w11 * eb.w;
-            const float ux = a.vx[p] + a.qdt * ex;
-            const float uy = a.vy[p] + a.qdt * ey;
+            const float ux = vxu[u] + a.qdt * ex;
+            const float uy = vyu[u] + a.qdt * ey;
             const float Dx = ux * a.dtf, Dy = uy * a.dtf;
             const float x1 = x0 + Dx, y1 = y0 + Dy;
             const float fsx = floorf(x1), fsy = floorf(y1);
@@ -900,6 +960,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
             atomicAdd(&a.rho[(long long)i1 * g.NY + j1], X * Y);
             nfb++;
         }
+    }
     }
     if (nfb) atomicAdd(a.fallbacks, nfb);
     __syncthreads();
@@ -1020,18 +1081,46 @@ __device__ __forceinline__ bool live_code(int c, int nx, int ny)
     return c >= 0 && (int)((unsigned)c >> 16) < nx && (c & 0xFFFF) < ny;
 }
 
-__global__ void k_bin_count(BinArgs a)
+// Count and scatter work in blocks of kBinPer consecutive slots: a block
+// first counts its live particles per tile in LDS (one LDS atomic per
+// distinct tile per wavefront), then adds each non-zero count to the global
+// counters (count pass) or reserves that many consecutive destination slots
+// with one global atomic per tile (scatter pass) and hands them out in LDS.
+// Tiles beyond kBinLds fall back to global wavefront-aggregated atomics.
+constexpr int kBinPer = 4096;
+constexpr int kBinLds = 8192;
+
+__device__ __forceinline__ void bin_local_count(const BinArgs &a, long long lo, long long hi,
+                                                unsigned *hist, bool count_bad)
 {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long n = *a.slots;
-    int c = -1;
-    if (p < n) c = a.cell[p];
-    const bool act = live_code(c, a.nx, a.ny);
-    if (c >= 0 && !act) atomicAdd(a.bad, 1ull);
-    const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
-    wave_add(a.counts, key, act);
+    const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
+    for (int k = threadIdx.x; k < nl; k += 256) hist[k] = 0u;
+    __syncthreads();
+    for (long long p0 = lo; p0 < hi; p0 += 256) {
+        const long long p = p0 + threadIdx.x;
+        int c = -1;
+        if (p < hi) c = a.cell[p];
+        const bool act = live_code(c, a.nx, a.ny);
+        if (count_bad && c >= 0 && !act) atomicAdd(a.bad, 1ull);
+        const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
+        wave_add(hist, key, act && key < kBinLds);
+        if (count_bad) wave_add(a.counts, key, act && key >= kBinLds);
+    }
+    __syncthreads();
 }
 
+__global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
+{
+    __shared__ unsigned hist[kBinLds];
+    const long long n = *a.slots;
+    const long long lo = (long long)blockIdx.x * kBinPer;
+    if (lo >= n) return;
+    const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
+    bin_local_count(a, lo, hi, hist, true);
+    const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
+    for (int k = threadIdx.x; k < nl; k += 256)
+        if (hist[k]) atomicAdd(&a.counts[k], hist[k]);
+}
 // Single work-group: exclusive scans of the tile counts and of the blocks
 // per tile; writes the cursor for the scatter and the totals.
 __global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
@@ -1085,21 +1174,35 @@ __global__ void k_bin_table(BinArgs a)
     }
 }
 
-__global__ void k_bin_scatter(BinArgs a)
+__global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
 {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ unsigned hist[kBinLds];
     const long long n = *a.slots;
-    int c = -1;
-    if (p < n) c = a.cell[p];
-    const bool act = live_code(c, a.nx, a.ny);
-    const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
-    const unsigned d = wave_add(a.cursor, key, act);
-    if (act) {
-        a.cell2[d] = c;
-        a.ox2[d] = a.ox[p];
-        a.oy2[d] = a.oy[p];
-        a.vx2[d] = a.vx[p];
-        a.vy2[d] = a.vy[p];
+    const long long lo = (long long)blockIdx.x * kBinPer;
+    if (lo >= n) return;
+    const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
+    bin_local_count(a, lo, hi, hist, false);
+    const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
+    // reserve: hist[t] becomes the first destination slot of this block in tile t
+    for (int k = threadIdx.x; k < nl; k += 256)
+        if (hist[k]) hist[k] = atomicAdd(&a.cursor[k], hist[k]);
+    __syncthreads();
+    for (long long p0 = lo; p0 < hi; p0 += 256) {
+        const long long p = p0 + threadIdx.x;
+        int c = -1;
+        if (p < hi) c = a.cell[p];
+        const bool act = live_code(c, a.nx, a.ny);
+        const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
+        const unsigned d0 = wave_add(hist, key, act && key < kBinLds);
+        const unsigned d1 = wave_add(a.cursor, key, act && key >= kBinLds);
+        if (act) {
+            const unsigned d = key < kBinLds ? d0 : d1;
+            a.cell2[d] = c;
+            a.ox2[d] = a.ox[p];
+            a.oy2[d] = a.oy[p];
+            a.vx2[d] = a.vx[p];
+            a.vy2[d] = a.vy[p];
+        }
     }
 }
 
@@ -1113,7 +1216,7 @@ void launch_bin(const BinArgs &a, long long max_slots, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_u32, dim3((a.ntiles + 255) / 256), dim3(256), 0, s, a.counts,
                        a.ntiles);
-    const unsigned nb = (unsigned)((max_slots + 255) / 256);
+    const unsigned nb = (unsigned)((max_slots + kBinPer - 1) / kBinPer);
     if (nb) hipLaunchKernelGGL(k_bin_count, dim3(nb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_bin_table, dim3((a.ntiles + 255) / 256), dim3(256), 0, s, a);

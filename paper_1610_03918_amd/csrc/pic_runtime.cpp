@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -203,6 +204,12 @@ struct pic_ctx {
     int inner_chunk = 12;
     pic_solve_info last{};
     std::string err;
+    // solver graphs: one outer pass (inner start, K iterations, phi update,
+    // float64 residual) captured per K and replayed on the caller's stream
+    hipStream_t cap_stream = nullptr;
+    std::map<int, hipGraphExec_t> outer_graphs;
+    bool use_graphs = true;
+    double eta2_host = 0.0;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev0, ev1;
@@ -448,12 +455,85 @@ pic_status read_scalars(pic_ctx *c, double *S, int *F)
     return PIC_OK;
 }
 
+// Kernels of one outer pass: inner preconditioned CG from e = 0 with K
+// iterations (later ones return at once after the stop test), phi += e and
+// the float64 residual with its norm.
+void enqueue_outer(pic_ctx *c, int K, double eta2, hipStream_t st)
+{
+    Red r = red_of(c);
+    LevelDev L0 = level(c, 0);
+    const int mg = c->L.mg ? 1 : 0;
+    const hipStream_t keep = c->stream;
+    c->stream = st;
+    launch_init_red0(c->g, L0, c->d_e, eta2, mg, r, st);
+    if (mg) enqueue_vcycle_rest(c);
+    for (int k = 0; k < K; k++) {
+        const float *pold = c->d_p[k & 1];
+        float *pnew = c->d_p[(k + 1) & 1];
+        launch_pupdate_Ap(c->g, L0, pold, pnew, c->d_q, k == 0 ? 1 : 0, r, st);
+        launch_update_red0(c->g, L0, pnew, c->d_q, c->d_e, mg, r, st);
+        if (mg) enqueue_vcycle_rest(c);
+    }
+    launch_phi_update(c->g, c->d_fix[0], c->d_e, c->buf.phi, st);
+    launch_resid64(c->g, c->d_fix[0], c->buf.b, c->buf.phi, L0.g, r, st);
+    c->stream = keep;
+}
+
+int round_chunk(int k)
+{
+    static const int steps[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+    for (int v : steps)
+        if (k <= v) return v;
+    return k;
+}
+
+// The stop ratio of the inner solve is passed through S_ETA2 by a tiny copy
+// so one captured graph serves every ratio.
+pic_status run_outer(pic_ctx *c, int K, double eta2)
+{
+    if (!c->use_graphs || K > 128) {
+        enqueue_outer(c, K, eta2, c->stream);
+        HIPCHK(c, hipGetLastError());
+        return PIC_OK;
+    }
+    auto it = c->outer_graphs.find(K);
+    if (it == c->outer_graphs.end()) {
+        if (!c->cap_stream)
+            HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        enqueue_outer(c, K, -1.0, c->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e1 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e1 != hipSuccess || !g) {
+            c->use_graphs = false;
+            (void)hipGetLastError();
+            enqueue_outer(c, K, eta2, c->stream);
+            return PIC_OK;
+        }
+        hipGraphExec_t ex = nullptr;
+        hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            c->use_graphs = false;
+            (void)hipGetLastError();
+            enqueue_outer(c, K, eta2, c->stream);
+            return PIC_OK;
+        }
+        it = c->outer_graphs.emplace(K, ex).first;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_S + S_ETA2, &c->eta2_host, sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    return PIC_OK;
+}
+
 pic_status do_solve(pic_ctx *c, int kind, const double *guess, pic_solve_info *info)
 {
     Red r = red_of(c);
     LevelDev L0 = level(c, 0);
     if (kind == 0 || kind == 2)
         launch_set_guess(c->g, c->d_fix[0], kind, guess, c->buf.phi, c->stream);
+    if (c->g.px && c->g.py) launch_pin_shift(c->g, c->buf.phi, r, c->stream);
     launch_resid64(c->g, c->d_fix[0], c->buf.b, c->buf.phi, L0.g, r, c->stream);
     double S[S_NSCAL];
     int F[F_NFLAG];
@@ -468,25 +548,18 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess, pic_solve_info *i
     while (relres > c->cfg.rtol && total < c->cfg.max_iter && outer < 64 && std::isfinite(relres)) {
         double eta = 0.3 * c->cfg.rtol / relres;
         eta = std::min(0.5, std::max(eta, mg ? 2e-6 : 1e-5));
-        launch_init_red0(c->g, L0, c->d_e, eta * eta, mg, r, c->stream);
-        if (mg) enqueue_vcycle_rest(c);
-        const int K = std::max(1, std::min(c->inner_chunk, c->cfg.max_iter - total));
-        for (int k = 0; k < K; k++) {
-            const float *pold = c->d_p[k & 1];
-            float *pnew = c->d_p[(k + 1) & 1];
-            launch_pupdate_Ap(c->g, L0, pold, pnew, c->d_q, k == 0 ? 1 : 0, r, c->stream);
-            launch_update_red0(c->g, L0, pnew, c->d_q, c->d_e, mg, r, c->stream);
-            if (mg) enqueue_vcycle_rest(c);
-        }
-        launch_phi_update(c->g, c->d_fix[0], c->d_e, c->buf.phi, c->stream);
-        launch_resid64(c->g, c->d_fix[0], c->buf.b, c->buf.phi, L0.g, r, c->stream);
+        c->eta2_host = eta * eta;
+        int K = std::max(1, std::min(c->inner_chunk, c->cfg.max_iter - total));
+        K = round_chunk(K);
+        st = run_outer(c, K, c->eta2_host);
+        if (st != PIC_OK) return st;
         st = read_scalars(c, S, F);
         if (st != PIC_OK) return st;
         total += F[F_ITER];
         outer++;
         relres = std::sqrt(S[S_RR64] / bb);
         if (F[F_DONE]) c->inner_chunk = std::max(2, F[F_ITER] + 1);
-        else c->inner_chunk = std::min(4 * K, mg ? 64 : 4096);
+        else c->inner_chunk = std::min(2 * K, mg ? 64 : 4096);
     }
     if (c->g.px && c->g.py) launch_shift_mean(c->g, c->buf.phi, r, c->stream);
     si.iterations = total;
@@ -839,6 +912,8 @@ void pic_destroy(pic_ctx *c)
 {
     if (!c) return;
     if (c->d_E4) (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->outer_graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto e : c->ev0) if (e) (void)hipEventDestroy(e);
     for (auto e : c->ev1) if (e) (void)hipEventDestroy(e);
     delete c;
