@@ -13,6 +13,7 @@ constexpr int kGridBX = 64;      // grid kernels: 64 x 4 threads over (y, x) nod
 constexpr int kGridBY = 4;
 constexpr int kPushThreads = 256;
 constexpr int kUnroll = 4;        // particles per thread per pass of the push loop
+constexpr int kMergeKeys = 4;     // distinct cells merged per wavefront before plain LDS atomics
 
 struct Geom {
     int nx, ny;     // cells

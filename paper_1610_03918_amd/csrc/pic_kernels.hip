@@ -455,7 +455,10 @@ __device__ __forceinline__ float node_resid(const float *u, const float *gg, con
 }
 
 // Restricted residual at coarse node (I, J): sum over the 3x3 fine stencil
-// around (2I, 2J) of weight * residual at free fine nodes.
+// around (2I, 2J) of weight * residual at free fine nodes.  It is always
+// taken right after a black half-sweep, which leaves zero residual on the
+// black nodes (the four edge neighbours, weight 1/2), so only the red ones
+// are evaluated: the centre (weight 1) and the four diagonals (weight 1/4).
 __device__ __forceinline__ float restrict_node(const float *u, const float *gg, const uint8_t *fix,
                                                int NX, int NY, int px, int py, int I, int J)
 {
@@ -464,13 +467,14 @@ __device__ __forceinline__ float restrict_node(const float *u, const float *gg, 
     for (int di = -1; di <= 1; di++) {
 #pragma unroll
         for (int dj = -1; dj <= 1; dj++) {
+            if ((di + dj) & 1) continue;
             int a = 2 * I + di, c = 2 * J + dj;
             if (px) a = wrap_hi(wrap_lo(a, NX), NX);
             else if (a < 0 || a >= NX) continue;
             if (py) c = wrap_hi(wrap_lo(c, NY), NY);
             else if (c < 0 || c >= NY) continue;
             if (fix[(long long)a * NY + c]) continue;
-            float w = (di == 0 ? 1.0f : 0.5f) * (dj == 0 ? 1.0f : 0.5f);
+            const float w = (di == 0) ? 1.0f : 0.25f;
             acc += w * node_resid(u, gg, fix, a, c, NX, NY);
         }
     }
@@ -787,6 +791,133 @@ void launch_coarse(const CoarseArgs &a, const int *done, hipStream_t s)
 // particles: gather, leapfrog push, wall test, deposit (eqs. 1-4)
 // ---------------------------------------------------------------------------
 
+// Sum of a 32-bit value over the 64 lanes (all active); lane 63 holds the
+// total, returned as a wave-uniform value.  Row-local butterflies (quad
+// permutes and row mirrors) give every lane its row sum, then two row
+// broadcasts carry the sums of rows 0-2 upward.
+__device__ __forceinline__ unsigned wave_sum_u32(unsigned x)
+{
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false); // row half mirror
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false); // row mirror
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false); // row bcast 15
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false); // row bcast 31
+    return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Leapfrog push of one particle with the bilinear gather of its cell's
+// corner fields and the cell-by-cell wall test (eqs. 1-4).  Updates the
+// particle in memory; returns false when it was removed (class in *dead).
+__device__ __forceinline__ bool push_particle(const PushArgs &a, int p, int c, float &x0, float &y0,
+                                              float vx0, float vy0, float4 ea, float4 eb, int &ci,
+                                              int &cj, int &dead, int &ei, int &ej, float &ux,
+                                              float &uy)
+{
+    const Geom &g = a.g;
+    const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
+    const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
+    float ex = w00 * ea.x;
+    ex = ex + w10 * ea.z;
+    ex = ex + w01 * eb.x;
+    ex = ex + w11 * eb.z;
+    float ey = w00 * ea.y;
+    ey = ey + w10 * ea.w;
+    ey = ey + w01 * eb.y;
+    ey = ey + w11 * eb.w;
+    ux = vx0 + a.qdt * ex;
+    uy = vy0 + a.qdt * ey;
+    const float Dx = ux * a.dtf, Dy = uy * a.dtf;
+    const float x1 = x0 + Dx, y1 = y0 + Dy;
+    const float fsx = floorf(x1), fsy = floorf(y1);
+    a.vx[p] = ux;
+    a.vy[p] = uy;
+    dead = -1;
+    ei = ci;
+    ej = cj;
+    int sx = 0, sy = 0;
+    if (!(fabsf(fsx) < 1.0e6f && fabsf(fsy) < 1.0e6f)) {
+        dead = 8;
+    } else {
+        sx = (int)fsx;
+        sy = (int)fsy;
+        if (sx != 0 || sy != 0) {
+            // walk the straight segment cell by cell; the earlier face first,
+            // compared as (fx + kx)|Dy| <= (fy + ky)|Dx| (ties cross x)
+            const float ax = fabsf(Dx), ay = fabsf(Dy);
+            const float fx = sx > 0 ? 1.0f - x0 : x0, fy = sy > 0 ? 1.0f - y0 : y0;
+            const int nxs = abs(sx), nys = abs(sy);
+            const int di = sx > 0 ? 1 : -1, dj = sy > 0 ? 1 : -1;
+            int kx = 0, ky = 0;
+            while (kx < nxs || ky < nys) {
+                bool gox;
+                if (ky >= nys) gox = true;
+                else if (kx >= nxs) gox = false;
+                else gox = ((fx + (float)kx) * ay <= (fy + (float)ky) * ax);
+                int ni = ei, nj = ej, dir;
+                if (gox) { ni = ei + di; kx++; dir = di > 0 ? 0 : 1; }
+                else { nj = ej + dj; ky++; dir = dj > 0 ? 2 : 3; }
+                bool out = false;
+                if (g.px) ni = wrap_hi(wrap_lo(ni, g.nx), g.nx);
+                else if (ni < 0 || ni >= g.nx) out = true;
+                if (g.py) nj = wrap_hi(wrap_lo(nj, g.ny), g.ny);
+                else if (nj < 0 || nj >= g.ny) out = true;
+                if (!out && a.cell_cond[(long long)ni * g.ny + nj]) out = true;
+                if (out) {
+                    const bool inbox = ei >= a.box_i_top && ej >= a.box_j_lo && ej < a.box_j_hi;
+                    dead = dir + (inbox ? 4 : 0);
+                    break;
+                }
+                ei = ni;
+                ej = nj;
+            }
+        }
+    }
+    if (dead >= 0) {
+        a.cell[p] = -1 - dead;
+        return false;
+    }
+    float nxo = x1 - (float)sx, nyo = y1 - (float)sy;
+    if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
+    if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
+    a.ox[p] = nxo;
+    a.oy[p] = nyo;
+    const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
+    if (nc != c) a.cell[p] = nc;
+    x0 = nxo;
+    y0 = nyo;
+    ci = ei;
+    cj = ej;
+    return true;
+}
+
+// Records a removal: class counter in LDS, trench-bottom charge, hit ring.
+__device__ __forceinline__ void record_hit(const PushArgs &a, unsigned *tl, int dead, int ei, int ej,
+                                           float ux, float uy)
+{
+    atomicAdd(&tl[dead], 1u);
+    if (a.surf && dead == 4) atomicAdd(&a.surf[ej], 1ull);
+    if (a.log.rec && ((a.log.species_mask >> a.species) & 1)) {
+        unsigned long long k = atomicAdd(a.log.count, 1ull);
+        long long slot = (long long)(k % (unsigned long long)a.log.capacity);
+        int32_t *r = a.log.rec + 6 * slot;
+        r[0] = (a.species << 8) | dead;
+        r[1] = (int)(((unsigned)ei << 16) | (unsigned)ej);
+        r[2] = __float_as_int(ux);
+        r[3] = __float_as_int(uy);
+        r[4] = a.step;
+        r[5] = 0;
+    }
+}
+
+// One tile of particles per block (table entry): gather + push + wall test,
+// then area weighting of the new positions into the block's LDS window of
+// cell moments (count, sum ux, sum uy, sum ux*uy with ux, uy the 16-bit
+// quantised offsets).  Lanes of a wavefront that land in the same cell are
+// summed first (up to kMergeKeys distinct cells per wavefront), so sorted
+// particles cost one LDS atomic per cell rather than one per particle.
+// Particles that drifted beyond the window add their four corner weights to
+// global memory directly.  The window is flushed to the node charge at the end.
 template <bool PUSH>
 __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
 {
@@ -802,6 +933,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
     unsigned *mC = (unsigned *)(mB + WC);
     unsigned *tl = mC + WC;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
     for (int k = tid; k < WC; k += kPushThreads) {
         mA[k] = 0ull;
         mB[k] = 0ull;
@@ -814,153 +946,102 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
     unsigned long long nfb = 0;
     // kUnroll particles per thread per pass: all their loads are issued
     // before any is used, so each wave keeps several requests in flight.
-    for (int base = start + tid; base < end; base += kUnroll * kPushThreads) {
-    int cu[kUnroll];
-    float xu[kUnroll], yu[kUnroll], vxu[kUnroll], vyu[kUnroll];
-    float4 eau[kUnroll], ebu[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
-        const int p = base + u * kPushThreads;
-        cu[u] = (p < end) ? a.cell[p] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
-        const int p = base + u * kPushThreads;
-        if (p < end) {
-            xu[u] = a.ox[p];
-            yu[u] = a.oy[p];
-            if (PUSH) {
-                vxu[u] = a.vx[p];
-                vyu[u] = a.vy[p];
-            }
-        }
-    }
-    if (PUSH) {
+    // The loop bound is uniform per block so whole wavefronts stay active.
+    for (int base = start; base < end; base += kUnroll * kPushThreads) {
+        int cu[kUnroll];
+        float xu[kUnroll], yu[kUnroll], vxu[kUnroll], vyu[kUnroll];
+        float4 eau[kUnroll], ebu[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; u++) {
-            const int c = cu[u] < 0 ? 0 : cu[u];
-            const long long cc = (long long)((unsigned)c >> 16) * g.ny + (c & 0xFFFF);
-            eau[u] = a.E4[2 * cc];
-            ebu[u] = a.E4[2 * cc + 1];
+            const int p = base + u * kPushThreads + tid;
+            cu[u] = (p < end) ? a.cell[p] : -1;
         }
-    }
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
-        const int p = base + u * kPushThreads;
-        int c = cu[u];
-        if (c < 0) continue;
-        float x0 = xu[u], y0 = yu[u];
-        int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
+        for (int u = 0; u < kUnroll; u++) {
+            const int p = base + u * kPushThreads + tid;
+            if (p < end) {
+                xu[u] = a.ox[p];
+                yu[u] = a.oy[p];
+                if (PUSH) {
+                    vxu[u] = a.vx[p];
+                    vyu[u] = a.vy[p];
+                }
+            }
+        }
         if (PUSH) {
-            const float4 ea = eau[u], eb = ebu[u];
-            const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
-            const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
-            float ex = w00 * ea.x;
-            ex = ex + w10 * ea.z;
-            ex = ex + w01 * eb.x;
-            ex = ex + w11 * eb.z;
-            float ey = w00 * ea.y;
-            ey = ey + w10 * ea.w;
-            ey = ey + w01 * eb.y;
-            ey = ey + w11 * eb.w;
-            const float ux = vxu[u] + a.qdt * ex;
-            const float uy = vyu[u] + a.qdt * ey;
-            const float Dx = ux * a.dtf, Dy = uy * a.dtf;
-            const float x1 = x0 + Dx, y1 = y0 + Dy;
-            const float fsx = floorf(x1), fsy = floorf(y1);
-            a.vx[p] = ux;
-            a.vy[p] = uy;
-            int dead = -1;
-            int ei = ci, ej = cj;
-            int sx = 0, sy = 0;
-            if (!(fabsf(fsx) < 1.0e6f && fabsf(fsy) < 1.0e6f)) {
-                dead = 8;
-            } else {
-                sx = (int)fsx;
-                sy = (int)fsy;
-                if (sx != 0 || sy != 0) {
-                    const float ax = fabsf(Dx), ay = fabsf(Dy);
-                    const float fx = sx > 0 ? 1.0f - x0 : x0, fy = sy > 0 ? 1.0f - y0 : y0;
-                    const int nxs = abs(sx), nys = abs(sy);
-                    const int di = sx > 0 ? 1 : -1, dj = sy > 0 ? 1 : -1;
-                    int kx = 0, ky = 0;
-                    while (kx < nxs || ky < nys) {
-                        bool gox;
-                        if (ky >= nys) gox = true;
-                        else if (kx >= nxs) gox = false;
-                        else gox = ((fx + (float)kx) * ay <= (fy + (float)ky) * ax);
-                        int ni = ei, nj = ej, dir;
-                        if (gox) { ni = ei + di; kx++; dir = di > 0 ? 0 : 1; }
-                        else { nj = ej + dj; ky++; dir = dj > 0 ? 2 : 3; }
-                        bool out = false;
-                        if (g.px) ni = wrap_hi(wrap_lo(ni, g.nx), g.nx);
-                        else if (ni < 0 || ni >= g.nx) out = true;
-                        if (g.py) nj = wrap_hi(wrap_lo(nj, g.ny), g.ny);
-                        else if (nj < 0 || nj >= g.ny) out = true;
-                        if (!out && a.cell_cond[(long long)ni * g.ny + nj]) out = true;
-                        if (out) {
-                            bool inbox = ei >= a.box_i_top && ej >= a.box_j_lo && ej < a.box_j_hi;
-                            dead = dir + (inbox ? 4 : 0);
-                            break;
-                        }
-                        ei = ni;
-                        ej = nj;
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++) {
+                const int c = cu[u] < 0 ? 0 : cu[u];
+                const long long cc = (long long)((unsigned)c >> 16) * g.ny + (c & 0xFFFF);
+                eau[u] = a.E4[2 * cc];
+                ebu[u] = a.E4[2 * cc + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const int p = base + u * kPushThreads + tid;
+            int c = cu[u];
+            int key = -1;
+            unsigned ux = 0, uy = 0;
+            if (c >= 0) {
+                float x0 = xu[u], y0 = yu[u];
+                int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
+                bool alive = true;
+                if (PUSH) {
+                    int dead, ei, ej;
+                    float vnx, vny;
+                    alive = push_particle(a, p, c, x0, y0, vxu[u], vyu[u], eau[u], ebu[u], ci, cj,
+                                          dead, ei, ej, vnx, vny);
+                    if (!alive) record_hit(a, tl, dead, ei, ej, vnx, vny);
+                }
+                if (alive) {
+                    ux = (unsigned)floorf(x0 * 65536.0f);
+                    uy = (unsigned)floorf(y0 * 65536.0f);
+                    int wi = ci - i0, wj = cj - j0;
+                    if (g.px) { if (wi < 0) wi += g.nx; else if (wi >= g.nx) wi -= g.nx; }
+                    if (g.py) { if (wj < 0) wj += g.ny; else if (wj >= g.ny) wj -= g.ny; }
+                    if (wi >= 0 && wi < WX && wj >= 0 && wj < WY) {
+                        key = wi * WY + wj;
+                    } else {
+                        const unsigned long long S = 65536ull;
+                        const int i1 = g.px ? wrap_hi(ci + 1, g.nx) : ci + 1;
+                        const int j1 = g.py ? wrap_hi(cj + 1, g.ny) : cj + 1;
+                        const unsigned long long X = ux, Y = uy;
+                        atomicAdd(&a.rho[(long long)ci * g.NY + cj], (S - X) * (S - Y));
+                        atomicAdd(&a.rho[(long long)i1 * g.NY + cj], X * (S - Y));
+                        atomicAdd(&a.rho[(long long)ci * g.NY + j1], (S - X) * Y);
+                        atomicAdd(&a.rho[(long long)i1 * g.NY + j1], X * Y);
+                        nfb++;
                     }
                 }
             }
-            if (dead >= 0) {
-                a.cell[p] = -1 - dead;
-                atomicAdd(&tl[dead], 1u);
-                if (a.surf && dead == 4) atomicAdd(&a.surf[ej], 1ull);
-                if (a.log.rec && ((a.log.species_mask >> a.species) & 1)) {
-                    unsigned long long k = atomicAdd(a.log.count, 1ull);
-                    long long slot = (long long)(k % (unsigned long long)a.log.capacity);
-                    int32_t *r = a.log.rec + 6 * slot;
-                    r[0] = (a.species << 8) | dead;
-                    r[1] = (int)(((unsigned)ei << 16) | (unsigned)ej);
-                    r[2] = __float_as_int(ux);
-                    r[3] = __float_as_int(uy);
-                    r[4] = a.step;
-                    r[5] = 0;
-                }
-                continue;
-            }
-            float nxo = x1 - (float)sx, nyo = y1 - (float)sy;
-            if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
-            if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
-            a.ox[p] = nxo;
-            a.oy[p] = nyo;
-            const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
-            if (nc != c) a.cell[p] = nc;
-            x0 = nxo;
-            y0 = nyo;
-            ci = ei;
-            cj = ej;
-        }
-        // area weighting, integer moments of the cell (exact, order-free)
-        const unsigned ux = (unsigned)floorf(x0 * 65536.0f);
-        const unsigned uy = (unsigned)floorf(y0 * 65536.0f);
-        int wi = ci - i0, wj = cj - j0;
-        if (g.px) { if (wi < 0) wi += g.nx; else if (wi >= g.nx) wi -= g.nx; }
-        if (g.py) { if (wj < 0) wj += g.ny; else if (wj >= g.ny) wj -= g.ny; }
-        if (wi >= 0 && wi < WX && wj >= 0 && wj < WY) {
-            const int k = wi * WY + wj;
+            // wavefront merge of equal cells (all lanes take part)
             const unsigned m3 = ux * uy;
-            atomicAdd(&mA[k], ((unsigned long long)ux << 32) | 1ull);
-            atomicAdd(&mB[k], ((unsigned long long)uy << 32) | (unsigned long long)(m3 >> 16));
-            atomicAdd(&mC[k], m3 & 0xFFFFu);
-        } else {
-            const unsigned long long S = 65536ull;
-            const int i1 = g.px ? wrap_hi(ci + 1, g.nx) : ci + 1;
-            const int j1 = g.py ? wrap_hi(cj + 1, g.ny) : cj + 1;
-            const unsigned long long X = ux, Y = uy;
-            atomicAdd(&a.rho[(long long)ci * g.NY + cj], (S - X) * (S - Y));
-            atomicAdd(&a.rho[(long long)i1 * g.NY + cj], X * (S - Y));
-            atomicAdd(&a.rho[(long long)ci * g.NY + j1], (S - X) * Y);
-            atomicAdd(&a.rho[(long long)i1 * g.NY + j1], X * Y);
-            nfb++;
+            unsigned long long pend = __ballot(key >= 0);
+            for (int it = 0; it < kMergeKeys && pend; it++) {
+                const int leader = __builtin_ctzll(pend);
+                const int lk = __builtin_amdgcn_readlane(key, leader);
+                const bool m = key == lk;
+                const unsigned long long mask = __ballot(m);
+                const unsigned sx = wave_sum_u32(m ? ux : 0u);
+                const unsigned sy = wave_sum_u32(m ? uy : 0u);
+                const unsigned sh = wave_sum_u32(m ? (m3 >> 16) : 0u);
+                const unsigned sl = wave_sum_u32(m ? (m3 & 0xFFFFu) : 0u);
+                if (lane == leader) {
+                    const unsigned cnt = (unsigned)__popcll(mask);
+                    atomicAdd(&mA[lk], ((unsigned long long)sx << 32) | cnt);
+                    atomicAdd(&mB[lk], ((unsigned long long)sy << 32) | sh);
+                    atomicAdd(&mC[lk], sl);
+                }
+                if (m) key = -1;
+                pend &= ~mask;
+            }
+            if (key >= 0) {
+                atomicAdd(&mA[key], ((unsigned long long)ux << 32) | 1ull);
+                atomicAdd(&mB[key], ((unsigned long long)uy << 32) | (unsigned long long)(m3 >> 16));
+                atomicAdd(&mC[key], m3 & 0xFFFFu);
+            }
         }
-    }
     }
     if (nfb) atomicAdd(a.fallbacks, nfb);
     __syncthreads();

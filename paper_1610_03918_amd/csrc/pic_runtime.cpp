@@ -711,7 +711,7 @@ pic_status pic_init(const pic_config *cfg, const pic_buffers *buf, void *stream,
         ca.px = L.px;
         ca.py = L.py;
         const int last = ca.nlev - 1;
-        ca.sweeps = std::min(64, std::max(8, 2 * std::max(ca.NX[last], ca.NY[last])));
+        ca.sweeps = std::min(64, std::max(2, std::max(ca.NX[last], ca.NY[last])));
     }
     // zero counters and scalars
     HIPCHK(c, hipMemsetAsync(c->d_S, 0, sizeof(double) * S_NSCAL, s));
