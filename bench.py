@@ -67,6 +67,11 @@ def main():
     ap.add_argument("--workload", default="trench1024x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort", default="8,64")
+    ap.add_argument("--unroll", type=int, default=2)
+    ap.add_argument("--merge", type=int, default=0)
+    ap.add_argument("--tile", default="16,16")
+    ap.add_argument("--chunk", type=int, default=8192)
+    ap.add_argument("--halo", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -85,7 +90,10 @@ def main():
     n0 = [p["cell"].size for p in parts]
     log(f"loaded {n0} particles in {time.perf_counter() - t:.1f}s")
     sort = tuple(int(x) for x in args.sort.split(","))
-    pic = Pic(w, parts, device="cuda:0", sort_interval=sort)
+    tile = tuple(int(x) for x in args.tile.split(","))
+    opts = dict(sort_interval=sort, push_unroll=args.unroll, push_merge=args.merge, tile=tile,
+                chunk=args.chunk, halo=args.halo)
+    pic = Pic(w, parts, device="cuda:0", **opts)
     info0 = pic.start()
     log(f"start solve: {info0}")
     for _ in range(args.warmup):
@@ -127,7 +135,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "cells": [w.nx, w.ny], "ppc": w.species[0].ppc,
-                   "particles": n0, "dt": w.dt, "rtol": w.rtol, "sort_interval": list(sort)},
+                   "particles": n0, "dt": w.dt, "rtol": w.rtol, "sort_interval": list(sort),
+                   "tile": list(tile), "chunk": args.chunk, "halo": args.halo,
+                   "push_unroll": args.unroll, "push_merge": args.merge},
         "poisson_ms_per_step": 1e3 * solve_t / args.steps,
         "poisson_iters_per_step": iters / args.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

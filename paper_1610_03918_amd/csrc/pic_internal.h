@@ -12,8 +12,6 @@ constexpr int kNClass = 9;
 constexpr int kGridBX = 64;      // grid kernels: 64 x 4 threads over (y, x) nodes
 constexpr int kGridBY = 4;
 constexpr int kPushThreads = 256;
-constexpr int kUnroll = 4;        // particles per thread per pass of the push loop
-constexpr int kMergeKeys = 4;     // distinct cells merged per wavefront before plain LDS atomics
 
 struct Geom {
     int nx, ny;     // cells
@@ -142,7 +140,8 @@ void launch_restrict(const Geom &g, const LevelDev &F, const LevelDev &Cc, const
 void launch_prolong_black(const Geom &g, const LevelDev &F, const LevelDev &Cc, const int *done,
                           hipStream_t s);
 void launch_coarse(const CoarseArgs &a, const int *done, hipStream_t s);
-void launch_push(const PushArgs &a, int max_blocks, bool push, hipStream_t s);
+void launch_push(const PushArgs &a, int max_blocks, bool push, int unroll, int merge,
+                 hipStream_t s);
 void launch_rewind(const Geom &g, const float4 *E4, const int32_t *cell, const float *ox,
                    const float *oy, float *vx, float *vy, long long n, const long long *slots,
                    float hq, hipStream_t s);

@@ -791,20 +791,30 @@ void launch_coarse(const CoarseArgs &a, const int *done, hipStream_t s)
 // particles: gather, leapfrog push, wall test, deposit (eqs. 1-4)
 // ---------------------------------------------------------------------------
 
-// Sum of a 32-bit value over the 64 lanes (all active); lane 63 holds the
-// total, returned as a wave-uniform value.  Row-local butterflies (quad
-// permutes and row mirrors) give every lane its row sum, then two row
-// broadcasts carry the sums of rows 0-2 upward.
-__device__ __forceinline__ unsigned wave_sum_u32(unsigned x)
+// Sums of four 32-bit values over the 64 lanes (all lanes active), returned
+// as wave-uniform values.  Row-local butterflies (quad permutes, row
+// mirrors) give every lane its row sum, then two row broadcasts carry the
+// sums of rows 0-2 upward to lane 63.  The four chains are interleaved so
+// the DPP read-after-write wait states are filled with useful work.
+#define DPP_STEP(ctrl, rmask)                                                                  \
+    a += (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, ctrl, rmask, 0xF, false);            \
+    b += (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, ctrl, rmask, 0xF, false);            \
+    c += (unsigned)__builtin_amdgcn_update_dpp(0, (int)c, ctrl, rmask, 0xF, false);            \
+    d += (unsigned)__builtin_amdgcn_update_dpp(0, (int)d, ctrl, rmask, 0xF, false);
+__device__ __forceinline__ void wave_sum4_u32(unsigned &a, unsigned &b, unsigned &c, unsigned &d)
 {
-    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
-    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
-    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false); // row half mirror
-    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false); // row mirror
-    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false); // row bcast 15
-    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false); // row bcast 31
-    return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+    DPP_STEP(0xB1, 0xF)   // quad_perm [1,0,3,2]
+    DPP_STEP(0x4E, 0xF)   // quad_perm [2,3,0,1]
+    DPP_STEP(0x141, 0xF)  // row_half_mirror
+    DPP_STEP(0x140, 0xF)  // row_mirror
+    DPP_STEP(0x142, 0xA)  // row_bcast:15 into rows 1, 3
+    DPP_STEP(0x143, 0xC)  // row_bcast:31 into rows 2, 3
+    a = (unsigned)__builtin_amdgcn_readlane((int)a, 63);
+    b = (unsigned)__builtin_amdgcn_readlane((int)b, 63);
+    c = (unsigned)__builtin_amdgcn_readlane((int)c, 63);
+    d = (unsigned)__builtin_amdgcn_readlane((int)d, 63);
 }
+#undef DPP_STEP
 
 // Leapfrog push of one particle with the bilinear gather of its cell's
 // corner fields and the cell-by-cell wall test (eqs. 1-4).  Updates the
@@ -914,11 +924,11 @@ __device__ __forceinline__ void record_hit(const PushArgs &a, unsigned *tl, int 
 // then area weighting of the new positions into the block's LDS window of
 // cell moments (count, sum ux, sum uy, sum ux*uy with ux, uy the 16-bit
 // quantised offsets).  Lanes of a wavefront that land in the same cell are
-// summed first (up to kMergeKeys distinct cells per wavefront), so sorted
-// particles cost one LDS atomic per cell rather than one per particle.
+// summed first when MERGE > 0 (up to MERGE distinct cells per wavefront),
+// so runs of particles in one cell cost one LDS atomic per cell.
 // Particles that drifted beyond the window add their four corner weights to
 // global memory directly.  The window is flushed to the node charge at the end.
-template <bool PUSH>
+template <bool PUSH, int U, int MERGE>
 __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -928,36 +938,36 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
     const int ti = tile / a.tiles_y, tj = tile - ti * a.tiles_y;
     const int i0 = ti * a.TX - a.H, j0 = tj * a.TY - a.H;
     const int WX = a.WX, WY = a.WY, WC = WX * WY;
+    // per window cell: mA = count << 45 | sum(ux*uy), mB = sum(ux) | sum(uy) << 29
+    // (at most 8192 particles per block keep every field free of carries)
     unsigned long long *mA = (unsigned long long *)smem;
     unsigned long long *mB = mA + WC;
-    unsigned *mC = (unsigned *)(mB + WC);
-    unsigned *tl = mC + WC;
+    unsigned *tl = (unsigned *)(mB + WC);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     for (int k = tid; k < WC; k += kPushThreads) {
         mA[k] = 0ull;
         mB[k] = 0ull;
-        mC[k] = 0u;
     }
     if (tid < kNClass) tl[tid] = 0u;
     __syncthreads();
 
     const Geom g = a.g;
     unsigned long long nfb = 0;
-    // kUnroll particles per thread per pass: all their loads are issued
+    // U particles per thread per pass: all their loads are issued
     // before any is used, so each wave keeps several requests in flight.
     // The loop bound is uniform per block so whole wavefronts stay active.
-    for (int base = start; base < end; base += kUnroll * kPushThreads) {
-        int cu[kUnroll];
-        float xu[kUnroll], yu[kUnroll], vxu[kUnroll], vyu[kUnroll];
-        float4 eau[kUnroll], ebu[kUnroll];
+    for (int base = start; base < end; base += U * kPushThreads) {
+        int cu[U];
+        float xu[U], yu[U], vxu[U], vyu[U];
+        float4 eau[U], ebu[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
+        for (int u = 0; u < U; u++) {
             const int p = base + u * kPushThreads + tid;
             cu[u] = (p < end) ? a.cell[p] : -1;
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
+        for (int u = 0; u < U; u++) {
             const int p = base + u * kPushThreads + tid;
             if (p < end) {
                 xu[u] = a.ox[p];
@@ -970,7 +980,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
         }
         if (PUSH) {
 #pragma unroll
-            for (int u = 0; u < kUnroll; u++) {
+            for (int u = 0; u < U; u++) {
                 const int c = cu[u] < 0 ? 0 : cu[u];
                 const long long cc = (long long)((unsigned)c >> 16) * g.ny + (c & 0xFFFF);
                 eau[u] = a.E4[2 * cc];
@@ -978,7 +988,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
             }
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
+        for (int u = 0; u < U; u++) {
             const int p = base + u * kPushThreads + tid;
             int c = cu[u];
             int key = -1;
@@ -1017,29 +1027,29 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
             }
             // wavefront merge of equal cells (all lanes take part)
             const unsigned m3 = ux * uy;
-            unsigned long long pend = __ballot(key >= 0);
-            for (int it = 0; it < kMergeKeys && pend; it++) {
-                const int leader = __builtin_ctzll(pend);
-                const int lk = __builtin_amdgcn_readlane(key, leader);
-                const bool m = key == lk;
-                const unsigned long long mask = __ballot(m);
-                const unsigned sx = wave_sum_u32(m ? ux : 0u);
-                const unsigned sy = wave_sum_u32(m ? uy : 0u);
-                const unsigned sh = wave_sum_u32(m ? (m3 >> 16) : 0u);
-                const unsigned sl = wave_sum_u32(m ? (m3 & 0xFFFFu) : 0u);
-                if (lane == leader) {
-                    const unsigned cnt = (unsigned)__popcll(mask);
-                    atomicAdd(&mA[lk], ((unsigned long long)sx << 32) | cnt);
-                    atomicAdd(&mB[lk], ((unsigned long long)sy << 32) | sh);
-                    atomicAdd(&mC[lk], sl);
+            if (MERGE > 0) {
+                unsigned long long pend = __ballot(key >= 0);
+                for (int it = 0; it < MERGE && pend; it++) {
+                    const int leader = __builtin_ctzll(pend);
+                    const int lk = __builtin_amdgcn_readlane(key, leader);
+                    const bool m = key == lk;
+                    const unsigned long long mask = __ballot(m);
+                    unsigned sx = m ? ux : 0u, sy = m ? uy : 0u;
+                    unsigned sh = m ? (m3 >> 16) : 0u, sl = m ? (m3 & 0xFFFFu) : 0u;
+                    wave_sum4_u32(sx, sy, sh, sl);
+                    if (lane == leader) {
+                        const unsigned long long cnt = (unsigned long long)__popcll(mask);
+                        const unsigned long long s3 = ((unsigned long long)sh << 16) + sl;
+                        atomicAdd(&mA[lk], (cnt << 45) + s3);
+                        atomicAdd(&mB[lk], (unsigned long long)sx | ((unsigned long long)sy << 29));
+                    }
+                    if (m) key = -1;
+                    pend &= ~mask;
                 }
-                if (m) key = -1;
-                pend &= ~mask;
             }
             if (key >= 0) {
-                atomicAdd(&mA[key], ((unsigned long long)ux << 32) | 1ull);
-                atomicAdd(&mB[key], ((unsigned long long)uy << 32) | (unsigned long long)(m3 >> 16));
-                atomicAdd(&mC[key], m3 & 0xFFFFu);
+                atomicAdd(&mA[key], (1ull << 45) + (unsigned long long)m3);
+                atomicAdd(&mB[key], (unsigned long long)ux | ((unsigned long long)uy << 29));
             }
         }
     }
@@ -1061,8 +1071,8 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
             if (A == 0ull) continue;
             any = true;
             const unsigned long long B = mB[m];
-            const unsigned long long M0 = A & 0xFFFFFFFFull, M1 = A >> 32, M2 = B >> 32;
-            const unsigned long long M3 = ((B & 0xFFFFFFFFull) << 16) + (unsigned long long)mC[m];
+            const unsigned long long M0 = A >> 45, M3 = A & ((1ull << 45) - 1ull);
+            const unsigned long long M1 = B & ((1ull << 29) - 1ull), M2 = B >> 29;
             if (q == 0) v += S * S * M0 - S * M1 - S * M2 + M3;  // node is the cell's 00 corner
             else if (q == 1) v += S * M1 - M3;                    // 10 corner of cell (wa-1, wb)
             else if (q == 2) v += S * M2 - M3;                    // 01 corner of cell (wa, wb-1)
@@ -1079,14 +1089,29 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
     if (PUSH && tid < kNClass && tl[tid]) atomicAdd(&a.tally[tid], (unsigned long long)tl[tid]);
 }
 
-void launch_push(const PushArgs &a, int max_blocks, bool push, hipStream_t s)
+template <bool PUSH>
+static void launch_push_t(const PushArgs &a, int max_blocks, int unroll, int merge, size_t lds,
+                          hipStream_t s)
+{
+    const dim3 gr(max_blocks), bl(kPushThreads);
+#define PUSH_CASE(U, M)                                                                   \
+    if (unroll == U && merge == M) {                                                      \
+        hipLaunchKernelGGL((k_push<PUSH, U, M>), gr, bl, lds, s, a);                      \
+        return;                                                                           \
+    }
+    PUSH_CASE(1, 0) PUSH_CASE(2, 0) PUSH_CASE(4, 0)
+    PUSH_CASE(1, 2) PUSH_CASE(2, 2) PUSH_CASE(4, 2)
+    PUSH_CASE(1, 4) PUSH_CASE(2, 4) PUSH_CASE(4, 4)
+#undef PUSH_CASE
+    hipLaunchKernelGGL((k_push<PUSH, 2, 0>), gr, bl, lds, s, a);
+}
+
+void launch_push(const PushArgs &a, int max_blocks, bool push, int unroll, int merge, hipStream_t s)
 {
     const int WC = a.WX * a.WY;
-    const size_t lds = (size_t)WC * 20 + kNClass * 4 + 16;
-    if (push)
-        hipLaunchKernelGGL(k_push<true>, dim3(max_blocks), dim3(kPushThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_push<false>, dim3(max_blocks), dim3(kPushThreads), lds, s, a);
+    const size_t lds = (size_t)WC * 16 + kNClass * 4 + 16;
+    if (push) launch_push_t<true>(a, max_blocks, unroll, merge, lds, s);
+    else launch_push_t<false>(a, max_blocks, unroll, merge, lds, s);
 }
 
 // Leapfrog start: v -= (alpha dt / 2) E(x), same gather as the push.
@@ -1169,7 +1194,7 @@ __device__ __forceinline__ bool live_code(int c, int nx, int ny)
 // with one global atomic per tile (scatter pass) and hands them out in LDS.
 // Tiles beyond kBinLds fall back to global wavefront-aggregated atomics.
 constexpr int kBinPer = 4096;
-constexpr int kBinLds = 8192;
+constexpr int kBinLds = 4096;
 
 __device__ __forceinline__ void bin_local_count(const BinArgs &a, long long lo, long long hi,
                                                 unsigned *hist, bool count_bad)
@@ -1255,18 +1280,40 @@ __global__ void k_bin_table(BinArgs a)
     }
 }
 
+__device__ __forceinline__ unsigned gcd_u(unsigned x, unsigned y)
+{
+    while (y) {
+        unsigned t = x % y;
+        x = y;
+        y = t;
+    }
+    return x;
+}
+
+// Scatter: the m particles a block sends to tile t land on its reserved
+// slots base..base+m-1 in the order r -> (r * stride) mod m, with stride
+// near 0.618 m and coprime to m.  Runs of particles from one cell are thus
+// spread over the tile's range, so the lanes of a wavefront in the push
+// mostly deposit into different cells.
 __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
 {
-    __shared__ unsigned hist[kBinLds];
+    __shared__ unsigned hist[kBinLds], base[kBinLds], mstr[kBinLds];   // mstr = m << 16 | stride
     const long long n = *a.slots;
     const long long lo = (long long)blockIdx.x * kBinPer;
     if (lo >= n) return;
     const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
     bin_local_count(a, lo, hi, hist, false);
     const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
-    // reserve: hist[t] becomes the first destination slot of this block in tile t
-    for (int k = threadIdx.x; k < nl; k += 256)
-        if (hist[k]) hist[k] = atomicAdd(&a.cursor[k], hist[k]);
+    for (int k = threadIdx.x; k < nl; k += 256) {
+        const unsigned m = hist[k];
+        if (m) {
+            base[k] = atomicAdd(&a.cursor[k], m);
+            unsigned st = (unsigned)(0.618034f * (float)m) | 1u;
+            while (gcd_u(st, m) != 1u) st++;
+            mstr[k] = (m << 16) | (st % m);
+            hist[k] = 0u;
+        }
+    }
     __syncthreads();
     for (long long p0 = lo; p0 < hi; p0 += 256) {
         const long long p = p0 + threadIdx.x;
@@ -1274,10 +1321,15 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
         if (p < hi) c = a.cell[p];
         const bool act = live_code(c, a.nx, a.ny);
         const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
-        const unsigned d0 = wave_add(hist, key, act && key < kBinLds);
+        const bool loc = act && key < kBinLds;
+        const unsigned r = wave_add(hist, key, loc);
         const unsigned d1 = wave_add(a.cursor, key, act && key >= kBinLds);
         if (act) {
-            const unsigned d = key < kBinLds ? d0 : d1;
+            unsigned d = d1;
+            if (loc) {
+                const unsigned ms = mstr[key];
+                d = base[key] + (r * (ms & 0xFFFFu)) % (ms >> 16);
+            }
             a.cell2[d] = c;
             a.ox2[d] = a.ox[p];
             a.oy2[d] = a.oy[p];

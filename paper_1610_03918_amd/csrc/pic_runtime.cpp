@@ -43,6 +43,7 @@ struct Layout {
     int lg = 0;                             // first level handled by the coarse kernel
     bool mg = false;
     int TX, TY, lx, ly, tiles_x, tiles_y, ntiles, H, chunk;
+    int unroll, merge;                      // push kernel variant
     long long max_blocks[2];
     int grid_blocks;                        // blocks of the largest grid kernel
 };
@@ -84,8 +85,12 @@ std::string validate(const pic_config *c, const int64_t *cap)
     int H = c->halo ? c->halo : 4;
     if (H < 0 || H > 64) return "halo out of range";
     int chunk = c->chunk ? c->chunk : 8192;
-    if (chunk < 256 || chunk > 65535) return "chunk must be in 256..65535";
-    size_t lds = (size_t)(tx + 2 * H) * (ty + 2 * H) * 20 + 64;
+    if (chunk < 256 || chunk > 8192) return "chunk must be in 256..8192";
+    if (c->push_unroll != 0 && c->push_unroll != 1 && c->push_unroll != 2 && c->push_unroll != 4)
+        return "push_unroll must be 0 (default), 1, 2 or 4";
+    if (c->push_merge != 0 && c->push_merge != 2 && c->push_merge != 4)
+        return "push_merge must be 0, 2 or 4";
+    size_t lds = (size_t)(tx + 2 * H) * (ty + 2 * H) * 16 + 64;
     if (lds > 64 * 1024) return "tile + halo window exceeds 64 KiB of LDS";
     if (cap && (cap[0] < 0 || cap[1] < 0 || cap[0] > 0x7fffffffLL || cap[1] > 0x7fffffffLL))
         return "capacity out of range";
@@ -165,6 +170,8 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
     L.ntiles = L.tiles_x * L.tiles_y;
     L.H = c->halo ? c->halo : 4;
     L.chunk = c->chunk ? c->chunk : 8192;
+    L.unroll = c->push_unroll ? c->push_unroll : 2;
+    L.merge = c->push_merge;
     for (int s = 0; s < 2; s++) L.max_blocks[s] = L.ntiles + (cap[s] + L.chunk - 1) / L.chunk;
     int maxrows = std::max(L.NX, L.nx), maxcols = std::max(L.NY, L.ny);
     L.grid_blocks = ((maxcols + kGridBX - 1) / kGridBX) * ((maxrows + kGridBY - 1) / kGridBY);
@@ -425,7 +432,7 @@ void enqueue_deposit(pic_ctx *c)
                         (long long)c->g.NX * c->g.NY, c->stream);
     for (int s = 0; s < 2; s++) {
         PushArgs a = push_args(c, s);
-        launch_push(a, (int)c->L.max_blocks[s], false, c->stream);
+        launch_push(a, (int)c->L.max_blocks[s], false, c->L.unroll, c->L.merge, c->stream);
     }
     enqueue_assemble(c);
 }
@@ -586,7 +593,7 @@ pic_status do_push(pic_ctx *c)
         PushArgs a = push_args(c, s);
         const bool tm = c->timing && c->nev < kMaxTiming;
         if (tm) HIPCHK(c, hipEventRecord(c->ev0[c->nev], c->stream));
-        launch_push(a, (int)c->L.max_blocks[s], true, c->stream);
+        launch_push(a, (int)c->L.max_blocks[s], true, c->L.unroll, c->L.merge, c->stream);
         if (tm) {
             HIPCHK(c, hipEventRecord(c->ev1[c->nev], c->stream));
             c->nev++;

@@ -34,6 +34,7 @@ class pic_config(C.Structure):
         ("static_j_lo", C.c_int32), ("static_j_hi", C.c_int32), ("rtol", C.c_double),
         ("max_iter", C.c_int32), ("solver", C.c_int32), ("sort_interval", C.c_int32 * 2),
         ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("halo", C.c_int32), ("chunk", C.c_int32),
+        ("push_unroll", C.c_int32), ("push_merge", C.c_int32),
         ("hitlog_capacity", C.c_int64), ("hitlog_species_mask", C.c_int32),
     ]
 
@@ -121,7 +122,8 @@ class PicError(RuntimeError):
 
 
 def make_config(w, *, solver=0, max_iter=2000, sort_interval=(8, 64), tile=(16, 16), halo=4,
-                chunk=8192, hitlog_capacity=0, hitlog_species_mask=2, rtol=None):
+                chunk=8192, push_unroll=2, push_merge=0, hitlog_capacity=0,
+                hitlog_species_mask=2, rtol=None):
     """pic_config from a workload description (see synth.Workload)."""
     cc = np.ascontiguousarray(w.cell_cond, dtype=np.uint8)
     cfg = pic_config()
@@ -148,6 +150,8 @@ def make_config(w, *, solver=0, max_iter=2000, sort_interval=(8, 64), tile=(16, 
     cfg.tile_x, cfg.tile_y = tile
     cfg.halo = halo
     cfg.chunk = chunk
+    cfg.push_unroll = push_unroll
+    cfg.push_merge = push_merge
     cfg.hitlog_capacity = hitlog_capacity
     cfg.hitlog_species_mask = hitlog_species_mask
     return cfg, cc
