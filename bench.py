@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--unroll", type=int, default=2)
     ap.add_argument("--merge", type=int, default=0)
     ap.add_argument("--tile", default="16,16")
-    ap.add_argument("--chunk", type=int, default=8192)
+    ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--halo", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:

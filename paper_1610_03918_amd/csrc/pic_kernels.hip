@@ -1193,8 +1193,8 @@ __device__ __forceinline__ bool live_code(int c, int nx, int ny)
 // counters (count pass) or reserves that many consecutive destination slots
 // with one global atomic per tile (scatter pass) and hands them out in LDS.
 // Tiles beyond kBinLds fall back to global wavefront-aggregated atomics.
-constexpr int kBinPer = 4096;
-constexpr int kBinLds = 4096;
+constexpr int kBinPer = 2048;
+constexpr int kBinLds = 2048;
 
 __device__ __forceinline__ void bin_local_count(const BinArgs &a, long long lo, long long hi,
                                                 unsigned *hist, bool count_bad)
@@ -1290,29 +1290,53 @@ __device__ __forceinline__ unsigned gcd_u(unsigned x, unsigned y)
     return x;
 }
 
-// Scatter: the m particles a block sends to tile t land on its reserved
-// slots base..base+m-1 in the order r -> (r * stride) mod m, with stride
-// near 0.618 m and coprime to m.  Runs of particles from one cell are thus
-// spread over the tile's range, so the lanes of a wavefront in the push
-// mostly deposit into different cells.
+// Scatter: the m particles a block sends to tile t take its reserved slots
+// base..base+m-1.  They are staged in LDS in the order r -> (r * stride) mod m
+// (r = arrival rank, stride near 0.618 m and coprime to m) and then copied
+// with consecutive destination slots, so the stores stay coalesced while runs
+// of particles from one cell are spread over the tile's range (the lanes of a
+// wavefront in the push then mostly deposit into different cells).
 __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
 {
-    __shared__ unsigned hist[kBinLds], base[kBinLds], mstr[kBinLds];   // mstr = m << 16 | stride
+    __shared__ unsigned hist[kBinLds], base[kBinLds], loff[kBinLds], mstr[kBinLds];
+    __shared__ int src[kBinPer];
+    __shared__ unsigned dst[kBinPer];
+    __shared__ unsigned part[256];
     const long long n = *a.slots;
     const long long lo = (long long)blockIdx.x * kBinPer;
     if (lo >= n) return;
     const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
     bin_local_count(a, lo, hi, hist, false);
     const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
-    for (int k = threadIdx.x; k < nl; k += 256) {
+    const int per = (nl + 255) / 256;
+    const int t0 = threadIdx.x * per, t1 = min(nl, t0 + per);
+    unsigned sum = 0;
+    for (int k = t0; k < t1; k++) {
         const unsigned m = hist[k];
         if (m) {
             base[k] = atomicAdd(&a.cursor[k], m);
             unsigned st = (unsigned)(0.618034f * (float)m) | 1u;
             while (gcd_u(st, m) != 1u) st++;
             mstr[k] = (m << 16) | (st % m);
-            hist[k] = 0u;
         }
+        sum += m;
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned acc = 0;
+        for (int k = 0; k < 256; k++) {
+            const unsigned v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    unsigned off = part[threadIdx.x];
+    for (int k = t0; k < t1; k++) {
+        loff[k] = off;
+        off += hist[k];
+        hist[k] = 0u;
     }
     __syncthreads();
     for (long long p0 = lo; p0 < hi; p0 += 256) {
@@ -1324,18 +1348,30 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
         const bool loc = act && key < kBinLds;
         const unsigned r = wave_add(hist, key, loc);
         const unsigned d1 = wave_add(a.cursor, key, act && key >= kBinLds);
-        if (act) {
-            unsigned d = d1;
-            if (loc) {
-                const unsigned ms = mstr[key];
-                d = base[key] + (r * (ms & 0xFFFFu)) % (ms >> 16);
-            }
-            a.cell2[d] = c;
-            a.ox2[d] = a.ox[p];
-            a.oy2[d] = a.oy[p];
-            a.vx2[d] = a.vx[p];
-            a.vy2[d] = a.vy[p];
+        if (loc) {
+            const unsigned ms = mstr[key];
+            const unsigned q = loff[key] + (r * (ms & 0xFFFFu)) % (ms >> 16);
+            src[q] = (int)(p - lo);
+            dst[q] = base[key] + (q - loff[key]);
+        } else if (act) {
+            a.cell2[d1] = c;
+            a.ox2[d1] = a.ox[p];
+            a.oy2[d1] = a.oy[p];
+            a.vx2[d1] = a.vx[p];
+            a.vy2[d1] = a.vy[p];
         }
+    }
+    __syncthreads();
+    // staged total: offset of the last bin plus its count (its rank counter)
+    const unsigned total = (nl > 0) ? loff[nl - 1] + hist[nl - 1] : 0u;
+    for (unsigned q = threadIdx.x; q < total; q += 256) {
+        const long long p = lo + src[q];
+        const unsigned d = dst[q];
+        a.cell2[d] = a.cell[p];
+        a.ox2[d] = a.ox[p];
+        a.oy2[d] = a.oy[p];
+        a.vx2[d] = a.vx[p];
+        a.vy2[d] = a.vy[p];
     }
 }
 
