@@ -87,6 +87,7 @@ typedef struct {
     int32_t push_merge;          /* distinct cells summed per wavefront before LDS atomics: 0, 2, 4 */
     int64_t hitlog_capacity;     /* ring of wall-hit records in the workspace (0 = none) */
     int32_t hitlog_species_mask; /* bit s logs species s */
+    int32_t warm_start;          /* start of pic_step's solves: 0 previous phi, 1 linear extrapolation */
 } pic_config;
 
 typedef struct {
@@ -156,8 +157,10 @@ pic_status pic_deposit(pic_ctx *ctx);
 
 /* Solves eq. (5) for phi from b.  guess_kind 0: start from zero on the free
  * nodes; 1: from the current phi (previous step); 2: from the device float64
- * array guess (NX*NY, free nodes used).  Waits for the stream.  info may be
- * NULL.  Returns PIC_ERR_NOT_CONVERGED (phi written) at max_iter. */
+ * array guess (NX*NY, free nodes used); 3: from 2 phi - phi_prev, the linear
+ * extrapolation of the last two kind-3 solutions (the current phi on the first
+ * call).  Waits for the stream.  info may be NULL.  Returns
+ * PIC_ERR_NOT_CONVERGED (phi written) at max_iter. */
 pic_status pic_solve(pic_ctx *ctx, int32_t guess_kind, const double *guess, pic_solve_info *info);
 
 /* Leapfrog start: v <- v - (alpha dt / 2) E(x) with E from the current phi
@@ -170,8 +173,8 @@ pic_status pic_rewind(pic_ctx *ctx);
  * species' sort interval is due. */
 pic_status pic_push(pic_ctx *ctx);
 
-/* nsteps x (pic_solve from the previous phi; pic_push).  Stops at the first
- * failing solve and returns its status. */
+/* nsteps x (pic_solve started as cfg.warm_start selects; pic_push).  Stops
+ * at the first failing solve and returns its status. */
 pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
 
 /* Waits for the stream and copies counters to the host. */

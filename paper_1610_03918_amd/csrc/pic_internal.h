@@ -121,6 +121,8 @@ void launch_assemble(const Geom &g, const uint8_t *node_cond, const uint8_t *fix
 void launch_project_mean(const Geom &g, const uint8_t *fix0, double *b, Red red, hipStream_t s);
 void launch_shift_mean(const Geom &g, double *phi, Red red, hipStream_t s);
 void launch_pin_shift(const Geom &g, double *phi, Red red, hipStream_t s);
+void launch_extrapolate(const Geom &g, const uint8_t *fix0, double *phi, double *prev, int have_prev,
+                        hipStream_t s);
 void launch_set_guess(const Geom &g, const uint8_t *fix0, int kind, const double *guess,
                       double *phi, hipStream_t s);
 void launch_resid64(const Geom &g, const uint8_t *fix0, const double *b, const double *phi,

@@ -341,6 +341,26 @@ __global__ void k_set_guess(Geom g, const uint8_t *fix0, int kind, const double 
     phi[n] = (kind == 0) ? 0.0 : guess[n];
 }
 
+// Linear extrapolation in time of the unknowns: phi <- 2 phi - prev and
+// prev <- phi (the previous step's solution); with have_prev = 0 only the
+// copy is made.
+__global__ void k_extrapolate(Geom g, const uint8_t *fix0, double *phi, double *prev, int have_prev)
+{
+    const int NX = g.NX, NY = g.NY;
+    GRID_IDX
+    if (!inb || (fix0[n] && !(g.px && g.py))) return;
+    const double t = phi[n];
+    if (have_prev) phi[n] = 2.0 * t - prev[n];
+    prev[n] = t;
+}
+
+void launch_extrapolate(const Geom &g, const uint8_t *fix0, double *phi, double *prev, int have_prev,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_extrapolate, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, phi, prev,
+                       have_prev);
+}
+
 void launch_set_guess(const Geom &g, const uint8_t *fix0, int kind, const double *guess,
                       double *phi, hipStream_t s)
 {

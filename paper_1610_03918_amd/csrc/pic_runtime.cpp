@@ -95,6 +95,7 @@ std::string validate(const pic_config *c, const int64_t *cap)
     if (cap && (cap[0] < 0 || cap[1] < 0 || cap[0] > 0x7fffffffLL || cap[1] > 0x7fffffffLL))
         return "capacity out of range";
     if (c->hitlog_capacity < 0) return "hitlog_capacity must be >= 0";
+    if (c->warm_start < 0 || c->warm_start > 1) return "warm_start must be 0 or 1";
     return "";
 }
 
@@ -196,6 +197,8 @@ struct pic_ctx {
     uint8_t *d_fix[kMaxLev] = {};
     float *d_u[kMaxLev] = {}, *d_g[kMaxLev] = {};
     float *d_e = nullptr, *d_p[2] = {}, *d_q = nullptr;
+    double *d_phi_prev = nullptr;          // solution of the previous step (extrapolated start)
+    bool have_prev = false;
     float4 *d_E4 = nullptr;
     double *d_part = nullptr, *d_S = nullptr;
     int *d_F = nullptr;
@@ -267,6 +270,7 @@ size_t carve(pic_ctx *c, const Layout &L, const pic_config *cfg, char *base)
     float *e = w.take<float>(nodes), *p0 = w.take<float>(nodes), *p1 = w.take<float>(nodes);
     float *q = w.take<float>(nodes);
     float4 *E4 = w.take<float4>(2 * cells);
+    double *phi_prev = w.take<double>(nodes);
     double *part = w.take<double>((size_t)L.grid_blocks * 2);
     double *S = w.take<double>(S_NSCAL);
     int *F = w.take<int>(F_NFLAG);
@@ -299,6 +303,7 @@ size_t carve(pic_ctx *c, const Layout &L, const pic_config *cfg, char *base)
         c->d_p[1] = p1;
         c->d_q = q;
         c->d_E4 = E4;
+        c->d_phi_prev = phi_prev;
         c->d_part = part;
         c->d_S = S;
         c->d_F = F;
@@ -540,6 +545,13 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess, pic_solve_info *i
     LevelDev L0 = level(c, 0);
     if (kind == 0 || kind == 2)
         launch_set_guess(c->g, c->d_fix[0], kind, guess, c->buf.phi, c->stream);
+    if (kind == 3) {
+        launch_extrapolate(c->g, c->d_fix[0], c->buf.phi, c->d_phi_prev, c->have_prev ? 1 : 0,
+                           c->stream);
+        c->have_prev = true;
+    } else {
+        c->have_prev = false;
+    }
     if (c->g.px && c->g.py) launch_pin_shift(c->g, c->buf.phi, r, c->stream);
     launch_resid64(c->g, c->d_fix[0], c->buf.b, c->buf.phi, L0.g, r, c->stream);
     double S[S_NSCAL];
@@ -767,8 +779,8 @@ pic_status pic_deposit(pic_ctx *c)
 pic_status pic_solve(pic_ctx *c, int32_t guess_kind, const double *guess, pic_solve_info *info)
 {
     if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
-    if (guess_kind < 0 || guess_kind > 2 || (guess_kind == 2 && !guess))
-        return fail(c, PIC_ERR_ARG, "guess_kind must be 0, 1 or 2 (with a guess array)");
+    if (guess_kind < 0 || guess_kind > 3 || (guess_kind == 2 && !guess))
+        return fail(c, PIC_ERR_ARG, "guess_kind must be 0, 1, 2 (with a guess array) or 3");
     return do_solve(c, guess_kind, guess, info);
 }
 
@@ -797,7 +809,7 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps)
     if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
     if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps < 0");
     for (int k = 0; k < nsteps; k++) {
-        pic_status st = do_solve(c, 1, nullptr, nullptr);
+        pic_status st = do_solve(c, c->cfg.warm_start == 1 ? 3 : 1, nullptr, nullptr);
         if (st != PIC_OK) return st;
         st = do_push(c);
         if (st != PIC_OK) return st;

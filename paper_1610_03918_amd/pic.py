@@ -36,6 +36,7 @@ class pic_config(C.Structure):
         ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("halo", C.c_int32), ("chunk", C.c_int32),
         ("push_unroll", C.c_int32), ("push_merge", C.c_int32),
         ("hitlog_capacity", C.c_int64), ("hitlog_species_mask", C.c_int32),
+        ("warm_start", C.c_int32),
     ]
 
 
@@ -123,7 +124,7 @@ class PicError(RuntimeError):
 
 def make_config(w, *, solver=0, max_iter=2000, sort_interval=(8, 64), tile=(16, 16), halo=4,
                 chunk=4096, push_unroll=2, push_merge=0, hitlog_capacity=0,
-                hitlog_species_mask=2, rtol=None):
+                hitlog_species_mask=2, rtol=None, warm_start=1):
     """pic_config from a workload description (see synth.Workload)."""
     cc = np.ascontiguousarray(w.cell_cond, dtype=np.uint8)
     cfg = pic_config()
@@ -154,6 +155,7 @@ def make_config(w, *, solver=0, max_iter=2000, sort_interval=(8, 64), tile=(16, 
     cfg.push_merge = push_merge
     cfg.hitlog_capacity = hitlog_capacity
     cfg.hitlog_species_mask = hitlog_species_mask
+    cfg.warm_start = warm_start
     return cfg, cc
 
 
