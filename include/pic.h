@@ -199,6 +199,38 @@ pic_status pic_push_timing(pic_ctx *ctx, double *avg_ms, double *avg_particles, 
 /* Enables or disables HIP event timing of the push kernels (default off). */
 pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
 
+/* ---- batched form: several independent instances (e.g. a sweep of trench
+ * widths, Sec. III.C) advanced together; every kernel launch covers all of
+ * them.  Instances may differ in grid size, geometry and particle count but
+ * share one push variant (push_unroll, push_merge) and the sort intervals
+ * of instance 0.  The single-instance calls above act on every instance of
+ * a batch (pic_solve / pic_step converge every instance; pic_diagnostics,
+ * pic_particles and pic_read_hits report instance 0). */
+
+/* Workspace bytes for n (1..16) instances; capacity: host int64[2 n]. */
+pic_status pic_batch_workspace_size(int32_t n, const pic_config *cfgs, const int64_t *capacity,
+                                    size_t *bytes);
+
+/* As pic_init for n instances: cfgs[n], bufs[n] (their workspace fields are
+ * ignored), one caller-owned workspace of pic_batch_workspace_size bytes. */
+pic_status pic_batch_init(int32_t n, const pic_config *cfgs, const pic_buffers *bufs,
+                          void *workspace, size_t workspace_bytes, void *stream, pic_ctx **out);
+
+/* nsteps steps of every instance as captured HIP graphs, one launch per
+ * re-binning period of species 0 (its sort_interval, or 8): each step solves
+ * from the extrapolated potential with a fixed schedule of `passes`
+ * float64 refinement passes of `iters` preconditioned CG iterations, every
+ * instance leaving the schedule as soon as it meets its rtol, then pushes.
+ * Waits at the end; per-instance results in pic_batch_solve_info (converged
+ * = 0 flags an instance the schedule was too short for).  If no earlier
+ * extrapolated solve exists, the first step runs as pic_step(1). */
+pic_status pic_batch_step(pic_ctx *ctx, int32_t nsteps, int32_t passes, int32_t iters);
+
+/* Per-instance counters, particle set and last solve (i in 0..n-1). */
+pic_status pic_batch_diagnostics(pic_ctx *ctx, int32_t i, pic_diag *out);
+pic_status pic_batch_particles(pic_ctx *ctx, int32_t i, int32_t species, int32_t *set, int64_t *slots);
+pic_status pic_batch_solve_info(pic_ctx *ctx, int32_t i, pic_solve_info *out);
+
 void pic_destroy(pic_ctx *ctx);
 const char *pic_last_error(const pic_ctx *ctx);
 const char *pic_version(void);

@@ -5,4 +5,4 @@ push with wall absorption and trench-bottom charge build-up.
 
 The kernels live in ``csrc/`` behind the C ABI of ``include/pic.h``;
 ``pic.py`` is the ctypes binding."""
-from .pic import Pic, PicError, lib, make_config  # noqa: F401
+from .pic import Pic, PicBatch, PicError, lib, make_config  # noqa: F401

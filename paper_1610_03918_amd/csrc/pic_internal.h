@@ -1,5 +1,10 @@
 // Internal interface between the gfx950 kernels (pic_kernels.hip) and the
 // host runtime behind the C ABI (pic_runtime.cpp).  Not installed.
+//
+// Every kernel works on a batch of independent instances (one for pic_init,
+// up to kMaxInst for pic_batch_init).  Per-instance state lives in a device
+// array of Inst descriptors; a launch covers the blocks of several units
+// (instances, or instance x species pairs) listed in a Tab passed by value.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,6 +14,8 @@ namespace pic {
 
 constexpr int kMaxLev = 16;
 constexpr int kNClass = 9;
+constexpr int kMaxInst = 16;
+constexpr int kMaxUnits = 2 * kMaxInst;
 constexpr int kGridBX = 64;      // grid kernels: 64 x 4 threads over (y, x) nodes
 constexpr int kGridBY = 4;
 constexpr int kPushThreads = 256;
@@ -19,7 +26,7 @@ struct Geom {
     int px, py;     // periodic axes
 };
 
-// Slots of the float64 scalar block and the int flag block of the solver.
+// Slots of the float64 scalar block and the int flag block of an instance.
 enum {
     S_BB = 0,    // ||b||^2 over unknowns
     S_RR64,      // ||b - A phi||^2 (float64 residual)
@@ -31,17 +38,18 @@ enum {
     S_ETA2,      // inner stop ratio (squared)
     S_SUM,       // scratch sum (mean projection)
     S_PIN,       // value of the pinned node (fully periodic gauge)
+    S_RELRES,    // last float64 relative residual
+    S_RELRES0,   // relative residual at the start of the solve
     S_NSCAL = 16
 };
-enum { F_DONE = 0, F_ITER, F_NFLAG = 8 };
-
-// Reduction bookkeeping: one partial per block, one counter per reduction.
-struct Red {
-    double *part;      // partial sums, stride max_blocks per quantity
-    int stride;
-    unsigned *count;   // arrival counter (reset by the last block)
-    double *S;         // float64 scalars
-    int *F;            // int flags / counters
+enum {
+    F_DONE = 0,  // inner solve finished (kernels of the pass return at once)
+    F_ITER,      // inner iterations of the current pass
+    F_CONV,      // float64 residual below rtol
+    F_SKIP,      // the current pass was skipped (already converged)
+    F_ITER_TOT,  // inner iterations since the start of the solve
+    F_PASSES,    // refinement passes since the start of the solve
+    F_NFLAG = 8
 };
 
 struct LevelDev {
@@ -63,8 +71,33 @@ struct CoarseArgs {
     int lds_bytes;
 };
 
-struct VTab {
-    double v[8];                   // conductor potentials at the assembly time
+// Device descriptor of one instance.
+struct Inst {
+    Geom g;
+    int nlev, lg, mg;
+    LevelDev lev[kMaxLev];
+    const uint8_t *node_cond, *cell_cond;
+    double *phi, *b, *phi_prev;
+    unsigned long long *rho[2];
+    float *e, *p[2], *q;
+    float4 *E4;
+    double *S;
+    int *F;
+    unsigned long long *surf;
+    double qcharge;                // weight * 2^-32
+    int charge_mode, charge_row, sjl, sjh;
+    double sden;
+    double rtol, eta_min;
+    CoarseArgs coarse;
+};
+
+// Units of one launch: blocks boff[k] .. boff[k+1]-1 belong to unit id[k];
+// grid kernels split a unit's blocks as bx[k] blocks across y.
+struct Tab {
+    int n;
+    int id[kMaxUnits];
+    int boff[kMaxUnits + 1];
+    int bx[kMaxUnits];
 };
 
 struct HitLog {
@@ -79,18 +112,18 @@ struct PushArgs {
     int TX, TY, lx, ly, tiles_y, H, WX, WY;
     const uint8_t *cell_cond;
     const float4 *E4;              // per cell: (Ex,Ey) at corners 00,10 then 01,11
-    int32_t *cell;
-    float *ox, *oy, *vx, *vy;
+    int32_t *cell[2];              // both storage sets; info[7] selects the one in use
+    float *ox[2], *oy[2], *vx[2], *vy[2];
     const int4 *table;             // (tile, start, end, 0) per block
-    const long long *info;         // [1] = number of table entries
+    const long long *info;         // [1] table entries, [2 + set] slots, [7] set in use
     unsigned long long *rho;
-    float qdt, dtf;
+    float qdt, dtf, hq;            // alpha dt, dt, alpha dt / 2 (float32)
     int box_i_top, box_j_lo, box_j_hi;
-    int species;
+    int species, inst;
     unsigned long long *tally;     // 9 counters of this species
     unsigned long long *surf;      // trench-bottom hits per column, or null
     HitLog log;
-    int step;
+    const long long *step;         // device step counter (hit records)
     unsigned long long *fallbacks;
 };
 
@@ -98,57 +131,60 @@ struct BinArgs {
     int nx, ny;
     int lx, ly, tiles_y, ntiles, chunk;
     unsigned long long *bad;       // count of slots with a code outside the grid
-    const int32_t *cell;
-    const float *ox, *oy, *vx, *vy;
-    int32_t *cell2;
-    float *ox2, *oy2, *vx2, *vy2;
-    const long long *slots;        // device slot count of the source set
+    int32_t *cell[2];              // both storage sets: source info[7], destination the other
+    float *ox[2], *oy[2], *vx[2], *vy[2];
     unsigned *counts, *offsets, *cursor, *boff;
     int4 *table;
-    long long *info;               // [0] alive, [1] table entries, [2 + set] slots of each set
-    int dst;                       // destination set
+    long long *info;               // [0] alive, [1] table entries, [2 + set] slots, [7] set in use
+};
+
+// Reduction partials: one float64 per block and quantity.
+struct Part {
+    double *p;
+    int stride;
+};
+
+enum {
+    OP_ASM = 0,      // after assembly: S_BB (or the source sum on fully periodic grids)
+    OP_BB_PER,       // after the mean projection (fully periodic only): S_BB
+    OP_SUM,          // S_SUM = t0
+    OP_RR64_START,   // start residual: S_RR64, relres0, F_CONV, counters reset
+    OP_RR64_PASS,    // residual after a pass (skipped passes keep their state)
+    OP_INIT,         // inner start (inner stop ratio from the current residual)
+    OP_PQ,           // S_PQ
+    OP_UPDATE,       // S_RR, iteration count, inner stop test
+    OP_RZ            // rz rotation
 };
 
 // ---- launchers (pic_kernels.hip) --------------------------------------
+// All launchers take the device Inst array and a Tab describing the units.
 void launch_zero_u64(unsigned long long *p, long long n, hipStream_t s);
-void launch_field(const Geom &g, const uint8_t *node_cond, const double *phi, float4 *E4,
-                  unsigned long long *rho0, unsigned long long *rho1, hipStream_t s);
-void launch_assemble(const Geom &g, const uint8_t *node_cond, const uint8_t *fix0,
-                     const long long *rho_e, const long long *rho_i, double q,
-                     const VTab &V, int charge_mode, int charge_row,
-                     const unsigned long long *surf, double static_density, int sj_lo,
-                     int sj_hi, double *b, double *phi, Red red, hipStream_t s);
-void launch_project_mean(const Geom &g, const uint8_t *fix0, double *b, Red red, hipStream_t s);
-void launch_shift_mean(const Geom &g, double *phi, Red red, hipStream_t s);
-void launch_pin_shift(const Geom &g, double *phi, Red red, hipStream_t s);
-void launch_extrapolate(const Geom &g, const uint8_t *fix0, double *phi, double *prev, int have_prev,
-                        hipStream_t s);
-void launch_set_guess(const Geom &g, const uint8_t *fix0, int kind, const double *guess,
-                      double *phi, hipStream_t s);
-void launch_resid64(const Geom &g, const uint8_t *fix0, const double *b, const double *phi,
-                    float *r, Red red, hipStream_t s);
-void launch_phi_update(const Geom &g, const uint8_t *fix0, const float *e, double *phi,
-                       hipStream_t s);
-void launch_init_red0(const Geom &g, const LevelDev &L0, float *e, double eta2, int mg,
-                      Red red, hipStream_t s);
-void launch_pupdate_Ap(const Geom &g, const LevelDev &L0, const float *p_old, float *p_new,
-                       float *q, int first, Red red, hipStream_t s);
-void launch_update_red0(const Geom &g, const LevelDev &L0, const float *p, const float *q,
-                        float *e, int mg, Red red, hipStream_t s);
-void launch_smooth(const Geom &g, const LevelDev &L, int color, int level0_rz, Red red,
+void launch_field(const Inst *I, const Tab &t, int zero_rho, hipStream_t s);
+void launch_assemble(const Inst *I, const Tab &t, const double *Vtab, const long long *ctl,
+                     int ninst, Part pt, hipStream_t s);
+void launch_project_mean(const Inst *I, const Tab &t, Part pt, hipStream_t s);
+void launch_shift_mean(const Inst *I, const Tab &t, Part pt, hipStream_t s);
+void launch_pin_shift(const Inst *I, const Tab &t, hipStream_t s);
+void launch_set_guess(const Inst *I, const Tab &t, int kind, const double *guess, hipStream_t s);
+void launch_extrapolate(const Inst *I, const Tab &t, int have_prev, hipStream_t s);
+void launch_resid64(const Inst *I, const Tab &t, int after_pass, Part pt, hipStream_t s);
+void launch_phi_update(const Inst *I, const Tab &t, hipStream_t s);
+void launch_init_red0(const Inst *I, const Tab &t, Part pt, hipStream_t s);
+void launch_pupdate_Ap(const Inst *I, const Tab &t, int kold, int first, Part pt, hipStream_t s);
+void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStream_t s);
+void launch_smooth(const Inst *I, const Tab &t, int level, int color, int level0_rz, Part pt,
                    hipStream_t s);
-void launch_restrict(const Geom &g, const LevelDev &F, const LevelDev &Cc, const int *done,
-                     hipStream_t s);
-void launch_prolong_black(const Geom &g, const LevelDev &F, const LevelDev &Cc, const int *done,
-                          hipStream_t s);
-void launch_coarse(const CoarseArgs &a, const int *done, hipStream_t s);
-void launch_push(const PushArgs &a, int max_blocks, bool push, int unroll, int merge,
+void launch_restrict(const Inst *I, const Tab &t, int level, hipStream_t s);
+void launch_prolong_black(const Inst *I, const Tab &t, int level, hipStream_t s);
+void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s);
+void launch_push(const PushArgs *A, const Tab &t, bool push, int unroll, int merge, size_t lds,
                  hipStream_t s);
-void launch_rewind(const Geom &g, const float4 *E4, const int32_t *cell, const float *ox,
-                   const float *oy, float *vx, float *vy, long long n, const long long *slots,
-                   float hq, hipStream_t s);
-void launch_bin(const BinArgs &a, long long max_slots, hipStream_t s);
+void launch_rewind(const PushArgs *A, const Tab &t, hipStream_t s);
+void launch_bin(const BinArgs *B, const Tab &tcount, const Tab &tscan, const Tab &ttable,
+                hipStream_t s);
 void launch_rho_sum(const unsigned long long *rho, long long n, unsigned long long *out,
                     hipStream_t s);
+void launch_tick(long long *step, hipStream_t s);
+int bin_per_block();
 
 } // namespace pic

@@ -1,12 +1,15 @@
 // gfx950 kernels of the 2D electrostatic PIC step (arXiv:1610.03918, Sec. II).
 //
-// Grid kernels work on the node grid (NX x NY, row-major in x) with 64x4
-// thread blocks; floating-point reductions are float64, summed per block in
-// a fixed tree and finished by the last block to arrive in block order, so
-// every result is reproducible bit for bit.  The particle kernel processes
-// one tile of cells per block, accumulating the area-weighting moments of
-// its particles in LDS as integers and flushing them to the int64 node
-// charge with atomics (exact, order-free).
+// Every kernel serves a batch of independent instances: per-instance state
+// is read from a device array of Inst descriptors, and a launch covers the
+// blocks of several units (instances, or instance x species pairs) listed in
+// a Tab.  Grid kernels work on node grids (NX x NY, row-major in x) with
+// 64x4 thread blocks; floating-point reductions are float64 block partials
+// summed in block order by a one-block-per-unit finalize kernel, so every
+// result is reproducible bit for bit.  The particle kernel processes one tile
+// of cells per block, accumulating the area-weighting moments of its
+// particles in LDS as integers and flushing them to the int64 node charge
+// with atomics (exact, order-free).
 //
 // Compiled with -ffp-contract=off: every float operation of the push is
 // rounded in the order written.
@@ -28,17 +31,41 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Unit of a launch that owns block b (uniform per block).
+__device__ __forceinline__ int unit_of(const Tab &t, int b)
+{
+    int k = 0;
+    while (k + 1 < t.n && b >= t.boff[k + 1]) k++;
+    return k;
+}
+
+static inline int tab_blocks(const Tab &t) { return t.boff[t.n]; }
+
+// Grid kernels: node (i, j) of the unit that owns this block.
+#define GRID_BEGIN(t)                                                        \
+    const int ku = unit_of(t, (int)blockIdx.x);                              \
+    const int lb = (int)blockIdx.x - t.boff[ku];                             \
+    const int byb = lb / t.bx[ku], bxb = lb - byb * t.bx[ku];                \
+    const int j = bxb * kGridBX + (int)threadIdx.x;                          \
+    const int i = byb * kGridBY + (int)threadIdx.y;                          \
+    const Inst &I = insts[t.id[ku]];
+
+#define NODE_IDX(NX_, NY_)                                                   \
+    const int NX = (NX_), NY = (NY_);                                        \
+    const bool inb = (i < NX) && (j < NY);                                   \
+    const long long n = (long long)i * NY + j;
+
+static inline dim3 gblock() { return dim3(kGridBX, kGridBY); }
+
 // Writes this block's sums of NQ per-thread values (fixed tree order) to
-// red.part[q * stride + block].  A one-block k_finalize launched next adds
-// the partials in block order, so every total is reproducible bit for bit.
+// pt.p[q * stride + block].  k_finalize adds a unit's partials in block order.
 template <int NQ>
-__device__ void block_partials(const double (&val)[NQ], const Red &red)
+__device__ void block_partials(const double (&val)[NQ], const Part &pt)
 {
     __shared__ double sh[NQ][16];
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nt = blockDim.x * blockDim.y;
     const int lane = tid & 63, wid = tid >> 6, nw = (nt + 63) >> 6;
-    const int bid = blockIdx.x + blockIdx.y * gridDim.x;
 #pragma unroll
     for (int q = 0; q < NQ; q++) {
         double v = wave_sum(val[q]);
@@ -50,83 +77,95 @@ __device__ void block_partials(const double (&val)[NQ], const Red &red)
         for (int q = 0; q < NQ; q++) {
             double s = 0.0;
             for (int w = 0; w < nw; w++) s += sh[q][w];
-            red.part[q * red.stride + bid] = s;
+            pt.p[q * pt.stride + blockIdx.x] = s;
         }
     }
 }
 
-// What k_finalize does with the totals.
-enum {
-    OP_BB = 0,      // S_BB = t0
-    OP_SUM,         // S_SUM = t0
-    OP_SUM2,        // S_SUM = t1 (second quantity)
-    OP_RR64,        // S_RR64 = t0
-    OP_INIT,        // inner start: S_RR0 = S_RR = t0, flags reset, (no MG) rz <- t1
-    OP_PQ,          // S_PQ = t0
-    OP_UPDATE,      // S_RR = t0, one more iteration, stop test, (no MG) rz <- t1
-    OP_RZ           // rz <- t0
-};
-
-__global__ __launch_bounds__(256) void k_finalize(Red red, int nb, int op, int mg, double eta2)
+// One block per unit: totals of the unit's partials, then the scalar logic
+// of the operation on that instance.
+__global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part pt, int op)
 {
+    const Inst &I = insts[t.id[blockIdx.x]];
+    double *S = I.S;
+    int *F = I.F;
     const bool inner = op == OP_PQ || op == OP_UPDATE || op == OP_RZ;
-    if (inner && red.F[F_DONE]) return;
+    if (inner && F[F_DONE]) return;
+    if (op == OP_RR64_PASS && F[F_SKIP]) return;
+    if (op == OP_INIT && F[F_CONV]) {
+        if (threadIdx.x == 0) {
+            F[F_SKIP] = 1;
+            F[F_DONE] = 1;
+        }
+        return;
+    }
     __shared__ double sh[2][4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int nq = (op == OP_INIT || op == OP_UPDATE || op == OP_SUM2) ? 2 : 1;
-    double t[2] = {0.0, 0.0};
+    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE) ? 2 : 1;
+    const int b0 = t.boff[blockIdx.x], b1 = t.boff[blockIdx.x + 1];
     for (int q = 0; q < nq; q++) {
         double s = 0.0;
-        for (int k = tid; k < nb; k += 256) s += red.part[q * red.stride + k];
+        for (int k = b0 + tid; k < b1; k += 256) s += pt.p[q * pt.stride + k];
         s = wave_sum(s);
         if (lane == 0) sh[q][wid] = s;
     }
     __syncthreads();
     if (tid != 0) return;
-    for (int q = 0; q < nq; q++) t[q] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
-    double *S = red.S;
-    int *F = red.F;
+    double tt[2] = {0.0, 0.0};
+    for (int q = 0; q < nq; q++) tt[q] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
+    const double bb = S[S_BB] > 0.0 ? S[S_BB] : 1.0;
+    const double tol2 = I.rtol * I.rtol;
     switch (op) {
-    case OP_BB: S[S_BB] = t[0]; break;
-    case OP_SUM: S[S_SUM] = t[0]; break;
-    case OP_SUM2: S[S_SUM] = t[1]; break;
-    case OP_RR64: S[S_RR64] = t[0]; break;
-    case OP_INIT:
-        S[S_RR0] = t[0];
-        S[S_RR] = t[0];
-        if (eta2 >= 0.0) S[S_ETA2] = eta2;   // negative: already stored by the host
-        F[F_DONE] = (t[0] == 0.0) ? 1 : 0;
+    case OP_ASM:
+        if (I.g.px && I.g.py) S[S_SUM] = tt[1];
+        else S[S_BB] = tt[0];
+        break;
+    case OP_BB_PER: S[S_BB] = tt[0]; break;
+    case OP_SUM: S[S_SUM] = tt[0]; break;
+    case OP_RR64_START:
+        S[S_RR64] = tt[0];
+        S[S_RELRES0] = tt[0];
+        F[F_CONV] = (tt[0] <= tol2 * bb) ? 1 : 0;
+        F[F_ITER_TOT] = 0;
+        F[F_PASSES] = 0;
+        F[F_DONE] = 0;
+        F[F_SKIP] = 0;
+        break;
+    case OP_RR64_PASS:
+        S[S_RR64] = tt[0];
+        F[F_CONV] = (tt[0] <= tol2 * bb) ? 1 : 0;
+        break;
+    case OP_INIT: {
+        // inner stop ratio: 0.3 rtol / relres, kept within [eta_min, 0.5]
+        double eta2 = 0.09 * tol2 * bb / (S[S_RR64] > 0.0 ? S[S_RR64] : 1.0);
+        const double lo = I.eta_min * I.eta_min;
+        eta2 = eta2 < lo ? lo : (eta2 > 0.25 ? 0.25 : eta2);
+        F[F_SKIP] = 0;
+        S[S_ETA2] = eta2;
+        S[S_RR0] = tt[0];
+        S[S_RR] = tt[0];
+        F[F_DONE] = (tt[0] == 0.0) ? 1 : 0;
         F[F_ITER] = 0;
-        if (!mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t[1]; }
+        F[F_PASSES] += 1;
+        if (!I.mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = tt[1]; }
         break;
-    case OP_PQ: S[S_PQ] = t[0]; break;
+    }
+    case OP_PQ: S[S_PQ] = tt[0]; break;
     case OP_UPDATE:
-        S[S_RR] = t[0];
+        S[S_RR] = tt[0];
         F[F_ITER] += 1;
-        if (t[0] <= S[S_ETA2] * S[S_RR0]) F[F_DONE] = 1;
-        if (!mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t[1]; }
+        F[F_ITER_TOT] += 1;
+        if (tt[0] <= S[S_ETA2] * S[S_RR0]) F[F_DONE] = 1;
+        if (!I.mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = tt[1]; }
         break;
-    case OP_RZ: S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t[0]; break;
+    case OP_RZ: S[S_RZOLD] = S[S_RZ]; S[S_RZ] = tt[0]; break;
     }
 }
 
-static void finalize(const Red &red, int nb, int op, int mg, double eta2, hipStream_t s)
+static void finalize(const Inst *I, const Tab &t, Part pt, int op, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, red, nb, op, mg, eta2);
+    if (t.n > 0) hipLaunchKernelGGL(k_finalize, dim3(t.n), dim3(256), 0, s, I, t, pt, op);
 }
-
-#define GRID_IDX                                                     \
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;             \
-    const int i = blockIdx.y * blockDim.y + threadIdx.y;             \
-    const bool inb = (i < NX) && (j < NY);                           \
-    const long long n = (long long)i * NY + j;
-
-static inline dim3 grid_of(int NX, int NY)
-{
-    return dim3((NY + kGridBX - 1) / kGridBX, (NX + kGridBY - 1) / kGridBY);
-}
-static inline dim3 gblock() { return dim3(kGridBX, kGridBY); }
-static inline int nblk(int NX, int NY) { dim3 d = grid_of(NX, NY); return (int)(d.x * d.y); }
 
 __global__ void k_zero_u64(unsigned long long *p, long long n)
 {
@@ -141,6 +180,13 @@ void launch_zero_u64(unsigned long long *p, long long n, hipStream_t s)
     long long nb = (n + 255) / 256;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)nb), dim3(256), 0, s, p, n);
+}
+
+__global__ void k_tick(long long *step) { *step += 1; }
+
+void launch_tick(long long *step, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,181 +237,184 @@ __device__ __forceinline__ float2 node_field(const Geom g, const uint8_t *nc, co
 
 // One thread per cell; writes the cell's four corner fields (float32) and,
 // when requested, clears both species' node charge for the coming deposit.
-__global__ void k_field(Geom g, const uint8_t *nc, const double *phi, float4 *E4,
-                        unsigned long long *rho0, unsigned long long *rho1)
+__global__ void k_field(const Inst *insts, Tab t, int zero_rho)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y * blockDim.y + threadIdx.y;
-    if (rho0 && i < g.NX && j < g.NY) {
-        long long n = (long long)i * g.NY + j;
-        rho0[n] = 0ull;
-        rho1[n] = 0ull;
+    GRID_BEGIN(t)
+    const Geom g = I.g;
+    if (zero_rho && i < g.NX && j < g.NY) {
+        const long long n = (long long)i * g.NY + j;
+        I.rho[0][n] = 0ull;
+        I.rho[1][n] = 0ull;
     }
     if (i >= g.nx || j >= g.ny) return;
     const int i1 = g.px ? wrap_hi(i + 1, g.nx) : i + 1;
     const int j1 = g.py ? wrap_hi(j + 1, g.ny) : j + 1;
+    const uint8_t *nc = I.node_cond;
+    const double *phi = I.phi;
     float2 e00 = node_field(g, nc, phi, i, j);
     float2 e10 = node_field(g, nc, phi, i1, j);
     float2 e01 = node_field(g, nc, phi, i, j1);
     float2 e11 = node_field(g, nc, phi, i1, j1);
-    long long c = (long long)i * g.ny + j;
-    E4[2 * c] = make_float4(e00.x, e00.y, e10.x, e10.y);
-    E4[2 * c + 1] = make_float4(e01.x, e01.y, e11.x, e11.y);
+    const long long c = (long long)i * g.ny + j;
+    I.E4[2 * c] = make_float4(e00.x, e00.y, e10.x, e10.y);
+    I.E4[2 * c + 1] = make_float4(e01.x, e01.y, e11.x, e11.y);
 }
 
-void launch_field(const Geom &g, const uint8_t *nc, const double *phi, float4 *E4,
-                  unsigned long long *rho0, unsigned long long *rho1, hipStream_t s)
+void launch_field(const Inst *I, const Tab &t, int zero_rho, hipStream_t s)
 {
-    int rx = g.NX > g.nx ? g.NX : g.nx, ry = g.NY > g.ny ? g.NY : g.ny;
-    hipLaunchKernelGGL(k_field, grid_of(rx, ry), gblock(), 0, s, g, nc, phi, E4, rho0, rho1);
+    if (t.n) hipLaunchKernelGGL(k_field, dim3(tab_blocks(t)), gblock(), 0, s, I, t, zero_rho);
 }
 
 // ---------------------------------------------------------------------------
 // assemble: b = (N_i - N_e) w 2^-32 + Dirichlet lifts (eq. 5, unit spacing)
+// V: conductor potentials, 8 per instance (indexed by instance id)
 // ---------------------------------------------------------------------------
 
-__global__ void k_assemble(Geom g, const uint8_t *nc, const uint8_t *fix0, const long long *re,
-                           const long long *ri, double q, VTab V, int mode, int row,
-                           const unsigned long long *surf, double sden, int sjl, int sjh,
-                           double *b, double *phi, Red red, int want_sum)
+// V: conductor potentials of every step of the table window, indexed
+// ((step - base) * ninst + instance) * 8 with the device step counter.
+__global__ void k_assemble(const Inst *insts, Tab t, const double *Vtab, const long long *ctl,
+                           int ninst, Part pt)
 {
-    const int NX = g.NX, NY = g.NY;
-    GRID_IDX
+    GRID_BEGIN(t)
+    const Geom g = I.g;
+    NODE_IDX(g.NX, g.NY)
+    const double *V = Vtab + ((ctl[0] - ctl[1]) * ninst + t.id[ku]) * 8;
     double bb = 0.0, sm = 0.0;
     if (inb) {
+        const uint8_t *nc = I.node_cond;
         const int c = nc[n];
         if (c) {
-            b[n] = V.v[c];
-            phi[n] = V.v[c];
+            I.b[n] = V[c];
+            I.phi[n] = V[c];
         } else {
-            long long Ni = ri[n];
-            if (mode == 2 && i == row) {
-                int jl = g.py ? wrap_lo(j - 1, g.ny) : j - 1;
-                if (j < g.ny) Ni += (long long)surf[j] << 31;
-                if (jl >= 0) Ni += (long long)surf[jl] << 31;
+            long long Ni = (long long)I.rho[1][n];
+            if (I.charge_mode == 2 && i == I.charge_row) {
+                const int jl = g.py ? wrap_lo(j - 1, g.ny) : j - 1;
+                if (j < g.ny) Ni += (long long)I.surf[j] << 31;
+                if (jl >= 0) Ni += (long long)I.surf[jl] << 31;
             }
-            double r = (double)(Ni - re[n]) * q;
-            if (mode == 1 && i == row && j >= sjl && j <= sjh) r += sden;
-            int im = g.px ? wrap_lo(i - 1, NX) : i - 1, ip = g.px ? wrap_hi(i + 1, NX) : i + 1;
-            int jm = g.py ? wrap_lo(j - 1, NY) : j - 1, jp = g.py ? wrap_hi(j + 1, NY) : j + 1;
+            double r = (double)(Ni - (long long)I.rho[0][n]) * I.qcharge;
+            if (I.charge_mode == 1 && i == I.charge_row && j >= I.sjl && j <= I.sjh) r += I.sden;
+            const int im = g.px ? wrap_lo(i - 1, NX) : i - 1, ip = g.px ? wrap_hi(i + 1, NX) : i + 1;
+            const int jm = g.py ? wrap_lo(j - 1, NY) : j - 1, jp = g.py ? wrap_hi(j + 1, NY) : j + 1;
             int cn;
-            if ((cn = nc[(long long)im * NY + j])) r += V.v[cn];
-            if ((cn = nc[(long long)ip * NY + j])) r += V.v[cn];
-            if ((cn = nc[(long long)i * NY + jm])) r += V.v[cn];
-            if ((cn = nc[(long long)i * NY + jp])) r += V.v[cn];
-            b[n] = r;
-            if (!fix0[n]) bb = r * r;
+            if ((cn = nc[(long long)im * NY + j])) r += V[cn];
+            if ((cn = nc[(long long)ip * NY + j])) r += V[cn];
+            if ((cn = nc[(long long)i * NY + jm])) r += V[cn];
+            if ((cn = nc[(long long)i * NY + jp])) r += V[cn];
+            I.b[n] = r;
+            if (!I.lev[0].fix[n]) bb = r * r;
             sm = r;
         }
     }
     double v[2] = {bb, sm};
-    block_partials<2>(v, red);
+    block_partials<2>(v, pt);
 }
 
-void launch_assemble(const Geom &g, const uint8_t *nc, const uint8_t *fix0, const long long *re,
-                     const long long *ri, double q, const VTab &V, int mode, int row,
-                     const unsigned long long *surf, double sden, int sjl, int sjh, double *b,
-                     double *phi, Red red, hipStream_t s)
+void launch_assemble(const Inst *I, const Tab &t, const double *Vtab, const long long *ctl,
+                     int ninst, Part pt, hipStream_t s)
 {
-    int want_sum = (g.px && g.py) ? 1 : 0;
-    hipLaunchKernelGGL(k_assemble, grid_of(g.NX, g.NY), gblock(), 0, s, g, nc, fix0, re, ri, q,
-                       V, mode, row, surf, sden, sjl, sjh, b, phi, red, want_sum);
-    finalize(red, nblk(g.NX, g.NY), want_sum ? OP_SUM2 : OP_BB, 0, 0.0, s);
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_assemble, dim3(tab_blocks(t)), gblock(), 0, s, I, t, Vtab, ctl, ninst, pt);
+    finalize(I, t, pt, OP_ASM, s);
 }
 
 // Fully periodic grid: the source must have zero mean (gauge); subtract it
 // and form ||b||^2 over the unknowns (the pinned node excluded).
-__global__ void k_project_mean(Geom g, const uint8_t *fix0, double *b, Red red)
+__global__ void k_project_mean(const Inst *insts, Tab t, Part pt)
 {
-    const int NX = g.NX, NY = g.NY;
-    GRID_IDX
-    const double mean = red.S[S_SUM] / ((double)NX * (double)NY);
+    GRID_BEGIN(t)
+    NODE_IDX(I.g.NX, I.g.NY)
+    const double mean = I.S[S_SUM] / ((double)NX * (double)NY);
     double bb = 0.0;
     if (inb) {
-        double r = b[n] - mean;
-        b[n] = r;
-        if (!fix0[n]) bb = r * r;
+        const double r = I.b[n] - mean;
+        I.b[n] = r;
+        if (!I.lev[0].fix[n]) bb = r * r;
     }
     double v[1] = {bb};
-    block_partials<1>(v, red);
+    block_partials<1>(v, pt);
 }
 
-void launch_project_mean(const Geom &g, const uint8_t *fix0, double *b, Red red, hipStream_t s)
+void launch_project_mean(const Inst *I, const Tab &t, Part pt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_project_mean, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, b, red);
-    finalize(red, nblk(g.NX, g.NY), OP_BB, 0, 0.0, s);
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_project_mean, dim3(tab_blocks(t)), gblock(), 0, s, I, t, pt);
+    finalize(I, t, pt, OP_BB_PER, s);
 }
 
-__global__ void k_sum_phi(Geom g, const double *phi, Red red)
+__global__ void k_sum_phi(const Inst *insts, Tab t, Part pt)
 {
-    const int NX = g.NX, NY = g.NY;
-    GRID_IDX
-    double v[1] = {inb ? phi[n] : 0.0};
-    block_partials<1>(v, red);
+    GRID_BEGIN(t)
+    NODE_IDX(I.g.NX, I.g.NY)
+    double v[1] = {inb ? I.phi[n] : 0.0};
+    block_partials<1>(v, pt);
 }
 
-// phi -= S[slot] * scale on every node
-__global__ void k_shift_phi(Geom g, double *phi, const double *S, int slot, double scale)
+// phi -= S[slot] * (mean ? 1 / (NX NY) : 1) on every node
+__global__ void k_shift_phi(const Inst *insts, Tab t, int slot, int mean)
 {
-    const int NX = g.NX, NY = g.NY;
-    GRID_IDX
-    if (inb) phi[n] -= S[slot] * scale;
+    GRID_BEGIN(t)
+    NODE_IDX(I.g.NX, I.g.NY)
+    const double sc = mean ? 1.0 / ((double)NX * (double)NY) : 1.0;
+    if (inb) I.phi[n] -= I.S[slot] * sc;
 }
 
-__global__ void k_read_node0(const double *phi, double *S) { S[S_PIN] = phi[0]; }
-
-void launch_shift_mean(const Geom &g, double *phi, Red red, hipStream_t s)
+__global__ void k_read_node0(const Inst *insts, Tab t)
 {
-    hipLaunchKernelGGL(k_sum_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red);
-    finalize(red, nblk(g.NX, g.NY), OP_SUM, 0, 0.0, s);
-    hipLaunchKernelGGL(k_shift_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red.S, (int)S_SUM,
-                       1.0 / ((double)g.NX * (double)g.NY));
+    const Inst &I = insts[t.id[blockIdx.x]];
+    I.S[S_PIN] = I.phi[0];
+}
+
+void launch_shift_mean(const Inst *I, const Tab &t, Part pt, hipStream_t s)
+{
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_sum_phi, dim3(tab_blocks(t)), gblock(), 0, s, I, t, pt);
+    finalize(I, t, pt, OP_SUM, s);
+    hipLaunchKernelGGL(k_shift_phi, dim3(tab_blocks(t)), gblock(), 0, s, I, t, (int)S_SUM, 1);
 }
 
 // Fully periodic grid: node 0 is held at 0 during the solve (gauge); shift a
-// warm start so that it already satisfies that.
-void launch_pin_shift(const Geom &g, double *phi, Red red, hipStream_t s)
+// start so that it already satisfies that.
+void launch_pin_shift(const Inst *I, const Tab &t, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_read_node0, dim3(1), dim3(1), 0, s, phi, red.S);
-    hipLaunchKernelGGL(k_shift_phi, grid_of(g.NX, g.NY), gblock(), 0, s, g, phi, red.S, (int)S_PIN,
-                       1.0);
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_read_node0, dim3(t.n), dim3(1), 0, s, I, t);
+    hipLaunchKernelGGL(k_shift_phi, dim3(tab_blocks(t)), gblock(), 0, s, I, t, (int)S_PIN, 0);
 }
 
 // Start of the solve on the unknowns; on a fully periodic grid also on the
-// pinned node (the gauge shift that follows moves it back to 0).
-__global__ void k_set_guess(Geom g, const uint8_t *fix0, int kind, const double *guess, double *phi)
+// pinned node (the gauge shift that follows moves it back to 0).  kind 0:
+// zero; kind 2: copy from guess (single-unit launches only).
+__global__ void k_set_guess(const Inst *insts, Tab t, int kind, const double *guess)
 {
-    const int NX = g.NX, NY = g.NY;
-    GRID_IDX
-    if (!inb || (fix0[n] && !(g.px && g.py))) return;
-    phi[n] = (kind == 0) ? 0.0 : guess[n];
+    GRID_BEGIN(t)
+    NODE_IDX(I.g.NX, I.g.NY)
+    if (!inb || (I.lev[0].fix[n] && !(I.g.px && I.g.py))) return;
+    I.phi[n] = (kind == 0) ? 0.0 : guess[n];
+}
+
+void launch_set_guess(const Inst *I, const Tab &t, int kind, const double *guess, hipStream_t s)
+{
+    if (t.n) hipLaunchKernelGGL(k_set_guess, dim3(tab_blocks(t)), gblock(), 0, s, I, t, kind, guess);
 }
 
 // Linear extrapolation in time of the unknowns: phi <- 2 phi - prev and
 // prev <- phi (the previous step's solution); with have_prev = 0 only the
 // copy is made.
-__global__ void k_extrapolate(Geom g, const uint8_t *fix0, double *phi, double *prev, int have_prev)
+__global__ void k_extrapolate(const Inst *insts, Tab t, int have_prev)
 {
-    const int NX = g.NX, NY = g.NY;
-    GRID_IDX
-    if (!inb || (fix0[n] && !(g.px && g.py))) return;
-    const double t = phi[n];
-    if (have_prev) phi[n] = 2.0 * t - prev[n];
-    prev[n] = t;
+    GRID_BEGIN(t)
+    NODE_IDX(I.g.NX, I.g.NY)
+    if (!inb || (I.lev[0].fix[n] && !(I.g.px && I.g.py))) return;
+    const double v = I.phi[n];
+    if (have_prev) I.phi[n] = 2.0 * v - I.phi_prev[n];
+    I.phi_prev[n] = v;
 }
 
-void launch_extrapolate(const Geom &g, const uint8_t *fix0, double *phi, double *prev, int have_prev,
-                        hipStream_t s)
+void launch_extrapolate(const Inst *I, const Tab &t, int have_prev, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_extrapolate, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, phi, prev,
-                       have_prev);
-}
-
-void launch_set_guess(const Geom &g, const uint8_t *fix0, int kind, const double *guess,
-                      double *phi, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_set_guess, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, kind, guess,
-                       phi);
+    if (t.n) hipLaunchKernelGGL(k_extrapolate, dim3(tab_blocks(t)), gblock(), 0, s, I, t, have_prev);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,52 +423,54 @@ void launch_set_guess(const Geom &g, const uint8_t *fix0, int kind, const double
 // A = 4 - (sum of free neighbours); fixed neighbours sit in b already.
 // ---------------------------------------------------------------------------
 
-__global__ void k_resid64(Geom g, const uint8_t *fix, const double *b, const double *phi,
-                          float *r32, Red red)
+__global__ void k_resid64(const Inst *insts, Tab t, int after_pass, Part pt)
 {
-    const int NX = g.NX, NY = g.NY;
-    GRID_IDX
+    GRID_BEGIN(t)
+    if (after_pass && I.F[F_SKIP]) return;
+    NODE_IDX(I.g.NX, I.g.NY)
+    const uint8_t *fix = I.lev[0].fix;
+    const double *phi = I.phi;
     double rr = 0.0;
     if (inb) {
         if (fix[n]) {
-            r32[n] = 0.0f;
+            I.lev[0].g[n] = 0.0f;
         } else {
-            int im = wrap_lo(i - 1, NX), ip = wrap_hi(i + 1, NX);
-            int jm = wrap_lo(j - 1, NY), jp = wrap_hi(j + 1, NY);
-            long long a = (long long)im * NY + j, c = (long long)ip * NY + j;
-            long long d = (long long)i * NY + jm, e = (long long)i * NY + jp;
+            const int im = wrap_lo(i - 1, NX), ip = wrap_hi(i + 1, NX);
+            const int jm = wrap_lo(j - 1, NY), jp = wrap_hi(j + 1, NY);
+            const long long a = (long long)im * NY + j, c = (long long)ip * NY + j;
+            const long long d = (long long)i * NY + jm, e = (long long)i * NY + jp;
             double s = 4.0 * phi[n];
             if (!fix[a]) s -= phi[a];
             if (!fix[c]) s -= phi[c];
             if (!fix[d]) s -= phi[d];
             if (!fix[e]) s -= phi[e];
-            double r = b[n] - s;
-            r32[n] = (float)r;
+            const double r = I.b[n] - s;
+            I.lev[0].g[n] = (float)r;
             rr = r * r;
         }
     }
     double v[1] = {rr};
-    block_partials<1>(v, red);
+    block_partials<1>(v, pt);
 }
 
-void launch_resid64(const Geom &g, const uint8_t *fix0, const double *b, const double *phi,
-                    float *r, Red red, hipStream_t s)
+void launch_resid64(const Inst *I, const Tab &t, int after_pass, Part pt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resid64, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, b, phi, r, red);
-    finalize(red, nblk(g.NX, g.NY), OP_RR64, 0, 0.0, s);
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_resid64, dim3(tab_blocks(t)), gblock(), 0, s, I, t, after_pass, pt);
+    finalize(I, t, pt, after_pass ? OP_RR64_PASS : OP_RR64_START, s);
 }
 
-__global__ void k_phi_update(Geom g, const uint8_t *fix, const float *e, double *phi)
+__global__ void k_phi_update(const Inst *insts, Tab t)
 {
-    const int NX = g.NX, NY = g.NY;
-    GRID_IDX
-    if (inb && !fix[n]) phi[n] += (double)e[n];
+    GRID_BEGIN(t)
+    if (I.F[F_SKIP]) return;
+    NODE_IDX(I.g.NX, I.g.NY)
+    if (inb && !I.lev[0].fix[n]) I.phi[n] += (double)I.e[n];
 }
 
-void launch_phi_update(const Geom &g, const uint8_t *fix0, const float *e, double *phi,
-                       hipStream_t s)
+void launch_phi_update(const Inst *I, const Tab &t, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_phi_update, grid_of(g.NX, g.NY), gblock(), 0, s, g, fix0, e, phi);
+    if (t.n) hipLaunchKernelGGL(k_phi_update, dim3(tab_blocks(t)), gblock(), 0, s, I, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -534,16 +585,19 @@ __device__ __forceinline__ float prolong_black_value(const float *u, const float
 // preconditioned CG on level 0 (float32 vectors, float64 dot products)
 // ---------------------------------------------------------------------------
 
-// Inner start: e = 0, z = red-from-zero of M r (or z = r/4 when no MG),
-// ||r||^2 -> S_RR0, S_RR; iteration flag reset.
-__global__ void k_init_red0(Geom g, LevelDev L, float *e, int mg, Red red)
+// Inner start: e = 0, z = red-from-zero of M r (or z = r/4 without MG),
+// ||r||^2 and r.z partials.  Skipped once the float64 residual converged.
+__global__ void k_init_red0(const Inst *insts, Tab t, Part pt)
 {
-    const int NX = L.NX, NY = L.NY;
-    GRID_IDX
+    GRID_BEGIN(t)
+    if (I.F[F_CONV]) return;
+    const LevelDev L = I.lev[0];
+    NODE_IDX(L.NX, L.NY)
+    const int mg = I.mg;
     double rr = 0.0, rz = 0.0;
     if (inb) {
-        float r = L.g[n];
-        e[n] = 0.0f;
+        const float r = L.g[n];
+        I.e[n] = 0.0f;
         float z = 0.0f;
         if (!L.fix[n]) {
             rr = (double)r * (double)r;
@@ -553,24 +607,27 @@ __global__ void k_init_red0(Geom g, LevelDev L, float *e, int mg, Red red)
         L.u[n] = z;
     }
     double v[2] = {rr, rz};
-    block_partials<2>(v, red);
+    block_partials<2>(v, pt);
 }
 
-void launch_init_red0(const Geom &g, const LevelDev &L0, float *e, double eta2, int mg, Red red,
-                      hipStream_t s)
+void launch_init_red0(const Inst *I, const Tab &t, Part pt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init_red0, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, e, mg, red);
-    finalize(red, nblk(L0.NX, L0.NY), OP_INIT, mg, eta2, s);
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_init_red0, dim3(tab_blocks(t)), gblock(), 0, s, I, t, pt);
+    finalize(I, t, pt, OP_INIT, s);
 }
 
 // p_new = z + beta p_old, q = A p_new, p.q  (beta = rz / rz_old; 0 on the first)
-__global__ void k_pupdate_Ap(Geom g, LevelDev L, const float *p_old, float *p_new, float *q,
-                             int first, Red red)
+__global__ void k_pupdate_Ap(const Inst *insts, Tab t, int kold, int first, Part pt)
 {
-    if (red.F[F_DONE]) return;
-    const int NX = L.NX, NY = L.NY;
-    GRID_IDX
-    const float beta = first ? 0.0f : (float)(red.S[S_RZ] / red.S[S_RZOLD]);
+    GRID_BEGIN(t)
+    if (I.F[F_DONE]) return;
+    const LevelDev L = I.lev[0];
+    NODE_IDX(L.NX, L.NY)
+    const float *p_old = I.p[kold];
+    float *p_new = I.p[1 - kold];
+    float *q = I.q;
+    const float beta = first ? 0.0f : (float)(I.S[S_RZ] / I.S[S_RZOLD]);
     double pq = 0.0;
     if (inb) {
         if (L.fix[n]) {
@@ -578,14 +635,14 @@ __global__ void k_pupdate_Ap(Geom g, LevelDev L, const float *p_old, float *p_ne
             q[n] = 0.0f;
         } else {
             Nb b = nbs(i, j, NX, NY);
-            long long m[4] = {(long long)b.im * NY + j, (long long)b.ip * NY + j,
-                              (long long)i * NY + b.jm, (long long)i * NY + b.jp};
-            float pc = first ? L.u[n] : L.u[n] + beta * p_old[n];
+            const long long m[4] = {(long long)b.im * NY + j, (long long)b.ip * NY + j,
+                                    (long long)i * NY + b.jm, (long long)i * NY + b.jp};
+            const float pc = first ? L.u[n] : L.u[n] + beta * p_old[n];
             float s = 4.0f * pc;
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 if (L.fix[m[k]]) continue;
-                float pn = first ? L.u[m[k]] : L.u[m[k]] + beta * p_old[m[k]];
+                const float pn = first ? L.u[m[k]] : L.u[m[k]] + beta * p_old[m[k]];
                 s -= pn;
             }
             p_new[n] = pc;
@@ -594,33 +651,34 @@ __global__ void k_pupdate_Ap(Geom g, LevelDev L, const float *p_old, float *p_ne
         }
     }
     double v[1] = {pq};
-    block_partials<1>(v, red);
+    block_partials<1>(v, pt);
 }
 
-void launch_pupdate_Ap(const Geom &g, const LevelDev &L0, const float *p_old, float *p_new,
-                       float *q, int first, Red red, hipStream_t s)
+void launch_pupdate_Ap(const Inst *I, const Tab &t, int kold, int first, Part pt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pupdate_Ap, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, p_old, p_new,
-                       q, first, red);
-    finalize(red, nblk(L0.NX, L0.NY), OP_PQ, 0, 0.0, s);
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_pupdate_Ap, dim3(tab_blocks(t)), gblock(), 0, s, I, t, kold, first, pt);
+    finalize(I, t, pt, OP_PQ, s);
 }
 
 // alpha = rz / pq; e += alpha p; r -= alpha q; ||r||^2; z = red-from-zero of
-// M r (or r/4 without MG, with r.z).  Marks the inner solve done when
-// ||r||^2 <= eta^2 ||r0||^2 and counts the iteration.
-__global__ void k_update_red0(Geom g, LevelDev L, const float *p, const float *q, float *e, int mg,
-                              Red red)
+// M r (or r/4 without MG, with r.z).  The finalize marks the inner solve
+// done when ||r||^2 <= eta^2 ||r0||^2 and counts the iteration.
+__global__ void k_update_red0(const Inst *insts, Tab t, int knew, Part pt)
 {
-    if (red.F[F_DONE]) return;
-    const int NX = L.NX, NY = L.NY;
-    GRID_IDX
-    const float alpha = (float)(red.S[S_RZ] / red.S[S_PQ]);
+    GRID_BEGIN(t)
+    if (I.F[F_DONE]) return;
+    const LevelDev L = I.lev[0];
+    NODE_IDX(L.NX, L.NY)
+    const int mg = I.mg;
+    const float *p = I.p[knew];
+    const float alpha = (float)(I.S[S_RZ] / I.S[S_PQ]);
     double rr = 0.0, rz = 0.0;
     if (inb) {
         float z = 0.0f;
         if (!L.fix[n]) {
-            e[n] = e[n] + alpha * p[n];
-            float r = L.g[n] - alpha * q[n];
+            I.e[n] = I.e[n] + alpha * p[n];
+            const float r = L.g[n] - alpha * I.q[n];
             L.g[n] = r;
             rr = (double)r * (double)r;
             if (!mg || (((i + j) & 1) == 0)) z = r * 0.25f;
@@ -629,25 +687,25 @@ __global__ void k_update_red0(Geom g, LevelDev L, const float *p, const float *q
         L.u[n] = z;
     }
     double v[2] = {rr, rz};
-    block_partials<2>(v, red);
+    block_partials<2>(v, pt);
 }
 
-void launch_update_red0(const Geom &g, const LevelDev &L0, const float *p, const float *q, float *e,
-                        int mg, Red red, hipStream_t s)
+void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update_red0, grid_of(L0.NX, L0.NY), gblock(), 0, s, g, L0, p, q, e, mg,
-                       red);
-    finalize(red, nblk(L0.NX, L0.NY), OP_UPDATE, mg, 0.0, s);
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_update_red0, dim3(tab_blocks(t)), gblock(), 0, s, I, t, knew, pt);
+    finalize(I, t, pt, OP_UPDATE, s);
 }
 
 // One colour of red-black Gauss-Seidel on a level.  On level 0 with
 // level0_rz the kernel also forms r.z (after the final red sweep of the
-// V-cycle) and rotates rz -> rz_old.
-__global__ void k_smooth(Geom g, LevelDev L, int color, int level0_rz, Red red)
+// V-cycle); the finalize rotates rz -> rz_old.
+__global__ void k_smooth(const Inst *insts, Tab t, int level, int color, int level0_rz, Part pt)
 {
-    if (red.F[F_DONE]) return;
-    const int NX = L.NX, NY = L.NY;
-    GRID_IDX
+    GRID_BEGIN(t)
+    if (I.F[F_DONE]) return;
+    const LevelDev L = I.lev[level];
+    NODE_IDX(L.NX, L.NY)
     double rz = 0.0;
     if (inb && !L.fix[n]) {
         float z;
@@ -661,60 +719,65 @@ __global__ void k_smooth(Geom g, LevelDev L, int color, int level0_rz, Red red)
     }
     if (!level0_rz) return;
     double v[1] = {rz};
-    block_partials<1>(v, red);
+    block_partials<1>(v, pt);
 }
 
-void launch_smooth(const Geom &g, const LevelDev &L, int color, int level0_rz, Red red,
+void launch_smooth(const Inst *I, const Tab &t, int level, int color, int level0_rz, Part pt,
                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_smooth, grid_of(L.NX, L.NY), gblock(), 0, s, g, L, color, level0_rz, red);
-    if (level0_rz) finalize(red, nblk(L.NX, L.NY), OP_RZ, 0, 0.0, s);
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_smooth, dim3(tab_blocks(t)), gblock(), 0, s, I, t, level, color,
+                       level0_rz, pt);
+    if (level0_rz) finalize(I, t, pt, OP_RZ, s);
 }
 
 // g_c = P^T (g - A u) on the coarse level; u_c = red-from-zero.
-__global__ void k_restrict(Geom g, LevelDev F, LevelDev Cc, const int *done)
+__global__ void k_restrict(const Inst *insts, Tab t, int level)
 {
-    if (*done) return;
-    const int NX = Cc.NX, NY = Cc.NY;
-    GRID_IDX
+    GRID_BEGIN(t)
+    if (I.F[F_DONE]) return;
+    const LevelDev F = I.lev[level], Cc = I.lev[level + 1];
+    NODE_IDX(Cc.NX, Cc.NY)
     if (!inb) return;
     float gv = 0.0f, uv = 0.0f;
     if (!Cc.fix[n]) {
-        gv = restrict_node(F.u, F.g, F.fix, F.NX, F.NY, g.px, g.py, i, j);
+        gv = restrict_node(F.u, F.g, F.fix, F.NX, F.NY, I.g.px, I.g.py, i, j);
         if (((i + j) & 1) == 0) uv = gv * 0.25f;
     }
     Cc.g[n] = gv;
     Cc.u[n] = uv;
 }
 
-void launch_restrict(const Geom &g, const LevelDev &F, const LevelDev &Cc, const int *done,
-                     hipStream_t s)
+void launch_restrict(const Inst *I, const Tab &t, int level, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_restrict, grid_of(Cc.NX, Cc.NY), gblock(), 0, s, g, F, Cc, done);
+    if (t.n) hipLaunchKernelGGL(k_restrict, dim3(tab_blocks(t)), gblock(), 0, s, I, t, level);
 }
 
-__global__ void k_prolong_black(Geom g, LevelDev F, LevelDev Cc, const int *done)
+__global__ void k_prolong_black(const Inst *insts, Tab t, int level)
 {
-    if (*done) return;
-    const int NX = F.NX, NY = F.NY;
-    GRID_IDX
+    GRID_BEGIN(t)
+    if (I.F[F_DONE]) return;
+    const LevelDev F = I.lev[level], Cc = I.lev[level + 1];
+    NODE_IDX(F.NX, F.NY)
     if (!inb || F.fix[n] || ((i + j) & 1) != 1) return;
     F.u[n] = prolong_black_value(F.u, F.g, F.fix, Cc.u, NX, NY, Cc.NX, Cc.NY, i, j);
 }
 
-void launch_prolong_black(const Geom &g, const LevelDev &F, const LevelDev &Cc, const int *done,
-                          hipStream_t s)
+void launch_prolong_black(const Inst *I, const Tab &t, int level, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prolong_black, grid_of(F.NX, F.NY), gblock(), 0, s, g, F, Cc, done);
+    if (t.n) hipLaunchKernelGGL(k_prolong_black, dim3(tab_blocks(t)), gblock(), 0, s, I, t, level);
 }
 
 // ---------------------------------------------------------------------------
-// coarse levels: the rest of the V-cycle in one work-group, all in LDS
+// coarse levels: the rest of the V-cycle in one work-group per instance,
+// all in LDS
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(1024) void k_coarse(CoarseArgs a, const int *done)
+__global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
 {
-    if (*done) return;
+    const Inst &I = insts[t.id[blockIdx.x]];
+    if (I.F[F_DONE]) return;
+    const CoarseArgs &a = I.coarse;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int tab[5][kMaxLev];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -802,9 +865,9 @@ __global__ __launch_bounds__(1024) void k_coarse(CoarseArgs a, const int *done)
 #undef fx
 }
 
-void launch_coarse(const CoarseArgs &a, const int *done, hipStream_t s)
+void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_coarse, dim3(1), dim3(1024), a.lds_bytes, s, a, done);
+    if (t.n) hipLaunchKernelGGL(k_coarse, dim3(t.n), dim3(1024), lds_bytes, s, I, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -836,10 +899,29 @@ __device__ __forceinline__ void wave_sum4_u32(unsigned &a, unsigned &b, unsigned
 }
 #undef DPP_STEP
 
+// The storage set in use (device info[7], flipped by every re-binning).
+struct PView {
+    int32_t *cell;
+    float *ox, *oy, *vx, *vy;
+};
+
+__device__ __forceinline__ PView pview(const PushArgs &a)
+{
+    const int set = (int)a.info[7];
+    PView v;
+    v.cell = a.cell[set];
+    v.ox = a.ox[set];
+    v.oy = a.oy[set];
+    v.vx = a.vx[set];
+    v.vy = a.vy[set];
+    return v;
+}
+
 // Leapfrog push of one particle with the bilinear gather of its cell's
 // corner fields and the cell-by-cell wall test (eqs. 1-4).  Updates the
 // particle in memory; returns false when it was removed (class in *dead).
-__device__ __forceinline__ bool push_particle(const PushArgs &a, int p, int c, float &x0, float &y0,
+__device__ __forceinline__ bool push_particle(const PushArgs &a, const PView &v, int p, int c,
+                                              float &x0, float &y0,
                                               float vx0, float vy0, float4 ea, float4 eb, int &ci,
                                               int &cj, int &dead, int &ei, int &ej, float &ux,
                                               float &uy)
@@ -860,8 +942,8 @@ __device__ __forceinline__ bool push_particle(const PushArgs &a, int p, int c, f
     const float Dx = ux * a.dtf, Dy = uy * a.dtf;
     const float x1 = x0 + Dx, y1 = y0 + Dy;
     const float fsx = floorf(x1), fsy = floorf(y1);
-    a.vx[p] = ux;
-    a.vy[p] = uy;
+    v.vx[p] = ux;
+    v.vy[p] = uy;
     dead = -1;
     ei = ci;
     ej = cj;
@@ -904,16 +986,16 @@ __device__ __forceinline__ bool push_particle(const PushArgs &a, int p, int c, f
         }
     }
     if (dead >= 0) {
-        a.cell[p] = -1 - dead;
+        v.cell[p] = -1 - dead;
         return false;
     }
     float nxo = x1 - (float)sx, nyo = y1 - (float)sy;
     if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
     if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
-    a.ox[p] = nxo;
-    a.oy[p] = nyo;
+    v.ox[p] = nxo;
+    v.oy[p] = nyo;
     const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
-    if (nc != c) a.cell[p] = nc;
+    if (nc != c) v.cell[p] = nc;
     x0 = nxo;
     y0 = nyo;
     ci = ei;
@@ -935,7 +1017,7 @@ __device__ __forceinline__ void record_hit(const PushArgs &a, unsigned *tl, int 
         r[1] = (int)(((unsigned)ei << 16) | (unsigned)ej);
         r[2] = __float_as_int(ux);
         r[3] = __float_as_int(uy);
-        r[4] = a.step;
+        r[4] = (int)a.step[0];
         r[5] = 0;
     }
 }
@@ -949,11 +1031,15 @@ __device__ __forceinline__ void record_hit(const PushArgs &a, unsigned *tl, int 
 // Particles that drifted beyond the window add their four corner weights to
 // global memory directly.  The window is flushed to the node charge at the end.
 template <bool PUSH, int U, int MERGE>
-__global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
+__global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    if ((long long)blockIdx.x >= a.info[1]) return;
-    const int4 ent = a.table[blockIdx.x];
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const PushArgs &a = A[t.id[ku]];
+    const int lb = (int)blockIdx.x - t.boff[ku];
+    if ((long long)lb >= a.info[1]) return;
+    const int4 ent = a.table[lb];
+    const PView v = pview(a);
     const int tile = ent.x, start = ent.y, end = ent.z;
     const int ti = tile / a.tiles_y, tj = tile - ti * a.tiles_y;
     const int i0 = ti * a.TX - a.H, j0 = tj * a.TY - a.H;
@@ -984,17 +1070,17 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int p = base + u * kPushThreads + tid;
-            cu[u] = (p < end) ? a.cell[p] : -1;
+            cu[u] = (p < end) ? v.cell[p] : -1;
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int p = base + u * kPushThreads + tid;
             if (p < end) {
-                xu[u] = a.ox[p];
-                yu[u] = a.oy[p];
+                xu[u] = v.ox[p];
+                yu[u] = v.oy[p];
                 if (PUSH) {
-                    vxu[u] = a.vx[p];
-                    vyu[u] = a.vy[p];
+                    vxu[u] = v.vx[p];
+                    vyu[u] = v.vy[p];
                 }
             }
         }
@@ -1020,7 +1106,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
                 if (PUSH) {
                     int dead, ei, ej;
                     float vnx, vny;
-                    alive = push_particle(a, p, c, x0, y0, vxu[u], vyu[u], eau[u], ebu[u], ci, cj,
+                    alive = push_particle(a, v, p, c, x0, y0, vxu[u], vyu[u], eau[u], ebu[u], ci, cj,
                                           dead, ei, ej, vnx, vny);
                     if (!alive) record_hit(a, tl, dead, ei, ej, vnx, vny);
                 }
@@ -1110,42 +1196,44 @@ __global__ __launch_bounds__(kPushThreads) void k_push(PushArgs a)
 }
 
 template <bool PUSH>
-static void launch_push_t(const PushArgs &a, int max_blocks, int unroll, int merge, size_t lds,
+static void launch_push_t(const PushArgs *A, const Tab &t, int unroll, int merge, size_t lds,
                           hipStream_t s)
 {
-    const dim3 gr(max_blocks), bl(kPushThreads);
+    const dim3 gr(tab_blocks(t)), bl(kPushThreads);
 #define PUSH_CASE(U, M)                                                                   \
     if (unroll == U && merge == M) {                                                      \
-        hipLaunchKernelGGL((k_push<PUSH, U, M>), gr, bl, lds, s, a);                      \
+        hipLaunchKernelGGL((k_push<PUSH, U, M>), gr, bl, lds, s, A, t);                   \
         return;                                                                           \
     }
     PUSH_CASE(1, 0) PUSH_CASE(2, 0) PUSH_CASE(4, 0)
     PUSH_CASE(1, 2) PUSH_CASE(2, 2) PUSH_CASE(4, 2)
     PUSH_CASE(1, 4) PUSH_CASE(2, 4) PUSH_CASE(4, 4)
 #undef PUSH_CASE
-    hipLaunchKernelGGL((k_push<PUSH, 2, 0>), gr, bl, lds, s, a);
+    hipLaunchKernelGGL((k_push<PUSH, 2, 0>), gr, bl, lds, s, A, t);
 }
 
-void launch_push(const PushArgs &a, int max_blocks, bool push, int unroll, int merge, hipStream_t s)
+void launch_push(const PushArgs *A, const Tab &t, bool push, int unroll, int merge, size_t lds,
+                 hipStream_t s)
 {
-    const int WC = a.WX * a.WY;
-    const size_t lds = (size_t)WC * 16 + kNClass * 4 + 16;
-    if (push) launch_push_t<true>(a, max_blocks, unroll, merge, lds, s);
-    else launch_push_t<false>(a, max_blocks, unroll, merge, lds, s);
+    if (!t.n) return;
+    if (push) launch_push_t<true>(A, t, unroll, merge, lds, s);
+    else launch_push_t<false>(A, t, unroll, merge, lds, s);
 }
 
 // Leapfrog start: v -= (alpha dt / 2) E(x), same gather as the push.
-__global__ void k_rewind(Geom g, const float4 *E4, const int32_t *cell, const float *ox,
-                         const float *oy, float *vx, float *vy, const long long *slots, float hq)
+__global__ void k_rewind(const PushArgs *A, Tab t)
 {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= *slots) return;
-    const int c = cell[p];
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const PushArgs &a = A[t.id[ku]];
+    const long long p = (long long)((int)blockIdx.x - t.boff[ku]) * blockDim.x + threadIdx.x;
+    if (p >= a.info[2 + a.info[7]]) return;
+    const PView v = pview(a);
+    const int c = v.cell[p];
     if (c < 0) return;
     const int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
-    const long long cc = (long long)ci * g.ny + cj;
-    const float4 ea = E4[2 * cc], eb = E4[2 * cc + 1];
-    const float x0 = ox[p], y0 = oy[p];
+    const long long cc = (long long)ci * a.g.ny + cj;
+    const float4 ea = a.E4[2 * cc], eb = a.E4[2 * cc + 1];
+    const float x0 = v.ox[p], y0 = v.oy[p];
     const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
     const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
     float ex = w00 * ea.x;
@@ -1156,17 +1244,13 @@ __global__ void k_rewind(Geom g, const float4 *E4, const int32_t *cell, const fl
     ey = ey + w10 * ea.w;
     ey = ey + w01 * eb.y;
     ey = ey + w11 * eb.w;
-    vx[p] = vx[p] - hq * ex;
-    vy[p] = vy[p] - hq * ey;
+    v.vx[p] = v.vx[p] - a.hq * ex;
+    v.vy[p] = v.vy[p] - a.hq * ey;
 }
 
-void launch_rewind(const Geom &g, const float4 *E4, const int32_t *cell, const float *ox,
-                   const float *oy, float *vx, float *vy, long long n, const long long *slots,
-                   float hq, hipStream_t s)
+void launch_rewind(const PushArgs *A, const Tab &t, hipStream_t s)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_rewind, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, E4, cell,
-                       ox, oy, vx, vy, slots, hq);
+    if (t.n) hipLaunchKernelGGL(k_rewind, dim3(tab_blocks(t)), dim3(256), 0, s, A, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1216,7 +1300,37 @@ __device__ __forceinline__ bool live_code(int c, int nx, int ny)
 constexpr int kBinPer = 2048;
 constexpr int kBinLds = 2048;
 
-__device__ __forceinline__ void bin_local_count(const BinArgs &a, long long lo, long long hi,
+// Source (info[7]) and destination sets of a re-binning.
+struct BView {
+    const int32_t *cell;
+    const float *ox, *oy, *vx, *vy;
+    int32_t *cell2;
+    float *ox2, *oy2, *vx2, *vy2;
+    long long slots;
+    int src, dst;
+};
+
+__device__ __forceinline__ BView bview(const BinArgs &a)
+{
+    BView v;
+    v.src = (int)a.info[7];
+    v.dst = 1 - v.src;
+    v.cell = a.cell[v.src];
+    v.ox = a.ox[v.src];
+    v.oy = a.oy[v.src];
+    v.vx = a.vx[v.src];
+    v.vy = a.vy[v.src];
+    v.cell2 = a.cell[v.dst];
+    v.ox2 = a.ox[v.dst];
+    v.oy2 = a.oy[v.dst];
+    v.vx2 = a.vx[v.dst];
+    v.vy2 = a.vy[v.dst];
+    v.slots = a.info[2 + v.src];
+    return v;
+}
+
+__device__ __forceinline__ void bin_local_count(const BinArgs &a, const BView &v, long long lo,
+                                                long long hi,
                                                 unsigned *hist, bool count_bad)
 {
     const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
@@ -1225,7 +1339,7 @@ __device__ __forceinline__ void bin_local_count(const BinArgs &a, long long lo, 
     for (long long p0 = lo; p0 < hi; p0 += 256) {
         const long long p = p0 + threadIdx.x;
         int c = -1;
-        if (p < hi) c = a.cell[p];
+        if (p < hi) c = v.cell[p];
         const bool act = live_code(c, a.nx, a.ny);
         if (count_bad && c >= 0 && !act) atomicAdd(a.bad, 1ull);
         const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
@@ -1235,22 +1349,26 @@ __device__ __forceinline__ void bin_local_count(const BinArgs &a, long long lo, 
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
+__global__ __launch_bounds__(256) void k_bin_count(const BinArgs *B, Tab t)
 {
     __shared__ unsigned hist[kBinLds];
-    const long long n = *a.slots;
-    const long long lo = (long long)blockIdx.x * kBinPer;
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const BinArgs &a = B[t.id[ku]];
+    const BView v = bview(a);
+    const long long n = v.slots;
+    const long long lo = (long long)((int)blockIdx.x - t.boff[ku]) * kBinPer;
     if (lo >= n) return;
     const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
-    bin_local_count(a, lo, hi, hist, true);
+    bin_local_count(a, v, lo, hi, hist, true);
     const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
     for (int k = threadIdx.x; k < nl; k += 256)
         if (hist[k]) atomicAdd(&a.counts[k], hist[k]);
 }
 // Single work-group: exclusive scans of the tile counts and of the blocks
 // per tile; writes the cursor for the scatter and the totals.
-__global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
+__global__ __launch_bounds__(1024) void k_bin_scan(const BinArgs *B, Tab t)
 {
+    const BinArgs &a = B[t.id[blockIdx.x]];
     __shared__ unsigned long long sp[1024], sb[1024];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (a.ntiles + nt - 1) / nt;
@@ -1283,13 +1401,17 @@ __global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
     if (tid == nt - 1) {
         a.info[0] = (long long)sp[tid];
         a.info[1] = (long long)sb[tid];
-        a.info[2 + a.dst] = (long long)sp[tid];
+        a.info[2 + (1 - (int)a.info[7])] = (long long)sp[tid];
     }
 }
 
-__global__ void k_bin_table(BinArgs a)
+// Push-block table of the new set; clears the tile counts for the next
+// re-binning.
+__global__ void k_bin_table(const BinArgs *B, Tab tb)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ku = unit_of(tb, (int)blockIdx.x);
+    const BinArgs &a = B[tb.id[ku]];
+    const int t = ((int)blockIdx.x - tb.boff[ku]) * blockDim.x + threadIdx.x;
     if (t >= a.ntiles) return;
     const unsigned c = a.counts[t], o = a.offsets[t], b0 = a.boff[t];
     const unsigned nb = (c + a.chunk - 1) / a.chunk;
@@ -1298,6 +1420,7 @@ __global__ void k_bin_table(BinArgs a)
         unsigned e = min(o + c, s + (unsigned)a.chunk);
         a.table[b0 + k] = make_int4(t, (int)s, (int)e, 0);
     }
+    a.counts[t] = 0u;
 }
 
 __device__ __forceinline__ unsigned gcd_u(unsigned x, unsigned y)
@@ -1316,17 +1439,20 @@ __device__ __forceinline__ unsigned gcd_u(unsigned x, unsigned y)
 // with consecutive destination slots, so the stores stay coalesced while runs
 // of particles from one cell are spread over the tile's range (the lanes of a
 // wavefront in the push then mostly deposit into different cells).
-__global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
+__global__ __launch_bounds__(256) void k_bin_scatter(const BinArgs *B, Tab tb)
 {
     __shared__ unsigned hist[kBinLds], base[kBinLds], loff[kBinLds], mstr[kBinLds];
     __shared__ int src[kBinPer];
     __shared__ unsigned dst[kBinPer];
     __shared__ unsigned part[256];
-    const long long n = *a.slots;
-    const long long lo = (long long)blockIdx.x * kBinPer;
+    const int ku = unit_of(tb, (int)blockIdx.x);
+    const BinArgs &a = B[tb.id[ku]];
+    const BView v = bview(a);
+    const long long n = v.slots;
+    const long long lo = (long long)((int)blockIdx.x - tb.boff[ku]) * kBinPer;
     if (lo >= n) return;
     const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
-    bin_local_count(a, lo, hi, hist, false);
+    bin_local_count(a, v, lo, hi, hist, false);
     const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
     const int per = (nl + 255) / 256;
     const int t0 = threadIdx.x * per, t1 = min(nl, t0 + per);
@@ -1362,7 +1488,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
     for (long long p0 = lo; p0 < hi; p0 += 256) {
         const long long p = p0 + threadIdx.x;
         int c = -1;
-        if (p < hi) c = a.cell[p];
+        if (p < hi) c = v.cell[p];
         const bool act = live_code(c, a.nx, a.ny);
         const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
         const bool loc = act && key < kBinLds;
@@ -1374,11 +1500,11 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
             src[q] = (int)(p - lo);
             dst[q] = base[key] + (q - loff[key]);
         } else if (act) {
-            a.cell2[d1] = c;
-            a.ox2[d1] = a.ox[p];
-            a.oy2[d1] = a.oy[p];
-            a.vx2[d1] = a.vx[p];
-            a.vy2[d1] = a.vy[p];
+            v.cell2[d1] = c;
+            v.ox2[d1] = v.ox[p];
+            v.oy2[d1] = v.oy[p];
+            v.vx2[d1] = v.vx[p];
+            v.vy2[d1] = v.vy[p];
         }
     }
     __syncthreads();
@@ -1387,30 +1513,35 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
     for (unsigned q = threadIdx.x; q < total; q += 256) {
         const long long p = lo + src[q];
         const unsigned d = dst[q];
-        a.cell2[d] = a.cell[p];
-        a.ox2[d] = a.ox[p];
-        a.oy2[d] = a.oy[p];
-        a.vx2[d] = a.vx[p];
-        a.vy2[d] = a.vy[p];
+        v.cell2[d] = v.cell[p];
+        v.ox2[d] = v.ox[p];
+        v.oy2[d] = v.oy[p];
+        v.vx2[d] = v.vx[p];
+        v.vy2[d] = v.vy[p];
     }
 }
 
-__global__ void k_zero_u32(unsigned *p, int n)
+// The destination set becomes the set in use.
+__global__ void k_bin_flip(const BinArgs *B, Tab t)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) p[k] = 0u;
+    const BinArgs &a = B[t.id[blockIdx.x]];
+    a.info[7] = 1 - a.info[7];
 }
 
-void launch_bin(const BinArgs &a, long long max_slots, hipStream_t s)
+// Tabs: tcount/tscatter cover ceil(slots / kBinPer) blocks per unit, tscan
+// one block per unit, ttable ceil(ntiles / 256) blocks per unit.
+void launch_bin(const BinArgs *B, const Tab &tcount, const Tab &tscan, const Tab &ttable,
+                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_u32, dim3((a.ntiles + 255) / 256), dim3(256), 0, s, a.counts,
-                       a.ntiles);
-    const unsigned nb = (unsigned)((max_slots + kBinPer - 1) / kBinPer);
-    if (nb) hipLaunchKernelGGL(k_bin_count, dim3(nb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_bin_table, dim3((a.ntiles + 255) / 256), dim3(256), 0, s, a);
-    if (nb) hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(256), 0, s, a);
+    if (!tscan.n) return;
+    if (tab_blocks(tcount)) hipLaunchKernelGGL(k_bin_count, dim3(tab_blocks(tcount)), dim3(256), 0, s, B, tcount);
+    hipLaunchKernelGGL(k_bin_scan, dim3(tscan.n), dim3(1024), 0, s, B, tscan);
+    hipLaunchKernelGGL(k_bin_table, dim3(tab_blocks(ttable)), dim3(256), 0, s, B, ttable);
+    if (tab_blocks(tcount)) hipLaunchKernelGGL(k_bin_scatter, dim3(tab_blocks(tcount)), dim3(256), 0, s, B, tcount);
+    hipLaunchKernelGGL(k_bin_flip, dim3(tscan.n), dim3(1), 0, s, B, tscan);
 }
+
+int bin_per_block() { return kBinPer; }
 
 // Sum of a node charge array (exact integer sum).
 __global__ void k_rho_sum(const unsigned long long *rho, long long n, unsigned long long *out)

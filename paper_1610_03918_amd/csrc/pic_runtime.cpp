@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI of include/pic.h: validation, geometry
 // (Dirichlet node map from the conductor cells), multigrid hierarchy,
-// workspace carve-up, the solver's convergence loop and the step driver.
+// workspace carve-up, launch tables of a batch of instances, the solver's
+// convergence loop, the step driver and graph-captured multi-step launches.
 // Every device operation is a kernel from pic_kernels.hip on the caller's
 // stream; the library allocates no device memory.
 #include <hip/hip_runtime.h>
@@ -23,18 +24,6 @@ namespace {
 constexpr int kCoarseMaxNodes = 4096;   // largest level solved inside one work-group
 constexpr int kCoarseMaxLds = 64 * 1024;
 constexpr int kMaxTiming = 512;
-
-struct Carve {
-    size_t off = 0;
-    char *base = nullptr;
-    template <class T> T *take(size_t count)
-    {
-        off = (off + 255) & ~size_t(255);
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += count * sizeof(T);
-        return p;
-    }
-};
 
 struct Layout {
     int nx, ny, NX, NY, px, py;
@@ -181,50 +170,88 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
 
 } // namespace
 
-struct pic_ctx {
-    pic_config cfg;
-    std::vector<uint8_t> cell_cond;
-    std::vector<uint8_t> node_cond;
-    Layout L;
-    Geom g;
-    hipStream_t stream = nullptr;
-    pic_buffers buf;
-    int cur[2] = {0, 0};
-    long long slots_ub[2] = {0, 0};
+// ---------------------------------------------------------------------------
+// host-side state
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct InstHost {
+    pic_config cfg{};
+    std::vector<uint8_t> cell_cond, node_cond;
+    Layout L{};
+    Geom g{};
+    pic_buffers buf{};
     long long loaded[2] = {0, 0};
-    // workspace
+    long long slots_ub[2] = {0, 0};
     uint8_t *d_cell_cond = nullptr, *d_node_cond = nullptr;
     uint8_t *d_fix[kMaxLev] = {};
     float *d_u[kMaxLev] = {}, *d_g[kMaxLev] = {};
     float *d_e = nullptr, *d_p[2] = {}, *d_q = nullptr;
-    double *d_phi_prev = nullptr;          // solution of the previous step (extrapolated start)
-    bool have_prev = false;
     float4 *d_E4 = nullptr;
-    double *d_part = nullptr, *d_S = nullptr;
-    int *d_F = nullptr;
-    unsigned *d_count = nullptr;
+    double *d_phi_prev = nullptr;
     unsigned *d_counts[2] = {}, *d_offsets[2] = {}, *d_cursor[2] = {}, *d_boff[2] = {};
     int4 *d_table[2] = {};
     long long *d_info[2] = {};
     unsigned long long *d_tally = nullptr, *d_surf = nullptr, *d_misc = nullptr;
     int32_t *d_hits = nullptr;
-    CoarseArgs coarse;
-    // state
-    long long step = 0;
-    int inner_chunk = 12;
+    std::vector<std::vector<uint8_t>> fixh;  // level masks (host copies kept until uploaded)
+    Inst dev{};
     pic_solve_info last{};
-    std::string err;
-    // solver graphs: one outer pass (inner start, K iterations, phi update,
-    // float64 residual) captured per K and replayed on the caller's stream
+};
+
+struct Carve {
+    size_t off = 0;
+    char *base = nullptr;
+    template <class T> T *take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+constexpr int kVWindow = 512;   // steps of conductor potentials held on the device
+
+} // namespace
+
+struct pic_ctx {
+    int n = 0;
+    std::vector<InstHost> in;
+    hipStream_t stream = nullptr;
+    // shared device objects
+    Inst *d_inst = nullptr;
+    PushArgs *d_push = nullptr;
+    BinArgs *d_bin = nullptr;
+    double *d_part = nullptr;
+    int part_stride = 0;
+    double *d_S = nullptr;          // n x S_NSCAL
+    int *d_F = nullptr;             // n x F_NFLAG
+    double *d_V = nullptr;          // kVWindow x n x 8
+    long long *d_ctl = nullptr;     // [0] step, [1] first step of the V window
+    long long step = 0, vbase = 0;
+    std::vector<double> vhost;
+    // launch tables
+    Tab t_l0{}, t_field{}, t_per{}, t_coarse{}, t_push{}, t_rewind{};
+    Tab t_fine[kMaxLev] = {}, t_crs[kMaxLev] = {};
+    int maxlg = 0, coarse_lds = 0, any_mg = 0;
+    size_t push_lds = 0;
+    int unroll = 2, merge = 0;
+    // solver control
+    bool have_prev = false;
+    int inner_chunk = 12;
+    // graphs
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> outer_graphs;
+    std::map<long long, hipGraphExec_t> step_graphs;
     bool use_graphs = true;
-    double eta2_host = 0.0;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev0, ev1;
     int nev = 0;
     long long timed_particles = 0;
+    std::string err;
 };
 
 namespace {
@@ -235,28 +262,36 @@ pic_status fail(pic_ctx *c, pic_status st, const std::string &msg)
     return st;
 }
 
-#define HIPCHK(ctx, call)                                                            \
-    do {                                                                             \
-        hipError_t e_ = (call);                                                      \
-        if (e_ != hipSuccess)                                                        \
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
             return fail(ctx, PIC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-Red red_of(pic_ctx *c)
+Part part_of(pic_ctx *c) { return Part{c->d_part, c->part_stride}; }
+
+int grid_blocks(int NX, int NY) { return ((NY + kGridBX - 1) / kGridBX) * ((NX + kGridBY - 1) / kGridBY); }
+
+void tab_add_grid(Tab &t, int id, int NX, int NY)
 {
-    Red r;
-    r.part = c->d_part;
-    r.stride = c->L.grid_blocks;
-    r.count = c->d_count;
-    r.S = c->d_S;
-    r.F = c->d_F;
-    return r;
+    const int k = t.n++;
+    t.id[k] = id;
+    t.bx[k] = (NY + kGridBX - 1) / kGridBX;
+    t.boff[k + 1] = t.boff[k] + t.bx[k] * ((NX + kGridBY - 1) / kGridBY);
 }
 
-size_t carve(pic_ctx *c, const Layout &L, const pic_config *cfg, char *base)
+void tab_add(Tab &t, int id, int blocks)
 {
-    Carve w;
-    w.base = base;
+    const int k = t.n++;
+    t.id[k] = id;
+    t.bx[k] = 1;
+    t.boff[k + 1] = t.boff[k] + blocks;
+}
+
+// Per-instance device memory inside the shared workspace.
+void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, const int64_t *cap)
+{
     const size_t cells = (size_t)L.nx * L.ny, nodes = (size_t)L.NX * L.NY;
     uint8_t *cc = w.take<uint8_t>(cells);
     uint8_t *nc = w.take<uint8_t>(nodes);
@@ -271,10 +306,6 @@ size_t carve(pic_ctx *c, const Layout &L, const pic_config *cfg, char *base)
     float *q = w.take<float>(nodes);
     float4 *E4 = w.take<float4>(2 * cells);
     double *phi_prev = w.take<double>(nodes);
-    double *part = w.take<double>((size_t)L.grid_blocks * 2);
-    double *S = w.take<double>(S_NSCAL);
-    int *F = w.take<int>(F_NFLAG);
-    unsigned *cnt = w.take<unsigned>(16);
     unsigned *counts[2], *offs[2], *curs[2], *boff[2];
     int4 *table[2];
     long long *info[2];
@@ -290,205 +321,170 @@ size_t carve(pic_ctx *c, const Layout &L, const pic_config *cfg, char *base)
     unsigned long long *surf = w.take<unsigned long long>(L.ny + 1);
     unsigned long long *misc = w.take<unsigned long long>(16);
     int32_t *hits = w.take<int32_t>((size_t)6 * std::max<int64_t>(cfg->hitlog_capacity, 1));
+    (void)cap;
+    if (!h) return;
+    h->d_cell_cond = cc;
+    h->d_node_cond = nc;
+    for (int l = 0; l < L.nlev; l++) {
+        h->d_fix[l] = fix[l];
+        h->d_u[l] = u[l];
+        h->d_g[l] = gg[l];
+    }
+    h->d_e = e;
+    h->d_p[0] = p0;
+    h->d_p[1] = p1;
+    h->d_q = q;
+    h->d_E4 = E4;
+    h->d_phi_prev = phi_prev;
+    for (int s = 0; s < 2; s++) {
+        h->d_counts[s] = counts[s];
+        h->d_offsets[s] = offs[s];
+        h->d_cursor[s] = curs[s];
+        h->d_boff[s] = boff[s];
+        h->d_table[s] = table[s];
+        h->d_info[s] = info[s];
+    }
+    h->d_tally = tally;
+    h->d_surf = surf;
+    h->d_misc = misc;
+    h->d_hits = hits;
+}
+
+// Whole workspace: shared part, then every instance.
+size_t carve_all(pic_ctx *c, int n, const pic_config *cfgs, const int64_t *caps, char *base)
+{
+    Carve w;
+    w.base = base;
+    int stride = 0;
+    for (int k = 0; k < n; k++) {
+        Layout L = make_layout(&cfgs[k], caps + 2 * k);
+        stride += grid_blocks(std::max(L.NX, L.nx), std::max(L.NY, L.ny));
+    }
+    Inst *di = w.take<Inst>(n);
+    PushArgs *dp = w.take<PushArgs>(2 * n);
+    BinArgs *db = w.take<BinArgs>(2 * n);
+    double *part = w.take<double>((size_t)2 * stride);
+    double *S = w.take<double>((size_t)n * S_NSCAL);
+    int *F = w.take<int>((size_t)n * F_NFLAG);
+    double *V = w.take<double>((size_t)kVWindow * n * 8);
+    long long *ctl = w.take<long long>(4);
     if (c) {
-        c->d_cell_cond = cc;
-        c->d_node_cond = nc;
-        for (int l = 0; l < L.nlev; l++) {
-            c->d_fix[l] = fix[l];
-            c->d_u[l] = u[l];
-            c->d_g[l] = gg[l];
-        }
-        c->d_e = e;
-        c->d_p[0] = p0;
-        c->d_p[1] = p1;
-        c->d_q = q;
-        c->d_E4 = E4;
-        c->d_phi_prev = phi_prev;
+        c->d_inst = di;
+        c->d_push = dp;
+        c->d_bin = db;
         c->d_part = part;
+        c->part_stride = stride;
         c->d_S = S;
         c->d_F = F;
-        c->d_count = cnt;
-        for (int s = 0; s < 2; s++) {
-            c->d_counts[s] = counts[s];
-            c->d_offsets[s] = offs[s];
-            c->d_cursor[s] = curs[s];
-            c->d_boff[s] = boff[s];
-            c->d_table[s] = table[s];
-            c->d_info[s] = info[s];
-        }
-        c->d_tally = tally;
-        c->d_surf = surf;
-        c->d_misc = misc;
-        c->d_hits = hits;
+        c->d_V = V;
+        c->d_ctl = ctl;
+    }
+    for (int k = 0; k < n; k++) {
+        Layout L = make_layout(&cfgs[k], caps + 2 * k);
+        carve_inst(c ? &c->in[k] : nullptr, w, L, &cfgs[k], caps + 2 * k);
     }
     return w.off + 256;
 }
 
-LevelDev level(pic_ctx *c, int l)
+void fill_vwindow(pic_ctx *c, long long first)
 {
-    LevelDev d;
-    d.NX = c->L.NXl[l];
-    d.NY = c->L.NYl[l];
-    d.u = c->d_u[l];
-    d.g = c->d_g[l];
-    d.fix = c->d_fix[l];
-    return d;
-}
-
-void vtab(pic_ctx *c, double t, VTab &V)
-{
-    for (int k = 0; k < 8; k++) V.v[k] = 0.0;
-    for (int k = 1; k < PIC_MAX_COND; k++)
-        if (c->cfg.v_amp[k] != 0.0) V.v[k] = c->cfg.v_amp[k] * std::sin(c->cfg.v_omega[k] * t);
-}
-
-void enqueue_assemble(pic_ctx *c)
-{
-    VTab V;
-    vtab(c, c->step * c->cfg.dt, V);
-    const double q = std::ldexp(c->cfg.weight, -32);
-    launch_assemble(c->g, c->d_node_cond, c->d_fix[0],
-                    reinterpret_cast<const long long *>(c->buf.rho[0]),
-                    reinterpret_cast<const long long *>(c->buf.rho[1]), q, V, c->cfg.charge_mode,
-                    c->cfg.charge_row, c->d_surf, c->cfg.static_density, c->cfg.static_j_lo,
-                    c->cfg.static_j_hi, c->buf.b, c->buf.phi, red_of(c), c->stream);
-    if (c->g.px && c->g.py) launch_project_mean(c->g, c->d_fix[0], c->buf.b, red_of(c), c->stream);
-}
-
-PushArgs push_args(pic_ctx *c, int s)
-{
-    PushArgs a;
-    a.g = c->g;
-    a.TX = c->L.TX;
-    a.TY = c->L.TY;
-    a.lx = c->L.lx;
-    a.ly = c->L.ly;
-    a.tiles_y = c->L.tiles_y;
-    a.H = c->L.H;
-    a.WX = c->L.TX + 2 * c->L.H;
-    a.WY = c->L.TY + 2 * c->L.H;
-    a.cell_cond = c->d_cell_cond;
-    a.E4 = c->d_E4;
-    const int k = c->cur[s];
-    a.cell = c->buf.sp[s].cell[k];
-    a.ox = c->buf.sp[s].ox[k];
-    a.oy = c->buf.sp[s].oy[k];
-    a.vx = c->buf.sp[s].vx[k];
-    a.vy = c->buf.sp[s].vy[k];
-    a.table = c->d_table[s];
-    a.info = c->d_info[s];
-    a.rho = reinterpret_cast<unsigned long long *>(c->buf.rho[s]);
-    a.qdt = (float)(c->cfg.alpha[s] * c->cfg.dt);
-    a.dtf = (float)c->cfg.dt;
-    a.box_i_top = c->cfg.box_i_top;
-    a.box_j_lo = c->cfg.box_j_lo;
-    a.box_j_hi = c->cfg.box_j_hi;
-    a.species = s;
-    a.tally = c->d_tally + s * kNClass;
-    a.surf = (c->cfg.charge_mode == 2 && s == 1) ? c->d_surf : nullptr;
-    a.log.rec = c->cfg.hitlog_capacity > 0 ? c->d_hits : nullptr;
-    a.log.count = c->d_misc + 1;
-    a.log.capacity = std::max<int64_t>(c->cfg.hitlog_capacity, 1);
-    a.log.species_mask = c->cfg.hitlog_species_mask;
-    a.step = (int)c->step;
-    a.fallbacks = c->d_misc + 0;
-    return a;
-}
-
-void enqueue_bin(pic_ctx *c, int s)
-{
-    BinArgs a;
-    a.nx = c->L.nx;
-    a.ny = c->L.ny;
-    a.bad = c->d_misc + 2;
-    a.lx = c->L.lx;
-    a.ly = c->L.ly;
-    a.tiles_y = c->L.tiles_y;
-    a.ntiles = c->L.ntiles;
-    a.chunk = c->L.chunk;
-    const int src = c->cur[s], dst = 1 - src;
-    const pic_species_buffers &B = c->buf.sp[s];
-    a.cell = B.cell[src];
-    a.ox = B.ox[src];
-    a.oy = B.oy[src];
-    a.vx = B.vx[src];
-    a.vy = B.vy[src];
-    a.cell2 = B.cell[dst];
-    a.ox2 = B.ox[dst];
-    a.oy2 = B.oy[dst];
-    a.vx2 = B.vx[dst];
-    a.vy2 = B.vy[dst];
-    a.slots = c->d_info[s] + 2 + src;
-    a.counts = c->d_counts[s];
-    a.offsets = c->d_offsets[s];
-    a.cursor = c->d_cursor[s];
-    a.boff = c->d_boff[s];
-    a.table = c->d_table[s];
-    a.info = c->d_info[s];
-    a.dst = dst;
-    launch_bin(a, c->slots_ub[s], c->stream);
-    c->cur[s] = dst;
-}
-
-void enqueue_deposit(pic_ctx *c)
-{
-    for (int s = 0; s < 2; s++)
-        launch_zero_u64(reinterpret_cast<unsigned long long *>(c->buf.rho[s]),
-                        (long long)c->g.NX * c->g.NY, c->stream);
-    for (int s = 0; s < 2; s++) {
-        PushArgs a = push_args(c, s);
-        launch_push(a, (int)c->L.max_blocks[s], false, c->L.unroll, c->L.merge, c->stream);
-    }
-    enqueue_assemble(c);
-}
-
-// One V-cycle after the level-0 red-from-zero sweep (already applied).
-void enqueue_vcycle_rest(pic_ctx *c)
-{
-    const Layout &L = c->L;
-    Red r = red_of(c);
-    const int *done = c->d_F + F_DONE;
-    for (int l = 0; l < L.lg; l++) {
-        launch_smooth(c->g, level(c, l), 1, 0, r, c->stream);
-        launch_restrict(c->g, level(c, l), level(c, l + 1), done, c->stream);
-    }
-    launch_coarse(c->coarse, done, c->stream);
-    for (int l = L.lg - 1; l >= 0; l--) {
-        launch_prolong_black(c->g, level(c, l), level(c, l + 1), done, c->stream);
-        launch_smooth(c->g, level(c, l), 0, l == 0 ? 1 : 0, r, c->stream);
+    c->vbase = first;
+    c->vhost.assign((size_t)kVWindow * c->n * 8, 0.0);
+    for (long long s = 0; s < kVWindow; s++) {
+        for (int k = 0; k < c->n; k++) {
+            const pic_config &cf = c->in[k].cfg;
+            const double t = (double)(first + s) * cf.dt;
+            double *v = &c->vhost[((size_t)s * c->n + k) * 8];
+            for (int q = 1; q < PIC_MAX_COND; q++)
+                if (cf.v_amp[q] != 0.0) v[q] = cf.v_amp[q] * std::sin(cf.v_omega[q] * t);
+        }
     }
 }
 
-pic_status read_scalars(pic_ctx *c, double *S, int *F)
+// Keeps steps [from, from + ahead] inside the device window of potentials.
+pic_status ensure_vwindow(pic_ctx *c, long long from, long long ahead)
 {
-    HIPCHK(c, hipMemcpyAsync(S, c->d_S, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(F, c->d_F, sizeof(int) * F_NFLAG, hipMemcpyDeviceToHost, c->stream));
+    if (from >= c->vbase && from + ahead < c->vbase + kVWindow) return PIC_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    fill_vwindow(c, from);
+    long long ctl[2] = {c->step, c->vbase};
+    HIPCHK(c, hipMemcpyAsync(c->d_V, c->vhost.data(), c->vhost.size() * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_ctl, ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
 }
 
-// Kernels of one outer pass: inner preconditioned CG from e = 0 with K
-// iterations (later ones return at once after the stop test), phi += e and
-// the float64 residual with its norm.
-void enqueue_outer(pic_ctx *c, int K, double eta2, hipStream_t st)
+void enqueue_assemble(pic_ctx *c, hipStream_t s)
 {
-    Red r = red_of(c);
-    LevelDev L0 = level(c, 0);
-    const int mg = c->L.mg ? 1 : 0;
-    const hipStream_t keep = c->stream;
-    c->stream = st;
-    launch_init_red0(c->g, L0, c->d_e, eta2, mg, r, st);
-    if (mg) enqueue_vcycle_rest(c);
-    for (int k = 0; k < K; k++) {
-        const float *pold = c->d_p[k & 1];
-        float *pnew = c->d_p[(k + 1) & 1];
-        launch_pupdate_Ap(c->g, L0, pold, pnew, c->d_q, k == 0 ? 1 : 0, r, st);
-        launch_update_red0(c->g, L0, pnew, c->d_q, c->d_e, mg, r, st);
-        if (mg) enqueue_vcycle_rest(c);
+    launch_assemble(c->d_inst, c->t_l0, c->d_V, c->d_ctl, c->n, part_of(c), s);
+    launch_project_mean(c->d_inst, c->t_per, part_of(c), s);
+}
+
+// Tabs over (instance, species) pairs selected by mask bits (bit s: species s).
+void bin_tabs(pic_ctx *c, int species_mask, Tab &tc, Tab &ts, Tab &tt)
+{
+    tc = Tab{};
+    ts = Tab{};
+    tt = Tab{};
+    for (int k = 0; k < c->n; k++)
+        for (int s = 0; s < 2; s++) {
+            if (!((species_mask >> s) & 1)) continue;
+            const InstHost &h = c->in[k];
+            const int id = 2 * k + s;
+            tab_add(tc, id, (int)((h.slots_ub[s] + bin_per_block() - 1) / bin_per_block()));
+            tab_add(ts, id, 1);
+            tab_add(tt, id, (h.L.ntiles + 255) / 256);
+        }
+}
+
+void enqueue_bin(pic_ctx *c, int species_mask, hipStream_t s)
+{
+    Tab tc, ts, tt;
+    bin_tabs(c, species_mask, tc, ts, tt);
+    launch_bin(c->d_bin, tc, ts, tt, s);
+}
+
+void enqueue_deposit(pic_ctx *c, hipStream_t s)
+{
+    for (auto &h : c->in)
+        for (int sp = 0; sp < 2; sp++)
+            launch_zero_u64(reinterpret_cast<unsigned long long *>(h.buf.rho[sp]),
+                            (long long)h.g.NX * h.g.NY, s);
+    launch_push(c->d_push, c->t_push, false, c->unroll, c->merge, c->push_lds, s);
+    enqueue_assemble(c, s);
+}
+
+// One V-cycle after the level-0 red-from-zero sweep (already applied).
+void enqueue_vcycle_rest(pic_ctx *c, hipStream_t s)
+{
+    if (!c->any_mg) return;
+    Part pt = part_of(c);
+    for (int l = 0; l < c->maxlg; l++) {
+        launch_smooth(c->d_inst, c->t_fine[l], l, 1, 0, pt, s);
+        launch_restrict(c->d_inst, c->t_crs[l], l, s);
     }
-    launch_phi_update(c->g, c->d_fix[0], c->d_e, c->buf.phi, st);
-    launch_resid64(c->g, c->d_fix[0], c->buf.b, c->buf.phi, L0.g, r, st);
-    c->stream = keep;
+    launch_coarse(c->d_inst, c->t_coarse, c->coarse_lds, s);
+    for (int l = c->maxlg - 1; l >= 0; l--) {
+        launch_prolong_black(c->d_inst, c->t_fine[l], l, s);
+        launch_smooth(c->d_inst, c->t_fine[l], l, 0, l == 0 ? 1 : 0, pt, s);
+    }
+}
+
+// One refinement pass: inner preconditioned CG from e = 0 with K iterations
+// (later ones return at once after the stop test), phi += e, float64 residual.
+void enqueue_pass(pic_ctx *c, int K, hipStream_t s)
+{
+    Part pt = part_of(c);
+    launch_init_red0(c->d_inst, c->t_l0, pt, s);
+    enqueue_vcycle_rest(c, s);
+    for (int k = 0; k < K; k++) {
+        launch_pupdate_Ap(c->d_inst, c->t_l0, k & 1, k == 0 ? 1 : 0, pt, s);
+        launch_update_red0(c->d_inst, c->t_l0, (k + 1) & 1, pt, s);
+        enqueue_vcycle_rest(c, s);
+    }
+    launch_phi_update(c->d_inst, c->t_l0, s);
+    launch_resid64(c->d_inst, c->t_l0, 1, pt, s);
 }
 
 int round_chunk(int k)
@@ -499,127 +495,483 @@ int round_chunk(int k)
     return k;
 }
 
-// The stop ratio of the inner solve is passed through S_ETA2 by a tiny copy
-// so one captured graph serves every ratio.
-pic_status run_outer(pic_ctx *c, int K, double eta2)
+pic_status capture_begin(pic_ctx *c)
+{
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    return PIC_OK;
+}
+
+pic_status capture_end(pic_ctx *c, hipGraphExec_t *ex)
+{
+    hipGraph_t g = nullptr;
+    *ex = nullptr;
+    HIPCHK(c, hipStreamEndCapture(c->cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, PIC_ERR_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+    return PIC_OK;
+}
+
+pic_status run_pass(pic_ctx *c, int K)
 {
     if (!c->use_graphs || K > 128) {
-        enqueue_outer(c, K, eta2, c->stream);
+        enqueue_pass(c, K, c->stream);
         HIPCHK(c, hipGetLastError());
         return PIC_OK;
     }
     auto it = c->outer_graphs.find(K);
     if (it == c->outer_graphs.end()) {
-        if (!c->cap_stream)
-            HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-        enqueue_outer(c, K, -1.0, c->cap_stream);
-        hipGraph_t g = nullptr;
-        hipError_t e1 = hipStreamEndCapture(c->cap_stream, &g);
-        if (e1 != hipSuccess || !g) {
-            c->use_graphs = false;
-            (void)hipGetLastError();
-            enqueue_outer(c, K, eta2, c->stream);
-            return PIC_OK;
-        }
-        hipGraphExec_t ex = nullptr;
-        hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e2 != hipSuccess) {
-            c->use_graphs = false;
-            (void)hipGetLastError();
-            enqueue_outer(c, K, eta2, c->stream);
-            return PIC_OK;
-        }
+        pic_status st = capture_begin(c);
+        if (st != PIC_OK) return st;
+        enqueue_pass(c, K, c->cap_stream);
+        hipGraphExec_t ex;
+        st = capture_end(c, &ex);
+        if (st != PIC_OK) return st;
         it = c->outer_graphs.emplace(K, ex).first;
     }
-    HIPCHK(c, hipMemcpyAsync(c->d_S + S_ETA2, &c->eta2_host, sizeof(double), hipMemcpyHostToDevice,
-                             c->stream));
     HIPCHK(c, hipGraphLaunch(it->second, c->stream));
     return PIC_OK;
 }
 
-pic_status do_solve(pic_ctx *c, int kind, const double *guess, pic_solve_info *info)
+pic_status read_flags(pic_ctx *c, std::vector<double> &S, std::vector<int> &F)
 {
-    Red r = red_of(c);
-    LevelDev L0 = level(c, 0);
-    if (kind == 0 || kind == 2)
-        launch_set_guess(c->g, c->d_fix[0], kind, guess, c->buf.phi, c->stream);
-    if (kind == 3) {
-        launch_extrapolate(c->g, c->d_fix[0], c->buf.phi, c->d_phi_prev, c->have_prev ? 1 : 0,
-                           c->stream);
-        c->have_prev = true;
-    } else {
-        c->have_prev = false;
-    }
-    if (c->g.px && c->g.py) launch_pin_shift(c->g, c->buf.phi, r, c->stream);
-    launch_resid64(c->g, c->d_fix[0], c->buf.b, c->buf.phi, L0.g, r, c->stream);
-    double S[S_NSCAL];
-    int F[F_NFLAG];
-    pic_status st = read_scalars(c, S, F);
-    if (st != PIC_OK) return st;
-    const double bb = S[S_BB] > 0 ? S[S_BB] : 1.0;
-    double relres = std::sqrt(S[S_RR64] / bb);
-    pic_solve_info si{};
-    si.relres0 = relres;
-    int total = 0, outer = 0;
-    const int mg = c->L.mg ? 1 : 0;
-    while (relres > c->cfg.rtol && total < c->cfg.max_iter && outer < 64 && std::isfinite(relres)) {
-        double eta = 0.3 * c->cfg.rtol / relres;
-        eta = std::min(0.5, std::max(eta, mg ? 2e-6 : 1e-5));
-        c->eta2_host = eta * eta;
-        int K = std::max(1, std::min(c->inner_chunk, c->cfg.max_iter - total));
-        K = round_chunk(K);
-        st = run_outer(c, K, c->eta2_host);
-        if (st != PIC_OK) return st;
-        st = read_scalars(c, S, F);
-        if (st != PIC_OK) return st;
-        total += F[F_ITER];
-        outer++;
-        relres = std::sqrt(S[S_RR64] / bb);
-        if (F[F_DONE]) c->inner_chunk = std::max(2, F[F_ITER] + 1);
-        else c->inner_chunk = std::min(2 * K, mg ? 64 : 4096);
-    }
-    if (c->g.px && c->g.py) launch_shift_mean(c->g, c->buf.phi, r, c->stream);
-    si.iterations = total;
-    si.outer = outer;
-    si.relres = relres;
-    si.converged = relres <= c->cfg.rtol ? 1 : 0;
-    c->last = si;
-    if (info) *info = si;
-    if (!si.converged) {
-        char msg[160];
-        snprintf(msg, sizeof msg, "solver stopped at relative residual %.3e after %d iterations",
-                 relres, total);
-        return fail(c, PIC_ERR_NOT_CONVERGED, msg);
-    }
+    S.resize((size_t)c->n * S_NSCAL);
+    F.resize((size_t)c->n * F_NFLAG);
+    HIPCHK(c, hipMemcpyAsync(S.data(), c->d_S, S.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(F.data(), c->d_F, F.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
+}
+
+void record_solve_info(pic_ctx *c, const std::vector<double> &S, const std::vector<int> &F)
+{
+    for (int k = 0; k < c->n; k++) {
+        const double *s = &S[(size_t)k * S_NSCAL];
+        const int *f = &F[(size_t)k * F_NFLAG];
+        const double bb = s[S_BB] > 0 ? s[S_BB] : 1.0;
+        pic_solve_info &si = c->in[k].last;
+        si.iterations = f[F_ITER_TOT];
+        si.outer = f[F_PASSES];
+        si.converged = f[F_CONV];
+        si.relres0 = std::sqrt(s[S_RELRES0] / bb);
+        si.relres = std::sqrt(s[S_RR64] / bb);
+    }
+}
+
+// Start of a solve: starting potential and the float64 residual.
+void enqueue_solve_start(pic_ctx *c, int kind, const double *guess, hipStream_t s)
+{
+    if (kind == 0 || kind == 2) launch_set_guess(c->d_inst, c->t_l0, kind, guess, s);
+    if (kind == 3) launch_extrapolate(c->d_inst, c->t_l0, c->have_prev ? 1 : 0, s);
+    launch_pin_shift(c->d_inst, c->t_per, s);
+    launch_resid64(c->d_inst, c->t_l0, 0, part_of(c), s);
+}
+
+pic_status do_solve(pic_ctx *c, int kind, const double *guess)
+{
+    enqueue_solve_start(c, kind, guess, c->stream);
+    c->have_prev = (kind == 3);
+    std::vector<double> S;
+    std::vector<int> F;
+    pic_status st = read_flags(c, S, F);
+    if (st != PIC_OK) return st;
+    int max_iter = 0;
+    for (auto &h : c->in) max_iter = std::max(max_iter, (int)h.cfg.max_iter);
+    for (int pass = 0; pass < 64; pass++) {
+        bool all = true;
+        bool finite = true;
+        int most = 0;
+        for (int k = 0; k < c->n; k++) {
+            const int *f = &F[(size_t)k * F_NFLAG];
+            if (!f[F_CONV]) all = false;
+            if (!std::isfinite(S[(size_t)k * S_NSCAL + S_RR64])) finite = false;
+            most = std::max(most, f[F_ITER_TOT]);
+        }
+        if (all || !finite || most >= max_iter) break;
+        int K = round_chunk(std::max(1, std::min(c->inner_chunk, max_iter - most)));
+        st = run_pass(c, K);
+        if (st != PIC_OK) return st;
+        st = read_flags(c, S, F);
+        if (st != PIC_OK) return st;
+        int need = 0;
+        bool unfinished = false;
+        for (int k = 0; k < c->n; k++) {
+            const int *f = &F[(size_t)k * F_NFLAG];
+            if (f[F_SKIP]) continue;
+            need = std::max(need, f[F_ITER]);
+            if (!f[F_DONE]) unfinished = true;
+        }
+        c->inner_chunk = unfinished ? std::min(2 * K, 128) : std::max(2, need + 1);
+    }
+    launch_shift_mean(c->d_inst, c->t_per, part_of(c), c->stream);
+    record_solve_info(c, S, F);
+    for (int k = 0; k < c->n; k++)
+        if (!c->in[k].last.converged) {
+            char msg[200];
+            snprintf(msg, sizeof msg, "instance %d: solver stopped at relative residual %.3e after %d iterations",
+                     k, c->in[k].last.relres, c->in[k].last.iterations);
+            return fail(c, PIC_ERR_NOT_CONVERGED, msg);
+        }
+    return PIC_OK;
+}
+
+// field, push + deposit of both species of every instance, step + 1,
+// assembly at the new time; re-binnings due after this step.
+void enqueue_push(pic_ctx *c, hipStream_t s, bool timed)
+{
+    launch_field(c->d_inst, c->t_field, 1, s);
+    const bool tm = timed && c->timing && c->nev < (int)c->ev0.size();
+    if (tm) (void)hipEventRecord(c->ev0[c->nev], s);
+    launch_push(c->d_push, c->t_push, true, c->unroll, c->merge, c->push_lds, s);
+    if (tm) {
+        (void)hipEventRecord(c->ev1[c->nev], s);
+        c->nev++;
+        for (auto &h : c->in) c->timed_particles += h.slots_ub[0] + h.slots_ub[1];
+    }
+    launch_tick(c->d_ctl, s);
+    enqueue_assemble(c, s);
+}
+
+int sorts_due(pic_ctx *c, long long step_after)
+{
+    int mask = 0;
+    for (int sp = 0; sp < 2; sp++) {
+        const int K = c->in[0].cfg.sort_interval[sp];
+        if (K > 0 && step_after % K == 0) mask |= 1 << sp;
+    }
+    return mask;
 }
 
 pic_status do_push(pic_ctx *c)
 {
-    launch_field(c->g, c->d_node_cond, c->buf.phi, c->d_E4,
-                 reinterpret_cast<unsigned long long *>(c->buf.rho[0]),
-                 reinterpret_cast<unsigned long long *>(c->buf.rho[1]), c->stream);
-    for (int s = 0; s < 2; s++) {
-        PushArgs a = push_args(c, s);
-        const bool tm = c->timing && c->nev < kMaxTiming;
-        if (tm) HIPCHK(c, hipEventRecord(c->ev0[c->nev], c->stream));
-        launch_push(a, (int)c->L.max_blocks[s], true, c->L.unroll, c->L.merge, c->stream);
-        if (tm) {
-            HIPCHK(c, hipEventRecord(c->ev1[c->nev], c->stream));
-            c->nev++;
-            c->timed_particles += c->slots_ub[s];
-        }
-    }
-    HIPCHK(c, hipGetLastError());
+    pic_status st = ensure_vwindow(c, c->step + 1, 1);
+    if (st != PIC_OK) return st;
+    enqueue_push(c, c->stream, true);
     c->step++;
-    enqueue_assemble(c);
-    for (int s = 0; s < 2; s++) {
-        const int K = c->cfg.sort_interval[s];
-        if (K > 0 && c->step % K == 0) enqueue_bin(c, s);
-    }
+    const int mask = sorts_due(c, c->step);
+    if (mask) enqueue_bin(c, mask, c->stream);
     HIPCHK(c, hipGetLastError());
+    return PIC_OK;
+}
+
+pic_status check(pic_ctx *c)
+{
+    if (!c || !c->d_inst) return fail(c, PIC_ERR_STATE, "not initialised");
+    return PIC_OK;
+}
+
+pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buffers *buf)
+{
+    InstHost &h = c->in[k];
+    const int64_t cap[2] = {buf->sp[0].capacity, buf->sp[1].capacity};
+    h.cfg = *cfg;
+    h.cell_cond.assign(cfg->cell_cond, cfg->cell_cond + (size_t)cfg->nx * cfg->ny);
+    h.cfg.cell_cond = h.cell_cond.data();
+    for (auto v8 : h.cell_cond)
+        if (v8 >= PIC_MAX_COND) return fail(c, PIC_ERR_ARG, "cell conductor id above 7");
+    if (!node_map(&h.cfg, h.node_cond))
+        return fail(c, PIC_ERR_ARG, "two different conductors meet at a node");
+    h.L = make_layout(&h.cfg, cap);
+    const Layout &L = h.L;
+    h.buf = *buf;
+    h.g = Geom{L.nx, L.ny, L.NX, L.NY, L.px, L.py};
+    for (int s = 0; s < 2; s++) {
+        h.loaded[s] = buf->sp[s].count;
+        h.slots_ub[s] = buf->sp[s].count;
+    }
+    // masks of every level: level 0 = Dirichlet nodes (plus node 0 pinned on a
+    // fully periodic grid); coarse node fixed iff its coincident fine node is
+    h.fixh.assign(L.nlev, {});
+    h.fixh[0].resize((size_t)L.NX * L.NY);
+    for (size_t q = 0; q < h.fixh[0].size(); q++) h.fixh[0][q] = h.node_cond[q] ? 1 : 0;
+    if (L.px && L.py) h.fixh[0][0] = 1;
+    for (int l = 1; l < L.nlev; l++) {
+        const int NXc = L.NXl[l], NYc = L.NYl[l], NYf = L.NYl[l - 1];
+        h.fixh[l].resize((size_t)NXc * NYc);
+        for (int I = 0; I < NXc; I++)
+            for (int J = 0; J < NYc; J++)
+                h.fixh[l][(size_t)I * NYc + J] = h.fixh[l - 1][(size_t)(2 * I) * NYf + 2 * J];
+    }
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(h.d_cell_cond, h.cell_cond.data(), h.cell_cond.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(h.d_node_cond, h.node_cond.data(), h.node_cond.size(), hipMemcpyHostToDevice, s));
+    for (int l = 0; l < L.nlev; l++)
+        HIPCHK(c, hipMemcpyAsync(h.d_fix[l], h.fixh[l].data(), h.fixh[l].size(), hipMemcpyHostToDevice, s));
+    // device descriptor
+    Inst &d = h.dev;
+    memset(&d, 0, sizeof d);
+    d.g = h.g;
+    d.nlev = L.nlev;
+    d.lg = L.mg ? L.lg : 0;
+    d.mg = L.mg ? 1 : 0;
+    for (int l = 0; l < L.nlev; l++) {
+        d.lev[l].NX = L.NXl[l];
+        d.lev[l].NY = L.NYl[l];
+        d.lev[l].u = h.d_u[l];
+        d.lev[l].g = h.d_g[l];
+        d.lev[l].fix = h.d_fix[l];
+    }
+    d.node_cond = h.d_node_cond;
+    d.cell_cond = h.d_cell_cond;
+    d.phi = buf->phi;
+    d.b = buf->b;
+    d.phi_prev = h.d_phi_prev;
+    d.rho[0] = reinterpret_cast<unsigned long long *>(buf->rho[0]);
+    d.rho[1] = reinterpret_cast<unsigned long long *>(buf->rho[1]);
+    d.e = h.d_e;
+    d.p[0] = h.d_p[0];
+    d.p[1] = h.d_p[1];
+    d.q = h.d_q;
+    d.E4 = h.d_E4;
+    d.S = c->d_S + (size_t)k * S_NSCAL;
+    d.F = c->d_F + (size_t)k * F_NFLAG;
+    d.surf = h.d_surf;
+    d.qcharge = std::ldexp(h.cfg.weight, -32);
+    d.charge_mode = h.cfg.charge_mode;
+    d.charge_row = h.cfg.charge_row;
+    d.sjl = h.cfg.static_j_lo;
+    d.sjh = h.cfg.static_j_hi;
+    d.sden = h.cfg.static_density;
+    d.rtol = h.cfg.rtol;
+    d.eta_min = d.mg ? 2e-6 : 1e-5;
+    if (L.mg) {
+        CoarseArgs &ca = d.coarse;
+        ca.nlev = L.nlev - L.lg;
+        int off = 0;
+        for (int q = 0; q < ca.nlev; q++) {
+            const int l = L.lg + q;
+            const int nn = L.NXl[l] * L.NYl[l];
+            ca.NX[q] = L.NXl[l];
+            ca.NY[q] = L.NYl[l];
+            ca.off_u[q] = off;
+            off += (nn * 4 + 15) & ~15;
+            ca.off_g[q] = off;
+            off += (nn * 4 + 15) & ~15;
+            ca.off_f[q] = off;
+            off += (nn + 15) & ~15;
+            ca.fix[q] = h.d_fix[l];
+        }
+        ca.lds_bytes = off;
+        ca.u_top = h.d_u[L.lg];
+        ca.g_top = h.d_g[L.lg];
+        ca.px = L.px;
+        ca.py = L.py;
+        const int last = ca.nlev - 1;
+        ca.sweeps = std::min(64, std::max(2, std::max(ca.NX[last], ca.NY[last])));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_inst + k, &d, sizeof d, hipMemcpyHostToDevice, s));
+    // particle kernels' arguments (both storage sets; info[7] selects)
+    for (int sp = 0; sp < 2; sp++) {
+        PushArgs a;
+        memset(&a, 0, sizeof a);
+        a.g = h.g;
+        a.TX = L.TX;
+        a.TY = L.TY;
+        a.lx = L.lx;
+        a.ly = L.ly;
+        a.tiles_y = L.tiles_y;
+        a.H = L.H;
+        a.WX = L.TX + 2 * L.H;
+        a.WY = L.TY + 2 * L.H;
+        a.cell_cond = h.d_cell_cond;
+        a.E4 = h.d_E4;
+        for (int q = 0; q < 2; q++) {
+            a.cell[q] = buf->sp[sp].cell[q];
+            a.ox[q] = buf->sp[sp].ox[q];
+            a.oy[q] = buf->sp[sp].oy[q];
+            a.vx[q] = buf->sp[sp].vx[q];
+            a.vy[q] = buf->sp[sp].vy[q];
+        }
+        a.table = h.d_table[sp];
+        a.info = h.d_info[sp];
+        a.rho = reinterpret_cast<unsigned long long *>(buf->rho[sp]);
+        a.qdt = (float)(h.cfg.alpha[sp] * h.cfg.dt);
+        a.dtf = (float)h.cfg.dt;
+        a.hq = (float)(0.5 * h.cfg.alpha[sp] * h.cfg.dt);
+        a.box_i_top = h.cfg.box_i_top;
+        a.box_j_lo = h.cfg.box_j_lo;
+        a.box_j_hi = h.cfg.box_j_hi;
+        a.species = sp;
+        a.inst = k;
+        a.tally = h.d_tally + sp * kNClass;
+        a.surf = (h.cfg.charge_mode == 2 && sp == 1) ? h.d_surf : nullptr;
+        a.log.rec = h.cfg.hitlog_capacity > 0 ? h.d_hits : nullptr;
+        a.log.count = h.d_misc + 1;
+        a.log.capacity = std::max<int64_t>(h.cfg.hitlog_capacity, 1);
+        a.log.species_mask = h.cfg.hitlog_species_mask;
+        a.step = c->d_ctl;
+        a.fallbacks = h.d_misc + 0;
+        HIPCHK(c, hipMemcpyAsync(c->d_push + 2 * k + sp, &a, sizeof a, hipMemcpyHostToDevice, s));
+        BinArgs b;
+        memset(&b, 0, sizeof b);
+        b.nx = L.nx;
+        b.ny = L.ny;
+        b.lx = L.lx;
+        b.ly = L.ly;
+        b.tiles_y = L.tiles_y;
+        b.ntiles = L.ntiles;
+        b.chunk = L.chunk;
+        b.bad = h.d_misc + 2;
+        for (int q = 0; q < 2; q++) {
+            b.cell[q] = buf->sp[sp].cell[q];
+            b.ox[q] = buf->sp[sp].ox[q];
+            b.oy[q] = buf->sp[sp].oy[q];
+            b.vx[q] = buf->sp[sp].vx[q];
+            b.vy[q] = buf->sp[sp].vy[q];
+        }
+        b.counts = h.d_counts[sp];
+        b.offsets = h.d_offsets[sp];
+        b.cursor = h.d_cursor[sp];
+        b.boff = h.d_boff[sp];
+        b.table = h.d_table[sp];
+        b.info = h.d_info[sp];
+        HIPCHK(c, hipMemcpyAsync(c->d_bin + 2 * k + sp, &b, sizeof b, hipMemcpyHostToDevice, s));
+        long long info[8] = {0, 0, buf->sp[sp].count, 0, 0, 0, 0, 0};
+        HIPCHK(c, hipMemcpyAsync(h.d_info[sp], info, sizeof info, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));   // the small host structs above go out of scope
+    }
+    HIPCHK(c, hipMemsetAsync(h.d_tally, 0, sizeof(unsigned long long) * 2 * kNClass, s));
+    HIPCHK(c, hipMemsetAsync(h.d_surf, 0, sizeof(unsigned long long) * (L.ny + 1), s));
+    HIPCHK(c, hipMemsetAsync(h.d_misc, 0, sizeof(unsigned long long) * 16, s));
+    HIPCHK(c, hipMemsetAsync(h.d_e, 0, sizeof(float) * (size_t)L.NX * L.NY, s));
+    HIPCHK(c, hipMemsetAsync(h.d_p[0], 0, sizeof(float) * (size_t)L.NX * L.NY, s));
+    HIPCHK(c, hipMemsetAsync(h.d_p[1], 0, sizeof(float) * (size_t)L.NX * L.NY, s));
+    HIPCHK(c, hipMemsetAsync(h.d_counts[0], 0, sizeof(unsigned) * L.ntiles, s));
+    HIPCHK(c, hipMemsetAsync(h.d_counts[1], 0, sizeof(unsigned) * L.ntiles, s));
+    HIPCHK(c, hipMemsetAsync(buf->phi, 0, sizeof(double) * (size_t)L.NX * L.NY, s));
+    return PIC_OK;
+}
+
+void build_tabs(pic_ctx *c)
+{
+    c->t_l0 = c->t_field = c->t_per = c->t_coarse = c->t_push = c->t_rewind = Tab{};
+    for (int l = 0; l < kMaxLev; l++) c->t_fine[l] = c->t_crs[l] = Tab{};
+    c->maxlg = 0;
+    c->coarse_lds = 0;
+    c->any_mg = 0;
+    c->push_lds = 0;
+    for (int k = 0; k < c->n; k++) {
+        const InstHost &h = c->in[k];
+        const Layout &L = h.L;
+        tab_add_grid(c->t_l0, k, L.NX, L.NY);
+        tab_add_grid(c->t_field, k, std::max(L.NX, L.nx), std::max(L.NY, L.ny));
+        if (L.px && L.py) tab_add_grid(c->t_per, k, L.NX, L.NY);
+        if (L.mg) {
+            c->any_mg = 1;
+            c->maxlg = std::max(c->maxlg, L.lg);
+            for (int l = 0; l < L.lg; l++) {
+                tab_add_grid(c->t_fine[l], k, L.NXl[l], L.NYl[l]);
+                tab_add_grid(c->t_crs[l], k, L.NXl[l + 1], L.NYl[l + 1]);
+            }
+            tab_add(c->t_coarse, k, 1);
+            c->coarse_lds = std::max(c->coarse_lds, h.dev.coarse.lds_bytes);
+        }
+        for (int s = 0; s < 2; s++) {
+            tab_add(c->t_push, 2 * k + s, (int)L.max_blocks[s]);
+            tab_add(c->t_rewind, 2 * k + s, (int)((h.slots_ub[s] + 255) / 256));
+        }
+        const size_t lds = (size_t)(L.TX + 2 * L.H) * (L.TY + 2 * L.H) * 16 + kNClass * 4 + 16;
+        c->push_lds = std::max(c->push_lds, lds);
+    }
+    c->unroll = c->in[0].L.unroll;
+    c->merge = c->in[0].L.merge;
+}
+
+pic_status batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void *ws, size_t wsb,
+                      void *stream, pic_ctx **out)
+{
+    if (!out) return PIC_ERR_ARG;
+    *out = nullptr;
+    pic_ctx *c = new (std::nothrow) pic_ctx();
+    if (!c) return PIC_ERR_ARG;
+    *out = c;
+    if (n < 1 || n > kMaxInst) return fail(c, PIC_ERR_ARG, "instance count must be 1..16");
+    if (!cfgs || !bufs) return fail(c, PIC_ERR_ARG, "null configurations or buffers");
+    if (!ws) return fail(c, PIC_ERR_ARG, "missing workspace");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, PIC_ERR_ARG, "workspace must be 256-byte aligned");
+    std::vector<int64_t> caps(2 * n);
+    for (int k = 0; k < n; k++) {
+        const pic_buffers *b = &bufs[k];
+        caps[2 * k] = b->sp[0].capacity;
+        caps[2 * k + 1] = b->sp[1].capacity;
+        std::string v = validate(&cfgs[k], &caps[2 * k]);
+        if (!v.empty()) return fail(c, PIC_ERR_ARG, "instance " + std::to_string(k) + ": " + v);
+        for (int s = 0; s < 2; s++) {
+            if (b->sp[s].count < 0 || b->sp[s].count > b->sp[s].capacity)
+                return fail(c, PIC_ERR_CAPACITY, "particle count exceeds capacity");
+            for (int q = 0; q < 2; q++)
+                if (b->sp[s].capacity > 0 &&
+                    (!b->sp[s].cell[q] || !b->sp[s].ox[q] || !b->sp[s].oy[q] || !b->sp[s].vx[q] || !b->sp[s].vy[q]))
+                    return fail(c, PIC_ERR_ARG, "missing particle buffer");
+            if (!b->rho[s]) return fail(c, PIC_ERR_ARG, "missing rho buffer");
+        }
+        if (!b->phi || !b->b) return fail(c, PIC_ERR_ARG, "missing phi or b");
+        const int us = cfgs[k].push_unroll, ms = cfgs[k].push_merge;
+        if (k > 0 && (us != cfgs[0].push_unroll || ms != cfgs[0].push_merge))
+            return fail(c, PIC_ERR_ARG, "all instances of a batch use one push variant");
+    }
+    const size_t need = carve_all(nullptr, n, cfgs, caps.data(), nullptr);
+    if (wsb < need) return fail(c, PIC_ERR_ARG, "workspace too small");
+    c->n = n;
+    c->in.resize(n);
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    carve_all(c, n, cfgs, caps.data(), reinterpret_cast<char *>(ws));
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemsetAsync(c->d_S, 0, sizeof(double) * n * S_NSCAL, s));
+    HIPCHK(c, hipMemsetAsync(c->d_F, 0, sizeof(int) * n * F_NFLAG, s));
+    for (int k = 0; k < n; k++) {
+        pic_status st = init_instance(c, k, &cfgs[k], &bufs[k]);
+        if (st != PIC_OK) return st;
+    }
+    build_tabs(c);
+    c->step = 0;
+    c->vbase = -1;
+    pic_status st = ensure_vwindow(c, 0, 0);
+    if (st != PIC_OK) return st;
+    enqueue_bin(c, 3, s);
+    c->ev0.resize(kMaxTiming);
+    c->ev1.resize(kMaxTiming);
+    for (int k = 0; k < kMaxTiming; k++) {
+        HIPCHK(c, hipEventCreate(&c->ev0[k]));
+        HIPCHK(c, hipEventCreate(&c->ev1[k]));
+    }
+    enqueue_deposit(c, s);
+    HIPCHK(c, hipGetLastError());
+    std::vector<unsigned long long> bad(n);
+    for (int k = 0; k < n; k++)
+        HIPCHK(c, hipMemcpyAsync(&bad[k], c->in[k].d_misc + 2, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int k = 0; k < n; k++)
+        if (bad[k]) return fail(c, PIC_ERR_ARG, "particles with cell codes outside the grid");
+    for (auto &h : c->in) h.fixh.clear();
+    return PIC_OK;
+}
+
+// Captured graph of P whole steps (fixed solver schedule: `passes` passes of
+// K iterations with per-instance early exit) ending with the re-binnings in
+// sort_mask.
+pic_status step_graph(pic_ctx *c, int P, int passes, int K, int sort_mask, hipGraphExec_t *ex)
+{
+    const long long key = ((long long)P << 32) | ((long long)passes << 24) | ((long long)K << 8) | sort_mask;
+    auto it = c->step_graphs.find(key);
+    if (it != c->step_graphs.end()) {
+        *ex = it->second;
+        return PIC_OK;
+    }
+    pic_status st = capture_begin(c);
+    if (st != PIC_OK) return st;
+    hipStream_t s = c->cap_stream;
+    for (int k = 0; k < P; k++) {
+        enqueue_solve_start(c, 3, nullptr, s);
+        for (int q = 0; q < passes; q++) enqueue_pass(c, K, s);
+        launch_shift_mean(c->d_inst, c->t_per, part_of(c), s);
+        enqueue_push(c, s, false);
+    }
+    if (sort_mask) enqueue_bin(c, sort_mask, s);
+    st = capture_end(c, ex);
+    if (st != PIC_OK) return st;
+    c->step_graphs.emplace(key, *ex);
     return PIC_OK;
 }
 
@@ -627,189 +979,78 @@ pic_status do_push(pic_ctx *c)
 
 extern "C" {
 
-const char *pic_version(void) { return "pic-gfx950 1.0"; }
+const char *pic_version(void) { return "pic-gfx950 1.1"; }
 
 const char *pic_last_error(const pic_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+pic_status pic_batch_workspace_size(int32_t n, const pic_config *cfgs, const int64_t *capacity, size_t *bytes)
+{
+    if (n < 1 || n > kMaxInst || !cfgs || !capacity || !bytes) return PIC_ERR_ARG;
+    for (int k = 0; k < n; k++)
+        if (!validate(&cfgs[k], capacity + 2 * k).empty()) return PIC_ERR_ARG;
+    *bytes = carve_all(nullptr, n, cfgs, capacity, nullptr);
+    return PIC_OK;
+}
+
 pic_status pic_workspace_size(const pic_config *cfg, const int64_t *capacity, size_t *bytes)
 {
-    std::string v = validate(cfg, capacity);
-    if (!v.empty() || !bytes || !capacity) return PIC_ERR_ARG;
-    Layout L = make_layout(cfg, capacity);
-    *bytes = carve(nullptr, L, cfg, nullptr);
-    return PIC_OK;
+    return pic_batch_workspace_size(1, cfg, capacity, bytes);
 }
 
 pic_status pic_init(const pic_config *cfg, const pic_buffers *buf, void *stream, pic_ctx **out)
 {
-    if (!out) return PIC_ERR_ARG;
-    *out = nullptr;
-    pic_ctx *c = new (std::nothrow) pic_ctx();
-    if (!c) return PIC_ERR_ARG;
-    *out = c;
-    if (!buf) return fail(c, PIC_ERR_ARG, "null buffers");
-    const int64_t cap[2] = {buf->sp[0].capacity, buf->sp[1].capacity};
-    std::string v = validate(cfg, cap);
-    if (!v.empty()) return fail(c, PIC_ERR_ARG, v);
-    for (int s = 0; s < 2; s++) {
-        if (buf->sp[s].count < 0 || buf->sp[s].count > buf->sp[s].capacity)
-            return fail(c, PIC_ERR_CAPACITY, "particle count exceeds capacity");
-        for (int k = 0; k < 2; k++)
-            if (buf->sp[s].capacity > 0 &&
-                (!buf->sp[s].cell[k] || !buf->sp[s].ox[k] || !buf->sp[s].oy[k] ||
-                 !buf->sp[s].vx[k] || !buf->sp[s].vy[k]))
-                return fail(c, PIC_ERR_ARG, "missing particle buffer");
-        if (!buf->rho[s]) return fail(c, PIC_ERR_ARG, "missing rho buffer");
+    if (!buf) {
+        if (out) *out = nullptr;
+        return PIC_ERR_ARG;
     }
-    if (!buf->phi || !buf->b || !buf->workspace) return fail(c, PIC_ERR_ARG, "missing phi, b or workspace");
-    if (reinterpret_cast<uintptr_t>(buf->workspace) & 255)
-        return fail(c, PIC_ERR_ARG, "workspace must be 256-byte aligned");
-    c->cfg = *cfg;
-    c->cell_cond.assign(cfg->cell_cond, cfg->cell_cond + (size_t)cfg->nx * cfg->ny);
-    c->cfg.cell_cond = c->cell_cond.data();
-    for (auto v8 : c->cell_cond)
-        if (v8 >= PIC_MAX_COND) return fail(c, PIC_ERR_ARG, "cell conductor id above 7");
-    if (!node_map(&c->cfg, c->node_cond))
-        return fail(c, PIC_ERR_ARG, "two different conductors meet at a node");
-    c->L = make_layout(&c->cfg, cap);
-    const Layout &L = c->L;
-    size_t need = carve(nullptr, L, &c->cfg, nullptr);
-    if (buf->workspace_bytes < need) return fail(c, PIC_ERR_ARG, "workspace too small");
-    carve(c, L, &c->cfg, reinterpret_cast<char *>(buf->workspace));
-    c->buf = *buf;
-    c->stream = reinterpret_cast<hipStream_t>(stream);
-    c->g.nx = L.nx;
-    c->g.ny = L.ny;
-    c->g.NX = L.NX;
-    c->g.NY = L.NY;
-    c->g.px = L.px;
-    c->g.py = L.py;
+    return batch_init(1, cfg, buf, buf->workspace, buf->workspace_bytes, stream, out);
+}
 
-    // masks of every level: level 0 = Dirichlet nodes (plus node 0 pinned on a
-    // fully periodic grid); coarse node fixed iff its coincident fine node is
-    std::vector<std::vector<uint8_t>> fix(L.nlev);
-    fix[0].resize((size_t)L.NX * L.NY);
-    for (size_t n = 0; n < fix[0].size(); n++) fix[0][n] = c->node_cond[n] ? 1 : 0;
-    if (L.px && L.py) fix[0][0] = 1;
-    for (int l = 1; l < L.nlev; l++) {
-        const int NXc = L.NXl[l], NYc = L.NYl[l], NYf = L.NYl[l - 1];
-        fix[l].resize((size_t)NXc * NYc);
-        for (int I = 0; I < NXc; I++)
-            for (int J = 0; J < NYc; J++)
-                fix[l][(size_t)I * NYc + J] = fix[l - 1][(size_t)(2 * I) * NYf + 2 * J];
-    }
-    hipStream_t s = c->stream;
-    HIPCHK(c, hipMemcpyAsync(c->d_cell_cond, c->cell_cond.data(), c->cell_cond.size(),
-                             hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->d_node_cond, c->node_cond.data(), c->node_cond.size(),
-                             hipMemcpyHostToDevice, s));
-    for (int l = 0; l < L.nlev; l++)
-        HIPCHK(c, hipMemcpyAsync(c->d_fix[l], fix[l].data(), fix[l].size(), hipMemcpyHostToDevice, s));
-    // coarse-kernel description
-    CoarseArgs &ca = c->coarse;
-    memset(&ca, 0, sizeof ca);
-    if (L.mg) {
-        ca.nlev = L.nlev - L.lg;
-        int off = 0;
-        for (int k = 0; k < ca.nlev; k++) {
-            const int l = L.lg + k;
-            const int n = L.NXl[l] * L.NYl[l];
-            ca.NX[k] = L.NXl[l];
-            ca.NY[k] = L.NYl[l];
-            ca.off_u[k] = off;
-            off += (n * 4 + 15) & ~15;
-            ca.off_g[k] = off;
-            off += (n * 4 + 15) & ~15;
-            ca.off_f[k] = off;
-            off += (n + 15) & ~15;
-            ca.fix[k] = c->d_fix[l];
-        }
-        ca.lds_bytes = off;
-        ca.u_top = c->d_u[L.lg];
-        ca.g_top = c->d_g[L.lg];
-        ca.px = L.px;
-        ca.py = L.py;
-        const int last = ca.nlev - 1;
-        ca.sweeps = std::min(64, std::max(2, std::max(ca.NX[last], ca.NY[last])));
-    }
-    // zero counters and scalars
-    HIPCHK(c, hipMemsetAsync(c->d_S, 0, sizeof(double) * S_NSCAL, s));
-    HIPCHK(c, hipMemsetAsync(c->d_F, 0, sizeof(int) * F_NFLAG, s));
-    HIPCHK(c, hipMemsetAsync(c->d_count, 0, sizeof(unsigned) * 16, s));
-    HIPCHK(c, hipMemsetAsync(c->d_tally, 0, sizeof(unsigned long long) * 2 * kNClass, s));
-    HIPCHK(c, hipMemsetAsync(c->d_surf, 0, sizeof(unsigned long long) * (L.ny + 1), s));
-    HIPCHK(c, hipMemsetAsync(c->d_misc, 0, sizeof(unsigned long long) * 16, s));
-    HIPCHK(c, hipMemsetAsync(c->d_e, 0, sizeof(float) * (size_t)L.NX * L.NY, s));
-    HIPCHK(c, hipMemsetAsync(c->d_p[0], 0, sizeof(float) * (size_t)L.NX * L.NY, s));
-    HIPCHK(c, hipMemsetAsync(c->buf.phi, 0, sizeof(double) * (size_t)L.NX * L.NY, s));
-    for (int sp = 0; sp < 2; sp++) {
-        long long info[8] = {0, 0, buf->sp[sp].count, 0, 0, 0, 0, 0};
-        HIPCHK(c, hipMemcpyAsync(c->d_info[sp], info, sizeof info, hipMemcpyHostToDevice, s));
-        c->cur[sp] = 0;
-        c->slots_ub[sp] = buf->sp[sp].count;
-        c->loaded[sp] = buf->sp[sp].count;
-        // the copy above reads host memory: finish it before info goes out of scope
-        HIPCHK(c, hipStreamSynchronize(s));
-        enqueue_bin(c, sp);
-    }
-    c->ev0.resize(kMaxTiming);
-    c->ev1.resize(kMaxTiming);
-    for (int k = 0; k < kMaxTiming; k++) {
-        HIPCHK(c, hipEventCreate(&c->ev0[k]));
-        HIPCHK(c, hipEventCreate(&c->ev1[k]));
-    }
-    c->step = 0;
-    enqueue_deposit(c);
-    HIPCHK(c, hipGetLastError());
-    unsigned long long bad = 0;
-    HIPCHK(c, hipMemcpyAsync(&bad, c->d_misc + 2, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (bad) return fail(c, PIC_ERR_ARG, "particles with cell codes outside the grid");
-    return PIC_OK;
+pic_status pic_batch_init(int32_t n, const pic_config *cfgs, const pic_buffers *bufs, void *workspace,
+                          size_t workspace_bytes, void *stream, pic_ctx **out)
+{
+    return batch_init(n, cfgs, bufs, workspace, workspace_bytes, stream, out);
 }
 
 pic_status pic_deposit(pic_ctx *c)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
-    enqueue_deposit(c);
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    enqueue_deposit(c, c->stream);
     HIPCHK(c, hipGetLastError());
     return PIC_OK;
 }
 
 pic_status pic_solve(pic_ctx *c, int32_t guess_kind, const double *guess, pic_solve_info *info)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
-    if (guess_kind < 0 || guess_kind > 3 || (guess_kind == 2 && !guess))
-        return fail(c, PIC_ERR_ARG, "guess_kind must be 0, 1, 2 (with a guess array) or 3");
-    return do_solve(c, guess_kind, guess, info);
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (guess_kind < 0 || guess_kind > 3 || (guess_kind == 2 && (!guess || c->n != 1)))
+        return fail(c, PIC_ERR_ARG, "guess_kind must be 0, 1, 2 (one instance, with a guess array) or 3");
+    pic_status st = do_solve(c, guess_kind, guess);
+    if (info) *info = c->in[0].last;
+    return st;
 }
 
 pic_status pic_rewind(pic_ctx *c)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
-    launch_field(c->g, c->d_node_cond, c->buf.phi, c->d_E4, nullptr, nullptr, c->stream);
-    for (int s = 0; s < 2; s++) {
-        const int k = c->cur[s];
-        const pic_species_buffers &B = c->buf.sp[s];
-        launch_rewind(c->g, c->d_E4, B.cell[k], B.ox[k], B.oy[k], B.vx[k], B.vy[k], c->slots_ub[s],
-                      c->d_info[s] + 2 + k, (float)(0.5 * c->cfg.alpha[s] * c->cfg.dt), c->stream);
-    }
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    launch_field(c->d_inst, c->t_field, 0, c->stream);
+    launch_rewind(c->d_push, c->t_rewind, c->stream);
     HIPCHK(c, hipGetLastError());
     return PIC_OK;
 }
 
 pic_status pic_push(pic_ctx *c)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
     return do_push(c);
 }
 
 pic_status pic_step(pic_ctx *c, int32_t nsteps)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
     if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps < 0");
     for (int k = 0; k < nsteps; k++) {
-        pic_status st = do_solve(c, c->cfg.warm_start == 1 ? 3 : 1, nullptr, nullptr);
+        pic_status st = do_solve(c, c->in[0].cfg.warm_start == 1 ? 3 : 1, nullptr);
         if (st != PIC_OK) return st;
         st = do_push(c);
         if (st != PIC_OK) return st;
@@ -817,41 +1058,74 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps)
     return PIC_OK;
 }
 
+pic_status pic_batch_step(pic_ctx *c, int32_t nsteps, int32_t passes, int32_t iters)
+{
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (nsteps < 0 || passes < 1 || passes > 8 || iters < 1 || iters > 128)
+        return fail(c, PIC_ERR_ARG, "nsteps >= 0, passes in 1..8, iters in 1..128");
+    if (!c->have_prev) {
+        // the captured schedule extrapolates from two earlier solutions
+        pic_status st = pic_step(c, 1);
+        if (st != PIC_OK) return st;
+        nsteps--;
+    }
+    const int P = c->in[0].cfg.sort_interval[0] > 0 ? c->in[0].cfg.sort_interval[0] : 8;
+    while (nsteps > 0) {
+        const int len = (int)std::min<long long>(nsteps, P - (c->step % P));
+        pic_status st = ensure_vwindow(c, c->step, len + 1);
+        if (st != PIC_OK) return st;
+        const int mask = sorts_due(c, c->step + len);
+        hipGraphExec_t ex;
+        st = step_graph(c, len, passes, iters, mask, &ex);
+        if (st != PIC_OK) return st;
+        HIPCHK(c, hipGraphLaunch(ex, c->stream));
+        c->step += len;
+        nsteps -= len;
+    }
+    std::vector<double> S;
+    std::vector<int> F;
+    pic_status st = read_flags(c, S, F);
+    if (st != PIC_OK) return st;
+    record_solve_info(c, S, F);
+    return PIC_OK;
+}
+
 pic_status pic_sort(pic_ctx *c, int32_t species)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
     if (species < 0 || species > 1) return fail(c, PIC_ERR_ARG, "species must be 0 or 1");
-    enqueue_bin(c, species);
+    enqueue_bin(c, 1 << species, c->stream);
     HIPCHK(c, hipGetLastError());
     return PIC_OK;
 }
 
-pic_status pic_diagnostics(pic_ctx *c, pic_diag *out)
+pic_status pic_batch_diagnostics(pic_ctx *c, int32_t i, pic_diag *out)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
-    if (!out) return fail(c, PIC_ERR_ARG, "null output");
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (!out || i < 0 || i >= c->n) return fail(c, PIC_ERR_ARG, "bad instance or output");
+    InstHost &h = c->in[i];
     hipStream_t s = c->stream;
-    HIPCHK(c, hipMemsetAsync(c->d_misc + 4, 0, 2 * sizeof(unsigned long long), s));
+    HIPCHK(c, hipMemsetAsync(h.d_misc + 4, 0, 2 * sizeof(unsigned long long), s));
     for (int sp = 0; sp < 2; sp++)
-        launch_rho_sum(reinterpret_cast<const unsigned long long *>(c->buf.rho[sp]),
-                       (long long)c->g.NX * c->g.NY, c->d_misc + 4 + sp, s);
+        launch_rho_sum(reinterpret_cast<const unsigned long long *>(h.buf.rho[sp]),
+                       (long long)h.g.NX * h.g.NY, h.d_misc + 4 + sp, s);
     unsigned long long tally[2 * kNClass], misc[16];
-    std::vector<unsigned long long> surf(c->L.ny + 1);
-    HIPCHK(c, hipMemcpyAsync(tally, c->d_tally, sizeof tally, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(misc, c->d_misc, sizeof misc, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(surf.data(), c->d_surf, surf.size() * 8, hipMemcpyDeviceToHost, s));
+    std::vector<unsigned long long> surf(h.L.ny + 1);
+    HIPCHK(c, hipMemcpyAsync(tally, h.d_tally, sizeof tally, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(misc, h.d_misc, sizeof misc, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(surf.data(), h.d_surf, surf.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     memset(out, 0, sizeof *out);
     out->step = c->step;
-    out->t = c->step * c->cfg.dt;
+    out->t = c->step * h.cfg.dt;
     for (int sp = 0; sp < 2; sp++) {
         long long lost = 0;
         for (int k = 0; k < kNClass; k++) {
             out->tally[sp][k] = (int64_t)tally[sp * kNClass + k];
             lost += (long long)tally[sp * kNClass + k];
         }
-        out->loaded[sp] = c->loaded[sp];
-        out->alive[sp] = c->loaded[sp] - lost;
+        out->loaded[sp] = h.loaded[sp];
+        out->alive[sp] = h.loaded[sp] - lost;
         out->charge[sp] = (int64_t)misc[4 + sp];
     }
     long long sh = 0;
@@ -859,44 +1133,59 @@ pic_status pic_diagnostics(pic_ctx *c, pic_diag *out)
     out->surf_hits = sh;
     out->hits_logged = (int64_t)misc[1];
     out->deposit_fallbacks = (int64_t)misc[0];
-    out->last_solve = c->last;
+    out->last_solve = h.last;
+    return PIC_OK;
+}
+
+pic_status pic_diagnostics(pic_ctx *c, pic_diag *out) { return pic_batch_diagnostics(c, 0, out); }
+
+pic_status pic_batch_particles(pic_ctx *c, int32_t i, int32_t species, int32_t *set, int64_t *slots)
+{
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (i < 0 || i >= c->n || species < 0 || species > 1) return fail(c, PIC_ERR_ARG, "bad instance or species");
+    long long info[8];
+    HIPCHK(c, hipMemcpyAsync(info, c->in[i].d_info[species], sizeof info, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (set) *set = (int32_t)info[7];
+    if (slots) *slots = info[2 + info[7]];
     return PIC_OK;
 }
 
 pic_status pic_particles(pic_ctx *c, int32_t species, int32_t *set, int64_t *slots)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
-    if (species < 0 || species > 1) return fail(c, PIC_ERR_ARG, "species must be 0 or 1");
-    long long info[8];
-    HIPCHK(c, hipMemcpyAsync(info, c->d_info[species], sizeof info, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (set) *set = c->cur[species];
-    if (slots) *slots = info[2 + c->cur[species]];
-    return PIC_OK;
+    return pic_batch_particles(c, 0, species, set, slots);
 }
 
 pic_status pic_read_hits(pic_ctx *c, pic_hit *out, int64_t max, int64_t *n)
 {
-    if (!c || !c->d_E4) return fail(c, PIC_ERR_STATE, "not initialised");
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
     if (!out || !n || max < 0) return fail(c, PIC_ERR_ARG, "bad output");
     *n = 0;
-    if (c->cfg.hitlog_capacity <= 0) return PIC_OK;
+    InstHost &h = c->in[0];
+    if (h.cfg.hitlog_capacity <= 0) return PIC_OK;
     unsigned long long total = 0;
-    HIPCHK(c, hipMemcpyAsync(&total, c->d_misc + 1, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&total, h.d_misc + 1, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const long long cap = c->cfg.hitlog_capacity;
-    long long have = (long long)std::min<unsigned long long>(total, (unsigned long long)cap);
-    long long take = std::min<long long>(have, max);
+    const long long cap = h.cfg.hitlog_capacity;
+    const long long have = (long long)std::min<unsigned long long>(total, (unsigned long long)cap);
+    const long long take = std::min<long long>(have, max);
     std::vector<int32_t> all((size_t)cap * 6);
-    HIPCHK(c, hipMemcpyAsync(all.data(), c->d_hits, all.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(all.data(), h.d_hits, all.size() * 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    // oldest of the kept records first
-    long long first = (long long)total - take;
+    const long long first = (long long)total - take;
     for (long long k = 0; k < take; k++) {
-        long long slot = (first + k) % cap;
+        const long long slot = (first + k) % cap;
         memcpy(&out[k], &all[(size_t)slot * 6], sizeof(pic_hit));
     }
     *n = take;
+    return PIC_OK;
+}
+
+pic_status pic_batch_solve_info(pic_ctx *c, int32_t i, pic_solve_info *out)
+{
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (!out || i < 0 || i >= c->n) return fail(c, PIC_ERR_ARG, "bad instance or output");
+    *out = c->in[i].last;
     return PIC_OK;
 }
 
@@ -930,8 +1219,9 @@ pic_status pic_push_timing(pic_ctx *c, double *avg_ms, double *avg_particles, in
 void pic_destroy(pic_ctx *c)
 {
     if (!c) return;
-    if (c->d_E4) (void)hipStreamSynchronize(c->stream);
+    if (c->d_inst) (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->outer_graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto e : c->ev0) if (e) (void)hipEventDestroy(e);
     for (auto e : c->ev1) if (e) (void)hipEventDestroy(e);

@@ -76,8 +76,9 @@ _lib = None
 
 ENTRY_POINTS = ["pic_workspace_size", "pic_init", "pic_deposit", "pic_solve", "pic_rewind",
                 "pic_push", "pic_step", "pic_diagnostics", "pic_particles", "pic_read_hits",
-                "pic_sort", "pic_push_timing", "pic_set_timing", "pic_destroy", "pic_last_error",
-                "pic_version"]
+                "pic_sort", "pic_push_timing", "pic_set_timing", "pic_batch_workspace_size",
+                "pic_batch_init", "pic_batch_step", "pic_batch_diagnostics", "pic_batch_particles",
+                "pic_batch_solve_info", "pic_destroy", "pic_last_error", "pic_version"]
 
 
 def lib():
@@ -103,6 +104,14 @@ def lib():
     L.pic_sort.argtypes = [P, i32]
     L.pic_push_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i32)]
     L.pic_set_timing.argtypes = [P, i32]
+    L.pic_batch_workspace_size.argtypes = [i32, C.POINTER(pic_config), C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_size_t)]
+    L.pic_batch_init.argtypes = [i32, C.POINTER(pic_config), C.POINTER(pic_buffers), P, C.c_size_t, P,
+                                 C.POINTER(P)]
+    L.pic_batch_step.argtypes = [P, i32, i32, i32]
+    L.pic_batch_diagnostics.argtypes = [P, i32, C.POINTER(pic_diag)]
+    L.pic_batch_particles.argtypes = [P, i32, i32, C.POINTER(i32), C.POINTER(i64)]
+    L.pic_batch_solve_info.argtypes = [P, i32, C.POINTER(pic_solve_info)]
     L.pic_destroy.argtypes = [P]
     L.pic_destroy.restype = None
     L.pic_last_error.argtypes = [P]
@@ -159,30 +168,24 @@ def make_config(w, *, solver=0, max_iter=2000, sort_interval=(8, 64), tile=(16, 
     return cfg, cc
 
 
-class Pic:
-    """One simulation context on one GPU.  Method names follow the C ABI."""
+class _Instance:
+    """Device buffers of one instance, allocated with torch."""
 
-    def __init__(self, w, particles, device="cuda:0", capacity=None, **opts):
-        import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
-        L = lib()
-        self.torch = torch
+    def __init__(self, torch, dev, w, particles, capacity, opts):
+        t = torch
         self.w = w
-        self.dev = torch.device(device)
         self.cfg, self._cc = make_config(w, **opts)
         counts = [int(p["cell"].size) for p in particles]
         cap = [int(capacity[s]) if capacity else max(counts[s], 1) for s in range(2)]
         self.capacity = cap
-        t = torch
         self.sets = []
         bufs = pic_buffers()
         for s in range(2):
             sets = []
             for k in range(2):
-                d = {"cell": t.full((cap[s],), -1, dtype=t.int32, device=self.dev)}
+                d = {"cell": t.full((cap[s],), -1, dtype=t.int32, device=dev)}
                 for f in ("ox", "oy", "vx", "vy"):
-                    d[f] = t.zeros((cap[s],), dtype=t.float32, device=self.dev)
+                    d[f] = t.zeros((cap[s],), dtype=t.float32, device=dev)
                 sets.append(d)
             p = particles[s]
             n = counts[s]
@@ -198,43 +201,86 @@ class Pic:
                 sb.oy[k] = sets[k]["oy"].data_ptr()
                 sb.vx[k] = sets[k]["vx"].data_ptr()
                 sb.vy[k] = sets[k]["vy"].data_ptr()
-        nodes = w.NX * w.NY
-        self.rho_t = [t.zeros((w.NX, w.NY), dtype=t.int64, device=self.dev) for _ in range(2)]
-        self.phi_t = t.zeros((w.NX, w.NY), dtype=t.float64, device=self.dev)
-        self.b_t = t.zeros((w.NX, w.NY), dtype=t.float64, device=self.dev)
-        ws = C.c_size_t(0)
-        capa = (C.c_int64 * 2)(*cap)
-        st = L.pic_workspace_size(C.byref(self.cfg), capa, C.byref(ws))
-        if st != PIC_OK:
-            raise PicError(st, "invalid configuration")
-        self.ws_t = t.empty((ws.value + 256,), dtype=t.uint8, device=self.dev)
-        base = self.ws_t.data_ptr()
-        off = (-base) % 256
+        self.rho_t = [t.zeros((w.NX, w.NY), dtype=t.int64, device=dev) for _ in range(2)]
+        self.phi_t = t.zeros((w.NX, w.NY), dtype=t.float64, device=dev)
+        self.b_t = t.zeros((w.NX, w.NY), dtype=t.float64, device=dev)
         bufs.rho[0] = self.rho_t[0].data_ptr()
         bufs.rho[1] = self.rho_t[1].data_ptr()
         bufs.phi = self.phi_t.data_ptr()
         bufs.b = self.b_t.data_ptr()
-        bufs.workspace = base + off
-        bufs.workspace_bytes = ws.value
         self.bufs = bufs
-        self.stream = t.cuda.current_stream(self.dev)
-        t.cuda.synchronize(self.dev)
-        ctx = C.c_void_p()
-        st = L.pic_init(C.byref(self.cfg), C.byref(bufs), C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
-        self.ctx = ctx
-        if st != PIC_OK:
-            msg = L.pic_last_error(ctx).decode() if ctx.value else "init failed"
-            L.pic_destroy(ctx)
-            self.ctx = None
-            raise PicError(st, msg)
-        self.nodes = nodes
 
-    # -- ABI calls ------------------------------------------------------
+
+class _Context:
+    """Shared parts of Pic and PicBatch: the context handle and error checks."""
+
+    ctx = None
+
     def _chk(self, st, allow=()):
         if st != PIC_OK and st not in allow:
             raise PicError(st, lib().pic_last_error(self.ctx).decode())
         return st
 
+    def _workspace(self, nbytes):
+        self.ws_t = self.torch.empty((nbytes + 256,), dtype=self.torch.uint8, device=self.dev)
+        base = self.ws_t.data_ptr()
+        return base + (-base) % 256
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().pic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _fail_init(self, st, ctx):
+        L = lib()
+        msg = L.pic_last_error(ctx).decode() if ctx.value else "init failed"
+        L.pic_destroy(ctx)
+        self.ctx = None
+        raise PicError(st, msg)
+
+
+class Pic(_Context):
+    """One simulation context on one GPU.  Method names follow the C ABI."""
+
+    def __init__(self, w, particles, device="cuda:0", capacity=None, **opts):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
+        L = lib()
+        self.torch = torch
+        self.w = w
+        self.dev = torch.device(device)
+        inst = _Instance(torch, self.dev, w, particles, capacity, opts)
+        self.inst = inst
+        self.cfg = inst.cfg
+        self.capacity = inst.capacity
+        self.sets = inst.sets
+        self.rho_t, self.phi_t, self.b_t = inst.rho_t, inst.phi_t, inst.b_t
+        ws = C.c_size_t(0)
+        capa = (C.c_int64 * 2)(*inst.capacity)
+        st = L.pic_workspace_size(C.byref(inst.cfg), capa, C.byref(ws))
+        if st != PIC_OK:
+            raise PicError(st, "invalid configuration")
+        bufs = inst.bufs
+        bufs.workspace = self._workspace(ws.value)
+        bufs.workspace_bytes = ws.value
+        self.bufs = bufs
+        self.stream = torch.cuda.current_stream(self.dev)
+        torch.cuda.synchronize(self.dev)
+        ctx = C.c_void_p()
+        st = L.pic_init(C.byref(inst.cfg), C.byref(bufs), C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        self.ctx = ctx
+        if st != PIC_OK:
+            self._fail_init(st, ctx)
+        self.nodes = w.NX * w.NY
+
+    # -- ABI calls ------------------------------------------------------
     def pic_deposit(self):
         self._chk(lib().pic_deposit(self.ctx))
 
@@ -295,17 +341,6 @@ class Pic:
         self._chk(lib().pic_push_timing(self.ctx, C.byref(ms), C.byref(npart), C.byref(k)))
         return ms.value, npart.value, k.value
 
-    def close(self):
-        if getattr(self, "ctx", None):
-            lib().pic_destroy(self.ctx)
-            self.ctx = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
     # -- views ------------------------------------------------------------
     def particles(self, s):
         """Current particle arrays of species s (torch views of the live slots)."""
@@ -329,6 +364,95 @@ class Pic:
 
     def start(self):
         """Solve at t = 0 and move the velocities back half a step (leapfrog start)."""
+        info = self.pic_solve(0)
+        self.pic_rewind()
+        return info
+
+
+class PicBatch(_Context):
+    """Several independent instances (e.g. a trench-width sweep) in one
+    context; every kernel launch covers all of them (pic_batch_* calls)."""
+
+    def __init__(self, workloads, particles, device="cuda:0", **opts):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
+        L = lib()
+        self.torch = torch
+        self.dev = torch.device(device)
+        self.ws = list(workloads)
+        self.n = len(self.ws)
+        self.insts = [_Instance(torch, self.dev, w, p, None, opts) for w, p in zip(self.ws, particles)]
+        cfgs = (pic_config * self.n)(*[x.cfg for x in self.insts])
+        bufs = (pic_buffers * self.n)(*[x.bufs for x in self.insts])
+        caps = (C.c_int64 * (2 * self.n))(*[c for x in self.insts for c in x.capacity])
+        nb = C.c_size_t(0)
+        st = L.pic_batch_workspace_size(self.n, cfgs, caps, C.byref(nb))
+        if st != PIC_OK:
+            raise PicError(st, "invalid configuration")
+        wsp = self._workspace(nb.value)
+        self._cfgs, self._bufs = cfgs, bufs
+        self.stream = torch.cuda.current_stream(self.dev)
+        torch.cuda.synchronize(self.dev)
+        ctx = C.c_void_p()
+        st = L.pic_batch_init(self.n, cfgs, bufs, C.c_void_p(wsp), nb.value,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        self.ctx = ctx
+        if st != PIC_OK:
+            self._fail_init(st, ctx)
+
+    def pic_solve(self, guess_kind=1):
+        self._chk(lib().pic_solve(self.ctx, int(guess_kind), None, None))
+        return [self.pic_batch_solve_info(i) for i in range(self.n)]
+
+    def pic_rewind(self):
+        self._chk(lib().pic_rewind(self.ctx))
+
+    def pic_push(self):
+        self._chk(lib().pic_push(self.ctx))
+
+    def pic_step(self, n=1):
+        self._chk(lib().pic_step(self.ctx, int(n)))
+
+    def pic_batch_step(self, n, passes=2, iters=12):
+        self._chk(lib().pic_batch_step(self.ctx, int(n), int(passes), int(iters)))
+        return [self.pic_batch_solve_info(i) for i in range(self.n)]
+
+    def pic_batch_solve_info(self, i):
+        info = pic_solve_info()
+        self._chk(lib().pic_batch_solve_info(self.ctx, int(i), C.byref(info)))
+        return info.as_dict()
+
+    def pic_batch_diagnostics(self, i):
+        d = pic_diag()
+        self._chk(lib().pic_batch_diagnostics(self.ctx, int(i), C.byref(d)))
+        return {
+            "step": d.step, "t": d.t, "alive": list(d.alive), "loaded": list(d.loaded),
+            "charge": list(d.charge), "tally": [list(d.tally[s]) for s in range(2)],
+            "surf_hits": d.surf_hits, "hits_logged": d.hits_logged,
+            "deposit_fallbacks": d.deposit_fallbacks, "last_solve": d.last_solve.as_dict(),
+        }
+
+    def pic_batch_particles(self, i, s):
+        sset, slots = C.c_int32(0), C.c_int64(0)
+        self._chk(lib().pic_batch_particles(self.ctx, int(i), int(s), C.byref(sset), C.byref(slots)))
+        return sset.value, slots.value
+
+    def particles_numpy(self, i, s):
+        k, n = self.pic_batch_particles(i, s)
+        self.torch.cuda.synchronize(self.dev)
+        return {f: v[:n].cpu().numpy() for f, v in self.insts[i].sets[s][k].items()}
+
+    def rho(self, i, s):
+        return self.insts[i].rho_t[s]
+
+    def phi(self, i):
+        return self.insts[i].phi_t
+
+    def b(self, i):
+        return self.insts[i].b_t
+
+    def start(self):
         info = self.pic_solve(0)
         self.pic_rewind()
         return info
