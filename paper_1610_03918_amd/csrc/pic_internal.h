@@ -161,7 +161,7 @@ enum {
 void launch_zero_u64(unsigned long long *p, long long n, hipStream_t s);
 void launch_field(const Inst *I, const Tab &t, int zero_rho, hipStream_t s);
 void launch_assemble(const Inst *I, const Tab &t, const double *Vtab, const long long *ctl,
-                     int ninst, Part pt, hipStream_t s);
+                     int ninst, int vwin, Part pt, hipStream_t s);
 void launch_project_mean(const Inst *I, const Tab &t, Part pt, hipStream_t s);
 void launch_shift_mean(const Inst *I, const Tab &t, Part pt, hipStream_t s);
 void launch_pin_shift(const Inst *I, const Tab &t, hipStream_t s);

@@ -272,13 +272,17 @@ void launch_field(const Inst *I, const Tab &t, int zero_rho, hipStream_t s)
 
 // V: conductor potentials of every step of the table window, indexed
 // ((step - base) * ninst + instance) * 8 with the device step counter.
+// A window row outside [0, vwin) (never produced by the runtime) falls back
+// to row 0 rather than reading outside the table.
 __global__ void k_assemble(const Inst *insts, Tab t, const double *Vtab, const long long *ctl,
-                           int ninst, Part pt)
+                           int ninst, int vwin, Part pt)
 {
     GRID_BEGIN(t)
     const Geom g = I.g;
     NODE_IDX(g.NX, g.NY)
-    const double *V = Vtab + ((ctl[0] - ctl[1]) * ninst + t.id[ku]) * 8;
+    long long row = ctl[0] - ctl[1];
+    if (row < 0 || row >= vwin) row = 0;
+    const double *V = Vtab + (row * ninst + t.id[ku]) * 8;
     double bb = 0.0, sm = 0.0;
     if (inb) {
         const uint8_t *nc = I.node_cond;
@@ -312,10 +316,11 @@ __global__ void k_assemble(const Inst *insts, Tab t, const double *Vtab, const l
 }
 
 void launch_assemble(const Inst *I, const Tab &t, const double *Vtab, const long long *ctl,
-                     int ninst, Part pt, hipStream_t s)
+                     int ninst, int vwin, Part pt, hipStream_t s)
 {
     if (!t.n) return;
-    hipLaunchKernelGGL(k_assemble, dim3(tab_blocks(t)), gblock(), 0, s, I, t, Vtab, ctl, ninst, pt);
+    hipLaunchKernelGGL(k_assemble, dim3(tab_blocks(t)), gblock(), 0, s, I, t, Vtab, ctl, ninst, vwin,
+                       pt);
     finalize(I, t, pt, OP_ASM, s);
 }
 

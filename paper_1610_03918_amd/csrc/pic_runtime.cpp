@@ -401,12 +401,12 @@ void fill_vwindow(pic_ctx *c, long long first)
     }
 }
 
-// Keeps steps [from, from + ahead] inside the device window of potentials.
-pic_status ensure_vwindow(pic_ctx *c, long long from, long long ahead)
+// Uploads the potentials of steps [first, first + kVWindow) and the device
+// step counter / window start.
+pic_status upload_vwindow(pic_ctx *c, long long first)
 {
-    if (from >= c->vbase && from + ahead < c->vbase + kVWindow) return PIC_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    fill_vwindow(c, from);
+    fill_vwindow(c, first);
     long long ctl[2] = {c->step, c->vbase};
     HIPCHK(c, hipMemcpyAsync(c->d_V, c->vhost.data(), c->vhost.size() * sizeof(double),
                              hipMemcpyHostToDevice, c->stream));
@@ -415,9 +415,16 @@ pic_status ensure_vwindow(pic_ctx *c, long long from, long long ahead)
     return PIC_OK;
 }
 
+// Keeps steps [from, from + ahead] inside the device window of potentials.
+pic_status ensure_vwindow(pic_ctx *c, long long from, long long ahead)
+{
+    if (from >= c->vbase && from + ahead < c->vbase + kVWindow) return PIC_OK;
+    return upload_vwindow(c, from);
+}
+
 void enqueue_assemble(pic_ctx *c, hipStream_t s)
 {
-    launch_assemble(c->d_inst, c->t_l0, c->d_V, c->d_ctl, c->n, part_of(c), s);
+    launch_assemble(c->d_inst, c->t_l0, c->d_V, c->d_ctl, c->n, kVWindow, part_of(c), s);
     launch_project_mean(c->d_inst, c->t_per, part_of(c), s);
 }
 
@@ -926,8 +933,7 @@ pic_status batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, vo
     }
     build_tabs(c);
     c->step = 0;
-    c->vbase = -1;
-    pic_status st = ensure_vwindow(c, 0, 0);
+    pic_status st = upload_vwindow(c, 0);
     if (st != PIC_OK) return st;
     enqueue_bin(c, 3, s);
     c->ev0.resize(kMaxTiming);
@@ -1015,6 +1021,8 @@ pic_status pic_batch_init(int32_t n, const pic_config *cfgs, const pic_buffers *
 pic_status pic_deposit(pic_ctx *c)
 {
     if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    pic_status st = ensure_vwindow(c, c->step, 0);
+    if (st != PIC_OK) return st;
     enqueue_deposit(c, c->stream);
     HIPCHK(c, hipGetLastError());
     return PIC_OK;
