@@ -53,6 +53,16 @@ def test_batch_init_deposit_matches_oracle():
         assert np.array_equal(b.b(i).cpu().numpy(), oracle.assemble(w, nc, rho[0], rho[1], 0.0))
     info = b.start()
     assert all(x["converged"] for x in info)
+    # after a push the Dirichlet nodes carry the conductor potentials at t = dt
+    for _ in range(3):
+        b.pic_push()
+    for i, w in enumerate(ws):
+        nc = oracle.node_cond(w)
+        V = w.voltages(3 * w.dt)
+        got = b.b(i).cpu().numpy()
+        assert np.array_equal(got[nc != 0], V[nc[nc != 0]])
+        if w.v_amp[2]:
+            assert np.any(got[nc == 2] != 0.0)
     b.close()
 
 
