@@ -904,29 +904,60 @@ __device__ __forceinline__ void wave_sum4_u32(unsigned &a, unsigned &b, unsigned
 }
 #undef DPP_STEP
 
-// The storage set in use (device info[7], flipped by every re-binning).
-struct PView {
+// Arguments of the particle kernels resolved once per block into plain
+// scalars and pointers (the storage set in use is device info[7], flipped
+// by every re-binning), so particle stores cannot force them to be reloaded.
+struct PK {
+    Geom g;
+    int TX, TY, H, WX, WY, tiles_y;
+    const uint8_t *cell_cond;
+    const float4 *E4;
     int32_t *cell;
     float *ox, *oy, *vx, *vy;
+    unsigned long long *rho;
+    float qdt, dtf, hq;
+    int box_i_top, box_j_lo, box_j_hi, species;
+    unsigned long long *surf;
+    HitLog log;
+    const long long *step;
 };
 
-__device__ __forceinline__ PView pview(const PushArgs &a)
+__device__ __forceinline__ PK resolve(const PushArgs &a)
 {
+    PK k;
     const int set = (int)a.info[7];
-    PView v;
-    v.cell = a.cell[set];
-    v.ox = a.ox[set];
-    v.oy = a.oy[set];
-    v.vx = a.vx[set];
-    v.vy = a.vy[set];
-    return v;
+    k.g = a.g;
+    k.TX = a.TX;
+    k.TY = a.TY;
+    k.H = a.H;
+    k.WX = a.WX;
+    k.WY = a.WY;
+    k.tiles_y = a.tiles_y;
+    k.cell_cond = a.cell_cond;
+    k.E4 = a.E4;
+    k.cell = set ? a.cell[1] : a.cell[0];
+    k.ox = set ? a.ox[1] : a.ox[0];
+    k.oy = set ? a.oy[1] : a.oy[0];
+    k.vx = set ? a.vx[1] : a.vx[0];
+    k.vy = set ? a.vy[1] : a.vy[0];
+    k.rho = a.rho;
+    k.qdt = a.qdt;
+    k.dtf = a.dtf;
+    k.hq = a.hq;
+    k.box_i_top = a.box_i_top;
+    k.box_j_lo = a.box_j_lo;
+    k.box_j_hi = a.box_j_hi;
+    k.species = a.species;
+    k.surf = a.surf;
+    k.log = a.log;
+    k.step = a.step;
+    return k;
 }
 
 // Leapfrog push of one particle with the bilinear gather of its cell's
 // corner fields and the cell-by-cell wall test (eqs. 1-4).  Updates the
 // particle in memory; returns false when it was removed (class in *dead).
-__device__ __forceinline__ bool push_particle(const PushArgs &a, const PView &v, int p, int c,
-                                              float &x0, float &y0,
+__device__ __forceinline__ bool push_particle(const PK &a, int p, int c, float &x0, float &y0,
                                               float vx0, float vy0, float4 ea, float4 eb, int &ci,
                                               int &cj, int &dead, int &ei, int &ej, float &ux,
                                               float &uy)
@@ -947,8 +978,8 @@ __device__ __forceinline__ bool push_particle(const PushArgs &a, const PView &v,
     const float Dx = ux * a.dtf, Dy = uy * a.dtf;
     const float x1 = x0 + Dx, y1 = y0 + Dy;
     const float fsx = floorf(x1), fsy = floorf(y1);
-    v.vx[p] = ux;
-    v.vy[p] = uy;
+    a.vx[p] = ux;
+    a.vy[p] = uy;
     dead = -1;
     ei = ci;
     ej = cj;
@@ -991,16 +1022,16 @@ __device__ __forceinline__ bool push_particle(const PushArgs &a, const PView &v,
         }
     }
     if (dead >= 0) {
-        v.cell[p] = -1 - dead;
+        a.cell[p] = -1 - dead;
         return false;
     }
     float nxo = x1 - (float)sx, nyo = y1 - (float)sy;
     if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
     if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
-    v.ox[p] = nxo;
-    v.oy[p] = nyo;
+    a.ox[p] = nxo;
+    a.oy[p] = nyo;
     const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
-    if (nc != c) v.cell[p] = nc;
+    if (nc != c) a.cell[p] = nc;
     x0 = nxo;
     y0 = nyo;
     ci = ei;
@@ -1009,7 +1040,7 @@ __device__ __forceinline__ bool push_particle(const PushArgs &a, const PView &v,
 }
 
 // Records a removal: class counter in LDS, trench-bottom charge, hit ring.
-__device__ __forceinline__ void record_hit(const PushArgs &a, unsigned *tl, int dead, int ei, int ej,
+__device__ __forceinline__ void record_hit(const PK &a, unsigned *tl, int dead, int ei, int ej,
                                            float ux, float uy)
 {
     atomicAdd(&tl[dead], 1u);
@@ -1040,11 +1071,13 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int ku = unit_of(t, (int)blockIdx.x);
-    const PushArgs &a = A[t.id[ku]];
+    const PushArgs &aa = A[t.id[ku]];
     const int lb = (int)blockIdx.x - t.boff[ku];
-    if ((long long)lb >= a.info[1]) return;
-    const int4 ent = a.table[lb];
-    const PView v = pview(a);
+    if ((long long)lb >= aa.info[1]) return;
+    const int4 ent = aa.table[lb];
+    const PK a = resolve(aa);
+    unsigned long long *const tally = aa.tally;
+    unsigned long long *const fallbacks = aa.fallbacks;
     const int tile = ent.x, start = ent.y, end = ent.z;
     const int ti = tile / a.tiles_y, tj = tile - ti * a.tiles_y;
     const int i0 = ti * a.TX - a.H, j0 = tj * a.TY - a.H;
@@ -1075,17 +1108,17 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int p = base + u * kPushThreads + tid;
-            cu[u] = (p < end) ? v.cell[p] : -1;
+            cu[u] = (p < end) ? a.cell[p] : -1;
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int p = base + u * kPushThreads + tid;
             if (p < end) {
-                xu[u] = v.ox[p];
-                yu[u] = v.oy[p];
+                xu[u] = a.ox[p];
+                yu[u] = a.oy[p];
                 if (PUSH) {
-                    vxu[u] = v.vx[p];
-                    vyu[u] = v.vy[p];
+                    vxu[u] = a.vx[p];
+                    vyu[u] = a.vy[p];
                 }
             }
         }
@@ -1111,7 +1144,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
                 if (PUSH) {
                     int dead, ei, ej;
                     float vnx, vny;
-                    alive = push_particle(a, v, p, c, x0, y0, vxu[u], vyu[u], eau[u], ebu[u], ci, cj,
+                    alive = push_particle(a, p, c, x0, y0, vxu[u], vyu[u], eau[u], ebu[u], ci, cj,
                                           dead, ei, ej, vnx, vny);
                     if (!alive) record_hit(a, tl, dead, ei, ej, vnx, vny);
                 }
@@ -1164,7 +1197,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
             }
         }
     }
-    if (nfb) atomicAdd(a.fallbacks, nfb);
+    if (nfb) atomicAdd(fallbacks, nfb);
     __syncthreads();
     // flush: node (wa, wb) of the window collects the four cells around it
     const unsigned long long S = 65536ull;
@@ -1197,7 +1230,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
         else if (gj < 0 || gj >= g.NY) continue;
         atomicAdd(&a.rho[(long long)gi * g.NY + gj], v);
     }
-    if (PUSH && tid < kNClass && tl[tid]) atomicAdd(&a.tally[tid], (unsigned long long)tl[tid]);
+    if (PUSH && tid < kNClass && tl[tid]) atomicAdd(&tally[tid], (unsigned long long)tl[tid]);
 }
 
 template <bool PUSH>
@@ -1229,16 +1262,16 @@ void launch_push(const PushArgs *A, const Tab &t, bool push, int unroll, int mer
 __global__ void k_rewind(const PushArgs *A, Tab t)
 {
     const int ku = unit_of(t, (int)blockIdx.x);
-    const PushArgs &a = A[t.id[ku]];
+    const PushArgs &aa = A[t.id[ku]];
     const long long p = (long long)((int)blockIdx.x - t.boff[ku]) * blockDim.x + threadIdx.x;
-    if (p >= a.info[2 + a.info[7]]) return;
-    const PView v = pview(a);
-    const int c = v.cell[p];
+    if (p >= aa.info[2 + aa.info[7]]) return;
+    const PK a = resolve(aa);
+    const int c = a.cell[p];
     if (c < 0) return;
     const int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
     const long long cc = (long long)ci * a.g.ny + cj;
     const float4 ea = a.E4[2 * cc], eb = a.E4[2 * cc + 1];
-    const float x0 = v.ox[p], y0 = v.oy[p];
+    const float x0 = a.ox[p], y0 = a.oy[p];
     const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
     const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
     float ex = w00 * ea.x;
@@ -1249,8 +1282,8 @@ __global__ void k_rewind(const PushArgs *A, Tab t)
     ey = ey + w10 * ea.w;
     ey = ey + w01 * eb.y;
     ey = ey + w11 * eb.w;
-    v.vx[p] = v.vx[p] - a.hq * ex;
-    v.vy[p] = v.vy[p] - a.hq * ey;
+    a.vx[p] = a.vx[p] - a.hq * ex;
+    a.vy[p] = a.vy[p] - a.hq * ey;
 }
 
 void launch_rewind(const PushArgs *A, const Tab &t, hipStream_t s)
