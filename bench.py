@@ -102,6 +102,19 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration():
+    """A plain device copy of known size (1 GiB read + 1 GiB written), the
+    reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes."""
+    import torch
+    n = 1 << 28                                     # 2^28 float32 = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +122,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="trench1024x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sort", default="8,64")
     ap.add_argument("--unroll", type=int, default=2)
     ap.add_argument("--merge", type=int, default=0)
@@ -121,6 +136,8 @@ def main():
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calibration:
+        return copy_calibration()
     if args.workload == "sweep":
         return run_sweep(args)
 
