@@ -20,6 +20,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 40      # 20 B read + 20 B written per particle (cell, ox, oy, vx, vy)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "push_trench1024x512_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_03918_amd", "csrc", "pic_kernels.hip")
 
 
 def log(*a):
@@ -37,6 +39,28 @@ def workload(name):
     if name.startswith("trench_small"):
         return synth.trench(nx=256, ny=128, width=8, depth=32, ppc=64)
     raise SystemExit(f"unknown workload {name}")
+
+
+def measured_traffic(workload_name, particles_per_launch):
+    """HBM bytes per push launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (scaled by the plain-copy calibration), rescaled to the
+    live particle count.  None when the kernel source changed since the
+    counters were taken, or for another workload."""
+    import hashlib
+    if not workload_name.startswith("trench1024x512") or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, _, v = line.partition(":")
+            kv[k.strip()] = v.strip()
+    try:
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"]) * particles_per_launch / float(kv["particles_per_launch"])
+    except (KeyError, ValueError, OSError):
+        return None
 
 
 def cpu_baseline(w, parts):
@@ -187,6 +211,7 @@ def main():
     value = particle_steps / elapsed
     per_launch = 0.5 * (alive0 + alive1)           # one push launch covers both species
     achieved = per_launch * BYTES_PER_PARTICLE_STEP / (push_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w.name, per_launch)
     out = {
         "metric": "particle-steps/s (push+deposit+solve)",
         "value": value,
@@ -208,7 +233,8 @@ def main():
         "poisson_iters_per_step": iters / args.steps,
         "poisson_start_relres_median": float(np.median(r0)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "kernel": "k_push<true,2,0>", "avg_launch_ms": push_ms, "launches": launches,
                      "bytes_per_launch": per_launch * BYTES_PER_PARTICLE_STEP},
     }
