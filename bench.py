@@ -19,6 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0         # dense bf16 MFMA
 BYTES_PER_PARTICLE_STEP = 40      # 20 B read + 20 B written per particle (cell, ox, oy, vx, vy)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "push_trench1024x512_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_03918_amd", "csrc", "pic_kernels.hip")
@@ -41,12 +42,23 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def push_source_hash():
+    """sha256 of what the push kernel is built from: the internal header and
+    the particle section of the kernel source (gather, push, wall test,
+    deposit), so that edits elsewhere in the file keep its counters valid."""
+    import hashlib
+    hdr = open(os.path.join(os.path.dirname(KERNEL_SOURCE), "pic_internal.h"), "rb").read()
+    src = open(KERNEL_SOURCE, "rb").read()
+    a = src.index(b"// particles: gather, leapfrog push")
+    b = src.index(b"// re-binning: counting sort")
+    return hashlib.sha256(hdr + src[a:b]).hexdigest()
+
+
 def measured_traffic(workload_name, particles_per_launch):
     """HBM bytes per push launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE passes (scaled by the plain-copy calibration), rescaled to the
-    live particle count.  None when the kernel source changed since the
-    counters were taken, or for another workload."""
-    import hashlib
+    live particle count.  None when the push kernel's source changed since
+    the counters were taken, or for another workload."""
     if not workload_name.startswith("trench1024x512") or not os.path.exists(TRAFFIC_PROFILE):
         return None
     kv = {}
@@ -55,8 +67,7 @@ def measured_traffic(workload_name, particles_per_launch):
             k, _, v = line.partition(":")
             kv[k.strip()] = v.strip()
     try:
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256") != sha:
+        if kv.get("push_source_sha256") != push_source_hash():
             return None
         return float(kv["traffic_bytes_per_launch"]) * particles_per_launch / float(kv["particles_per_launch"])
     except (KeyError, ValueError, OSError):
@@ -81,6 +92,88 @@ def cpu_baseline(w, parts):
             "sample": f"one full step of {w.name} ({n} particles, {w.nx}x{w.ny} cells) "
                       f"after the oracle's start (sparse LU factorisation excluded), "
                       f"{t3 - t2:.1f} s of CPU time"}
+
+
+def flops_per_inference(H, W):
+    """Algorithmic multiply-add flops of one U-Net inference on H x W pixels
+    (2 per multiply-add over every 3x3 convolution and the 1x1 head)."""
+    from paper_1610_03918_amd.unet import layers
+    fl = 0
+    ys = layers()
+    for y in ys[:-1]:
+        P = (H >> y["level"]) * (W >> y["level"])
+        fl += 2 * P * y["cout"] * 9 * y["cin"]
+    return fl + 2 * H * W * 16
+
+
+def learned_start(w, pic, parts, args):
+    """Plain masked CG to the workload's tolerance on held-out snapshots of
+    this run, from a cold start and from the U-Net's prediction (inference
+    included); the network is first trained on earlier snapshots of the same
+    run with the library's forward / backward / Adam kernels."""
+    import numpy as np
+    import torch
+
+    from paper_1610_03918_amd import Pic, learned
+    from paper_1610_03918_amd.unet import UNet
+    t0 = time.perf_counter()
+    train = learned.collect(pic, args.learn_snapshots)
+    for _ in range(8):
+        pic.pic_step(1)
+    evals = learned.collect(pic, args.learn_evals + 1)
+    sc = learned.scales(w, train, pic.node_map_host())
+    H, W = learned.window(w)
+    net = UNet(args.learn_batch, H, W, seed=5)
+    t1 = time.perf_counter()
+    losses = learned.train(net, train, pic.pic_node_map(), sc, steps=args.learn_steps, lr=2e-3, seed=2)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"learned start: {len(train)} snapshots in {t1 - t0:.1f}s, {args.learn_steps} training steps "
+        f"in {t2 - t1:.1f}s, loss {np.mean(losses[:5]):.3e} -> {np.mean(losses[-10:]):.3e}")
+    u1 = UNet(1, H, W, params=net.params)
+    net.close()
+    del train
+    u1.pic_unet_snapshot(0, evals[0][0], None, pic.pic_node_map(), sc)
+    u1.pic_unet_forward()
+    u1.pic_unet_set_timing(True)
+    for _ in range(20):
+        u1.pic_unet_forward()
+    fwd_ms, _ = u1.pic_unet_forward_timing()
+    u1.pic_unet_set_timing(False)
+    few = [{f: p[f][:4096] for f in p} for p in parts]
+    cg = Pic(w, few, solver=1, max_iter=50000)
+    rows = learned.evaluate(cg, u1, evals, sc, torch)
+    cg.close()
+    u1.close()
+    rows = rows[1:]
+    for r in rows:
+        log(f"  cold {r['cold']['iterations']} it {r['cold']['ms']:.1f} ms | prev {r['prev']['iterations']} it "
+            f"{r['prev']['ms']:.1f} ms | learned {r['learned']['iterations']} it {r['learned']['ms']:.1f} ms "
+            f"(relres0 {r['learned']['relres0']:.3g}) | max diff {r['max_diff']:.2e}")
+
+    def mean(kind, key):
+        return float(np.mean([r[kind][key] for r in rows]))
+
+    fl = flops_per_inference(H, W)
+    tf = fl / (fwd_ms * 1e-3) / 1e12
+    return {
+        "solver": f"plain masked CG (float64 refinement of float32 CG), rtol {w.rtol:g}",
+        "snapshots_evaluated": len(rows),
+        "cold": {"iterations": mean("cold", "iterations"), "ms": mean("cold", "ms")},
+        "previous_step": {"iterations": mean("prev", "iterations"), "ms": mean("prev", "ms")},
+        "learned": {"iterations": mean("learned", "iterations"), "ms": mean("learned", "ms"),
+                    "relres0": float(np.median([r["learned"]["relres0"] for r in rows]))},
+        "iterations_cold_over_learned": mean("cold", "iterations") / mean("learned", "iterations"),
+        "ms_cold_over_learned": mean("cold", "ms") / mean("learned", "ms"),
+        "all_converged": all(r[k]["converged"] for r in rows for k in ("cold", "prev", "learned")),
+        "max_solution_diff_over_scale": max(r["max_diff"] / r["scale"] for r in rows),
+        "training": {"snapshots": args.learn_snapshots, "steps": args.learn_steps,
+                     "batch": args.learn_batch, "loss_first": float(np.mean(losses[:5])),
+                     "loss_last": float(np.mean(losses[-10:])), "seconds": t2 - t1},
+        "unet": {"pixels": [H, W], "forward_ms": fwd_ms, "gflop_per_inference": fl / 1e9,
+                 "roofline": {"bound": "mfma", "achieved": tf, "peak": BF16_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": tf / BF16_PEAK_TFLOPS}},
+    }
 
 
 def run_sweep(args):
@@ -155,6 +248,11 @@ def main():
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--halo", type=int, default=4)
     ap.add_argument("--warm", type=int, default=1, help="0 previous phi, 1 extrapolated")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
+    ap.add_argument("--learn-snapshots", type=int, default=128)
+    ap.add_argument("--learn-steps", type=int, default=2000)
+    ap.add_argument("--learn-batch", type=int, default=4)
+    ap.add_argument("--learn-evals", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -213,7 +311,7 @@ def main():
     achieved = per_launch * BYTES_PER_PARTICLE_STEP / (push_ms * 1e-3) / 1e9
     traffic = measured_traffic(w.name, per_launch)
     out = {
-        "metric": "particle-steps/s (push+deposit+solve)",
+        "metric": "particle-steps/s (push+deposit+solve); Poisson ms/step, plain vs learned start",
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -238,6 +336,8 @@ def main():
                      "kernel": "k_push<true,2,0>", "avg_launch_ms": push_ms, "launches": launches,
                      "bytes_per_launch": per_launch * BYTES_PER_PARTICLE_STEP},
     }
+    if not args.no_learned and w.name.startswith("trench"):
+        out["learned_start"] = learned_start(w, pic, parts, args)
     pic.close()
     del pic
     torch.cuda.empty_cache()

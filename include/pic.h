@@ -231,6 +231,15 @@ pic_status pic_batch_diagnostics(pic_ctx *ctx, int32_t i, pic_diag *out);
 pic_status pic_batch_particles(pic_ctx *ctx, int32_t i, int32_t species, int32_t *set, int64_t *slots);
 pic_status pic_batch_solve_info(pic_ctx *ctx, int32_t i, pic_solve_info *out);
 
+/* Node map of instance i (NX*NY bytes: 0 free node, k > 0 Dirichlet node
+ * held by conductor k; the boundary conditions of Sec. II).  node_cond
+ * receives the device copy, owned by the context and valid until
+ * pic_destroy; host_copy (caller memory of NX*NY bytes) receives a host
+ * copy; NX and NY receive the node counts.  Every output may be NULL.  No
+ * device work. */
+pic_status pic_node_map(pic_ctx *ctx, int32_t i, const uint8_t **node_cond, uint8_t *host_copy,
+                        int32_t *NX, int32_t *NY);
+
 void pic_destroy(pic_ctx *ctx);
 const char *pic_last_error(const pic_ctx *ctx);
 const char *pic_version(void);

@@ -1,0 +1,135 @@
+/*
+ * pic_unet.h - C ABI of the learned warm start for the field solve of
+ * eq. (5) (arXiv:1610.03918, Sec. II).  The paper names the field solver as
+ * the part of the cycle whose speed matters most (Sec. IV); this library
+ * starts the Poisson solve from the prediction of a small convolutional
+ * network and always finishes it with the ordinary solver to the requested
+ * tolerance, so the result does not depend on the prediction beyond that
+ * tolerance.
+ *
+ * Network: a 4-level U-Net.  Level l (0..3) works on (H >> l) x (W >> l)
+ * pixels with 16 << l channels: two 3x3 convolutions with zero padding and
+ * ReLU per level, 2x2 average pooling between encoder levels, copying
+ * (nearest-neighbour) upsampling, concatenation [upsampled, skip] before the
+ * first decoder convolution of a level, and a 1x1 head (16 -> 1, float32).
+ * Weights and activations are bfloat16, products accumulate in float32.
+ *
+ * Tensors are NHWC: pixel (b, h, w) at ((b*H + h)*W + w).  Pixel (h, w)
+ * stands for node (h, w) of the Poisson grid (NX x NY nodes, row-major in x;
+ * H <= NX and W <= NY, both multiples of 8).  Input channels: 0 the source
+ * term on free nodes times s_rho, 1 a free-node indicator, 2 the Dirichlet
+ * value times s_v on conductor nodes.  Output: phi / s_phi.
+ *
+ * Parameters: one float32 array of pic_unet_param_count() values.  For each
+ * 3x3 convolution k = 0..13 in network order (encoder levels 0..3, then the
+ * decoder levels 2, 1, 0) the weight [Cout][3][3][Cin] (tap row along H)
+ * followed by the bias [Cout]; then the head weight [16] and bias [1].
+ * pic_unet_layer reports the shapes and offsets.
+ *
+ * Ownership: the caller allocates parameters, gradients, the two Adam
+ * moment arrays (each param_count float32, device) and one workspace of
+ * pic_unet_workspace_size bytes, and keeps them alive until
+ * pic_unet_destroy.  The library never allocates device memory.  Calls are
+ * enqueued on the stream given at creation and return without waiting unless
+ * stated.  Errors: a pic_status; pic_unet_last_error explains.  Not thread
+ * safe.
+ */
+#ifndef PIC_UNET_H
+#define PIC_UNET_H
+
+#include "pic.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_unet pic_unet;
+
+#define PIC_UNET_NCONV 14
+
+typedef struct {
+    int32_t cin, cout;           /* channels (the head: 16, 1) */
+    int32_t level;               /* resolution level 0..3 */
+    int32_t pad;
+    int64_t w_offset, b_offset;  /* offsets (float32 values) into the parameter array */
+} pic_unet_layer;
+
+typedef struct {
+    uint16_t *input;             /* bfloat16 [B][H][W][3] */
+    float *output;               /* [B][H][W] (phi / s_phi) */
+    float *target;               /* [B][H][W] training target (phi / s_phi) */
+    float *mask;                 /* [B][H][W] loss weight (1 on free nodes) */
+    float *grad_output;          /* [B][H][W] d loss / d output */
+} pic_unet_io;
+
+/* Number of float32 parameters. */
+int64_t pic_unet_param_count(void);
+
+/* Shape and offsets of convolution k (0..13) or of the head (k = 14). */
+pic_status pic_unet_layer_info(int32_t k, pic_unet_layer *out);
+
+/* Workspace bytes for batch B of H x W images (H, W multiples of 8). */
+pic_status pic_unet_workspace_size(int32_t batch, int32_t H, int32_t W, size_t *bytes);
+
+/* Creates a network over caller-owned device arrays (see Ownership).  The
+ * parameters are read at the first forward pass (and after
+ * pic_unet_params_changed); the Adam moments must start at zero. */
+pic_status pic_unet_create(int32_t batch, int32_t H, int32_t W, float *params, float *grads,
+                           float *adam_m, float *adam_v, void *workspace, size_t workspace_bytes,
+                           void *stream, pic_unet **out);
+
+/* Device pointers of the input/output tensors inside the workspace. */
+pic_status pic_unet_io_buffers(pic_unet *u, pic_unet_io *io);
+
+/* The caller rewrote the parameter array: re-derive the bfloat16 copies. */
+pic_status pic_unet_params_changed(pic_unet *u);
+
+/* input -> output for the whole batch (keeps the activations for backward). */
+pic_status pic_unet_forward(pic_unet *u);
+
+/* Masked mean-square loss sum(mask (output - target)^2) / sum(mask) over
+ * the batch, and grad_output.  Waits; *loss (may be NULL) receives it. */
+pic_status pic_unet_loss(pic_unet *u, double *loss);
+
+/* grad_output -> gradients of every parameter (overwrites the gradient
+ * array).  Needs the activations of the last pic_unet_forward. */
+pic_status pic_unet_backward(pic_unet *u);
+
+/* One Adam step (bias-corrected moments) on the parameters from the
+ * gradients; counts its own steps. */
+pic_status pic_unet_adam(pic_unet *u, float lr, float beta1, float beta2, float eps);
+
+/* Writes batch slot `slot` of the input from a Poisson problem: b (device
+ * NX*NY float64, the assembled right-hand side whose Dirichlet nodes hold
+ * their potentials) and node_cond (device NX*NY, see pic_node_map).  If phi
+ * (device NX*NY float64) is not NULL also the target (phi / s_phi) and the
+ * mask (free nodes) of that slot. */
+pic_status pic_unet_snapshot(pic_unet *u, int32_t slot, const double *b, const double *phi,
+                             const uint8_t *node_cond, int32_t NX, int32_t NY, float s_rho,
+                             float s_v, float s_phi);
+
+/* Writes guess (device NX*NY float64): output of `slot` times s_phi on free
+ * nodes inside the H x W window, 0 on free nodes outside it, b on Dirichlet
+ * nodes - a start for pic_solve(ctx, 2, guess, ...). */
+pic_status pic_unet_guess(pic_unet *u, int32_t slot, const double *b, const uint8_t *node_cond,
+                          int32_t NX, int32_t NY, float s_phi, double *guess);
+
+/* Learned start of instance 0 of ctx (batch slot 0 of u): snapshot of the
+ * current right-hand side b (the caller's pic_buffers.b), forward pass,
+ * guess into the caller's device scratch guess (NX*NY float64), then
+ * pic_solve(ctx, 2, guess, info).  Waits (as pic_solve). */
+pic_status pic_solve_learned(pic_ctx *ctx, pic_unet *u, const double *b, float s_rho, float s_v,
+                             float s_phi, double *guess, pic_solve_info *info);
+
+/* HIP-event timing of pic_unet_forward on the library stream (default off);
+ * average ms per forward pass since the last read, then reset. */
+pic_status pic_unet_set_timing(pic_unet *u, int32_t on);
+pic_status pic_unet_forward_timing(pic_unet *u, double *avg_ms, int32_t *passes);
+
+void pic_unet_destroy(pic_unet *u);
+const char *pic_unet_last_error(const pic_unet *u);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_UNET_H */

@@ -1,0 +1,202 @@
+"""CPU oracle of the learned warm start's network (test infrastructure only).
+
+A 4-level U-Net: at each level two 3x3 convolutions with ReLU (16, 32, 64,
+128 channels), 2x2 average pooling down, nearest-neighbour upsampling, skip
+concatenation (upsampled channels first, then the skip), and a 1x1 head to
+one output channel.  Tensors are NHWC float64; convolutions are
+cross-correlations with zero padding.  ``quantize=True`` rounds inputs,
+weights and every stored activation to bfloat16 (round to nearest even), the
+storage precision of the device network, while all arithmetic stays float64.
+
+Parameter order (one flat list):  for every 3x3 convolution in network
+order, its weight [Cout, 3, 3, Cin] then bias [Cout]; then the head weight
+[16] and head bias [1].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CH = (16, 32, 64, 128)
+IN_CH = 3
+
+
+def conv_shapes(in_ch: int = IN_CH):
+    """(Cin, Cout) of every 3x3 convolution in network order."""
+    s = []
+    c = in_ch
+    for k, ch in enumerate(CH):          # encoder + bottleneck
+        s.append((c, ch))
+        s.append((ch, ch))
+        c = ch
+    for k in range(len(CH) - 2, -1, -1):  # decoder
+        s.append((c + CH[k], CH[k]))
+        s.append((CH[k], CH[k]))
+        c = CH[k]
+    return s
+
+
+def bf16(x):
+    """Round float64 values to bfloat16 (nearest even) and back."""
+    a = np.asarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def init_params(seed: int = 100, in_ch: int = IN_CH):
+    """He-normal weights, zero biases (float32 values)."""
+    rng = np.random.Generator(np.random.Philox(key=np.array([seed, 5], np.uint64)))
+    ps = []
+    for cin, cout in conv_shapes(in_ch):
+        std = np.sqrt(2.0 / (9 * cin))
+        ps.append((rng.standard_normal((cout, 3, 3, cin)) * std).astype(np.float32))
+        ps.append(np.zeros(cout, np.float32))
+    ps.append((rng.standard_normal(CH[0]) * np.sqrt(1.0 / CH[0])).astype(np.float32))
+    ps.append(np.zeros(1, np.float32))
+    return ps
+
+
+def conv3x3(x, w, b):
+    B, H, W, C = x.shape
+    xp = np.zeros((B, H + 2, W + 2, C))
+    xp[:, 1:-1, 1:-1] = x
+    y = np.zeros((B, H, W, w.shape[0]))
+    for dy in range(3):
+        for dx in range(3):
+            y += np.tensordot(xp[:, dy:dy + H, dx:dx + W], w[:, dy, dx, :], axes=([3], [1]))
+    return y + b
+
+
+def conv3x3_grads(x, w, gy):
+    """Gradients of conv3x3 w.r.t. input, weight and bias."""
+    B, H, W, C = x.shape
+    xp = np.zeros((B, H + 2, W + 2, C))
+    xp[:, 1:-1, 1:-1] = x
+    gw = np.zeros_like(w)
+    gxp = np.zeros_like(xp)
+    for dy in range(3):
+        for dx in range(3):
+            gw[:, dy, dx, :] = np.tensordot(gy, xp[:, dy:dy + H, dx:dx + W], axes=([0, 1, 2], [0, 1, 2]))
+            gxp[:, dy:dy + H, dx:dx + W] += np.tensordot(gy, w[:, dy, dx, :], axes=([3], [0]))
+    return gxp[:, 1:-1, 1:-1], gw, gy.sum(axis=(0, 1, 2))
+
+
+def pool(x):
+    B, H, W, C = x.shape
+    return x.reshape(B, H // 2, 2, W // 2, 2, C).mean(axis=(2, 4))
+
+
+def pool_grad(gy):
+    return np.repeat(np.repeat(gy, 2, axis=1), 2, axis=2) * 0.25
+
+
+def up(x):
+    return np.repeat(np.repeat(x, 2, axis=1), 2, axis=2)
+
+
+def up_grad(gy):
+    B, H, W, C = gy.shape
+    return gy.reshape(B, H // 2, 2, W // 2, 2, C).sum(axis=(2, 4))
+
+
+def forward(params, x, quantize=False):
+    """Returns (output [B,H,W], cache for backward)."""
+    q = bf16 if quantize else (lambda a: np.asarray(a, np.float64))
+    P = [q(p) if i < len(params) - 2 else np.asarray(p, np.float64) for i, p in enumerate(params)]
+    cache = {"P": P, "acts": []}
+    h = q(x)
+    k = 0
+    skips = []
+    # encoder
+    for lev in range(len(CH)):
+        for _ in range(2):
+            inp = h
+            h = q(np.maximum(conv3x3(inp, P[2 * k], P[2 * k + 1]), 0.0))
+            cache["acts"].append((inp, h))
+            k += 1
+        if lev < len(CH) - 1:
+            skips.append(h)
+            h = q(pool(h))
+    # decoder
+    for lev in range(len(CH) - 2, -1, -1):
+        h = np.concatenate([up(h), skips[lev]], axis=3)
+        for _ in range(2):
+            inp = h
+            h = q(np.maximum(conv3x3(inp, P[2 * k], P[2 * k + 1]), 0.0))
+            cache["acts"].append((inp, h))
+            k += 1
+    out = h @ P[-2] + P[-1][0]
+    cache["last"] = h
+    return out, cache
+
+
+def backward(cache, gout):
+    """Gradients (same order as the parameters) and the input gradient."""
+    P = cache["P"]
+    grads = [None] * len(P)
+    h = cache["last"]
+    grads[-2] = np.tensordot(gout, h, axes=([0, 1, 2], [0, 1, 2]))
+    grads[-1] = np.array([gout.sum()])
+    g = gout[..., None] * P[-2]
+    nconv = len(cache["acts"])
+    ne = 2 * len(CH)                     # encoder + bottleneck convolutions
+    skip_grads = [None] * (len(CH) - 1)
+    k = nconv - 1
+    for lev in range(0, len(CH) - 1):    # decoder in reverse: finest level first
+        for _ in range(2):
+            inp, out = cache["acts"][k]
+            gy = g * (out > 0)
+            gx, grads[2 * k], grads[2 * k + 1] = conv3x3_grads(inp, P[2 * k], gy)
+            g = gx
+            k -= 1
+        cu = g.shape[3] - CH[lev]
+        skip_grads[lev] = g[..., cu:]
+        g = up_grad(g[..., :cu])
+    for lev in range(len(CH) - 1, -1, -1):
+        if lev < len(CH) - 1:
+            g = pool_grad(g) + skip_grads[lev]
+        for _ in range(2):
+            inp, out = cache["acts"][k]
+            gy = g * (out > 0)
+            gx, grads[2 * k], grads[2 * k + 1] = conv3x3_grads(inp, P[2 * k], gy)
+            g = gx
+            k -= 1
+    assert k == -1 and ne == 2 * len(CH)
+    return grads, g
+
+
+def mse(pred, target, weight):
+    """Loss = sum(weight (pred - target)^2) / sum(weight) and its gradient."""
+    d = pred - target
+    ws = weight.sum()
+    return float((weight * d * d).sum() / ws), 2.0 * weight * d / ws
+
+
+def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba, bias-corrected moments); t counts from 1."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def features(b, node_cond, H, W, s_rho, s_v):
+    """Network input [H, W, 3] of a Poisson problem: source on free nodes
+    times s_rho, free-node indicator, Dirichlet value times s_v (bfloat16)."""
+    bb = b[:H, :W]
+    free = node_cond[:H, :W] == 0
+    x = np.zeros((H, W, 3))
+    x[..., 0] = np.where(free, bf16(bb * s_rho), 0.0)
+    x[..., 1] = free
+    x[..., 2] = np.where(free, 0.0, bf16(bb * s_v))
+    return x
+
+
+def guess(out, b, node_cond, s_phi):
+    """Start potential: out * s_phi on free nodes of the network window, 0 on
+    other free nodes, b (the Dirichlet value) on conductor nodes."""
+    H, W = out.shape
+    g = np.zeros(b.shape)
+    g[:H, :W] = out * s_phi
+    return np.where(node_cond != 0, b, g)

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libpic.so")
-SOURCES = ["pic_kernels.hip", "pic_runtime.cpp"]
+SOURCES = ["pic_kernels.hip", "pic_runtime.cpp", "unet_kernels.hip", "unet_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part
     }
     __shared__ double sh[2][4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE) ? 2 : 1;
+    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE || op == OP_RR64_START) ? 2 : 1;
     const int b0 = t.boff[blockIdx.x], b1 = t.boff[blockIdx.x + 1];
     for (int q = 0; q < nq; q++) {
         double s = 0.0;
@@ -123,9 +123,12 @@ __global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part
     case OP_BB_PER: S[S_BB] = tt[0]; break;
     case OP_SUM: S[S_SUM] = tt[0]; break;
     case OP_RR64_START:
+        // ||b||^2 of the right-hand side being solved (b may have been written
+        // by the caller since the last assembly)
+        S[S_BB] = tt[1];
         S[S_RR64] = tt[0];
         S[S_RELRES0] = tt[0];
-        F[F_CONV] = (tt[0] <= tol2 * bb) ? 1 : 0;
+        F[F_CONV] = (tt[0] <= tol2 * (tt[1] > 0.0 ? tt[1] : 1.0)) ? 1 : 0;
         F[F_ITER_TOT] = 0;
         F[F_PASSES] = 0;
         F[F_DONE] = 0;
@@ -424,7 +427,8 @@ void launch_extrapolate(const Inst *I, const Tab &t, int have_prev, hipStream_t 
 
 // ---------------------------------------------------------------------------
 // float64 outer residual: r = b - A phi on the unknowns, ||r||^2 (float64),
-// r rounded to float32 for the inner preconditioned CG.
+// r rounded to float32 for the inner preconditioned CG; at the start of a
+// solve also ||b||^2 over the unknowns (the reference of the tolerance).
 // A = 4 - (sum of free neighbours); fixed neighbours sit in b already.
 // ---------------------------------------------------------------------------
 
@@ -435,11 +439,12 @@ __global__ void k_resid64(const Inst *insts, Tab t, int after_pass, Part pt)
     NODE_IDX(I.g.NX, I.g.NY)
     const uint8_t *fix = I.lev[0].fix;
     const double *phi = I.phi;
-    double rr = 0.0;
+    double rr = 0.0, bsq = 0.0;
     if (inb) {
         if (fix[n]) {
             I.lev[0].g[n] = 0.0f;
         } else {
+            bsq = I.b[n] * I.b[n];
             const int im = wrap_lo(i - 1, NX), ip = wrap_hi(i + 1, NX);
             const int jm = wrap_lo(j - 1, NY), jp = wrap_hi(j + 1, NY);
             const long long a = (long long)im * NY + j, c = (long long)ip * NY + j;
@@ -454,8 +459,8 @@ __global__ void k_resid64(const Inst *insts, Tab t, int after_pass, Part pt)
             rr = r * r;
         }
     }
-    double v[1] = {rr};
-    block_partials<1>(v, pt);
+    double v[2] = {rr, bsq};
+    block_partials<2>(v, pt);
 }
 
 void launch_resid64(const Inst *I, const Tab &t, int after_pass, Part pt, hipStream_t s)

@@ -213,6 +213,7 @@ struct Carve {
 };
 
 constexpr int kVWindow = 512;   // steps of conductor potentials held on the device
+constexpr int kContinueChunk = 64; // inner iterations per graph between stop tests (plain CG)
 
 } // namespace
 
@@ -244,6 +245,7 @@ struct pic_ctx {
     // graphs
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> outer_graphs;
+    std::map<int, hipGraphExec_t> chunk_graphs;
     std::map<long long, hipGraphExec_t> step_graphs;
     bool use_graphs = true;
     // timing
@@ -478,20 +480,40 @@ void enqueue_vcycle_rest(pic_ctx *c, hipStream_t s)
     }
 }
 
+// Start of a refinement pass: inner CG from e = 0 (first residual, z, r.z).
+void enqueue_pass_begin(pic_ctx *c, hipStream_t s)
+{
+    launch_init_red0(c->d_inst, c->t_l0, part_of(c), s);
+    enqueue_vcycle_rest(c, s);
+}
+
+// K inner iterations; `first` when they open the pass.  Continuation chunks
+// must follow an even number of iterations (the search direction ping-pongs
+// between two buffers by iteration parity).
+void enqueue_iters(pic_ctx *c, int K, bool first, hipStream_t s)
+{
+    Part pt = part_of(c);
+    for (int k = 0; k < K; k++) {
+        launch_pupdate_Ap(c->d_inst, c->t_l0, k & 1, (first && k == 0) ? 1 : 0, pt, s);
+        launch_update_red0(c->d_inst, c->t_l0, (k + 1) & 1, pt, s);
+        enqueue_vcycle_rest(c, s);
+    }
+}
+
+// End of a pass: phi += e, float64 residual and convergence test.
+void enqueue_pass_end(pic_ctx *c, hipStream_t s)
+{
+    launch_phi_update(c->d_inst, c->t_l0, s);
+    launch_resid64(c->d_inst, c->t_l0, 1, part_of(c), s);
+}
+
 // One refinement pass: inner preconditioned CG from e = 0 with K iterations
 // (later ones return at once after the stop test), phi += e, float64 residual.
 void enqueue_pass(pic_ctx *c, int K, hipStream_t s)
 {
-    Part pt = part_of(c);
-    launch_init_red0(c->d_inst, c->t_l0, pt, s);
-    enqueue_vcycle_rest(c, s);
-    for (int k = 0; k < K; k++) {
-        launch_pupdate_Ap(c->d_inst, c->t_l0, k & 1, k == 0 ? 1 : 0, pt, s);
-        launch_update_red0(c->d_inst, c->t_l0, (k + 1) & 1, pt, s);
-        enqueue_vcycle_rest(c, s);
-    }
-    launch_phi_update(c->d_inst, c->t_l0, s);
-    launch_resid64(c->d_inst, c->t_l0, 1, pt, s);
+    enqueue_pass_begin(c, s);
+    enqueue_iters(c, K, true, s);
+    enqueue_pass_end(c, s);
 }
 
 int round_chunk(int k)
@@ -541,6 +563,26 @@ pic_status run_pass(pic_ctx *c, int K)
     return PIC_OK;
 }
 
+// Graph of `begin + K first iterations` (first) or of K continuation
+// iterations, cached by (K, first).
+pic_status launch_chunk(pic_ctx *c, int K, bool first)
+{
+    const int key = 2 * K + (first ? 1 : 0);
+    auto it = c->chunk_graphs.find(key);
+    if (it == c->chunk_graphs.end()) {
+        pic_status st = capture_begin(c);
+        if (st != PIC_OK) return st;
+        if (first) enqueue_pass_begin(c, c->cap_stream);
+        enqueue_iters(c, K, first, c->cap_stream);
+        hipGraphExec_t ex;
+        st = capture_end(c, &ex);
+        if (st != PIC_OK) return st;
+        it = c->chunk_graphs.emplace(key, ex).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    return PIC_OK;
+}
+
 pic_status read_flags(pic_ctx *c, std::vector<double> &S, std::vector<int> &F)
 {
     S.resize((size_t)c->n * S_NSCAL);
@@ -584,7 +626,11 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess)
     pic_status st = read_flags(c, S, F);
     if (st != PIC_OK) return st;
     int max_iter = 0;
-    for (auto &h : c->in) max_iter = std::max(max_iter, (int)h.cfg.max_iter);
+    bool plain_cg = false;
+    for (auto &h : c->in) {
+        max_iter = std::max(max_iter, (int)h.cfg.max_iter);
+        if (!h.dev.mg) plain_cg = true;
+    }
     for (int pass = 0; pass < 64; pass++) {
         bool all = true;
         bool finite = true;
@@ -597,7 +643,30 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess)
         }
         if (all || !finite || most >= max_iter) break;
         int K = round_chunk(std::max(1, std::min(c->inner_chunk, max_iter - most)));
-        st = run_pass(c, K);
+        if (plain_cg) {
+            // Unpreconditioned CG needs long uninterrupted inner runs: continue
+            // the pass's CG in graph chunks until its stop test, then update.
+            K = std::min(K, 128);
+            K += K & 1;
+            st = launch_chunk(c, K, true);
+            for (int guard = 0; st == PIC_OK && guard < (1 << 20); guard++) {
+                if ((st = read_flags(c, S, F)) != PIC_OK) break;
+                bool open = false;
+                int tot = 0;
+                for (int k = 0; k < c->n; k++) {
+                    const int *f = &F[(size_t)k * F_NFLAG];
+                    if (!f[F_SKIP] && !f[F_DONE]) open = true;
+                    tot = std::max(tot, f[F_ITER_TOT]);
+                }
+                if (!open || tot >= max_iter) break;
+                st = launch_chunk(c, kContinueChunk, false);
+            }
+            if (st != PIC_OK) return st;
+            enqueue_pass_end(c, c->stream);
+            HIPCHK(c, hipGetLastError());
+        } else {
+            st = run_pass(c, K);
+        }
         if (st != PIC_OK) return st;
         st = read_flags(c, S, F);
         if (st != PIC_OK) return st;
@@ -989,6 +1058,19 @@ const char *pic_version(void) { return "pic-gfx950 1.1"; }
 
 const char *pic_last_error(const pic_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+pic_status pic_node_map(pic_ctx *ctx, int32_t i, const uint8_t **node_cond, uint8_t *host_copy,
+                        int32_t *NX, int32_t *NY)
+{
+    if (!ctx) return PIC_ERR_ARG;
+    if (i < 0 || i >= ctx->n) return fail(ctx, PIC_ERR_ARG, "pic_node_map: bad instance");
+    const InstHost &h = ctx->in[i];
+    if (node_cond) *node_cond = h.d_node_cond;
+    if (host_copy) std::memcpy(host_copy, h.node_cond.data(), h.node_cond.size());
+    if (NX) *NX = h.g.NX;
+    if (NY) *NY = h.g.NY;
+    return PIC_OK;
+}
+
 pic_status pic_batch_workspace_size(int32_t n, const pic_config *cfgs, const int64_t *capacity, size_t *bytes)
 {
     if (n < 1 || n > kMaxInst || !cfgs || !capacity || !bytes) return PIC_ERR_ARG;
@@ -1229,6 +1311,7 @@ void pic_destroy(pic_ctx *c)
     if (!c) return;
     if (c->d_inst) (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->outer_graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->chunk_graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto e : c->ev0) if (e) (void)hipEventDestroy(e);

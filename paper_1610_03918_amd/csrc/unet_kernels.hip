@@ -1,0 +1,636 @@
+// gfx950 kernels of the learned warm start: a 4-level U-Net (16/32/64/128
+// channels, 3x3 convolutions, bfloat16 weights and activations, float32
+// accumulation on the matrix cores) with its backward pass, loss, Adam step,
+// and the maps between the Poisson problem and the network's tensors.
+//
+// Convolutions run as implicit GEMMs on v_mfma_f32_16x16x32_bf16: the
+// weights are the M operand (output channels), the pixels the N operand and
+// the K dimension walks (tap, input channel).  A block stages a
+// (rows+2) x 18 pixel patch of 32 input channels and the matching weights in
+// LDS, then every wave multiplies 16 x 16 tiles.  The input gradient is the
+// same kernel with the taps flipped and the weights transposed; the weight
+// gradient contracts over pixels in a split-K kernel whose partial sums are
+// added in a fixed order (deterministic).
+#include "unet_internal.h"
+
+namespace unet {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int KS = 40;           // LDS row length (bf16) of one pixel's 32-channel chunk, padded
+constexpr int PC = 18;           // patch columns: 16 output columns + 2 halo
+
+// float32 -> bfloat16, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
+    return __builtin_bit_cast(bf16x8, *(const uint4 *)p);
+}
+__device__ __forceinline__ bf16x8 pack8(const uint32_t *x) {
+    uint4 v = make_uint4(x[0] | (x[1] << 16), x[2] | (x[3] << 16), x[4] | (x[5] << 16),
+                         x[6] | (x[7] << 16));
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// Stage the input patch rows h0-1 .. h0+PR-2, columns w0-1 .. w0+16, channels
+// c0 .. c0+31 of the concatenation [upsampled(up), src] into LDS as
+// [row][col][KS] (zeros outside the image and beyond the channel count).
+template <int PR>
+__device__ __forceinline__ void stage_patch(uint16_t *sp, const uint16_t *src, int Cs,
+                                            const uint16_t *up, int Cu, int b, int H, int W,
+                                            int h0, int w0, int c0) {
+    const int Cin = Cu + Cs;
+    const int Hh = H >> 1, Wh = W >> 1;
+    for (int e = threadIdx.x; e < PR * PC * 4; e += blockDim.x) {
+        const int q = e & 3, pix = e >> 2;
+        const int r = pix / PC, s = pix - r * PC;
+        const int h = h0 - 1 + r, w = w0 - 1 + s;
+        const int c = c0 + 8 * q;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (h >= 0 && h < H && w >= 0 && w < W && c < Cin) {
+            const size_t pu = ((size_t)b * Hh + (h >> 1)) * Wh + (w >> 1);
+            const size_t ps = ((size_t)b * H + h) * W + w;
+            if (c + 8 <= Cu) {
+                v = *(const uint4 *)(up + pu * Cu + c);
+            } else if (c >= Cu && c + 8 <= Cin && (Cs & 7) == 0) {
+                v = *(const uint4 *)(src + ps * Cs + (c - Cu));
+            } else {
+                uint32_t x[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int cc = c + k;
+                    x[k] = cc < Cu ? up[pu * Cu + cc] : (cc < Cin ? src[ps * Cs + (cc - Cu)] : 0u);
+                }
+                v = make_uint4(x[0] | (x[1] << 16), x[2] | (x[3] << 16), x[4] | (x[5] << 16),
+                               x[6] | (x[7] << 16));
+            }
+        }
+        *(uint4 *)(sp + pix * KS + 8 * q) = v;
+    }
+}
+
+// ---- convolution (forward: + bias, ReLU, bf16 out; gradient: f32 out) ----
+// Block: 4 waves; output tile 4*NR rows x 16 columns x 16*NCO channels.
+// Wave w owns rows w*NR .. w*NR+NR-1.
+template <int NCO, int NR, bool F32OUT>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+    constexpr int TX = 4 * NR, PR = TX + 2, CT = 16 * NCO;
+    __shared__ __align__(16) uint16_t sp[PR * PC * KS];
+    __shared__ __align__(16) uint16_t sw[CT * 9 * KS];
+    const int tilesW = (a.W + 15) >> 4, tilesH = (a.H + TX - 1) / TX;
+    int bid = blockIdx.x;
+    const int tw = bid % tilesW;
+    bid /= tilesW;
+    const int th = bid % tilesH;
+    const int b = bid / tilesH;
+    const int co0 = blockIdx.y * CT;
+    const int h0 = th * TX, w0 = tw * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+
+    f4 acc[NCO][NR];
+#pragma unroll
+    for (int j = 0; j < NCO; ++j)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[j][r] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int c0 = 0; c0 < a.Cin_pad; c0 += kKChunk) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < CT * 9 * 4; e += 256) {
+            const int q = e & 3, row = e >> 2;          // row = local channel * 9 + tap
+            const int co = co0 + row / 9, t = row - (row / 9) * 9;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (co < a.Cout) v = *(const uint4 *)(a.wt + ((size_t)co * 9 + t) * a.Cin_pad + c0 + 8 * q);
+            *(uint4 *)(sw + row * KS + 8 * q) = v;
+        }
+        stage_patch<PR>(sp, a.src, a.Cs, a.up, a.Cu, b, a.H, a.W, h0, w0, c0);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dh = t / 3, dw = t - 3 * (t / 3);
+            bf16x8 A[NCO], Bv[NR];
+#pragma unroll
+            for (int j = 0; j < NCO; ++j) A[j] = ld8(sw + ((16 * j + n) * 9 + t) * KS + 8 * g);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) Bv[r] = ld8(sp + ((wave * NR + r + dh) * PC + n + dw) * KS + 8 * g);
+#pragma unroll
+            for (int j = 0; j < NCO; ++j)
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    acc[j][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[j], Bv[r], acc[j][r], 0, 0, 0);
+        }
+    }
+    // lane holds output channels co0 + 16j + 4g + (0..3) of pixel column n
+#pragma unroll
+    for (int j = 0; j < NCO; ++j) {
+        const int co = co0 + 16 * j + 4 * g;
+        if (co >= a.Cout) continue;
+        float bb[4] = {0.f, 0.f, 0.f, 0.f};
+        if (!F32OUT) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bb[i] = bf2f(f2bf(a.bias[co + i]));
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int h = h0 + wave * NR + r, w = w0 + n;
+            if (h >= a.H || w >= a.W) continue;
+            const size_t o = (((size_t)b * a.H + h) * a.W + w) * a.Cout + co;
+            if (F32OUT) {
+                *(f4 *)((float *)a.out + o) = acc[j][r];
+            } else {
+                uint32_t y[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) y[i] = f2bf(fmaxf(acc[j][r][i] + bb[i], 0.f));
+                *(uint2 *)((uint16_t *)a.out + o) = make_uint2(y[0] | (y[1] << 16), y[2] | (y[3] << 16));
+            }
+        }
+    }
+}
+
+template <int NCO, int NR>
+static void conv_variant(const ConvArgs &a, bool f32out, hipStream_t s) {
+    constexpr int TX = 4 * NR;
+    const int tilesW = (a.W + 15) >> 4, tilesH = (a.H + TX - 1) / TX;
+    dim3 grid(a.B * tilesH * tilesW, (a.Cout + 16 * NCO - 1) / (16 * NCO));
+    if (f32out) hipLaunchKernelGGL((k_conv<NCO, NR, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_conv<NCO, NR, false>), grid, dim3(256), 0, s, a);
+}
+
+void launch_conv(const ConvArgs &a, bool f32out, hipStream_t s) {
+    if (a.Cout % 64 == 0) conv_variant<4, 2>(a, f32out, s);
+    else if (a.Cout % 48 == 0) conv_variant<3, 2>(a, f32out, s);
+    else if (a.Cout % 32 == 0) conv_variant<2, 2>(a, f32out, s);
+    else conv_variant<1, 4>(a, f32out, s);
+}
+
+// ---- weight gradient ------------------------------------------------------
+// gw[co][t][ci] = sum over pixels p of gy[p][co] * in(p + tap t)[ci]
+// Block (split, co tile, 32-channel chunk) walks pixel tiles of 16 x 16
+// (tile = split, split + nsplit, ...).  Wave w owns tile rows 4w .. 4w+3, two
+// K steps of 32 pixels (2 rows x 16 columns); lane group g takes row
+// 2*step + g/2, columns 8*(g%2) .. +7.  Blocks of chunk 0 also sum gy (bias).
+constexpr int kWTX = 16;
+
+template <int NCO>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+    constexpr int PR = kWTX + 2, CT = 16 * NCO, GS = CT + 8;
+    constexpr int SP = PR * PC * KS, SG = kWTX * 16 * GS;
+    constexpr int RED = CT * 9 * 32;
+    constexpr int STAGE_B = 2 * (SP + SG), RED_B = 4 * (RED + CT);
+    __shared__ __align__(16) unsigned char smem[STAGE_B > RED_B ? STAGE_B : RED_B];
+    uint16_t *sp = (uint16_t *)smem;
+    uint16_t *sg = sp + SP;
+    const int tilesW = (a.W + 15) >> 4, tilesH = (a.H + kWTX - 1) / kWTX;
+    const int ntiles = a.B * tilesH * tilesW;
+    const int split = blockIdx.x, co0 = blockIdx.y * CT, c0 = blockIdx.z * kKChunk;
+    const bool with_bias = blockIdx.z == 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, make_uint4(0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u));
+
+    f4 acc[NCO][9][2];
+    f4 bacc[NCO];
+#pragma unroll
+    for (int j = 0; j < NCO; ++j) {
+        bacc[j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[j][t][0] = acc[j][t][1] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    for (int tile = split; tile < ntiles; tile += a.nsplit) {
+        const int tw = tile % tilesW, rest = tile / tilesW;
+        const int th = rest % tilesH, b = rest / tilesH;
+        const int h0 = th * kWTX, w0 = tw * 16;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kWTX * 16 * (CT / 8); e += 256) {
+            const int q = e % (CT / 8), px = e / (CT / 8);
+            const int h = h0 + (px >> 4), w = w0 + (px & 15);
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (h < a.H && w < a.W)
+                v = *(const uint4 *)(a.gy + (((size_t)b * a.H + h) * a.W + w) * a.Cout + co0 + 8 * q);
+            *(uint4 *)(sg + px * GS + 8 * q) = v;
+        }
+        stage_patch<PR>(sp, a.src, a.Cs, a.up, a.Cu, b, a.H, a.W, h0, w0, c0);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int R = 4 * wave + 2 * ks + (g >> 1);
+            const int col0 = 8 * (g & 1);
+            bf16x8 A[NCO];
+#pragma unroll
+            for (int j = 0; j < NCO; ++j) {
+                uint32_t x[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[i] = sg[(R * 16 + col0 + i) * GS + 16 * j + n];
+                A[j] = pack8(x);
+            }
+#pragma unroll
+            for (int dh = 0; dh < 3; ++dh) {
+#pragma unroll
+                for (int cs = 0; cs < 2; ++cs) {
+                    uint32_t x[10];
+#pragma unroll
+                    for (int k = 0; k < 10; ++k) x[k] = sp[((R + dh) * PC + col0 + k) * KS + 16 * cs + n];
+#pragma unroll
+                    for (int dw = 0; dw < 3; ++dw) {
+                        const bf16x8 Bv = pack8(x + dw);
+#pragma unroll
+                        for (int j = 0; j < NCO; ++j)
+                            acc[j][3 * dh + dw][cs] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[j], Bv, acc[j][3 * dh + dw][cs], 0, 0, 0);
+                    }
+                }
+            }
+            if (with_bias) {
+#pragma unroll
+                for (int j = 0; j < NCO; ++j)
+                    bacc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[j], ones, bacc[j], 0, 0, 0);
+            }
+        }
+    }
+    // sum the four waves in a fixed order, then write this split's partial
+    __syncthreads();
+    float *red = (float *)smem;
+    float *bred = red + RED;
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int j = 0; j < NCO; ++j)
+#pragma unroll
+                for (int t = 0; t < 9; ++t)
+#pragma unroll
+                    for (int cs = 0; cs < 2; ++cs)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int idx = ((16 * j + 4 * g + i) * 9 + t) * 32 + 16 * cs + n;
+                            red[idx] = (w == 0 ? 0.f : red[idx]) + acc[j][t][cs][i];
+                        }
+            if (with_bias && n == 0) {
+#pragma unroll
+                for (int j = 0; j < NCO; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int idx = 16 * j + 4 * g + i;
+                        bred[idx] = (w == 0 ? 0.f : bred[idx]) + bacc[j][i];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < RED; e += 256) {
+        const int col = e / 288, rem = e - col * 288;
+        const int t = rem >> 5, ci = rem & 31;
+        a.part[(((size_t)split * a.Cout + co0 + col) * 9 + t) * a.Cin_pad + c0 + ci] = red[e];
+    }
+    if (with_bias)
+        for (int e = threadIdx.x; e < CT; e += 256) a.bpart[(size_t)split * a.Cout + co0 + e] = bred[e];
+}
+
+int wgrad_tiles(int B, int H, int W) {
+    return B * ((H + kWTX - 1) / kWTX) * ((W + 15) >> 4);
+}
+
+void launch_wgrad(const WgradArgs &a, int ci_chunks, hipStream_t s) {
+    if (a.Cout % 32 == 0) {
+        dim3 grid(a.nsplit, a.Cout / 32, ci_chunks);
+        hipLaunchKernelGGL(k_wgrad<2>, grid, dim3(256), 0, s, a);
+    } else {
+        dim3 grid(a.nsplit, a.Cout / 16, ci_chunks);
+        hipLaunchKernelGGL(k_wgrad<1>, grid, dim3(256), 0, s, a);
+    }
+}
+
+// Sum of the split partials: a block owns 64 consecutive outputs and splits
+// the partials over 4 lanes per output (k = lane, lane + 4, ...), then adds
+// the 4 lane sums in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *part, const float *bpart, int nsplit,
+                                                      int Cout, int Cin, int Cin_pad, float *gw, float *gb)
+{
+    __shared__ double sh[4][64];
+    const int o = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const long long idx = (long long)blockIdx.x * 64 + o;
+    const long long total = (long long)Cout * 9 * Cin;
+    double s = 0.0;
+    if (idx < total) {
+        const int ci = (int)(idx % Cin);
+        const long long row = idx / Cin;             // co * 9 + t
+        for (int k = q; k < nsplit; k += 4) s += part[((size_t)k * Cout * 9 + row) * Cin_pad + ci];
+    } else if (idx < total + Cout) {
+        const int co = (int)(idx - total);
+        for (int k = q; k < nsplit; k += 4) s += bpart[(size_t)k * Cout + co];
+    }
+    sh[q][o] = s;
+    __syncthreads();
+    if (q != 0) return;
+    s = ((sh[0][o] + sh[1][o]) + sh[2][o]) + sh[3][o];
+    if (idx < total) gw[idx] = (float)s;
+    else if (idx < total + Cout) gb[idx - total] = (float)s;
+}
+
+void launch_wgrad_reduce(const float *part, const float *bpart, int nsplit, int Cout, int Cin,
+                         int Cin_pad, float *gw, float *gb, hipStream_t s) {
+    const long long n = (long long)Cout * 9 * Cin + Cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part, bpart,
+                       nsplit, Cout, Cin, Cin_pad, gw, gb);
+}
+
+// ---- 2 x 2 average pooling --------------------------------------------------
+__global__ void k_pool(const uint16_t *in, uint16_t *out, int B, int H, int W, int C) {
+    const int Ho = H >> 1, Wo = W >> 1, G = C >> 3;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)B * Ho * Wo * G) return;
+    const int q = (int)(idx % G);
+    long long p = idx / G;
+    const int w = (int)(p % Wo);
+    p /= Wo;
+    const int h = (int)(p % Ho);
+    const int b = (int)(p / Ho);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int dh = 0; dh < 2; ++dh)
+#pragma unroll
+        for (int dw = 0; dw < 2; ++dw) {
+            const uint4 v = *(const uint4 *)(in + (((size_t)b * H + 2 * h + dh) * W + 2 * w + dw) * C + 8 * q);
+            const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s[2 * k] += bf2f(u[k] & 0xFFFFu);
+                s[2 * k + 1] += bf2f(u[k] >> 16);
+            }
+        }
+    uint32_t y[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y[k] = f2bf(0.25f * s[k]);
+    *(uint4 *)(out + (((size_t)b * Ho + h) * Wo + w) * C + 8 * q) =
+        make_uint4(y[0] | (y[1] << 16), y[2] | (y[3] << 16), y[4] | (y[5] << 16), y[6] | (y[7] << 16));
+}
+
+void launch_pool(const uint16_t *in, uint16_t *out, int B, int H, int W, int C, hipStream_t s) {
+    const long long n = (long long)B * (H >> 1) * (W >> 1) * (C >> 3);
+    hipLaunchKernelGGL(k_pool, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, B, H, W, C);
+}
+
+// ---- gradient through ReLU and the joins ------------------------------------
+__global__ void k_relu_bwd(ReluBwdArgs a) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)a.B * a.H * a.W * a.C;
+    if (idx >= total) return;
+    const int c = (int)(idx % a.C);
+    long long p = idx / a.C;
+    const int w = (int)(p % a.W);
+    const long long bh = p / a.W;
+    const int h = (int)(bh % a.H);
+    const int b = (int)(bh / a.H);
+    float s;
+    if (!a.a_up) {
+        s = a.ga[p * a.sa + a.oa + c];
+    } else {
+        const int H2 = 2 * a.H, W2 = 2 * a.W;
+        s = 0.f;
+#pragma unroll
+        for (int dh = 0; dh < 2; ++dh)
+#pragma unroll
+            for (int dw = 0; dw < 2; ++dw)
+                s += a.ga[(((size_t)b * H2 + 2 * h + dh) * W2 + 2 * w + dw) * a.sa + a.oa + c];
+    }
+    if (a.gb) {
+        const int Hh = a.H >> 1, Wh = a.W >> 1;
+        s += 0.25f * a.gb[(((size_t)b * Hh + (h >> 1)) * Wh + (w >> 1)) * a.C + c];
+    }
+    a.gy[idx] = (uint16_t)(bf2f(a.h[idx]) > 0.f ? f2bf(s) : 0u);
+}
+
+void launch_relu_bwd(const ReluBwdArgs &a, hipStream_t s) {
+    const long long n = (long long)a.B * a.H * a.W * a.C;
+    hipLaunchKernelGGL(k_relu_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+}
+
+// ---- 1 x 1 head (16 -> 1, float32 weights) ---------------------------------
+__global__ void k_head_fwd(const uint16_t *h, const float *wh, float *out, long long P) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const uint4 v0 = *(const uint4 *)(h + p * 16), v1 = *(const uint4 *)(h + p * 16 + 8);
+    const uint32_t u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        s += bf2f(u[k] & 0xFFFFu) * wh[2 * k];
+        s += bf2f(u[k] >> 16) * wh[2 * k + 1];
+    }
+    out[p] = s + wh[16];
+}
+
+void launch_head_fwd(const uint16_t *h, const float *wh, float *out, long long P, hipStream_t s) {
+    hipLaunchKernelGGL(k_head_fwd, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, h, wh, out, P);
+}
+
+constexpr int kRedPx = 4096;     // pixels per block of the reducing kernels
+
+template <int N>
+__device__ __forceinline__ void block_sum_store(double (&v)[N], double *dst) {
+    __shared__ double sh[N][256];
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) dst[k] = sh[k][0];
+    }
+}
+
+int head_bwd_blocks(long long P) { return (int)((P + kRedPx - 1) / kRedPx); }
+
+__global__ void k_head_bwd(const uint16_t *h, const float *wh, const float *gout, uint16_t *gy,
+                           double *part, long long P) {
+    double acc[17];
+#pragma unroll
+    for (int k = 0; k < 17; ++k) acc[k] = 0.0;
+    const long long p0 = (long long)blockIdx.x * kRedPx;
+    for (long long p = p0 + threadIdx.x; p < p0 + kRedPx && p < P; p += blockDim.x) {
+        const float go = gout[p];
+        const uint4 v0 = *(const uint4 *)(h + p * 16), v1 = *(const uint4 *)(h + p * 16 + 8);
+        const uint32_t u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        uint32_t y[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float a0 = bf2f(u[k] & 0xFFFFu), a1 = bf2f(u[k] >> 16);
+            acc[2 * k] += (double)go * a0;
+            acc[2 * k + 1] += (double)go * a1;
+            const uint32_t g0 = a0 > 0.f ? f2bf(go * wh[2 * k]) : 0u;
+            const uint32_t g1 = a1 > 0.f ? f2bf(go * wh[2 * k + 1]) : 0u;
+            y[k] = g0 | (g1 << 16);
+        }
+        acc[16] += go;
+        *(uint4 *)(gy + p * 16) = make_uint4(y[0], y[1], y[2], y[3]);
+        *(uint4 *)(gy + p * 16 + 8) = make_uint4(y[4], y[5], y[6], y[7]);
+    }
+    block_sum_store<17>(acc, part + 17 * (size_t)blockIdx.x);
+}
+
+void launch_head_bwd(const uint16_t *h, const float *wh, const float *gout, uint16_t *gy,
+                     double *part, long long P, hipStream_t s) {
+    hipLaunchKernelGGL(k_head_bwd, dim3(head_bwd_blocks(P)), dim3(256), 0, s, h, wh, gout, gy, part, P);
+}
+
+__global__ void k_head_finalize(const double *part, int nblk, float *gwh) {
+    const int k = threadIdx.x;
+    if (k >= 17) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[17 * (size_t)b + k];
+    gwh[k] = (float)s;
+}
+
+void launch_head_finalize(const double *part, int nblk, float *gwh, hipStream_t s) {
+    hipLaunchKernelGGL(k_head_finalize, dim3(1), dim3(64), 0, s, part, nblk, gwh);
+}
+
+// ---- masked mean-square loss ---------------------------------------------------
+int loss_blocks(long long P) { return (int)((P + kRedPx - 1) / kRedPx); }
+
+__global__ void k_mask_sum(const float *mask, double *part, long long P) {
+    double acc[1] = {0.0};
+    const long long p0 = (long long)blockIdx.x * kRedPx;
+    for (long long p = p0 + threadIdx.x; p < p0 + kRedPx && p < P; p += blockDim.x) acc[0] += mask[p];
+    block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+void launch_mask_sum(const float *mask, double *part, long long P, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_sum, dim3(loss_blocks(P)), dim3(256), 0, s, mask, part, P);
+}
+
+// loss = sum m (out - t)^2 / sum m;  gout = 2 m (out - t) / sum m
+__global__ void k_loss(const float *out, const float *target, const float *mask, const double *msum,
+                       float *gout, double *part, long long P) {
+    double acc[1] = {0.0};
+    const double inv = *msum > 0.0 ? 1.0 / *msum : 0.0;
+    const long long p0 = (long long)blockIdx.x * kRedPx;
+    for (long long p = p0 + threadIdx.x; p < p0 + kRedPx && p < P; p += blockDim.x) {
+        const double d = (double)out[p] - (double)target[p];
+        acc[0] += (double)mask[p] * d * d;
+        gout[p] = (float)(2.0 * mask[p] * d * inv);
+    }
+    acc[0] *= inv;
+    block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+void launch_loss(const float *out, const float *target, const float *mask, const double *msum,
+                 float *gout, double *part, long long P, hipStream_t s) {
+    hipLaunchKernelGGL(k_loss, dim3(loss_blocks(P)), dim3(256), 0, s, out, target, mask, msum, gout, part, P);
+}
+
+__global__ void k_sum_parts(const double *part, int n, double *dst) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += part[k];
+    *dst = s;
+}
+
+void launch_sum_parts(const double *part, int n, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, n, dst);
+}
+
+// ---- parameters -------------------------------------------------------------------
+// wf[co][t][ci] (ci < Cin_pad) for the forward; wd[ci][t][co] (co < Cout_pad)
+// = w[co][8 - t][ci] for the input gradient (taps flipped, channels swapped).
+__global__ void k_wprep(const float *w, int Cin, int Cout, uint16_t *wf, uint16_t *wd) {
+    const int Cip = pad32(Cin), Cop = pad32(Cout);
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nf = (long long)Cout * 9 * Cip;
+    if (idx < nf) {
+        const int ci = (int)(idx % Cip);
+        const long long row = idx / Cip;
+        wf[idx] = (uint16_t)(ci < Cin ? f2bf(w[row * Cin + ci]) : 0u);
+    } else if (idx < nf + (long long)Cin * 9 * Cop) {
+        const long long k = idx - nf;
+        const int co = (int)(k % Cop);
+        const long long row = k / Cop;               // ci * 9 + t
+        const int t = (int)(row % 9), ci = (int)(row / 9);
+        wd[k] = (uint16_t)(co < Cout ? f2bf(w[((long long)co * 9 + 8 - t) * Cin + ci]) : 0u);
+    }
+}
+
+void launch_wprep(const float *w, int Cin, int Cout, uint16_t *wf, uint16_t *wd, hipStream_t s) {
+    const long long n = (long long)Cout * 9 * pad32(Cin) + (long long)Cin * 9 * pad32(Cout);
+    hipLaunchKernelGGL(k_wprep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, Cin, Cout, wf, wd);
+}
+
+__global__ void k_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+void launch_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1,
+                 float b2, float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr,
+                       b1, b2, eps, c1, c2);
+}
+
+// ---- Poisson problem <-> network tensors -----------------------------------------
+// Pixel (h, w) is node (h, w) of the NX x NY node grid (h < H <= NX, w < W <= NY).
+// Input channels: source term on free nodes * s_rho; free-node indicator;
+// Dirichlet value * s_v on conductor nodes.  Target: phi / s_phi; mask: free.
+__global__ void k_snapshot(const double *b, const double *phi, const uint8_t *nc, int NX, int NY,
+                           int H, int W, float s_rho, float s_v, float s_phi, uint16_t *x,
+                           float *target, float *mask) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long long)H * W) return;
+    const int h = (int)(p / W), w = (int)(p % W);
+    const long long node = (long long)h * NY + w;
+    const bool freen = nc[node] == 0;
+    const double bv = b[node];
+    x[3 * p + 0] = (uint16_t)(freen ? f2bf((float)(bv * s_rho)) : 0u);
+    x[3 * p + 1] = (uint16_t)(freen ? 0x3F80u : 0u);
+    x[3 * p + 2] = (uint16_t)(freen ? 0u : f2bf((float)(bv * s_v)));
+    if (phi) {
+        target[p] = (float)(phi[node] / s_phi);
+        mask[p] = freen ? 1.f : 0.f;
+    }
+}
+
+void launch_snapshot(const double *b, const double *phi, const uint8_t *node_cond, int NX, int NY,
+                     int H, int W, float s_rho, float s_v, float s_phi, uint16_t *x, float *target,
+                     float *mask, hipStream_t s) {
+    const long long n = (long long)H * W;
+    hipLaunchKernelGGL(k_snapshot, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, phi, node_cond,
+                       NX, NY, H, W, s_rho, s_v, s_phi, x, target, mask);
+}
+
+__global__ void k_guess(const float *out, const double *b, const uint8_t *nc, int NX, int NY, int H,
+                        int W, float s_phi, double *guess) {
+    const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= (long long)NX * NY) return;
+    const int i = (int)(node / NY), j = (int)(node % NY);
+    double v = 0.0;
+    if (nc[node] != 0) v = b[node];
+    else if (i < H && j < W) v = (double)out[(long long)i * W + j] * (double)s_phi;
+    guess[node] = v;
+}
+
+void launch_guess(const float *out, const double *b, const uint8_t *node_cond, int NX, int NY,
+                  int H, int W, float s_phi, double *guess, hipStream_t s) {
+    const long long n = (long long)NX * NY;
+    hipLaunchKernelGGL(k_guess, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, b, node_cond, NX,
+                       NY, H, W, s_phi, guess);
+}
+
+} // namespace unet

@@ -78,7 +78,8 @@ ENTRY_POINTS = ["pic_workspace_size", "pic_init", "pic_deposit", "pic_solve", "p
                 "pic_push", "pic_step", "pic_diagnostics", "pic_particles", "pic_read_hits",
                 "pic_sort", "pic_push_timing", "pic_set_timing", "pic_batch_workspace_size",
                 "pic_batch_init", "pic_batch_step", "pic_batch_diagnostics", "pic_batch_particles",
-                "pic_batch_solve_info", "pic_destroy", "pic_last_error", "pic_version"]
+                "pic_batch_solve_info", "pic_node_map", "pic_destroy", "pic_last_error",
+                "pic_version"]
 
 
 def lib():
@@ -112,6 +113,7 @@ def lib():
     L.pic_batch_diagnostics.argtypes = [P, i32, C.POINTER(pic_diag)]
     L.pic_batch_particles.argtypes = [P, i32, i32, C.POINTER(i32), C.POINTER(i64)]
     L.pic_batch_solve_info.argtypes = [P, i32, C.POINTER(pic_solve_info)]
+    L.pic_node_map.argtypes = [P, i32, C.POINTER(P), P, C.POINTER(i32), C.POINTER(i32)]
     L.pic_destroy.argtypes = [P]
     L.pic_destroy.restype = None
     L.pic_last_error.argtypes = [P]
@@ -225,6 +227,19 @@ class _Context:
         self.ws_t = self.torch.empty((nbytes + 256,), dtype=self.torch.uint8, device=self.dev)
         base = self.ws_t.data_ptr()
         return base + (-base) % 256
+
+    def pic_node_map(self, i=0):
+        """(device pointer, NX, NY) of the library's node map of instance i."""
+        p, nx, ny = C.c_void_p(), C.c_int32(), C.c_int32()
+        self._chk(lib().pic_node_map(self.ctx, int(i), C.byref(p), None, C.byref(nx), C.byref(ny)))
+        return p.value, nx.value, ny.value
+
+    def node_map_host(self, i=0):
+        """Host copy (numpy uint8 [NX, NY]) of the node map of instance i."""
+        _, nx, ny = self.pic_node_map(i)
+        out = np.zeros((nx, ny), np.uint8)
+        self._chk(lib().pic_node_map(self.ctx, int(i), None, out.ctypes.data_as(C.c_void_p), None, None))
+        return out
 
     def close(self):
         if getattr(self, "ctx", None):

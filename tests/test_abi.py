@@ -11,8 +11,8 @@ import synth
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared():
-    txt = open(os.path.join(ROOT, "include", "pic.h")).read()
+def declared(header="pic.h"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", txt)))
 
@@ -26,6 +26,34 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(L, nm), nm
     assert set(names) == set(pic.ENTRY_POINTS)
     assert L.pic_version().startswith(b"pic-gfx950")
+
+
+def test_every_network_symbol_is_exported():
+    from paper_1610_03918_amd import unet
+    L = unet.lib()
+    names = declared("pic_unet.h")
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(names) == set(unet.UNET_ENTRY_POINTS)
+
+
+def test_network_layer_table_matches_the_oracle():
+    """The library's parameter layout (host computation, no GPU) equals the
+    oracle network's shapes, in the same order."""
+    from oracle import unet as ounet
+    from paper_1610_03918_amd import unet
+    ys = unet.layers()
+    assert [(y["cin"], y["cout"]) for y in ys[:-1]] == ounet.conv_shapes()
+    off = 0
+    for y in ys[:-1]:
+        assert y["w"] == off and y["b"] == off + y["cout"] * 9 * y["cin"]
+        off = y["b"] + y["cout"]
+    assert ys[-1]["w"] == off and ys[-1]["b"] == off + 16
+    assert unet.param_count() == off + 17 == sum(p.size for p in ounet.init_params())
+    nb = C.c_size_t(0)
+    assert unet.lib().pic_unet_workspace_size(1, 1024, 512, C.byref(nb)) == 0
+    assert 2e8 < nb.value < 1.5e9
+    assert unet.lib().pic_unet_workspace_size(1, 1020, 512, C.byref(nb)) == -1
 
 
 def _ws(cfg, cap):

@@ -1,0 +1,191 @@
+"""GPU tests of the learned warm start's network against the oracle U-Net.
+
+Forward: the device network (bfloat16 weights and activations, float32
+accumulation on the matrix cores) against the float64 oracle with the same
+bfloat16 rounding of inputs, weights and stored activations.  The two differ
+only by float32 versus float64 accumulation, which moves an activation by
+one bfloat16 step (2^-8 relative) where it lands next to a rounding
+boundary, and 14 layers of random weights amplify such flips: perturbing
+the oracle's sums by float32-sized relative noise moves its output by up to
+about 3e-3 (relative L2; pinned on the CPU in test_oracle_unet).  The bar is
+1e-2.
+
+Backward: parameter gradients against the oracle's float64 backward pass on
+the oracle's own (quantised) forward activations.  The device rounds the
+gradient entering every convolution to bfloat16 (relative 2^-9 per value),
+so each gradient tensor is held to a relative L2 error of 2e-2.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import unet as ou
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed):
+    """Seeded parameters in the flat layout (He-normal weights, small random biases)."""
+    r = np.random.default_rng(seed)
+    ps = []
+    for cin, cout in ou.conv_shapes():
+        ps.append((r.standard_normal((cout, 3, 3, cin)) * np.sqrt(2.0 / (9 * cin))).astype(np.float32))
+        ps.append((r.standard_normal(cout) * 0.05).astype(np.float32))
+    ps.append((r.standard_normal(16) * 0.25).astype(np.float32))
+    ps.append(np.array([0.1], np.float32))
+    return ps
+
+
+def _flat(ps):
+    return np.concatenate([p.reshape(-1) for p in ps]).astype(np.float32)
+
+
+def _unflat(flat, like):
+    out, off = [], 0
+    for p in like:
+        out.append(np.asarray(flat[off:off + p.size], np.float64).reshape(p.shape))
+        off += p.size
+    return out
+
+
+def _net(B, H, W, ps):
+    import torch
+    from paper_1610_03918_amd.unet import UNet
+    return UNet(B, H, W, params=_flat(ps)), torch
+
+
+def _set_input(u, torch, x):
+    u.input().copy_(torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(u.dev))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 24), (1, 64, 48)])
+def test_forward_matches_oracle(B, H, W):
+    ps = _params(11)
+    u, torch = _net(B, H, W, ps)
+    r = np.random.default_rng(3)
+    x = ou.bf16(r.standard_normal((B, H, W, 3)))
+    _set_input(u, torch, x)
+    u.pic_unet_forward()
+    got = u.output().cpu().numpy().astype(np.float64)
+    ref, _ = ou.forward(ps, x, quantize=True)
+    assert got.shape == ref.shape
+    assert np.all(np.isfinite(got))
+    assert _rel(got, ref) < 1e-2, _rel(got, ref)
+    u.close()
+
+
+def test_forward_full_size_on_crops():
+    """1024 x 512 (the trench grid's node rows): the oracle evaluates
+    aligned crops; outputs farther than the receptive radius (< 64 pixels)
+    from a crop edge that is not an image edge equal the full-image output."""
+    H, W, M = 1024, 512, 64
+    ps = _params(12)
+    u, torch = _net(1, H, W, ps)
+    r = np.random.default_rng(4)
+    x = ou.bf16(r.standard_normal((1, H, W, 3)))
+    _set_input(u, torch, x)
+    u.pic_unet_forward()
+    got = u.output().cpu().numpy().astype(np.float64)
+    for h0, w0 in [(0, 0), (448, 192), (1024 - 192, 512 - 192)]:
+        ref, _ = ou.forward(ps, x[:, h0:h0 + 192, w0:w0 + 192], quantize=True)
+        hs = slice(0 if h0 == 0 else M, 192 if h0 + 192 == H else 192 - M)
+        ws = slice(0 if w0 == 0 else M, 192 if w0 + 192 == W else 192 - M)
+        g = got[:, h0:h0 + 192, w0:w0 + 192][:, hs, ws]
+        assert _rel(g, ref[:, hs, ws]) < 1e-2, (h0, w0, _rel(g, ref[:, hs, ws]))
+    u.close()
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 24), (1, 32, 64)])
+def test_backward_matches_oracle(B, H, W):
+    ps = _params(13)
+    u, torch = _net(B, H, W, ps)
+    r = np.random.default_rng(5)
+    x = ou.bf16(r.standard_normal((B, H, W, 3)))
+    gout = r.standard_normal((B, H, W)).astype(np.float32)
+    _set_input(u, torch, x)
+    u.pic_unet_forward()
+    u.grad_output().copy_(torch.from_numpy(gout).to(u.dev))
+    u.pic_unet_backward()
+    grads = _unflat(u.grads.cpu().numpy(), ps)
+    _, cache = ou.forward(ps, x, quantize=True)
+    ref, _ = ou.backward(cache, gout.astype(np.float64))
+    for k, (g, rf) in enumerate(zip(grads, ref)):
+        assert np.all(np.isfinite(g)), k
+        assert _rel(g, rf) < 2e-2, (k, _rel(g, rf))
+    u.close()
+
+
+def test_loss_and_adam_step():
+    ps = _params(14)
+    B, H, W = 2, 16, 16
+    u, torch = _net(B, H, W, ps)
+    r = np.random.default_rng(6)
+    _set_input(u, torch, ou.bf16(r.standard_normal((B, H, W, 3))))
+    t = r.standard_normal((B, H, W)).astype(np.float32)
+    m = (r.random((B, H, W)) < 0.6).astype(np.float32)
+    u.target().copy_(torch.from_numpy(t).to(u.dev))
+    u.mask().copy_(torch.from_numpy(m).to(u.dev))
+    u.pic_unet_forward()
+    out = u.output().cpu().numpy().astype(np.float64)
+    loss = u.pic_unet_loss()
+    L, g = ou.mse(out, t.astype(np.float64), m.astype(np.float64))
+    assert abs(loss - L) <= 1e-9 * max(1.0, L)
+    assert np.allclose(u.grad_output().cpu().numpy(), g, rtol=1e-6, atol=1e-9)
+    u.pic_unet_backward()
+    p0 = u.params.cpu().numpy().astype(np.float64)
+    g0 = u.grads.cpu().numpy().astype(np.float64)
+    u.pic_unet_adam(1e-3)
+    # the device takes the hyper-parameters as float32
+    hp = dict(lr=float(np.float32(1e-3)), b1=float(np.float32(0.9)), b2=float(np.float32(0.999)),
+              eps=float(np.float32(1e-8)))
+    p1, m1, v1 = ou.adam(p0, g0, np.zeros_like(p0), np.zeros_like(p0), 1, **hp)
+    assert np.allclose(u.params.cpu().numpy(), p1, rtol=1e-6, atol=1e-7)
+    assert np.allclose(u.m.cpu().numpy(), m1, rtol=1e-6, atol=1e-12)
+    assert np.allclose(u.v.cpu().numpy(), v1, rtol=1e-5, atol=1e-15)
+    # a second step counts t = 2 and starts from the stored moments
+    u.pic_unet_forward()
+    u.pic_unet_loss()
+    u.pic_unet_backward()
+    g1 = u.grads.cpu().numpy().astype(np.float64)
+    u.pic_unet_adam(1e-3)
+    p2, _, _ = ou.adam(p1, g1, m1, v1, 2, **hp)
+    assert np.allclose(u.params.cpu().numpy(), p2, rtol=1e-5, atol=1e-6), np.max(np.abs(u.params.cpu().numpy() - p2))
+    u.close()
+
+
+def test_snapshot_and_guess_maps():
+    import torch
+    from paper_1610_03918_amd import Pic
+    from paper_1610_03918_amd.unet import UNet
+    w = synth.workload_for_tests("trench")
+    parts = synth.load(w)
+    pic = Pic(w, parts)
+    pic.start()
+    pic.pic_step(2)
+    nm = pic.pic_node_map()
+    nc = oracle.node_cond(w)
+    H, W = (w.NX // 8) * 8, (w.NY // 8) * 8
+    u = UNet(2, H, W)
+    scales = (np.float32(0.37), np.float32(1 / 50), np.float32(50.0))
+    u.pic_unet_snapshot(1, pic.b, pic.phi, nm, scales)
+    b = pic.b.cpu().numpy().reshape(w.NX, w.NY)
+    phi = pic.phi.cpu().numpy().reshape(w.NX, w.NY)
+    x = u.input()[1].float().cpu().numpy()
+    assert np.array_equal(x, ou.features(b, nc.reshape(w.NX, w.NY), H, W, float(scales[0]), float(scales[1])))
+    assert np.array_equal(u.target()[1].cpu().numpy(), (phi[:H, :W] / float(scales[2])).astype(np.float32))
+    assert np.array_equal(u.mask()[1].cpu().numpy(), (nc.reshape(w.NX, w.NY)[:H, :W] == 0).astype(np.float32))
+    u.pic_unet_forward()
+    guess = torch.empty(w.NX * w.NY, dtype=torch.float64, device="cuda:0")
+    u.pic_unet_guess(1, pic.b, nm, float(scales[2]), guess)
+    out = u.output()[1].cpu().numpy().astype(np.float64)
+    ref = ou.guess(out * np.float32(1.0), b, nc.reshape(w.NX, w.NY), float(scales[2]))
+    assert np.array_equal(guess.cpu().numpy().reshape(w.NX, w.NY), ref)
+    u.close()
+    pic.close()

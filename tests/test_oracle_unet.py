@@ -1,0 +1,188 @@
+"""Pins of the oracle U-Net (CPU only).
+
+The network is this project's learned warm start, not something the paper
+defines, so its oracle is pinned against independent definitions: the
+convolution against SciPy's 2D correlation, bfloat16 rounding against
+torch's conversion, pooling / upsampling against their adjoint identities,
+the wiring (skip levels, concatenation order, pooling before upsampling)
+against a closed form on a pass-through network, and the backward pass
+against central finite differences of the forward pass.
+"""
+import numpy as np
+import pytest
+import scipy.signal
+
+from oracle import unet
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    r = _rng(1)
+    x = np.concatenate([r.standard_normal(4000) * 10.0 ** r.integers(-6, 6, 4000),
+                        np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -1.0 - 2.0 ** -8, 0.0, -0.0])])
+    x32 = x.astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(unet.bf16(x32), ref)
+
+
+def test_conv_matches_scipy_correlate2d():
+    r = _rng(2)
+    B, H, W, C, Co = 2, 8, 12, 3, 5
+    x = r.standard_normal((B, H, W, C))
+    w = r.standard_normal((Co, 3, 3, C))
+    b = r.standard_normal(Co)
+    y = unet.conv3x3(x, w, b)
+    for bi in range(B):
+        for co in range(Co):
+            ref = b[co] + sum(scipy.signal.correlate2d(x[bi, :, :, ci], w[co, :, :, ci], mode="same")
+                              for ci in range(C))
+            assert np.allclose(y[bi, :, :, co], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_pool_and_upsample_adjoints():
+    r = _rng(3)
+    x = r.standard_normal((2, 8, 6, 4))
+    y = r.standard_normal((2, 4, 3, 4))
+    assert np.isclose((unet.pool(x) * y).sum(), (x * unet.pool_grad(y)).sum())
+    assert np.isclose((unet.up(y) * x).sum(), (y * unet.up_grad(x)).sum())
+    assert np.allclose(unet.pool(unet.up(y)), y)
+    # block mean written out
+    assert np.isclose(unet.pool(x)[1, 2, 1, 3], x[1, 4:6, 2:4, 3].mean())
+
+
+def test_shapes_of_the_network():
+    s = unet.conv_shapes()
+    assert s[:8] == [(3, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 128)]
+    assert s[8:] == [(192, 64), (64, 64), (96, 32), (32, 32), (48, 16), (16, 16)]
+    ps = unet.init_params()
+    assert len(ps) == 2 * len(s) + 2
+    out, _ = unet.forward(ps, _rng(4).standard_normal((1, 16, 24, 3)))
+    assert out.shape == (1, 16, 24)
+
+
+def _block_mean(x, k):
+    B, H, W = x.shape
+    return x.reshape(B, H // k, k, W // k, k).mean(axis=(2, 4))
+
+
+def _block_repeat(x, k):
+    return np.kron(x, np.ones((1, k, k)))
+
+
+def test_pass_through_network_closed_form():
+    """Every convolution copies channel 0 (centre tap 1); the first decoder
+    convolution of each level adds channel 0 of the upsampled input and
+    channel 0 of the skip.  With a non-negative input the output is then
+    x + U(P x) + U^2(P^2 x) + U^3(P^3 x) with P a 2x2 block mean and U a 2x2
+    block copy; a wrong skip level, concatenation order or pool/upsample
+    placement changes this sum."""
+    shapes = unet.conv_shapes()
+    ps = []
+    for k, (cin, cout) in enumerate(shapes):
+        w = np.zeros((cout, 3, 3, cin))
+        w[0, 1, 1, 0] = 1.0
+        if k in (8, 10, 12):          # first decoder conv: up channels first, then the skip
+            w[0, 1, 1, cin - unet.CH[(12 - k) // 2]] = 1.0
+        ps += [w, np.zeros(cout)]
+    hw = np.zeros(unet.CH[0])
+    hw[0] = 1.0
+    ps += [hw, np.zeros(1)]
+    x = np.zeros((2, 16, 24, 3))
+    x[..., 0] = _rng(5).random((2, 16, 24))
+    x[..., 1:] = _rng(6).random((2, 16, 24, 2))      # ignored channels
+    out, _ = unet.forward(ps, x)
+    x0 = x[..., 0]
+    ref = x0 + sum(_block_repeat(_block_mean(x0, 2 ** k), 2 ** k) for k in (1, 2, 3))
+    assert np.allclose(out, ref, rtol=1e-13, atol=1e-13)
+
+
+def _loss(ps, x, c):
+    out, cache = unet.forward(ps, x)
+    return (out * c).sum(), cache
+
+
+def test_backward_matches_finite_differences():
+    r = _rng(7)
+    ps = [p.astype(np.float64) for p in unet.init_params(seed=3)]
+    for k in range(1, len(ps), 2):                   # non-zero biases
+        ps[k] = r.standard_normal(ps[k].shape) * 0.1
+    x = r.standard_normal((1, 16, 16, 3))
+    c = r.standard_normal((1, 16, 16))
+    _, cache = _loss(ps, x, c)
+    grads, gx = unet.backward(cache, c)
+    h = 1e-6
+    checked = 0
+    for pi, p in enumerate(ps):
+        assert grads[pi].shape == p.shape
+        flat = p.reshape(-1)
+        for idx in r.choice(flat.size, size=min(4, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = _loss(ps, x, c)
+            flat[idx] = old - h
+            lm, _ = _loss(ps, x, c)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            g = grads[pi].reshape(-1)[idx]
+            assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (pi, idx, fd, g)
+            checked += 1
+    for idx in r.choice(x.size, size=6, replace=False):
+        xf = x.reshape(-1)
+        old = xf[idx]
+        xf[idx] = old + h
+        lp, _ = _loss(ps, x, c)
+        xf[idx] = old - h
+        lm, _ = _loss(ps, x, c)
+        xf[idx] = old
+        assert abs((lp - lm) / (2 * h) - gx.reshape(-1)[idx]) <= 1e-6
+    assert checked >= 100
+
+
+def test_mse_gradient():
+    r = _rng(8)
+    p, t = r.standard_normal((2, 8, 8)), r.standard_normal((2, 8, 8))
+    m = (r.random((2, 8, 8)) < 0.7).astype(float)
+    L, g = unet.mse(p, t, m)
+    assert np.isclose(L, ((p - t) ** 2 * m).sum() / m.sum())
+    h = 1e-6
+    for idx in [(0, 1, 2), (1, 7, 7), (1, 0, 3)]:
+        q = p.copy()
+        q[idx] += h
+        Lp, _ = unet.mse(q, t, m)
+        q[idx] -= 2 * h
+        Lm, _ = unet.mse(q, t, m)
+        assert abs((Lp - Lm) / (2 * h) - g[idx]) < 1e-7
+
+
+def test_forward_sensitivity_to_float32_sums():
+    """Bound used by the device forward test: rounding every convolution sum
+    to float32 (with float32-sized relative noise) before the bfloat16
+    rounding of the activations moves the network output by less than
+    5e-3 (relative L2) at the tested shapes."""
+    r = np.random.default_rng(9)
+    ps = []
+    for cin, cout in unet.conv_shapes():
+        ps.append(r.standard_normal((cout, 3, 3, cin)) * np.sqrt(2.0 / (9 * cin)))
+        ps.append(r.standard_normal(cout) * 0.05)
+    ps += [r.standard_normal(16) * 0.25, np.array([0.1])]
+    orig = unet.conv3x3
+    noise = np.random.default_rng(1)
+
+    def conv32(x, w, b):
+        y = orig(x, w, b).astype(np.float32)
+        return (y * (1 + noise.standard_normal(y.shape).astype(np.float32) * 3e-7)).astype(np.float64)
+
+    for shape in [(2, 16, 24, 3), (1, 64, 48, 3)]:
+        x = unet.bf16(r.standard_normal(shape))
+        ref, _ = unet.forward(ps, x, quantize=True)
+        unet.conv3x3 = conv32
+        try:
+            alt, _ = unet.forward(ps, x, quantize=True)
+        finally:
+            unet.conv3x3 = orig
+        rel = np.linalg.norm(alt - ref) / np.linalg.norm(ref)
+        assert 1e-5 < rel < 5e-3, rel
