@@ -187,8 +187,22 @@ def run_sweep(args):
     parts = [synth.load(w) for w in ws]
     n0 = sum(p["cell"].size for q in parts for p in q)
     log(f"loaded {len(ws)} instances, {n0} particles in {time.perf_counter() - t:.1f}s")
-    sort = tuple(int(x) for x in args.sort.split(","))
-    b = PicBatch(ws, parts, sort_interval=sort, chunk=args.chunk, push_unroll=args.unroll)
+    from paper_1610_03918_amd import autotune
+    entry = autotune.lookup(ws, parts)
+    if entry is None and args.autotune:
+        log("no cached schedule for this batch: running the autotuner")
+        entry = autotune.tune(ws, parts, log=log)
+    if entry is not None:
+        sch = entry["schedule"]
+        source = f"autotuned (cache key {autotune.signature(ws, parts)})"
+    else:
+        sch = dict(autotune.DEFAULT)
+        sch.update(sort_interval=[int(x) for x in args.sort.split(",")], chunk=args.chunk,
+                   push_unroll=args.unroll)
+        source = "command line (no cached autotune result)"
+    sort = tuple(sch["sort_interval"])
+    b = PicBatch(ws, parts, sort_interval=sort, chunk=sch["chunk"], push_unroll=sch["push_unroll"],
+                 push_merge=sch["push_merge"], tile=tuple(sch["tile"]), halo=sch["halo"])
     b.start()
     # eager steps tell how many iterations the captured schedule needs
     most = 0
@@ -214,7 +228,7 @@ def run_sweep(args):
            "config": {"workload": "trench-width sweep x16 (batched, graph-captured)",
                       "widths": list(synth.SWEEP_WIDTHS), "ppc": ws[0].species[0].ppc,
                       "particles": int(n0), "solver_schedule": [passes, iters],
-                      "all_converged": conv, "sort_interval": list(sort)}}
+                      "all_converged": conv, "schedule": sch, "schedule_source": source}}
     b.close()
     print(json.dumps(out), flush=True)
 
@@ -249,6 +263,8 @@ def main():
     ap.add_argument("--halo", type=int, default=4)
     ap.add_argument("--warm", type=int, default=1, help="0 previous phi, 1 extrapolated")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
+    ap.add_argument("--autotune", action="store_true",
+                    help="sweep: tune the schedule when the cache has no entry for the batch")
     ap.add_argument("--learn-snapshots", type=int, default=128)
     ap.add_argument("--learn-steps", type=int, default=2000)
     ap.add_argument("--learn-batch", type=int, default=4)

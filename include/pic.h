@@ -188,6 +188,15 @@ pic_status pic_particles(pic_ctx *ctx, int32_t species, int32_t *set, int64_t *s
  * host memory out; *n receives the number copied.  Waits. */
 pic_status pic_read_hits(pic_ctx *ctx, pic_hit *out, int64_t max, int64_t *n);
 
+/* Changes the schedule of a running context (all instances): the push
+ * variant (push_unroll 1, 2 or 4; push_merge 0, 2 or 4, as in pic_config)
+ * and the re-binning intervals of electrons and ions (steps; 0 = never).
+ * Results do not depend on any of them (integer deposit, independent
+ * particles); only the time per step does.  Waits for the stream and drops
+ * the captured step graphs. */
+pic_status pic_tune(pic_ctx *ctx, int32_t push_unroll, int32_t push_merge, int32_t sort_e,
+                    int32_t sort_i);
+
 /* Re-bins species s now (tile sort; drops removed particles). */
 pic_status pic_sort(pic_ctx *ctx, int32_t species);
 

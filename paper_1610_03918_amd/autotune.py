@@ -1,0 +1,159 @@
+"""Schedule autotuner of the batched form.
+
+The particle kernels have free choices that change only the time per step,
+never a result (the deposit is integer and order-free, particles are
+independent): the tile of cells a block owns (its LDS charge window), the
+particles per block (chunk), the push variant (particles per thread per pass,
+wavefront-level merging of equal cells before the LDS atomics) and the
+re-binning intervals of electrons and ions.  The tuner times candidates on
+the GPU with the captured batched step and keeps the fastest:
+
+  1. layout (tile, chunk): each candidate needs its own context;
+  2. push variant (unroll, merge) on the best layout, via pic_tune;
+  3. re-binning intervals, via pic_tune.
+
+Results are cached in ``tuning/schedules.json`` under a key derived from the
+instances' grids, geometry and particle counts.
+
+  python -m paper_1610_03918_amd.autotune [--sweep] [--out PATH]
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning", "schedules.json")
+
+DEFAULT = {"tile": [16, 16], "chunk": 4096, "halo": 4, "push_unroll": 2, "push_merge": 0,
+           "sort_interval": [8, 64]}
+LAYOUTS = [((16, 16), 4096), ((16, 16), 8192), ((32, 16), 4096), ((16, 32), 4096), ((32, 32), 8192)]
+VARIANTS = [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2)]
+SORTS = [(4, 32), (8, 64), (16, 64), (8, 128), (16, 128), (32, 128)]
+
+
+def signature(workloads, parts):
+    """Key of a batch: grids, geometry, species and particle counts."""
+    desc = []
+    for w, p in zip(workloads, parts):
+        desc.append([w.nx, w.ny, int(w.periodic_x), int(w.periodic_y), w.box_i_top, w.box_j_lo,
+                     w.box_j_hi, [int(q["cell"].size) for q in p], [s.alpha for s in w.species]])
+    return hashlib.sha1(json.dumps(desc, sort_keys=True).encode()).hexdigest()[:16]
+
+
+def load_cache(path=CACHE):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(workloads, parts, path=CACHE):
+    """The cached schedule of this batch, or None."""
+    return load_cache(path).get(signature(workloads, parts))
+
+
+def _measure(b, period, steps, passes, iters, repeats=2):
+    """Best of `repeats` timings of `steps` captured steps (ms/step)."""
+    import torch
+    b.pic_batch_step(period or 8, passes, iters)     # capture + warm
+    best, ok = None, True
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = b.pic_batch_step(steps, passes, iters)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        best = ms if best is None else min(best, ms)
+        ok = ok and all(x["converged"] for x in infos)
+    return best, ok
+
+
+def _solver_schedule(b, warm):
+    most = 0
+    for _ in range(max(2, warm)):
+        b.pic_step(1)
+        most = max(most, max(b.pic_batch_solve_info(i)["iterations"] for i in range(b.n)))
+    return 2, min(128, most + 2)
+
+
+def tune(workloads, parts, steps=32, log=None, path=CACHE):
+    """Times the candidates, stores and returns the best schedule."""
+    from .pic import PicBatch
+    say = log or (lambda *a: None)
+    trials = []
+    best = None
+    schedule = None
+    for tile, chunk in LAYOUTS:
+        opts = dict(DEFAULT)
+        opts.update(tile=list(tile), chunk=chunk)
+        b = PicBatch(workloads, parts, tile=tuple(tile), chunk=chunk, halo=opts["halo"],
+                     push_unroll=opts["push_unroll"], push_merge=opts["push_merge"],
+                     sort_interval=tuple(opts["sort_interval"]))
+        b.start()
+        if schedule is None:
+            schedule = _solver_schedule(b, 3)
+        ms, ok = _measure(b, opts["sort_interval"][0], steps, *schedule)
+        b.close()
+        trials.append({"stage": "layout", "tile": list(tile), "chunk": chunk, "ms": ms, "converged": ok})
+        say(f"layout tile {tile} chunk {chunk}: {ms:.3f} ms/step")
+        if ok and (best is None or ms < best[0]):
+            best = (ms, opts)
+    opts = dict(best[1])
+    b = PicBatch(workloads, parts, tile=tuple(opts["tile"]), chunk=opts["chunk"], halo=opts["halo"],
+                 push_unroll=opts["push_unroll"], push_merge=opts["push_merge"],
+                 sort_interval=tuple(opts["sort_interval"]))
+    b.start()
+    _solver_schedule(b, 2)
+    cur = None
+    for unroll, merge in VARIANTS:
+        b.pic_tune(unroll, merge, opts["sort_interval"])
+        ms, ok = _measure(b, opts["sort_interval"][0], steps, *schedule)
+        trials.append({"stage": "push", "push_unroll": unroll, "push_merge": merge, "ms": ms, "converged": ok})
+        say(f"push unroll {unroll} merge {merge}: {ms:.3f} ms/step")
+        if ok and (cur is None or ms < cur[0]):
+            cur = (ms, unroll, merge)
+    opts["push_unroll"], opts["push_merge"] = cur[1], cur[2]
+    cur = None
+    for sort in SORTS:
+        b.pic_tune(opts["push_unroll"], opts["push_merge"], sort)
+        n = max(steps, 2 * sort[0])
+        ms, ok = _measure(b, sort[0], n, *schedule)
+        trials.append({"stage": "sort", "sort_interval": list(sort), "ms": ms, "converged": ok})
+        say(f"sort {sort}: {ms:.3f} ms/step")
+        if ok and (cur is None or ms < cur[0]):
+            cur = (ms, sort)
+    opts["sort_interval"] = list(cur[1])
+    b.close()
+    entry = {"schedule": opts, "ms_per_step": cur[0], "solver_schedule": list(schedule),
+             "instances": len(workloads), "trials": trials}
+    cache = load_cache(path)
+    cache[signature(workloads, parts)] = entry
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path + ".tmp", "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(path + ".tmp", path)
+    return entry
+
+
+def main():
+    import argparse
+    sys.path.insert(0, os.path.dirname(HERE))
+    import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sweep", action="store_true", help="the 16-width trench sweep (default)")
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args()
+    ws = synth.sweep()
+    parts = [synth.load(w) for w in ws]
+    entry = tune(ws, parts, steps=args.steps, log=lambda m: print(m, flush=True), path=args.out)
+    print(json.dumps({k: v for k, v in entry.items() if k != "trials"}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1180,6 +1180,32 @@ pic_status pic_batch_step(pic_ctx *c, int32_t nsteps, int32_t passes, int32_t it
     return PIC_OK;
 }
 
+pic_status pic_tune(pic_ctx *c, int32_t push_unroll, int32_t push_merge, int32_t sort_e, int32_t sort_i)
+{
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (push_unroll != 1 && push_unroll != 2 && push_unroll != 4)
+        return fail(c, PIC_ERR_ARG, "push_unroll must be 1, 2 or 4");
+    if (push_merge != 0 && push_merge != 2 && push_merge != 4)
+        return fail(c, PIC_ERR_ARG, "push_merge must be 0, 2 or 4");
+    if (sort_e < 0 || sort_i < 0 || sort_e > 1 << 20 || sort_i > 1 << 20)
+        return fail(c, PIC_ERR_ARG, "sort intervals must be in 0 .. 2^20");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->unroll = push_unroll;
+    c->merge = push_merge;
+    for (auto &h : c->in) {
+        h.cfg.push_unroll = push_unroll;
+        h.cfg.push_merge = push_merge;
+        h.cfg.sort_interval[0] = sort_e;
+        h.cfg.sort_interval[1] = sort_i;
+        h.L.unroll = push_unroll;
+        h.L.merge = push_merge;
+    }
+    // captured steps embed the push variant and the re-binning points
+    for (auto &kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->step_graphs.clear();
+    return PIC_OK;
+}
+
 pic_status pic_sort(pic_ctx *c, int32_t species)
 {
     if (check(c) != PIC_OK) return PIC_ERR_STATE;

@@ -78,7 +78,7 @@ ENTRY_POINTS = ["pic_workspace_size", "pic_init", "pic_deposit", "pic_solve", "p
                 "pic_push", "pic_step", "pic_diagnostics", "pic_particles", "pic_read_hits",
                 "pic_sort", "pic_push_timing", "pic_set_timing", "pic_batch_workspace_size",
                 "pic_batch_init", "pic_batch_step", "pic_batch_diagnostics", "pic_batch_particles",
-                "pic_batch_solve_info", "pic_node_map", "pic_destroy", "pic_last_error",
+                "pic_batch_solve_info", "pic_node_map", "pic_tune", "pic_destroy", "pic_last_error",
                 "pic_version"]
 
 
@@ -114,6 +114,7 @@ def lib():
     L.pic_batch_particles.argtypes = [P, i32, i32, C.POINTER(i32), C.POINTER(i64)]
     L.pic_batch_solve_info.argtypes = [P, i32, C.POINTER(pic_solve_info)]
     L.pic_node_map.argtypes = [P, i32, C.POINTER(P), P, C.POINTER(i32), C.POINTER(i32)]
+    L.pic_tune.argtypes = [P, i32, i32, i32, i32]
     L.pic_destroy.argtypes = [P]
     L.pic_destroy.restype = None
     L.pic_last_error.argtypes = [P]
@@ -240,6 +241,10 @@ class _Context:
         out = np.zeros((nx, ny), np.uint8)
         self._chk(lib().pic_node_map(self.ctx, int(i), None, out.ctypes.data_as(C.c_void_p), None, None))
         return out
+
+    def pic_tune(self, push_unroll, push_merge, sort_interval):
+        self._chk(lib().pic_tune(self.ctx, int(push_unroll), int(push_merge), int(sort_interval[0]),
+                                 int(sort_interval[1])))
 
     def close(self):
         if getattr(self, "ctx", None):
