@@ -17,6 +17,10 @@ Functions and the passages they follow:
   push_f32/f64   gather + leapfrog + wall test                  eqs. (1)-(4), Sec. III
   rewind_f32/f64 leapfrog start (half step back)                eqs. (1)-(2)
   Sim            one step = deposit, solve, field, push          Sec. II ordering (reading Q1)
+
+``oracle.unet`` is the float64 reference of the learned warm start's network
+(forward, backward, loss, Adam, and the maps between the Poisson problem
+and the network's tensors).
 """
 from __future__ import annotations
 
