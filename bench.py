@@ -256,7 +256,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sort", default="8,64")
-    ap.add_argument("--unroll", type=int, default=2)
+    ap.add_argument("--unroll", type=int, default=4)
     ap.add_argument("--merge", type=int, default=0)
     ap.add_argument("--tile", default="16,16")
     ap.add_argument("--chunk", type=int, default=4096)
@@ -349,7 +349,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-                     "kernel": "k_push<true,2,0>", "avg_launch_ms": push_ms, "launches": launches,
+                     "kernel": f"k_push<true,{args.unroll},{args.merge}>", "avg_launch_ms": push_ms, "launches": launches,
                      "bytes_per_launch": per_launch * BYTES_PER_PARTICLE_STEP},
     }
     if not args.no_learned and w.name.startswith("trench"):

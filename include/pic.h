@@ -83,7 +83,8 @@ typedef struct {
     int32_t tile_x, tile_y;      /* particle tile in cells (powers of two; 0 = 16) */
     int32_t halo;                /* cells of drift a tile absorbs before a global fallback (0 = 4) */
     int32_t chunk;               /* particles per thread block (0 = 8192; at most 8192) */
-    int32_t push_unroll;         /* particles per thread per pass of the push loop: 1, 2, 4 (0 = 2) */
+    int32_t push_unroll;         /* particles per thread per pass of the push loop: 1, 2, 4 (0 = 4;
+                                    4 moves 4 consecutive particles with 16-byte accesses) */
     int32_t push_merge;          /* distinct cells summed per wavefront before LDS atomics: 0, 2, 4 */
     int64_t hitlog_capacity;     /* ring of wall-hit records in the workspace (0 = none) */
     int32_t hitlog_species_mask; /* bit s logs species s */

@@ -28,7 +28,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning", "schedules.json")
 
-DEFAULT = {"tile": [16, 16], "chunk": 4096, "halo": 4, "push_unroll": 2, "push_merge": 0,
+DEFAULT = {"tile": [16, 16], "chunk": 4096, "halo": 4, "push_unroll": 4, "push_merge": 0,
            "sort_interval": [8, 64]}
 LAYOUTS = [((16, 16), 4096), ((16, 16), 8192), ((32, 16), 4096), ((16, 32), 4096), ((32, 32), 8192)]
 VARIANTS = [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2)]

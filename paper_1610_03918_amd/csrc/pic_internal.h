@@ -187,4 +187,13 @@ void launch_rho_sum(const unsigned long long *rho, long long n, unsigned long lo
 void launch_tick(long long *step, hipStream_t s);
 int bin_per_block();
 
+// Dynamic LDS of the particle kernels: the tile + halo window of cell
+// moments (16 B per cell), the class counters, and the corner fields of the
+// tile + 1-cell frame (32 B per cell).
+inline size_t push_lds_bytes(int TX, int TY, int H)
+{
+    const size_t mom = (size_t)(TX + 2 * H) * (TY + 2 * H) * 16 + kNClass * 4;
+    return ((mom + 15) & ~(size_t)15) + (size_t)(TX + 2) * (TY + 2) * 32;
+}
+
 } // namespace pic

@@ -912,17 +912,36 @@ __device__ __forceinline__ void wave_sum4_u32(unsigned &a, unsigned &b, unsigned
 // Arguments of the particle kernels resolved once per block into plain
 // scalars and pointers (the storage set in use is device info[7], flipped
 // by every re-binning), so particle stores cannot force them to be reloaded.
+// Global-memory (address space 1) pointers: loads, stores and atomics on
+// them compile to global_* instructions, which do not share the LDS wait
+// counter the way flat accesses do, so the deposit's LDS atomics never wait
+// for outstanding particle loads.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ GLOBAL T *to_global(T *p) { return (GLOBAL T *)p; }
+typedef int nt_i4 __attribute__((ext_vector_type(4)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_f4(GLOBAL const float4 *p)
+{
+    const nt_f4 v = *(GLOBAL const nt_f4 *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void gatomic_add(GLOBAL unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct PK {
     Geom g;
     int TX, TY, H, WX, WY, tiles_y;
-    const uint8_t *cell_cond;
-    const float4 *E4;
-    int32_t *cell;
-    float *ox, *oy, *vx, *vy;
-    unsigned long long *rho;
+    GLOBAL const uint8_t *cell_cond;
+    GLOBAL const float4 *E4;
+    GLOBAL int32_t *cell;
+    GLOBAL float *ox, *oy, *vx, *vy;
+    GLOBAL unsigned long long *rho;
     float qdt, dtf, hq;
     int box_i_top, box_j_lo, box_j_hi, species;
-    unsigned long long *surf;
+    GLOBAL unsigned long long *surf;
     HitLog log;
     const long long *step;
 };
@@ -938,14 +957,14 @@ __device__ __forceinline__ PK resolve(const PushArgs &a)
     k.WX = a.WX;
     k.WY = a.WY;
     k.tiles_y = a.tiles_y;
-    k.cell_cond = a.cell_cond;
-    k.E4 = a.E4;
-    k.cell = set ? a.cell[1] : a.cell[0];
-    k.ox = set ? a.ox[1] : a.ox[0];
-    k.oy = set ? a.oy[1] : a.oy[0];
-    k.vx = set ? a.vx[1] : a.vx[0];
-    k.vy = set ? a.vy[1] : a.vy[0];
-    k.rho = a.rho;
+    k.cell_cond = to_global(a.cell_cond);
+    k.E4 = to_global(a.E4);
+    k.cell = to_global(set ? a.cell[1] : a.cell[0]);
+    k.ox = to_global(set ? a.ox[1] : a.ox[0]);
+    k.oy = to_global(set ? a.oy[1] : a.oy[0]);
+    k.vx = to_global(set ? a.vx[1] : a.vx[0]);
+    k.vy = to_global(set ? a.vy[1] : a.vy[0]);
+    k.rho = to_global(a.rho);
     k.qdt = a.qdt;
     k.dtf = a.dtf;
     k.hq = a.hq;
@@ -953,19 +972,19 @@ __device__ __forceinline__ PK resolve(const PushArgs &a)
     k.box_j_lo = a.box_j_lo;
     k.box_j_hi = a.box_j_hi;
     k.species = a.species;
-    k.surf = a.surf;
+    k.surf = to_global(a.surf);
     k.log = a.log;
     k.step = a.step;
     return k;
 }
 
 // Leapfrog push of one particle with the bilinear gather of its cell's
-// corner fields and the cell-by-cell wall test (eqs. 1-4).  Updates the
-// particle in memory; returns false when it was removed (class in *dead).
-__device__ __forceinline__ bool push_particle(const PK &a, int p, int c, float &x0, float &y0,
-                                              float vx0, float vy0, float4 ea, float4 eb, int &ci,
-                                              int &cj, int &dead, int &ei, int &ej, float &ux,
-                                              float &uy)
+// corner fields and the cell-by-cell wall test (eqs. 1-4).  Computes the new
+// velocity (ux, uy), offsets (nxo, nyo) and cell (ei, ej); returns false when
+// the particle was removed (class in dead, last cell occupied in ei, ej).
+__device__ __forceinline__ bool push_core(const PK &a, float x0, float y0, float vx0, float vy0,
+                                          float4 ea, float4 eb, int ci, int cj, int &dead, int &ei,
+                                          int &ej, float &ux, float &uy, float &nxo, float &nyo)
 {
     const Geom &g = a.g;
     const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
@@ -983,8 +1002,6 @@ __device__ __forceinline__ bool push_particle(const PK &a, int p, int c, float &
     const float Dx = ux * a.dtf, Dy = uy * a.dtf;
     const float x1 = x0 + Dx, y1 = y0 + Dy;
     const float fsx = floorf(x1), fsy = floorf(y1);
-    a.vx[p] = ux;
-    a.vy[p] = uy;
     dead = -1;
     ei = ci;
     ej = cj;
@@ -1026,13 +1043,31 @@ __device__ __forceinline__ bool push_particle(const PK &a, int p, int c, float &
             }
         }
     }
-    if (dead >= 0) {
+    nxo = x0;
+    nyo = y0;
+    if (dead >= 0) return false;
+    nxo = x1 - (float)sx;
+    nyo = y1 - (float)sy;
+    if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
+    if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
+    return true;
+}
+
+// push_core plus the particle's stores (velocity always; offsets if it
+// stays; the cell code when it changes or the particle is removed).
+__device__ __forceinline__ bool push_particle(const PK &a, int p, int c, float &x0, float &y0,
+                                              float vx0, float vy0, float4 ea, float4 eb, int &ci,
+                                              int &cj, int &dead, int &ei, int &ej, float &ux,
+                                              float &uy)
+{
+    float nxo, nyo;
+    const bool alive = push_core(a, x0, y0, vx0, vy0, ea, eb, ci, cj, dead, ei, ej, ux, uy, nxo, nyo);
+    a.vx[p] = ux;
+    a.vy[p] = uy;
+    if (!alive) {
         a.cell[p] = -1 - dead;
         return false;
     }
-    float nxo = x1 - (float)sx, nyo = y1 - (float)sy;
-    if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
-    if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
     a.ox[p] = nxo;
     a.oy[p] = nyo;
     const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
@@ -1049,7 +1084,7 @@ __device__ __forceinline__ void record_hit(const PK &a, unsigned *tl, int dead, 
                                            float ux, float uy)
 {
     atomicAdd(&tl[dead], 1u);
-    if (a.surf && dead == 4) atomicAdd(&a.surf[ej], 1ull);
+    if (a.surf && dead == 4) gatomic_add(&a.surf[ej], 1ull);
     if (a.log.rec && ((a.log.species_mask >> a.species) & 1)) {
         unsigned long long k = atomicAdd(a.log.count, 1ull);
         long long slot = (long long)(k % (unsigned long long)a.log.capacity);
@@ -1060,6 +1095,105 @@ __device__ __forceinline__ void record_hit(const PK &a, unsigned *tl, int dead, 
         r[3] = __float_as_int(uy);
         r[4] = (int)a.step[0];
         r[5] = 0;
+    }
+}
+
+// Streaming (non-temporal) 16-byte particle loads and stores: each slot is
+// read and written once per step, so they need not displace the field and
+// charge arrays from the caches.
+__device__ __forceinline__ nt_i4 ld_nt_i4(GLOBAL const int32_t *p)
+{
+    return __builtin_nontemporal_load((GLOBAL const nt_i4 *)p);
+}
+__device__ __forceinline__ nt_f4 ld_nt_f4(GLOBAL const float *p)
+{
+    return __builtin_nontemporal_load((GLOBAL const nt_f4 *)p);
+}
+__device__ __forceinline__ void st_nt_f4(GLOBAL float *p, float a, float b, float c, float d)
+{
+    nt_f4 v = {a, b, c, d};
+    __builtin_nontemporal_store(v, (GLOBAL nt_f4 *)p);
+}
+
+// Corner fields of the particle's cell (packed code c >= 0): from the
+// block's LDS copy of the tile + 1-cell frame (origin e0i, e0j; EW x EH
+// cells), or from global memory for a particle that left the frame.
+__device__ __forceinline__ void cell_fields(const PK &a, const float4 *sE, int e0i, int e0j, int EW,
+                                            int EH, int c, float4 &ea, float4 &eb)
+{
+    const Geom &g = a.g;
+    const int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
+    int li = ci - e0i, lj = cj - e0j;
+    if (g.px) { if (li < 0) li += g.nx; else if (li >= g.nx) li -= g.nx; }
+    if (g.py) { if (lj < 0) lj += g.ny; else if (lj >= g.ny) lj -= g.ny; }
+    if (li >= 0 && li < EW && lj >= 0 && lj < EH) {
+        const int m = 2 * (li * EH + lj);
+        ea = sE[m];
+        eb = sE[m + 1];
+    } else {
+        const long long cc = (long long)ci * g.ny + cj;
+        ea = ld_f4(a.E4 + 2 * cc);
+        eb = ld_f4(a.E4 + 2 * cc + 1);
+    }
+}
+
+// Area weighting of one lane's particle (alive, in cell (ci, cj) at offsets
+// (x0, y0)) into the block's LDS window of cell moments, or straight into the
+// node charge when it lies outside the window.  Called by every lane of the
+// wavefront (the merge of equal cells is wavefront-wide).
+template <int MERGE>
+__device__ __forceinline__ void deposit_lane(const PK &a, unsigned long long *mA, unsigned long long *mB,
+                                             int lane, bool alive, int ci, int cj, float x0, float y0,
+                                             int i0, int j0, int WX, int WY, unsigned long long &nfb)
+{
+    const Geom &g = a.g;
+    int key = -1;
+    unsigned ux = 0, uy = 0;
+    if (alive) {
+        ux = (unsigned)floorf(x0 * 65536.0f);
+        uy = (unsigned)floorf(y0 * 65536.0f);
+        int wi = ci - i0, wj = cj - j0;
+        if (g.px) { if (wi < 0) wi += g.nx; else if (wi >= g.nx) wi -= g.nx; }
+        if (g.py) { if (wj < 0) wj += g.ny; else if (wj >= g.ny) wj -= g.ny; }
+        if (wi >= 0 && wi < WX && wj >= 0 && wj < WY) {
+            key = wi * WY + wj;
+        } else {
+            const unsigned long long S = 65536ull;
+            const int i1 = g.px ? wrap_hi(ci + 1, g.nx) : ci + 1;
+            const int j1 = g.py ? wrap_hi(cj + 1, g.ny) : cj + 1;
+            const unsigned long long X = ux, Y = uy;
+            gatomic_add(&a.rho[(long long)ci * g.NY + cj], (S - X) * (S - Y));
+            gatomic_add(&a.rho[(long long)i1 * g.NY + cj], X * (S - Y));
+            gatomic_add(&a.rho[(long long)ci * g.NY + j1], (S - X) * Y);
+            gatomic_add(&a.rho[(long long)i1 * g.NY + j1], X * Y);
+            nfb++;
+        }
+    }
+    // wavefront merge of equal cells (all lanes take part)
+    const unsigned m3 = ux * uy;
+    if (MERGE > 0) {
+        unsigned long long pend = __ballot(key >= 0);
+        for (int it = 0; it < MERGE && pend; it++) {
+            const int leader = __builtin_ctzll(pend);
+            const int lk = __builtin_amdgcn_readlane(key, leader);
+            const bool m = key == lk;
+            const unsigned long long mask = __ballot(m);
+            unsigned sx = m ? ux : 0u, sy = m ? uy : 0u;
+            unsigned sh = m ? (m3 >> 16) : 0u, sl = m ? (m3 & 0xFFFFu) : 0u;
+            wave_sum4_u32(sx, sy, sh, sl);
+            if (lane == leader) {
+                const unsigned long long cnt = (unsigned long long)__popcll(mask);
+                const unsigned long long s3 = ((unsigned long long)sh << 16) + sl;
+                atomicAdd(&mA[lk], (cnt << 45) + s3);
+                atomicAdd(&mB[lk], (unsigned long long)sx | ((unsigned long long)sy << 29));
+            }
+            if (m) key = -1;
+            pend &= ~mask;
+        }
+    }
+    if (key >= 0) {
+        atomicAdd(&mA[key], (1ull << 45) + (unsigned long long)m3);
+        atomicAdd(&mB[key], (unsigned long long)ux | ((unsigned long long)uy << 29));
     }
 }
 
@@ -1092,17 +1226,126 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
     unsigned long long *mA = (unsigned long long *)smem;
     unsigned long long *mB = mA + WC;
     unsigned *tl = (unsigned *)(mB + WC);
+    // corner fields of the tile + 1-cell frame
+    float4 *sE = (float4 *)(smem + (((size_t)WC * 16 + kNClass * 4 + 15) & ~(size_t)15));
+    const int EW = a.TX + 2, EH = a.TY + 2;
+    const int e0i = ti * a.TX - 1, e0j = tj * a.TY - 1;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const Geom g = a.g;
     for (int k = tid; k < WC; k += kPushThreads) {
         mA[k] = 0ull;
         mB[k] = 0ull;
     }
     if (tid < kNClass) tl[tid] = 0u;
+    if (PUSH) {
+        for (int k = tid; k < 2 * EW * EH; k += kPushThreads) {
+            const int m = k >> 1, li = m / EH, lj = m - li * EH;
+            int ci = e0i + li, cj = e0j + lj;
+            if (g.px) ci = wrap_hi(wrap_lo(ci, g.nx), g.nx);
+            if (g.py) cj = wrap_hi(wrap_lo(cj, g.ny), g.ny);
+            if (ci >= 0 && ci < g.nx && cj >= 0 && cj < g.ny)
+                sE[k] = ld_f4(a.E4 + 2 * ((long long)ci * g.ny + cj) + (k & 1));
+        }
+    }
     __syncthreads();
 
-    const Geom g = a.g;
     unsigned long long nfb = 0;
+    if constexpr (U == 4) {
+        // 4 consecutive particles per thread per pass, moved with 16-byte
+        // loads and stores where the 4 slots lie inside [start, end) (the
+        // head and tail of the range go element by element).  Slots of
+        // removed particles in a full vector are written back unchanged.
+        for (int vb = start & ~3; vb < end; vb += 4 * kPushThreads) {
+            const int v = vb + 4 * tid;
+            const bool full = v >= start && v + 4 <= end;
+            int cv[4];
+            float xv[4], yv[4], uxv[4], uyv[4];
+            if (full) {
+                const nt_i4 c4 = ld_nt_i4(a.cell + v);
+                const nt_f4 x4 = ld_nt_f4(a.ox + v), y4 = ld_nt_f4(a.oy + v);
+                cv[0] = c4.x; cv[1] = c4.y; cv[2] = c4.z; cv[3] = c4.w;
+                xv[0] = x4.x; xv[1] = x4.y; xv[2] = x4.z; xv[3] = x4.w;
+                yv[0] = y4.x; yv[1] = y4.y; yv[2] = y4.z; yv[3] = y4.w;
+                if (PUSH) {
+                    const nt_f4 u4 = ld_nt_f4(a.vx + v), w4 = ld_nt_f4(a.vy + v);
+                    uxv[0] = u4.x; uxv[1] = u4.y; uxv[2] = u4.z; uxv[3] = u4.w;
+                    uyv[0] = w4.x; uyv[1] = w4.y; uyv[2] = w4.z; uyv[3] = w4.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int p = v + k;
+                    const bool in = p >= start && p < end;
+                    cv[k] = in ? a.cell[p] : -1;
+                    xv[k] = in ? a.ox[p] : 0.f;
+                    yv[k] = in ? a.oy[p] : 0.f;
+                    uxv[k] = (PUSH && in) ? a.vx[p] : 0.f;
+                    uyv[k] = (PUSH && in) ? a.vy[p] : 0.f;
+                }
+            }
+            float4 eav[4], ebv[4];
+            if (PUSH) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    eav[k] = ebv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (cv[k] >= 0) cell_fields(a, sE, e0i, e0j, EW, EH, cv[k], eav[k], ebv[k]);
+                }
+            }
+            bool alv[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int c = cv[k];
+                bool alive = false;
+                int ci = 0, cj = 0;
+                if (c >= 0) {
+                    ci = (int)((unsigned)c >> 16);
+                    cj = c & 0xFFFF;
+                    alive = true;
+                    if (PUSH) {
+                        int dead, ei, ej;
+                        float ux, uy, nxo, nyo;
+                        alive = push_core(a, xv[k], yv[k], uxv[k], uyv[k], eav[k], ebv[k], ci, cj, dead,
+                                          ei, ej, ux, uy, nxo, nyo);
+                        uxv[k] = ux;
+                        uyv[k] = uy;
+                        if (!alive) {
+                            a.cell[v + k] = -1 - dead;
+                            record_hit(a, tl, dead, ei, ej, ux, uy);
+                        } else {
+                            const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
+                            if (nc != c) a.cell[v + k] = nc;
+                            xv[k] = nxo;
+                            yv[k] = nyo;
+                            ci = ei;
+                            cj = ej;
+                        }
+                    }
+                }
+                alv[k] = alive;
+                deposit_lane<MERGE>(a, mA, mB, lane, alive, ci, cj, xv[k], yv[k], i0, j0, WX, WY, nfb);
+            }
+            if (PUSH) {
+                if (full) {
+                    st_nt_f4(a.vx + v, uxv[0], uxv[1], uxv[2], uxv[3]);
+                    st_nt_f4(a.vy + v, uyv[0], uyv[1], uyv[2], uyv[3]);
+                    st_nt_f4(a.ox + v, xv[0], xv[1], xv[2], xv[3]);
+                    st_nt_f4(a.oy + v, yv[0], yv[1], yv[2], yv[3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        if (cv[k] < 0) continue;          // outside the range, or removed earlier
+                        a.vx[v + k] = uxv[k];
+                        a.vy[v + k] = uyv[k];
+                        if (alv[k]) {
+                            a.ox[v + k] = xv[k];
+                            a.oy[v + k] = yv[k];
+                        }
+                    }
+                }
+            }
+        }
+    } else
     // U particles per thread per pass: all their loads are issued
     // before any is used, so each wave keeps several requests in flight.
     // The loop bound is uniform per block so whole wavefronts stay active.
@@ -1130,22 +1373,23 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
         if (PUSH) {
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                const int c = cu[u] < 0 ? 0 : cu[u];
-                const long long cc = (long long)((unsigned)c >> 16) * g.ny + (c & 0xFFFF);
-                eau[u] = a.E4[2 * cc];
-                ebu[u] = a.E4[2 * cc + 1];
+                eau[u] = ebu[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (cu[u] >= 0) cell_fields(a, sE, e0i, e0j, EW, EH, cu[u], eau[u], ebu[u]);
             }
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int p = base + u * kPushThreads + tid;
             int c = cu[u];
-            int key = -1;
-            unsigned ux = 0, uy = 0;
+            bool alive = false;
+            float x0 = 0.f, y0 = 0.f;
+            int ci = 0, cj = 0;
             if (c >= 0) {
-                float x0 = xu[u], y0 = yu[u];
-                int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
-                bool alive = true;
+                x0 = xu[u];
+                y0 = yu[u];
+                ci = (int)((unsigned)c >> 16);
+                cj = c & 0xFFFF;
+                alive = true;
                 if (PUSH) {
                     int dead, ei, ej;
                     float vnx, vny;
@@ -1153,53 +1397,8 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
                                           dead, ei, ej, vnx, vny);
                     if (!alive) record_hit(a, tl, dead, ei, ej, vnx, vny);
                 }
-                if (alive) {
-                    ux = (unsigned)floorf(x0 * 65536.0f);
-                    uy = (unsigned)floorf(y0 * 65536.0f);
-                    int wi = ci - i0, wj = cj - j0;
-                    if (g.px) { if (wi < 0) wi += g.nx; else if (wi >= g.nx) wi -= g.nx; }
-                    if (g.py) { if (wj < 0) wj += g.ny; else if (wj >= g.ny) wj -= g.ny; }
-                    if (wi >= 0 && wi < WX && wj >= 0 && wj < WY) {
-                        key = wi * WY + wj;
-                    } else {
-                        const unsigned long long S = 65536ull;
-                        const int i1 = g.px ? wrap_hi(ci + 1, g.nx) : ci + 1;
-                        const int j1 = g.py ? wrap_hi(cj + 1, g.ny) : cj + 1;
-                        const unsigned long long X = ux, Y = uy;
-                        atomicAdd(&a.rho[(long long)ci * g.NY + cj], (S - X) * (S - Y));
-                        atomicAdd(&a.rho[(long long)i1 * g.NY + cj], X * (S - Y));
-                        atomicAdd(&a.rho[(long long)ci * g.NY + j1], (S - X) * Y);
-                        atomicAdd(&a.rho[(long long)i1 * g.NY + j1], X * Y);
-                        nfb++;
-                    }
-                }
             }
-            // wavefront merge of equal cells (all lanes take part)
-            const unsigned m3 = ux * uy;
-            if (MERGE > 0) {
-                unsigned long long pend = __ballot(key >= 0);
-                for (int it = 0; it < MERGE && pend; it++) {
-                    const int leader = __builtin_ctzll(pend);
-                    const int lk = __builtin_amdgcn_readlane(key, leader);
-                    const bool m = key == lk;
-                    const unsigned long long mask = __ballot(m);
-                    unsigned sx = m ? ux : 0u, sy = m ? uy : 0u;
-                    unsigned sh = m ? (m3 >> 16) : 0u, sl = m ? (m3 & 0xFFFFu) : 0u;
-                    wave_sum4_u32(sx, sy, sh, sl);
-                    if (lane == leader) {
-                        const unsigned long long cnt = (unsigned long long)__popcll(mask);
-                        const unsigned long long s3 = ((unsigned long long)sh << 16) + sl;
-                        atomicAdd(&mA[lk], (cnt << 45) + s3);
-                        atomicAdd(&mB[lk], (unsigned long long)sx | ((unsigned long long)sy << 29));
-                    }
-                    if (m) key = -1;
-                    pend &= ~mask;
-                }
-            }
-            if (key >= 0) {
-                atomicAdd(&mA[key], (1ull << 45) + (unsigned long long)m3);
-                atomicAdd(&mB[key], (unsigned long long)ux | ((unsigned long long)uy << 29));
-            }
+            deposit_lane<MERGE>(a, mA, mB, lane, alive, ci, cj, x0, y0, i0, j0, WX, WY, nfb);
         }
     }
     if (nfb) atomicAdd(fallbacks, nfb);
@@ -1233,7 +1432,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
         else if (gi < 0 || gi >= g.NX) continue;
         if (g.py) { gj = ((gj % g.NY) + g.NY) % g.NY; }
         else if (gj < 0 || gj >= g.NY) continue;
-        atomicAdd(&a.rho[(long long)gi * g.NY + gj], v);
+        gatomic_add(&a.rho[(long long)gi * g.NY + gj], v);
     }
     if (PUSH && tid < kNClass && tl[tid]) atomicAdd(&tally[tid], (unsigned long long)tl[tid]);
 }
@@ -1275,7 +1474,7 @@ __global__ void k_rewind(const PushArgs *A, Tab t)
     if (c < 0) return;
     const int ci = (int)((unsigned)c >> 16), cj = c & 0xFFFF;
     const long long cc = (long long)ci * a.g.ny + cj;
-    const float4 ea = a.E4[2 * cc], eb = a.E4[2 * cc + 1];
+    const float4 ea = ld_f4(a.E4 + 2 * cc), eb = ld_f4(a.E4 + 2 * cc + 1);
     const float x0 = a.ox[p], y0 = a.oy[p];
     const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
     const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;

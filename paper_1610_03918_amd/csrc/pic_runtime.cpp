@@ -79,8 +79,7 @@ std::string validate(const pic_config *c, const int64_t *cap)
         return "push_unroll must be 0 (default), 1, 2 or 4";
     if (c->push_merge != 0 && c->push_merge != 2 && c->push_merge != 4)
         return "push_merge must be 0, 2 or 4";
-    size_t lds = (size_t)(tx + 2 * H) * (ty + 2 * H) * 16 + 64;
-    if (lds > 64 * 1024) return "tile + halo window exceeds 64 KiB of LDS";
+    if (push_lds_bytes(tx, ty, H) > 64 * 1024) return "tile + halo window exceeds 64 KiB of LDS";
     if (cap && (cap[0] < 0 || cap[1] < 0 || cap[0] > 0x7fffffffLL || cap[1] > 0x7fffffffLL))
         return "capacity out of range";
     if (c->hitlog_capacity < 0) return "hitlog_capacity must be >= 0";
@@ -160,7 +159,7 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
     L.ntiles = L.tiles_x * L.tiles_y;
     L.H = c->halo ? c->halo : 4;
     L.chunk = c->chunk ? c->chunk : 8192;
-    L.unroll = c->push_unroll ? c->push_unroll : 2;
+    L.unroll = c->push_unroll ? c->push_unroll : 4;
     L.merge = c->push_merge;
     for (int s = 0; s < 2; s++) L.max_blocks[s] = L.ntiles + (cap[s] + L.chunk - 1) / L.chunk;
     int maxrows = std::max(L.NX, L.nx), maxcols = std::max(L.NY, L.ny);
@@ -947,8 +946,7 @@ void build_tabs(pic_ctx *c)
             tab_add(c->t_push, 2 * k + s, (int)L.max_blocks[s]);
             tab_add(c->t_rewind, 2 * k + s, (int)((h.slots_ub[s] + 255) / 256));
         }
-        const size_t lds = (size_t)(L.TX + 2 * L.H) * (L.TY + 2 * L.H) * 16 + kNClass * 4 + 16;
-        c->push_lds = std::max(c->push_lds, lds);
+        c->push_lds = std::max(c->push_lds, push_lds_bytes(L.TX, L.TY, L.H));
     }
     c->unroll = c->in[0].L.unroll;
     c->merge = c->in[0].L.merge;

@@ -135,7 +135,7 @@ class PicError(RuntimeError):
 
 
 def make_config(w, *, solver=0, max_iter=2000, sort_interval=(8, 64), tile=(16, 16), halo=4,
-                chunk=4096, push_unroll=2, push_merge=0, hitlog_capacity=0,
+                chunk=4096, push_unroll=4, push_merge=0, hitlog_capacity=0,
                 hitlog_species_mask=2, rtol=None, warm_start=1):
     """pic_config from a workload description (see synth.Workload)."""
     cc = np.ascontiguousarray(w.cell_cond, dtype=np.uint8)
