@@ -263,6 +263,8 @@ def main():
     ap.add_argument("--halo", type=int, default=4)
     ap.add_argument("--warm", type=int, default=1, help="0 previous phi, 1 extrapolated")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
+    ap.add_argument("--no-autotuned", action="store_true",
+                    help="ignore a cached autotuned schedule for the workload")
     ap.add_argument("--autotune", action="store_true",
                     help="sweep: tune the schedule when the cache has no entry for the batch")
     ap.add_argument("--learn-snapshots", type=int, default=128)
@@ -290,6 +292,17 @@ def main():
     parts = synth.load(w)
     n0 = [p["cell"].size for p in parts]
     log(f"loaded {n0} particles in {time.perf_counter() - t:.1f}s")
+    from paper_1610_03918_amd import autotune
+    entry = None if args.no_autotuned else autotune.lookup([w], parts)
+    if entry is not None:
+        sch = entry["schedule"]
+        args.sort = ",".join(str(x) for x in sch["sort_interval"])
+        args.tile = ",".join(str(x) for x in sch["tile"])
+        args.unroll, args.merge, args.chunk, args.halo = (sch["push_unroll"], sch["push_merge"],
+                                                          sch["chunk"], sch["halo"])
+        schedule_source = f"autotuned (cache key {autotune.signature([w], parts)})"
+    else:
+        schedule_source = "command line"
     sort = tuple(int(x) for x in args.sort.split(","))
     tile = tuple(int(x) for x in args.tile.split(","))
     opts = dict(sort_interval=sort, push_unroll=args.unroll, push_merge=args.merge, tile=tile,
@@ -342,7 +355,8 @@ def main():
         "config": {"workload": w.name, "cells": [w.nx, w.ny], "ppc": w.species[0].ppc,
                    "particles": n0, "dt": w.dt, "rtol": w.rtol, "sort_interval": list(sort),
                    "tile": list(tile), "chunk": args.chunk, "halo": args.halo,
-                   "push_unroll": args.unroll, "push_merge": args.merge, "warm_start": args.warm},
+                   "push_unroll": args.unroll, "push_merge": args.merge, "warm_start": args.warm,
+                   "schedule_source": schedule_source},
         "poisson_ms_per_step": 1e3 * solve_t / args.steps,
         "poisson_iters_per_step": iters / args.steps,
         "poisson_start_relres_median": float(np.median(r0)),

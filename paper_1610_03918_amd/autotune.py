@@ -146,10 +146,11 @@ def main():
     import synth
     ap = argparse.ArgumentParser()
     ap.add_argument("--sweep", action="store_true", help="the 16-width trench sweep (default)")
+    ap.add_argument("--trench", action="store_true", help="the single 1024 x 512 trench instead")
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--out", default=CACHE)
     args = ap.parse_args()
-    ws = synth.sweep()
+    ws = [synth.trench()] if args.trench else synth.sweep()
     parts = [synth.load(w) for w in ws]
     entry = tune(ws, parts, steps=args.steps, log=lambda m: print(m, flush=True), path=args.out)
     print(json.dumps({k: v for k, v in entry.items() if k != "trials"}), flush=True)

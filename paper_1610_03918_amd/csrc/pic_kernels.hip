@@ -836,17 +836,37 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
         }
         __syncthreads();
     }
-    // coarsest: red-black sweeps (first black completes the pre-smoothing)
+    // coarsest: red-black sweeps (first black completes the pre-smoothing).
+    // A level of at most 64 nodes is swept by the first wavefront alone: its
+    // lanes run in lockstep and LDS serves one wavefront's accesses in
+    // order, so a wavefront barrier separates the colours.
     {
         const int l = a.nlev - 1, NX = a.NX[l], NY = a.NY[l], N = NX * NY;
-        for (int sw = 0; sw < a.sweeps; sw++) {
-            for (int col = 1; col >= 0; col--) {
-                for (int k = tid; k < N; k += nt) {
-                    int i = k / NY, j = k - i * NY;
-                    if (!fx(l)[k] && ((i + j) & 1) == col)
-                        u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+        if (N <= 64) {
+            if (tid < 64) {
+                const int k = tid;
+                const int i = k / NY, j = k - i * NY;
+                const bool mine = k < N && !fx(l)[k];
+                for (int sw = 0; sw < a.sweeps; sw++) {
+                    for (int col = 1; col >= 0; col--) {
+                        if (mine && ((i + j) & 1) == col) u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
                 }
-                __syncthreads();
+            }
+            __syncthreads();
+        } else {
+            for (int sw = 0; sw < a.sweeps; sw++) {
+                for (int col = 1; col >= 0; col--) {
+                    for (int k = tid; k < N; k += nt) {
+                        int i = k / NY, j = k - i * NY;
+                        if (!fx(l)[k] && ((i + j) & 1) == col)
+                            u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+                    }
+                    __syncthreads();
+                }
             }
         }
     }
@@ -877,7 +897,13 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
 
 void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s)
 {
-    if (t.n) hipLaunchKernelGGL(k_coarse, dim3(t.n), dim3(1024), lds_bytes, s, I, t);
+    if (!t.n) return;
+    static int allowed = 64 * 1024;
+    if (lds_bytes > allowed) {
+        (void)hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        allowed = lds_bytes;
+    }
+    hipLaunchKernelGGL(k_coarse, dim3(t.n), dim3(1024), lds_bytes, s, I, t);
 }
 
 // ---------------------------------------------------------------------------

@@ -240,7 +240,7 @@ struct pic_ctx {
     int unroll = 2, merge = 0;
     // solver control
     bool have_prev = false;
-    int inner_chunk = 12;
+    int pass_chunk[2] = {12, 12};   // inner iterations per pass (first pass, later passes)
     // graphs
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> outer_graphs;
@@ -515,14 +515,6 @@ void enqueue_pass(pic_ctx *c, int K, hipStream_t s)
     enqueue_pass_end(c, s);
 }
 
-int round_chunk(int k)
-{
-    static const int steps[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128};
-    for (int v : steps)
-        if (k <= v) return v;
-    return k;
-}
-
 pic_status capture_begin(pic_ctx *c)
 {
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -641,7 +633,8 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess)
             most = std::max(most, f[F_ITER_TOT]);
         }
         if (all || !finite || most >= max_iter) break;
-        int K = round_chunk(std::max(1, std::min(c->inner_chunk, max_iter - most)));
+        int &chunk = c->pass_chunk[std::min(pass, 1)];
+        int K = std::max(1, std::min(std::min(chunk, 128), max_iter - most));
         if (plain_cg) {
             // Unpreconditioned CG needs long uninterrupted inner runs: continue
             // the pass's CG in graph chunks until its stop test, then update.
@@ -677,7 +670,9 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess)
             need = std::max(need, f[F_ITER]);
             if (!f[F_DONE]) unfinished = true;
         }
-        c->inner_chunk = unfinished ? std::min(2 * K, 128) : std::max(2, need + 1);
+        // next solve: the iterations this pass needed (passes differ: the
+        // first starts far from the tolerance), doubled when it ran short
+        chunk = unfinished ? std::min(2 * K, 128) : std::max(1, need);
     }
     launch_shift_mean(c->d_inst, c->t_per, part_of(c), c->stream);
     record_solve_info(c, S, F);
