@@ -54,7 +54,8 @@ enum {
 
 struct LevelDev {
     int NX, NY;
-    float *u;          // correction (level 0: z)
+    float *u;          // correction (level 0: z at the start of the V-cycle)
+    float *uo;         // result of the level's up half-cycle (fine levels; = u on LDS levels)
     float *g;          // right-hand side (level 0: r)
     const uint8_t *fix;
 };
@@ -63,6 +64,7 @@ struct CoarseArgs {
     int nlev;                      // levels handled in LDS
     int NX[kMaxLev], NY[kMaxLev];
     int off_u[kMaxLev], off_g[kMaxLev], off_f[kMaxLev]; // LDS byte offsets
+    int off_s;                     // LDS scratch of the largest level (float per node)
     const uint8_t *fix[kMaxLev];   // global masks of those levels
     float *u_top;                  // global u of the first LDS level (output)
     const float *g_top;            // global g of the first LDS level (input)
@@ -80,6 +82,7 @@ struct Inst {
     double *phi, *b, *phi_prev;
     unsigned long long *rho[2];
     float *e, *p[2], *q;
+    float *z;                      // preconditioned residual of the CG (level-0 uo with MG, else u)
     float4 *E4;
     double *S;
     int *F;
@@ -172,11 +175,11 @@ void launch_phi_update(const Inst *I, const Tab &t, hipStream_t s);
 void launch_init_red0(const Inst *I, const Tab &t, Part pt, hipStream_t s);
 void launch_pupdate_Ap(const Inst *I, const Tab &t, int kold, int first, Part pt, hipStream_t s);
 void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStream_t s);
-void launch_smooth(const Inst *I, const Tab &t, int level, int color, int level0_rz, Part pt,
-                   hipStream_t s);
-void launch_restrict(const Inst *I, const Tab &t, int level, hipStream_t s);
-void launch_prolong_black(const Inst *I, const Tab &t, int level, hipStream_t s);
 void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s);
+// fused fine-level V-cycle halves (tables of 32 x 32 tiles of level l)
+constexpr int kMgTileHost = 32;
+void launch_mg_down(const Inst *I, const Tab &t, int level, hipStream_t s);
+void launch_mg_up(const Inst *I, const Tab &t, int level, int level0_rz, Part pt, hipStream_t s);
 void launch_push(const PushArgs *A, const Tab &t, bool push, int unroll, int merge, size_t lds,
                  hipStream_t s);
 void launch_rewind(const PushArgs *A, const Tab &t, hipStream_t s);

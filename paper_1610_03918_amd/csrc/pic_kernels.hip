@@ -504,64 +504,6 @@ __device__ __forceinline__ Nb nbs(int i, int j, int NX, int NY)
     return r;
 }
 
-// Gauss-Seidel value of a free node from its neighbours.
-__device__ __forceinline__ float gs_value(const float *u, const float *gg, const uint8_t *fix,
-                                          int i, int j, int NX, int NY)
-{
-    Nb b = nbs(i, j, NX, NY);
-    long long a = (long long)b.im * NY + j, c = (long long)b.ip * NY + j;
-    long long d = (long long)i * NY + b.jm, e = (long long)i * NY + b.jp;
-    float s = gg[(long long)i * NY + j];
-    if (!fix[a]) s += u[a];
-    if (!fix[c]) s += u[c];
-    if (!fix[d]) s += u[d];
-    if (!fix[e]) s += u[e];
-    return s * 0.25f;
-}
-
-// Residual g - A u at a free fine node.
-__device__ __forceinline__ float node_resid(const float *u, const float *gg, const uint8_t *fix,
-                                            int i, int j, int NX, int NY)
-{
-    Nb b = nbs(i, j, NX, NY);
-    long long n = (long long)i * NY + j;
-    long long a = (long long)b.im * NY + j, c = (long long)b.ip * NY + j;
-    long long d = (long long)i * NY + b.jm, e = (long long)i * NY + b.jp;
-    float s = 4.0f * u[n];
-    if (!fix[a]) s -= u[a];
-    if (!fix[c]) s -= u[c];
-    if (!fix[d]) s -= u[d];
-    if (!fix[e]) s -= u[e];
-    return gg[n] - s;
-}
-
-// Restricted residual at coarse node (I, J): sum over the 3x3 fine stencil
-// around (2I, 2J) of weight * residual at free fine nodes.  It is always
-// taken right after a black half-sweep, which leaves zero residual on the
-// black nodes (the four edge neighbours, weight 1/2), so only the red ones
-// are evaluated: the centre (weight 1) and the four diagonals (weight 1/4).
-__device__ __forceinline__ float restrict_node(const float *u, const float *gg, const uint8_t *fix,
-                                               int NX, int NY, int px, int py, int I, int J)
-{
-    float acc = 0.0f;
-#pragma unroll
-    for (int di = -1; di <= 1; di++) {
-#pragma unroll
-        for (int dj = -1; dj <= 1; dj++) {
-            if ((di + dj) & 1) continue;
-            int a = 2 * I + di, c = 2 * J + dj;
-            if (px) a = wrap_hi(wrap_lo(a, NX), NX);
-            else if (a < 0 || a >= NX) continue;
-            if (py) c = wrap_hi(wrap_lo(c, NY), NY);
-            else if (c < 0 || c >= NY) continue;
-            if (fix[(long long)a * NY + c]) continue;
-            const float w = (di == 0) ? 1.0f : 0.25f;
-            acc += w * node_resid(u, gg, fix, a, c, NX, NY);
-        }
-    }
-    return acc;
-}
-
 // Bilinear prolongation of the coarse correction e at a red fine node
 // (both indices even: coincident node; both odd: cell centre).
 __device__ __forceinline__ float prolong_red(const float *e, int NXc, int NYc, int a, int c)
@@ -571,24 +513,6 @@ __device__ __forceinline__ float prolong_red(const float *e, int NXc, int NYc, i
     int I1 = wrap_hi(I + 1, NXc), J1 = wrap_hi(J + 1, NYc);
     return 0.25f * (e[(long long)I * NYc + J] + e[(long long)I1 * NYc + J] +
                     e[(long long)I * NYc + J1] + e[(long long)I1 * NYc + J1]);
-}
-
-// Post-smoothing black update after the coarse correction: the red
-// neighbours enter with their correction, black values are overwritten.
-__device__ __forceinline__ float prolong_black_value(const float *u, const float *gg,
-                                                     const uint8_t *fix, const float *e, int NX,
-                                                     int NY, int NXc, int NYc, int i, int j)
-{
-    Nb b = nbs(i, j, NX, NY);
-    int ni[4] = {b.im, b.ip, i, i};
-    int nj[4] = {j, j, b.jm, b.jp};
-    float s = gg[(long long)i * NY + j];
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        long long m = (long long)ni[k] * NY + nj[k];
-        if (!fix[m]) s += u[m] + prolong_red(e, NXc, NYc, ni[k], nj[k]);
-    }
-    return s * 0.25f;
 }
 
 // ---------------------------------------------------------------------------
@@ -647,12 +571,13 @@ __global__ void k_pupdate_Ap(const Inst *insts, Tab t, int kold, int first, Part
             Nb b = nbs(i, j, NX, NY);
             const long long m[4] = {(long long)b.im * NY + j, (long long)b.ip * NY + j,
                                     (long long)i * NY + b.jm, (long long)i * NY + b.jp};
-            const float pc = first ? L.u[n] : L.u[n] + beta * p_old[n];
+            const float *z = I.z;
+            const float pc = first ? z[n] : z[n] + beta * p_old[n];
             float s = 4.0f * pc;
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 if (L.fix[m[k]]) continue;
-                const float pn = first ? L.u[m[k]] : L.u[m[k]] + beta * p_old[m[k]];
+                const float pn = first ? z[m[k]] : z[m[k]] + beta * p_old[m[k]];
                 s -= pn;
             }
             p_new[n] = pc;
@@ -707,81 +632,241 @@ void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStrea
     finalize(I, t, pt, OP_UPDATE, s);
 }
 
-// One colour of red-black Gauss-Seidel on a level.  On level 0 with
-// level0_rz the kernel also forms r.z (after the final red sweep of the
-// V-cycle); the finalize rotates rz -> rz_old.
-__global__ void k_smooth(const Inst *insts, Tab t, int level, int color, int level0_rz, Part pt)
+// ---------------------------------------------------------------------------
+// fused V-cycle kernels for the fine levels, one block per 32 x 32 tile of the
+// fine level (launch table: tiles, bx = tiles across y).  Each block stages a
+// window of u, g and the mask around its tile in LDS (periodic axes wrap, nodes
+// outside a bounded axis enter as fixed), recomputes in the window what it
+// needs, and writes only its own tile (or its own coarse nodes).
+//   down: black half-sweep on level l, then restriction to level l + 1
+//   up:   black update with the prolonged coarse correction, then the red
+//         half-sweep (on level 0 also the r.z partials of the CG)
+// Arithmetic per node: Gauss-Seidel value (g + neighbours) / 4 with the
+// neighbours added in the order x-1, x+1, y-1, y+1; restriction = sum over
+// the red fine nodes of the 3 x 3 stencil of weight x residual (centre 1,
+// diagonals 1/4; the black residuals vanish after the black half-sweep);
+// bilinear prolongation of the coarse correction onto the red nodes.
+// ---------------------------------------------------------------------------
+
+constexpr int kMgTile = 32;
+constexpr int kMgThreads = 256;
+constexpr int kDnW = kMgTile + 5;   // down window: tile rows i0-3 .. i0+33
+constexpr int kUpW = kMgTile + 4;   // up window: tile rows i0-2 .. i0+33
+
+__device__ __forceinline__ int wrap_any(int x, int n) { return ((x % n) + n) % n; }
+
+// Stages u, g, fix of the W x W window with origin (wi0, wj0) on level L.
+// Fixed nodes hold u = 0 on every level (no update ever writes them), so
+// the stencils below add neighbours without testing their mask; all loads
+// of a thread are issued before the LDS stores.
+template <int W>
+__device__ __forceinline__ void mg_stage(const LevelDev &L, int px, int py, int wi0, int wj0,
+                                         float *su, float *sg, uint8_t *sf)
 {
-    GRID_BEGIN(t)
-    if (I.F[F_DONE]) return;
-    const LevelDev L = I.lev[level];
-    NODE_IDX(L.NX, L.NY)
-    double rz = 0.0;
-    if (inb && !L.fix[n]) {
-        float z;
-        if (((i + j) & 1) == color) {
-            z = gs_value(L.u, L.g, L.fix, i, j, NX, NY);
-            L.u[n] = z;
-        } else {
-            z = L.u[n];
+    constexpr int R = (W * W + kMgThreads - 1) / kMgThreads;
+    float uv[R], gv[R];
+    uint8_t fv[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int k = (int)threadIdx.x + r * kMgThreads;
+        const int a = k / W, c = k - a * W;
+        int gi = wi0 + a, gj = wj0 + c;
+        bool in = k < W * W;
+        if (px) gi = wrap_any(gi, L.NX); else in = in && gi >= 0 && gi < L.NX;
+        if (py) gj = wrap_any(gj, L.NY); else in = in && gj >= 0 && gj < L.NY;
+        uv[r] = 0.0f;
+        gv[r] = 0.0f;
+        fv[r] = 1;
+        if (in) {
+            const long long n = (long long)gi * L.NY + gj;
+            fv[r] = L.fix[n];
+            uv[r] = L.u[n];
+            gv[r] = L.g[n];
         }
-        if (level0_rz) rz = (double)L.g[n] * (double)z;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int k = (int)threadIdx.x + r * kMgThreads;
+        if (k < W * W) {
+            su[k] = uv[r];
+            sg[k] = gv[r];
+            sf[k] = fv[r];
+        }
+    }
+}
+
+// Gauss-Seidel value at window node k (neighbours in the window; fixed
+// neighbours contribute their zero).
+template <int W>
+__device__ __forceinline__ float win_gs(const float *su, const float *sg, int k)
+{
+    float s = sg[k];
+    s += su[k - W];
+    s += su[k + W];
+    s += su[k - 1];
+    s += su[k + 1];
+    return s * 0.25f;
+}
+
+__global__ __launch_bounds__(kMgThreads) void k_mg_down(const Inst *insts, Tab t, int level)
+{
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const Inst &I = insts[t.id[ku]];
+    if (I.F[F_DONE]) return;
+    const int lb = (int)blockIdx.x - t.boff[ku];
+    const int ti = lb / t.bx[ku], tj = lb - ti * t.bx[ku];
+    const LevelDev F = I.lev[level], Cc = I.lev[level + 1];
+    const int i0 = ti * kMgTile, j0 = tj * kMgTile;
+    __shared__ float su[kDnW * kDnW], sg[kDnW * kDnW], sr[kDnW * kDnW];
+    __shared__ uint8_t sf[kDnW * kDnW];
+    mg_stage<kDnW>(F, I.g.px, I.g.py, i0 - 3, j0 - 3, su, sg, sf);
+    __syncthreads();
+    // black half-sweep over window rows/cols 1 .. W-2 (red values unchanged)
+    for (int k = threadIdx.x; k < kDnW * kDnW; k += kMgThreads) {
+        const int a = k / kDnW, c = k - a * kDnW;
+        if (a < 1 || a > kDnW - 2 || c < 1 || c > kDnW - 2 || sf[k]) continue;
+        if (((i0 + j0 + a + c) & 1) != 1) continue;        // parity of the global node
+        su[k] = win_gs<kDnW>(su, sg, k);
+    }
+    __syncthreads();
+    // own black nodes back to the level; residuals at the red nodes the
+    // restriction reads (window rows/cols 2 .. W-3)
+    for (int k = threadIdx.x; k < kMgTile * kMgTile; k += kMgThreads) {
+        const int a = k / kMgTile, c = k - a * kMgTile;
+        const int gi = i0 + a, gj = j0 + c;
+        if (gi >= F.NX || gj >= F.NY || ((gi + gj) & 1) != 1) continue;
+        const int w = (a + 3) * kDnW + (c + 3);
+        if (!sf[w]) F.u[(long long)gi * F.NY + gj] = su[w];
+    }
+    for (int k = threadIdx.x; k < kDnW * kDnW; k += kMgThreads) {
+        const int a = k / kDnW, c = k - a * kDnW;
+        if (a < 2 || a > kDnW - 3 || c < 2 || c > kDnW - 3) continue;
+        if (((i0 + j0 + a + c) & 1) != 0) continue;
+        float r = 0.0f;
+        if (!sf[k]) {
+            float q = 4.0f * su[k];
+            q -= su[k - kDnW];
+            q -= su[k + kDnW];
+            q -= su[k - 1];
+            q -= su[k + 1];
+            r = sg[k] - q;
+        }
+        sr[k] = r;
+    }
+    __syncthreads();
+    // restriction: coarse nodes (i0/2 .. i0/2+15, j0/2 .. j0/2+15)
+    {
+        const int ci = threadIdx.x >> 4, cj = threadIdx.x & 15;
+        const int CI = (i0 >> 1) + ci, CJ = (j0 >> 1) + cj;
+        if (CI < Cc.NX && CJ < Cc.NY) {
+            const long long n = (long long)CI * Cc.NY + CJ;
+            float gv = 0.0f, uv = 0.0f;
+            if (!Cc.fix[n]) {
+                const int k = (2 * ci + 3) * kDnW + (2 * cj + 3);
+                float acc = 0.0f;
+                acc += 0.25f * sr[k - kDnW - 1];
+                acc += 0.25f * sr[k - kDnW + 1];
+                acc += 1.0f * sr[k];
+                acc += 0.25f * sr[k + kDnW - 1];
+                acc += 0.25f * sr[k + kDnW + 1];
+                gv = acc;
+                if (((CI + CJ) & 1) == 0) uv = gv * 0.25f;
+            }
+            Cc.g[n] = gv;
+            Cc.u[n] = uv;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMgThreads) void k_mg_up(const Inst *insts, Tab t, int level, int level0_rz,
+                                                      Part pt)
+{
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const Inst &I = insts[t.id[ku]];
+    if (I.F[F_DONE]) return;
+    const int lb = (int)blockIdx.x - t.boff[ku];
+    const int ti = lb / t.bx[ku], tj = lb - ti * t.bx[ku];
+    const LevelDev F = I.lev[level], Cc = I.lev[level + 1];
+    const int i0 = ti * kMgTile, j0 = tj * kMgTile;
+    __shared__ float su[kUpW * kUpW], sg[kUpW * kUpW], sc[kUpW * kUpW];
+    __shared__ uint8_t sf[kUpW * kUpW];
+    mg_stage<kUpW>(F, I.g.px, I.g.py, i0 - 2, j0 - 2, su, sg, sf);
+    __syncthreads();
+    // red nodes: value plus the prolonged coarse correction (0 on fixed nodes)
+    for (int k = threadIdx.x; k < kUpW * kUpW; k += kMgThreads) {
+        const int a = k / kUpW, c = k - a * kUpW;
+        int gi = i0 - 2 + a, gj = j0 - 2 + c;
+        float v = 0.0f;
+        if (((gi + gj) & 1) == 0 && !sf[k]) {
+            if (I.g.px) gi = wrap_any(gi, F.NX);
+            if (I.g.py) gj = wrap_any(gj, F.NY);
+            v = su[k] + prolong_red(Cc.uo, Cc.NX, Cc.NY, gi, gj);
+        }
+        sc[k] = v;
+    }
+    __syncthreads();
+    // black update over window rows/cols 1 .. W-2 from the corrected reds
+    for (int k = threadIdx.x; k < kUpW * kUpW; k += kMgThreads) {
+        const int a = k / kUpW, c = k - a * kUpW;
+        if (a < 1 || a > kUpW - 2 || c < 1 || c > kUpW - 2 || sf[k]) continue;
+        if (((i0 + j0 + a + c) & 1) != 1) continue;
+        float s = sg[k];
+        s += sc[k - kUpW];
+        s += sc[k + kUpW];
+        s += sc[k - 1];
+        s += sc[k + 1];
+        su[k] = s * 0.25f;
+    }
+    __syncthreads();
+    // red half-sweep on the own tile; write both colours to uo
+    double rz = 0.0;
+    for (int k = threadIdx.x; k < kMgTile * kMgTile; k += kMgThreads) {
+        const int a = k / kMgTile, c = k - a * kMgTile;
+        const int gi = i0 + a, gj = j0 + c;
+        if (gi >= F.NX || gj >= F.NY) continue;
+        const int w = (a + 2) * kUpW + (c + 2);
+        float z = 0.0f;                                   // fixed nodes carry no correction
+        if (!sf[w]) {
+            z = su[w];
+            if (((gi + gj) & 1) == 0) z = win_gs<kUpW>(su, sg, w);
+            if (level0_rz) rz += (double)sg[w] * (double)z;
+        }
+        F.uo[(long long)gi * F.NY + gj] = z;
     }
     if (!level0_rz) return;
     double v[1] = {rz};
     block_partials<1>(v, pt);
 }
 
-void launch_smooth(const Inst *I, const Tab &t, int level, int color, int level0_rz, Part pt,
-                   hipStream_t s)
+void launch_mg_down(const Inst *I, const Tab &t, int level, hipStream_t s)
+{
+    if (t.n) hipLaunchKernelGGL(k_mg_down, dim3(tab_blocks(t)), dim3(kMgThreads), 0, s, I, t, level);
+}
+
+void launch_mg_up(const Inst *I, const Tab &t, int level, int level0_rz, Part pt, hipStream_t s)
 {
     if (!t.n) return;
-    hipLaunchKernelGGL(k_smooth, dim3(tab_blocks(t)), gblock(), 0, s, I, t, level, color,
-                       level0_rz, pt);
+    hipLaunchKernelGGL(k_mg_up, dim3(tab_blocks(t)), dim3(kMgThreads), 0, s, I, t, level, level0_rz, pt);
     if (level0_rz) finalize(I, t, pt, OP_RZ, s);
-}
-
-// g_c = P^T (g - A u) on the coarse level; u_c = red-from-zero.
-__global__ void k_restrict(const Inst *insts, Tab t, int level)
-{
-    GRID_BEGIN(t)
-    if (I.F[F_DONE]) return;
-    const LevelDev F = I.lev[level], Cc = I.lev[level + 1];
-    NODE_IDX(Cc.NX, Cc.NY)
-    if (!inb) return;
-    float gv = 0.0f, uv = 0.0f;
-    if (!Cc.fix[n]) {
-        gv = restrict_node(F.u, F.g, F.fix, F.NX, F.NY, I.g.px, I.g.py, i, j);
-        if (((i + j) & 1) == 0) uv = gv * 0.25f;
-    }
-    Cc.g[n] = gv;
-    Cc.u[n] = uv;
-}
-
-void launch_restrict(const Inst *I, const Tab &t, int level, hipStream_t s)
-{
-    if (t.n) hipLaunchKernelGGL(k_restrict, dim3(tab_blocks(t)), gblock(), 0, s, I, t, level);
-}
-
-__global__ void k_prolong_black(const Inst *insts, Tab t, int level)
-{
-    GRID_BEGIN(t)
-    if (I.F[F_DONE]) return;
-    const LevelDev F = I.lev[level], Cc = I.lev[level + 1];
-    NODE_IDX(F.NX, F.NY)
-    if (!inb || F.fix[n] || ((i + j) & 1) != 1) return;
-    F.u[n] = prolong_black_value(F.u, F.g, F.fix, Cc.u, NX, NY, Cc.NX, Cc.NY, i, j);
-}
-
-void launch_prolong_black(const Inst *I, const Tab &t, int level, hipStream_t s)
-{
-    if (t.n) hipLaunchKernelGGL(k_prolong_black, dim3(tab_blocks(t)), gblock(), 0, s, I, t, level);
 }
 
 // ---------------------------------------------------------------------------
 // coarse levels: the rest of the V-cycle in one work-group per instance,
 // all in LDS
 // ---------------------------------------------------------------------------
+
+// Gauss-Seidel value from the four neighbours without mask tests: fixed
+// nodes hold u = 0 on the LDS levels (staged as 0, never updated).
+__device__ __forceinline__ float gs_nofix(const float *u, const float *gg, int i, int j, int NX, int NY)
+{
+    Nb b = nbs(i, j, NX, NY);
+    float s = gg[(long long)i * NY + j];
+    s += u[(long long)b.im * NY + j];
+    s += u[(long long)b.ip * NY + j];
+    s += u[(long long)i * NY + b.jm];
+    s += u[(long long)i * NY + b.jp];
+    return s * 0.25f;
+}
 
 __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
 {
@@ -800,6 +885,7 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
 #define u(l) ((float *)(lds + tab[0][l]))
 #define gg(l) ((float *)(lds + tab[1][l]))
 #define fx(l) ((uint8_t *)(lds + tab[2][l]))
+    float *sr = (float *)(lds + a.off_s);   // per level: red residuals (down), corrected reds (up)
     for (int l = 0; l < a.nlev; l++) {
         const int N = a.NX[l] * a.NY[l];
         const uint8_t *src = a.fix[l];
@@ -815,21 +901,54 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
         }
     }
     __syncthreads();
-    // descend
+    // descend: black half-sweep, residuals at the red nodes, restriction
     for (int l = 0; l < a.nlev - 1; l++) {
         const int NX = a.NX[l], NY = a.NY[l], N = NX * NY;
+        float *ul = u(l), *gl = gg(l);
+        const uint8_t *fl = fx(l);
         for (int k = tid; k < N; k += nt) {
             int i = k / NY, j = k - i * NY;
-            if (!fx(l)[k] && ((i + j) & 1) == 1) u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+            if (!fl[k] && ((i + j) & 1) == 1) ul[k] = gs_nofix(ul, gl, i, j, NX, NY);
+        }
+        __syncthreads();
+        for (int k = tid; k < N; k += nt) {
+            int i = k / NY, j = k - i * NY;
+            if (((i + j) & 1) != 0) continue;
+            float r = 0.0f;
+            if (!fl[k]) {
+                Nb b = nbs(i, j, NX, NY);
+                float q = 4.0f * ul[k];
+                q -= ul[(long long)b.im * NY + j];
+                q -= ul[(long long)b.ip * NY + j];
+                q -= ul[(long long)i * NY + b.jm];
+                q -= ul[(long long)i * NY + b.jp];
+                r = gl[k] - q;
+            }
+            sr[k] = r;
         }
         __syncthreads();
         const int NXc = a.NX[l + 1], NYc = a.NY[l + 1], Nc = NXc * NYc;
         for (int k = tid; k < Nc; k += nt) {
-            int I = k / NYc, J = k - I * NYc;
+            int Ic = k / NYc, Jc = k - Ic * NYc;
             float gv = 0.0f, uv = 0.0f;
             if (!fx(l + 1)[k]) {
-                gv = restrict_node(u(l), gg(l), fx(l), NX, NY, a.px, a.py, I, J);
-                if (((I + J) & 1) == 0) uv = gv * 0.25f;
+                float acc = 0.0f;
+#pragma unroll
+                for (int di = -1; di <= 1; di++) {
+#pragma unroll
+                    for (int dj = -1; dj <= 1; dj++) {
+                        if ((di + dj) & 1) continue;
+                        int ai = 2 * Ic + di, cj = 2 * Jc + dj;
+                        if (a.px) ai = wrap_hi(wrap_lo(ai, NX), NX);
+                        else if (ai < 0 || ai >= NX) continue;
+                        if (a.py) cj = wrap_hi(wrap_lo(cj, NY), NY);
+                        else if (cj < 0 || cj >= NY) continue;
+                        const float w = (di == 0) ? 1.0f : 0.25f;
+                        acc += w * sr[(long long)ai * NY + cj];
+                    }
+                }
+                gv = acc;
+                if (((Ic + Jc) & 1) == 0) uv = gv * 0.25f;
             }
             gg(l + 1)[k] = gv;
             u(l + 1)[k] = uv;
@@ -849,7 +968,7 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
                 const bool mine = k < N && !fx(l)[k];
                 for (int sw = 0; sw < a.sweeps; sw++) {
                     for (int col = 1; col >= 0; col--) {
-                        if (mine && ((i + j) & 1) == col) u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+                        if (mine && ((i + j) & 1) == col) u(l)[k] = gs_nofix(u(l), gg(l), i, j, NX, NY);
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                         __builtin_amdgcn_wave_barrier();
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -862,27 +981,40 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
                 for (int col = 1; col >= 0; col--) {
                     for (int k = tid; k < N; k += nt) {
                         int i = k / NY, j = k - i * NY;
-                        if (!fx(l)[k] && ((i + j) & 1) == col)
-                            u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+                        if (!fx(l)[k] && ((i + j) & 1) == col) u(l)[k] = gs_nofix(u(l), gg(l), i, j, NX, NY);
                     }
                     __syncthreads();
                 }
             }
         }
     }
-    // ascend
+    // ascend: corrected reds, black update from them, red half-sweep
     for (int l = a.nlev - 2; l >= 0; l--) {
         const int NX = a.NX[l], NY = a.NY[l], N = NX * NY;
+        const int NXc = a.NX[l + 1], NYc = a.NY[l + 1];
+        float *ul = u(l), *gl = gg(l);
+        const uint8_t *fl = fx(l);
         for (int k = tid; k < N; k += nt) {
             int i = k / NY, j = k - i * NY;
-            if (!fx(l)[k] && ((i + j) & 1) == 1)
-                u(l)[k] = prolong_black_value(u(l), gg(l), fx(l), u(l + 1), NX, NY, a.NX[l + 1],
-                                              a.NY[l + 1], i, j);
+            if (((i + j) & 1) != 0) continue;
+            sr[k] = fl[k] ? 0.0f : ul[k] + prolong_red(u(l + 1), NXc, NYc, i, j);
         }
         __syncthreads();
         for (int k = tid; k < N; k += nt) {
             int i = k / NY, j = k - i * NY;
-            if (!fx(l)[k] && ((i + j) & 1) == 0) u(l)[k] = gs_value(u(l), gg(l), fx(l), i, j, NX, NY);
+            if (fl[k] || ((i + j) & 1) != 1) continue;
+            Nb b = nbs(i, j, NX, NY);
+            float s = gl[k];
+            s += sr[(long long)b.im * NY + j];
+            s += sr[(long long)b.ip * NY + j];
+            s += sr[(long long)i * NY + b.jm];
+            s += sr[(long long)i * NY + b.jp];
+            ul[k] = s * 0.25f;
+        }
+        __syncthreads();
+        for (int k = tid; k < N; k += nt) {
+            int i = k / NY, j = k - i * NY;
+            if (!fl[k] && ((i + j) & 1) == 0) ul[k] = gs_nofix(ul, gl, i, j, NX, NY);
         }
         __syncthreads();
     }

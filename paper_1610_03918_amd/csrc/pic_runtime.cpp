@@ -148,6 +148,7 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
             size_t n = (size_t)L.NXl[l] * L.NYl[l];
             lds += ((n * 4 + 15) & ~size_t(15)) * 2 + ((n + 15) & ~size_t(15));
         }
+        if (L.lg < L.nlev) lds += ((size_t)L.NXl[L.lg] * L.NYl[L.lg] * 4 + 15) & ~size_t(15);
         if (lds > kCoarseMaxLds) L.mg = false;
     }
     L.TX = c->tile_x ? c->tile_x : 16;
@@ -185,7 +186,7 @@ struct InstHost {
     long long slots_ub[2] = {0, 0};
     uint8_t *d_cell_cond = nullptr, *d_node_cond = nullptr;
     uint8_t *d_fix[kMaxLev] = {};
-    float *d_u[kMaxLev] = {}, *d_g[kMaxLev] = {};
+    float *d_u[kMaxLev] = {}, *d_g[kMaxLev] = {}, *d_uo[kMaxLev] = {};
     float *d_e = nullptr, *d_p[2] = {}, *d_q = nullptr;
     float4 *d_E4 = nullptr;
     double *d_phi_prev = nullptr;
@@ -234,7 +235,7 @@ struct pic_ctx {
     std::vector<double> vhost;
     // launch tables
     Tab t_l0{}, t_field{}, t_per{}, t_coarse{}, t_push{}, t_rewind{};
-    Tab t_fine[kMaxLev] = {}, t_crs[kMaxLev] = {};
+    Tab t_fine[kMaxLev] = {};      // 32 x 32 tiles of the fine multigrid levels
     int maxlg = 0, coarse_lds = 0, any_mg = 0;
     size_t push_lds = 0;
     int unroll = 2, merge = 0;
@@ -297,11 +298,13 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     uint8_t *cc = w.take<uint8_t>(cells);
     uint8_t *nc = w.take<uint8_t>(nodes);
     uint8_t *fix[kMaxLev];
-    float *u[kMaxLev], *gg[kMaxLev];
+    float *u[kMaxLev], *gg[kMaxLev], *uo[kMaxLev] = {};
     for (int l = 0; l < L.nlev; l++) fix[l] = w.take<uint8_t>((size_t)L.NXl[l] * L.NYl[l]);
     for (int l = 0; l < L.nlev; l++) {
         u[l] = w.take<float>((size_t)L.NXl[l] * L.NYl[l]);
         gg[l] = w.take<float>((size_t)L.NXl[l] * L.NYl[l]);
+        // fine multigrid levels keep the up half-cycle's result apart from its input
+        if (L.mg && l < L.lg) uo[l] = w.take<float>((size_t)L.NXl[l] * L.NYl[l]);
     }
     float *e = w.take<float>(nodes), *p0 = w.take<float>(nodes), *p1 = w.take<float>(nodes);
     float *q = w.take<float>(nodes);
@@ -330,6 +333,7 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
         h->d_fix[l] = fix[l];
         h->d_u[l] = u[l];
         h->d_g[l] = gg[l];
+        h->d_uo[l] = uo[l] ? uo[l] : u[l];
     }
     h->d_e = e;
     h->d_p[0] = p0;
@@ -468,15 +472,9 @@ void enqueue_vcycle_rest(pic_ctx *c, hipStream_t s)
 {
     if (!c->any_mg) return;
     Part pt = part_of(c);
-    for (int l = 0; l < c->maxlg; l++) {
-        launch_smooth(c->d_inst, c->t_fine[l], l, 1, 0, pt, s);
-        launch_restrict(c->d_inst, c->t_crs[l], l, s);
-    }
+    for (int l = 0; l < c->maxlg; l++) launch_mg_down(c->d_inst, c->t_fine[l], l, s);
     launch_coarse(c->d_inst, c->t_coarse, c->coarse_lds, s);
-    for (int l = c->maxlg - 1; l >= 0; l--) {
-        launch_prolong_black(c->d_inst, c->t_fine[l], l, s);
-        launch_smooth(c->d_inst, c->t_fine[l], l, 0, l == 0 ? 1 : 0, pt, s);
-    }
+    for (int l = c->maxlg - 1; l >= 0; l--) launch_mg_up(c->d_inst, c->t_fine[l], l, l == 0 ? 1 : 0, pt, s);
 }
 
 // Start of a refinement pass: inner CG from e = 0 (first residual, z, r.z).
@@ -779,9 +777,11 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
         d.lev[l].NX = L.NXl[l];
         d.lev[l].NY = L.NYl[l];
         d.lev[l].u = h.d_u[l];
+        d.lev[l].uo = h.d_uo[l];
         d.lev[l].g = h.d_g[l];
         d.lev[l].fix = h.d_fix[l];
     }
+    d.z = L.mg ? h.d_uo[0] : h.d_u[0];
     d.node_cond = h.d_node_cond;
     d.cell_cond = h.d_cell_cond;
     d.phi = buf->phi;
@@ -822,6 +822,8 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
             off += (nn + 15) & ~15;
             ca.fix[q] = h.d_fix[l];
         }
+        ca.off_s = off;
+        off += (L.NXl[L.lg] * L.NYl[L.lg] * 4 + 15) & ~15;
         ca.lds_bytes = off;
         ca.u_top = h.d_u[L.lg];
         ca.g_top = h.d_g[L.lg];
@@ -916,7 +918,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
 void build_tabs(pic_ctx *c)
 {
     c->t_l0 = c->t_field = c->t_per = c->t_coarse = c->t_push = c->t_rewind = Tab{};
-    for (int l = 0; l < kMaxLev; l++) c->t_fine[l] = c->t_crs[l] = Tab{};
+    for (int l = 0; l < kMaxLev; l++) c->t_fine[l] = Tab{};
     c->maxlg = 0;
     c->coarse_lds = 0;
     c->any_mg = 0;
@@ -931,8 +933,11 @@ void build_tabs(pic_ctx *c)
             c->any_mg = 1;
             c->maxlg = std::max(c->maxlg, L.lg);
             for (int l = 0; l < L.lg; l++) {
-                tab_add_grid(c->t_fine[l], k, L.NXl[l], L.NYl[l]);
-                tab_add_grid(c->t_crs[l], k, L.NXl[l + 1], L.NYl[l + 1]);
+                const int tx = (L.NXl[l] + kMgTileHost - 1) / kMgTileHost;
+                const int ty = (L.NYl[l] + kMgTileHost - 1) / kMgTileHost;
+                const int q = c->t_fine[l].n;
+                tab_add(c->t_fine[l], k, tx * ty);
+                c->t_fine[l].bx[q] = ty;
             }
             tab_add(c->t_coarse, k, 1);
             c->coarse_lds = std::max(c->coarse_lds, h.dev.coarse.lds_bytes);
