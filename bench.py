@@ -176,6 +176,48 @@ def learned_start(w, pic, parts, args):
     }
 
 
+def run_unet(args):
+    """The learned start's network alone on the trench's 1024 x 512 node
+    window: forward passes at batch 1 (inference) and training steps at
+    batch 4, random bfloat16 inputs."""
+    import torch
+
+    from paper_1610_03918_amd.unet import UNet
+    H, W = 1024, 512
+    fl = flops_per_inference(H, W)
+    out = {"metric": "U-Net inference (1024 x 512, batch 1)", "unit": "ms", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "learned-start network, 4 levels 16/32/64/128", "pixels": [H, W]}}
+    u = UNet(1, H, W, seed=3)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    u.input().copy_(torch.randn(1, H, W, 3, generator=g).to(torch.bfloat16))
+    for _ in range(3):
+        u.pic_unet_forward()
+    torch.cuda.synchronize()
+    u.pic_unet_set_timing(True)
+    for _ in range(20):
+        u.pic_unet_forward()
+    ms, n = u.pic_unet_forward_timing()
+    u.close()
+    tf = fl / (ms * 1e-3) / 1e12
+    out.update(value=ms, roofline={"bound": "mfma", "achieved": tf, "peak": BF16_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": tf / BF16_PEAK_TFLOPS, "traffic": None},
+               gflop_per_inference=fl / 1e9)
+    t4 = UNet(4, H, W, seed=3)
+    t4.input().copy_(torch.randn(4, H, W, 3, generator=g).to(torch.bfloat16))
+    t4.target().normal_(generator=None)
+    t4.mask().fill_(1.0)
+    t4.train_step(1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        t4.train_step(1e-4)
+    torch.cuda.synchronize()
+    out["train_step_ms_batch4"] = 1e3 * (time.perf_counter() - t0) / 5
+    t4.close()
+    print(json.dumps(out), flush=True)
+
+
 def run_sweep(args):
     """The 16-width trench sweep advanced as one batch with captured graphs."""
     import torch
@@ -253,6 +295,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="trench1024x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="only time the learned start's network (1024 x 512)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sort", default="8,64")
@@ -278,6 +322,8 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         return copy_calibration()
+    if args.unet_only:
+        return run_unet(args)
     if args.workload == "sweep":
         return run_sweep(args)
 
@@ -293,14 +339,14 @@ def main():
     n0 = [p["cell"].size for p in parts]
     log(f"loaded {n0} particles in {time.perf_counter() - t:.1f}s")
     from paper_1610_03918_amd import autotune
-    entry = None if args.no_autotuned else autotune.lookup([w], parts)
+    entry = None if args.no_autotuned else autotune.lookup([w], [parts])
     if entry is not None:
         sch = entry["schedule"]
         args.sort = ",".join(str(x) for x in sch["sort_interval"])
         args.tile = ",".join(str(x) for x in sch["tile"])
         args.unroll, args.merge, args.chunk, args.halo = (sch["push_unroll"], sch["push_merge"],
                                                           sch["chunk"], sch["halo"])
-        schedule_source = f"autotuned (cache key {autotune.signature([w], parts)})"
+        schedule_source = f"autotuned (cache key {autotune.signature([w], [parts])})"
     else:
         schedule_source = "command line"
     sort = tuple(int(x) for x in args.sort.split(","))
