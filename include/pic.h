@@ -60,6 +60,7 @@ typedef enum {
 
 #define PIC_MAX_COND 8           /* conductor ids 1..7; 0 = plasma / free */
 #define PIC_NCLASS 9             /* hit classes, see pic_diag */
+#define PIC_IAD_BINS 90          /* ion angular distribution bins (2 degrees each) */
 
 typedef struct {
     int32_t nx, ny;              /* cells along x (plate normal) and y */
@@ -128,6 +129,11 @@ typedef struct {
     int64_t hits_logged;         /* records written to the hit ring (total) */
     int64_t deposit_fallbacks;   /* particles deposited outside their tile window */
     pic_solve_info last_solve;
+    double kinetic[2];           /* 0.5 (m_s/m_e) w sum(v_x^2 + v_y^2) over live particles
+                                    (n_0 T_e per unit area; leapfrog velocities v^{n-1/2}) */
+    double field_energy;         /* 0.5 sum over nodes of |E|^2 (node field of the current phi) */
+    int64_t iad[PIC_IAD_BINS];   /* ions absorbed by the trench bottom per 2-degree bin of the
+                                    impact angle atan2(v_y, v_x) in [-90, 90) degrees (Sec. III.C) */
 } pic_diag;
 
 typedef struct {

@@ -14,6 +14,8 @@ namespace pic {
 
 constexpr int kMaxLev = 16;
 constexpr int kNClass = 9;
+constexpr int kIadBins = 90;     // 2-degree bins of the bottom-impact angle, -90 .. 90 degrees
+constexpr int kDiagBlocks = 512; // blocks (and partial sums) of the diagnostic reductions
 constexpr int kMaxInst = 16;
 constexpr int kMaxUnits = 2 * kMaxInst;
 constexpr int kGridBX = 64;      // grid kernels: 64 x 4 threads over (y, x) nodes
@@ -125,6 +127,7 @@ struct PushArgs {
     int species, inst;
     unsigned long long *tally;     // 9 counters of this species
     unsigned long long *surf;      // trench-bottom hits per column, or null
+    unsigned long long *iad;       // bottom-impact angle histogram (ions), or null
     HitLog log;
     const long long *step;         // device step counter (hit records)
     unsigned long long *fallbacks;
@@ -188,6 +191,11 @@ void launch_bin(const BinArgs *B, const Tab &tcount, const Tab &tscan, const Tab
 void launch_rho_sum(const unsigned long long *rho, long long n, unsigned long long *out,
                     hipStream_t s);
 void launch_tick(long long *step, hipStream_t s);
+// diagnostics: kinetic sums of one species' live particles (set in use) and
+// the node-field energy of an instance, as kDiagBlocks partials each, then
+// summed in block order into out[0] (kinetic) / out[0] (field)
+void launch_kinetic(const PushArgs *A, int unit, double *part, double *out, hipStream_t s);
+void launch_field_energy(const Inst *I, int inst, double *part, double *out, hipStream_t s);
 int bin_per_block();
 
 // Dynamic LDS of the particle kernels: the tile + halo window of cell

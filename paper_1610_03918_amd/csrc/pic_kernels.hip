@@ -1100,6 +1100,7 @@ struct PK {
     float qdt, dtf, hq;
     int box_i_top, box_j_lo, box_j_hi, species;
     GLOBAL unsigned long long *surf;
+    GLOBAL unsigned long long *iad;
     HitLog log;
     const long long *step;
 };
@@ -1131,6 +1132,7 @@ __device__ __forceinline__ PK resolve(const PushArgs &a)
     k.box_j_hi = a.box_j_hi;
     k.species = a.species;
     k.surf = to_global(a.surf);
+    k.iad = to_global(a.iad);
     k.log = a.log;
     k.step = a.step;
     return k;
@@ -1243,6 +1245,13 @@ __device__ __forceinline__ void record_hit(const PK &a, unsigned *tl, int dead, 
 {
     atomicAdd(&tl[dead], 1u);
     if (a.surf && dead == 4) gatomic_add(&a.surf[ej], 1ull);
+    if (a.iad && dead == 4) {
+        // impact angle to the plate normal (+x), 2-degree bins over [-90, 90)
+        const float ang = atan2f(uy, ux);
+        int bin = (int)floorf((ang + 1.57079632679f) * (float)(kIadBins / 3.14159265359));
+        bin = bin < 0 ? 0 : (bin >= kIadBins ? kIadBins - 1 : bin);
+        gatomic_add(&a.iad[bin], 1ull);
+    }
     if (a.log.rec && ((a.log.species_mask >> a.species) & 1)) {
         unsigned long long k = atomicAdd(a.log.count, 1ull);
         long long slot = (long long)(k % (unsigned long long)a.log.capacity);
@@ -1651,6 +1660,69 @@ __global__ void k_rewind(const PushArgs *A, Tab t)
 void launch_rewind(const PushArgs *A, const Tab &t, hipStream_t s)
 {
     if (t.n) hipLaunchKernelGGL(k_rewind, dim3(tab_blocks(t)), dim3(256), 0, s, A, t);
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics (not on the stepping path): float64 sums in a fixed order
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void diag_block_sum(double v, double *part)
+{
+    __shared__ double sh[256];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_kinetic(const PushArgs *A, int unit, double *part)
+{
+    const PushArgs &aa = A[unit];
+    const int set = (int)aa.info[7];
+    const long long n = aa.info[2 + set];
+    const int32_t *cell = aa.cell[set];
+    const float *vx = aa.vx[set], *vy = aa.vy[set];
+    double s = 0.0;
+    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < n; p += (long long)gridDim.x * 256)
+        if (cell[p] >= 0) s += (double)vx[p] * vx[p] + (double)vy[p] * vy[p];
+    diag_block_sum(s, part);
+}
+
+__global__ __launch_bounds__(256) void k_field_energy(const Inst *insts, int inst, double *part)
+{
+    const Inst &I = insts[inst];
+    const Geom g = I.g;
+    const long long n = (long long)g.NX * g.NY;
+    double s = 0.0;
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+        const int i = (int)(k / g.NY), j = (int)(k % g.NY);
+        const float2 e = node_field(g, I.node_cond, I.phi, i, j);
+        s += (double)e.x * e.x + (double)e.y * e.y;
+    }
+    diag_block_sum(0.5 * s, part);
+}
+
+__global__ void k_sum_partials(const double *part, int n, double *out)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < n; k++) s += part[k];
+    *out = s;
+}
+
+void launch_kinetic(const PushArgs *A, int unit, double *part, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kinetic, dim3(kDiagBlocks), dim3(256), 0, s, A, unit, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, kDiagBlocks, out);
+}
+
+void launch_field_energy(const Inst *I, int inst, double *part, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_field_energy, dim3(kDiagBlocks), dim3(256), 0, s, I, inst, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, kDiagBlocks, out);
 }
 
 // ---------------------------------------------------------------------------

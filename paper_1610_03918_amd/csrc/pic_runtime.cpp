@@ -193,7 +193,8 @@ struct InstHost {
     unsigned *d_counts[2] = {}, *d_offsets[2] = {}, *d_cursor[2] = {}, *d_boff[2] = {};
     int4 *d_table[2] = {};
     long long *d_info[2] = {};
-    unsigned long long *d_tally = nullptr, *d_surf = nullptr, *d_misc = nullptr;
+    unsigned long long *d_tally = nullptr, *d_surf = nullptr, *d_misc = nullptr, *d_iad = nullptr;
+    double *d_diag = nullptr;
     int32_t *d_hits = nullptr;
     std::vector<std::vector<uint8_t>> fixh;  // level masks (host copies kept until uploaded)
     Inst dev{};
@@ -324,6 +325,8 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     unsigned long long *tally = w.take<unsigned long long>(2 * kNClass);
     unsigned long long *surf = w.take<unsigned long long>(L.ny + 1);
     unsigned long long *misc = w.take<unsigned long long>(16);
+    unsigned long long *iad = w.take<unsigned long long>(kIadBins);
+    double *diag = w.take<double>(kDiagBlocks + 4);
     int32_t *hits = w.take<int32_t>((size_t)6 * std::max<int64_t>(cfg->hitlog_capacity, 1));
     (void)cap;
     if (!h) return;
@@ -352,6 +355,8 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     h->d_tally = tally;
     h->d_surf = surf;
     h->d_misc = misc;
+    h->d_iad = iad;
+    h->d_diag = diag;
     h->d_hits = hits;
 }
 
@@ -868,6 +873,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
         a.inst = k;
         a.tally = h.d_tally + sp * kNClass;
         a.surf = (h.cfg.charge_mode == 2 && sp == 1) ? h.d_surf : nullptr;
+        a.iad = (sp == 1 && h.cfg.box_i_top < h.cfg.nx) ? h.d_iad : nullptr;
         a.log.rec = h.cfg.hitlog_capacity > 0 ? h.d_hits : nullptr;
         a.log.count = h.d_misc + 1;
         a.log.capacity = std::max<int64_t>(h.cfg.hitlog_capacity, 1);
@@ -906,6 +912,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
     HIPCHK(c, hipMemsetAsync(h.d_tally, 0, sizeof(unsigned long long) * 2 * kNClass, s));
     HIPCHK(c, hipMemsetAsync(h.d_surf, 0, sizeof(unsigned long long) * (L.ny + 1), s));
     HIPCHK(c, hipMemsetAsync(h.d_misc, 0, sizeof(unsigned long long) * 16, s));
+    HIPCHK(c, hipMemsetAsync(h.d_iad, 0, sizeof(unsigned long long) * kIadBins, s));
     HIPCHK(c, hipMemsetAsync(h.d_e, 0, sizeof(float) * (size_t)L.NX * L.NY, s));
     HIPCHK(c, hipMemsetAsync(h.d_p[0], 0, sizeof(float) * (size_t)L.NX * L.NY, s));
     HIPCHK(c, hipMemsetAsync(h.d_p[1], 0, sizeof(float) * (size_t)L.NX * L.NY, s));
@@ -1223,9 +1230,15 @@ pic_status pic_batch_diagnostics(pic_ctx *c, int32_t i, pic_diag *out)
     for (int sp = 0; sp < 2; sp++)
         launch_rho_sum(reinterpret_cast<const unsigned long long *>(h.buf.rho[sp]),
                        (long long)h.g.NX * h.g.NY, h.d_misc + 4 + sp, s);
-    unsigned long long tally[2 * kNClass], misc[16];
+    for (int sp = 0; sp < 2; sp++)
+        launch_kinetic(c->d_push, 2 * i + sp, h.d_diag, h.d_diag + kDiagBlocks + sp, s);
+    launch_field_energy(c->d_inst, i, h.d_diag, h.d_diag + kDiagBlocks + 2, s);
+    unsigned long long tally[2 * kNClass], misc[16], iad[kIadBins];
+    double dsum[4];
     std::vector<unsigned long long> surf(h.L.ny + 1);
     HIPCHK(c, hipMemcpyAsync(tally, h.d_tally, sizeof tally, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(iad, h.d_iad, sizeof iad, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(dsum, h.d_diag + kDiagBlocks, sizeof dsum, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(misc, h.d_misc, sizeof misc, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(surf.data(), h.d_surf, surf.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -1248,6 +1261,10 @@ pic_status pic_batch_diagnostics(pic_ctx *c, int32_t i, pic_diag *out)
     out->hits_logged = (int64_t)misc[1];
     out->deposit_fallbacks = (int64_t)misc[0];
     out->last_solve = h.last;
+    for (int sp = 0; sp < 2; sp++)
+        out->kinetic[sp] = 0.5 * h.cfg.weight * dsum[sp] / std::fabs(h.cfg.alpha[sp]);
+    out->field_energy = dsum[2];
+    for (int k = 0; k < kIadBins; k++) out->iad[k] = (int64_t)iad[k];
     return PIC_OK;
 }
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libpic.so")
 
 MAX_COND = 8
 NCLASS = 9
+IAD_BINS = 90
 
 PIC_OK = 0
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -3: "PIC_ERR_HIP", -4: "PIC_ERR_NOT_CONVERGED",
@@ -64,7 +65,8 @@ class pic_diag(C.Structure):
                 ("loaded", C.c_int64 * 2), ("charge", C.c_int64 * 2),
                 ("tally", (C.c_int64 * NCLASS) * 2), ("surf_hits", C.c_int64),
                 ("hits_logged", C.c_int64), ("deposit_fallbacks", C.c_int64),
-                ("last_solve", pic_solve_info)]
+                ("last_solve", pic_solve_info), ("kinetic", C.c_double * 2),
+                ("field_energy", C.c_double), ("iad", C.c_int64 * IAD_BINS)]
 
 
 class pic_hit(C.Structure):
@@ -331,6 +333,7 @@ class Pic(_Context):
             "charge": list(d.charge),
             "tally": [list(d.tally[s]) for s in range(2)], "surf_hits": d.surf_hits,
             "hits_logged": d.hits_logged, "deposit_fallbacks": d.deposit_fallbacks,
+            "kinetic": list(d.kinetic), "field_energy": d.field_energy, "iad": list(d.iad),
             "last_solve": d.last_solve.as_dict(),
         }
 
@@ -387,6 +390,16 @@ class Pic(_Context):
         info = self.pic_solve(0)
         self.pic_rewind()
         return info
+
+    def trench_profiles(self):
+        """Potential across the trench at mid-depth (node row, columns
+        box_j_lo - 4 .. box_j_hi + 4) and down its centre line (node column,
+        rows box_i_top - 16 .. NX - 1); a copy of the caller's phi."""
+        w = self.w
+        phi = self.phi.cpu().numpy().reshape(w.NX, w.NY)
+        jc = (w.box_j_lo + w.box_j_hi) // 2
+        im = (w.box_i_top + w.nx) // 2
+        return phi[im, w.box_j_lo - 4:w.box_j_hi + 5].copy(), phi[w.box_i_top - 16:, jc].copy()
 
 
 class PicBatch(_Context):
@@ -450,7 +463,8 @@ class PicBatch(_Context):
             "step": d.step, "t": d.t, "alive": list(d.alive), "loaded": list(d.loaded),
             "charge": list(d.charge), "tally": [list(d.tally[s]) for s in range(2)],
             "surf_hits": d.surf_hits, "hits_logged": d.hits_logged,
-            "deposit_fallbacks": d.deposit_fallbacks, "last_solve": d.last_solve.as_dict(),
+            "deposit_fallbacks": d.deposit_fallbacks,
+            "kinetic": list(d.kinetic), "field_energy": d.field_energy, "iad": list(d.iad), "last_solve": d.last_solve.as_dict(),
         }
 
     def pic_batch_particles(self, i, s):
