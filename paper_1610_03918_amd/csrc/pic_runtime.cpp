@@ -809,7 +809,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
     d.sjh = h.cfg.static_j_hi;
     d.sden = h.cfg.static_density;
     d.rtol = h.cfg.rtol;
-    d.eta_min = d.mg ? 2e-6 : 1e-5;
+    d.eta_min = d.mg ? 5e-7 : 1e-5;
     if (L.mg) {
         CoarseArgs &ca = d.coarse;
         ca.nlev = L.nlev - L.lg;
