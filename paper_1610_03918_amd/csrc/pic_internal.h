@@ -42,6 +42,9 @@ enum {
     S_PIN,       // value of the pinned node (fully periodic gauge)
     S_RELRES,    // last float64 relative residual
     S_RELRES0,   // relative residual at the start of the solve
+    S_CG_ALPHA,  // step length of the next CG step (multigrid-preconditioned form)
+    S_CG_BETA,   // direction coefficient of the next CG step
+    S_CG_GAMMA,  // r.z of the last V-cycle
     S_NSCAL = 16
 };
 enum {
@@ -57,7 +60,7 @@ enum {
 struct LevelDev {
     int NX, NY;
     float *u;          // correction (level 0: z at the start of the V-cycle)
-    float *uo;         // result of the level's up half-cycle (fine levels; = u on LDS levels)
+    float *uo;         // pre-smoothed level from the down half-cycle (fine levels; = u on LDS levels)
     float *g;          // right-hand side (level 0: r)
     const uint8_t *fix;
 };
@@ -84,7 +87,10 @@ struct Inst {
     double *phi, *b, *phi_prev;
     unsigned long long *rho[2];
     float *e, *p[2], *q;
-    float *z;                      // preconditioned residual of the CG (level-0 uo with MG, else u)
+    float *z;                      // preconditioned residual of the CG (level-0 u)
+    // multigrid-preconditioned CG in the Chronopoulos-Gear form: residual
+    // pair (lev[0].g, cg_r1), s = A p pair, w = A z
+    float *cg_r1, *cg_s[2], *cg_w;
     float4 *E4;
     double *S;
     int *F;
@@ -159,7 +165,8 @@ enum {
     OP_INIT,         // inner start (inner stop ratio from the current residual)
     OP_PQ,           // S_PQ
     OP_UPDATE,       // S_RR, iteration count, inner stop test
-    OP_RZ            // rz rotation
+    OP_RZ,           // rz rotation
+    OP_CG_DOTS       // r.z and w.z of a V-cycle: the next step's alpha and beta
 };
 
 // ---- launchers (pic_kernels.hip) --------------------------------------
@@ -181,8 +188,10 @@ void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStrea
 void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s);
 // fused fine-level V-cycle halves (tables of 32 x 32 tiles of level l)
 constexpr int kMgTileHost = 32;
-void launch_mg_down(const Inst *I, const Tab &t, int level, hipStream_t s);
-void launch_mg_up(const Inst *I, const Tab &t, int level, int level0_rz, Part pt, hipStream_t s);
+// down: mode 0 level >= 1, mode 1 level 0 at the start of an inner pass,
+// mode 2 level 0 after a CG step; par = buffer of the r / s pairs read
+void launch_mg_down(const Inst *I, const Tab &t, int level, int mode, int par, Part pt, hipStream_t s);
+void launch_mg_up(const Inst *I, const Tab &t, int level, int par, Part pt, hipStream_t s);
 void launch_push(const PushArgs *A, const Tab &t, bool push, int unroll, int merge, size_t lds,
                  hipStream_t s);
 void launch_rewind(const PushArgs *A, const Tab &t, hipStream_t s);

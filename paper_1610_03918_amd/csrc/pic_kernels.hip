@@ -82,61 +82,43 @@ __device__ void block_partials(const double (&val)[NQ], const Part &pt)
     }
 }
 
-// One block per unit: totals of the unit's partials, then the scalar logic
-// of the operation on that instance.
-__global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part pt, int op)
+// Scalar logic of operation op on one instance, from the totals t0, t1 of
+// its partials (one thread).
+__device__ void apply_op(const Inst &I, int op, double t0, double t1)
 {
-    const Inst &I = insts[t.id[blockIdx.x]];
     double *S = I.S;
     int *F = I.F;
-    const bool inner = op == OP_PQ || op == OP_UPDATE || op == OP_RZ;
-    if (inner && F[F_DONE]) return;
+    if ((op == OP_PQ || op == OP_UPDATE || op == OP_RZ || op == OP_CG_DOTS) && F[F_DONE]) return;
     if (op == OP_RR64_PASS && F[F_SKIP]) return;
     if (op == OP_INIT && F[F_CONV]) {
-        if (threadIdx.x == 0) {
-            F[F_SKIP] = 1;
-            F[F_DONE] = 1;
-        }
+        F[F_SKIP] = 1;
+        F[F_DONE] = 1;
         return;
     }
-    __shared__ double sh[2][4];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE || op == OP_RR64_START) ? 2 : 1;
-    const int b0 = t.boff[blockIdx.x], b1 = t.boff[blockIdx.x + 1];
-    for (int q = 0; q < nq; q++) {
-        double s = 0.0;
-        for (int k = b0 + tid; k < b1; k += 256) s += pt.p[q * pt.stride + k];
-        s = wave_sum(s);
-        if (lane == 0) sh[q][wid] = s;
-    }
-    __syncthreads();
-    if (tid != 0) return;
-    double tt[2] = {0.0, 0.0};
-    for (int q = 0; q < nq; q++) tt[q] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
     const double bb = S[S_BB] > 0.0 ? S[S_BB] : 1.0;
     const double tol2 = I.rtol * I.rtol;
     switch (op) {
     case OP_ASM:
-        if (I.g.px && I.g.py) S[S_SUM] = tt[1];
-        else S[S_BB] = tt[0];
+        if (I.g.px && I.g.py) S[S_SUM] = t1;
+        else S[S_BB] = t0;
         break;
-    case OP_BB_PER: S[S_BB] = tt[0]; break;
-    case OP_SUM: S[S_SUM] = tt[0]; break;
+    case OP_BB_PER: S[S_BB] = t0; break;
+    case OP_SUM: S[S_SUM] = t0; break;
     case OP_RR64_START:
         // ||b||^2 of the right-hand side being solved (b may have been written
         // by the caller since the last assembly)
-        S[S_BB] = tt[1];
-        S[S_RR64] = tt[0];
-        S[S_RELRES0] = tt[0];
-        F[F_CONV] = (tt[0] <= tol2 * (tt[1] > 0.0 ? tt[1] : 1.0)) ? 1 : 0;
+        S[S_BB] = t1;
+        S[S_RR64] = t0;
+        S[S_RELRES0] = t0;
+        F[F_CONV] = (t0 <= tol2 * (t1 > 0.0 ? t1 : 1.0)) ? 1 : 0;
         F[F_ITER_TOT] = 0;
         F[F_PASSES] = 0;
         F[F_DONE] = 0;
         F[F_SKIP] = 0;
         break;
     case OP_RR64_PASS:
-        S[S_RR64] = tt[0];
-        F[F_CONV] = (tt[0] <= tol2 * bb) ? 1 : 0;
+        S[S_RR64] = t0;
+        F[F_CONV] = (t0 <= tol2 * bb) ? 1 : 0;
         break;
     case OP_INIT: {
         // inner stop ratio: 0.3 rtol / relres, kept within [eta_min, 0.5]
@@ -145,24 +127,84 @@ __global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part
         eta2 = eta2 < lo ? lo : (eta2 > 0.25 ? 0.25 : eta2);
         F[F_SKIP] = 0;
         S[S_ETA2] = eta2;
-        S[S_RR0] = tt[0];
-        S[S_RR] = tt[0];
-        F[F_DONE] = (tt[0] == 0.0) ? 1 : 0;
+        S[S_RR0] = t0;
+        S[S_RR] = t0;
+        F[F_DONE] = (t0 == 0.0) ? 1 : 0;
         F[F_ITER] = 0;
         F[F_PASSES] += 1;
-        if (!I.mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = tt[1]; }
+        if (!I.mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t1; }
         break;
     }
-    case OP_PQ: S[S_PQ] = tt[0]; break;
+    case OP_PQ: S[S_PQ] = t0; break;
     case OP_UPDATE:
-        S[S_RR] = tt[0];
+        S[S_RR] = t0;
         F[F_ITER] += 1;
         F[F_ITER_TOT] += 1;
-        if (tt[0] <= S[S_ETA2] * S[S_RR0]) F[F_DONE] = 1;
-        if (!I.mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = tt[1]; }
+        if (t0 <= S[S_ETA2] * S[S_RR0]) F[F_DONE] = 1;
+        if (!I.mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t1; }
         break;
-    case OP_RZ: S[S_RZOLD] = S[S_RZ]; S[S_RZ] = tt[0]; break;
+    case OP_RZ: S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t0; break;
+    case OP_CG_DOTS: {
+        // Chronopoulos-Gear recurrences: gamma = r.z, delta = (A z).z;
+        // beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old)
+        // (= r.z / p.Ap); a step length that is not positive and finite
+        // ends the inner solve (the float64 refinement carries on)
+        double alpha, beta = 0.0;
+        if (F[F_ITER] == 0) {
+            alpha = t0 / t1;
+        } else {
+            beta = t0 / S[S_CG_GAMMA];
+            alpha = t0 / (t1 - beta * t0 / S[S_CG_ALPHA]);
+        }
+        if (!(alpha > 0.0) || !(alpha < INFINITY) || !(beta < INFINITY)) F[F_DONE] = 1;
+        S[S_CG_ALPHA] = alpha;
+        S[S_CG_BETA] = beta;
+        S[S_CG_GAMMA] = t0;
+        break;
     }
+    }
+}
+
+// One block per unit: totals of the unit's partials in block order, then the
+// scalar logic of the operation on that instance.
+__global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part pt, int op)
+{
+    const Inst &I = insts[t.id[blockIdx.x]];
+    const int *F = I.F;
+    const bool inner = op == OP_PQ || op == OP_UPDATE || op == OP_RZ || op == OP_CG_DOTS;
+    if (inner && F[F_DONE]) return;
+    if (op == OP_RR64_PASS && F[F_SKIP]) return;
+    if (op == OP_INIT && F[F_CONV]) {
+        if (threadIdx.x == 0) apply_op(I, op, 0.0, 0.0);
+        return;
+    }
+    __shared__ double sh[2][4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE || op == OP_RR64_START || op == OP_CG_DOTS) ? 2 : 1;
+    const int b0 = t.boff[blockIdx.x], b1 = t.boff[blockIdx.x + 1];
+    double s[2] = {0.0, 0.0};
+    // loads of a round issued together
+    for (int k0 = b0; k0 < b1; k0 += 8 * 256) {
+        double v[2][8];
+#pragma unroll
+        for (int r = 0; r < 8; r++) {
+            const int k = k0 + r * 256 + tid;
+            v[0][r] = k < b1 ? pt.p[k] : 0.0;
+            v[1][r] = (nq > 1 && k < b1) ? pt.p[pt.stride + k] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; r++) {
+            s[0] += v[0][r];
+            s[1] += v[1][r];
+        }
+    }
+    for (int q = 0; q < 2; q++) {
+        const double w = wave_sum(s[q]);
+        if (lane == 0) sh[q][wid] = w;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    apply_op(I, op, sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
 }
 
 static void finalize(const Inst *I, const Tab &t, Part pt, int op, hipStream_t s)
@@ -637,31 +679,46 @@ void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStrea
 // fine level (launch table: tiles, bx = tiles across y).  Each block stages a
 // window of u, g and the mask around its tile in LDS (periodic axes wrap, nodes
 // outside a bounded axis enter as fixed), recomputes in the window what it
-// needs, and writes only its own tile (or its own coarse nodes).
-//   down: black half-sweep on level l, then restriction to level l + 1
-//   up:   black update with the prolonged coarse correction, then the red
-//         half-sweep (on level 0 also the r.z partials of the CG)
+// needs, and writes only its own tile (or its own coarse nodes).  Each
+// launch reads one buffer of the level and writes the other, so no block sees
+// another block's writes:
+//   down: u (red-from-zero start) -> pre-smoothing (black, then red + black
+//         NU - 1 times) -> uo, and the restricted residual to level l + 1
+//   up:   uo -> black update with the prolonged coarse correction, then red,
+//         then black + red NU - 1 times -> u (on level 0 the CG's z, with
+//         the r.z partials)
+// The post-smoothing is the pre-smoothing's colour sequence reversed, which
+// keeps the V-cycle symmetric.
 // Arithmetic per node: Gauss-Seidel value (g + neighbours) / 4 with the
 // neighbours added in the order x-1, x+1, y-1, y+1; restriction = sum over
 // the red fine nodes of the 3 x 3 stencil of weight x residual (centre 1,
-// diagonals 1/4; the black residuals vanish after the black half-sweep);
+// diagonals 1/4; the black residuals vanish after a black half-sweep);
 // bilinear prolongation of the coarse correction onto the red nodes.
 // ---------------------------------------------------------------------------
 
 constexpr int kMgTile = 32;
 constexpr int kMgThreads = 256;
-constexpr int kDnW = kMgTile + 5;   // down window: tile rows i0-3 .. i0+33
-constexpr int kUpW = kMgTile + 4;   // up window: tile rows i0-2 .. i0+33
 
 __device__ __forceinline__ int wrap_any(int x, int n) { return ((x % n) + n) % n; }
 
-// Stages u, g, fix of the W x W window with origin (wi0, wj0) on level L.
-// Fixed nodes hold u = 0 on every level (no update ever writes them), so
-// the stencils below add neighbours without testing their mask; all loads
-// of a thread are issued before the LDS stores.
+// Window index (wi0 + a, wj0 + c) -> global node of level (NX, NY), or -1
+// outside a bounded axis.
+__device__ __forceinline__ long long win_node(int NX, int NY, int px, int py, int gi, int gj)
+{
+    if (px) gi = wrap_any(gi, NX);
+    else if (gi < 0 || gi >= NX) return -1;
+    if (py) gj = wrap_any(gj, NY);
+    else if (gj < 0 || gj >= NY) return -1;
+    return (long long)gi * NY + gj;
+}
+
+// Stages u (from src), g, fix of the W x W window with origin (wi0, wj0) on
+// level L.  Fixed nodes hold u = 0 on every level (no update ever writes
+// them), so the stencils below add neighbours without testing their mask;
+// all loads of a thread are issued before the LDS stores.
 template <int W>
-__device__ __forceinline__ void mg_stage(const LevelDev &L, int px, int py, int wi0, int wj0,
-                                         float *su, float *sg, uint8_t *sf)
+__device__ __forceinline__ void mg_stage(const LevelDev &L, const float *src, const float *gsrc, int px, int py,
+                                         int wi0, int wj0, float *su, float *sg, uint8_t *sf)
 {
     constexpr int R = (W * W + kMgThreads - 1) / kMgThreads;
     float uv[R], gv[R];
@@ -670,18 +727,14 @@ __device__ __forceinline__ void mg_stage(const LevelDev &L, int px, int py, int 
     for (int r = 0; r < R; r++) {
         const int k = (int)threadIdx.x + r * kMgThreads;
         const int a = k / W, c = k - a * W;
-        int gi = wi0 + a, gj = wj0 + c;
-        bool in = k < W * W;
-        if (px) gi = wrap_any(gi, L.NX); else in = in && gi >= 0 && gi < L.NX;
-        if (py) gj = wrap_any(gj, L.NY); else in = in && gj >= 0 && gj < L.NY;
+        const long long n = k < W * W ? win_node(L.NX, L.NY, px, py, wi0 + a, wj0 + c) : -1;
         uv[r] = 0.0f;
         gv[r] = 0.0f;
         fv[r] = 1;
-        if (in) {
-            const long long n = (long long)gi * L.NY + gj;
+        if (n >= 0) {
             fv[r] = L.fix[n];
-            uv[r] = L.u[n];
-            gv[r] = L.g[n];
+            uv[r] = src[n];
+            gv[r] = gsrc[n];
         }
     }
 #pragma unroll
@@ -692,6 +745,57 @@ __device__ __forceinline__ void mg_stage(const LevelDev &L, int px, int py, int 
             sg[k] = gv[r];
             sf[k] = fv[r];
         }
+    }
+}
+
+// Level 0 of the inner CG (Chronopoulos-Gear form): stages the residual
+// after this iteration's update, r - alpha (w + beta s), as g and its
+// red-from-zero start as u.  With `update` false the residual is r itself
+// (start of a pass).  Every block evaluates the same float32 expression for
+// a node, so window copies agree with the owner's stored values.
+template <int W>
+__device__ __forceinline__ void mg_stage_l0(const Inst &I, int update, int first, float alpha, float beta,
+                                            const float *r, const float *sv, const float *wv, int wi0, int wj0,
+                                            float *su, float *sg, uint8_t *sf)
+{
+    constexpr int R = (W * W + kMgThreads - 1) / kMgThreads;
+    const LevelDev &L = I.lev[0];
+    float rv[R], s_[R], w_[R];
+    uint8_t fv[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const int k = (int)threadIdx.x + q * kMgThreads;
+        const int a = k / W, c = k - a * W;
+        const long long n = k < W * W ? win_node(L.NX, L.NY, I.g.px, I.g.py, wi0 + a, wj0 + c) : -1;
+        rv[q] = 0.0f;
+        s_[q] = 0.0f;
+        w_[q] = 0.0f;
+        fv[q] = 1;
+        if (n >= 0) {
+            fv[q] = L.fix[n];
+            rv[q] = r[n];
+            if (update) {
+                w_[q] = wv[n];
+                if (!first) s_[q] = sv[n];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const int k = (int)threadIdx.x + q * kMgThreads;
+        if (k >= W * W) continue;
+        const int a = k / W, c = k - a * W;
+        float rn = 0.0f;
+        if (!fv[q]) {
+            rn = rv[q];
+            if (update) {
+                const float sn = first ? w_[q] : w_[q] + beta * s_[q];
+                rn = rn - alpha * sn;
+            }
+        }
+        sg[k] = rn;
+        su[k] = (((a + c) & 1) == 0) ? rn * 0.25f : 0.0f;
+        sf[k] = fv[q];
     }
 }
 
@@ -708,79 +812,158 @@ __device__ __forceinline__ float win_gs(const float *su, const float *sg, int k)
     return s * 0.25f;
 }
 
-__global__ __launch_bounds__(kMgThreads) void k_mg_down(const Inst *insts, Tab t, int level)
+// One colour of Gauss-Seidel over window rows/cols m .. W-1-m.  The window
+// origin is an even offset from an even tile corner, so (a + c) & 1 is the
+// colour of the global node.
+template <int W>
+__device__ __forceinline__ void win_sweep(float *su, const float *sg, const uint8_t *sf, int m, int col)
 {
-    const int ku = unit_of(t, (int)blockIdx.x);
-    const Inst &I = insts[t.id[ku]];
-    if (I.F[F_DONE]) return;
-    const int lb = (int)blockIdx.x - t.boff[ku];
-    const int ti = lb / t.bx[ku], tj = lb - ti * t.bx[ku];
-    const LevelDev F = I.lev[level], Cc = I.lev[level + 1];
-    const int i0 = ti * kMgTile, j0 = tj * kMgTile;
-    __shared__ float su[kDnW * kDnW], sg[kDnW * kDnW], sr[kDnW * kDnW];
-    __shared__ uint8_t sf[kDnW * kDnW];
-    mg_stage<kDnW>(F, I.g.px, I.g.py, i0 - 3, j0 - 3, su, sg, sf);
-    __syncthreads();
-    // black half-sweep over window rows/cols 1 .. W-2 (red values unchanged)
-    for (int k = threadIdx.x; k < kDnW * kDnW; k += kMgThreads) {
-        const int a = k / kDnW, c = k - a * kDnW;
-        if (a < 1 || a > kDnW - 2 || c < 1 || c > kDnW - 2 || sf[k]) continue;
-        if (((i0 + j0 + a + c) & 1) != 1) continue;        // parity of the global node
-        su[k] = win_gs<kDnW>(su, sg, k);
-    }
-    __syncthreads();
-    // own black nodes back to the level; residuals at the red nodes the
-    // restriction reads (window rows/cols 2 .. W-3)
-    for (int k = threadIdx.x; k < kMgTile * kMgTile; k += kMgThreads) {
-        const int a = k / kMgTile, c = k - a * kMgTile;
-        const int gi = i0 + a, gj = j0 + c;
-        if (gi >= F.NX || gj >= F.NY || ((gi + gj) & 1) != 1) continue;
-        const int w = (a + 3) * kDnW + (c + 3);
-        if (!sf[w]) F.u[(long long)gi * F.NY + gj] = su[w];
-    }
-    for (int k = threadIdx.x; k < kDnW * kDnW; k += kMgThreads) {
-        const int a = k / kDnW, c = k - a * kDnW;
-        if (a < 2 || a > kDnW - 3 || c < 2 || c > kDnW - 3) continue;
-        if (((i0 + j0 + a + c) & 1) != 0) continue;
-        float r = 0.0f;
-        if (!sf[k]) {
-            float q = 4.0f * su[k];
-            q -= su[k - kDnW];
-            q -= su[k + kDnW];
-            q -= su[k - 1];
-            q -= su[k + 1];
-            r = sg[k] - q;
-        }
-        sr[k] = r;
-    }
-    __syncthreads();
-    // restriction: coarse nodes (i0/2 .. i0/2+15, j0/2 .. j0/2+15)
-    {
-        const int ci = threadIdx.x >> 4, cj = threadIdx.x & 15;
-        const int CI = (i0 >> 1) + ci, CJ = (j0 >> 1) + cj;
-        if (CI < Cc.NX && CJ < Cc.NY) {
-            const long long n = (long long)CI * Cc.NY + CJ;
-            float gv = 0.0f, uv = 0.0f;
-            if (!Cc.fix[n]) {
-                const int k = (2 * ci + 3) * kDnW + (2 * cj + 3);
-                float acc = 0.0f;
-                acc += 0.25f * sr[k - kDnW - 1];
-                acc += 0.25f * sr[k - kDnW + 1];
-                acc += 1.0f * sr[k];
-                acc += 0.25f * sr[k + kDnW - 1];
-                acc += 0.25f * sr[k + kDnW + 1];
-                gv = acc;
-                if (((CI + CJ) & 1) == 0) uv = gv * 0.25f;
-            }
-            Cc.g[n] = gv;
-            Cc.u[n] = uv;
-        }
+    for (int k = threadIdx.x; k < W * W; k += kMgThreads) {
+        const int a = k / W, c = k - a * W;
+        if (a < m || a > W - 1 - m || c < m || c > W - 1 - m || sf[k]) continue;
+        if (((a + c) & 1) != col) continue;
+        su[k] = win_gs<W>(su, sg, k);
     }
 }
 
-__global__ __launch_bounds__(kMgThreads) void k_mg_up(const Inst *insts, Tab t, int level, int level0_rz,
-                                                      Part pt)
+// Down half-cycle of level l with NU pre-smoothing steps: from the
+// red-from-zero start, black, then (red, black) x (NU - 1); the pre-smoothed
+// level goes to uo, the restricted residual to level l + 1 (g, and u = its
+// red-from-zero start).
+// MODE 0: level l >= 1 (start staged from u).
+// MODE 1: level 0 at the start of an inner pass: r = R[0], e = 0, ||r||^2
+//         (inner stop ratio and counters in the last block).
+// MODE 2: level 0 after a CG step: s' = w + beta s, r' = r - alpha s',
+//         p = z + beta p, e += alpha p (beta = 0 on the first step), r' and
+//         s' to the other buffers of the pair, ||r'||^2 and the inner stop
+//         test in the last block.  par: buffer of the pair holding r and s.
+template <int NU, int MODE>
+__global__ __launch_bounds__(kMgThreads) void k_mg_down(const Inst *insts, Tab t, int level, int par, Part pt)
 {
+    constexpr int HD = 2 * NU + 1, W = kMgTile + 2 * HD - 1;
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const Inst &I = insts[t.id[ku]];
+    int *F = I.F;
+    double *S = I.S;
+    const int lb = (int)blockIdx.x - t.boff[ku];
+    const int ti = lb / t.bx[ku], tj = lb - ti * t.bx[ku];
+    const LevelDev F0 = I.lev[level], Cc = I.lev[level + 1];
+    const int i0 = ti * kMgTile, j0 = tj * kMgTile;
+    __shared__ float su[W * W], sg[W * W], sr[W * W];
+    __shared__ uint8_t sf[W * W];
+    double rr = 0.0;
+    bool work = true;
+    if (MODE == 1) {
+        work = !F[F_CONV];
+    } else {
+        if (F[F_DONE]) return;
+    }
+    if (work) {
+        if (MODE == 0) {
+            mg_stage<W>(F0, F0.u, F0.g, I.g.px, I.g.py, i0 - HD, j0 - HD, su, sg, sf);
+        } else {
+            const int first = F[F_ITER] == 0;
+            const float alpha = MODE == 2 ? (float)S[S_CG_ALPHA] : 0.0f;
+            const float beta = MODE == 2 && !first ? (float)S[S_CG_BETA] : 0.0f;
+            const float *r = par ? I.cg_r1 : F0.g;
+            mg_stage_l0<W>(I, MODE == 2, first, alpha, beta, r, I.cg_s[par], I.cg_w, i0 - HD, j0 - HD, su, sg, sf);
+            __syncthreads();
+            // own tile: the vector updates and ||r'||^2 (reads the window only)
+            float *rn_out = par ? F0.g : I.cg_r1;
+            float *sn_out = I.cg_s[1 - par];
+            for (int k = threadIdx.x; k < kMgTile * kMgTile; k += kMgThreads) {
+                const int a = k / kMgTile, c = k - a * kMgTile;
+                const int gi = i0 + a, gj = j0 + c;
+                if (gi >= F0.NX || gj >= F0.NY) continue;
+                const long long n = (long long)gi * F0.NY + gj;
+                const int w = (a + HD) * W + (c + HD);
+                if (MODE == 1) {
+                    I.e[n] = 0.0f;
+                } else if (!sf[w]) {
+                    const float z = I.z[n];
+                    const float pn = first ? z : z + beta * I.p[0][n];
+                    const float sn = first ? I.cg_w[n] : I.cg_w[n] + beta * I.cg_s[par][n];
+                    I.p[0][n] = pn;
+                    I.e[n] = I.e[n] + alpha * pn;
+                    sn_out[n] = sn;
+                    rn_out[n] = sg[w];
+                } else {
+                    I.p[0][n] = 0.0f;
+                    sn_out[n] = 0.0f;
+                    rn_out[n] = 0.0f;
+                }
+                if (!sf[w]) rr += (double)sg[w] * (double)sg[w];
+            }
+        }
+        if (MODE == 0) __syncthreads();
+#pragma unroll
+        for (int m = 1; m < 2 * NU; m++) {
+            win_sweep<W>(su, sg, sf, m, m & 1);           // odd m: black, even m: red
+            __syncthreads();
+        }
+        // own nodes (both colours) to uo; residuals at the red nodes the
+        // restriction reads (window rows/cols 2NU .. W-1-2NU)
+        for (int k = threadIdx.x; k < kMgTile * kMgTile; k += kMgThreads) {
+            const int a = k / kMgTile, c = k - a * kMgTile;
+            const int gi = i0 + a, gj = j0 + c;
+            if (gi >= F0.NX || gj >= F0.NY) continue;
+            F0.uo[(long long)gi * F0.NY + gj] = su[(a + HD) * W + (c + HD)];
+        }
+        for (int k = threadIdx.x; k < W * W; k += kMgThreads) {
+            const int a = k / W, c = k - a * W;
+            if (a < 2 * NU || a > W - 1 - 2 * NU || c < 2 * NU || c > W - 1 - 2 * NU) continue;
+            if (((a + c) & 1) != 0) continue;
+            float r = 0.0f;
+            if (!sf[k]) {
+                float q = 4.0f * su[k];
+                q -= su[k - W];
+                q -= su[k + W];
+                q -= su[k - 1];
+                q -= su[k + 1];
+                r = sg[k] - q;
+            }
+            sr[k] = r;
+        }
+        __syncthreads();
+        // restriction: coarse nodes (i0/2 .. i0/2+15, j0/2 .. j0/2+15)
+        {
+            const int ci = threadIdx.x >> 4, cj = threadIdx.x & 15;
+            const int CI = (i0 >> 1) + ci, CJ = (j0 >> 1) + cj;
+            if (CI < Cc.NX && CJ < Cc.NY) {
+                const long long n = (long long)CI * Cc.NY + CJ;
+                float gv = 0.0f, uv = 0.0f;
+                if (!Cc.fix[n]) {
+                    const int k = (2 * ci + HD) * W + (2 * cj + HD);
+                    float acc = 0.0f;
+                    acc += 0.25f * sr[k - W - 1];
+                    acc += 0.25f * sr[k - W + 1];
+                    acc += 1.0f * sr[k];
+                    acc += 0.25f * sr[k + W - 1];
+                    acc += 0.25f * sr[k + W + 1];
+                    gv = acc;
+                    if (((CI + CJ) & 1) == 0) uv = gv * 0.25f;
+                }
+                Cc.g[n] = gv;
+                Cc.u[n] = uv;
+            }
+        }
+    }
+    if (MODE == 0) return;
+    double v[1] = {rr};
+    block_partials<1>(v, pt);
+}
+
+// Up half-cycle of level l with NU post-smoothing steps: black from the
+// corrected reds (pre-smoothed value + bilinear prolongation of level l+1's
+// result u), then red, then (black, red) x (NU - 1); result to u.
+// L0: level 0 of the inner CG: z = the V-cycle result on the tile and a
+// one-node ring around it, z to u (the CG's z), w = A z to cg_w, r.z and w.z
+// partials, the step scalars alpha and beta in the last block.  par: buffer
+// of the pair holding the current residual.
+template <int NU, int L0>
+__global__ __launch_bounds__(kMgThreads) void k_mg_up(const Inst *insts, Tab t, int level, int par, Part pt)
+{
+    constexpr int HU = 2 * NU + L0, W = kMgTile + 2 * HU;
     const int ku = unit_of(t, (int)blockIdx.x);
     const Inst &I = insts[t.id[ku]];
     if (I.F[F_DONE]) return;
@@ -788,66 +971,115 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_up(const Inst *insts, Tab t, 
     const int ti = lb / t.bx[ku], tj = lb - ti * t.bx[ku];
     const LevelDev F = I.lev[level], Cc = I.lev[level + 1];
     const int i0 = ti * kMgTile, j0 = tj * kMgTile;
-    __shared__ float su[kUpW * kUpW], sg[kUpW * kUpW], sc[kUpW * kUpW];
-    __shared__ uint8_t sf[kUpW * kUpW];
-    mg_stage<kUpW>(F, I.g.px, I.g.py, i0 - 2, j0 - 2, su, sg, sf);
+    __shared__ float su[W * W], sg[W * W], sc[W * W];
+    __shared__ uint8_t sf[W * W];
+    const float *gsrc = (L0 && par) ? I.cg_r1 : F.g;
+    mg_stage<W>(F, F.uo, gsrc, I.g.px, I.g.py, i0 - HU, j0 - HU, su, sg, sf);
     __syncthreads();
     // red nodes: value plus the prolonged coarse correction (0 on fixed nodes)
-    for (int k = threadIdx.x; k < kUpW * kUpW; k += kMgThreads) {
-        const int a = k / kUpW, c = k - a * kUpW;
-        int gi = i0 - 2 + a, gj = j0 - 2 + c;
+    for (int k = threadIdx.x; k < W * W; k += kMgThreads) {
+        const int a = k / W, c = k - a * W;
+        int gi = i0 - HU + a, gj = j0 - HU + c;
         float v = 0.0f;
-        if (((gi + gj) & 1) == 0 && !sf[k]) {
+        if (((a + c) & 1) == 0 && !sf[k]) {
             if (I.g.px) gi = wrap_any(gi, F.NX);
             if (I.g.py) gj = wrap_any(gj, F.NY);
-            v = su[k] + prolong_red(Cc.uo, Cc.NX, Cc.NY, gi, gj);
+            v = su[k] + prolong_red(Cc.u, Cc.NX, Cc.NY, gi, gj);
         }
         sc[k] = v;
     }
     __syncthreads();
     // black update over window rows/cols 1 .. W-2 from the corrected reds
-    for (int k = threadIdx.x; k < kUpW * kUpW; k += kMgThreads) {
-        const int a = k / kUpW, c = k - a * kUpW;
-        if (a < 1 || a > kUpW - 2 || c < 1 || c > kUpW - 2 || sf[k]) continue;
-        if (((i0 + j0 + a + c) & 1) != 1) continue;
+    for (int k = threadIdx.x; k < W * W; k += kMgThreads) {
+        const int a = k / W, c = k - a * W;
+        if (a < 1 || a > W - 2 || c < 1 || c > W - 2 || sf[k]) continue;
+        if (((a + c) & 1) != 1) continue;
         float s = sg[k];
-        s += sc[k - kUpW];
-        s += sc[k + kUpW];
+        s += sc[k - W];
+        s += sc[k + W];
         s += sc[k - 1];
         s += sc[k + 1];
         su[k] = s * 0.25f;
     }
     __syncthreads();
-    // red half-sweep on the own tile; write both colours to uo
-    double rz = 0.0;
+    constexpr int MEND = L0 ? 2 * NU + 1 : 2 * NU;
+#pragma unroll
+    for (int m = 2; m < MEND; m++) {
+        win_sweep<W>(su, sg, sf, m, m & 1);               // even m: red, odd m: black
+        __syncthreads();
+    }
+    if (!L0) {
+        // last red half-sweep on the own tile; write both colours to u
+        for (int k = threadIdx.x; k < kMgTile * kMgTile; k += kMgThreads) {
+            const int a = k / kMgTile, c = k - a * kMgTile;
+            const int gi = i0 + a, gj = j0 + c;
+            if (gi >= F.NX || gj >= F.NY) continue;
+            const int w = (a + HU) * W + (c + HU);
+            float z = 0.0f;                               // fixed nodes carry no correction
+            if (!sf[w]) {
+                z = su[w];
+                if (((gi + gj) & 1) == 0) z = win_gs<W>(su, sg, w);
+            }
+            F.u[(long long)gi * F.NY + gj] = z;
+        }
+        return;
+    }
+    // level 0: the last red sweep covered the tile and its ring; z = su
+    // (0 on fixed nodes), w = A z with the neighbours in the order x-1, x+1,
+    // y-1, y+1
+    double rz = 0.0, wz = 0.0;
     for (int k = threadIdx.x; k < kMgTile * kMgTile; k += kMgThreads) {
         const int a = k / kMgTile, c = k - a * kMgTile;
         const int gi = i0 + a, gj = j0 + c;
         if (gi >= F.NX || gj >= F.NY) continue;
-        const int w = (a + 2) * kUpW + (c + 2);
-        float z = 0.0f;                                   // fixed nodes carry no correction
+        const long long n = (long long)gi * F.NY + gj;
+        const int w = (a + HU) * W + (c + HU);
+        float z = 0.0f, wv = 0.0f;
         if (!sf[w]) {
             z = su[w];
-            if (((gi + gj) & 1) == 0) z = win_gs<kUpW>(su, sg, w);
-            if (level0_rz) rz += (double)sg[w] * (double)z;
+            float q = 4.0f * z;
+            q -= su[w - W];
+            q -= su[w + W];
+            q -= su[w - 1];
+            q -= su[w + 1];
+            wv = q;
+            rz += (double)sg[w] * (double)z;
+            wz += (double)wv * (double)z;
         }
-        F.uo[(long long)gi * F.NY + gj] = z;
+        F.u[n] = z;
+        I.cg_w[n] = wv;
     }
-    if (!level0_rz) return;
-    double v[1] = {rz};
-    block_partials<1>(v, pt);
+    double v[2] = {rz, wz};
+    block_partials<2>(v, pt);
 }
 
-void launch_mg_down(const Inst *I, const Tab &t, int level, hipStream_t s)
-{
-    if (t.n) hipLaunchKernelGGL(k_mg_down, dim3(tab_blocks(t)), dim3(kMgThreads), 0, s, I, t, level);
-}
+constexpr int kMgSmooth = 1;     // pre- and post-smoothing steps on the fine levels
 
-void launch_mg_up(const Inst *I, const Tab &t, int level, int level0_rz, Part pt, hipStream_t s)
+void launch_mg_down(const Inst *I, const Tab &t, int level, int mode, int par, Part pt, hipStream_t s)
 {
     if (!t.n) return;
-    hipLaunchKernelGGL(k_mg_up, dim3(tab_blocks(t)), dim3(kMgThreads), 0, s, I, t, level, level0_rz, pt);
-    if (level0_rz) finalize(I, t, pt, OP_RZ, s);
+    const dim3 g(tab_blocks(t)), b(kMgThreads);
+    if (mode == 0) {
+        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 0>), g, b, 0, s, I, t, level, par, pt);
+    } else if (mode == 1) {
+        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 1>), g, b, 0, s, I, t, level, par, pt);
+        finalize(I, t, pt, OP_INIT, s);
+    } else {
+        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 2>), g, b, 0, s, I, t, level, par, pt);
+        finalize(I, t, pt, OP_UPDATE, s);
+    }
+}
+
+void launch_mg_up(const Inst *I, const Tab &t, int level, int par, Part pt, hipStream_t s)
+{
+    if (!t.n) return;
+    const dim3 g(tab_blocks(t)), b(kMgThreads);
+    if (level == 0) {
+        hipLaunchKernelGGL((k_mg_up<kMgSmooth, 1>), g, b, 0, s, I, t, level, par, pt);
+        finalize(I, t, pt, OP_CG_DOTS, s);
+    } else {
+        hipLaunchKernelGGL((k_mg_up<kMgSmooth, 0>), g, b, 0, s, I, t, level, par, pt);
+    }
 }
 
 // ---------------------------------------------------------------------------

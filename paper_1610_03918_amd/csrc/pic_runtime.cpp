@@ -188,6 +188,7 @@ struct InstHost {
     uint8_t *d_fix[kMaxLev] = {};
     float *d_u[kMaxLev] = {}, *d_g[kMaxLev] = {}, *d_uo[kMaxLev] = {};
     float *d_e = nullptr, *d_p[2] = {}, *d_q = nullptr;
+    float *d_cg_r1 = nullptr, *d_cg_s[2] = {}, *d_cg_w = nullptr;
     float4 *d_E4 = nullptr;
     double *d_phi_prev = nullptr;
     unsigned *d_counts[2] = {}, *d_offsets[2] = {}, *d_cursor[2] = {}, *d_boff[2] = {};
@@ -236,6 +237,7 @@ struct pic_ctx {
     std::vector<double> vhost;
     // launch tables
     Tab t_l0{}, t_field{}, t_per{}, t_coarse{}, t_push{}, t_rewind{};
+    Tab t_plain{};                 // level-0 grid of the instances solved by plain CG
     Tab t_fine[kMaxLev] = {};      // 32 x 32 tiles of the fine multigrid levels
     int maxlg = 0, coarse_lds = 0, any_mg = 0;
     size_t push_lds = 0;
@@ -304,11 +306,15 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     for (int l = 0; l < L.nlev; l++) {
         u[l] = w.take<float>((size_t)L.NXl[l] * L.NYl[l]);
         gg[l] = w.take<float>((size_t)L.NXl[l] * L.NYl[l]);
-        // fine multigrid levels keep the up half-cycle's result apart from its input
+        // fine multigrid levels keep the down half-cycle's result apart from its input
         if (L.mg && l < L.lg) uo[l] = w.take<float>((size_t)L.NXl[l] * L.NYl[l]);
     }
     float *e = w.take<float>(nodes), *p0 = w.take<float>(nodes), *p1 = w.take<float>(nodes);
     float *q = w.take<float>(nodes);
+    // multigrid-preconditioned CG: second residual buffer, the s pair, w
+    float *cg[4] = {};
+    if (L.mg)
+        for (int k = 0; k < 4; k++) cg[k] = w.take<float>(nodes);
     float4 *E4 = w.take<float4>(2 * cells);
     double *phi_prev = w.take<double>(nodes);
     unsigned *counts[2], *offs[2], *curs[2], *boff[2];
@@ -342,6 +348,10 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     h->d_p[0] = p0;
     h->d_p[1] = p1;
     h->d_q = q;
+    h->d_cg_r1 = cg[0];
+    h->d_cg_s[0] = cg[1];
+    h->d_cg_s[1] = cg[2];
+    h->d_cg_w = cg[3];
     h->d_E4 = E4;
     h->d_phi_prev = phi_prev;
     for (int s = 0; s < 2; s++) {
@@ -368,7 +378,8 @@ size_t carve_all(pic_ctx *c, int n, const pic_config *cfgs, const int64_t *caps,
     int stride = 0;
     for (int k = 0; k < n; k++) {
         Layout L = make_layout(&cfgs[k], caps + 2 * k);
-        stride += grid_blocks(std::max(L.NX, L.nx), std::max(L.NY, L.ny));
+        const int tiles0 = ((L.NX + kMgTileHost - 1) / kMgTileHost) * ((L.NY + kMgTileHost - 1) / kMgTileHost);
+        stride += std::max(grid_blocks(std::max(L.NX, L.nx), std::max(L.NY, L.ny)), tiles0);
     }
     Inst *di = w.take<Inst>(n);
     PushArgs *dp = w.take<PushArgs>(2 * n);
@@ -472,33 +483,43 @@ void enqueue_deposit(pic_ctx *c, hipStream_t s)
     enqueue_assemble(c, s);
 }
 
-// One V-cycle after the level-0 red-from-zero sweep (already applied).
-void enqueue_vcycle_rest(pic_ctx *c, hipStream_t s)
+// Levels 1 .. of a V-cycle: down half-cycles, the LDS levels, up
+// half-cycles (level 0's halves carry the CG step and its dot products).
+void enqueue_vcycle_mid(pic_ctx *c, hipStream_t s)
 {
-    if (!c->any_mg) return;
     Part pt = part_of(c);
-    for (int l = 0; l < c->maxlg; l++) launch_mg_down(c->d_inst, c->t_fine[l], l, s);
+    for (int l = 1; l < c->maxlg; l++) launch_mg_down(c->d_inst, c->t_fine[l], l, 0, 0, pt, s);
     launch_coarse(c->d_inst, c->t_coarse, c->coarse_lds, s);
-    for (int l = c->maxlg - 1; l >= 0; l--) launch_mg_up(c->d_inst, c->t_fine[l], l, l == 0 ? 1 : 0, pt, s);
+    for (int l = c->maxlg - 1; l >= 1; l--) launch_mg_up(c->d_inst, c->t_fine[l], l, 0, pt, s);
 }
 
-// Start of a refinement pass: inner CG from e = 0 (first residual, z, r.z).
+// Start of a refinement pass: inner CG from e = 0.  Plain CG: first
+// residual, z = r / 4, r.z.  Multigrid: ||r||^2, then the V-cycle of r
+// with z, w = A z and the first step's alpha.
 void enqueue_pass_begin(pic_ctx *c, hipStream_t s)
 {
-    launch_init_red0(c->d_inst, c->t_l0, part_of(c), s);
-    enqueue_vcycle_rest(c, s);
+    Part pt = part_of(c);
+    launch_init_red0(c->d_inst, c->t_plain, pt, s);
+    if (!c->any_mg) return;
+    launch_mg_down(c->d_inst, c->t_fine[0], 0, 1, 0, pt, s);
+    enqueue_vcycle_mid(c, s);
+    launch_mg_up(c->d_inst, c->t_fine[0], 0, 0, pt, s);
 }
 
 // K inner iterations; `first` when they open the pass.  Continuation chunks
-// must follow an even number of iterations (the search direction ping-pongs
-// between two buffers by iteration parity).
+// must follow an even number of iterations (plain CG: the search direction
+// ping-pongs between two buffers by iteration parity; multigrid: so do the
+// residual and s = A p).
 void enqueue_iters(pic_ctx *c, int K, bool first, hipStream_t s)
 {
     Part pt = part_of(c);
     for (int k = 0; k < K; k++) {
-        launch_pupdate_Ap(c->d_inst, c->t_l0, k & 1, (first && k == 0) ? 1 : 0, pt, s);
-        launch_update_red0(c->d_inst, c->t_l0, (k + 1) & 1, pt, s);
-        enqueue_vcycle_rest(c, s);
+        launch_pupdate_Ap(c->d_inst, c->t_plain, k & 1, (first && k == 0) ? 1 : 0, pt, s);
+        launch_update_red0(c->d_inst, c->t_plain, (k + 1) & 1, pt, s);
+        if (!c->any_mg) continue;
+        launch_mg_down(c->d_inst, c->t_fine[0], 0, 2, k & 1, pt, s);
+        enqueue_vcycle_mid(c, s);
+        launch_mg_up(c->d_inst, c->t_fine[0], 0, (k + 1) & 1, pt, s);
     }
 }
 
@@ -786,7 +807,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
         d.lev[l].g = h.d_g[l];
         d.lev[l].fix = h.d_fix[l];
     }
-    d.z = L.mg ? h.d_uo[0] : h.d_u[0];
+    d.z = h.d_u[0];
     d.node_cond = h.d_node_cond;
     d.cell_cond = h.d_cell_cond;
     d.phi = buf->phi;
@@ -798,6 +819,10 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
     d.p[0] = h.d_p[0];
     d.p[1] = h.d_p[1];
     d.q = h.d_q;
+    d.cg_r1 = h.d_cg_r1;
+    d.cg_s[0] = h.d_cg_s[0];
+    d.cg_s[1] = h.d_cg_s[1];
+    d.cg_w = h.d_cg_w;
     d.E4 = h.d_E4;
     d.S = c->d_S + (size_t)k * S_NSCAL;
     d.F = c->d_F + (size_t)k * F_NFLAG;
@@ -916,6 +941,10 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
     HIPCHK(c, hipMemsetAsync(h.d_e, 0, sizeof(float) * (size_t)L.NX * L.NY, s));
     HIPCHK(c, hipMemsetAsync(h.d_p[0], 0, sizeof(float) * (size_t)L.NX * L.NY, s));
     HIPCHK(c, hipMemsetAsync(h.d_p[1], 0, sizeof(float) * (size_t)L.NX * L.NY, s));
+    if (L.mg) {
+        for (float *b : {h.d_cg_r1, h.d_cg_s[0], h.d_cg_s[1], h.d_cg_w})
+            HIPCHK(c, hipMemsetAsync(b, 0, sizeof(float) * (size_t)L.NX * L.NY, s));
+    }
     HIPCHK(c, hipMemsetAsync(h.d_counts[0], 0, sizeof(unsigned) * L.ntiles, s));
     HIPCHK(c, hipMemsetAsync(h.d_counts[1], 0, sizeof(unsigned) * L.ntiles, s));
     HIPCHK(c, hipMemsetAsync(buf->phi, 0, sizeof(double) * (size_t)L.NX * L.NY, s));
@@ -924,7 +953,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
 
 void build_tabs(pic_ctx *c)
 {
-    c->t_l0 = c->t_field = c->t_per = c->t_coarse = c->t_push = c->t_rewind = Tab{};
+    c->t_l0 = c->t_field = c->t_per = c->t_coarse = c->t_push = c->t_rewind = c->t_plain = Tab{};
     for (int l = 0; l < kMaxLev; l++) c->t_fine[l] = Tab{};
     c->maxlg = 0;
     c->coarse_lds = 0;
@@ -936,6 +965,7 @@ void build_tabs(pic_ctx *c)
         tab_add_grid(c->t_l0, k, L.NX, L.NY);
         tab_add_grid(c->t_field, k, std::max(L.NX, L.nx), std::max(L.NY, L.ny));
         if (L.px && L.py) tab_add_grid(c->t_per, k, L.NX, L.NY);
+        if (!L.mg) tab_add_grid(c->t_plain, k, L.NX, L.NY);
         if (L.mg) {
             c->any_mg = 1;
             c->maxlg = std::max(c->maxlg, L.lg);
