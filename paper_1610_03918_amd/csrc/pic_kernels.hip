@@ -862,7 +862,7 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_down(const Inst *insts, Tab t
         if (MODE == 0) {
             mg_stage<W>(F0, F0.u, F0.g, I.g.px, I.g.py, i0 - HD, j0 - HD, su, sg, sf);
         } else {
-            const int first = F[F_ITER] == 0;
+            const int first = MODE == 2 ? F[F_ITER] == 0 : 1;
             const float alpha = MODE == 2 ? (float)S[S_CG_ALPHA] : 0.0f;
             const float beta = MODE == 2 && !first ? (float)S[S_CG_BETA] : 0.0f;
             const float *r = par ? I.cg_r1 : F0.g;
@@ -1088,82 +1088,111 @@ void launch_mg_up(const Inst *I, const Tab &t, int level, int par, Part pt, hipS
 // ---------------------------------------------------------------------------
 
 // Gauss-Seidel value from the four neighbours without mask tests: fixed
-// nodes hold u = 0 on the LDS levels (staged as 0, never updated).
+// nodes hold u = 0 on the LDS levels (staged as 0, never updated).  A free
+// node never lies on a bounded edge, so only periodic axes wrap.
 __device__ __forceinline__ float gs_nofix(const float *u, const float *gg, int i, int j, int NX, int NY)
 {
     Nb b = nbs(i, j, NX, NY);
-    float s = gg[(long long)i * NY + j];
-    s += u[(long long)b.im * NY + j];
-    s += u[(long long)b.ip * NY + j];
-    s += u[(long long)i * NY + b.jm];
-    s += u[(long long)i * NY + b.jp];
+    float s = gg[i * NY + j];
+    s += u[b.im * NY + j];
+    s += u[b.ip * NY + j];
+    s += u[i * NY + b.jm];
+    s += u[i * NY + b.jp];
     return s * 0.25f;
 }
 
+// q / d for 0 <= q < 2^22 and d >= 1 from rcp = 1/d in float32: the exact
+// quotient (q + 1/2) / d lies at least 1/(2d) from an integer, more than
+// the rounding error of the product.
+__device__ __forceinline__ int div_rcp(int q, float rcp) { return (int)(((float)q + 0.5f) * rcp); }
+
+// Residual g - A u at a node of an LDS level (0 at fixed nodes).
+__device__ __forceinline__ float resid_nofix(const float *u, const float *gg, const uint8_t *f, int i, int j,
+                                             int NX, int NY)
+{
+    const int k = i * NY + j;
+    if (f[k]) return 0.0f;
+    Nb b = nbs(i, j, NX, NY);
+    float q = 4.0f * u[k];
+    q -= u[b.im * NY + j];
+    q -= u[b.ip * NY + j];
+    q -= u[i * NY + b.jm];
+    q -= u[i * NY + b.jp];
+    return gg[k] - q;
+}
+
+// Red node value plus the prolonged correction of the next coarser level
+// (0 at fixed nodes).
+__device__ __forceinline__ float corrected_red(const float *u, const uint8_t *f, const float *uc, int i, int j,
+                                               int NY, int NXc, int NYc)
+{
+    const int k = i * NY + j;
+    return f[k] ? 0.0f : u[k] + prolong_red(uc, NXc, NYc, i, j);
+}
+
+// The levels from lg on: one 1024-thread work-group per instance, every level
+// in LDS.  Per level on the way down a black half-sweep, then the restriction
+// of the red residuals (formed on the fly) to the next level with its
+// red-from-zero start; on the coarsest level red-black sweeps; per level on
+// the way up the black update from the corrected reds (formed on the fly),
+// then a red half-sweep.  Half-sweeps visit the nodes of their colour only.
 __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
 {
     const Inst &I = insts[t.id[blockIdx.x]];
     if (I.F[F_DONE]) return;
     const CoarseArgs &a = I.coarse;
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int tab[5][kMaxLev];
+    __shared__ int tab[3][kMaxLev];
+    __shared__ int dims[2][kMaxLev];
     const int tid = threadIdx.x, nt = blockDim.x;
     if (tid < a.nlev) {
         tab[0][tid] = a.off_u[tid];
         tab[1][tid] = a.off_g[tid];
         tab[2][tid] = a.off_f[tid];
+        dims[0][tid] = a.NX[tid];
+        dims[1][tid] = a.NY[tid];
     }
     __syncthreads();
 #define u(l) ((float *)(lds + tab[0][l]))
 #define gg(l) ((float *)(lds + tab[1][l]))
 #define fx(l) ((uint8_t *)(lds + tab[2][l]))
-    float *sr = (float *)(lds + a.off_s);   // per level: red residuals (down), corrected reds (up)
     for (int l = 0; l < a.nlev; l++) {
-        const int N = a.NX[l] * a.NY[l];
+        const int N = dims[0][l] * dims[1][l];
         const uint8_t *src = a.fix[l];
         for (int k = tid; k < N; k += nt) fx(l)[k] = src[k];
     }
     {
-        const int N = a.NX[0] * a.NY[0];
+        const int NY = dims[1][0], N = dims[0][0] * NY;
+        const float rcp = 1.0f / (float)NY;
         for (int k = tid; k < N; k += nt) {
-            float gv = a.g_top[k];
+            const float gv = a.g_top[k];
             gg(0)[k] = gv;
-            int i = k / a.NY[0], j = k - i * a.NY[0];
+            const int i = div_rcp(k, rcp), j = k - i * NY;
             u(0)[k] = (!a.fix[0][k] && ((i + j) & 1) == 0) ? gv * 0.25f : 0.0f;
         }
     }
     __syncthreads();
-    // descend: black half-sweep, residuals at the red nodes, restriction
+    // descend
     for (int l = 0; l < a.nlev - 1; l++) {
-        const int NX = a.NX[l], NY = a.NY[l], N = NX * NY;
-        float *ul = u(l), *gl = gg(l);
+        const int NX = dims[0][l], NY = dims[1][l];
+        const int HW = (NY + 1) >> 1;
+        const float rcpw = 1.0f / (float)HW;
+        float *ul = u(l);
+        const float *gl = gg(l);
         const uint8_t *fl = fx(l);
-        for (int k = tid; k < N; k += nt) {
-            int i = k / NY, j = k - i * NY;
-            if (!fl[k] && ((i + j) & 1) == 1) ul[k] = gs_nofix(ul, gl, i, j, NX, NY);
+        for (int q = tid; q < NX * HW; q += nt) {          // black half-sweep
+            const int i = div_rcp(q, rcpw), j = 2 * (q - i * HW) + ((i + 1) & 1);
+            if (j < NY && !fl[i * NY + j]) ul[i * NY + j] = gs_nofix(ul, gl, i, j, NX, NY);
         }
         __syncthreads();
-        for (int k = tid; k < N; k += nt) {
-            int i = k / NY, j = k - i * NY;
-            if (((i + j) & 1) != 0) continue;
-            float r = 0.0f;
-            if (!fl[k]) {
-                Nb b = nbs(i, j, NX, NY);
-                float q = 4.0f * ul[k];
-                q -= ul[(long long)b.im * NY + j];
-                q -= ul[(long long)b.ip * NY + j];
-                q -= ul[(long long)i * NY + b.jm];
-                q -= ul[(long long)i * NY + b.jp];
-                r = gl[k] - q;
-            }
-            sr[k] = r;
-        }
-        __syncthreads();
-        const int NXc = a.NX[l + 1], NYc = a.NY[l + 1], Nc = NXc * NYc;
-        for (int k = tid; k < Nc; k += nt) {
-            int Ic = k / NYc, Jc = k - Ic * NYc;
+        const int NXc = dims[0][l + 1], NYc = dims[1][l + 1];
+        const float rcpc = 1.0f / (float)NYc;
+        float *uc = u(l + 1), *gc = gg(l + 1);
+        const uint8_t *fc = fx(l + 1);
+        for (int k = tid; k < NXc * NYc; k += nt) {        // restriction
+            const int Ic = div_rcp(k, rcpc), Jc = k - Ic * NYc;
             float gv = 0.0f, uv = 0.0f;
-            if (!fx(l + 1)[k]) {
+            if (!fc[k]) {
                 float acc = 0.0f;
 #pragma unroll
                 for (int di = -1; di <= 1; di++) {
@@ -1176,14 +1205,14 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
                         if (a.py) cj = wrap_hi(wrap_lo(cj, NY), NY);
                         else if (cj < 0 || cj >= NY) continue;
                         const float w = (di == 0) ? 1.0f : 0.25f;
-                        acc += w * sr[(long long)ai * NY + cj];
+                        acc += w * resid_nofix(ul, gl, fl, ai, cj, NX, NY);
                     }
                 }
                 gv = acc;
                 if (((Ic + Jc) & 1) == 0) uv = gv * 0.25f;
             }
-            gg(l + 1)[k] = gv;
-            u(l + 1)[k] = uv;
+            gc[k] = gv;
+            uc[k] = uv;
         }
         __syncthreads();
     }
@@ -1192,11 +1221,12 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
     // lanes run in lockstep and LDS serves one wavefront's accesses in
     // order, so a wavefront barrier separates the colours.
     {
-        const int l = a.nlev - 1, NX = a.NX[l], NY = a.NY[l], N = NX * NY;
+        const int l = a.nlev - 1, NX = dims[0][l], NY = dims[1][l], N = NX * NY;
+        const float rcp = 1.0f / (float)NY;
         if (N <= 64) {
             if (tid < 64) {
                 const int k = tid;
-                const int i = k / NY, j = k - i * NY;
+                const int i = div_rcp(k, rcp), j = k - i * NY;
                 const bool mine = k < N && !fx(l)[k];
                 for (int sw = 0; sw < a.sweeps; sw++) {
                     for (int col = 1; col >= 0; col--) {
@@ -1212,7 +1242,7 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
             for (int sw = 0; sw < a.sweeps; sw++) {
                 for (int col = 1; col >= 0; col--) {
                     for (int k = tid; k < N; k += nt) {
-                        int i = k / NY, j = k - i * NY;
+                        const int i = div_rcp(k, rcp), j = k - i * NY;
                         if (!fx(l)[k] && ((i + j) & 1) == col) u(l)[k] = gs_nofix(u(l), gg(l), i, j, NX, NY);
                     }
                     __syncthreads();
@@ -1220,38 +1250,35 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
             }
         }
     }
-    // ascend: corrected reds, black update from them, red half-sweep
+    // ascend
     for (int l = a.nlev - 2; l >= 0; l--) {
-        const int NX = a.NX[l], NY = a.NY[l], N = NX * NY;
-        const int NXc = a.NX[l + 1], NYc = a.NY[l + 1];
-        float *ul = u(l), *gl = gg(l);
+        const int NX = dims[0][l], NY = dims[1][l];
+        const int NXc = dims[0][l + 1], NYc = dims[1][l + 1];
+        const int HW = (NY + 1) >> 1;
+        const float rcpw = 1.0f / (float)HW;
+        float *ul = u(l);
+        const float *gl = gg(l), *uc = u(l + 1);
         const uint8_t *fl = fx(l);
-        for (int k = tid; k < N; k += nt) {
-            int i = k / NY, j = k - i * NY;
-            if (((i + j) & 1) != 0) continue;
-            sr[k] = fl[k] ? 0.0f : ul[k] + prolong_red(u(l + 1), NXc, NYc, i, j);
-        }
-        __syncthreads();
-        for (int k = tid; k < N; k += nt) {
-            int i = k / NY, j = k - i * NY;
-            if (fl[k] || ((i + j) & 1) != 1) continue;
+        for (int q = tid; q < NX * HW; q += nt) {          // black update from the corrected reds
+            const int i = div_rcp(q, rcpw), j = 2 * (q - i * HW) + ((i + 1) & 1);
+            if (j >= NY || fl[i * NY + j]) continue;
             Nb b = nbs(i, j, NX, NY);
-            float s = gl[k];
-            s += sr[(long long)b.im * NY + j];
-            s += sr[(long long)b.ip * NY + j];
-            s += sr[(long long)i * NY + b.jm];
-            s += sr[(long long)i * NY + b.jp];
-            ul[k] = s * 0.25f;
+            float s = gl[i * NY + j];
+            s += corrected_red(ul, fl, uc, b.im, j, NY, NXc, NYc);
+            s += corrected_red(ul, fl, uc, b.ip, j, NY, NXc, NYc);
+            s += corrected_red(ul, fl, uc, i, b.jm, NY, NXc, NYc);
+            s += corrected_red(ul, fl, uc, i, b.jp, NY, NXc, NYc);
+            ul[i * NY + j] = s * 0.25f;
         }
         __syncthreads();
-        for (int k = tid; k < N; k += nt) {
-            int i = k / NY, j = k - i * NY;
-            if (!fl[k] && ((i + j) & 1) == 0) ul[k] = gs_nofix(ul, gl, i, j, NX, NY);
+        for (int q = tid; q < NX * HW; q += nt) {          // red half-sweep
+            const int i = div_rcp(q, rcpw), j = 2 * (q - i * HW) + (i & 1);
+            if (j < NY && !fl[i * NY + j]) ul[i * NY + j] = gs_nofix(ul, gl, i, j, NX, NY);
         }
         __syncthreads();
     }
     {
-        const int N = a.NX[0] * a.NY[0];
+        const int N = dims[0][0] * dims[1][0];
         for (int k = tid; k < N; k += nt) a.u_top[k] = u(0)[k];
     }
 #undef u

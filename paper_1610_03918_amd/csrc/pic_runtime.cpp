@@ -21,8 +21,8 @@ using namespace pic;
 
 namespace {
 
-constexpr int kCoarseMaxNodes = 4096;   // largest level solved inside one work-group
-constexpr int kCoarseMaxLds = 64 * 1024;
+constexpr int kCoarseMaxNodes = 12288;  // largest level solved inside one work-group
+constexpr int kCoarseMaxLds = 159 * 1024;   // dynamic LDS of the coarse kernel (160 KiB per work-group)
 constexpr int kMaxTiming = 512;
 
 struct Layout {
@@ -138,19 +138,19 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
         L.NYl[L.nlev] = coarser(L.NYl[L.nlev - 1], L.py);
         L.nlev++;
     }
-    // coarse kernel takes every level from lg on; lg >= 1 and level lg must fit
-    L.lg = 1;
-    while (L.lg < L.nlev && L.NXl[L.lg] * L.NYl[L.lg] > kCoarseMaxNodes) L.lg++;
-    L.mg = (c->solver == 0) && L.nlev >= 2 && L.lg < L.nlev;
-    if (L.mg) {
+    // coarse kernel takes every level from lg on: the first level from 1 on
+    // within kCoarseMaxNodes whose levels fit in the kernel's LDS together
+    auto lds_from = [&](int lg) {
         size_t lds = 0;
-        for (int l = L.lg; l < L.nlev; l++) {
+        for (int l = lg; l < L.nlev; l++) {
             size_t n = (size_t)L.NXl[l] * L.NYl[l];
             lds += ((n * 4 + 15) & ~size_t(15)) * 2 + ((n + 15) & ~size_t(15));
         }
-        if (L.lg < L.nlev) lds += ((size_t)L.NXl[L.lg] * L.NYl[L.lg] * 4 + 15) & ~size_t(15);
-        if (lds > kCoarseMaxLds) L.mg = false;
-    }
+        return lds;
+    };
+    L.lg = 1;
+    while (L.lg < L.nlev && (L.NXl[L.lg] * L.NYl[L.lg] > kCoarseMaxNodes || lds_from(L.lg) > kCoarseMaxLds)) L.lg++;
+    L.mg = (c->solver == 0) && L.nlev >= 2 && L.lg < L.nlev;
     L.TX = c->tile_x ? c->tile_x : 16;
     L.TY = c->tile_y ? c->tile_y : 16;
     L.lx = ilog2(L.TX);
@@ -852,8 +852,6 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
             off += (nn + 15) & ~15;
             ca.fix[q] = h.d_fix[l];
         }
-        ca.off_s = off;
-        off += (L.NXl[L.lg] * L.NYl[L.lg] * 4 + 15) & ~15;
         ca.lds_bytes = off;
         ca.u_top = h.d_u[L.lg];
         ca.g_top = h.d_g[L.lg];
