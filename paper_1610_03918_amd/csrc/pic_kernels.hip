@@ -2060,17 +2060,24 @@ __device__ __forceinline__ BView bview(const BinArgs &a)
     return v;
 }
 
-__device__ __forceinline__ void bin_local_count(const BinArgs &a, const BView &v, long long lo,
-                                                long long hi,
-                                                unsigned *hist, bool count_bad)
+// Loads the block's cell codes (all loads issued before use) and counts the
+// live ones per tile: tiles below kBinLds in LDS, the rest in global counts
+// (count pass only).
+constexpr int kBinRP = kBinPer / 256;
+__device__ __forceinline__ void bin_local_count(const BinArgs &a, const BView &v, long long lo, long long hi,
+                                                unsigned *hist, bool count_bad, int (&cv)[kBinRP])
 {
     const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
+#pragma unroll
+    for (int r8 = 0; r8 < kBinRP; r8++) {
+        const long long p = lo + r8 * 256 + threadIdx.x;
+        cv[r8] = p < hi ? v.cell[p] : -1;
+    }
     for (int k = threadIdx.x; k < nl; k += 256) hist[k] = 0u;
     __syncthreads();
-    for (long long p0 = lo; p0 < hi; p0 += 256) {
-        const long long p = p0 + threadIdx.x;
-        int c = -1;
-        if (p < hi) c = v.cell[p];
+#pragma unroll
+    for (int r8 = 0; r8 < kBinRP; r8++) {
+        const int c = cv[r8];
         const bool act = live_code(c, a.nx, a.ny);
         if (count_bad && c >= 0 && !act) atomicAdd(a.bad, 1ull);
         const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
@@ -2078,6 +2085,23 @@ __device__ __forceinline__ void bin_local_count(const BinArgs &a, const BView &v
         if (count_bad) wave_add(a.counts, key, act && key >= kBinLds);
     }
     __syncthreads();
+}
+
+// Exclusive prefix sum of one value per thread over a 256-thread block.
+__device__ __forceinline__ unsigned block_exclusive_scan(unsigned x, unsigned *wsum)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    unsigned before = 0;
+    for (int w = 0; w < wid; w++) before += wsum[w];
+    return before + inc - x;
 }
 
 __global__ __launch_bounds__(256) void k_bin_count(const BinArgs *B, Tab t)
@@ -2090,7 +2114,8 @@ __global__ __launch_bounds__(256) void k_bin_count(const BinArgs *B, Tab t)
     const long long lo = (long long)((int)blockIdx.x - t.boff[ku]) * kBinPer;
     if (lo >= n) return;
     const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
-    bin_local_count(a, v, lo, hi, hist, true);
+    int cv[kBinRP];
+    bin_local_count(a, v, lo, hi, hist, true, cv);
     const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
     for (int k = threadIdx.x; k < nl; k += 256)
         if (hist[k]) atomicAdd(&a.counts[k], hist[k]);
@@ -2165,17 +2190,37 @@ __device__ __forceinline__ unsigned gcd_u(unsigned x, unsigned y)
 }
 
 // Scatter: the m particles a block sends to tile t take its reserved slots
-// base..base+m-1.  They are staged in LDS in the order r -> (r * stride) mod m
-// (r = arrival rank, stride near 0.618 m and coprime to m) and then copied
-// with consecutive destination slots, so the stores stay coalesced while runs
-// of particles from one cell are spread over the tile's range (the lanes of a
-// wavefront in the push then mostly deposit into different cells).
+// base..base+m-1, in the order r -> (r * stride) mod m (r = arrival rank,
+// stride near 0.618 m and coprime to m), so runs of particles from one cell
+// are spread over the tile's range (the lanes of a wavefront in the push then
+// mostly deposit into different cells).  Each of the five arrays passes
+// through LDS: coalesced loads of the block's slots, stores into LDS at the
+// staging position, then coalesced stores of the staged runs to their
+// consecutive destination slots.
+// One array of the block through LDS: values (in registers, slot order) to
+// their staging positions, then the staged runs to their destination slots.
+__device__ __forceinline__ void bin_move(const float (&vals)[kBinRP], float *dst_arr, const int (&qv)[kBinRP],
+                                         const unsigned *dst, float *buf, unsigned total)
+{
+#pragma unroll
+    for (int r8 = 0; r8 < kBinRP; r8++)
+        if (qv[r8] >= 0) buf[qv[r8]] = vals[r8];
+    __syncthreads();
+    for (unsigned q = threadIdx.x; q < total; q += 256) dst_arr[dst[q]] = buf[q];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_bin_scatter(const BinArgs *B, Tab tb)
 {
-    __shared__ unsigned hist[kBinLds], base[kBinLds], loff[kBinLds], mstr[kBinLds];
-    __shared__ int src[kBinPer];
+    constexpr int RP = kBinPer / 256;
+    // tile tables until the staging positions are known, then the staging
+    // buffer in the same LDS
+    __shared__ unsigned tabs[4 * kBinLds];
     __shared__ unsigned dst[kBinPer];
-    __shared__ unsigned part[256];
+    __shared__ unsigned wsum[4];
+    static_assert(kBinPer <= 4 * kBinLds, "staging buffer inside the tile tables");
+    unsigned *hist = tabs, *base = tabs + kBinLds, *loff = tabs + 2 * kBinLds, *mstr = tabs + 3 * kBinLds;
+    float *buf = reinterpret_cast<float *>(tabs);
     const int ku = unit_of(tb, (int)blockIdx.x);
     const BinArgs &a = B[tb.id[ku]];
     const BView v = bview(a);
@@ -2183,7 +2228,18 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const BinArgs *B, Tab tb)
     const long long lo = (long long)((int)blockIdx.x - tb.boff[ku]) * kBinPer;
     if (lo >= n) return;
     const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
-    bin_local_count(a, v, lo, hi, hist, false);
+    // every load of the block's slots issued up front
+    float fv[4][RP];
+    const float *fsrc[4] = {v.ox, v.oy, v.vx, v.vy};
+#pragma unroll
+    for (int f = 0; f < 4; f++)
+#pragma unroll
+        for (int r8 = 0; r8 < RP; r8++) {
+            const long long p = lo + r8 * 256 + threadIdx.x;
+            fv[f][r8] = p < hi ? fsrc[f][p] : 0.0f;
+        }
+    int cv[RP];
+    bin_local_count(a, v, lo, hi, hist, false, cv);
     const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
     const int per = (nl + 255) / 256;
     const int t0 = threadIdx.x * per, t1 = min(nl, t0 + per);
@@ -2198,58 +2254,52 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const BinArgs *B, Tab tb)
         }
         sum += m;
     }
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned acc = 0;
-        for (int k = 0; k < 256; k++) {
-            const unsigned v = part[k];
-            part[k] = acc;
-            acc += v;
-        }
-    }
-    __syncthreads();
-    unsigned off = part[threadIdx.x];
+    unsigned off = block_exclusive_scan(sum, wsum);
     for (int k = t0; k < t1; k++) {
         loff[k] = off;
         off += hist[k];
         hist[k] = 0u;
     }
     __syncthreads();
-    for (long long p0 = lo; p0 < hi; p0 += 256) {
-        const long long p = p0 + threadIdx.x;
-        int c = -1;
-        if (p < hi) c = v.cell[p];
+    int qv[RP];                                           // staging position of each own slot, or -1
+#pragma unroll
+    for (int r8 = 0; r8 < RP; r8++) {
+        const int c = cv[r8];
         const bool act = live_code(c, a.nx, a.ny);
         const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
         const bool loc = act && key < kBinLds;
         const unsigned r = wave_add(hist, key, loc);
         const unsigned d1 = wave_add(a.cursor, key, act && key >= kBinLds);
+        int qp = -1;
         if (loc) {
             const unsigned ms = mstr[key];
             const unsigned q = loff[key] + (r * (ms & 0xFFFFu)) % (ms >> 16);
-            src[q] = (int)(p - lo);
+            qp = (int)q;
             dst[q] = base[key] + (q - loff[key]);
         } else if (act) {
             v.cell2[d1] = c;
-            v.ox2[d1] = v.ox[p];
-            v.oy2[d1] = v.oy[p];
-            v.vx2[d1] = v.vx[p];
-            v.vy2[d1] = v.vy[p];
+            v.ox2[d1] = fv[0][r8];
+            v.oy2[d1] = fv[1][r8];
+            v.vx2[d1] = fv[2][r8];
+            v.vy2[d1] = fv[3][r8];
         }
+        qv[r8] = qp;
     }
     __syncthreads();
-    // staged total: offset of the last bin plus its count (its rank counter)
+    // staged total: offset of the last bin plus its count (its rank counter);
+    // read by every thread before the tables become the staging buffer
     const unsigned total = (nl > 0) ? loff[nl - 1] + hist[nl - 1] : 0u;
-    for (unsigned q = threadIdx.x; q < total; q += 256) {
-        const long long p = lo + src[q];
-        const unsigned d = dst[q];
-        v.cell2[d] = v.cell[p];
-        v.ox2[d] = v.ox[p];
-        v.oy2[d] = v.oy[p];
-        v.vx2[d] = v.vx[p];
-        v.vy2[d] = v.vy[p];
-    }
+    __syncthreads();
+#pragma unroll
+    for (int r8 = 0; r8 < RP; r8++)
+        if (qv[r8] >= 0) buf[qv[r8]] = __int_as_float(cv[r8]);
+    __syncthreads();
+    for (unsigned q = threadIdx.x; q < total; q += 256) v.cell2[dst[q]] = __float_as_int(buf[q]);
+    __syncthreads();
+    bin_move(fv[0], v.ox2, qv, dst, buf, total);
+    bin_move(fv[1], v.oy2, qv, dst, buf, total);
+    bin_move(fv[2], v.vx2, qv, dst, buf, total);
+    bin_move(fv[3], v.vy2, qv, dst, buf, total);
 }
 
 // The destination set becomes the set in use.
