@@ -1632,7 +1632,7 @@ __device__ __forceinline__ void deposit_lane(const PK &a, unsigned long long *mA
 // Particles that drifted beyond the window add their four corner weights to
 // global memory directly.  The window is flushed to the node charge at the end.
 template <bool PUSH, int U, int MERGE>
-__global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
+__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_push(const PushArgs *A, Tab t)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int ku = unit_of(t, (int)blockIdx.x);
@@ -1710,14 +1710,6 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
                     uyv[k] = (PUSH && in) ? a.vy[p] : 0.f;
                 }
             }
-            float4 eav[4], ebv[4];
-            if (PUSH) {
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    eav[k] = ebv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (cv[k] >= 0) cell_fields(a, sE, e0i, e0j, EW, EH, cv[k], eav[k], ebv[k]);
-                }
-            }
             bool alv[4];
 #pragma unroll
             for (int k = 0; k < 4; k++) {
@@ -1729,9 +1721,13 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs *A, Tab t)
                     cj = c & 0xFFFF;
                     alive = true;
                     if (PUSH) {
+                        // the corner fields of this particle's cell only (fewer
+                        // live registers than gathering all four first)
+                        float4 ea, eb;
+                        cell_fields(a, sE, e0i, e0j, EW, EH, c, ea, eb);
                         int dead, ei, ej;
                         float ux, uy, nxo, nyo;
-                        alive = push_core(a, xv[k], yv[k], uxv[k], uyv[k], eav[k], ebv[k], ci, cj, dead,
+                        alive = push_core(a, xv[k], yv[k], uxv[k], uyv[k], ea, eb, ci, cj, dead,
                                           ei, ej, ux, uy, nxo, nyo);
                         uxv[k] = ux;
                         uyv[k] = uy;
