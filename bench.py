@@ -43,15 +43,21 @@ def workload(name):
 
 
 def push_source_hash():
-    """sha256 of what the push kernel is built from: the internal header and
-    the particle section of the kernel source (gather, push, wall test,
-    deposit), so that edits elsewhere in the file keep its counters valid."""
+    """sha256 of what the push kernel is built from: the header's constants
+    and the structs it reads (Geom, HitLog, PushArgs, the LDS size formula)
+    and the particle section of the kernel source (gather, push, wall test,
+    deposit), so that edits elsewhere keep its counters valid."""
     import hashlib
+    import re
     hdr = open(os.path.join(os.path.dirname(KERNEL_SOURCE), "pic_internal.h"), "rb").read()
+    parts = re.findall(rb"^constexpr int k\w+ = [^\n]*", hdr, re.M)
+    for name in (b"struct Geom {", b"struct HitLog {", b"struct PushArgs {", b"inline size_t push_lds_bytes("):
+        a = hdr.index(name)
+        parts.append(hdr[a:hdr.index(b"\n}", a) + 2])
     src = open(KERNEL_SOURCE, "rb").read()
     a = src.index(b"// particles: gather, leapfrog push")
     b = src.index(b"// re-binning: counting sort")
-    return hashlib.sha256(hdr + src[a:b]).hexdigest()
+    return hashlib.sha256(b"\n".join(parts) + src[a:b]).hexdigest()
 
 
 def measured_traffic(workload_name, particles_per_launch):
