@@ -30,9 +30,12 @@ CACHE = os.path.join(HERE, "tuning", "schedules.json")
 
 DEFAULT = {"tile": [16, 16], "chunk": 4096, "halo": 4, "push_unroll": 4, "push_merge": 0,
            "sort_interval": [8, 64]}
-LAYOUTS = [((16, 16), 4096), ((16, 16), 8192), ((32, 16), 4096), ((16, 32), 4096), ((32, 32), 8192)]
+# (tile, chunk, halo): the halo bounds how far particles may drift between re-binnings before their
+# charge goes to global memory directly, so it trades against the re-binning interval
+LAYOUTS = [((16, 16), 4096, 4), ((16, 16), 8192, 4), ((16, 16), 8192, 6), ((32, 16), 4096, 4),
+           ((16, 32), 4096, 4), ((32, 32), 8192, 4)]
 VARIANTS = [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2)]
-SORTS = [(4, 32), (8, 64), (16, 64), (8, 128), (16, 128), (32, 128)]
+SORTS = [(4, 32), (8, 64), (12, 128), (16, 64), (16, 128), (24, 128), (32, 128)]
 
 
 def signature(workloads, parts):
@@ -88,9 +91,9 @@ def tune(workloads, parts, steps=32, log=None, path=CACHE):
     trials = []
     best = None
     schedule = None
-    for tile, chunk in LAYOUTS:
+    for tile, chunk, halo in LAYOUTS:
         opts = dict(DEFAULT)
-        opts.update(tile=list(tile), chunk=chunk)
+        opts.update(tile=list(tile), chunk=chunk, halo=halo)
         b = PicBatch(workloads, parts, tile=tuple(tile), chunk=chunk, halo=opts["halo"],
                      push_unroll=opts["push_unroll"], push_merge=opts["push_merge"],
                      sort_interval=tuple(opts["sort_interval"]))
@@ -99,8 +102,9 @@ def tune(workloads, parts, steps=32, log=None, path=CACHE):
             schedule = _solver_schedule(b, 3)
         ms, ok = _measure(b, opts["sort_interval"][0], steps, *schedule)
         b.close()
-        trials.append({"stage": "layout", "tile": list(tile), "chunk": chunk, "ms": ms, "converged": ok})
-        say(f"layout tile {tile} chunk {chunk}: {ms:.3f} ms/step")
+        trials.append({"stage": "layout", "tile": list(tile), "chunk": chunk, "halo": halo, "ms": ms,
+                       "converged": ok})
+        say(f"layout tile {tile} chunk {chunk} halo {halo}: {ms:.3f} ms/step")
         if ok and (best is None or ms < best[0]):
             best = (ms, opts)
     opts = dict(best[1])
