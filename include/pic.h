@@ -204,6 +204,15 @@ pic_status pic_read_hits(pic_ctx *ctx, pic_hit *out, int64_t max, int64_t *n);
 pic_status pic_tune(pic_ctx *ctx, int32_t push_unroll, int32_t push_merge, int32_t sort_e,
                     int32_t sort_i);
 
+/* Chooses whether the fine multigrid levels below level 0 run two per launch
+ * (on = 1, the default: one block per tile of the coarser level recomputes
+ * the finer one on the window it needs) or one per launch (on = 0).  The
+ * paired kernels perform the same operations in the same order, so the
+ * potential is the same bit for bit; only the time per iteration differs.
+ * Waits for the stream and drops every captured graph.  PIC_ERR_ARG for on
+ * outside {0, 1}. */
+pic_status pic_set_level_pairs(pic_ctx *ctx, int32_t on);
+
 /* Re-bins species s now (tile sort; drops removed particles). */
 pic_status pic_sort(pic_ctx *ctx, int32_t species);
 

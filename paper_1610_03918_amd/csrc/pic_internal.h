@@ -191,6 +191,8 @@ constexpr int kMgTileHost = 32;
 // mode 2 level 0 after a CG step; par = buffer of the r / s pairs read
 void launch_mg_down(const Inst *I, const Tab &t, int level, int mode, int par, Part pt, hipStream_t s);
 void launch_mg_up(const Inst *I, const Tab &t, int level, int par, Part pt, hipStream_t s);
+// levels l and l + 1 in one launch (table of level-(l+1) tiles); down or up
+void launch_mg_pair(const Inst *I, const Tab &t, int level, bool down, hipStream_t s);
 void launch_push(const PushArgs *A, const Tab &t, bool push, int unroll, int merge, size_t lds,
                  hipStream_t s);
 void launch_rewind(const PushArgs *A, const Tab &t, hipStream_t s);

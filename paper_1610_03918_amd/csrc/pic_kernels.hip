@@ -716,16 +716,16 @@ __device__ __forceinline__ long long win_node(int NX, int NY, int px, int py, in
 // level L.  Fixed nodes hold u = 0 on every level (no update ever writes
 // them), so the stencils below add neighbours without testing their mask;
 // all loads of a thread are issued before the LDS stores.
-template <int W>
+template <int W, int NT = kMgThreads>
 __device__ __forceinline__ void mg_stage(const LevelDev &L, const float *src, const float *gsrc, int px, int py,
                                          int wi0, int wj0, float *su, float *sg, uint8_t *sf)
 {
-    constexpr int R = (W * W + kMgThreads - 1) / kMgThreads;
+    constexpr int R = (W * W + NT - 1) / NT;
     float uv[R], gv[R];
     uint8_t fv[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int k = (int)threadIdx.x + r * kMgThreads;
+        const int k = (int)threadIdx.x + r * NT;
         const int a = k / W, c = k - a * W;
         const long long n = k < W * W ? win_node(L.NX, L.NY, px, py, wi0 + a, wj0 + c) : -1;
         uv[r] = 0.0f;
@@ -739,7 +739,7 @@ __device__ __forceinline__ void mg_stage(const LevelDev &L, const float *src, co
     }
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int k = (int)threadIdx.x + r * kMgThreads;
+        const int k = (int)threadIdx.x + r * NT;
         if (k < W * W) {
             su[k] = uv[r];
             sg[k] = gv[r];
@@ -815,10 +815,10 @@ __device__ __forceinline__ float win_gs(const float *su, const float *sg, int k)
 // One colour of Gauss-Seidel over window rows/cols m .. W-1-m.  The window
 // origin is an even offset from an even tile corner, so (a + c) & 1 is the
 // colour of the global node.
-template <int W>
+template <int W, int NT = kMgThreads>
 __device__ __forceinline__ void win_sweep(float *su, const float *sg, const uint8_t *sf, int m, int col)
 {
-    for (int k = threadIdx.x; k < W * W; k += kMgThreads) {
+    for (int k = threadIdx.x; k < W * W; k += NT) {
         const int a = k / W, c = k - a * W;
         if (a < m || a > W - 1 - m || c < m || c > W - 1 - m || sf[k]) continue;
         if (((a + c) & 1) != col) continue;
@@ -1080,6 +1080,254 @@ void launch_mg_up(const Inst *I, const Tab &t, int level, int par, Part pt, hipS
     } else {
         hipLaunchKernelGGL((k_mg_up<kMgSmooth, 0>), g, b, 0, s, I, t, level, par, pt);
     }
+}
+
+// ---------------------------------------------------------------------------
+// two fine levels l and l + 1 in one launch (one pre- / post-smoothing step):
+// one 1024-thread block per 32 x 32 tile of level l + 1.  The block
+// recomputes level l on the wider window its level-(l+1) window needs, so no
+// block depends on another between the two levels.  Level l + 1's final
+// correction is consumed inside the up kernel and never stored.
+// ---------------------------------------------------------------------------
+
+constexpr int kPairThreads = 1024;
+constexpr int kPairDnF = 79;      // down, level l:     rows 2 I0 - 9 .. 2 I0 + 69
+constexpr int kPairDnC = 37;      // down, level l + 1: rows I0 - 3 .. I0 + 33
+constexpr int kPairUpC = 39;      // up, level l + 1:   rows I0 - 3 .. I0 + 35
+constexpr int kPairUpF = 68;      // up, level l:       rows 2 I0 - 2 .. 2 I0 + 65
+
+__host__ __device__ constexpr int pad16(int b) { return (b + 15) & ~15; }
+__host__ __device__ constexpr int win_lds(int W) { return pad16(3 * W * W * 4) + pad16(W * W); }
+constexpr int kPairDnLds = win_lds(kPairDnF) + win_lds(kPairDnC);
+constexpr int kPairUpLds = win_lds(kPairUpC) + win_lds(kPairUpF);
+
+// Window arrays at byte offset off: u, g, scratch (float) and the mask.
+struct WinLds {
+    float *u, *g, *r;
+    uint8_t *f;
+};
+__device__ __forceinline__ WinLds win_at(unsigned char *lds, int off, int W)
+{
+    WinLds w;
+    w.u = (float *)(lds + off);
+    w.g = w.u + W * W;
+    w.r = w.g + W * W;
+    w.f = (uint8_t *)(lds + off + pad16(3 * W * W * 4));
+    return w;
+}
+
+// Down half-cycles of levels l and l + 1: black half-sweep of level l from
+// its red-from-zero start, level l's pre-smoothed tile nodes to uo, the
+// restriction of its red residuals to the level-(l+1) window (g of the own
+// tile stored), black half-sweep there, level l+1's tile to uo, and the
+// restriction to level l + 2 (g and its red-from-zero start u).
+__global__ __launch_bounds__(kPairThreads) void k_mg_down_pair(const Inst *insts, Tab t, int level)
+{
+    constexpr int WF = kPairDnF, WC = kPairDnC, NT = kPairThreads;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const Inst &I = insts[t.id[ku]];
+    if (I.F[F_DONE]) return;
+    const int lb = (int)blockIdx.x - t.boff[ku];
+    const int ti = lb / t.bx[ku], tj = lb - ti * t.bx[ku];
+    const LevelDev F = I.lev[level], C = I.lev[level + 1], N = I.lev[level + 2];
+    const int px = I.g.px, py = I.g.py;
+    const int I0 = ti * kMgTile, J0 = tj * kMgTile;
+    const WinLds f = win_at(lds, 0, WF), c = win_at(lds, win_lds(WF), WC);
+    const int tid = threadIdx.x;
+    mg_stage<WF, NT>(F, F.u, F.g, px, py, 2 * I0 - 9, 2 * J0 - 9, f.u, f.g, f.f);
+    for (int k = tid; k < WC * WC; k += NT) {
+        const int a = k / WC, b = k - a * WC;
+        const long long n = win_node(C.NX, C.NY, px, py, I0 - 3 + a, J0 - 3 + b);
+        c.f[k] = n >= 0 ? C.fix[n] : 1;
+    }
+    __syncthreads();
+    win_sweep<WF, NT>(f.u, f.g, f.f, 1, 1);               // black, rows 1 .. WF-2
+    __syncthreads();
+    for (int k = tid; k < 64 * 64; k += NT) {             // own level-l nodes
+        const int a = k >> 6, b = k & 63;
+        const int gi = 2 * I0 + a, gj = 2 * J0 + b;
+        if (gi < F.NX && gj < F.NY) F.uo[(long long)gi * F.NY + gj] = f.u[(a + 9) * WF + (b + 9)];
+    }
+    for (int k = tid; k < WF * WF; k += NT) {             // red residuals, rows 2 .. WF-3
+        const int a = k / WF, b = k - a * WF;
+        if (a < 2 || a > WF - 3 || b < 2 || b > WF - 3 || ((a + b) & 1)) continue;
+        float r = 0.0f;
+        if (!f.f[k]) {
+            float q = 4.0f * f.u[k];
+            q -= f.u[k - WF];
+            q -= f.u[k + WF];
+            q -= f.u[k - 1];
+            q -= f.u[k + 1];
+            r = f.g[k] - q;
+        }
+        f.r[k] = r;
+    }
+    __syncthreads();
+    for (int k = tid; k < WC * WC; k += NT) {             // restriction to the level-(l+1) window
+        const int a = k / WC, b = k - a * WC;
+        float gv = 0.0f, uv = 0.0f;
+        if (!c.f[k]) {
+            const int m = (3 + 2 * a) * WF + (3 + 2 * b);
+            float acc = 0.0f;
+            acc += 0.25f * f.r[m - WF - 1];
+            acc += 0.25f * f.r[m - WF + 1];
+            acc += 1.0f * f.r[m];
+            acc += 0.25f * f.r[m + WF - 1];
+            acc += 0.25f * f.r[m + WF + 1];
+            gv = acc;
+            if (((a + b) & 1) == 0) uv = gv * 0.25f;
+        }
+        c.g[k] = gv;
+        c.u[k] = uv;
+        const int gi = I0 - 3 + a, gj = J0 - 3 + b;
+        if (a >= 3 && a < 35 && b >= 3 && b < 35 && gi < C.NX && gj < C.NY) C.g[(long long)gi * C.NY + gj] = gv;
+    }
+    __syncthreads();
+    win_sweep<WC, NT>(c.u, c.g, c.f, 1, 1);               // black, rows 1 .. WC-2
+    __syncthreads();
+    for (int k = tid; k < kMgTile * kMgTile; k += NT) {   // own level-(l+1) nodes
+        const int a = k / kMgTile, b = k - a * kMgTile;
+        const int gi = I0 + a, gj = J0 + b;
+        if (gi < C.NX && gj < C.NY) C.uo[(long long)gi * C.NY + gj] = c.u[(a + 3) * WC + (b + 3)];
+    }
+    for (int k = tid; k < WC * WC; k += NT) {             // red residuals, rows 2 .. WC-3
+        const int a = k / WC, b = k - a * WC;
+        if (a < 2 || a > WC - 3 || b < 2 || b > WC - 3 || ((a + b) & 1)) continue;
+        float r = 0.0f;
+        if (!c.f[k]) {
+            float q = 4.0f * c.u[k];
+            q -= c.u[k - WC];
+            q -= c.u[k + WC];
+            q -= c.u[k - 1];
+            q -= c.u[k + 1];
+            r = c.g[k] - q;
+        }
+        c.r[k] = r;
+    }
+    __syncthreads();
+    if (tid < 256) {                                      // restriction to level l + 2
+        const int ci = tid >> 4, cj = tid & 15;
+        const int CI = (I0 >> 1) + ci, CJ = (J0 >> 1) + cj;
+        if (CI < N.NX && CJ < N.NY) {
+            const long long n = (long long)CI * N.NY + CJ;
+            float gv = 0.0f, uv = 0.0f;
+            if (!N.fix[n]) {
+                const int m = (3 + 2 * ci) * WC + (3 + 2 * cj);
+                float acc = 0.0f;
+                acc += 0.25f * c.r[m - WC - 1];
+                acc += 0.25f * c.r[m - WC + 1];
+                acc += 1.0f * c.r[m];
+                acc += 0.25f * c.r[m + WC - 1];
+                acc += 0.25f * c.r[m + WC + 1];
+                gv = acc;
+                if (((CI + CJ) & 1) == 0) uv = gv * 0.25f;
+            }
+            N.g[n] = gv;
+            N.u[n] = uv;
+        }
+    }
+}
+
+// Up half-cycles of levels l + 1 and l: level l+1's pre-smoothed window plus
+// the prolonged level-(l+2) correction at its reds, black update, red
+// half-sweep (its final correction, in LDS); then level l likewise with the
+// prolongation read from that LDS result; level l's tile to u.
+__global__ __launch_bounds__(kPairThreads) void k_mg_up_pair(const Inst *insts, Tab t, int level)
+{
+    constexpr int WC = kPairUpC, WF = kPairUpF, NT = kPairThreads;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const Inst &I = insts[t.id[ku]];
+    if (I.F[F_DONE]) return;
+    const int lb = (int)blockIdx.x - t.boff[ku];
+    const int ti = lb / t.bx[ku], tj = lb - ti * t.bx[ku];
+    const LevelDev F = I.lev[level], C = I.lev[level + 1], N = I.lev[level + 2];
+    const int px = I.g.px, py = I.g.py;
+    const int I0 = ti * kMgTile, J0 = tj * kMgTile;
+    const WinLds c = win_at(lds, 0, WC), f = win_at(lds, win_lds(WC), WF);
+    const int tid = threadIdx.x;
+    mg_stage<WC, NT>(C, C.uo, C.g, px, py, I0 - 3, J0 - 3, c.u, c.g, c.f);
+    mg_stage<WF, NT>(F, F.uo, F.g, px, py, 2 * I0 - 2, 2 * J0 - 2, f.u, f.g, f.f);
+    __syncthreads();
+    for (int k = tid; k < WC * WC; k += NT) {             // corrected reds of level l + 1
+        const int a = k / WC, b = k - a * WC;
+        float v = 0.0f;
+        if (((a + b) & 1) == 0 && !c.f[k]) {
+            int gi = I0 - 3 + a, gj = J0 - 3 + b;
+            if (px) gi = wrap_any(gi, C.NX);
+            if (py) gj = wrap_any(gj, C.NY);
+            v = c.u[k] + prolong_red(N.u, N.NX, N.NY, gi, gj);
+        }
+        c.r[k] = v;
+    }
+    __syncthreads();
+    for (int k = tid; k < WC * WC; k += NT) {             // black update, rows 1 .. WC-2
+        const int a = k / WC, b = k - a * WC;
+        if (a < 1 || a > WC - 2 || b < 1 || b > WC - 2 || c.f[k] || ((a + b) & 1) != 1) continue;
+        float s = c.g[k];
+        s += c.r[k - WC];
+        s += c.r[k + WC];
+        s += c.r[k - 1];
+        s += c.r[k + 1];
+        c.u[k] = s * 0.25f;
+    }
+    __syncthreads();
+    win_sweep<WC, NT>(c.u, c.g, c.f, 2, 0);               // red, rows 2 .. WC-3
+    __syncthreads();
+    for (int k = tid; k < WF * WF; k += NT) {             // corrected reds of level l
+        const int a = k / WF, b = k - a * WF;
+        float v = 0.0f;
+        if (((a + b) & 1) == 0 && !f.f[k]) {
+            // level-(l+1) window row of fine row 2 I0 - 2 + a is 2 + (a >> 1)
+            const int m = (2 + (a >> 1)) * WC + (2 + (b >> 1));
+            float e;
+            if (((a | b) & 1) == 0) e = c.u[m];
+            else e = 0.25f * (c.u[m] + c.u[m + WC] + c.u[m + 1] + c.u[m + WC + 1]);
+            v = f.u[k] + e;
+        }
+        f.r[k] = v;
+    }
+    __syncthreads();
+    for (int k = tid; k < WF * WF; k += NT) {             // black update, rows 1 .. WF-2
+        const int a = k / WF, b = k - a * WF;
+        if (a < 1 || a > WF - 2 || b < 1 || b > WF - 2 || f.f[k] || ((a + b) & 1) != 1) continue;
+        float s = f.g[k];
+        s += f.r[k - WF];
+        s += f.r[k + WF];
+        s += f.r[k - 1];
+        s += f.r[k + 1];
+        f.u[k] = s * 0.25f;
+    }
+    __syncthreads();
+    for (int k = tid; k < 64 * 64; k += NT) {             // red half-sweep of the own tile; tile to u
+        const int a = k >> 6, b = k & 63;
+        const int gi = 2 * I0 + a, gj = 2 * J0 + b;
+        if (gi >= F.NX || gj >= F.NY) continue;
+        const int w = (a + 2) * WF + (b + 2);
+        float z = 0.0f;
+        if (!f.f[w]) {
+            z = f.u[w];
+            if (((gi + gj) & 1) == 0) z = win_gs<WF>(f.u, f.g, w);
+        }
+        F.u[(long long)gi * F.NY + gj] = z;
+    }
+}
+
+void launch_mg_pair(const Inst *I, const Tab &t, int level, bool down, hipStream_t s)
+{
+    if (!t.n) return;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_mg_down_pair, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kPairDnLds);
+        (void)hipFuncSetAttribute((const void *)k_mg_up_pair, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kPairUpLds);
+        attr = true;
+    }
+    const dim3 g(tab_blocks(t)), b(kPairThreads);
+    if (down) hipLaunchKernelGGL(k_mg_down_pair, g, b, kPairDnLds, s, I, t, level);
+    else hipLaunchKernelGGL(k_mg_up_pair, g, b, kPairUpLds, s, I, t, level);
 }
 
 // ---------------------------------------------------------------------------

@@ -238,8 +238,10 @@ struct pic_ctx {
     // launch tables
     Tab t_l0{}, t_field{}, t_per{}, t_coarse{}, t_push{}, t_rewind{};
     Tab t_plain{};                 // level-0 grid of the instances solved by plain CG
-    Tab t_fine[kMaxLev] = {};      // 32 x 32 tiles of the fine multigrid levels
+    Tab t_fine[kMaxLev] = {};      // 32 x 32 tiles of the fine multigrid levels handled one at a time
+    Tab t_pair[kMaxLev] = {};      // 32 x 32 tiles of level l + 1 for levels l, l + 1 in one launch
     int maxlg = 0, coarse_lds = 0, any_mg = 0;
+    int pair_levels = 1;           // fine levels 1, 2 (3, 4, ...) two per launch
     size_t push_lds = 0;
     int unroll = 2, merge = 0;
     // solver control
@@ -488,9 +490,15 @@ void enqueue_deposit(pic_ctx *c, hipStream_t s)
 void enqueue_vcycle_mid(pic_ctx *c, hipStream_t s)
 {
     Part pt = part_of(c);
-    for (int l = 1; l < c->maxlg; l++) launch_mg_down(c->d_inst, c->t_fine[l], l, 0, 0, pt, s);
+    for (int l = 1; l < c->maxlg; l++) {
+        launch_mg_pair(c->d_inst, c->t_pair[l], l, true, s);
+        launch_mg_down(c->d_inst, c->t_fine[l], l, 0, 0, pt, s);
+    }
     launch_coarse(c->d_inst, c->t_coarse, c->coarse_lds, s);
-    for (int l = c->maxlg - 1; l >= 1; l--) launch_mg_up(c->d_inst, c->t_fine[l], l, 0, pt, s);
+    for (int l = c->maxlg - 1; l >= 1; l--) {
+        launch_mg_up(c->d_inst, c->t_fine[l], l, 0, pt, s);
+        launch_mg_pair(c->d_inst, c->t_pair[l], l, false, s);
+    }
 }
 
 // Start of a refinement pass: inner CG from e = 0.  Plain CG: first
@@ -952,7 +960,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
 void build_tabs(pic_ctx *c)
 {
     c->t_l0 = c->t_field = c->t_per = c->t_coarse = c->t_push = c->t_rewind = c->t_plain = Tab{};
-    for (int l = 0; l < kMaxLev; l++) c->t_fine[l] = Tab{};
+    for (int l = 0; l < kMaxLev; l++) c->t_fine[l] = c->t_pair[l] = Tab{};
     c->maxlg = 0;
     c->coarse_lds = 0;
     c->any_mg = 0;
@@ -967,12 +975,18 @@ void build_tabs(pic_ctx *c)
         if (L.mg) {
             c->any_mg = 1;
             c->maxlg = std::max(c->maxlg, L.lg);
+            // level 0 alone (it carries the CG step); levels 1 .. lg-1 in pairs
+            // (1, 2), (3, 4), ..., a last odd one alone
             for (int l = 0; l < L.lg; l++) {
-                const int tx = (L.NXl[l] + kMgTileHost - 1) / kMgTileHost;
-                const int ty = (L.NYl[l] + kMgTileHost - 1) / kMgTileHost;
-                const int q = c->t_fine[l].n;
-                tab_add(c->t_fine[l], k, tx * ty);
-                c->t_fine[l].bx[q] = ty;
+                const bool pair = c->pair_levels && l >= 1 && (l & 1) && l + 1 < L.lg;
+                const int lt = pair ? l + 1 : l;
+                const int tx = (L.NXl[lt] + kMgTileHost - 1) / kMgTileHost;
+                const int ty = (L.NYl[lt] + kMgTileHost - 1) / kMgTileHost;
+                Tab &tb = pair ? c->t_pair[l] : c->t_fine[l];
+                const int q = tb.n;
+                tab_add(tb, k, tx * ty);
+                tb.bx[q] = ty;
+                if (pair) l++;
             }
             tab_add(c->t_coarse, k, 1);
             c->coarse_lds = std::max(c->coarse_lds, h.dev.coarse.lds_bytes);
@@ -1235,6 +1249,23 @@ pic_status pic_tune(pic_ctx *c, int32_t push_unroll, int32_t push_merge, int32_t
     }
     // captured steps embed the push variant and the re-binning points
     for (auto &kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->step_graphs.clear();
+    return PIC_OK;
+}
+
+pic_status pic_set_level_pairs(pic_ctx *c, int32_t on)
+{
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (on != 0 && on != 1) return fail(c, PIC_ERR_ARG, "on must be 0 or 1");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->pair_levels = on;
+    build_tabs(c);
+    // every captured graph embeds the V-cycle's launches
+    for (auto &kv : c->outer_graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->chunk_graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->outer_graphs.clear();
+    c->chunk_graphs.clear();
     c->step_graphs.clear();
     return PIC_OK;
 }

@@ -80,8 +80,8 @@ ENTRY_POINTS = ["pic_workspace_size", "pic_init", "pic_deposit", "pic_solve", "p
                 "pic_push", "pic_step", "pic_diagnostics", "pic_particles", "pic_read_hits",
                 "pic_sort", "pic_push_timing", "pic_set_timing", "pic_batch_workspace_size",
                 "pic_batch_init", "pic_batch_step", "pic_batch_diagnostics", "pic_batch_particles",
-                "pic_batch_solve_info", "pic_node_map", "pic_tune", "pic_destroy", "pic_last_error",
-                "pic_version"]
+                "pic_batch_solve_info", "pic_node_map", "pic_tune", "pic_set_level_pairs", "pic_destroy",
+                "pic_last_error", "pic_version"]
 
 
 def lib():
@@ -247,6 +247,9 @@ class _Context:
     def pic_tune(self, push_unroll, push_merge, sort_interval):
         self._chk(lib().pic_tune(self.ctx, int(push_unroll), int(push_merge), int(sort_interval[0]),
                                  int(sort_interval[1])))
+
+    def pic_set_level_pairs(self, on):
+        self._chk(lib().pic_set_level_pairs(self.ctx, int(bool(on))))
 
     def close(self):
         if getattr(self, "ctx", None):
