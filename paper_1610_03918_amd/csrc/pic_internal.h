@@ -69,6 +69,7 @@ struct CoarseArgs {
     int nlev;                      // levels handled in LDS
     int NX[kMaxLev], NY[kMaxLev];
     int off_u[kMaxLev], off_g[kMaxLev], off_f[kMaxLev]; // LDS byte offsets
+    int off_s;                     // LDS scratch: one float per node of the first LDS level
     const uint8_t *fix[kMaxLev];   // global masks of those levels
     float *u_top;                  // global u of the first LDS level (output)
     const float *g_top;            // global g of the first LDS level (input)

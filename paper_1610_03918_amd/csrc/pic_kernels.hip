@@ -697,7 +697,7 @@ void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStrea
 // ---------------------------------------------------------------------------
 
 constexpr int kMgTile = 32;
-constexpr int kMgThreads = 256;
+constexpr int kMgThreads = 512;
 
 __device__ __forceinline__ int wrap_any(int x, int n) { return ((x % n) + n) % n; }
 
@@ -926,7 +926,7 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_down(const Inst *insts, Tab t
         }
         __syncthreads();
         // restriction: coarse nodes (i0/2 .. i0/2+15, j0/2 .. j0/2+15)
-        {
+        if (threadIdx.x < 256) {
             const int ci = threadIdx.x >> 4, cj = threadIdx.x & 15;
             const int CI = (i0 >> 1) + ci, CJ = (j0 >> 1) + cj;
             if (CI < Cc.NX && CJ < Cc.NY) {
@@ -1354,36 +1354,135 @@ __device__ __forceinline__ float gs_nofix(const float *u, const float *gg, int i
 // the rounding error of the product.
 __device__ __forceinline__ int div_rcp(int q, float rcp) { return (int)(((float)q + 0.5f) * rcp); }
 
-// Residual g - A u at a node of an LDS level (0 at fixed nodes).
-__device__ __forceinline__ float resid_nofix(const float *u, const float *gg, const uint8_t *f, int i, int j,
-                                             int NX, int NY)
+// Phases of the LDS levels.  Each is run by a group of threads (first,
+// step): the whole work-group, or one wavefront for the small levels, with
+// the group's barrier between phases.  Half-sweeps and the red-node passes
+// visit the nodes of their colour only (j = 2 jj + ((i + colour) & 1)).
+struct CLev {
+    float *u, *g;
+    const uint8_t *f;
+    int NX, NY;
+};
+
+// Gauss-Seidel half-sweep of one colour (1 black, 0 red).
+__device__ __forceinline__ void c_sweep(const CLev &L, int col, int first, int step)
 {
-    const int k = i * NY + j;
-    if (f[k]) return 0.0f;
-    Nb b = nbs(i, j, NX, NY);
-    float q = 4.0f * u[k];
-    q -= u[b.im * NY + j];
-    q -= u[b.ip * NY + j];
-    q -= u[i * NY + b.jm];
-    q -= u[i * NY + b.jp];
-    return gg[k] - q;
+    const int HW = (L.NY + 1) >> 1;
+    const float rcp = 1.0f / (float)HW;
+    for (int q = first; q < L.NX * HW; q += step) {
+        const int i = div_rcp(q, rcp), j = 2 * (q - i * HW) + ((i + col) & 1);
+        if (j < L.NY && !L.f[i * L.NY + j]) L.u[i * L.NY + j] = gs_nofix(L.u, L.g, i, j, L.NX, L.NY);
+    }
 }
 
-// Red node value plus the prolonged correction of the next coarser level
-// (0 at fixed nodes).
-__device__ __forceinline__ float corrected_red(const float *u, const uint8_t *f, const float *uc, int i, int j,
-                                               int NY, int NXc, int NYc)
+// Residual g - A u at the red nodes into sr (0 at fixed nodes).
+__device__ __forceinline__ void c_resid_red(const CLev &L, float *sr, int first, int step)
 {
-    const int k = i * NY + j;
-    return f[k] ? 0.0f : u[k] + prolong_red(uc, NXc, NYc, i, j);
+    const int HW = (L.NY + 1) >> 1, NY = L.NY;
+    const float rcp = 1.0f / (float)HW;
+    for (int q = first; q < L.NX * HW; q += step) {
+        const int i = div_rcp(q, rcp), j = 2 * (q - i * HW) + (i & 1);
+        if (j >= NY) continue;
+        const int k = i * NY + j;
+        float r = 0.0f;
+        if (!L.f[k]) {
+            Nb b = nbs(i, j, L.NX, NY);
+            float v = 4.0f * L.u[k];
+            v -= L.u[b.im * NY + j];
+            v -= L.u[b.ip * NY + j];
+            v -= L.u[i * NY + b.jm];
+            v -= L.u[i * NY + b.jp];
+            r = L.g[k] - v;
+        }
+        sr[k] = r;
+    }
 }
+
+// Restriction of the red residuals sr of level L to level C (g), with C's
+// red-from-zero start (u).
+__device__ __forceinline__ void c_restrict(const CLev &L, const float *sr, const CLev &C, int px, int py,
+                                           int first, int step)
+{
+    const int NX = L.NX, NY = L.NY;
+    const float rcp = 1.0f / (float)C.NY;
+    for (int k = first; k < C.NX * C.NY; k += step) {
+        const int Ic = div_rcp(k, rcp), Jc = k - Ic * C.NY;
+        float gv = 0.0f, uv = 0.0f;
+        if (!C.f[k]) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int di = -1; di <= 1; di++) {
+#pragma unroll
+                for (int dj = -1; dj <= 1; dj++) {
+                    if ((di + dj) & 1) continue;
+                    int ai = 2 * Ic + di, cj = 2 * Jc + dj;
+                    if (px) ai = wrap_hi(wrap_lo(ai, NX), NX);
+                    else if (ai < 0 || ai >= NX) continue;
+                    if (py) cj = wrap_hi(wrap_lo(cj, NY), NY);
+                    else if (cj < 0 || cj >= NY) continue;
+                    const float w = (di == 0) ? 1.0f : 0.25f;
+                    acc += w * sr[ai * NY + cj];
+                }
+            }
+            gv = acc;
+            if (((Ic + Jc) & 1) == 0) uv = gv * 0.25f;
+        }
+        C.g[k] = gv;
+        C.u[k] = uv;
+    }
+}
+
+// Red nodes of level L plus the prolonged correction of level C into sr (0
+// at fixed nodes).
+__device__ __forceinline__ void c_correct_red(const CLev &L, const CLev &C, float *sr, int first, int step)
+{
+    const int HW = (L.NY + 1) >> 1, NY = L.NY;
+    const float rcp = 1.0f / (float)HW;
+    for (int q = first; q < L.NX * HW; q += step) {
+        const int i = div_rcp(q, rcp), j = 2 * (q - i * HW) + (i & 1);
+        if (j >= NY) continue;
+        const int k = i * NY + j;
+        sr[k] = L.f[k] ? 0.0f : L.u[k] + prolong_red(C.u, C.NX, C.NY, i, j);
+    }
+}
+
+// Black update of level L from the corrected reds in sr.
+__device__ __forceinline__ void c_black_from(const CLev &L, const float *sr, int first, int step)
+{
+    const int HW = (L.NY + 1) >> 1, NY = L.NY;
+    const float rcp = 1.0f / (float)HW;
+    for (int q = first; q < L.NX * HW; q += step) {
+        const int i = div_rcp(q, rcp), j = 2 * (q - i * HW) + ((i + 1) & 1);
+        if (j >= NY || L.f[i * NY + j]) continue;
+        Nb b = nbs(i, j, L.NX, NY);
+        float v = L.g[i * NY + j];
+        v += sr[b.im * NY + j];
+        v += sr[b.ip * NY + j];
+        v += sr[i * NY + b.jm];
+        v += sr[i * NY + b.jp];
+        L.u[i * NY + j] = v * 0.25f;
+    }
+}
+
+// One wavefront's barrier: its lanes run in lockstep and LDS serves one
+// wavefront's accesses in order, so fences around a wave barrier order the
+// phases.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kCoarseWaveNodes = 640;   // LDS levels at most this size are run by one wavefront
 
 // The levels from lg on: one 1024-thread work-group per instance, every level
-// in LDS.  Per level on the way down a black half-sweep, then the restriction
-// of the red residuals (formed on the fly) to the next level with its
-// red-from-zero start; on the coarsest level red-black sweeps; per level on
-// the way up the black update from the corrected reds (formed on the fly),
-// then a red half-sweep.  Half-sweeps visit the nodes of their colour only.
+// in LDS.  Per level on the way down a black half-sweep, the red residuals,
+// their restriction to the next level with its red-from-zero start; on the
+// coarsest level red-black sweeps; per level on the way up the corrected
+// reds, the black update from them, then a red half-sweep.  The levels of at
+// most kCoarseWaveNodes nodes, from the first such level to the coarsest and
+// back, are run by the first wavefront alone (no work-group barriers).
 __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
 {
     const Inst &I = insts[t.id[blockIdx.x]];
@@ -1401,137 +1500,101 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
         dims[1][tid] = a.NY[tid];
     }
     __syncthreads();
-#define u(l) ((float *)(lds + tab[0][l]))
-#define gg(l) ((float *)(lds + tab[1][l]))
-#define fx(l) ((uint8_t *)(lds + tab[2][l]))
-    for (int l = 0; l < a.nlev; l++) {
+    auto lev = [&](int l) {
+        CLev L;
+        L.u = (float *)(lds + tab[0][l]);
+        L.g = (float *)(lds + tab[1][l]);
+        L.f = (const uint8_t *)(lds + tab[2][l]);
+        L.NX = dims[0][l];
+        L.NY = dims[1][l];
+        return L;
+    };
+    float *sr = (float *)(lds + a.off_s);
+    const int nlev = a.nlev, px = a.px, py = a.py;
+    for (int l = 0; l < nlev; l++) {
         const int N = dims[0][l] * dims[1][l];
         const uint8_t *src = a.fix[l];
-        for (int k = tid; k < N; k += nt) fx(l)[k] = src[k];
+        uint8_t *dst = lds + tab[2][l];
+        for (int k = tid; k < N; k += nt) dst[k] = src[k];
     }
     {
-        const int NY = dims[1][0], N = dims[0][0] * NY;
-        const float rcp = 1.0f / (float)NY;
+        const CLev L = lev(0);
+        const int N = L.NX * L.NY;
+        const float rcp = 1.0f / (float)L.NY;
         for (int k = tid; k < N; k += nt) {
             const float gv = a.g_top[k];
-            gg(0)[k] = gv;
-            const int i = div_rcp(k, rcp), j = k - i * NY;
-            u(0)[k] = (!a.fix[0][k] && ((i + j) & 1) == 0) ? gv * 0.25f : 0.0f;
+            L.g[k] = gv;
+            const int i = div_rcp(k, rcp), j = k - i * L.NY;
+            L.u[k] = (!a.fix[0][k] && ((i + j) & 1) == 0) ? gv * 0.25f : 0.0f;
         }
     }
     __syncthreads();
-    // descend
-    for (int l = 0; l < a.nlev - 1; l++) {
-        const int NX = dims[0][l], NY = dims[1][l];
-        const int HW = (NY + 1) >> 1;
-        const float rcpw = 1.0f / (float)HW;
-        float *ul = u(l);
-        const float *gl = gg(l);
-        const uint8_t *fl = fx(l);
-        for (int q = tid; q < NX * HW; q += nt) {          // black half-sweep
-            const int i = div_rcp(q, rcpw), j = 2 * (q - i * HW) + ((i + 1) & 1);
-            if (j < NY && !fl[i * NY + j]) ul[i * NY + j] = gs_nofix(ul, gl, i, j, NX, NY);
-        }
+    // first level run by one wavefront (nlev when none is small enough)
+    int ls = 0;
+    while (ls < nlev && dims[0][ls] * dims[1][ls] > kCoarseWaveNodes) ls++;
+    const int lb = ls < nlev - 1 ? ls : nlev - 1;           // levels below lb descend with the work-group
+    for (int l = 0; l < lb; l++) {
+        const CLev L = lev(l), C = lev(l + 1);
+        c_sweep(L, 1, tid, nt);
         __syncthreads();
-        const int NXc = dims[0][l + 1], NYc = dims[1][l + 1];
-        const float rcpc = 1.0f / (float)NYc;
-        float *uc = u(l + 1), *gc = gg(l + 1);
-        const uint8_t *fc = fx(l + 1);
-        for (int k = tid; k < NXc * NYc; k += nt) {        // restriction
-            const int Ic = div_rcp(k, rcpc), Jc = k - Ic * NYc;
-            float gv = 0.0f, uv = 0.0f;
-            if (!fc[k]) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int di = -1; di <= 1; di++) {
-#pragma unroll
-                    for (int dj = -1; dj <= 1; dj++) {
-                        if ((di + dj) & 1) continue;
-                        int ai = 2 * Ic + di, cj = 2 * Jc + dj;
-                        if (a.px) ai = wrap_hi(wrap_lo(ai, NX), NX);
-                        else if (ai < 0 || ai >= NX) continue;
-                        if (a.py) cj = wrap_hi(wrap_lo(cj, NY), NY);
-                        else if (cj < 0 || cj >= NY) continue;
-                        const float w = (di == 0) ? 1.0f : 0.25f;
-                        acc += w * resid_nofix(ul, gl, fl, ai, cj, NX, NY);
-                    }
-                }
-                gv = acc;
-                if (((Ic + Jc) & 1) == 0) uv = gv * 0.25f;
-            }
-            gc[k] = gv;
-            uc[k] = uv;
-        }
+        c_resid_red(L, sr, tid, nt);
+        __syncthreads();
+        c_restrict(L, sr, C, px, py, tid, nt);
         __syncthreads();
     }
-    // coarsest: red-black sweeps (first black completes the pre-smoothing).
-    // A level of at most 64 nodes is swept by the first wavefront alone: its
-    // lanes run in lockstep and LDS serves one wavefront's accesses in
-    // order, so a wavefront barrier separates the colours.
-    {
-        const int l = a.nlev - 1, NX = dims[0][l], NY = dims[1][l], N = NX * NY;
-        const float rcp = 1.0f / (float)NY;
-        if (N <= 64) {
-            if (tid < 64) {
-                const int k = tid;
-                const int i = div_rcp(k, rcp), j = k - i * NY;
-                const bool mine = k < N && !fx(l)[k];
-                for (int sw = 0; sw < a.sweeps; sw++) {
-                    for (int col = 1; col >= 0; col--) {
-                        if (mine && ((i + j) & 1) == col) u(l)[k] = gs_nofix(u(l), gg(l), i, j, NX, NY);
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    }
-                }
+    if (ls < nlev) {
+        if (tid < 64) {
+            for (int l = ls; l < nlev - 1; l++) {
+                const CLev L = lev(l), C = lev(l + 1);
+                c_sweep(L, 1, tid, 64);
+                wave_sync();
+                c_resid_red(L, sr, tid, 64);
+                wave_sync();
+                c_restrict(L, sr, C, px, py, tid, 64);
+                wave_sync();
             }
-            __syncthreads();
-        } else {
+            // coarsest: red-black sweeps (the first black completes the pre-smoothing)
+            const CLev L = lev(nlev - 1);
             for (int sw = 0; sw < a.sweeps; sw++) {
-                for (int col = 1; col >= 0; col--) {
-                    for (int k = tid; k < N; k += nt) {
-                        const int i = div_rcp(k, rcp), j = k - i * NY;
-                        if (!fx(l)[k] && ((i + j) & 1) == col) u(l)[k] = gs_nofix(u(l), gg(l), i, j, NX, NY);
-                    }
-                    __syncthreads();
-                }
+                c_sweep(L, 1, tid, 64);
+                wave_sync();
+                c_sweep(L, 0, tid, 64);
+                wave_sync();
+            }
+            for (int l = nlev - 2; l >= ls; l--) {
+                const CLev F = lev(l), C = lev(l + 1);
+                c_correct_red(F, C, sr, tid, 64);
+                wave_sync();
+                c_black_from(F, sr, tid, 64);
+                wave_sync();
+                c_sweep(F, 0, tid, 64);
+                wave_sync();
             }
         }
-    }
-    // ascend
-    for (int l = a.nlev - 2; l >= 0; l--) {
-        const int NX = dims[0][l], NY = dims[1][l];
-        const int NXc = dims[0][l + 1], NYc = dims[1][l + 1];
-        const int HW = (NY + 1) >> 1;
-        const float rcpw = 1.0f / (float)HW;
-        float *ul = u(l);
-        const float *gl = gg(l), *uc = u(l + 1);
-        const uint8_t *fl = fx(l);
-        for (int q = tid; q < NX * HW; q += nt) {          // black update from the corrected reds
-            const int i = div_rcp(q, rcpw), j = 2 * (q - i * HW) + ((i + 1) & 1);
-            if (j >= NY || fl[i * NY + j]) continue;
-            Nb b = nbs(i, j, NX, NY);
-            float s = gl[i * NY + j];
-            s += corrected_red(ul, fl, uc, b.im, j, NY, NXc, NYc);
-            s += corrected_red(ul, fl, uc, b.ip, j, NY, NXc, NYc);
-            s += corrected_red(ul, fl, uc, i, b.jm, NY, NXc, NYc);
-            s += corrected_red(ul, fl, uc, i, b.jp, NY, NXc, NYc);
-            ul[i * NY + j] = s * 0.25f;
-        }
         __syncthreads();
-        for (int q = tid; q < NX * HW; q += nt) {          // red half-sweep
-            const int i = div_rcp(q, rcpw), j = 2 * (q - i * HW) + (i & 1);
-            if (j < NY && !fl[i * NY + j]) ul[i * NY + j] = gs_nofix(ul, gl, i, j, NX, NY);
+    } else {
+        const CLev L = lev(nlev - 1);
+        for (int sw = 0; sw < a.sweeps; sw++) {
+            c_sweep(L, 1, tid, nt);
+            __syncthreads();
+            c_sweep(L, 0, tid, nt);
+            __syncthreads();
         }
+    }
+    for (int l = lb - 1; l >= 0; l--) {
+        const CLev F = lev(l), C = lev(l + 1);
+        c_correct_red(F, C, sr, tid, nt);
+        __syncthreads();
+        c_black_from(F, sr, tid, nt);
+        __syncthreads();
+        c_sweep(F, 0, tid, nt);
         __syncthreads();
     }
     {
         const int N = dims[0][0] * dims[1][0];
-        for (int k = tid; k < N; k += nt) a.u_top[k] = u(0)[k];
+        const float *u0 = (const float *)(lds + tab[0][0]);
+        for (int k = tid; k < N; k += nt) a.u_top[k] = u0[k];
     }
-#undef u
-#undef gg
-#undef fx
 }
 
 void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s)

@@ -146,6 +146,7 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
             size_t n = (size_t)L.NXl[l] * L.NYl[l];
             lds += ((n * 4 + 15) & ~size_t(15)) * 2 + ((n + 15) & ~size_t(15));
         }
+        if (lg < L.nlev) lds += ((size_t)L.NXl[lg] * L.NYl[lg] * 4 + 15) & ~size_t(15);   // scratch
         return lds;
     };
     L.lg = 1;
@@ -860,6 +861,8 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
             off += (nn + 15) & ~15;
             ca.fix[q] = h.d_fix[l];
         }
+        ca.off_s = off;
+        off += (L.NXl[L.lg] * L.NYl[L.lg] * 4 + 15) & ~15;
         ca.lds_bytes = off;
         ca.u_top = h.d_u[L.lg];
         ca.g_top = h.d_g[L.lg];
