@@ -302,8 +302,9 @@ def copy_calibration():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=400,
+                    help="untimed steps first: the sheath forms and the push settles to its long-run rate")
     ap.add_argument("--workload", default="trench1024x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unet-only", action="store_true",
