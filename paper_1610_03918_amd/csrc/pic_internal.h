@@ -215,7 +215,10 @@ int bin_per_block();
 inline size_t push_lds_bytes(int TX, int TY, int H)
 {
     const size_t mom = (size_t)(TX + 2 * H) * (TY + 2 * H) * 16 + kNClass * 4;
-    return ((mom + 15) & ~(size_t)15) + (size_t)(TX + 2) * (TY + 2) * 32;
+    // cell moments of the window, the corner fields of the tile + 1-cell frame,
+    // the conductor map of the window + 1-cell frame
+    return ((mom + 15) & ~(size_t)15) + (size_t)(TX + 2) * (TY + 2) * 32 +
+           (size_t)(TX + 2 * H + 2) * (TY + 2 * H + 2);
 }
 
 } // namespace pic

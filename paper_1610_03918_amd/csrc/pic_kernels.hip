@@ -1673,11 +1673,17 @@ struct PK {
     GLOBAL unsigned long long *iad;
     HitLog log;
     const long long *step;
+    // LDS copy of the conductor map of cells c0i .. c0i+CW-1, c0j .. c0j+CH-1
+    // (the block's deposit window and a one-cell frame; CW = 0: none)
+    const uint8_t *scc;
+    int c0i, c0j, CW, CH;
 };
 
 __device__ __forceinline__ PK resolve(const PushArgs &a)
 {
     PK k;
+    k.scc = nullptr;
+    k.c0i = k.c0j = k.CW = k.CH = 0;
     const int set = (int)a.info[7];
     k.g = a.g;
     k.TX = a.TX;
@@ -1762,7 +1768,14 @@ __device__ __forceinline__ bool push_core(const PK &a, float x0, float y0, float
                 else if (ni < 0 || ni >= g.nx) out = true;
                 if (g.py) nj = wrap_hi(wrap_lo(nj, g.ny), g.ny);
                 else if (nj < 0 || nj >= g.ny) out = true;
-                if (!out && a.cell_cond[(long long)ni * g.ny + nj]) out = true;
+                if (!out) {
+                    // conductor test from the block's LDS map when the cell lies in it
+                    int li = ni - a.c0i, lj = nj - a.c0j;
+                    if (g.px) { if (li < 0) li += g.nx; else if (li >= g.nx) li -= g.nx; }
+                    if (g.py) { if (lj < 0) lj += g.ny; else if (lj >= g.ny) lj -= g.ny; }
+                    const bool loc = li >= 0 && li < a.CW && lj >= 0 && lj < a.CH;
+                    if (loc ? a.scc[li * a.CH + lj] : a.cell_cond[(long long)ni * g.ny + nj]) out = true;
+                }
                 if (out) {
                     const bool inbox = ei >= a.box_i_top && ej >= a.box_j_lo && ej < a.box_j_hi;
                     dead = dir + (inbox ? 4 : 0);
@@ -1951,7 +1964,7 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
     const int lb = (int)blockIdx.x - t.boff[ku];
     if ((long long)lb >= aa.info[1]) return;
     const int4 ent = aa.table[lb];
-    const PK a = resolve(aa);
+    PK a = resolve(aa);
     unsigned long long *const tally = aa.tally;
     unsigned long long *const fallbacks = aa.fallbacks;
     const int tile = ent.x, start = ent.y, end = ent.z;
@@ -1967,6 +1980,13 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
     float4 *sE = (float4 *)(smem + (((size_t)WC * 16 + kNClass * 4 + 15) & ~(size_t)15));
     const int EW = a.TX + 2, EH = a.TY + 2;
     const int e0i = ti * a.TX - 1, e0j = tj * a.TY - 1;
+    // conductor map of the window and a one-cell frame, after the fields
+    uint8_t *scc = (uint8_t *)(sE + 2 * EW * EH);
+    a.scc = scc;
+    a.c0i = i0 - 1;
+    a.c0j = j0 - 1;
+    a.CW = PUSH ? WX + 2 : 0;
+    a.CH = WY + 2;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const Geom g = a.g;
@@ -1983,6 +2003,15 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
             if (g.py) cj = wrap_hi(wrap_lo(cj, g.ny), g.ny);
             if (ci >= 0 && ci < g.nx && cj >= 0 && cj < g.ny)
                 sE[k] = ld_f4(a.E4 + 2 * ((long long)ci * g.ny + cj) + (k & 1));
+        }
+        for (int k = tid; k < a.CW * a.CH; k += kPushThreads) {
+            const int li = k / a.CH, lj = k - li * a.CH;
+            int ci = a.c0i + li, cj = a.c0j + lj;
+            if (g.px) ci = ((ci % g.nx) + g.nx) % g.nx;
+            if (g.py) cj = ((cj % g.ny) + g.ny) % g.ny;
+            // cells outside a bounded axis are never looked up (the walk
+            // tests the domain first)
+            scc[k] = (ci >= 0 && ci < g.nx && cj >= 0 && cj < g.ny) ? a.cell_cond[(long long)ci * g.ny + cj] : 1;
         }
     }
     __syncthreads();
