@@ -21,6 +21,7 @@ constexpr int kMaxUnits = 2 * kMaxInst;
 constexpr int kGridBX = 64;      // grid kernels: 64 x 4 threads over (y, x) nodes
 constexpr int kGridBY = 4;
 constexpr int kPushThreads = 256;
+constexpr int kFieldFrame = 1;    // cells around a push tile whose corner fields the block stages in LDS
 
 struct Geom {
     int nx, ny;     // cells
@@ -217,7 +218,7 @@ inline size_t push_lds_bytes(int TX, int TY, int H)
     const size_t mom = (size_t)(TX + 2 * H) * (TY + 2 * H) * 16 + kNClass * 4;
     // cell moments of the window, the corner fields of the tile + 1-cell frame,
     // the conductor map of the window + 1-cell frame
-    return ((mom + 15) & ~(size_t)15) + (size_t)(TX + 2) * (TY + 2) * 32 +
+    return ((mom + 15) & ~(size_t)15) + (size_t)(TX + 2 * kFieldFrame) * (TY + 2 * kFieldFrame) * 32 +
            (size_t)(TX + 2 * H + 2) * (TY + 2 * H + 2);
 }
 

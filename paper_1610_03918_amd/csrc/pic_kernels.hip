@@ -1978,8 +1978,8 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
     unsigned *tl = (unsigned *)(mB + WC);
     // corner fields of the tile + 1-cell frame
     float4 *sE = (float4 *)(smem + (((size_t)WC * 16 + kNClass * 4 + 15) & ~(size_t)15));
-    const int EW = a.TX + 2, EH = a.TY + 2;
-    const int e0i = ti * a.TX - 1, e0j = tj * a.TY - 1;
+    const int EW = a.TX + 2 * kFieldFrame, EH = a.TY + 2 * kFieldFrame;
+    const int e0i = ti * a.TX - kFieldFrame, e0j = tj * a.TY - kFieldFrame;
     // conductor map of the window and a one-cell frame, after the fields
     uint8_t *scc = (uint8_t *)(sE + 2 * EW * EH);
     a.scc = scc;
