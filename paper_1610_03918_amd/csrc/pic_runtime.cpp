@@ -232,6 +232,8 @@ struct pic_ctx {
     int part_stride = 0;
     double *d_S = nullptr;          // n x S_NSCAL
     int *d_F = nullptr;             // n x F_NFLAG
+    char *h_flags = nullptr;       // pinned host copy of the span d_S .. end of d_F
+    size_t flags_bytes = 0;
     double *d_V = nullptr;          // kVWindow x n x 8
     long long *d_ctl = nullptr;     // [0] step, [1] first step of the V window
     long long step = 0, vbase = 0;
@@ -611,9 +613,11 @@ pic_status read_flags(pic_ctx *c, std::vector<double> &S, std::vector<int> &F)
 {
     S.resize((size_t)c->n * S_NSCAL);
     F.resize((size_t)c->n * F_NFLAG);
-    HIPCHK(c, hipMemcpyAsync(S.data(), c->d_S, S.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(F.data(), c->d_F, F.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    // one copy of the scalar and flag blocks (adjacent in the workspace) into pinned memory
+    HIPCHK(c, hipMemcpyAsync(c->h_flags, c->d_S, c->flags_bytes, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    memcpy(S.data(), c->h_flags, S.size() * sizeof(double));
+    memcpy(F.data(), c->h_flags + ((char *)c->d_F - (char *)c->d_S), F.size() * sizeof(int));
     return PIC_OK;
 }
 
@@ -647,25 +651,34 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess)
     c->have_prev = (kind == 3);
     std::vector<double> S;
     std::vector<int> F;
-    pic_status st = read_flags(c, S, F);
-    if (st != PIC_OK) return st;
+    pic_status st = PIC_OK;
     int max_iter = 0;
     bool plain_cg = false;
     for (auto &h : c->in) {
         max_iter = std::max(max_iter, (int)h.cfg.max_iter);
         if (!h.dev.mg) plain_cg = true;
     }
+    // With multigrid the first pass is queued behind the start without a
+    // look at its flags (its kernels skip an instance that already
+    // converged), so a solve that needs one pass costs one host round trip.
+    bool have = false;
+    if (plain_cg) {
+        if ((st = read_flags(c, S, F)) != PIC_OK) return st;
+        have = true;
+    }
     for (int pass = 0; pass < 64; pass++) {
-        bool all = true;
-        bool finite = true;
         int most = 0;
-        for (int k = 0; k < c->n; k++) {
-            const int *f = &F[(size_t)k * F_NFLAG];
-            if (!f[F_CONV]) all = false;
-            if (!std::isfinite(S[(size_t)k * S_NSCAL + S_RR64])) finite = false;
-            most = std::max(most, f[F_ITER_TOT]);
+        if (have) {
+            bool all = true;
+            bool finite = true;
+            for (int k = 0; k < c->n; k++) {
+                const int *f = &F[(size_t)k * F_NFLAG];
+                if (!f[F_CONV]) all = false;
+                if (!std::isfinite(S[(size_t)k * S_NSCAL + S_RR64])) finite = false;
+                most = std::max(most, f[F_ITER_TOT]);
+            }
+            if (all || !finite || most >= max_iter) break;
         }
-        if (all || !finite || most >= max_iter) break;
         int &chunk = c->pass_chunk[std::min(pass, 1)];
         int K = std::max(1, std::min(std::min(chunk, 128), max_iter - most));
         if (plain_cg) {
@@ -695,17 +708,20 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess)
         if (st != PIC_OK) return st;
         st = read_flags(c, S, F);
         if (st != PIC_OK) return st;
-        int need = 0;
+        have = true;
+        int need = 0, ran = 0;
         bool unfinished = false;
         for (int k = 0; k < c->n; k++) {
             const int *f = &F[(size_t)k * F_NFLAG];
             if (f[F_SKIP]) continue;
+            ran++;
             need = std::max(need, f[F_ITER]);
             if (!f[F_DONE]) unfinished = true;
         }
         // next solve: the iterations this pass needed (passes differ: the
-        // first starts far from the tolerance), doubled when it ran short
-        chunk = unfinished ? std::min(2 * K, 128) : std::max(1, need);
+        // first starts far from the tolerance), doubled when it ran short;
+        // a pass every instance skipped tells nothing
+        if (ran) chunk = unfinished ? std::min(2 * K, 128) : std::max(1, need);
     }
     launch_shift_mean(c->d_inst, c->t_per, part_of(c), c->stream);
     record_solve_info(c, S, F);
@@ -1046,6 +1062,8 @@ pic_status batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, vo
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemsetAsync(c->d_S, 0, sizeof(double) * n * S_NSCAL, s));
     HIPCHK(c, hipMemsetAsync(c->d_F, 0, sizeof(int) * n * F_NFLAG, s));
+    c->flags_bytes = (size_t)((char *)(c->d_F + (size_t)n * F_NFLAG) - (char *)c->d_S);
+    HIPCHK(c, hipHostMalloc((void **)&c->h_flags, c->flags_bytes, hipHostMallocDefault));
     for (int k = 0; k < n; k++) {
         pic_status st = init_instance(c, k, &cfgs[k], &bufs[k]);
         if (st != PIC_OK) return st;
@@ -1419,6 +1437,7 @@ void pic_destroy(pic_ctx *c)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto e : c->ev0) if (e) (void)hipEventDestroy(e);
     for (auto e : c->ev1) if (e) (void)hipEventDestroy(e);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
     delete c;
 }
 
