@@ -257,18 +257,13 @@ def run_sweep(args):
     b = PicBatch(ws, parts, sort_interval=sort, chunk=sch["chunk"], push_unroll=sch["push_unroll"],
                  push_merge=sch["push_merge"], tile=tuple(sch["tile"]), halo=sch["halo"])
     b.start()
-    # eager steps tell how many iterations the captured schedule needs
-    most = 0
-    for _ in range(max(2, args.warmup)):
-        b.pic_step(1)
-        most = max(most, max(b.pic_batch_solve_info(i)["iterations"] for i in range(b.n)))
-    iters = min(128, most + 2)
-    passes = 2
-    b.pic_batch_step(sort[0] if sort[0] > 0 else 8, passes, iters)
+    # eager steps tell how many passes and iterations the captured schedule needs
+    passes, iters, iters_later = autotune.solver_schedule(b, args.warmup)
+    b.pic_batch_step(sort[0] if sort[0] > 0 else 8, passes, iters, iters_later)
     torch.cuda.synchronize()
     a0 = sum(sum(b.pic_batch_diagnostics(i)["alive"]) for i in range(b.n))
     t0 = time.perf_counter()
-    infos = b.pic_batch_step(args.steps, passes, iters)
+    infos = b.pic_batch_step(args.steps, passes, iters, iters_later)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     a1 = sum(sum(b.pic_batch_diagnostics(i)["alive"]) for i in range(b.n))
@@ -280,7 +275,7 @@ def run_sweep(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "trench-width sweep x16 (batched, graph-captured)",
                       "widths": list(synth.SWEEP_WIDTHS), "ppc": ws[0].species[0].ppc,
-                      "particles": int(n0), "solver_schedule": [passes, iters],
+                      "particles": int(n0), "solver_schedule": {"passes": passes, "iters_first": iters, "iters_later": iters_later},
                       "all_converged": conv, "schedule": sch, "schedule_source": source}}
     b.close()
     print(json.dumps(out), flush=True)

@@ -112,7 +112,7 @@ typedef struct {
     int32_t iterations;          /* preconditioned CG iterations (one V-cycle each) */
     int32_t outer;               /* float64 refinement passes */
     int32_t converged;
-    int32_t pad;
+    int32_t iterations_first;    /* of those, the iterations of the first refinement pass */
     double relres0;              /* relative residual of the start */
     double relres;               /* final relative residual (float64) */
 } pic_solve_info;
@@ -244,12 +244,13 @@ pic_status pic_batch_init(int32_t n, const pic_config *cfgs, const pic_buffers *
 /* nsteps steps of every instance as captured HIP graphs, one launch per
  * re-binning period of species 0 (its sort_interval, or 8): each step solves
  * from the extrapolated potential with a fixed schedule of `passes`
- * float64 refinement passes of `iters` preconditioned CG iterations, every
+ * float64 refinement passes, the first of `iters` preconditioned CG
+ * iterations and the later ones of `iters_later` (0: `iters`), every
  * instance leaving the schedule as soon as it meets its rtol, then pushes.
  * Waits at the end; per-instance results in pic_batch_solve_info (converged
  * = 0 flags an instance the schedule was too short for).  If no earlier
  * extrapolated solve exists, the first step runs as pic_step(1). */
-pic_status pic_batch_step(pic_ctx *ctx, int32_t nsteps, int32_t passes, int32_t iters);
+pic_status pic_batch_step(pic_ctx *ctx, int32_t nsteps, int32_t passes, int32_t iters, int32_t iters_later);
 
 /* Per-instance counters, particle set and last solve (i in 0..n-1). */
 pic_status pic_batch_diagnostics(pic_ctx *ctx, int32_t i, pic_diag *out);

@@ -60,15 +60,15 @@ def lookup(workloads, parts, path=CACHE):
     return load_cache(path).get(signature(workloads, parts))
 
 
-def _measure(b, period, steps, passes, iters, repeats=2):
+def _measure(b, period, steps, passes, iters, iters_later=0, repeats=2):
     """Best of `repeats` timings of `steps` captured steps (ms/step)."""
     import torch
-    b.pic_batch_step(period or 8, passes, iters)     # capture + warm
+    b.pic_batch_step(period or 8, passes, iters, iters_later)     # capture + warm
     best, ok = None, True
     for _ in range(repeats):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        infos = b.pic_batch_step(steps, passes, iters)
+        infos = b.pic_batch_step(steps, passes, iters, iters_later)
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / steps
         best = ms if best is None else min(best, ms)
@@ -76,12 +76,29 @@ def _measure(b, period, steps, passes, iters, repeats=2):
     return best, ok
 
 
-def _solver_schedule(b, warm):
-    most = 0
-    for _ in range(max(2, warm)):
+def solver_schedule(b, warm, window=100):
+    """Fixed solver schedule for captured steps, (passes, first-pass
+    iterations, later-pass iterations), from `warm` eager steps: the most
+    any instance needed over the last `window` of them, with margins."""
+    first = later = 0
+    passes = 1
+    n = max(2, warm)
+    for k in range(n):
         b.pic_step(1)
-        most = max(most, max(b.pic_batch_solve_info(i)["iterations"] for i in range(b.n)))
-    return 2, min(128, most + 2)
+        if k < n - window:
+            continue
+        for i in range(b.n):
+            info = b.pic_batch_solve_info(i)
+            first = max(first, info["iterations_first"])
+            later = max(later, info["iterations"] - info["iterations_first"])
+            passes = max(passes, info["outer"])
+    # a second, short pass always: a step that the window did not show may
+    # need it, and an instance that converged skips it
+    return max(passes, 2), min(128, first + 2), min(128, max(2, later + 1))
+
+
+def _solver_schedule(b, warm):
+    return solver_schedule(b, warm)
 
 
 def tune(workloads, parts, steps=32, log=None, path=CACHE):

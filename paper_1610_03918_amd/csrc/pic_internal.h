@@ -55,6 +55,7 @@ enum {
     F_SKIP,      // the current pass was skipped (already converged)
     F_ITER_TOT,  // inner iterations since the start of the solve
     F_PASSES,    // refinement passes since the start of the solve
+    F_ITER1,     // inner iterations of the solve's first pass
     F_NFLAG = 8
 };
 

@@ -113,6 +113,7 @@ __device__ void apply_op(const Inst &I, int op, double t0, double t1)
         F[F_CONV] = (t0 <= tol2 * (t1 > 0.0 ? t1 : 1.0)) ? 1 : 0;
         F[F_ITER_TOT] = 0;
         F[F_PASSES] = 0;
+        F[F_ITER1] = 0;
         F[F_DONE] = 0;
         F[F_SKIP] = 0;
         break;
@@ -140,6 +141,7 @@ __device__ void apply_op(const Inst &I, int op, double t0, double t1)
         S[S_RR] = t0;
         F[F_ITER] += 1;
         F[F_ITER_TOT] += 1;
+        if (F[F_PASSES] == 1) F[F_ITER1] = F[F_ITER];
         if (t0 <= S[S_ETA2] * S[S_RR0]) F[F_DONE] = 1;
         if (!I.mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t1; }
         break;

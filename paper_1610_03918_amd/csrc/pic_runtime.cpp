@@ -631,6 +631,7 @@ void record_solve_info(pic_ctx *c, const std::vector<double> &S, const std::vect
         si.iterations = f[F_ITER_TOT];
         si.outer = f[F_PASSES];
         si.converged = f[F_CONV];
+        si.iterations_first = f[F_ITER1];
         si.relres0 = std::sqrt(s[S_RELRES0] / bb);
         si.relres = std::sqrt(s[S_RR64] / bb);
     }
@@ -1094,9 +1095,10 @@ pic_status batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, vo
 // Captured graph of P whole steps (fixed solver schedule: `passes` passes of
 // K iterations with per-instance early exit) ending with the re-binnings in
 // sort_mask.
-pic_status step_graph(pic_ctx *c, int P, int passes, int K, int sort_mask, hipGraphExec_t *ex)
+pic_status step_graph(pic_ctx *c, int P, int passes, int K, int K2, int sort_mask, hipGraphExec_t *ex)
 {
-    const long long key = ((long long)P << 32) | ((long long)passes << 24) | ((long long)K << 8) | sort_mask;
+    const long long key = ((long long)P << 32) | ((long long)passes << 28) | ((long long)K << 20) |
+                          ((long long)K2 << 12) | sort_mask;
     auto it = c->step_graphs.find(key);
     if (it != c->step_graphs.end()) {
         *ex = it->second;
@@ -1107,7 +1109,7 @@ pic_status step_graph(pic_ctx *c, int P, int passes, int K, int sort_mask, hipGr
     hipStream_t s = c->cap_stream;
     for (int k = 0; k < P; k++) {
         enqueue_solve_start(c, 3, nullptr, s);
-        for (int q = 0; q < passes; q++) enqueue_pass(c, K, s);
+        for (int q = 0; q < passes; q++) enqueue_pass(c, q == 0 ? K : K2, s);
         launch_shift_mean(c->d_inst, c->t_per, part_of(c), s);
         enqueue_push(c, s, false);
     }
@@ -1216,11 +1218,12 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps)
     return PIC_OK;
 }
 
-pic_status pic_batch_step(pic_ctx *c, int32_t nsteps, int32_t passes, int32_t iters)
+pic_status pic_batch_step(pic_ctx *c, int32_t nsteps, int32_t passes, int32_t iters, int32_t iters_later)
 {
     if (check(c) != PIC_OK) return PIC_ERR_STATE;
-    if (nsteps < 0 || passes < 1 || passes > 8 || iters < 1 || iters > 128)
-        return fail(c, PIC_ERR_ARG, "nsteps >= 0, passes in 1..8, iters in 1..128");
+    if (iters_later == 0) iters_later = iters;
+    if (nsteps < 0 || passes < 1 || passes > 8 || iters < 1 || iters > 128 || iters_later < 1 || iters_later > 128)
+        return fail(c, PIC_ERR_ARG, "nsteps >= 0, passes in 1..8, iters and iters_later in 1..128");
     if (!c->have_prev) {
         // the captured schedule extrapolates from two earlier solutions
         pic_status st = pic_step(c, 1);
@@ -1234,7 +1237,7 @@ pic_status pic_batch_step(pic_ctx *c, int32_t nsteps, int32_t passes, int32_t it
         if (st != PIC_OK) return st;
         const int mask = sorts_due(c, c->step + len);
         hipGraphExec_t ex;
-        st = step_graph(c, len, passes, iters, mask, &ex);
+        st = step_graph(c, len, passes, iters, iters_later, mask, &ex);
         if (st != PIC_OK) return st;
         HIPCHK(c, hipGraphLaunch(ex, c->stream));
         c->step += len;

@@ -54,10 +54,11 @@ class pic_buffers(C.Structure):
 
 class pic_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer", C.c_int32), ("converged", C.c_int32),
-                ("pad", C.c_int32), ("relres0", C.c_double), ("relres", C.c_double)]
+                ("iterations_first", C.c_int32), ("relres0", C.c_double), ("relres", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k in ("iterations", "outer", "converged", "relres0", "relres")}
+        return {k: getattr(self, k) for k in ("iterations", "iterations_first", "outer", "converged", "relres0",
+                                              "relres")}
 
 
 class pic_diag(C.Structure):
@@ -111,7 +112,7 @@ def lib():
                                            C.POINTER(C.c_size_t)]
     L.pic_batch_init.argtypes = [i32, C.POINTER(pic_config), C.POINTER(pic_buffers), P, C.c_size_t, P,
                                  C.POINTER(P)]
-    L.pic_batch_step.argtypes = [P, i32, i32, i32]
+    L.pic_batch_step.argtypes = [P, i32, i32, i32, i32]
     L.pic_batch_diagnostics.argtypes = [P, i32, C.POINTER(pic_diag)]
     L.pic_batch_particles.argtypes = [P, i32, i32, C.POINTER(i32), C.POINTER(i64)]
     L.pic_batch_solve_info.argtypes = [P, i32, C.POINTER(pic_solve_info)]
@@ -450,8 +451,8 @@ class PicBatch(_Context):
     def pic_step(self, n=1):
         self._chk(lib().pic_step(self.ctx, int(n)))
 
-    def pic_batch_step(self, n, passes=2, iters=12):
-        self._chk(lib().pic_batch_step(self.ctx, int(n), int(passes), int(iters)))
+    def pic_batch_step(self, n, passes=2, iters=12, iters_later=0):
+        self._chk(lib().pic_batch_step(self.ctx, int(n), int(passes), int(iters), int(iters_later)))
         return [self.pic_batch_solve_info(i) for i in range(self.n)]
 
     def pic_batch_solve_info(self, i):
