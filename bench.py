@@ -229,6 +229,36 @@ def run_unet(args):
     print(json.dumps(out), flush=True)
 
 
+def run_solvers(args):
+    """The solvers side by side from a cold start (phi = 0 on free nodes) on the
+    periodic 64 x 64 and the grounded 256 x 256 squares: multigrid-
+    preconditioned CG, plain CG, and the paper's own Jacobi and Gauss-Seidel
+    sweeps (Sec. II), each to the workload's tolerance."""
+    import torch
+
+    import synth
+    from paper_1610_03918_amd import Pic
+    rows = []
+    for w in (synth.periodic_square(n=64, ppc=4), synth.bounded_square(n=256, ppc=4)):
+        parts = synth.load(w)
+        for solver, name in ((0, "multigrid CG"), (1, "CG"), (2, "Jacobi"), (3, "Gauss-Seidel")):
+            pic = Pic(w, parts, solver=solver, max_iter=2_000_000, sort_interval=(0, 0))
+            pic.pic_solve(0)                      # graphs captured, caches warm
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                info = pic.pic_solve(0)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            pic.close()
+            rows.append({"workload": w.name, "solver": name, "rtol": w.rtol, "iterations": info["iterations"],
+                         "ms_per_solve": ms, "relres": info["relres"], "converged": bool(info["converged"])})
+            log(f"{w.name:12s} {name:14s} {info['iterations']:8d} it {ms:10.3f} ms relres {info['relres']:.2e}")
+    print(json.dumps({"metric": "Poisson solve from a cold start: ms and iterations (sweeps for Jacobi and "
+                                "Gauss-Seidel)", "n_gpus": 1, "data": "synthetic", "results": rows}), flush=True)
+
+
 def run_sweep(args):
     """The 16-width trench sweep advanced as one batch with captured graphs."""
     import torch
@@ -304,6 +334,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unet-only", action="store_true",
                     help="only time the learned start's network (1024 x 512)")
+    ap.add_argument("--solvers", action="store_true",
+                    help="only compare the solvers (MG-CG, CG, Jacobi, Gauss-Seidel) from a cold start")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sort", default="8,64")
@@ -333,6 +365,8 @@ def main():
         return run_unet(args)
     if args.workload == "sweep":
         return run_sweep(args)
+    if args.solvers:
+        return run_solvers(args)
 
     import numpy as np
     import torch

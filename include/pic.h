@@ -78,8 +78,12 @@ typedef struct {
     double static_density;       /* mode 1: extra n_i on charge_row, static_j_lo..static_j_hi */
     int32_t static_j_lo, static_j_hi;
     double rtol;                 /* relative residual ||b - A phi|| / ||b|| of the solve */
-    int32_t max_iter;            /* cap on preconditioned CG iterations per solve */
-    int32_t solver;              /* 0 multigrid-preconditioned CG, 1 plain CG */
+    int32_t max_iter;            /* cap on iterations per solve (CG iterations, or sweeps) */
+    int32_t solver;              /* 0 multigrid-preconditioned CG, 1 plain CG, and the paper's own
+                                    iterations (Sec. II) in float64: 2 Jacobi sweeps, 3 red-black
+                                    Gauss-Seidel sweeps (a periodic axis needs an even node count);
+                                    a batch mixes no CG and sweep instances, and pic_batch_step
+                                    needs CG */
     int32_t sort_interval[2];    /* steps between re-binnings per species (0 = at init only) */
     int32_t tile_x, tile_y;      /* particle tile in cells (powers of two; 0 = 16) */
     int32_t halo;                /* cells of drift a tile absorbs before a global fallback (0 = 4) */

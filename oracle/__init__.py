@@ -13,6 +13,8 @@ Functions and the passages they follow:
   assemble       source of eq. (5) plus Dirichlet lifts          eq. (5), Sec. III.D
   solve_direct   exact solution of the 5-point system           eq. (5)
   cg             double-precision CG (independent check)       eq. (5)
+  jacobi         the paper's Jacobi iteration                   Sec. II
+  gauss_seidel   the paper's Gauss-Seidel iteration (red-black)  Sec. II
   field          E = -grad(phi), central / two-point at walls   Sec. II
   push_f32/f64   gather + leapfrog + wall test                  eqs. (1)-(4), Sec. III
   rewind_f32/f64 leapfrog start (half step back)                eqs. (1)-(2)
@@ -197,6 +199,70 @@ def cg(w, nc, b, phi0=None, rtol=1e-13, maxit=200000):
     it = lib().or_cg(w.NX, w.NY, int(w.periodic_x), int(w.periodic_y), _p(_c(nc, np.uint8)),
                      _p(_c(b, np.float64)), _p(phi), float(rtol), int(maxit), _p(rr))
     return phi, it, float(rr[0])
+
+
+def _sweep_setup(w, nc):
+    """Fixed-node mask (Dirichlet nodes, plus node (0, 0) on a fully periodic
+    grid) and, per direction x-1, x+1, y-1, y+1, the neighbour index of every
+    node (-1 outside a bounded axis)."""
+    NX, NY = w.NX, w.NY
+    fixed = nc.reshape(-1) != 0
+    if w.periodic_x and w.periodic_y:
+        fixed = fixed.copy()
+        fixed[0] = True
+    I, J = np.divmod(np.arange(NX * NY), NY)
+    nbrs = []
+    for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        a, c = I + di, J + dj
+        ok = np.ones(NX * NY, bool)
+        if w.periodic_x:
+            a = a % NX
+        else:
+            ok &= (a >= 0) & (a < NX)
+        if w.periodic_y:
+            c = c % NY
+        else:
+            ok &= (c >= 0) & (c < NY)
+        nbrs.append(np.where(ok, a * NY + np.where(ok, c, 0), -1))
+    return fixed, nbrs, (I + J) % 2
+
+
+def _sweep_values(phi, b, fixed, nbrs):
+    """(b + sum of the free neighbours) / 4 at every node, the neighbours added
+    in the order x-1, x+1, y-1, y+1 (a fixed neighbour's potential is in b)."""
+    s = b.copy()
+    for nb in nbrs:
+        use = (nb >= 0) & ~fixed[np.maximum(nb, 0)]
+        s = s + np.where(use, phi[np.maximum(nb, 0)], 0.0)
+    return s * 0.25
+
+
+def jacobi(w, nc, b, phi0, sweeps):
+    """`sweeps` Jacobi iterations of the masked 5-point system (Sec. II: the
+    paper solves eq. (5) with Jacobi or Gauss-Seidel iterations): every free
+    node from the previous iterate at once.  Fixed nodes keep phi0."""
+    fixed, nbrs, _ = _sweep_setup(w, nc)
+    phi = np.array(phi0, np.float64).reshape(-1).copy()
+    bf = np.asarray(b, np.float64).reshape(-1)
+    for _ in range(sweeps):
+        phi = np.where(fixed, phi, _sweep_values(phi, bf, fixed, nbrs))
+    return phi.reshape(w.NX, w.NY)
+
+
+def gauss_seidel(w, nc, b, phi0, sweeps):
+    """`sweeps` Gauss-Seidel iterations in red-black order (Sec. II): the
+    red nodes (i + j even) from the current iterate, then the black nodes from
+    the updated reds.  With an even node count on every periodic axis no two
+    nodes of one colour are neighbours, so each colour is one simultaneous
+    update.  Fixed nodes keep phi0."""
+    fixed, nbrs, colour = _sweep_setup(w, nc)
+    phi = np.array(phi0, np.float64).reshape(-1).copy()
+    bf = np.asarray(b, np.float64).reshape(-1)
+    for _ in range(sweeps):
+        for col in (0, 1):
+            upd = (colour == col) & ~fixed
+            phi = np.where(upd, _sweep_values(phi, bf, fixed, nbrs), phi)
+    return phi.reshape(w.NX, w.NY)
 
 
 def residual(w, nc, b, phi) -> float:

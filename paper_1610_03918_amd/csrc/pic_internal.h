@@ -87,6 +87,7 @@ struct Inst {
     LevelDev lev[kMaxLev];
     const uint8_t *node_cond, *cell_cond;
     double *phi, *b, *phi_prev;
+    double *phi2;                  // second potential buffer of the Jacobi sweeps (solver 2)
     unsigned long long *rho[2];
     float *e, *p[2], *q;
     float *z;                      // preconditioned residual of the CG (level-0 u)
@@ -184,6 +185,9 @@ void launch_set_guess(const Inst *I, const Tab &t, int kind, const double *guess
 void launch_extrapolate(const Inst *I, const Tab &t, int have_prev, hipStream_t s);
 void launch_resid64(const Inst *I, const Tab &t, int after_pass, Part pt, hipStream_t s);
 void launch_phi_update(const Inst *I, const Tab &t, hipStream_t s);
+// `sweeps` Jacobi (an even count: the result lands in phi) or red-black
+// Gauss-Seidel sweeps of the float64 system
+void launch_sweeps(const Inst *I, const Tab &t, int jacobi, int sweeps, hipStream_t s);
 void launch_init_red0(const Inst *I, const Tab &t, Part pt, hipStream_t s);
 void launch_pupdate_Ap(const Inst *I, const Tab &t, int kold, int first, Part pt, hipStream_t s);
 void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStream_t s);

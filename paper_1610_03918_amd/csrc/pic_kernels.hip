@@ -514,6 +514,67 @@ void launch_resid64(const Inst *I, const Tab &t, int after_pass, Part pt, hipStr
     finalize(I, t, pt, after_pass ? OP_RR64_PASS : OP_RR64_START, s);
 }
 
+// ---------------------------------------------------------------------------
+// the paper's own iterations for eq. (5) (Sec. II): Jacobi and Gauss-Seidel
+// sweeps of the masked 5-point system in float64.  A free node takes
+// (b + sum of its free neighbours) / 4 with the neighbours added in the order
+// x-1, x+1, y-1, y+1 (fixed neighbours' potentials sit in b); Gauss-Seidel
+// visits the red nodes (i + j even), then the black ones.  An instance whose
+// float64 residual already met rtol is left alone.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double sweep_value(const double *src, const double *b, const uint8_t *fix, int i,
+                                              int j, int NX, int NY, long long n)
+{
+    const int im = wrap_lo(i - 1, NX), ip = wrap_hi(i + 1, NX);
+    const int jm = wrap_lo(j - 1, NY), jp = wrap_hi(j + 1, NY);
+    const long long a = (long long)im * NY + j, c = (long long)ip * NY + j;
+    const long long d = (long long)i * NY + jm, e = (long long)i * NY + jp;
+    double s = b[n];
+    if (!fix[a]) s += src[a];
+    if (!fix[c]) s += src[c];
+    if (!fix[d]) s += src[d];
+    if (!fix[e]) s += src[e];
+    return s * 0.25;
+}
+
+// One Jacobi sweep: dir 0 reads phi and writes phi2, dir 1 the reverse.
+__global__ void k_jacobi64(const Inst *insts, Tab t, int dir)
+{
+    GRID_BEGIN(t)
+    if (I.F[F_CONV]) return;
+    NODE_IDX(I.g.NX, I.g.NY)
+    if (!inb) return;
+    const double *src = dir ? I.phi2 : I.phi;
+    double *dst = dir ? I.phi : I.phi2;
+    const uint8_t *fix = I.lev[0].fix;
+    dst[n] = fix[n] ? src[n] : sweep_value(src, I.b, fix, i, j, NX, NY, n);
+}
+
+// One colour of a red-black Gauss-Seidel sweep, in place.
+__global__ void k_gs64(const Inst *insts, Tab t, int col)
+{
+    GRID_BEGIN(t)
+    if (I.F[F_CONV]) return;
+    NODE_IDX(I.g.NX, I.g.NY)
+    if (!inb || ((i + j) & 1) != col) return;
+    const uint8_t *fix = I.lev[0].fix;
+    if (!fix[n]) I.phi[n] = sweep_value(I.phi, I.b, fix, i, j, NX, NY, n);
+}
+
+void launch_sweeps(const Inst *I, const Tab &t, int jacobi, int sweeps, hipStream_t s)
+{
+    if (!t.n) return;
+    for (int k = 0; k < sweeps; k++) {
+        if (jacobi) {
+            hipLaunchKernelGGL(k_jacobi64, dim3(tab_blocks(t)), gblock(), 0, s, I, t, k & 1);
+        } else {
+            hipLaunchKernelGGL(k_gs64, dim3(tab_blocks(t)), gblock(), 0, s, I, t, 0);
+            hipLaunchKernelGGL(k_gs64, dim3(tab_blocks(t)), gblock(), 0, s, I, t, 1);
+        }
+    }
+}
+
 __global__ void k_phi_update(const Inst *insts, Tab t)
 {
     GRID_BEGIN(t)

@@ -68,6 +68,9 @@ std::string validate(const pic_config *c, const int64_t *cap)
     int NX = c->periodic_x ? c->nx : c->nx + 1;
     if (c->charge_mode && (c->charge_row < 0 || c->charge_row >= NX)) return "charge_row outside the grid";
     if (!(c->rtol > 0)) return "rtol must be positive";
+    if (c->solver < 0 || c->solver > 3) return "solver must be 0 (MG-CG), 1 (CG), 2 (Jacobi) or 3 (Gauss-Seidel)";
+    if (c->solver == 3 && ((c->periodic_x && (c->nx & 1)) || (c->periodic_y && (c->ny & 1))))
+        return "red-black Gauss-Seidel needs an even node count on a periodic axis";
     if (c->max_iter <= 0) return "max_iter must be positive";
     int tx = c->tile_x ? c->tile_x : 16, ty = c->tile_y ? c->tile_y : 16;
     if ((tx & (tx - 1)) || (ty & (ty - 1)) || tx > 256 || ty > 256) return "tile sizes must be powers of two <= 256";
@@ -191,7 +194,7 @@ struct InstHost {
     float *d_e = nullptr, *d_p[2] = {}, *d_q = nullptr;
     float *d_cg_r1 = nullptr, *d_cg_s[2] = {}, *d_cg_w = nullptr;
     float4 *d_E4 = nullptr;
-    double *d_phi_prev = nullptr;
+    double *d_phi_prev = nullptr, *d_phi2 = nullptr;
     unsigned *d_counts[2] = {}, *d_offsets[2] = {}, *d_cursor[2] = {}, *d_boff[2] = {};
     int4 *d_table[2] = {};
     long long *d_info[2] = {};
@@ -252,7 +255,8 @@ struct pic_ctx {
     int pass_chunk[2] = {12, 12};   // inner iterations per pass (first pass, later passes)
     // graphs
     hipStream_t cap_stream = nullptr;
-    std::map<int, hipGraphExec_t> outer_graphs;
+    std::map<int, hipGraphExec_t> outer_graphs;   // CG passes by K; sweep chunks by kSweepKey + count
+    int sweep_solver = 0;          // 2 Jacobi, 3 Gauss-Seidel (every instance), 0 CG
     std::map<int, hipGraphExec_t> chunk_graphs;
     std::map<long long, hipGraphExec_t> step_graphs;
     bool use_graphs = true;
@@ -322,6 +326,7 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
         for (int k = 0; k < 4; k++) cg[k] = w.take<float>(nodes);
     float4 *E4 = w.take<float4>(2 * cells);
     double *phi_prev = w.take<double>(nodes);
+    double *phi2 = cfg->solver == 2 ? w.take<double>(nodes) : nullptr;
     unsigned *counts[2], *offs[2], *curs[2], *boff[2];
     int4 *table[2];
     long long *info[2];
@@ -359,6 +364,7 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     h->d_cg_w = cg[3];
     h->d_E4 = E4;
     h->d_phi_prev = phi_prev;
+    h->d_phi2 = phi2;
     for (int s = 0; s < 2; s++) {
         h->d_counts[s] = counts[s];
         h->d_offsets[s] = offs[s];
@@ -646,8 +652,92 @@ void enqueue_solve_start(pic_ctx *c, int kind, const double *guess, hipStream_t 
     launch_resid64(c->d_inst, c->t_l0, 0, part_of(c), s);
 }
 
+constexpr int kSweepChunk = 64;       // sweeps between float64 residual tests
+constexpr int kSweepKey = 1 << 20;
+
+// `count` sweeps of the paper's iteration, then the float64 residual and its
+// convergence flag (captured once per count).
+pic_status run_sweep_chunk(pic_ctx *c, int count)
+{
+    auto enqueue = [&](hipStream_t s) {
+        launch_sweeps(c->d_inst, c->t_l0, c->sweep_solver == 2 ? 1 : 0, count, s);
+        launch_resid64(c->d_inst, c->t_l0, 1, part_of(c), s);
+    };
+    if (!c->use_graphs) {
+        enqueue(c->stream);
+        HIPCHK(c, hipGetLastError());
+        return PIC_OK;
+    }
+    auto it = c->outer_graphs.find(kSweepKey + count);
+    if (it == c->outer_graphs.end()) {
+        pic_status st = capture_begin(c);
+        if (st != PIC_OK) return st;
+        enqueue(c->cap_stream);
+        hipGraphExec_t ex;
+        st = capture_end(c, &ex);
+        if (st != PIC_OK) return st;
+        it = c->outer_graphs.emplace(kSweepKey + count, ex).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    return PIC_OK;
+}
+
+// The paper's own iterations to rtol: chunks of sweeps, each followed by the
+// float64 residual test, until every instance converged or max_iter sweeps
+// ran (Jacobi chunks are even, so a solve may run one sweep past max_iter).
+// An instance's count is the sweeps run when its test first passed.
+pic_status do_sweep_solve(pic_ctx *c, int kind, const double *guess)
+{
+    enqueue_solve_start(c, kind, guess, c->stream);
+    c->have_prev = (kind == 3);
+    std::vector<double> S;
+    std::vector<int> F;
+    pic_status st = read_flags(c, S, F);
+    if (st != PIC_OK) return st;
+    int max_iter = 0;
+    for (auto &h : c->in) max_iter = std::max(max_iter, (int)h.cfg.max_iter);
+    std::vector<int> done(c->n, -1);
+    int total = 0;
+    auto settled = [&]() {
+        bool all = true, finite = true;
+        for (int k = 0; k < c->n; k++) {
+            if (F[(size_t)k * F_NFLAG + F_CONV]) {
+                if (done[k] < 0) done[k] = total;
+            } else {
+                all = false;
+            }
+            if (!std::isfinite(S[(size_t)k * S_NSCAL + S_RR64])) finite = false;
+        }
+        return all || !finite;
+    };
+    bool stop = settled();
+    while (!stop && total < max_iter) {
+        int count = std::min(kSweepChunk, max_iter - total);
+        if (c->sweep_solver == 2) count += count & 1;
+        if ((st = run_sweep_chunk(c, count)) != PIC_OK) return st;
+        total += count;
+        if ((st = read_flags(c, S, F)) != PIC_OK) return st;
+        stop = settled();
+    }
+    launch_shift_mean(c->d_inst, c->t_per, part_of(c), c->stream);
+    record_solve_info(c, S, F);
+    for (int k = 0; k < c->n; k++) {
+        pic_solve_info &si = c->in[k].last;
+        si.iterations = si.iterations_first = done[k] >= 0 ? done[k] : total;
+        si.outer = 1;
+        if (!si.converged) {
+            char msg[200];
+            snprintf(msg, sizeof msg, "instance %d: %s stopped at relative residual %.3e after %d sweeps", k,
+                     c->sweep_solver == 2 ? "Jacobi" : "Gauss-Seidel", si.relres, si.iterations);
+            return fail(c, PIC_ERR_NOT_CONVERGED, msg);
+        }
+    }
+    return PIC_OK;
+}
+
 pic_status do_solve(pic_ctx *c, int kind, const double *guess)
 {
+    if (c->sweep_solver) return do_sweep_solve(c, kind, guess);
     enqueue_solve_start(c, kind, guess, c->stream);
     c->have_prev = (kind == 3);
     std::vector<double> S;
@@ -839,6 +929,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
     d.phi = buf->phi;
     d.b = buf->b;
     d.phi_prev = h.d_phi_prev;
+    d.phi2 = h.d_phi2;
     d.rho[0] = reinterpret_cast<unsigned long long *>(buf->rho[0]);
     d.rho[1] = reinterpret_cast<unsigned long long *>(buf->rho[1]);
     d.e = h.d_e;
@@ -1069,6 +1160,12 @@ pic_status batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, vo
         pic_status st = init_instance(c, k, &cfgs[k], &bufs[k]);
         if (st != PIC_OK) return st;
     }
+    for (int k = 0; k < n; k++) {
+        const int sk = cfgs[k].solver >= 2 ? cfgs[k].solver : 0;
+        if (k > 0 && sk != c->sweep_solver)
+            return fail(c, PIC_ERR_ARG, "a batch mixes no CG and sweep solvers, nor Jacobi and Gauss-Seidel");
+        c->sweep_solver = sk;
+    }
     build_tabs(c);
     c->step = 0;
     pic_status st = upload_vwindow(c, 0);
@@ -1224,6 +1321,7 @@ pic_status pic_batch_step(pic_ctx *c, int32_t nsteps, int32_t passes, int32_t it
     if (iters_later == 0) iters_later = iters;
     if (nsteps < 0 || passes < 1 || passes > 8 || iters < 1 || iters > 128 || iters_later < 1 || iters_later > 128)
         return fail(c, PIC_ERR_ARG, "nsteps >= 0, passes in 1..8, iters and iters_later in 1..128");
+    if (c->sweep_solver) return fail(c, PIC_ERR_ARG, "pic_batch_step needs the CG solvers (solver 0 or 1)");
     if (!c->have_prev) {
         // the captured schedule extrapolates from two earlier solutions
         pic_status st = pic_step(c, 1);
