@@ -67,8 +67,12 @@ def lib():
         L.or_field.restype = None
         for nm in ("or_push_f32", "or_push_f64"):
             f = getattr(L, nm)
-            f.argtypes = [i, i, i, i, P, i, i, i, d, d, P, P, i64, P, P, P, P, P, P, P]
+            f.argtypes = [i, i, i, i, P, i, i, i, d, d, P, P, i64, P, P, P, P, P, P, P, P]
             f.restype = i64
+        L.or_philox4x32_10.argtypes = [P, P, P]
+        L.or_philox4x32_10.restype = None
+        L.or_recycled_ion.argtypes = [P, C.c_int32, C.c_float, C.c_float, i, P, P, P, P, P]
+        L.or_recycled_ion.restype = None
         for nm in ("or_rewind_f32", "or_rewind_f64"):
             f = getattr(L, nm)
             f.argtypes = [i, i, i, i, d, d, P, P, i64, P, P, P, P, P]
@@ -291,10 +295,46 @@ def _state(p: dict, dt):
             **{k: _c(p[k], dt).copy() for k in ("ox", "oy", "vx", "vy")}}
 
 
-def push(w, s: int, p: dict, Ex, Ey, precision="f32", tally=None, surf=None) -> int:
+class _Recycle(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("k0", C.c_uint32), ("k1", C.c_uint32), ("vth", C.c_double),
+                ("step", C.c_int64)]
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC 2011) of one counter (4 words) and key
+    (2 words), the generator of the recycled ions."""
+    c = np.array(ctr, np.uint32)
+    k = np.array(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def recycled_ion(w, step, old_code, ox0, oy0):
+    """(cell code, ox, oy, vx, vy) of the ion that replaces a lost one
+    (float32 offsets, float64 velocities)."""
+    k0, k1 = w.recycle_key()
+    rc = _Recycle(int(w.recycle_rows), k0, k1, float(w.species[1].vth), int(step))
+    code = C.c_int32()
+    ox, oy = C.c_float(), C.c_float()
+    vx, vy = C.c_double(), C.c_double()
+    lib().or_recycled_ion(C.cast(C.pointer(rc), C.c_void_p), int(old_code), float(ox0), float(oy0), w.ny,
+                          C.cast(C.pointer(code), C.c_void_p), C.cast(C.pointer(ox), C.c_void_p),
+                          C.cast(C.pointer(oy), C.c_void_p), C.cast(C.pointer(vx), C.c_void_p),
+                          C.cast(C.pointer(vy), C.c_void_p))
+    return code.value, ox.value, oy.value, vx.value, vy.value
+
+
+def push(w, s: int, p: dict, Ex, Ey, precision="f32", tally=None, surf=None, step=None) -> int:
     """In-place push of species s.  precision 'f32' needs float32 state,
-    'f64' float64 state.  Returns the number of particles removed."""
+    'f64' float64 state.  Returns the number of particles removed.  With
+    w.recycle_rows > 0 and the step index given, lost ions (species 1) are
+    replaced by recycled ones (Sec. III.A)."""
     sp = w.species[s]
+    rc = None
+    if s == 1 and w.recycle_rows > 0 and step is not None:
+        k0, k1 = w.recycle_key()
+        rc = _Recycle(int(w.recycle_rows), k0, k1, float(sp.vth), int(step))
     f = lib().or_push_f32 if precision == "f32" else lib().or_push_f64
     dt = np.float32 if precision == "f32" else np.float64
     for k in ("ox", "oy", "vx", "vy"):
@@ -305,7 +345,8 @@ def push(w, s: int, p: dict, Ex, Ey, precision="f32", tally=None, surf=None) -> 
     return f(w.nx, w.ny, int(w.periodic_x), int(w.periodic_y), _p(_c(w.cell_cond, np.uint8)),
              int(w.box_i_top), int(w.box_j_lo), int(w.box_j_hi), float(w.dt), float(sp.alpha),
              _p(_c(Ex, np.float64)), _p(_c(Ey, np.float64)), p["cell"].size, _p(p["cell"]),
-             _p(p["ox"]), _p(p["oy"]), _p(p["vx"]), _p(p["vy"]), _p(tally), surf_p)
+             _p(p["ox"]), _p(p["oy"]), _p(p["vx"]), _p(p["vy"]), _p(tally), surf_p,
+             C.cast(C.pointer(rc), C.c_void_p) if rc is not None else None)
 
 
 def rewind(w, s: int, p: dict, Ex, Ey, precision="f32"):
@@ -364,7 +405,7 @@ class Sim:
         Ex, Ey = field(w, self.nc, self.phi)
         for s, q in enumerate(self.p):
             surf = self.surf if (w.charge_mode == 2 and w.species[s].sign > 0) else None
-            push(w, s, q, Ex, Ey, self.prec, self.tally[s], surf)
+            push(w, s, q, Ex, Ey, self.prec, self.tally[s], surf, step=self.step_index)
         self.step_index += 1
 
     def alive(self, s):

@@ -294,6 +294,64 @@ void or_field(int NX, int NY, int px, int py, const uint8_t *node_cond,
  * tally has 9 entries.  T is float (every operation rounded to float32) or
  * double; the state arrays have the same type.
  * ---------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------
+ * Ion recycling (Sec. III.A, III.C): an ion lost at a wall is replaced by a
+ * thermal ion in the bulk plasma, the ionisation of the ambient gas, only in
+ * the bulk rows 0 .. rows-1.  The new ion's cell, offsets and velocity come
+ * from a counter-based generator, Philox4x32-10 (Salmon, Moraes, Dror and
+ * Shaw, SC 2011), keyed by the run's seed and counting on (step, the lost
+ * ion's cell code and offset bits), so they do not depend on the order in
+ * which particles are stored:
+ *   r  = Philox(ctr, key), r' = Philox(ctr, key + (0, 1))
+ *   i  = (r0 >> 8) * rows >> 24,  j = (r1 >> 8) * ny >> 24   (exact integers)
+ *   ox = (r2 >> 8) 2^-24,  oy = (r3 >> 8) 2^-24              (exact floats)
+ *   (vx, vy) = vth sqrt(-2 ln u) (cos 2 pi v, sin 2 pi v) in double,
+ *   u = ((r'0 >> 8) + 1) 2^-24, v = (r'1 >> 8) 2^-24        (Box-Muller)
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t rows;                 /* 0: no recycling */
+    uint32_t k0, k1;
+    double vth;                   /* ion thermal speed per component */
+    int64_t step;                 /* step being pushed */
+} or_recycle;
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static uint32_t f32_bits(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+
+void or_recycled_ion(const or_recycle *rc, int32_t old_code, float ox0, float oy0, int ny, int32_t *code,
+                     float *ox, float *oy, double *vx, double *vy)
+{
+    uint32_t ctr[4] = {(uint32_t)rc->step, (uint32_t)old_code, f32_bits(ox0), f32_bits(oy0)};
+    uint32_t key[2] = {rc->k0, rc->k1}, r[4], q[4];
+    or_philox4x32_10(ctr, key, r);
+    key[1] += 1u;
+    or_philox4x32_10(ctr, key, q);
+    uint32_t i = (uint32_t)(((uint64_t)(r[0] >> 8) * (uint32_t)rc->rows) >> 24);
+    uint32_t j = (uint32_t)(((uint64_t)(r[1] >> 8) * (uint32_t)ny) >> 24);
+    *code = (int32_t)((i << 16) | j);
+    *ox = (float)(r[2] >> 8) * 0x1p-24f;
+    *oy = (float)(r[3] >> 8) * 0x1p-24f;
+    double u = (double)((q[0] >> 8) + 1u) * 0x1p-24, v = (double)(q[1] >> 8) * 0x1p-24;
+    double rad = sqrt(-2.0 * log(u)), ang = 6.283185307179586 * v;
+    *vx = rc->vth * rad * cos(ang);
+    *vy = rc->vth * rad * sin(ang);
+}
+
 #define PUSH_BODY(T, FLOOR)                                                          \
     int NY = py ? ny : ny + 1;                                                       \
     T qdt = (T)(alpha * dt), dtt = (T)dt;                                            \
@@ -360,6 +418,13 @@ void or_field(int NX, int NY, int px, int py, const uint8_t *node_cond,
             lost++;                                                                  \
             if (tally) tally[dead]++;                                                \
             if (surf && dead == 4) surf[cj]++;                                       \
+            if (rc && rc->rows > 0) {                                                \
+                int32_t code; float nox, noy; double nvx, nvy;                       \
+                or_recycled_ion(rc, c, (float)x0, (float)y0, ny, &code, &nox, &noy,  \
+                             &nvx, &nvy);                                            \
+                cell[p] = code; ox[p] = (T)nox; oy[p] = (T)noy;                      \
+                vx[p] = (T)nvx; vy[p] = (T)nvy;                                      \
+            }                                                                        \
             continue;                                                                \
         }                                                                            \
         T nxo = x1 - (T)sx, nyo = y1 - (T)sy;                                        \
@@ -378,7 +443,7 @@ int64_t or_push_f32(int nx, int ny, int px, int py, const uint8_t *cell_cond,
                     int box_i_top, int box_j_lo, int box_j_hi, double dt, double alpha,
                     const double *Ex, const double *Ey, int64_t n, int32_t *cell,
                     float *ox, float *oy, float *vx, float *vy, int64_t *tally,
-                    int64_t *surf)
+                    int64_t *surf, const or_recycle *rc)
 {
     PUSH_BODY(float, floorf)
 }
@@ -387,7 +452,7 @@ int64_t or_push_f64(int nx, int ny, int px, int py, const uint8_t *cell_cond,
                     int box_i_top, int box_j_lo, int box_j_hi, double dt, double alpha,
                     const double *Ex, const double *Ey, int64_t n, int32_t *cell,
                     double *ox, double *oy, double *vx, double *vy, int64_t *tally,
-                    int64_t *surf)
+                    int64_t *surf, const or_recycle *rc)
 {
     PUSH_BODY(double, floor)
 }

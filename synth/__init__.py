@@ -64,7 +64,14 @@ class Workload:
     static_j_lo: int = 0
     static_j_hi: int = -1
     seed: int = 0
+    # ion recycling (Sec. III.A, III.C): a lost ion is replaced by a thermal ion
+    # in the bulk cell rows 0 .. recycle_rows-1 (0: off)
+    recycle_rows: int = 0
     extra: dict = field(default_factory=dict)
+
+    def recycle_key(self) -> tuple:
+        """Key of the recycling generator (two 32-bit words)."""
+        return (int(self.seed) & 0xFFFFFFFF, 0x1610D3F1)
 
     @property
     def NX(self) -> int:
