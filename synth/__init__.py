@@ -172,6 +172,70 @@ def trench(nx: int = 1024, ny: int = 512, width: int = 8, depth: int = 128,
         extra={"width": width, "depth": depth, "electrode_top": top})
 
 
+PAPER_TRENCH_J_LO = {15: 5, 4: 10}
+
+
+def paper_trench(width: int = 15, charged: bool = False, ppc: int = 100,
+                 steps: int = 10000, seed: int = 5) -> Workload:
+    """The trench runs of Sec. III.C-D at the paper's parameters: the 60-row
+    periodic bulk of Sec. III.B plus a 20-row trench cut through the RF
+    electrode (80 x 30 cells, y periodic), m_i/m_e = 3672, T_i = T_e, 100
+    particles per cell, dt = 0.1, RF amplitude 5 at omega 0.01 on the trench
+    side, ions lost at any wall recycled into the bulk rows 0..59.  Width 15
+    puts the trench at 5 <= j < 20 (Fig. 5), width 4 at 10 <= j < 14
+    (Fig. 6).  ``charged`` adds the static extra ion density 5 on node row 79
+    over 5 <= j <= 20 (Sec. III.D, Fig. 7)."""
+    nx, ny, depth = 80, 30, 20
+    top = nx - depth
+    j_lo = PAPER_TRENCH_J_LO.get(width, (ny - width) // 2)
+    j_hi = j_lo + width
+    a, o = _amps(c1=(0.0, 0.0), c2=(5.0, 0.01))
+    w = Workload(
+        name=f"paper_trench_w{width}" + ("_charged" if charged else ""),
+        nx=nx, ny=ny, periodic_x=False, periodic_y=True, dt=0.1, steps=steps,
+        cell_cond=trench_cells(nx, ny, top, j_lo, j_hi), edge_cond=(GROUND, RF, 0, 0),
+        v_amp=a, v_omega=o, species=_species(3672.0, 1.0, ppc), weight=1.0 / ppc,
+        rtol=1e-8, box_i_top=top, box_j_lo=j_lo, box_j_hi=j_hi, seed=seed,
+        recycle_rows=top, extra={"width": width, "depth": depth, "electrode_top": top})
+    if charged:
+        w.charge_mode = 1
+        w.charge_row = nx - 1
+        w.static_density = 5.0
+        w.static_j_lo, w.static_j_hi = j_lo, j_hi
+    return w
+
+
+def paper_slab(ppc: int = 100, steps: int = 5000, seed: int = 6, ny: int = 30,
+               recycle: bool = True) -> Workload:
+    """The y-periodic RF slab of Sec. III.B (Fig. 2-3): 60 x ny cells with no
+    trench, grounded plate at x = 0, RF plate at x = 60 with amplitude 5 at
+    omega 0.01, m_i/m_e = 3672, T_i = T_e, dt = 0.1, lost ions recycled over
+    the whole slab.  Its dynamics depend on x alone (the 1D equivalence)."""
+    nx = 60
+    a, o = _amps(c1=(0.0, 0.0), c2=(5.0, 0.01))
+    return Workload(
+        name=f"paper_slab60x{ny}", nx=nx, ny=ny, periodic_x=False, periodic_y=True, dt=0.1,
+        steps=steps, cell_cond=np.zeros((nx, ny), np.uint8), edge_cond=(GROUND, RF, 0, 0),
+        v_amp=a, v_omega=o, species=_species(3672.0, 1.0, ppc), weight=1.0 / ppc,
+        rtol=1e-8, box_i_top=nx, seed=seed, recycle_rows=nx if recycle else 0)
+
+
+def replicate_columns(w: Workload, x: np.ndarray, vx: np.ndarray, oy: float = 0.5) -> dict:
+    """A 2D particle load that repeats one 1D load (positions 0 <= x < nx,
+    velocities vx) in every column j, at offset ``oy`` and with v_y = 0: its
+    charge, potential and x dynamics do not depend on y."""
+    i = np.floor(x).astype(np.int64)
+    ox = (x - i).astype(np.float32)
+    n, ny = x.size, w.ny
+    j = np.repeat(np.arange(ny, dtype=np.int64)[None, :], n, axis=0).ravel()
+    ii = np.repeat(i, ny)
+    return {
+        "cell": ((ii << CODE_SHIFT) | j).astype(np.int32),
+        "ox": np.repeat(ox, ny), "oy": np.full(n * ny, oy, np.float32),
+        "vx": np.repeat(vx.astype(np.float32), ny), "vy": np.zeros(n * ny, np.float32),
+    }
+
+
 SWEEP_WIDTHS = (1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 32, 40, 48, 56, 64, 96)
 
 
