@@ -39,6 +39,8 @@ def workload(name):
         return synth.periodic_square()
     if name.startswith("trench_small"):
         return synth.trench(nx=256, ny=128, width=8, depth=32, ppc=64)
+    if name in synth.PRESETS:
+        return synth.PRESETS[name]()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -259,6 +261,77 @@ def run_solvers(args):
                                 "Gauss-Seidel)", "n_gpus": 1, "data": "synthetic", "results": rows}), flush=True)
 
 
+PAPER_TRENCH_COUNTS = {   # Sec. III.C-D: ions reaching the bottom / the two sidewalls
+    "paper_trench_w15": (2137, 4920),
+    "paper_trench_w4": (831, 1558),
+    "paper_trench_w15_charged": (1094, 3820),
+}
+
+
+def run_trench_study(args):
+    """The trench runs of Sec. III.C-D at the paper's parameters (80 x 30
+    cells, 100 particles per cell, dt = 0.1 to t = 1000, ions recycled into
+    the bulk): ions reaching the trench bottom (class 4, +x inside the trench
+    box) and the two sidewalls (classes 6 and 7) over 600 <= t <= 1000
+    (700 <= t <= 1000 with the charged bottom, as the paper counts), their
+    ratio, the same with only the sidewall hits at least 5 cells below the
+    trench mouth (the paper draws its sidewalls from x = 65 to 80), the
+    cumulative counts every 50 time units, and the mean impact angle of the
+    bottom and sidewall hits."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1610_03918_amd import Pic
+    rows = []
+    for width, charged, t_from in ((15, False, 600), (4, False, 600), (15, True, 700)):
+        w = synth.paper_trench(width, charged, seed=args.study_seed)
+        pic = Pic(w, synth.load(w), hitlog_capacity=1 << 21, hitlog_species_mask=2)
+        pic.start()
+        k_from = int(round(t_from / w.dt))
+        every = int(round(50 / w.dt))
+        curve = []
+        base = None
+        t0 = time.perf_counter()
+        for k in range(0, w.steps, every):
+            pic.pic_step(every)
+            tal = pic.pic_diagnostics()["tally"][1]
+            curve.append([round((k + every) * w.dt, 3), tal[4], tal[6] + tal[7]])
+            if k + every == k_from:
+                base = (tal[4], tal[6] + tal[7])
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        d = pic.pic_diagnostics()
+        tal = d["tally"][1]
+        nb, ns = tal[4] - base[0], tal[6] + tal[7] - base[1]
+        hits = pic.pic_read_hits()
+        h = hits[(hits["step"] >= k_from) & ((hits["species_class"] >> 8) == 1)]
+        cls = h["species_class"] & 0xFF
+        ang = np.degrees(np.arctan2(np.abs(h["vy"]), np.abs(h["vx"])))
+        pic.close()
+        assert d["hits_logged"] <= 1 << 21, "hit log wrapped"
+        side = (cls == 6) | (cls == 7)
+        deep = side & ((h["cell"] >> 16) >= w.extra["electrode_top"] + 5)
+        pb, ps = PAPER_TRENCH_COUNTS[w.name]
+        row = {"workload": w.name, "t_from": t_from, "t_to": w.steps * w.dt,
+               "n_bottom": int(nb), "n_sidewalls": int(ns), "ratio": ns / max(nb, 1),
+               "paper_n_bottom": pb, "paper_n_sidewalls": ps, "paper_ratio": round(ps / pb, 2),
+               "n_sidewalls_below_mouth_5": int(deep.sum()),
+               "ratio_below_mouth_5": int(deep.sum()) / max(int((cls == 4).sum()), 1),
+               "hits_logged_in_window": int(h.size), "hits_total": int(d["hits_logged"]),
+               "mean_angle_bottom_deg": float(ang[cls == 4].mean()) if np.any(cls == 4) else None,
+               "mean_angle_sidewall_deg": float(ang[side].mean()) if np.any(side) else None,
+               "electrons_alive": d["alive"][0], "ions_alive": d["alive"][1],
+               "ms_per_step": 1e3 * secs / w.steps, "cumulative_t_bottom_side": curve}
+        rows.append(row)
+        log(f"{w.name:26s} bottom {nb:6d} sidewalls {ns:6d} ratio {row['ratio']:.2f} "
+            f"(x >= {w.extra['electrode_top'] + 5}: {int(deep.sum())}, {row['ratio_below_mouth_5']:.2f}) "
+            f"(paper {pb}/{ps} = {ps / pb:.2f}) {row['ms_per_step']:.3f} ms/step")
+    print(json.dumps({"metric": "ions reaching the trench bottom and sidewalls (Sec. III.C-D)",
+                      "n_gpus": 1, "data": "synthetic", "seed": args.study_seed, "results": rows}),
+          flush=True)
+
+
 def run_sweep(args):
     """The 16-width trench sweep advanced as one batch with captured graphs."""
     import torch
@@ -336,6 +409,9 @@ def main():
                     help="only time the learned start's network (1024 x 512)")
     ap.add_argument("--solvers", action="store_true",
                     help="only compare the solvers (MG-CG, CG, Jacobi, Gauss-Seidel) from a cold start")
+    ap.add_argument("--trench-study", action="store_true",
+                    help="the paper's trench runs: bottom and sidewall ion counts")
+    ap.add_argument("--study-seed", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sort", default="8,64")
@@ -356,7 +432,7 @@ def main():
     ap.add_argument("--learn-evals", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "multi-GPU runs are not implemented: this benchmark measures one GPU",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calibration:
@@ -367,6 +443,8 @@ def main():
         return run_sweep(args)
     if args.solvers:
         return run_solvers(args)
+    if args.trench_study:
+        return run_trench_study(args)
 
     import numpy as np
     import torch

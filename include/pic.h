@@ -94,6 +94,15 @@ typedef struct {
     int64_t hitlog_capacity;     /* ring of wall-hit records in the workspace (0 = none) */
     int32_t hitlog_species_mask; /* bit s logs species s */
     int32_t warm_start;          /* start of pic_step's solves: 0 previous phi, 1 linear extrapolation */
+    /* ion recycling (Sec. III.A, III.C): an ion removed at a wall or conductor
+     * (classes 0..7) is replaced in the same slot, in the same push, by a
+     * thermal ion in a cell of the bulk rows 0 .. recycle_rows-1 (which must
+     * hold no solid cell): cell, offsets and Gaussian velocity from
+     * Philox4x32-10 with key recycle_key, counter (step, lost ion's cell code,
+     * bits of its offsets).  0 = off. */
+    int32_t recycle_rows;
+    uint32_t recycle_key[2];
+    double recycle_vth;          /* Gaussian sigma of each velocity component of a new ion */
 } pic_config;
 
 typedef struct {
@@ -124,7 +133,7 @@ typedef struct {
 typedef struct {
     int64_t step;                /* completed pushes */
     double t;                    /* step * dt */
-    int64_t alive[2];            /* particles per species */
+    int64_t alive[2];            /* particles per species: loaded minus removals not recycled */
     int64_t loaded[2];
     int64_t charge[2];           /* sum of rho over all nodes (2^-32 particle units / 2^32) */
     int64_t tally[2][PIC_NCLASS];/* removals: class = direction (0 +x, 1 -x, 2 +y, 3 -y)

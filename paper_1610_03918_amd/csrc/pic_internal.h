@@ -140,6 +140,9 @@ struct PushArgs {
     HitLog log;
     const long long *step;         // device step counter (hit records)
     unsigned long long *fallbacks;
+    int recycle_rows;              // > 0: lost ions of this species are recycled into rows 0 .. recycle_rows-1
+    unsigned recycle_key[2];
+    double recycle_vth;
 };
 
 struct BinArgs {

@@ -1740,6 +1740,9 @@ struct PK {
     // (the block's deposit window and a one-cell frame; CW = 0: none)
     const uint8_t *scc;
     int c0i, c0j, CW, CH;
+    int recycle_rows;
+    unsigned rk0, rk1;
+    double rvth;
 };
 
 __device__ __forceinline__ PK resolve(const PushArgs &a)
@@ -1770,6 +1773,10 @@ __device__ __forceinline__ PK resolve(const PushArgs &a)
     k.box_j_lo = a.box_j_lo;
     k.box_j_hi = a.box_j_hi;
     k.species = a.species;
+    k.recycle_rows = a.recycle_rows;
+    k.rk0 = a.recycle_key[0];
+    k.rk1 = a.recycle_key[1];
+    k.rvth = a.recycle_vth;
     k.surf = to_global(a.surf);
     k.iad = to_global(a.iad);
     k.log = a.log;
@@ -1857,6 +1864,57 @@ __device__ __forceinline__ bool push_core(const PK &a, float x0, float y0, float
     if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
     if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
     return true;
+}
+
+// ---- ion recycling (Sec. III.A, III.C) --------------------------------------
+// A lost ion is replaced by a thermal ion in the bulk rows 0 .. rows-1, the
+// ionisation of the ambient gas.  Counter-based generator Philox4x32-10
+// (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of two 32 x 32-bit
+// products (multipliers 0xD2511F53, 0xCD9E8D57), the key bumped by the Weyl
+// constants 0x9E3779B9, 0xBB67AE85 between rounds.  Counter (step, lost ion's
+// cell code, bits of its offsets), keys (k0, k1) and (k0, k1 + 1):
+//   cell (r0 >> 8) * rows >> 24, (r1 >> 8) * ny >> 24; offsets (r2 >> 8), (r3 >> 8) * 2^-24;
+//   velocity vth sqrt(-2 ln u) (cos, sin)(2 pi v), u = ((q0 >> 8) + 1) 2^-24,
+//   v = (q1 >> 8) 2^-24, in double, rounded to float.
+struct Philox4 {
+    unsigned x, y, z, w;
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(unsigned c0, unsigned c1, unsigned c2, unsigned c3, unsigned k0,
+                                                 unsigned k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const unsigned lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const unsigned lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const unsigned n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return Philox4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ void recycled_ion(const PK &a, long long step, int old_code, float x0, float y0,
+                                             int &ci, int &cj, float &ox, float &oy, float &vx, float &vy)
+{
+    const unsigned c0 = (unsigned)step, c1 = (unsigned)old_code;
+    const unsigned c2 = __float_as_uint(x0), c3 = __float_as_uint(y0);
+    const Philox4 r = philox4x32_10(c0, c1, c2, c3, a.rk0, a.rk1);
+    const Philox4 q = philox4x32_10(c0, c1, c2, c3, a.rk0, a.rk1 + 1u);
+    ci = (int)(((unsigned long long)(r.x >> 8) * (unsigned)a.recycle_rows) >> 24);
+    cj = (int)(((unsigned long long)(r.y >> 8) * (unsigned)a.g.ny) >> 24);
+    ox = (float)(r.z >> 8) * 0x1p-24f;
+    oy = (float)(r.w >> 8) * 0x1p-24f;
+    const double u = (double)((q.x >> 8) + 1u) * 0x1p-24, v = (double)(q.y >> 8) * 0x1p-24;
+    const double rad = sqrt(-2.0 * log(u)), ang = 6.283185307179586 * v;
+    vx = (float)(a.rvth * rad * cos(ang));
+    vy = (float)(a.rvth * rad * sin(ang));
 }
 
 // push_core plus the particle's stores (velocity always; offsets if it
@@ -2135,8 +2193,20 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                         uxv[k] = ux;
                         uyv[k] = uy;
                         if (!alive) {
-                            a.cell[v + k] = -1 - dead;
                             record_hit(a, tl, dead, ei, ej, ux, uy);
+                            if (a.recycle_rows && dead < 8) {
+                                // the slot takes the recycled ion (stored with the vector below)
+                                float nox, noy, nvx, nvy;
+                                recycled_ion(a, *a.step, c, xv[k], yv[k], ci, cj, nox, noy, nvx, nvy);
+                                a.cell[v + k] = (int)(((unsigned)ci << 16) | (unsigned)cj);
+                                xv[k] = nox;
+                                yv[k] = noy;
+                                uxv[k] = nvx;
+                                uyv[k] = nvy;
+                                alive = true;
+                            } else {
+                                a.cell[v + k] = -1 - dead;
+                            }
                         } else {
                             const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
                             if (nc != c) a.cell[v + k] = nc;
@@ -2220,7 +2290,19 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                     float vnx, vny;
                     alive = push_particle(a, p, c, x0, y0, vxu[u], vyu[u], eau[u], ebu[u], ci, cj,
                                           dead, ei, ej, vnx, vny);
-                    if (!alive) record_hit(a, tl, dead, ei, ej, vnx, vny);
+                    if (!alive) {
+                        record_hit(a, tl, dead, ei, ej, vnx, vny);
+                        if (a.recycle_rows && dead < 8) {
+                            float nvx, nvy;
+                            recycled_ion(a, *a.step, c, x0, y0, ci, cj, x0, y0, nvx, nvy);
+                            a.cell[p] = (int)(((unsigned)ci << 16) | (unsigned)cj);
+                            a.ox[p] = x0;
+                            a.oy[p] = y0;
+                            a.vx[p] = nvx;
+                            a.vy[p] = nvy;
+                            alive = true;
+                        }
+                    }
                 }
             }
             deposit_lane<MERGE>(a, mA, mB, lane, alive, ci, cj, x0, y0, i0, j0, WX, WY, nfb);

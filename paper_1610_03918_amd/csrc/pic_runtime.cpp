@@ -87,6 +87,11 @@ std::string validate(const pic_config *c, const int64_t *cap)
         return "capacity out of range";
     if (c->hitlog_capacity < 0) return "hitlog_capacity must be >= 0";
     if (c->warm_start < 0 || c->warm_start > 1) return "warm_start must be 0 or 1";
+    if (c->recycle_rows < 0 || c->recycle_rows > c->nx) return "recycle_rows must be in 0 .. nx";
+    if (c->recycle_rows > 0 && !(c->recycle_vth >= 0)) return "recycle_vth must be >= 0";
+    if (c->cell_cond)
+        for (size_t q = 0; q < (size_t)c->recycle_rows * c->ny; q++)
+            if (c->cell_cond[q]) return "the recycling rows must hold no solid cell";
     return "";
 }
 
@@ -1016,6 +1021,10 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
         a.tally = h.d_tally + sp * kNClass;
         a.surf = (h.cfg.charge_mode == 2 && sp == 1) ? h.d_surf : nullptr;
         a.iad = (sp == 1 && h.cfg.box_i_top < h.cfg.nx) ? h.d_iad : nullptr;
+        a.recycle_rows = sp == 1 ? h.cfg.recycle_rows : 0;
+        a.recycle_key[0] = h.cfg.recycle_key[0];
+        a.recycle_key[1] = h.cfg.recycle_key[1];
+        a.recycle_vth = h.cfg.recycle_vth;
         a.log.rec = h.cfg.hitlog_capacity > 0 ? h.d_hits : nullptr;
         a.log.count = h.d_misc + 1;
         a.log.capacity = std::max<int64_t>(h.cfg.hitlog_capacity, 1);
@@ -1428,9 +1437,11 @@ pic_status pic_batch_diagnostics(pic_ctx *c, int32_t i, pic_diag *out)
     out->t = c->step * h.cfg.dt;
     for (int sp = 0; sp < 2; sp++) {
         long long lost = 0;
+        // recycled ions (classes 0..7 of species 1) come back in the same push
+        const bool recycled = sp == 1 && h.cfg.recycle_rows > 0;
         for (int k = 0; k < kNClass; k++) {
             out->tally[sp][k] = (int64_t)tally[sp * kNClass + k];
-            lost += (long long)tally[sp * kNClass + k];
+            if (!recycled || k == kNClass - 1) lost += (long long)tally[sp * kNClass + k];
         }
         out->loaded[sp] = h.loaded[sp];
         out->alive[sp] = h.loaded[sp] - lost;

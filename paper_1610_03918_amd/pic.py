@@ -37,7 +37,8 @@ class pic_config(C.Structure):
         ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("halo", C.c_int32), ("chunk", C.c_int32),
         ("push_unroll", C.c_int32), ("push_merge", C.c_int32),
         ("hitlog_capacity", C.c_int64), ("hitlog_species_mask", C.c_int32),
-        ("warm_start", C.c_int32),
+        ("warm_start", C.c_int32), ("recycle_rows", C.c_int32), ("recycle_key", C.c_uint32 * 2),
+        ("recycle_vth", C.c_double),
     ]
 
 
@@ -171,6 +172,11 @@ def make_config(w, *, solver=0, max_iter=2000, sort_interval=(8, 64), tile=(16, 
     cfg.hitlog_capacity = hitlog_capacity
     cfg.hitlog_species_mask = hitlog_species_mask
     cfg.warm_start = warm_start
+    cfg.recycle_rows = int(getattr(w, "recycle_rows", 0))
+    if cfg.recycle_rows:
+        k0, k1 = w.recycle_key()
+        cfg.recycle_key[0], cfg.recycle_key[1] = k0, k1
+        cfg.recycle_vth = float(w.species[1].vth)
     return cfg, cc
 
 

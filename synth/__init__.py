@@ -260,6 +260,10 @@ PRESETS = {
     "periodic64": lambda: periodic_square(),
     "bounded256": lambda: bounded_square(),
     "trench1024x512": lambda: trench(),
+    "paper_trench_w15": lambda: paper_trench(15),
+    "paper_trench_w4": lambda: paper_trench(4),
+    "paper_trench_w15_charged": lambda: paper_trench(15, charged=True),
+    "paper_slab60x30": lambda: paper_slab(),
 }
 
 

@@ -1,0 +1,121 @@
+"""GPU parity of ion recycling (Sec. III.A, III.C: an ion lost to a wall is
+replaced by a thermal ion drawn in the bulk plasma rows).
+
+Bars: on identical particle states and an identical potential, one push
+gives bit-identical tallies, surface counts, cells and offsets for every
+particle, recycled ions included (their cell and offsets come from integer
+Philox words); the velocities of recycled ions come from a float64
+Box-Muller transform whose cos/sin/log may round differently on the two
+sides by an ulp before the cast to float32, so they are held to 1e-6
+relative of vth; every other velocity is bit-identical.  Over a run the
+number of ions stays constant."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import canonical
+
+pytestmark = pytest.mark.gpu
+
+
+def _workload():
+    w = synth.workload_for_tests("trench")
+    w.recycle_rows = w.box_i_top
+    return w
+
+
+def _make(w, parts):
+    from paper_1610_03918_amd import Pic
+    return Pic(w, parts, rtol=1e-12, sort_interval=(0, 0))
+
+
+def test_one_push_with_recycling_matches_oracle():
+    w = _workload()
+    parts = synth.load(w)
+    # thermal ions cross a tenth of a cell in a thousand steps; give them the
+    # electrons' velocities so that hundreds reach a wall in this one push
+    for f in ("vx", "vy"):
+        parts[1][f] = parts[0][f].copy()
+    pic = _make(w, parts)
+    nc = oracle.node_cond(w)
+    phi = synth.random_potential(w, 33, scale=4.0)
+    phi[nc != 0] = w.voltages(0.0)[nc[nc != 0]]
+    pic.phi.copy_(pic.torch.from_numpy(phi))
+    pic.pic_push()
+    Ex, Ey = oracle.field(w, nc, phi)
+    ref = [{k: v.copy() for k, v in parts[s].items()} for s in range(2)]
+    tally = np.zeros((2, 9), np.int64)
+    surf = np.zeros(w.ny, np.int64)
+    for s in range(2):
+        oracle.push(w, s, ref[s], Ex, Ey, "f32", tally[s],
+                    surf if (w.charge_mode == 2 and s == 1) else None, step=0)
+    d = pic.pic_diagnostics()
+    assert np.array_equal(np.array(d["tally"]), tally)
+    assert d["surf_hits"] == int(surf.sum())
+    assert tally[1, :8].sum() > 0, "no ion was lost, so none was recycled"
+    # electrons are not recycled: bit-identical as in the plain push
+    assert np.array_equal(canonical(pic.particles_numpy(0)), canonical(ref[0]))
+    # ions: every lost ion of classes 0..7 comes back, so the count holds
+    post = pic.particles_numpy(1)
+    n_alive = int((parts[1]["cell"] >= 0).sum())
+    assert int((post["cell"] >= 0).sum()) == int((ref[1]["cell"] >= 0).sum())
+    assert int((ref[1]["cell"] >= 0).sum()) == n_alive - int(tally[1, 8])
+    A, B = canonical(post), canonical(ref[1])
+    assert np.array_equal(A[:, :3], B[:, :3]), "cells or offsets differ"
+    va = A[:, 3:].view(np.float32).astype(np.float64)
+    vb = B[:, 3:].view(np.float32).astype(np.float64)
+    vth = w.species[1].vth
+    assert np.all(np.abs(va - vb) <= 1e-6 * np.maximum(np.abs(vb), vth))
+    # the rows that differ at all are recycled ions: they sit in the bulk rows
+    diff = np.any(A[:, 3:] != B[:, 3:], axis=1)
+    assert np.all((A[diff, 0] >> 16) < w.recycle_rows)
+    # the deposit of the new state is exact (it only reads cells and offsets)
+    assert np.array_equal(pic.rho(1).cpu().numpy(), oracle.deposit(w, ref[1]))
+    pic.close()
+
+
+def test_run_keeps_ion_count():
+    w = _workload()
+    parts = synth.load(w)
+    n0 = int((parts[1]["cell"] >= 0).sum())
+    pic = _make(w, parts)
+    pic.pic_step(20)
+    d = pic.pic_diagnostics()
+    post = pic.particles_numpy(1)
+    lost_for_good = d["tally"][1][8]
+    assert sum(d["tally"][1][:8]) > 0
+    assert int((post["cell"] >= 0).sum()) == n0 - lost_for_good
+    assert d["alive"][1] == n0 - lost_for_good
+    live = post["cell"] >= 0
+    assert np.all((post["ox"][live] >= 0) & (post["ox"][live] < 1))
+    assert np.all((post["oy"][live] >= 0) & (post["oy"][live] < 1))
+    pic.close()
+
+
+def test_paper_trench_hit_counts_match_oracle():
+    """The wide trench at the paper's parameters (Sec. III.C: 80 x 30 cells,
+    100 particles per cell, ions recycled) run 1500 steps on both sides.  The
+    trajectories part ways within a few hundred steps (float32 rounding of
+    the field, a CG against a direct solve), so the comparison is of the hit
+    counts per class, each a sum of many nearly independent events: within
+    five Poisson standard deviations (runs that differ only in their seed
+    differ by about one)."""
+    w = synth.paper_trench(15, seed=5)
+    parts = synth.load(w)
+    steps = 1500
+    pic = _make(w, parts)
+    pic.start()
+    pic.pic_step(steps)
+    g = np.array(pic.pic_diagnostics()["tally"], np.int64)
+    pic.close()
+    sim = oracle.Sim(w, parts)
+    sim.start()
+    for _ in range(steps):
+        sim.step()
+    o = sim.tally
+    assert g[1, 4] > 1000 and g[1, 6] + g[1, 7] > 1000
+    for s in range(2):
+        for k in range(9):
+            a, b = int(g[s, k]), int(o[s, k])
+            assert abs(a - b) <= 5.0 * np.sqrt(a + b) + 5, (s, k, a, b)
