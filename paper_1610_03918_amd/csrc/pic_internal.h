@@ -78,6 +78,8 @@ struct CoarseArgs {
     int px, py;
     int sweeps;                    // red-black pairs on the coarsest level
     int lds_bytes;
+    const float *ainv;             // inverse of the coarsest level's operator (n x n), or null
+    int dense_n;                   // its node count n when the coarsest level is solved exactly, else 0
 };
 
 // Device descriptor of one instance.

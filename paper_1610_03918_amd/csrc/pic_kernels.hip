@@ -1539,6 +1539,26 @@ __device__ __forceinline__ void wave_sync()
 
 constexpr int kCoarseWaveNodes = 640;   // LDS levels at most this size are run by one wavefront
 
+// Exact solve of the coarsest level, u = A^-1 g, with the inverse the host
+// factorised (float32, n x n, symmetric, zero rows and columns at fixed
+// nodes): thread r forms row r; lanes read consecutive entries of a column.
+__device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__ ainv, int n, int first, int step)
+{
+    for (int r = first; r < n; r += step) {
+        const float *col = ainv + r;
+        float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f;
+        int c = 0;
+        for (; c + 4 <= n; c += 4) {
+            acc0 += col[(size_t)c * n] * L.g[c];
+            acc1 += col[(size_t)(c + 1) * n] * L.g[c + 1];
+            acc2 += col[(size_t)(c + 2) * n] * L.g[c + 2];
+            acc3 += col[(size_t)(c + 3) * n] * L.g[c + 3];
+        }
+        for (; c < n; c++) acc0 += col[(size_t)c * n] * L.g[c];
+        L.u[r] = (acc0 + acc1) + (acc2 + acc3);
+    }
+}
+
 // The levels from lg on: one 1024-thread work-group per instance, every level
 // in LDS.  Per level on the way down a black half-sweep, the red residuals,
 // their restriction to the next level with its red-from-zero start; on the
@@ -1616,13 +1636,22 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
                 c_restrict(L, sr, C, px, py, tid, 64);
                 wave_sync();
             }
-            // coarsest: red-black sweeps (the first black completes the pre-smoothing)
-            const CLev L = lev(nlev - 1);
-            for (int sw = 0; sw < a.sweeps; sw++) {
-                c_sweep(L, 1, tid, 64);
-                wave_sync();
-                c_sweep(L, 0, tid, 64);
-                wave_sync();
+        }
+        if (a.dense_n) {
+            __syncthreads();
+            c_dense(lev(nlev - 1), a.ainv, a.dense_n, tid, nt);
+            __syncthreads();
+        }
+        if (tid < 64) {
+            if (!a.dense_n) {
+                // coarsest: red-black sweeps (the first black completes the pre-smoothing)
+                const CLev L = lev(nlev - 1);
+                for (int sw = 0; sw < a.sweeps; sw++) {
+                    c_sweep(L, 1, tid, 64);
+                    wave_sync();
+                    c_sweep(L, 0, tid, 64);
+                    wave_sync();
+                }
             }
             for (int l = nlev - 2; l >= ls; l--) {
                 const CLev F = lev(l), C = lev(l + 1);
@@ -1634,6 +1663,9 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
                 wave_sync();
             }
         }
+        __syncthreads();
+    } else if (a.dense_n) {
+        c_dense(lev(nlev - 1), a.ainv, a.dense_n, tid, nt);
         __syncthreads();
     } else {
         const CLev L = lev(nlev - 1);

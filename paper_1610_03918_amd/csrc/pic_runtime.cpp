@@ -31,6 +31,7 @@ struct Layout {
     int NXl[kMaxLev], NYl[kMaxLev];
     int lg = 0;                             // first level handled by the coarse kernel
     bool mg = false;
+    int dense_n = 0;                        // nodes of a coarsest level solved with its inverse (0: sweeps)
     int TX, TY, lx, ly, tiles_x, tiles_y, ntiles, H, chunk;
     int unroll, merge;                      // push kernel variant
     long long max_blocks[2];
@@ -43,6 +44,9 @@ int ilog2(int v)
     while ((1 << l) < v) l++;
     return l;
 }
+
+constexpr int kDenseMaxNodes = 800;    // largest coarsest level given an explicit inverse
+constexpr int kDenseMinDim = 8;        // below this the coarsest level's sweeps are cheap
 
 bool coarsenable(int n, int periodic)
 {
@@ -160,6 +164,13 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
     L.lg = 1;
     while (L.lg < L.nlev && (L.NXl[L.lg] * L.NYl[L.lg] > kCoarseMaxNodes || lds_from(L.lg) > kCoarseMaxLds)) L.lg++;
     L.mg = (c->solver == 0) && L.nlev >= 2 && L.lg < L.nlev;
+    // a coarsest level that red-black sweeps would need many passes over (a
+    // periodic axis with an odd factor stops the coarsening early) is solved
+    // exactly with its inverse instead
+    if (L.mg) {
+        const int last = L.nlev - 1, n = L.NXl[last] * L.NYl[last];
+        if (n <= kDenseMaxNodes && std::max(L.NXl[last], L.NYl[last]) > kDenseMinDim) L.dense_n = n;
+    }
     L.TX = c->tile_x ? c->tile_x : 16;
     L.TY = c->tile_y ? c->tile_y : 16;
     L.lx = ilog2(L.TX);
@@ -207,6 +218,9 @@ struct InstHost {
     double *d_diag = nullptr;
     int32_t *d_hits = nullptr;
     std::vector<std::vector<uint8_t>> fixh;  // level masks (host copies kept until uploaded)
+    std::vector<float> ainvh;               // coarsest-level inverse (host copy kept until uploaded)
+    float *d_ainv = nullptr;
+    bool dense = false;                     // the coarsest level is solved with d_ainv
     Inst dev{};
     pic_solve_info last{};
 };
@@ -308,6 +322,70 @@ void tab_add(Tab &t, int id, int blocks)
     t.boff[k + 1] = t.boff[k] + blocks;
 }
 
+// Inverse of the coarsest level's operator, 4 u_k minus the free neighbours'
+// u (periodic wrap as the kernels take it) on free nodes, u = 0 on fixed
+// ones: float64 Cholesky factor, then one column of the inverse per free
+// node, stored as float32 n x n with zero rows and columns at fixed nodes.
+// False when the operator is singular or nearly so (no fixed node).
+bool coarse_inverse(const std::vector<uint8_t> &fix, int NX, int NY, std::vector<float> &out)
+{
+    const int n = NX * NY;
+    std::vector<int> idx(n, -1), node;
+    for (int k = 0; k < n; k++)
+        if (!fix[k]) {
+            idx[k] = (int)node.size();
+            node.push_back(k);
+        }
+    const int m = (int)node.size();
+    if (m == 0) return false;
+    std::vector<double> A((size_t)m * m, 0.0);
+    for (int a = 0; a < m; a++) {
+        const int i = node[a] / NY, j = node[a] % NY;
+        A[(size_t)a * m + a] = 4.0;
+        const int nb[4] = {((i + NX - 1) % NX) * NY + j, ((i + 1) % NX) * NY + j, i * NY + (j + NY - 1) % NY,
+                           i * NY + (j + 1) % NY};
+        for (int q = 0; q < 4; q++)
+            if (idx[nb[q]] >= 0) A[(size_t)a * m + idx[nb[q]]] -= 1.0;
+    }
+    for (int p = 0; p < m; p++) {                 // lower factor in place: A = L L^T
+        double *rp = &A[(size_t)p * m];
+        double d = rp[p];
+        for (int q = 0; q < p; q++) d -= rp[q] * rp[q];
+        if (!(d > 1e-8)) return false;              // singular to rounding (no fixed node)
+        d = std::sqrt(d);
+        rp[p] = d;
+        for (int r = p + 1; r < m; r++) {
+            double *rr = &A[(size_t)r * m];
+            double v = rr[p];
+            for (int q = 0; q < p; q++) v -= rr[q] * rp[q];
+            rr[p] = v / d;
+        }
+    }
+    std::vector<double> LT((size_t)m * m);        // L^T, for the backward substitutions
+    for (int r = 0; r < m; r++)
+        for (int q = 0; q <= r; q++) LT[(size_t)q * m + r] = A[(size_t)r * m + q];
+    out.assign((size_t)n * n, 0.0f);
+    std::vector<double> x(m);
+    for (int cidx = 0; cidx < m; cidx++) {
+        std::fill(x.begin(), x.end(), 0.0);
+        x[cidx] = 1.0;
+        for (int r = cidx; r < m; r++) {           // L y = e_c (y is 0 above c)
+            const double *rr = &A[(size_t)r * m];
+            double v = x[r];
+            for (int q = cidx; q < r; q++) v -= rr[q] * x[q];
+            x[r] = v / rr[r];
+        }
+        for (int r = m - 1; r >= 0; r--) {         // L^T x = y
+            const double *tr = &LT[(size_t)r * m];
+            double v = x[r];
+            for (int q = r + 1; q < m; q++) v -= tr[q] * x[q];
+            x[r] = v / tr[r];
+        }
+        for (int r = 0; r < m; r++) out[(size_t)node[r] * n + node[cidx]] = (float)x[r];
+    }
+    return true;
+}
+
 // Per-instance device memory inside the shared workspace.
 void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, const int64_t *cap)
 {
@@ -332,6 +410,7 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     float4 *E4 = w.take<float4>(2 * cells);
     double *phi_prev = w.take<double>(nodes);
     double *phi2 = cfg->solver == 2 ? w.take<double>(nodes) : nullptr;
+    float *ainv = L.dense_n ? w.take<float>((size_t)L.dense_n * L.dense_n) : nullptr;
     unsigned *counts[2], *offs[2], *curs[2], *boff[2];
     int4 *table[2];
     long long *info[2];
@@ -353,6 +432,7 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     if (!h) return;
     h->d_cell_cond = cc;
     h->d_node_cond = nc;
+    h->d_ainv = ainv;
     for (int l = 0; l < L.nlev; l++) {
         h->d_fix[l] = fix[l];
         h->d_u[l] = u[l];
@@ -908,7 +988,10 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
             for (int J = 0; J < NYc; J++)
                 h.fixh[l][(size_t)I * NYc + J] = h.fixh[l - 1][(size_t)(2 * I) * NYf + 2 * J];
     }
+    h.dense = L.dense_n && coarse_inverse(h.fixh[L.nlev - 1], L.NXl[L.nlev - 1], L.NYl[L.nlev - 1], h.ainvh);
     hipStream_t s = c->stream;
+    if (h.dense)
+        HIPCHK(c, hipMemcpyAsync(h.d_ainv, h.ainvh.data(), h.ainvh.size() * sizeof(float), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(h.d_cell_cond, h.cell_cond.data(), h.cell_cond.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(h.d_node_cond, h.node_cond.data(), h.node_cond.size(), hipMemcpyHostToDevice, s));
     for (int l = 0; l < L.nlev; l++)
@@ -983,6 +1066,8 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
         ca.py = L.py;
         const int last = ca.nlev - 1;
         ca.sweeps = std::min(64, std::max(2, std::max(ca.NX[last], ca.NY[last])));
+        ca.ainv = h.dense ? h.d_ainv : nullptr;
+        ca.dense_n = h.dense ? L.dense_n : 0;
     }
     HIPCHK(c, hipMemcpyAsync(c->d_inst + k, &d, sizeof d, hipMemcpyHostToDevice, s));
     // particle kernels' arguments (both storage sets; info[7] selects)
@@ -1194,7 +1279,10 @@ pic_status batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, vo
     HIPCHK(c, hipStreamSynchronize(s));
     for (int k = 0; k < n; k++)
         if (bad[k]) return fail(c, PIC_ERR_ARG, "particles with cell codes outside the grid");
-    for (auto &h : c->in) h.fixh.clear();
+    for (auto &h : c->in) {
+        h.fixh.clear();
+        h.ainvh = std::vector<float>();
+    }
     return PIC_OK;
 }
 
