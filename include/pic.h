@@ -95,11 +95,12 @@ typedef struct {
     int32_t hitlog_species_mask; /* bit s logs species s */
     int32_t warm_start;          /* start of pic_step's solves: 0 previous phi, 1 linear extrapolation */
     /* ion recycling (Sec. III.A, III.C): an ion removed at a wall or conductor
-     * (classes 0..7) is replaced in the same slot, in the same push, by a
-     * thermal ion in a cell of the bulk rows 0 .. recycle_rows-1 (which must
-     * hold no solid cell): cell, offsets and Gaussian velocity from
-     * Philox4x32-10 with key recycle_key, counter (step, lost ion's cell code,
-     * bits of its offsets).  0 = off. */
+     * (classes 0..7) is replaced in the same slot, within the same pic_push,
+     * by a thermal ion in a cell of the bulk rows 0 .. recycle_rows-1 (which
+     * must hold no solid cell): cell, offsets and Gaussian velocity from
+     * Philox4x32-10 with key recycle_key, counter (step, bits of the lost
+     * ion's v_x after the kick, bits of its offsets before the move).
+     * 0 = off. */
     int32_t recycle_rows;
     uint32_t recycle_key[2];
     double recycle_vth;          /* Gaussian sigma of each velocity component of a new ion */

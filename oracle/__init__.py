@@ -71,7 +71,7 @@ def lib():
             f.restype = i64
         L.or_philox4x32_10.argtypes = [P, P, P]
         L.or_philox4x32_10.restype = None
-        L.or_recycled_ion.argtypes = [P, C.c_int32, C.c_float, C.c_float, i, P, P, P, P, P]
+        L.or_recycled_ion.argtypes = [P, C.c_float, C.c_float, C.c_float, i, P, P, P, P, P]
         L.or_recycled_ion.restype = None
         for nm in ("or_rewind_f32", "or_rewind_f64"):
             f = getattr(L, nm)
@@ -310,15 +310,16 @@ def philox4x32_10(ctr, key):
     return out
 
 
-def recycled_ion(w, step, old_code, ox0, oy0):
-    """(cell code, ox, oy, vx, vy) of the ion that replaces a lost one
-    (float32 offsets, float64 velocities)."""
+def recycled_ion(w, step, ux, ox0, oy0):
+    """(cell code, ox, oy, vx, vy) of the ion that replaces one lost in the
+    push of ``step`` with v_x = ux after the kick and offsets ox0, oy0 before
+    the move (float32 offsets, float64 velocities)."""
     k0, k1 = w.recycle_key()
     rc = _Recycle(int(w.recycle_rows), k0, k1, float(w.species[1].vth), int(step))
     code = C.c_int32()
     ox, oy = C.c_float(), C.c_float()
     vx, vy = C.c_double(), C.c_double()
-    lib().or_recycled_ion(C.cast(C.pointer(rc), C.c_void_p), int(old_code), float(ox0), float(oy0), w.ny,
+    lib().or_recycled_ion(C.cast(C.pointer(rc), C.c_void_p), float(ux), float(ox0), float(oy0), w.ny,
                           C.cast(C.pointer(code), C.c_void_p), C.cast(C.pointer(ox), C.c_void_p),
                           C.cast(C.pointer(oy), C.c_void_p), C.cast(C.pointer(vx), C.c_void_p),
                           C.cast(C.pointer(vy), C.c_void_p))

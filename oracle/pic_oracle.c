@@ -299,9 +299,9 @@ void or_field(int NX, int NY, int px, int py, const uint8_t *node_cond,
  * thermal ion in the bulk plasma, the ionisation of the ambient gas, only in
  * the bulk rows 0 .. rows-1.  The new ion's cell, offsets and velocity come
  * from a counter-based generator, Philox4x32-10 (Salmon, Moraes, Dror and
- * Shaw, SC 2011), keyed by the run's seed and counting on (step, the lost
- * ion's cell code and offset bits), so they do not depend on the order in
- * which particles are stored:
+ * Shaw, SC 2011), keyed by the run's seed and counting on (step, bits of the
+ * lost ion's v_x after the kick, bits of its offsets before the move), so
+ * they do not depend on the order in which particles are stored:
  *   r  = Philox(ctr, key), r' = Philox(ctr, key + (0, 1))
  *   i  = (r0 >> 8) * rows >> 24,  j = (r1 >> 8) * ny >> 24   (exact integers)
  *   ox = (r2 >> 8) 2^-24,  oy = (r3 >> 8) 2^-24              (exact floats)
@@ -333,10 +333,10 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 
 static uint32_t f32_bits(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
 
-void or_recycled_ion(const or_recycle *rc, int32_t old_code, float ox0, float oy0, int ny, int32_t *code,
+void or_recycled_ion(const or_recycle *rc, float ux, float ox0, float oy0, int ny, int32_t *code,
                      float *ox, float *oy, double *vx, double *vy)
 {
-    uint32_t ctr[4] = {(uint32_t)rc->step, (uint32_t)old_code, f32_bits(ox0), f32_bits(oy0)};
+    uint32_t ctr[4] = {(uint32_t)rc->step, f32_bits(ux), f32_bits(ox0), f32_bits(oy0)};
     uint32_t key[2] = {rc->k0, rc->k1}, r[4], q[4];
     or_philox4x32_10(ctr, key, r);
     key[1] += 1u;
@@ -420,8 +420,8 @@ void or_recycled_ion(const or_recycle *rc, int32_t old_code, float ox0, float oy
             if (surf && dead == 4) surf[cj]++;                                       \
             if (rc && rc->rows > 0) {                                                \
                 int32_t code; float nox, noy; double nvx, nvy;                       \
-                or_recycled_ion(rc, c, (float)x0, (float)y0, ny, &code, &nox, &noy,  \
-                             &nvx, &nvy);                                            \
+                or_recycled_ion(rc, (float)ux, (float)x0, (float)y0, ny, &code,      \
+                             &nox, &noy, &nvx, &nvy);                                \
                 cell[p] = code; ox[p] = (T)nox; oy[p] = (T)noy;                      \
                 vx[p] = (T)nvx; vy[p] = (T)nvy;                                      \
             }                                                                        \

@@ -143,6 +143,7 @@ struct PushArgs {
     const long long *step;         // device step counter (hit records)
     unsigned long long *fallbacks;
     int recycle_rows;              // > 0: lost ions of this species are recycled into rows 0 .. recycle_rows-1
+                                   // (by k_recycle, after the push)
     unsigned recycle_key[2];
     double recycle_vth;
 };
@@ -217,6 +218,7 @@ void launch_tick(long long *step, hipStream_t s);
 // the node-field energy of an instance, as kDiagBlocks partials each, then
 // summed in block order into out[0] (kinetic) / out[0] (field)
 void launch_kinetic(const PushArgs *A, int unit, double *part, double *out, hipStream_t s);
+void launch_recycle(const PushArgs *A, const Tab &t, hipStream_t s);
 void launch_field_energy(const Inst *I, int inst, double *part, double *out, hipStream_t s);
 int bin_per_block();
 

@@ -1772,9 +1772,6 @@ struct PK {
     // (the block's deposit window and a one-cell frame; CW = 0: none)
     const uint8_t *scc;
     int c0i, c0j, CW, CH;
-    int recycle_rows;
-    unsigned rk0, rk1;
-    double rvth;
 };
 
 __device__ __forceinline__ PK resolve(const PushArgs &a)
@@ -1805,10 +1802,6 @@ __device__ __forceinline__ PK resolve(const PushArgs &a)
     k.box_j_lo = a.box_j_lo;
     k.box_j_hi = a.box_j_hi;
     k.species = a.species;
-    k.recycle_rows = a.recycle_rows;
-    k.rk0 = a.recycle_key[0];
-    k.rk1 = a.recycle_key[1];
-    k.rvth = a.recycle_vth;
     k.surf = to_global(a.surf);
     k.iad = to_global(a.iad);
     k.log = a.log;
@@ -1903,8 +1896,9 @@ __device__ __forceinline__ bool push_core(const PK &a, float x0, float y0, float
 // ionisation of the ambient gas.  Counter-based generator Philox4x32-10
 // (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of two 32 x 32-bit
 // products (multipliers 0xD2511F53, 0xCD9E8D57), the key bumped by the Weyl
-// constants 0x9E3779B9, 0xBB67AE85 between rounds.  Counter (step, lost ion's
-// cell code, bits of its offsets), keys (k0, k1) and (k0, k1 + 1):
+// constants 0x9E3779B9, 0xBB67AE85 between rounds.  Counter (step, bits of
+// the lost ion's v_x after the kick, bits of its offsets before the move),
+// keys (k0, k1) and (k0, k1 + 1):
 //   cell (r0 >> 8) * rows >> 24, (r1 >> 8) * ny >> 24; offsets (r2 >> 8), (r3 >> 8) * 2^-24;
 //   velocity vth sqrt(-2 ln u) (cos, sin)(2 pi v), u = ((q0 >> 8) + 1) 2^-24,
 //   v = (q1 >> 8) 2^-24, in double, rounded to float.
@@ -1932,21 +1926,28 @@ __device__ __forceinline__ Philox4 philox4x32_10(unsigned c0, unsigned c1, unsig
     return Philox4{c0, c1, c2, c3};
 }
 
-__device__ __forceinline__ void recycled_ion(const PK &a, long long step, int old_code, float x0, float y0,
-                                             int &ci, int &cj, float &ox, float &oy, float &vx, float &vy)
+struct NewIon {
+    int ci, cj;
+    float ox, oy, vx, vy;
+};
+
+__device__ __forceinline__ NewIon recycled_ion(unsigned long long step, float ux, float x0, float y0, unsigned k0,
+                                               unsigned k1, int rows, int ny, double vth)
 {
-    const unsigned c0 = (unsigned)step, c1 = (unsigned)old_code;
+    const unsigned c0 = (unsigned)step, c1 = __float_as_uint(ux);
     const unsigned c2 = __float_as_uint(x0), c3 = __float_as_uint(y0);
-    const Philox4 r = philox4x32_10(c0, c1, c2, c3, a.rk0, a.rk1);
-    const Philox4 q = philox4x32_10(c0, c1, c2, c3, a.rk0, a.rk1 + 1u);
-    ci = (int)(((unsigned long long)(r.x >> 8) * (unsigned)a.recycle_rows) >> 24);
-    cj = (int)(((unsigned long long)(r.y >> 8) * (unsigned)a.g.ny) >> 24);
-    ox = (float)(r.z >> 8) * 0x1p-24f;
-    oy = (float)(r.w >> 8) * 0x1p-24f;
+    const Philox4 r = philox4x32_10(c0, c1, c2, c3, k0, k1);
+    const Philox4 q = philox4x32_10(c0, c1, c2, c3, k0, k1 + 1u);
+    NewIon n;
+    n.ci = (int)(((unsigned long long)(r.x >> 8) * (unsigned)rows) >> 24);
+    n.cj = (int)(((unsigned long long)(r.y >> 8) * (unsigned)ny) >> 24);
+    n.ox = (float)(r.z >> 8) * 0x1p-24f;
+    n.oy = (float)(r.w >> 8) * 0x1p-24f;
     const double u = (double)((q.x >> 8) + 1u) * 0x1p-24, v = (double)(q.y >> 8) * 0x1p-24;
     const double rad = sqrt(-2.0 * log(u)), ang = 6.283185307179586 * v;
-    vx = (float)(a.rvth * rad * cos(ang));
-    vy = (float)(a.rvth * rad * sin(ang));
+    n.vx = (float)(vth * rad * cos(ang));
+    n.vy = (float)(vth * rad * sin(ang));
+    return n;
 }
 
 // push_core plus the particle's stores (velocity always; offsets if it
@@ -2044,6 +2045,21 @@ __device__ __forceinline__ void cell_fields(const PK &a, const float4 *sE, int e
 // (x0, y0)) into the block's LDS window of cell moments, or straight into the
 // node charge when it lies outside the window.  Called by every lane of the
 // wavefront (the merge of equal cells is wavefront-wide).
+// Area weighting of one particle straight into the global charge (integer
+// weights as in the LDS window path).
+__device__ __forceinline__ void deposit_global(GLOBAL unsigned long long *rho, const Geom &g, int ci, int cj,
+                                               unsigned ux, unsigned uy)
+{
+    const unsigned long long S = 65536ull;
+    const int i1 = g.px ? wrap_hi(ci + 1, g.nx) : ci + 1;
+    const int j1 = g.py ? wrap_hi(cj + 1, g.ny) : cj + 1;
+    const unsigned long long X = ux, Y = uy;
+    gatomic_add(&rho[(long long)ci * g.NY + cj], (S - X) * (S - Y));
+    gatomic_add(&rho[(long long)i1 * g.NY + cj], X * (S - Y));
+    gatomic_add(&rho[(long long)ci * g.NY + j1], (S - X) * Y);
+    gatomic_add(&rho[(long long)i1 * g.NY + j1], X * Y);
+}
+
 template <int MERGE>
 __device__ __forceinline__ void deposit_lane(const PK &a, unsigned long long *mA, unsigned long long *mB,
                                              int lane, bool alive, int ci, int cj, float x0, float y0,
@@ -2061,14 +2077,7 @@ __device__ __forceinline__ void deposit_lane(const PK &a, unsigned long long *mA
         if (wi >= 0 && wi < WX && wj >= 0 && wj < WY) {
             key = wi * WY + wj;
         } else {
-            const unsigned long long S = 65536ull;
-            const int i1 = g.px ? wrap_hi(ci + 1, g.nx) : ci + 1;
-            const int j1 = g.py ? wrap_hi(cj + 1, g.ny) : cj + 1;
-            const unsigned long long X = ux, Y = uy;
-            gatomic_add(&a.rho[(long long)ci * g.NY + cj], (S - X) * (S - Y));
-            gatomic_add(&a.rho[(long long)i1 * g.NY + cj], X * (S - Y));
-            gatomic_add(&a.rho[(long long)ci * g.NY + j1], (S - X) * Y);
-            gatomic_add(&a.rho[(long long)i1 * g.NY + j1], X * Y);
+            deposit_global(a.rho, g, ci, cj, ux, uy);
             nfb++;
         }
     }
@@ -2225,20 +2234,8 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                         uxv[k] = ux;
                         uyv[k] = uy;
                         if (!alive) {
+                            a.cell[v + k] = -1 - dead;
                             record_hit(a, tl, dead, ei, ej, ux, uy);
-                            if (a.recycle_rows && dead < 8) {
-                                // the slot takes the recycled ion (stored with the vector below)
-                                float nox, noy, nvx, nvy;
-                                recycled_ion(a, *a.step, c, xv[k], yv[k], ci, cj, nox, noy, nvx, nvy);
-                                a.cell[v + k] = (int)(((unsigned)ci << 16) | (unsigned)cj);
-                                xv[k] = nox;
-                                yv[k] = noy;
-                                uxv[k] = nvx;
-                                uyv[k] = nvy;
-                                alive = true;
-                            } else {
-                                a.cell[v + k] = -1 - dead;
-                            }
                         } else {
                             const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
                             if (nc != c) a.cell[v + k] = nc;
@@ -2322,19 +2319,7 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                     float vnx, vny;
                     alive = push_particle(a, p, c, x0, y0, vxu[u], vyu[u], eau[u], ebu[u], ci, cj,
                                           dead, ei, ej, vnx, vny);
-                    if (!alive) {
-                        record_hit(a, tl, dead, ei, ej, vnx, vny);
-                        if (a.recycle_rows && dead < 8) {
-                            float nvx, nvy;
-                            recycled_ion(a, *a.step, c, x0, y0, ci, cj, x0, y0, nvx, nvy);
-                            a.cell[p] = (int)(((unsigned)ci << 16) | (unsigned)cj);
-                            a.ox[p] = x0;
-                            a.oy[p] = y0;
-                            a.vx[p] = nvx;
-                            a.vy[p] = nvy;
-                            alive = true;
-                        }
-                    }
+                    if (!alive) record_hit(a, tl, dead, ei, ej, vnx, vny);
                 }
             }
             deposit_lane<MERGE>(a, mA, mB, lane, alive, ci, cj, x0, y0, i0, j0, WX, WY, nfb);
@@ -2448,6 +2433,41 @@ __device__ __forceinline__ void diag_block_sum(double v, double *part)
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Ion recycling after a push: every slot whose ion that push removed at a
+// wall or conductor (code -1 - class, class 0..7) takes a thermal ion in the
+// bulk rows, and the new ion's charge goes straight into rho.  The push
+// leaves the lost ion's kicked v_x and its offsets before the move in the
+// slot; with the step they form the generator's counter.  One thread per
+// slot of the storage set in use.
+__global__ __launch_bounds__(256) void k_recycle(const PushArgs *A, Tab t)
+{
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const PushArgs &a = A[t.id[ku]];
+    const int set = (int)a.info[7];
+    const long long p = (long long)((int)blockIdx.x - t.boff[ku]) * 256 + threadIdx.x;
+    if (p >= a.info[2 + set]) return;
+    GLOBAL int32_t *cell = to_global(a.cell[set]);
+    const int c = cell[p];
+    if (c >= 0 || c < -8) return;
+    GLOBAL float *ox = to_global(a.ox[set]), *oy = to_global(a.oy[set]);
+    GLOBAL float *vx = to_global(a.vx[set]), *vy = to_global(a.vy[set]);
+    const NewIon n = recycled_ion((unsigned long long)*a.step, vx[p], ox[p], oy[p], a.recycle_key[0],
+                                  a.recycle_key[1], a.recycle_rows, a.g.ny, a.recycle_vth);
+    cell[p] = (int)(((unsigned)n.ci << 16) | (unsigned)n.cj);
+    ox[p] = n.ox;
+    oy[p] = n.oy;
+    vx[p] = n.vx;
+    vy[p] = n.vy;
+    deposit_global(to_global(a.rho), a.g, n.ci, n.cj, (unsigned)floorf(n.ox * 65536.0f),
+                   (unsigned)floorf(n.oy * 65536.0f));
+}
+
+void launch_recycle(const PushArgs *A, const Tab &t, hipStream_t s)
+{
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_recycle, dim3(tab_blocks(t)), dim3(256), 0, s, A, t);
 }
 
 __global__ __launch_bounds__(256) void k_kinetic(const PushArgs *A, int unit, double *part)

@@ -262,6 +262,7 @@ struct pic_ctx {
     std::vector<double> vhost;
     // launch tables
     Tab t_l0{}, t_field{}, t_per{}, t_coarse{}, t_push{}, t_rewind{};
+    Tab t_recycle{};                // ion units with recycling: one thread per slot
     Tab t_plain{};                 // level-0 grid of the instances solved by plain CG
     Tab t_fine[kMaxLev] = {};      // 32 x 32 tiles of the fine multigrid levels handled one at a time
     Tab t_pair[kMaxLev] = {};      // 32 x 32 tiles of level l + 1 for levels l, l + 1 in one launch
@@ -924,6 +925,7 @@ void enqueue_push(pic_ctx *c, hipStream_t s, bool timed)
         c->nev++;
         for (auto &h : c->in) c->timed_particles += h.slots_ub[0] + h.slots_ub[1];
     }
+    launch_recycle(c->d_push, c->t_recycle, s);     // before the step counter moves on
     launch_tick(c->d_ctl, s);
     enqueue_assemble(c, s);
 }
@@ -1164,7 +1166,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
 
 void build_tabs(pic_ctx *c)
 {
-    c->t_l0 = c->t_field = c->t_per = c->t_coarse = c->t_push = c->t_rewind = c->t_plain = Tab{};
+    c->t_l0 = c->t_field = c->t_per = c->t_coarse = c->t_push = c->t_rewind = c->t_plain = c->t_recycle = Tab{};
     for (int l = 0; l < kMaxLev; l++) c->t_fine[l] = c->t_pair[l] = Tab{};
     c->maxlg = 0;
     c->coarse_lds = 0;
@@ -1199,6 +1201,8 @@ void build_tabs(pic_ctx *c)
         for (int s = 0; s < 2; s++) {
             tab_add(c->t_push, 2 * k + s, (int)L.max_blocks[s]);
             tab_add(c->t_rewind, 2 * k + s, (int)((h.slots_ub[s] + 255) / 256));
+            if (s == 1 && h.cfg.recycle_rows > 0)
+                tab_add(c->t_recycle, 2 * k + s, (int)std::max<long long>(1, (h.slots_ub[s] + 255) / 256));
         }
         c->push_lds = std::max(c->push_lds, push_lds_bytes(L.TX, L.TY, L.H));
     }

@@ -38,12 +38,12 @@ def test_recycled_ion_distribution():
     w = _workload()
     rng = np.random.default_rng(3)
     n = 20000
-    codes = rng.integers(0, 1 << 20, n)
+    ux = rng.standard_normal(n).astype(np.float32)
     ox = rng.random(n, np.float32)
     rows = np.zeros(n, np.int64)
     v = np.zeros((n, 2))
     for k in range(n):
-        c, x, y, vx, vy = oracle.recycled_ion(w, 7, int(codes[k]), float(ox[k]), 0.5)
+        c, x, y, vx, vy = oracle.recycled_ion(w, 7, float(ux[k]), float(ox[k]), 0.5)
         i, j = c >> 16, c & 0xFFFF
         assert 0 <= i < w.recycle_rows and 0 <= j < w.ny and 0.0 <= x < 1.0 and 0.0 <= y < 1.0
         rows[k] = i
