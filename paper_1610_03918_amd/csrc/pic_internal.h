@@ -78,9 +78,22 @@ struct CoarseArgs {
     int px, py;
     int sweeps;                    // red-black pairs on the coarsest level
     int lds_bytes;
-    const float *ainv;             // inverse of the coarsest level's operator (n x n), or null
+    const float *ainv;             // inverse of the coarsest level's operator (packed lower triangle), or null
     int dense_n;                   // its node count n when the coarsest level is solved exactly, else 0
+    int off_p;                     // LDS: kCoarseWaves x n column partial sums of the exact solve
 };
+
+constexpr int kCoarseWaves = 16;   // wavefronts of the coarse kernel's work-group (1024 threads)
+constexpr int kDenseMaxNodes = 768; // largest coarsest level given an explicit inverse (3 x 64 lanes x 4 floats)
+
+// Packed lower triangle of a symmetric n x n matrix: row r holds columns
+// 0 .. r padded with zeros to a multiple of 4 floats; its first float sits
+// at tri_off(r) = sum over q < r of 4 (floor(q / 4) + 1).
+__host__ __device__ inline long long tri_off(int r)
+{
+    const long long M = r >> 2, T = r & 3;
+    return 4 * (M + 1) * (2 * M + T);
+}
 
 // Device descriptor of one instance.
 struct Inst {

@@ -1539,23 +1539,109 @@ __device__ __forceinline__ void wave_sync()
 
 constexpr int kCoarseWaveNodes = 640;   // LDS levels at most this size are run by one wavefront
 
-// Exact solve of the coarsest level, u = A^-1 g, with the inverse the host
-// factorised (float32, n x n, symmetric, zero rows and columns at fixed
-// nodes): thread r forms row r; lanes read consecutive entries of a column.
-__device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__ ainv, int n, int first, int step)
+// Sums of four floats over the 64 lanes of a wavefront (all lanes active),
+// returned in lane 63: row-local butterflies (quad permutes, row mirrors)
+// give every lane its row sum, then two row broadcasts carry the sums of
+// rows 0-2 up to row 3.  A fixed order of additions.
+#define DPPF_STEP(ctrl, rmask)                                                                          \
+    a += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), ctrl, rmask, 0xF, false));    \
+    b += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(b), ctrl, rmask, 0xF, false));    \
+    c += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(c), ctrl, rmask, 0xF, false));    \
+    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), ctrl, rmask, 0xF, false));
+__device__ __forceinline__ void wave_sum4_f32(float &a, float &b, float &c, float &d)
 {
-    for (int r = first; r < n; r += step) {
-        const float *col = ainv + r;
-        float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f;
-        int c = 0;
-        for (; c + 4 <= n; c += 4) {
-            acc0 += col[(size_t)c * n] * L.g[c];
-            acc1 += col[(size_t)(c + 1) * n] * L.g[c + 1];
-            acc2 += col[(size_t)(c + 2) * n] * L.g[c + 2];
-            acc3 += col[(size_t)(c + 3) * n] * L.g[c + 3];
+    DPPF_STEP(0xB1, 0xF)   // quad_perm [1,0,3,2]
+    DPPF_STEP(0x4E, 0xF)   // quad_perm [2,3,0,1]
+    DPPF_STEP(0x141, 0xF)  // row_half_mirror
+    DPPF_STEP(0x140, 0xF)  // row_mirror
+    DPPF_STEP(0x142, 0xA)  // row_bcast:15 into rows 1, 3
+    DPPF_STEP(0x143, 0xC)  // row_bcast:31 into rows 2, 3
+}
+#undef DPPF_STEP
+
+// Exact solve of the coarsest level, u = A^-1 g, from the packed lower
+// triangle T of the inverse the host factorised (row r: columns 0 .. r padded
+// to a multiple of 4, diagonal halved, zero rows and columns at fixed nodes).
+// Wavefront w takes rows w, w + 16, ...; its lanes read 16-byte pieces of the
+// row.  Each stored entry serves twice: its row's dot product with g (the
+// lower part of u[r] and half its diagonal term, summed across the wave) and
+// T[r][c] g[r] added to the lane's partial sum for column c (the upper part
+// and the other half).  The column partials of the 16 wavefronts meet in LDS
+// (part, 16 x n floats) and are summed in a fixed order.  Every stored float
+// is read once.
+__device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__ T, int n, float *part, int tid)
+{
+    const int lane = tid & 63, w = tid >> 6;
+    const int npc = (n + 3) >> 2;                 // 16-byte pieces of the longest row
+    // g is read in 16-byte pieces: its padding up to a multiple of 4 (inside
+    // the level's 16-byte rounded array) is cleared first
+    if (tid < 4 && n + tid < 4 * npc) L.g[n + tid] = 0.0f;
+    __syncthreads();
+    const float4 *g4 = (const float4 *)L.g;
+    constexpr int Q = (kDenseMaxNodes + 255) / 256;  // 16-byte pieces per lane and row
+    float4 acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // two rows per pass, all their loads issued before any is used (the
+    // wave's requests overlap instead of paying the latency row by row)
+    constexpr int R = 2;
+    for (int r0 = w; r0 < n; r0 += R * kCoarseWaves) {
+        float4 t[R][Q];
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            const int r = r0 + i * kCoarseWaves;
+            const int len = r < n ? (r >> 2) + 1 : 0;      // pieces of row r
+            const float4 *row = (const float4 *)(T + tri_off(r < n ? r : 0));
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+                const int k = lane + 64 * q;
+                t[i][q] = k < len ? row[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
-        for (; c < n; c++) acc0 += col[(size_t)c * n] * L.g[c];
-        L.u[r] = (acc0 + acc1) + (acc2 + acc3);
+        float dot[R];
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            const int r = r0 + i * kCoarseWaves;
+            const float gr = r < n ? L.g[r] : 0.0f;
+            dot[i] = 0.0f;
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+                const int k = lane + 64 * q;
+                const float4 gq = k < npc ? g4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+                dot[i] += t[i][q].x * gq.x + t[i][q].y * gq.y + t[i][q].z * gq.z + t[i][q].w * gq.w;
+                acc[q].x += t[i][q].x * gr;
+                acc[q].y += t[i][q].y * gr;
+                acc[q].z += t[i][q].z * gr;
+                acc[q].w += t[i][q].w * gr;
+            }
+        }
+        float d2 = 0.0f, d3 = 0.0f;
+        wave_sum4_f32(dot[0], dot[1], d2, d3);
+        if (lane == 63) {
+#pragma unroll
+            for (int i = 0; i < R; i++) {
+                const int r = r0 + i * kCoarseWaves;
+                if (r < n) L.u[r] = dot[i];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int k = lane + 64 * q, c = 4 * k;
+        if (k < npc) {
+            float *pw = part + (size_t)w * n;
+            if (c < n) pw[c] = acc[q].x;
+            if (c + 1 < n) pw[c + 1] = acc[q].y;
+            if (c + 2 < n) pw[c + 2] = acc[q].z;
+            if (c + 3 < n) pw[c + 3] = acc[q].w;
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < n; c += 64 * kCoarseWaves) {
+        float v = L.u[c];
+#pragma unroll
+        for (int q = 0; q < kCoarseWaves; q++) v += part[(size_t)q * n + c];
+        L.u[c] = v;
     }
 }
 
@@ -1594,21 +1680,32 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
     };
     float *sr = (float *)(lds + a.off_s);
     const int nlev = a.nlev, px = a.px, py = a.py;
+    // masks of every level and the first level's g, in 16-byte pieces (the
+    // global arrays are 256-byte aligned, the LDS ones 16-byte), bytes for the
+    // tails; then the first level's red start from them
     for (int l = 0; l < nlev; l++) {
-        const int N = dims[0][l] * dims[1][l];
-        const uint8_t *src = a.fix[l];
-        uint8_t *dst = lds + tab[2][l];
-        for (int k = tid; k < N; k += nt) dst[k] = src[k];
+        const int N = dims[0][l] * dims[1][l], N16 = N >> 4;
+        const uint4 *src = (const uint4 *)a.fix[l];
+        uint4 *dst = (uint4 *)(lds + tab[2][l]);
+        for (int k = tid; k < N16; k += nt) dst[k] = src[k];
+        for (int k = (N16 << 4) + tid; k < N; k += nt) lds[tab[2][l] + k] = a.fix[l][k];
     }
+    {
+        const int N = dims[0][0] * dims[1][0], N4 = N >> 2;
+        const float4 *src = (const float4 *)a.g_top;
+        float4 *dst = (float4 *)(lds + tab[1][0]);
+        for (int k = tid; k < N4; k += nt) dst[k] = src[k];
+        float *dg = (float *)(lds + tab[1][0]);
+        for (int k = (N4 << 2) + tid; k < N; k += nt) dg[k] = a.g_top[k];
+    }
+    __syncthreads();
     {
         const CLev L = lev(0);
         const int N = L.NX * L.NY;
         const float rcp = 1.0f / (float)L.NY;
         for (int k = tid; k < N; k += nt) {
-            const float gv = a.g_top[k];
-            L.g[k] = gv;
             const int i = div_rcp(k, rcp), j = k - i * L.NY;
-            L.u[k] = (!a.fix[0][k] && ((i + j) & 1) == 0) ? gv * 0.25f : 0.0f;
+            L.u[k] = (!L.f[k] && ((i + j) & 1) == 0) ? L.g[k] * 0.25f : 0.0f;
         }
     }
     __syncthreads();
@@ -1639,7 +1736,7 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
         }
         if (a.dense_n) {
             __syncthreads();
-            c_dense(lev(nlev - 1), a.ainv, a.dense_n, tid, nt);
+            c_dense(lev(nlev - 1), a.ainv, a.dense_n, (float *)(lds + a.off_p), tid);
             __syncthreads();
         }
         if (tid < 64) {
@@ -1665,7 +1762,7 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
         }
         __syncthreads();
     } else if (a.dense_n) {
-        c_dense(lev(nlev - 1), a.ainv, a.dense_n, tid, nt);
+        c_dense(lev(nlev - 1), a.ainv, a.dense_n, (float *)(lds + a.off_p), tid);
         __syncthreads();
     } else {
         const CLev L = lev(nlev - 1);

@@ -45,8 +45,6 @@ int ilog2(int v)
     return l;
 }
 
-constexpr int kDenseMaxNodes = 800;    // largest coarsest level given an explicit inverse
-constexpr int kDenseMinDim = 8;        // below this the coarsest level's sweeps are cheap
 
 bool coarsenable(int n, int periodic)
 {
@@ -164,12 +162,14 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
     L.lg = 1;
     while (L.lg < L.nlev && (L.NXl[L.lg] * L.NYl[L.lg] > kCoarseMaxNodes || lds_from(L.lg) > kCoarseMaxLds)) L.lg++;
     L.mg = (c->solver == 0) && L.nlev >= 2 && L.lg < L.nlev;
-    // a coarsest level that red-black sweeps would need many passes over (a
-    // periodic axis with an odd factor stops the coarsening early) is solved
-    // exactly with its inverse instead
+    // the coarsest level is solved exactly with its inverse rather than swept
+    // (a periodic axis with an odd factor stops the coarsening early, and a
+    // large coarsest level needs many sweeps) when it is small enough and its
+    // column partial sums fit in the coarse kernel's LDS
     if (L.mg) {
         const int last = L.nlev - 1, n = L.NXl[last] * L.NYl[last];
-        if (n <= kDenseMaxNodes && std::max(L.NXl[last], L.NYl[last]) > kDenseMinDim) L.dense_n = n;
+        const size_t part = ((size_t)kCoarseWaves * n * 4 + 15) & ~size_t(15);
+        if (n <= kDenseMaxNodes && lds_from(L.lg) + part <= (size_t)kCoarseMaxLds) L.dense_n = n;
     }
     L.TX = c->tile_x ? c->tile_x : 16;
     L.TY = c->tile_y ? c->tile_y : 16;
@@ -326,7 +326,9 @@ void tab_add(Tab &t, int id, int blocks)
 // Inverse of the coarsest level's operator, 4 u_k minus the free neighbours'
 // u (periodic wrap as the kernels take it) on free nodes, u = 0 on fixed
 // ones: float64 Cholesky factor, then one column of the inverse per free
-// node, stored as float32 n x n with zero rows and columns at fixed nodes.
+// node.  Stored as the packed lower triangle (tri_off) in float32, zero in
+// the rows and columns of fixed nodes, its diagonal halved: the kernel's
+// row sums and column sums each take half of it.
 // False when the operator is singular or nearly so (no fixed node).
 bool coarse_inverse(const std::vector<uint8_t> &fix, int NX, int NY, std::vector<float> &out)
 {
@@ -365,7 +367,7 @@ bool coarse_inverse(const std::vector<uint8_t> &fix, int NX, int NY, std::vector
     std::vector<double> LT((size_t)m * m);        // L^T, for the backward substitutions
     for (int r = 0; r < m; r++)
         for (int q = 0; q <= r; q++) LT[(size_t)q * m + r] = A[(size_t)r * m + q];
-    out.assign((size_t)n * n, 0.0f);
+    out.assign((size_t)tri_off(n), 0.0f);
     std::vector<double> x(m);
     for (int cidx = 0; cidx < m; cidx++) {
         std::fill(x.begin(), x.end(), 0.0);
@@ -382,7 +384,12 @@ bool coarse_inverse(const std::vector<uint8_t> &fix, int NX, int NY, std::vector
             for (int q = r + 1; q < m; q++) v -= tr[q] * x[q];
             x[r] = v / tr[r];
         }
-        for (int r = 0; r < m; r++) out[(size_t)node[r] * n + node[cidx]] = (float)x[r];
+        const int cn = node[cidx];
+        for (int r = 0; r < m; r++) {
+            const int rn = node[r];
+            if (rn > cn) out[(size_t)tri_off(rn) + cn] = (float)x[r];
+            else if (rn == cn) out[(size_t)tri_off(rn) + cn] = (float)(0.5 * x[r]);
+        }
     }
     return true;
 }
@@ -411,7 +418,7 @@ void carve_inst(InstHost *h, Carve &w, const Layout &L, const pic_config *cfg, c
     float4 *E4 = w.take<float4>(2 * cells);
     double *phi_prev = w.take<double>(nodes);
     double *phi2 = cfg->solver == 2 ? w.take<double>(nodes) : nullptr;
-    float *ainv = L.dense_n ? w.take<float>((size_t)L.dense_n * L.dense_n) : nullptr;
+    float *ainv = L.dense_n ? w.take<float>((size_t)tri_off(L.dense_n)) : nullptr;
     unsigned *counts[2], *offs[2], *curs[2], *boff[2];
     int4 *table[2];
     long long *info[2];
@@ -1061,6 +1068,8 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
         }
         ca.off_s = off;
         off += (L.NXl[L.lg] * L.NYl[L.lg] * 4 + 15) & ~15;
+        ca.off_p = off;
+        if (h.dense) off += (kCoarseWaves * L.dense_n * 4 + 15) & ~15;
         ca.lds_bytes = off;
         ca.u_top = h.d_u[L.lg];
         ca.g_top = h.d_g[L.lg];
