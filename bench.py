@@ -45,15 +45,17 @@ def workload(name):
 
 
 def push_source_hash():
-    """sha256 of what the push kernel is built from: the header's constants
-    and the structs it reads (Geom, HitLog, PushArgs, the LDS size formula)
-    and the particle section of the kernel source (gather, push, wall test,
-    deposit), so that edits elsewhere keep its counters valid."""
+    """sha256 of what the push kernel is built from: the header constants it
+    uses, the structs it reads (Geom, Tab, HitLog, PushArgs, the LDS size
+    formula) and the particle section of the kernel source (gather, push,
+    wall test, deposit), so that edits elsewhere keep its counters valid."""
     import hashlib
     import re
     hdr = open(os.path.join(os.path.dirname(KERNEL_SOURCE), "pic_internal.h"), "rb").read()
-    parts = re.findall(rb"^constexpr int k\w+ = [^\n]*", hdr, re.M)
-    for name in (b"struct Geom {", b"struct HitLog {", b"struct PushArgs {", b"inline size_t push_lds_bytes("):
+    names = (b"kNClass", b"kIadBins", b"kDiagBlocks", b"kMaxInst", b"kMaxUnits", b"kPushThreads", b"kFieldFrame")
+    parts = [re.search(rb"^constexpr int " + k + rb" = [^\n]*", hdr, re.M).group(0) for k in names]
+    for name in (b"struct Geom {", b"struct Tab {", b"struct HitLog {", b"struct PushArgs {",
+                 b"inline size_t push_lds_bytes("):
         a = hdr.index(name)
         parts.append(hdr[a:hdr.index(b"\n}", a) + 2])
     src = open(KERNEL_SOURCE, "rb").read()
