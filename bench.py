@@ -386,6 +386,28 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def measured_copy_rate():
+    """HBM bytes per second of a plain 1 GiB device-to-device copy (read +
+    written), timed with events: what a streaming kernel reaches on this GPU,
+    beside the published peak."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * 4 * n / (ms * 1e-3) / 1e9
+
+
 def copy_calibration():
     """A plain device copy of known size (1 GiB read + 1 GiB written), the
     reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes."""
@@ -512,6 +534,7 @@ def main():
     per_launch = 0.5 * (alive0 + alive1)           # one push launch covers both species
     achieved = per_launch * BYTES_PER_PARTICLE_STEP / (push_ms * 1e-3) / 1e9
     traffic = measured_traffic(w.name, per_launch)
+    copy_gbs = measured_copy_rate()
     out = {
         "metric": "particle-steps/s (push+deposit+solve); Poisson ms/step, plain vs learned start",
         "value": value,
@@ -538,7 +561,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "kernel": f"k_push<true,{args.unroll},{args.merge}>", "avg_launch_ms": push_ms, "launches": launches,
-                     "bytes_per_launch": per_launch * BYTES_PER_PARTICLE_STEP},
+                     "bytes_per_launch": per_launch * BYTES_PER_PARTICLE_STEP,
+                     "plain_copy_GBs": copy_gbs, "frac_of_plain_copy": achieved / copy_gbs},
     }
     if not args.no_learned and w.name.startswith("trench"):
         out["learned_start"] = learned_start(w, pic, parts, args)
