@@ -210,7 +210,7 @@ void launch_sweeps(const Inst *I, const Tab &t, int jacobi, int sweeps, hipStrea
 void launch_init_red0(const Inst *I, const Tab &t, Part pt, hipStream_t s);
 void launch_pupdate_Ap(const Inst *I, const Tab &t, int kold, int first, Part pt, hipStream_t s);
 void launch_update_red0(const Inst *I, const Tab &t, int knew, Part pt, hipStream_t s);
-void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s);
+void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, const Tab &t0, Part pt, bool fuse, hipStream_t s);
 // fused fine-level V-cycle halves (tables of 32 x 32 tiles of level l)
 constexpr int kMgTileHost = 32;
 // down: mode 0 level >= 1, mode 1 level 0 at the start of an inner pass,

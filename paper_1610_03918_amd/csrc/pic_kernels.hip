@@ -169,21 +169,14 @@ __device__ void apply_op(const Inst &I, int op, double t0, double t1)
 
 // One block per unit: totals of the unit's partials in block order, then the
 // scalar logic of the operation on that instance.
-__global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part pt, int op)
+// Sums of the partials b0 .. b1-1 of nq quantities by threads 0 .. 255 of a
+// block (others pass through): per-thread sums in a fixed order, then one
+// per wavefront into sh[q][0 .. 3].  The caller synchronises and adds the
+// four, so every kernel that reduces the same partials gets the same totals.
+__device__ __forceinline__ void partial_sums_256(const Part &pt, int b0, int b1, int nq, double (*sh)[4], int tid)
 {
-    const Inst &I = insts[t.id[blockIdx.x]];
-    const int *F = I.F;
-    const bool inner = op == OP_PQ || op == OP_UPDATE || op == OP_RZ || op == OP_CG_DOTS;
-    if (inner && F[F_DONE]) return;
-    if (op == OP_RR64_PASS && F[F_SKIP]) return;
-    if (op == OP_INIT && F[F_CONV]) {
-        if (threadIdx.x == 0) apply_op(I, op, 0.0, 0.0);
-        return;
-    }
-    __shared__ double sh[2][4];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE || op == OP_RR64_START || op == OP_CG_DOTS) ? 2 : 1;
-    const int b0 = t.boff[blockIdx.x], b1 = t.boff[blockIdx.x + 1];
+    if (tid >= 256) return;
+    const int lane = tid & 63, wid = tid >> 6;
     double s[2] = {0.0, 0.0};
     // loads of a round issued together
     for (int k0 = b0; k0 < b1; k0 += 8 * 256) {
@@ -204,6 +197,23 @@ __global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part
         const double w = wave_sum(s[q]);
         if (lane == 0) sh[q][wid] = w;
     }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part pt, int op)
+{
+    const Inst &I = insts[t.id[blockIdx.x]];
+    const int *F = I.F;
+    const bool inner = op == OP_PQ || op == OP_UPDATE || op == OP_RZ || op == OP_CG_DOTS;
+    if (inner && F[F_DONE]) return;
+    if (op == OP_RR64_PASS && F[F_SKIP]) return;
+    if (op == OP_INIT && F[F_CONV]) {
+        if (threadIdx.x == 0) apply_op(I, op, 0.0, 0.0);
+        return;
+    }
+    __shared__ double sh[2][4];
+    const int tid = threadIdx.x;
+    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE || op == OP_RR64_START || op == OP_CG_DOTS) ? 2 : 1;
+    partial_sums_256(pt, t.boff[blockIdx.x], t.boff[blockIdx.x + 1], nq, sh, tid);
     __syncthreads();
     if (tid != 0) return;
     apply_op(I, op, sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
@@ -1128,8 +1138,9 @@ void launch_mg_down(const Inst *I, const Tab &t, int level, int mode, int par, P
         hipLaunchKernelGGL((k_mg_down<kMgSmooth, 1>), g, b, 0, s, I, t, level, par, pt);
         finalize(I, t, pt, OP_INIT, s);
     } else {
+        // mode 3: the coarse kernel reduces the partials (fused update)
         hipLaunchKernelGGL((k_mg_down<kMgSmooth, 2>), g, b, 0, s, I, t, level, par, pt);
-        finalize(I, t, pt, OP_UPDATE, s);
+        if (mode == 2) finalize(I, t, pt, OP_UPDATE, s);
     }
 }
 
@@ -1537,7 +1548,7 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kCoarseWaveNodes = 640;   // LDS levels at most this size are run by one wavefront
+constexpr int kCoarseWaveNodes = 200;   // LDS levels at most this size are run by one wavefront
 
 // Sums of four floats over the 64 lanes of a wavefront (all lanes active),
 // returned in lane 63: row-local butterflies (quad permutes, row mirrors)
@@ -1652,15 +1663,35 @@ __device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__
 // reds, the black update from them, then a red half-sweep.  The levels of at
 // most kCoarseWaveNodes nodes, from the first such level to the coarsest and
 // back, are run by the first wavefront alone (no work-group barriers).
-__global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
+// With fuse set it first does what k_finalize(OP_UPDATE) does after the
+// level-0 CG step (t0: that launch's units, in the same order as t): the
+// totals of its partials in the same order, the iteration count and the
+// inner stop test; one launch fewer per iteration.  The paired or single
+// fine levels between the two run on regardless (their output is then
+// unused).
+__global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t, Tab t0, Part pt, int fuse)
 {
     const Inst &I = insts[t.id[blockIdx.x]];
-    if (I.F[F_DONE]) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (fuse) {
+        __shared__ double fsh[2][4];
+        __shared__ int fdone;
+        partial_sums_256(pt, t0.boff[blockIdx.x], t0.boff[blockIdx.x + 1], 2, fsh, tid);
+        __syncthreads();
+        if (tid == 0) {
+            apply_op(I, OP_UPDATE, fsh[0][0] + fsh[0][1] + fsh[0][2] + fsh[0][3],
+                     fsh[1][0] + fsh[1][1] + fsh[1][2] + fsh[1][3]);
+            fdone = I.F[F_DONE];
+        }
+        __syncthreads();
+        if (fdone) return;
+    } else if (I.F[F_DONE]) {
+        return;
+    }
     const CoarseArgs &a = I.coarse;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int tab[3][kMaxLev];
     __shared__ int dims[2][kMaxLev];
-    const int tid = threadIdx.x, nt = blockDim.x;
     if (tid < a.nlev) {
         tab[0][tid] = a.off_u[tid];
         tab[1][tid] = a.off_g[tid];
@@ -1789,7 +1820,7 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t)
     }
 }
 
-void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s)
+void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, const Tab &t0, Part pt, bool fuse, hipStream_t s)
 {
     if (!t.n) return;
     static int allowed = 64 * 1024;
@@ -1797,7 +1828,7 @@ void launch_coarse(const Inst *I, const Tab &t, int lds_bytes, hipStream_t s)
         (void)hipFuncSetAttribute((const void *)k_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         allowed = lds_bytes;
     }
-    hipLaunchKernelGGL(k_coarse, dim3(t.n), dim3(1024), lds_bytes, s, I, t);
+    hipLaunchKernelGGL(k_coarse, dim3(t.n), dim3(1024), lds_bytes, s, I, t, t0, pt, fuse ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------

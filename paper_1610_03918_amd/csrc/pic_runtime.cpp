@@ -589,14 +589,14 @@ void enqueue_deposit(pic_ctx *c, hipStream_t s)
 
 // Levels 1 .. of a V-cycle: down half-cycles, the LDS levels, up
 // half-cycles (level 0's halves carry the CG step and its dot products).
-void enqueue_vcycle_mid(pic_ctx *c, hipStream_t s)
+void enqueue_vcycle_mid(pic_ctx *c, bool fuse_update, hipStream_t s)
 {
     Part pt = part_of(c);
     for (int l = 1; l < c->maxlg; l++) {
         launch_mg_pair(c->d_inst, c->t_pair[l], l, true, s);
         launch_mg_down(c->d_inst, c->t_fine[l], l, 0, 0, pt, s);
     }
-    launch_coarse(c->d_inst, c->t_coarse, c->coarse_lds, s);
+    launch_coarse(c->d_inst, c->t_coarse, c->coarse_lds, c->t_fine[0], pt, fuse_update, s);
     for (int l = c->maxlg - 1; l >= 1; l--) {
         launch_mg_up(c->d_inst, c->t_fine[l], l, 0, pt, s);
         launch_mg_pair(c->d_inst, c->t_pair[l], l, false, s);
@@ -612,7 +612,7 @@ void enqueue_pass_begin(pic_ctx *c, hipStream_t s)
     launch_init_red0(c->d_inst, c->t_plain, pt, s);
     if (!c->any_mg) return;
     launch_mg_down(c->d_inst, c->t_fine[0], 0, 1, 0, pt, s);
-    enqueue_vcycle_mid(c, s);
+    enqueue_vcycle_mid(c, false, s);
     launch_mg_up(c->d_inst, c->t_fine[0], 0, 0, pt, s);
 }
 
@@ -627,8 +627,9 @@ void enqueue_iters(pic_ctx *c, int K, bool first, hipStream_t s)
         launch_pupdate_Ap(c->d_inst, c->t_plain, k & 1, (first && k == 0) ? 1 : 0, pt, s);
         launch_update_red0(c->d_inst, c->t_plain, (k + 1) & 1, pt, s);
         if (!c->any_mg) continue;
-        launch_mg_down(c->d_inst, c->t_fine[0], 0, 2, k & 1, pt, s);
-        enqueue_vcycle_mid(c, s);
+        // the CG step; its reduction and stop test run in the coarse kernel
+        launch_mg_down(c->d_inst, c->t_fine[0], 0, 3, k & 1, pt, s);
+        enqueue_vcycle_mid(c, true, s);
         launch_mg_up(c->d_inst, c->t_fine[0], 0, (k + 1) & 1, pt, s);
     }
 }
