@@ -68,6 +68,23 @@ def test_solve_matches_direct_solution(kind):
     pic.close()
 
 
+def test_solve_with_swept_coarsest_level_matches_direct_solution():
+    """A grid whose coarsest level (29 x 29: the periodic 58-node axis stops
+    the coarsening at once) is too large for the exact inverse, so red-black
+    sweeps solve it; the solution still reaches the direct one."""
+    w = synth.trench(nx=56, ny=58, width=6, depth=14, ppc=4, steps=5, seed=31)
+    parts = synth.load(w)
+    pic = make(w, parts, rtol=1e-12)
+    nc = oracle.node_cond(w)
+    rho = [oracle.deposit(w, parts[s]) for s in range(2)]
+    ref = oracle.solve_direct(w, nc, oracle.assemble(w, nc, rho[0], rho[1], 0.0))
+    info = pic.pic_solve(0)
+    assert info["converged"] and info["relres"] <= 1e-12
+    err = np.max(np.abs(pic.phi.cpu().numpy() - ref))
+    assert err <= 1e-6 * max(1.0, np.max(np.abs(ref))), err
+    pic.close()
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_one_push_bit_exact_on_identical_potential(kind):
     w = synth.workload_for_tests(kind)
