@@ -119,3 +119,46 @@ def test_paper_trench_hit_counts_match_oracle():
         for k in range(9):
             a, b = int(g[s, k]), int(o[s, k])
             assert abs(a - b) <= 5.0 * np.sqrt(a + b) + 5, (s, k, a, b)
+
+
+def test_batched_graph_steps_with_recycling_equal_each_instance_alone():
+    """A batch whose instances recycle ions or not (one recycling kernel
+    launch covers the recycling ones) gives, instance by instance, the same
+    integer charge, particles, counters and potential as the instance run
+    alone."""
+    from paper_1610_03918_amd import PicBatch
+    from gpu_util import live
+    ws = [synth.trench(nx=64, ny=32, width=4, depth=8, ppc=8, seed=41, rtol=1e-9),
+          synth.workload_for_tests("trench"),
+          synth.trench(nx=128, ny=64, width=12, depth=16, ppc=6, seed=42, rtol=1e-9)]
+    ws[0].recycle_rows = ws[0].box_i_top
+    ws[2].recycle_rows = ws[2].box_i_top // 2
+    parts = [synth.load(w) for w in ws]
+    steps = 20
+
+    def state(b, i):
+        return ([b.rho(i, s).cpu().numpy() for s in range(2)], b.phi(i).cpu().numpy(),
+                [canonical(live(b.particles_numpy(i, s))) for s in range(2)], b.pic_batch_diagnostics(i))
+
+    b = PicBatch(ws, parts, sort_interval=(4, 8))
+    b.start()
+    infos = b.pic_batch_step(steps, passes=3, iters=32)
+    assert all(x["converged"] for x in infos), infos
+    got = [state(b, i) for i in range(len(ws))]
+    b.close()
+    for i, w in enumerate(ws):
+        one = PicBatch([w], [parts[i]], sort_interval=(4, 8))
+        one.start()
+        assert one.pic_batch_step(steps, passes=3, iters=32)[0]["converged"]
+        rho, phi, prt, d = state(one, 0)
+        one.close()
+        for s in range(2):
+            assert np.array_equal(got[i][0][s], rho[s])
+            assert np.array_equal(got[i][2][s], prt[s])
+        assert np.array_equal(got[i][1], phi)
+        assert got[i][3]["tally"] == d["tally"] and got[i][3]["alive"] == d["alive"]
+        n_ion = parts[i][1]["cell"].size
+        if w.recycle_rows:
+            assert sum(d["tally"][1][:8]) > 0, "no ion was recycled"
+            assert d["alive"][1] == n_ion - d["tally"][1][8]
+            assert got[i][2][1].shape[0] == d["alive"][1]
