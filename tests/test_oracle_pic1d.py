@@ -107,3 +107,23 @@ def test_2d_oracle_on_replicated_load_equals_1d():
     assert one.lost[0].min() > 0
     assert two.tally[0][:2].tolist() == [w.ny * one.lost[0][1], w.ny * one.lost[0][0]]
     assert math.isfinite(scale)
+
+
+def test_recycling_keeps_ion_count_and_draws_thermal_ions():
+    """Ions lost at a plate come back at uniform positions in [0, recycle_len)
+    with Gaussian velocities of the given deviation; electrons are not
+    recycled."""
+    L, n = 20, 4000
+    rng = np.random.default_rng(5)
+    xe, xi = rng.random(n) * L, rng.random(n) * L
+    ve = rng.standard_normal(n)
+    vi = np.where(rng.random(n) < 0.5, -1.0, 1.0) * 50.0       # 25 cells in one step: every ion leaves
+    sim = pic1d.Slab1D(L, 0.5, 0.0, [(-1.0, -1, xe, ve), (0.0, 1, xi, vi)], amp=0.0, omega=0.0,
+                       recycle_len=8.0, recycle_vth=0.25, recycle_species=1, seed=3)
+    sim.step()
+    assert sim.x[1].size == n and sim.x[0].size < n
+    lost = int(sim.lost[1].sum())
+    assert lost == n
+    assert np.all((sim.x[1] >= 0) & (sim.x[1] < 8.0))
+    assert abs(sim.x[1].mean() - 4.0) < 0.2
+    assert abs(sim.v[1].std() / 0.25 - 1.0) < 0.05 and abs(sim.v[1].mean()) < 0.02
