@@ -8,6 +8,8 @@
 * Field and gather of a linear potential give its constant field.
 * Free streaming with no field: positions advance by v dt and particles
   past a plate are counted at that plate.
+* Recycling: every ion lost comes back inside the recycling length with a
+  Gaussian velocity of the given deviation; electrons are not recycled.
 * A 2D oracle run on a load that repeats one 1D load in every column (v_y = 0)
   keeps a y-independent potential and moves every copy as the 1D oracle
   moves the original: the equivalence the paper states for the slab.  The
