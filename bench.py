@@ -334,6 +334,52 @@ def run_trench_study(args):
           flush=True)
 
 
+def run_trench_study_batched(args):
+    """The three trench runs of Sec. III.C-D advanced together as one batch:
+    every launch covers the three instances and the steps replay as captured
+    graphs with a fixed solver schedule (per-instance early exit).  Bottom and
+    sidewall counts from the tallies over the same windows as the one-run-at-
+    a-time study, and the time per step of the three together."""
+    import torch
+
+    import synth
+    from paper_1610_03918_amd import PicBatch, autotune
+    cases = ((15, False, 600), (4, False, 600), (15, True, 700))
+    ws = [synth.paper_trench(wd, ch, seed=args.study_seed) for wd, ch, _ in cases]
+    b = PicBatch(ws, [synth.load(w) for w in ws])
+    b.start()
+    warm = 200
+    passes, iters, later = autotune.solver_schedule(b, warm)      # eager steps 0 .. warm-1
+    tallies = {}
+    step = warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    converged = True
+    for target in (6000, 7000, ws[0].steps):
+        infos = b.pic_batch_step(target - step, passes, iters, later)
+        converged = converged and all(x["converged"] for x in infos)
+        step = target
+        tallies[target] = [b.pic_batch_diagnostics(i)["tally"][1] for i in range(b.n)]
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / (step - warm)
+    b.close()
+    rows = []
+    for i, (w, (_, _, t_from)) in enumerate(zip(ws, cases)):
+        k_from = int(round(t_from / w.dt))
+        a, z = tallies[k_from][i], tallies[w.steps][i]
+        nb, ns = z[4] - a[4], (z[6] + z[7]) - (a[6] + a[7])
+        pb, ps = PAPER_TRENCH_COUNTS[w.name]
+        rows.append({"workload": w.name, "t_from": t_from, "n_bottom": int(nb), "n_sidewalls": int(ns),
+                     "ratio": ns / max(nb, 1), "paper_ratio": round(ps / pb, 2)})
+        log(f"{w.name:26s} bottom {nb:6d} sidewalls {ns:6d} ratio {ns / max(nb, 1):.2f} (paper {ps / pb:.2f})")
+    log(f"batched: {ms:.3f} ms per step of the three instances")
+    print(json.dumps({"metric": "ions reaching the trench bottom and sidewalls (Sec. III.C-D), batched",
+                      "n_gpus": 1, "data": "synthetic", "seed": args.study_seed,
+                      "ms_per_step_three_instances": ms, "all_converged": converged,
+                      "solver_schedule": {"passes": passes, "iters_first": iters, "iters_later": later},
+                      "results": rows}), flush=True)
+
+
 def run_sweep(args):
     """The 16-width trench sweep advanced as one batch with captured graphs."""
     import torch
@@ -436,6 +482,7 @@ def main():
     ap.add_argument("--trench-study", action="store_true",
                     help="the paper's trench runs: bottom and sidewall ion counts")
     ap.add_argument("--study-seed", type=int, default=5)
+    ap.add_argument("--batched", action="store_true", help="with --trench-study: the three runs as one batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sort", default="8,64")
@@ -468,7 +515,7 @@ def main():
     if args.solvers:
         return run_solvers(args)
     if args.trench_study:
-        return run_trench_study(args)
+        return run_trench_study_batched(args) if args.batched else run_trench_study(args)
 
     import numpy as np
     import torch
