@@ -77,3 +77,20 @@ def test_workspace_size_and_validation():
     assert _ws(cfgb, [10, 10])[0] == -1
     cfgc, ccc = make_config(w, chunk=100)
     assert _ws(cfgc, [10, 10])[0] == -1
+
+
+def test_recycling_config_validation():
+    """Ion recycling needs bulk rows inside the grid that hold no solid cell
+    and a non-negative thermal speed; the paper's trench passes."""
+    from paper_1610_03918_amd.pic import make_config
+    w = synth.paper_trench(15)
+    cap = [w.n_particles(0), w.n_particles(1)]
+    cfg, cc = make_config(w)
+    assert cfg.recycle_rows == 60 and _ws(cfg, cap)[0] == 0
+    for rows in (61, w.nx + 1, -1):           # rows into the electrode, past the grid, negative
+        bad, cc2 = make_config(w)
+        bad.recycle_rows = rows
+        assert _ws(bad, cap)[0] == -1, rows
+    bad, cc3 = make_config(w)
+    bad.recycle_vth = -0.1
+    assert _ws(bad, cap)[0] == -1
