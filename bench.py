@@ -323,6 +323,10 @@ def run_trench_study(args):
                "hits_logged_in_window": int(h.size), "hits_total": int(d["hits_logged"]),
                "mean_angle_bottom_deg": float(ang[cls == 4].mean()) if np.any(cls == 4) else None,
                "mean_angle_sidewall_deg": float(ang[side].mean()) if np.any(side) else None,
+               # impact angle from the surface normal in 10-degree bins (Fig. 5-7(b)): bottom hits
+               # against |atan(v_y / v_x)|, sidewall hits against |atan(v_x / v_y)|
+               "angle_hist_bottom_10deg": np.histogram(ang[cls == 4], bins=9, range=(0, 90))[0].tolist(),
+               "angle_hist_sidewall_10deg": np.histogram(90.0 - ang[side], bins=9, range=(0, 90))[0].tolist(),
                "electrons_alive": d["alive"][0], "ions_alive": d["alive"][1],
                "ms_per_step": 1e3 * secs / w.steps, "cumulative_t_bottom_side": curve}
         rows.append(row)
