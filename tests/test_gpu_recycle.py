@@ -93,15 +93,17 @@ def test_run_keeps_ion_count():
     pic.close()
 
 
-def test_paper_trench_hit_counts_match_oracle():
-    """The wide trench at the paper's parameters (Sec. III.C: 80 x 30 cells,
-    100 particles per cell, ions recycled) run 1500 steps on both sides.  The
+@pytest.mark.parametrize("width,charged", [(15, False), (4, False), (15, True)])
+def test_paper_trench_hit_counts_match_oracle(width, charged):
+    """The paper's trench runs (Sec. III.C-D: 80 x 30 cells, 100 particles per
+    cell, ions recycled; widths 15 and 4, and 15 with the static charge on
+    its bottom) run 1500 steps on both sides.  The
     trajectories part ways within a few hundred steps (float32 rounding of
     the field, a CG against a direct solve), so the comparison is of the hit
     counts per class, each a sum of many nearly independent events: within
     five Poisson standard deviations (runs that differ only in their seed
     differ by about one)."""
-    w = synth.paper_trench(15, seed=5)
+    w = synth.paper_trench(width, charged, seed=5)
     parts = synth.load(w)
     steps = 1500
     pic = _make(w, parts)
@@ -114,7 +116,7 @@ def test_paper_trench_hit_counts_match_oracle():
     for _ in range(steps):
         sim.step()
     o = sim.tally
-    assert g[1, 4] > 1000 and g[1, 6] + g[1, 7] > 1000
+    assert g[1, 4] > 100 and g[1, 6] + g[1, 7] > 1000
     for s in range(2):
         for k in range(9):
             a, b = int(g[s, k]), int(o[s, k])
