@@ -9,6 +9,7 @@ the exact discrete solution up to rounding.
 
 Functions and the passages they follow:
   node_cond      Dirichlet nodes from the conductor map        Sec. II, III.A, III.C
+  voltages       conductor potentials V_k(t)                   Sec. III.B
   deposit        area weighting, integer fixed point            (weighting not stated; see readings)
   assemble       source of eq. (5) plus Dirichlet lifts          eq. (5), Sec. III.D
   solve_direct   exact solution of the 5-point system           eq. (5)
@@ -117,11 +118,24 @@ def deposit(w, p: dict, rho: np.ndarray | None = None) -> np.ndarray:
     return rho
 
 
+def voltages(w, t: float) -> np.ndarray:
+    """Conductor potentials V_k(t) = amp_k sin(omega_k t) (Sec. III.B: the
+    RF electrode's sinusoidal bias; amplitude 0 for grounded conductors),
+    float64[8] indexed by conductor id, with the host's libm sin."""
+    import math
+    v = np.zeros(8, dtype=np.float64)
+    for k in range(1, 8):
+        a = float(w.v_amp[k])
+        if a != 0.0:
+            v[k] = a * math.sin(float(w.v_omega[k]) * t)
+    return v
+
+
 def assemble(w, nc, rho_e, rho_i, t: float, surf=None) -> np.ndarray:
     """float64 (NX, NY) right-hand side; Dirichlet nodes carry V(t).
     Fully periodic grids get the mean removed (gauge: mean(phi) = 0)."""
     b = np.zeros((w.NX, w.NY), np.float64)
-    V = w.voltages(t)
+    V = voltages(w, t)
     if surf is None:
         surf = np.zeros(w.ny, np.int64)
     lib().or_assemble(w.nx, w.ny, int(w.periodic_x), int(w.periodic_y), _p(_c(nc, np.uint8)),

@@ -88,15 +88,6 @@ class Workload:
     def n_particles(self, s: int) -> int:
         return self.plasma_cells() * self.species[s].ppc
 
-    def voltages(self, t: float) -> np.ndarray:
-        """Conductor potentials at time t, float64[MAX_COND] (host libm sin)."""
-        v = np.zeros(MAX_COND, dtype=np.float64)
-        for k in range(1, MAX_COND):
-            a = float(self.v_amp[k])
-            if a != 0.0:
-                v[k] = a * math.sin(float(self.v_omega[k]) * t)
-        return v
-
 
 def _species(mass_ratio: float, temp_ratio: float, ppc: int, ion_alpha=None):
     ion_a = (1.0 / mass_ratio) if ion_alpha is None else ion_alpha

@@ -58,7 +58,7 @@ def test_batch_init_deposit_matches_oracle():
         b.pic_push()
     for i, w in enumerate(ws):
         nc = oracle.node_cond(w)
-        V = w.voltages(3 * w.dt)
+        V = oracle.voltages(w, 3 * w.dt)
         got = b.b(i).cpu().numpy()
         assert np.array_equal(got[nc != 0], V[nc[nc != 0]])
         if w.v_amp[2]:

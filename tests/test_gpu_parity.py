@@ -92,7 +92,7 @@ def test_one_push_bit_exact_on_identical_potential(kind):
     pic = make(w, parts, rtol=1e-12)
     nc = oracle.node_cond(w)
     phi = synth.random_potential(w, 21, scale=4.0)
-    phi[nc != 0] = w.voltages(0.0)[nc[nc != 0]]
+    phi[nc != 0] = oracle.voltages(w, 0.0)[nc[nc != 0]]
     pic.phi.copy_(pic.torch.from_numpy(phi))
     pre = [pic.particles_numpy(s) for s in range(2)]
     pic.pic_push()

@@ -40,7 +40,7 @@ def test_one_push_with_recycling_matches_oracle():
     pic = _make(w, parts)
     nc = oracle.node_cond(w)
     phi = synth.random_potential(w, 33, scale=4.0)
-    phi[nc != 0] = w.voltages(0.0)[nc[nc != 0]]
+    phi[nc != 0] = oracle.voltages(w, 0.0)[nc[nc != 0]]
     pic.phi.copy_(pic.torch.from_numpy(phi))
     pic.pic_push()
     Ex, Ey = oracle.field(w, nc, phi)

@@ -117,7 +117,7 @@ def test_assemble_and_solve_satisfy_full_stencil(kind):
     t = 7.0
     b = oracle.assemble(w, nc, re, ri, t)
     phi = oracle.solve_direct(w, nc, b)
-    V = w.voltages(t)
+    V = oracle.voltages(w, t)
     fixed = nc != 0
     assert np.array_equal(phi[fixed], V[nc[fixed]])
     rho_bar = (ri - re).astype(np.float64) * w.weight / TWO32
@@ -188,3 +188,18 @@ def test_second_order_convergence_to_continuum():
         phi = oracle.solve_direct(w, nc, b)
         errs.append(np.max(np.abs(phi - ex)))
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+
+
+def test_conductor_potentials_follow_the_rf_bias():
+    """V(t) of the trench workload: the grounded plate stays at 0 and the RF
+    electrode (bottom plate and trench walls) follows 50 sin(0.05 t); the
+    paper-parameter trench runs use 5 sin(0.01 t) (Sec. III.B)."""
+    w = synth.trench(nx=32, ny=16, width=4, depth=8, ppc=1)
+    for t in (0.0, 0.1, 7.3, 31.4159, 1000.0):
+        V = oracle.voltages(w, t)
+        assert V.shape == (8,) and V[0] == 0.0 and V[1] == 0.0 and not V[3:].any()
+        assert abs(V[2] - 50.0 * np.sin(0.05 * t)) <= 1e-12 * 50.0
+    assert abs(oracle.voltages(w, 10 * np.pi)[2] - 50.0) < 1e-12    # quarter period: the crest
+    p = synth.paper_trench(15)
+    assert abs(oracle.voltages(p, 50 * np.pi)[2] - 5.0) < 1e-12
+    assert not oracle.voltages(synth.bounded_square(n=8, ppc=1), 3.0).any()

@@ -186,3 +186,79 @@ def test_forward_sensitivity_to_float32_sums():
             unet.conv3x3 = orig
         rel = np.linalg.norm(alt - ref) / np.linalg.norm(ref)
         assert 1e-5 < rel < 5e-3, rel
+
+
+def test_adam_two_steps_closed_form():
+    """Two Adam steps (Kingma & Ba 2015, Algorithm 1) written out by hand.
+    After step 1 the bias-corrected moments are exactly g1 and g1^2, so each
+    weight moves by lr * g1 / (|g1| + eps); after step 2 they are
+    (b1 g1 + g2) / (1 + b1) and (b2 g1^2 + g2^2) / (1 + b2).  A wrong
+    bias-correction power, a swapped beta or a missing square fails here."""
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    p0 = np.array([0.5, -1.25, 2.0, 0.0])
+    g1 = np.array([0.2, -0.4, 3.0, -1e-3])
+    g2 = np.array([-0.1, 0.3, 1.0, 5e-3])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    p1, m, v = unet.adam(p0, g1, m, v, 1, lr, b1, b2, eps)
+    want1 = p0 - lr * g1 / (np.abs(g1) + eps)
+    assert np.allclose(p1, want1, rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g1, rtol=1e-15) and np.allclose(v, 0.001 * g1 * g1, rtol=1e-12)
+    p2, m, v = unet.adam(p1, g2, m, v, 2, lr, b1, b2, eps)
+    mh = (0.9 * g1 + g2) / 1.9
+    vh = (0.999 * g1 * g1 + g2 * g2) / 1.999
+    want2 = p1 - lr * mh / (np.sqrt(vh) + eps)
+    assert np.allclose(p2, want2, rtol=1e-13, atol=1e-15)
+    # the first weight, by hand: step 1 moves it by 0.01 * 0.2 / (0.2 + 1e-8); then
+    # m^ = (0.18 - 0.1) / 1.9 and v^ = (0.03996 + 0.01) / 1.999
+    w0 = 0.5 - 0.002 / 0.20000001 - 0.01 * (0.08 / 1.9) / (np.sqrt(0.04996 / 1.999) + 1e-8)
+    assert abs(p2[0] - w0) < 1e-15
+
+
+# a 4 x 4 node grid: row 0 grounded (conductor 1), a 2-node RF conductor
+# (conductor 2) at (3, 2) and (3, 3), the other nodes free
+_NC = np.array([[1, 1, 1, 1],
+                [0, 0, 0, 0],
+                [0, 0, 0, 0],
+                [0, 0, 2, 2]], np.uint8)
+_B = np.array([[0.0, 0.0, 0.0, 0.0],        # Dirichlet values (ground)
+               [1.5, -2.0, 0.25, 3.0],      # source terms on free nodes
+               [-0.5, 0.125, 4.0, -1.0],
+               [2.0, -3.0, 7.5, 7.5]])      # 2 free, then the RF potential 7.5
+
+
+def test_features_on_a_hand_built_grid():
+    """Input channels of a 4 x 4 problem written out by hand: 0 the source
+    times s_rho on free nodes, 1 the free-node indicator, 2 the Dirichlet
+    value times s_v on conductor nodes; a swapped channel or a value written
+    on the wrong kind of node fails."""
+    x = unet.features(_B, _NC, 4, 4, s_rho=0.5, s_v=0.2)
+    want0 = np.array([[0, 0, 0, 0],
+                      [0.75, -1.0, 0.125, 1.5],
+                      [-0.25, 0.0625, 2.0, -0.5],
+                      [1.0, -1.5, 0, 0]])
+    want1 = np.array([[0, 0, 0, 0], [1, 1, 1, 1], [1, 1, 1, 1], [1, 1, 0, 0]], float)
+    want2 = np.zeros((4, 4))
+    want2[3, 2] = want2[3, 3] = unet.bf16(1.5)      # 7.5 * 0.2 rounded to bfloat16
+    assert np.array_equal(x[..., 0], want0)
+    assert np.array_equal(x[..., 1], want1)
+    assert np.array_equal(x[..., 2], want2)
+    # bfloat16 rounding of the scaled source: 1/3 is not representable
+    y = unet.features(_B / 3.0, _NC, 4, 4, s_rho=1.0, s_v=1.0)
+    assert y[1, 0, 0] == unet.bf16(0.5) and y[1, 1, 0] != -2.0 / 3.0
+    # a window smaller than the grid cuts rows and columns
+    assert unet.features(_B, _NC, 2, 2, 1.0, 1.0).shape == (2, 2, 3)
+
+
+def test_guess_on_a_hand_built_grid():
+    """Start potential from a network output on a 2 x 4 window of the 4 x 4
+    grid: output times s_phi on free window nodes, 0 on free nodes outside
+    the window, the Dirichlet value (b) on conductor nodes everywhere."""
+    out = np.array([[9.0, 9.0, 9.0, 9.0],
+                    [0.5, -1.0, 2.0, 0.25]])
+    g = unet.guess(out, _B, _NC, s_phi=4.0)
+    want = np.array([[0.0, 0.0, 0.0, 0.0],     # grounded row keeps b = 0, not 36
+                     [2.0, -4.0, 8.0, 1.0],
+                     [0.0, 0.0, 0.0, 0.0],     # free, outside the window
+                     [0.0, 0.0, 7.5, 7.5]])    # free outside the window; RF nodes keep b
+    assert np.array_equal(g, want)
