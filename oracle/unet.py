@@ -8,6 +8,10 @@ cross-correlations with zero padding.  ``quantize=True`` rounds inputs,
 weights and every stored activation to bfloat16 (round to nearest even), the
 storage precision of the device network, while all arithmetic stays float64.
 
+Residual learning (the start used by the solver): the network maps the
+residual of the linearly extrapolated potential to the correction of that
+start (``residual_sample`` / ``residual_guess``).
+
 Parameter order (one flat list):  for every 3x3 convolution in network
 order, its weight [Cout, 3, 3, Cin] then bias [Cout]; then the head weight
 [16] and head bias [1].
@@ -56,10 +60,21 @@ def init_params(seed: int = 100, in_ch: int = IN_CH):
     return ps
 
 
-def conv3x3(x, w, b):
+def _pad(x, periodic_w):
+    """One pixel of padding on each side: zeros along H; along W zeros, or
+    the image's own far columns when it wraps (circular padding)."""
     B, H, W, C = x.shape
     xp = np.zeros((B, H + 2, W + 2, C))
     xp[:, 1:-1, 1:-1] = x
+    if periodic_w:
+        xp[:, 1:-1, 0] = x[:, :, -1]
+        xp[:, 1:-1, -1] = x[:, :, 0]
+    return xp
+
+
+def conv3x3(x, w, b, periodic_w=False):
+    B, H, W, C = x.shape
+    xp = _pad(x, periodic_w)
     y = np.zeros((B, H, W, w.shape[0]))
     for dy in range(3):
         for dx in range(3):
@@ -67,18 +82,21 @@ def conv3x3(x, w, b):
     return y + b
 
 
-def conv3x3_grads(x, w, gy):
+def conv3x3_grads(x, w, gy, periodic_w=False):
     """Gradients of conv3x3 w.r.t. input, weight and bias."""
     B, H, W, C = x.shape
-    xp = np.zeros((B, H + 2, W + 2, C))
-    xp[:, 1:-1, 1:-1] = x
+    xp = _pad(x, periodic_w)
     gw = np.zeros_like(w)
     gxp = np.zeros_like(xp)
     for dy in range(3):
         for dx in range(3):
             gw[:, dy, dx, :] = np.tensordot(gy, xp[:, dy:dy + H, dx:dx + W], axes=([0, 1, 2], [0, 1, 2]))
             gxp[:, dy:dy + H, dx:dx + W] += np.tensordot(gy, w[:, dy, dx, :], axes=([3], [0]))
-    return gxp[:, 1:-1, 1:-1], gw, gy.sum(axis=(0, 1, 2))
+    gx = gxp[:, 1:-1, 1:-1].copy()
+    if periodic_w:                       # the padding columns are the far columns
+        gx[:, :, -1] += gxp[:, 1:-1, 0]
+        gx[:, :, 0] += gxp[:, 1:-1, -1]
+    return gx, gw, gy.sum(axis=(0, 1, 2))
 
 
 def pool(x):
@@ -99,11 +117,12 @@ def up_grad(gy):
     return gy.reshape(B, H // 2, 2, W // 2, 2, C).sum(axis=(2, 4))
 
 
-def forward(params, x, quantize=False):
-    """Returns (output [B,H,W], cache for backward)."""
+def forward(params, x, quantize=False, periodic_w=False):
+    """Returns (output [B,H,W], cache for backward).  periodic_w: every
+    convolution pads circularly along W (an image that wraps in W)."""
     q = bf16 if quantize else (lambda a: np.asarray(a, np.float64))
     P = [q(p) if i < len(params) - 2 else np.asarray(p, np.float64) for i, p in enumerate(params)]
-    cache = {"P": P, "acts": []}
+    cache = {"P": P, "acts": [], "periodic_w": periodic_w}
     h = q(x)
     k = 0
     skips = []
@@ -111,7 +130,7 @@ def forward(params, x, quantize=False):
     for lev in range(len(CH)):
         for _ in range(2):
             inp = h
-            h = q(np.maximum(conv3x3(inp, P[2 * k], P[2 * k + 1]), 0.0))
+            h = q(np.maximum(conv3x3(inp, P[2 * k], P[2 * k + 1], periodic_w), 0.0))
             cache["acts"].append((inp, h))
             k += 1
         if lev < len(CH) - 1:
@@ -122,7 +141,7 @@ def forward(params, x, quantize=False):
         h = np.concatenate([up(h), skips[lev]], axis=3)
         for _ in range(2):
             inp = h
-            h = q(np.maximum(conv3x3(inp, P[2 * k], P[2 * k + 1]), 0.0))
+            h = q(np.maximum(conv3x3(inp, P[2 * k], P[2 * k + 1], periodic_w), 0.0))
             cache["acts"].append((inp, h))
             k += 1
     out = h @ P[-2] + P[-1][0]
@@ -133,6 +152,7 @@ def forward(params, x, quantize=False):
 def backward(cache, gout):
     """Gradients (same order as the parameters) and the input gradient."""
     P = cache["P"]
+    pw = cache.get("periodic_w", False)
     grads = [None] * len(P)
     h = cache["last"]
     grads[-2] = np.tensordot(gout, h, axes=([0, 1, 2], [0, 1, 2]))
@@ -146,7 +166,7 @@ def backward(cache, gout):
         for _ in range(2):
             inp, out = cache["acts"][k]
             gy = g * (out > 0)
-            gx, grads[2 * k], grads[2 * k + 1] = conv3x3_grads(inp, P[2 * k], gy)
+            gx, grads[2 * k], grads[2 * k + 1] = conv3x3_grads(inp, P[2 * k], gy, pw)
             g = gx
             k -= 1
         cu = g.shape[3] - CH[lev]
@@ -158,7 +178,7 @@ def backward(cache, gout):
         for _ in range(2):
             inp, out = cache["acts"][k]
             gy = g * (out > 0)
-            gx, grads[2 * k], grads[2 * k + 1] = conv3x3_grads(inp, P[2 * k], gy)
+            gx, grads[2 * k], grads[2 * k + 1] = conv3x3_grads(inp, P[2 * k], gy, pw)
             g = gx
             k -= 1
     assert k == -1 and ne == 2 * len(CH)
@@ -200,3 +220,71 @@ def guess(out, b, node_cond, s_phi):
     g = np.zeros(b.shape)
     g[:H, :W] = out * s_phi
     return np.where(node_cond != 0, b, g)
+
+
+# ---------------------------------------------------------------------------
+# residual learning: the network corrects the linear extrapolation in time of
+# the potential (the warm start of the plain solver) from the residual of
+# that start
+# ---------------------------------------------------------------------------
+
+def extrapolated(phi_1, phi_2):
+    """Start potential 2 phi_1 - phi_2 from the two previous solutions (phi_1
+    alone when phi_2 is None)."""
+    return np.asarray(phi_1, np.float64).copy() if phi_2 is None else 2.0 * phi_1 - phi_2
+
+
+def masked_residual(b, phi, node_cond, periodic):
+    """r = b - A phi on the free nodes (0 elsewhere) of the 5-point system of
+    eq. (5): A phi = 4 phi minus the free neighbours, the Dirichlet
+    neighbours' potentials being part of b; neighbours wrap on a periodic
+    axis (periodic = (x, y)); a free node never lies on a bounded edge."""
+    NX, NY = b.shape
+    free = node_cond == 0
+    r = np.zeros((NX, NY))
+    for i in range(NX):
+        for j in range(NY):
+            if not free[i, j]:
+                continue
+            s = 4.0 * phi[i, j]
+            for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                a, c = i + di, j + dj
+                if periodic[0]:
+                    a %= NX
+                if periodic[1]:
+                    c %= NY
+                if 0 <= a < NX and 0 <= c < NY and free[a, c]:
+                    s -= phi[a, c]
+            r[i, j] = b[i, j] - s
+    return r
+
+
+def residual_sample(b, phi_1, phi_2, phi_t, node_cond, H, W, periodic, s_r, s_v, s_d):
+    """Training sample of the residual-learning start on the H x W window:
+    input [H, W, 3] = (r s_r on free nodes, free-node indicator, Dirichlet
+    value s_v on conductor nodes) with r the residual of the extrapolated
+    start, and target [H, W] = (phi_t - start) s_d on free nodes (None
+    without phi_t); both rounded to bfloat16, the stored precision."""
+    start = extrapolated(phi_1, phi_2)
+    r = masked_residual(b, start, node_cond, periodic)
+    free = node_cond[:H, :W] == 0
+    x = np.zeros((H, W, 3))
+    x[..., 0] = np.where(free, bf16(r[:H, :W] * s_r), 0.0)
+    x[..., 1] = free
+    x[..., 2] = np.where(free, 0.0, bf16(b[:H, :W] * s_v))
+    t = None
+    if phi_t is not None:
+        t = np.where(free, bf16((phi_t[:H, :W] - start[:H, :W]) * s_d), 0.0)
+    return x, t
+
+
+def residual_guess(out, phi_1, phi_2, node_cond, s_d, use_output=True):
+    """Start potential: the extrapolated start plus out / s_d on the free
+    nodes of the network window (use_output False: the extrapolation
+    alone)."""
+    g = extrapolated(phi_1, phi_2)
+    if use_output:
+        H, W = out.shape
+        free = node_cond[:H, :W] == 0
+        g[:H, :W] = np.where(free, g[:H, :W] + out / s_d, g[:H, :W])
+    return g

@@ -172,8 +172,8 @@ def test_forward_sensitivity_to_float32_sums():
     orig = unet.conv3x3
     noise = np.random.default_rng(1)
 
-    def conv32(x, w, b):
-        y = orig(x, w, b).astype(np.float32)
+    def conv32(x, w, b, periodic_w=False):
+        y = orig(x, w, b, periodic_w).astype(np.float32)
         return (y * (1 + noise.standard_normal(y.shape).astype(np.float32) * 3e-7)).astype(np.float64)
 
     for shape in [(2, 16, 24, 3), (1, 64, 48, 3)]:
@@ -262,3 +262,136 @@ def test_guess_on_a_hand_built_grid():
                      [0.0, 0.0, 0.0, 0.0],     # free, outside the window
                      [0.0, 0.0, 7.5, 7.5]])    # free outside the window; RF nodes keep b
     assert np.array_equal(g, want)
+
+
+def test_periodic_convolution_matches_scipy_wrap():
+    """Circular padding along W: SciPy's correlate2d with wrapped boundaries
+    on an image given one zero row above and below (zero padding along H),
+    cropped back; and a shift of the input along W shifts the output."""
+    r = _rng(11)
+    B, H, W, C, Co = 1, 6, 10, 3, 4
+    x = r.standard_normal((B, H, W, C))
+    w = r.standard_normal((Co, 3, 3, C))
+    b = r.standard_normal(Co)
+    y = unet.conv3x3(x, w, b, periodic_w=True)
+    for co in range(Co):
+        ref = b[co]
+        for ci in range(C):
+            xz = np.zeros((H + 2, W))
+            xz[1:-1] = x[0, :, :, ci]
+            ref = ref + scipy.signal.correlate2d(xz, w[co, :, :, ci], mode="same", boundary="wrap")[1:-1]
+        assert np.allclose(y[0, :, :, co], ref, rtol=1e-12, atol=1e-12)
+    ys = unet.conv3x3(np.roll(x, 3, axis=2), w, b, periodic_w=True)
+    assert np.allclose(ys, np.roll(y, 3, axis=2), rtol=1e-12, atol=1e-12)
+    # zero padding differs from it at the first and last columns only
+    y0 = unet.conv3x3(x, w, b)
+    assert np.allclose(y0[:, :, 1:-1], y[:, :, 1:-1]) and not np.allclose(y0[:, :, 0], y[:, :, 0])
+
+
+def test_periodic_network_is_shift_equivariant_and_its_backward_matches_differences():
+    """The whole network with circular padding along W commutes with shifts
+    of the image by multiples of 8 pixels (the pooling blocks of three
+    levels); its backward pass matches central differences."""
+    r = _rng(12)
+    ps = [p.astype(np.float64) for p in unet.init_params(seed=4)]
+    for k in range(1, len(ps), 2):
+        ps[k] = r.standard_normal(ps[k].shape) * 0.1
+    x = r.standard_normal((1, 16, 32, 3))
+    out, _ = unet.forward(ps, x, periodic_w=True)
+    outs, _ = unet.forward(ps, np.roll(x, 8, axis=2), periodic_w=True)
+    assert np.allclose(outs, np.roll(out, 8, axis=2), rtol=1e-11, atol=1e-11)
+    out0, _ = unet.forward(ps, x)
+    assert not np.allclose(out0, out)
+    c = r.standard_normal((1, 16, 32))
+    out, cache = unet.forward(ps, x, periodic_w=True)
+    grads, gx = unet.backward(cache, c)
+    h = 1e-6
+    for pi in (0, 7, 16, 26, 28):
+        flat = ps[pi].reshape(-1)
+        for idx in r.choice(flat.size, size=3, replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = (unet.forward(ps, x, periodic_w=True)[0] * c).sum()
+            flat[idx] = old - h
+            lm = (unet.forward(ps, x, periodic_w=True)[0] * c).sum()
+            flat[idx] = old
+            g = grads[pi].reshape(-1)[idx]
+            assert abs((lp - lm) / (2 * h) - g) <= 1e-6 * max(1.0, abs(g)), (pi, idx)
+    # input gradient at the wrapped columns
+    for (hh, ww) in ((3, 0), (9, 31), (5, 16)):
+        xp = x.copy()
+        xp[0, hh, ww, 0] += h
+        lp = (unet.forward(ps, xp, periodic_w=True)[0] * c).sum()
+        xp[0, hh, ww, 0] -= 2 * h
+        lm = (unet.forward(ps, xp, periodic_w=True)[0] * c).sum()
+        assert abs((lp - lm) / (2 * h) - gx[0, hh, ww, 0]) <= 1e-6
+
+
+def _trench_problem():
+    """A small y-periodic trench potential problem: its node map, a random
+    charge, and two earlier potentials."""
+    import oracle
+    import synth
+    w = synth.trench(nx=16, ny=8, width=2, depth=4, ppc=1)
+    nc = oracle.node_cond(w)
+    r = _rng(13)
+    ri = r.integers(0, 9 << 32, (w.NX, w.NY), dtype=np.int64)
+    re = r.integers(0, 9 << 32, (w.NX, w.NY), dtype=np.int64)
+    b = oracle.assemble(w, nc, re, ri, 3.0)
+    return w, nc, b
+
+
+def test_residual_of_the_exact_solution_is_zero_and_of_zero_is_the_source():
+    """The residual of the masked 5-point system: zero for the exact
+    solution of eq. (5) (direct solver), b on free nodes for a zero start,
+    and by hand for a start that is 1 on one free node (4 there, -1 on each
+    free neighbour, across the periodic seam too)."""
+    import oracle
+    w, nc, b = _trench_problem()
+    phi = oracle.solve_direct(w, nc, b)
+    per = (bool(w.periodic_x), bool(w.periodic_y))
+    r = unet.masked_residual(b, phi, nc, per)
+    assert np.max(np.abs(r)) < 1e-10 * np.max(np.abs(b))
+    r0 = unet.masked_residual(b, np.zeros_like(b), nc, per)
+    assert np.array_equal(r0, np.where(nc == 0, b, 0.0))
+    e = np.zeros_like(b)
+    e[5, 0] = 1.0                                     # free node on the periodic seam
+    assert nc[5, 0] == 0 and nc[4, 0] == 0 and nc[6, 0] == 0 and nc[5, w.NY - 1] == 0
+    re_ = unet.masked_residual(np.zeros_like(b), e, nc, per)
+    want = np.zeros_like(b)
+    want[5, 0] = -4.0
+    want[4, 0] = want[6, 0] = want[5, 1] = want[5, w.NY - 1] = 1.0
+    assert np.array_equal(re_, want)
+
+
+def test_residual_sample_and_guess_by_hand():
+    """Sample of the residual-learning start: the input holds the scaled
+    residual of 2 phi_1 - phi_2 (bfloat16), the free-node indicator and the
+    scaled Dirichlet values; the target is the scaled gap to phi_t; the
+    guess adds out / s_d to the extrapolation on free window nodes only."""
+    import oracle
+    w, nc, b = _trench_problem()
+    per = (False, True)
+    exact = oracle.solve_direct(w, nc, b)
+    r = _rng(14)
+    phi_1 = exact + 0.01 * r.standard_normal(exact.shape)
+    phi_2 = exact + 0.02 * r.standard_normal(exact.shape)
+    H, W = 16, 8
+    x, t = unet.residual_sample(b, phi_1, phi_2, exact, nc, H, W, per, 2.0, 0.5, 8.0)
+    start = 2.0 * phi_1 - phi_2
+    res = unet.masked_residual(b, start, nc, per)
+    free = nc[:H, :W] == 0
+    assert np.array_equal(x[..., 0], np.where(free, unet.bf16(2.0 * res[:H, :W]), 0.0))
+    assert np.array_equal(x[..., 1], free.astype(float))
+    assert np.array_equal(x[..., 2], np.where(free, 0.0, unet.bf16(0.5 * b[:H, :W])))
+    assert np.array_equal(t, np.where(free, unet.bf16(8.0 * (exact - start)[:H, :W]), 0.0))
+    # the target that reaches the exact solution, fed back through the guess
+    g = unet.residual_guess(8.0 * (exact - start)[:H, :W], phi_1, phi_2, nc, 8.0)
+    assert np.allclose(g[:H][free], exact[:H][free], rtol=0, atol=1e-12)
+    assert np.array_equal(g[H:], start[H:])                       # outside the window: the extrapolation
+    assert np.array_equal(g[:H][~free], start[:H][~free])         # Dirichlet nodes untouched
+    g0 = unet.residual_guess(np.ones((H, W)), phi_1, phi_2, nc, 8.0, use_output=False)
+    assert np.array_equal(g0, start)
+    # no earlier pair: the start is phi_1
+    x1, _ = unet.residual_sample(b, exact, None, None, nc, H, W, per, 1.0, 1.0, 1.0)
+    assert np.max(np.abs(x1[..., 0])) < 1e-9 * np.max(np.abs(b))
