@@ -53,10 +53,23 @@ typedef enum {
     PIC_OK = 0,
     PIC_ERR_ARG = -1,            /* invalid configuration or argument */
     PIC_ERR_HIP = -3,            /* a HIP runtime call failed */
-    PIC_ERR_NOT_CONVERGED = -4,  /* solver hit max_iter; phi still written */
-    PIC_ERR_STATE = -7,          /* call out of order (e.g. step before init) */
+    PIC_ERR_NOT_CONVERGED = -4,  /* solver hit max_iter (phi still written), or a batched
+                                    step pushed a potential above rtol */
+    PIC_ERR_CFL = -5,            /* pic_init / pic_batch_init: omega_pe dt >= 2 at the loaded
+                                    mean electron density (the leapfrog of eqs. 1-4 is
+                                    unstable for the plasma oscillation) */
+    PIC_ERR_OVERFLOW = -6,       /* a capacity above 2^31 - 1 particles per species: the int64
+                                    fixed-point charge of a node (2^32 units per particle)
+                                    could overflow */
+    PIC_ERR_STATE = -7,          /* call out of order (e.g. step before init), or a device
+                                    error bit was seen; the context then refuses every call */
     PIC_ERR_CAPACITY = -8        /* particle count exceeds buffer capacity */
 } pic_status;
+/* Not an error: a particle that drifts farther from its tile than the
+ * deposit halo between two re-binnings adds its charge with global atomics
+ * instead of the tile's LDS window (same integers; counted in
+ * pic_diag.deposit_fallbacks).  Class-8 removals (non-finite or runaway
+ * displacements) are tallied, not reported as errors. */
 
 #define PIC_MAX_COND 8           /* conductor ids 1..7; 0 = plasma / free */
 #define PIC_NCLASS 9             /* hit classes, see pic_diag */
@@ -129,6 +142,10 @@ typedef struct {
     int32_t iterations_first;    /* of those, the iterations of the first refinement pass */
     double relres0;              /* relative residual of the start */
     double relres;               /* final relative residual (float64) */
+    int32_t unconverged_pushes;  /* since pic_init: pushes whose potential had not met rtol
+                                    (its last residual test failed) */
+    int32_t pad;
+    double worst_relres;         /* the largest relative residual among those pushes (0 if none) */
 } pic_solve_info;
 
 typedef struct {
@@ -179,8 +196,10 @@ pic_status pic_deposit(pic_ctx *ctx);
 /* Solves eq. (5) for phi from b.  guess_kind 0: start from zero on the free
  * nodes; 1: from the current phi (previous step); 2: from the device float64
  * array guess (NX*NY, free nodes used); 3: from 2 phi - phi_prev, the linear
- * extrapolation of the last two kind-3 solutions (the current phi on the first
- * call).  Waits for the stream.  info may be NULL.  Returns
+ * extrapolation of the last two kind-3 or kind-4 solutions (the current phi
+ * on the first call); 4: from guess as kind 2, keeping the time history of
+ * kind 3 (the current phi becomes phi_prev first).  Kinds 2 and 4 need a
+ * single instance.  Waits for the stream.  info may be NULL.  Returns
  * PIC_ERR_NOT_CONVERGED (phi written) at max_iter. */
 pic_status pic_solve(pic_ctx *ctx, int32_t guess_kind, const double *guess, pic_solve_info *info);
 
@@ -256,14 +275,18 @@ pic_status pic_batch_init(int32_t n, const pic_config *cfgs, const pic_buffers *
                           void *workspace, size_t workspace_bytes, void *stream, pic_ctx **out);
 
 /* nsteps steps of every instance as captured HIP graphs, one launch per
- * re-binning period of species 0 (its sort_interval, or 8): each step solves
+ * re-binning period of species 0 (its sort_interval, or 8; at most 510
+ * steps, the device window of conductor potentials): each step solves
  * from the extrapolated potential with a fixed schedule of `passes`
  * float64 refinement passes, the first of `iters` preconditioned CG
  * iterations and the later ones of `iters_later` (0: `iters`), every
  * instance leaving the schedule as soon as it meets its rtol, then pushes.
- * Waits at the end; per-instance results in pic_batch_solve_info (converged
- * = 0 flags an instance the schedule was too short for).  If no earlier
- * extrapolated solve exists, the first step runs as pic_step(1). */
+ * Waits at the end; per-instance results in pic_batch_solve_info.  Returns
+ * PIC_ERR_NOT_CONVERGED (after all nsteps ran) when any step of any
+ * instance pushed a potential whose last residual test failed, i.e. the
+ * schedule was too short for it (pic_solve_info.unconverged_pushes counts
+ * them).  If no earlier extrapolated solve exists, the first step runs as
+ * pic_step(1).  nsteps = 0 does nothing. */
 pic_status pic_batch_step(pic_ctx *ctx, int32_t nsteps, int32_t passes, int32_t iters, int32_t iters_later);
 
 /* Per-instance counters, particle set and last solve (i in 0..n-1). */
@@ -279,6 +302,14 @@ pic_status pic_batch_solve_info(pic_ctx *ctx, int32_t i, pic_solve_info *out);
  * device work. */
 pic_status pic_node_map(pic_ctx *ctx, int32_t i, const uint8_t **node_cond, uint8_t *host_copy,
                         int32_t *NX, int32_t *NY);
+
+/* For tests of the error path only: what = 1 moves the device step counter
+ * past the window of conductor potentials, as a runtime that lost track of
+ * it would.  The next assembly (pic_push, pic_deposit) sets the device
+ * error bit instead of reading outside the table, the next call that looks
+ * at the device flags (pic_solve, pic_step, pic_batch_step,
+ * pic_diagnostics) returns PIC_ERR_STATE, and every later call does too. */
+pic_status pic_inject_fault(pic_ctx *ctx, int32_t what);
 
 void pic_destroy(pic_ctx *ctx);
 const char *pic_last_error(const pic_ctx *ctx);

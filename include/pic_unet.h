@@ -114,12 +114,69 @@ pic_status pic_unet_snapshot(pic_unet *u, int32_t slot, const double *b, const d
 pic_status pic_unet_guess(pic_unet *u, int32_t slot, const double *b, const uint8_t *node_cond,
                           int32_t NX, int32_t NY, float s_phi, double *guess);
 
-/* Learned start of instance 0 of ctx (batch slot 0 of u): snapshot of the
- * current right-hand side b (the caller's pic_buffers.b), forward pass,
- * guess into the caller's device scratch guess (NX*NY float64), then
- * pic_solve(ctx, 2, guess, info).  Waits (as pic_solve). */
+/* Learned start of instance 0 of ctx (batch slot 0 of u) that predicts phi
+ * itself: snapshot of the current right-hand side b (the caller's
+ * pic_buffers.b), forward pass, guess into the caller's device scratch
+ * guess (NX*NY float64), then pic_solve(ctx, 2, guess, info).  The
+ * network's stream first waits for the work queued on the context's
+ * stream.  Waits (as pic_solve).  (The residual form below is the one the
+ * solver uses.) */
 pic_status pic_solve_learned(pic_ctx *ctx, pic_unet *u, const double *b, float s_rho, float s_v,
                              float s_phi, double *guess, pic_solve_info *info);
+
+/* ---- residual learning: the start used with the plain solver ----------
+ * The network corrects the linear extrapolation in time of the potential,
+ * phi_s = 2 phi_1 - phi_2 (phi_1, phi_2 the solutions of the two previous
+ * steps; phi_1 alone when phi_2 is NULL), the start the solver already uses
+ * (pic_solve guess kind 3).  Input channels: 0 the residual r = b - A phi_s
+ * of eq. (5)'s 5-point system on free nodes times s_r, 1 the free-node
+ * indicator, 2 the Dirichlet value times s_v on conductor nodes.  Target:
+ * (phi - phi_s) s_d on free nodes.  The start is phi_s + output / s_d. */
+
+/* Circular padding of every convolution along W (periodic_w = 1) for a
+ * grid periodic along y whose node count NY equals the network's W; 0
+ * (the default) pads with zeros.  PIC_ERR_ARG for other values. */
+pic_status pic_unet_set_periodic(pic_unet *u, int32_t periodic_w);
+
+/* One training sample of the H x W window of a Poisson problem (no network
+ * needed): x (device bfloat16 [H][W][3]) receives the input channels above,
+ * t (device bfloat16 [H][W], or NULL) the target with phi_t the converged
+ * potential; stats (device float64[3], or NULL) accumulates, with atomics
+ * (so its last bits depend on the order of the blocks), the sums over the
+ * window's free nodes of r^2 and of (phi_t - phi_s)^2 and their count.
+ * b, phi_1, phi_2 (may be NULL), phi_t: device float64 NX x NY; node_cond:
+ * device NX x NY node map (0 free); periodic_x / periodic_y: the grid's
+ * periodic axes (neighbours wrap).  Enqueued on stream.  PIC_ERR_ARG for a
+ * window larger than the grid or a missing pointer. */
+pic_status pic_unet_residual_sample(const double *b, const double *phi_1, const double *phi_2,
+                                    const double *phi_t, const uint8_t *node_cond, int32_t NX, int32_t NY,
+                                    int32_t periodic_x, int32_t periodic_y, int32_t H, int32_t W, float s_r,
+                                    float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats,
+                                    void *stream);
+
+/* Copies a stored sample (x, t as written by pic_unet_residual_sample for
+ * this network's H x W) into batch slot `slot`: the input, and with t the
+ * training target (as float32) and the loss mask (the free-node channel). */
+pic_status pic_unet_load(pic_unet *u, int32_t slot, const uint16_t *x, const uint16_t *t);
+
+/* Writes guess (device float64 NX x NY): phi_s plus output(slot) / s_d on
+ * the free nodes of the H x W window (use_output = 0: phi_s alone, the plain
+ * extrapolation), phi_s on every other node - a start for pic_solve(ctx, 2
+ * or 4, guess, ...), which reads its free nodes only. */
+pic_status pic_unet_residual_guess(pic_unet *u, int32_t slot, const double *phi_1, const double *phi_2,
+                                   const uint8_t *node_cond, int32_t NX, int32_t NY, float s_d,
+                                   int32_t use_output, double *guess);
+
+/* Learned start of instance 0 of a running simulation ctx (batch slot 0 of
+ * u): the sample of the context's current b, its current potential (phi_1)
+ * and the solution before it (phi_2, when a kind-3 or kind-4 solve has run),
+ * a forward pass, the corrected start into the caller's device scratch
+ * guess (NX*NY float64), then pic_solve(ctx, 4, guess, info), which keeps
+ * the time history for the next extrapolation.  The network's stream first
+ * waits for the work queued on the context's stream.  Waits (as
+ * pic_solve). */
+pic_status pic_solve_learned_residual(pic_ctx *ctx, pic_unet *u, float s_r, float s_v, float s_d,
+                                      double *guess, pic_solve_info *info);
 
 /* HIP-event timing of pic_unet_forward on the library stream (default off);
  * average ms per forward pass since the last read, then reset. */

@@ -46,6 +46,7 @@ enum {
     S_CG_ALPHA,  // step length of the next CG step (multigrid-preconditioned form)
     S_CG_BETA,   // direction coefficient of the next CG step
     S_CG_GAMMA,  // r.z of the last V-cycle
+    S_WORST,     // largest relative residual of a potential that was pushed with unconverged
     S_NSCAL = 16
 };
 enum {
@@ -56,8 +57,14 @@ enum {
     F_ITER_TOT,  // inner iterations since the start of the solve
     F_PASSES,    // refinement passes since the start of the solve
     F_ITER1,     // inner iterations of the solve's first pass
-    F_NFLAG = 8
+    F_ERR,       // sticky device error bits (kErrVWindow)
+    F_UNCONV,    // sticky count of pushes whose potential had not met rtol
+    F_NFLAG = 12
 };
+
+// Device error bits (F_ERR): the assembly found the device step counter
+// outside the window of conductor potentials (it then reads row 0).
+constexpr int kErrVWindow = 1;
 
 struct LevelDev {
     int NX, NY;

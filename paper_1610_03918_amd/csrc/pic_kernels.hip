@@ -293,11 +293,20 @@ __device__ __forceinline__ float2 node_field(const Geom g, const uint8_t *nc, co
 }
 
 // One thread per cell; writes the cell's four corner fields (float32) and,
-// when requested, clears both species' node charge for the coming deposit.
+// when requested (the field of a push), clears both species' node charge for
+// the coming deposit.  The field of a push also counts, in F_UNCONV, a
+// potential whose last residual test failed, and keeps the largest such
+// relative residual in S_WORST (one thread per instance).
 __global__ void k_field(const Inst *insts, Tab t, int zero_rho)
 {
     GRID_BEGIN(t)
     const Geom g = I.g;
+    if (zero_rho && i == 0 && j == 0 && !I.F[F_CONV]) {
+        I.F[F_UNCONV] += 1;
+        const double bb = I.S[S_BB] > 0.0 ? I.S[S_BB] : 1.0;
+        const double rel = sqrt(I.S[S_RR64] / bb);
+        if (!(rel <= I.S[S_WORST])) I.S[S_WORST] = rel;
+    }
     if (zero_rho && i < g.NX && j < g.NY) {
         const long long n = (long long)i * g.NY + j;
         I.rho[0][n] = 0ull;
@@ -329,8 +338,9 @@ void launch_field(const Inst *I, const Tab &t, int zero_rho, hipStream_t s)
 
 // V: conductor potentials of every step of the table window, indexed
 // ((step - base) * ninst + instance) * 8 with the device step counter.
-// A window row outside [0, vwin) (never produced by the runtime) falls back
-// to row 0 rather than reading outside the table.
+// A window row outside [0, vwin) (the runtime never launches one) sets the
+// instance's kErrVWindow error bit, which the host reports as PIC_ERR_STATE
+// at its next look at the flags; the read itself stays inside the table.
 __global__ void k_assemble(const Inst *insts, Tab t, const double *Vtab, const long long *ctl,
                            int ninst, int vwin, Part pt)
 {
@@ -338,7 +348,10 @@ __global__ void k_assemble(const Inst *insts, Tab t, const double *Vtab, const l
     const Geom g = I.g;
     NODE_IDX(g.NX, g.NY)
     long long row = ctl[0] - ctl[1];
-    if (row < 0 || row >= vwin) row = 0;
+    if (row < 0 || row >= vwin) {
+        if (i == 0 && j == 0) I.F[F_ERR] |= kErrVWindow;
+        row = 0;
+    }
     const double *V = Vtab + (row * ninst + t.id[ku]) * 8;
     double bb = 0.0, sm = 0.0;
     if (inb) {

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/pic.h"
+#include "ctx_view.h"
 #include "pic_internal.h"
 
 using namespace pic;
@@ -53,6 +54,13 @@ bool coarsenable(int n, int periodic)
 
 int coarser(int n, int periodic) { return periodic ? n / 2 : (n + 1) / 2; }
 
+// Status of a validation message: PIC_ERR_OVERFLOW for the fixed-point
+// charge bound, PIC_ERR_ARG otherwise.
+pic_status validate_status(const std::string &v)
+{
+    return v.rfind("charge overflow", 0) == 0 ? PIC_ERR_OVERFLOW : PIC_ERR_ARG;
+}
+
 std::string validate(const pic_config *c, const int64_t *cap)
 {
     if (!c) return "null config";
@@ -85,8 +93,10 @@ std::string validate(const pic_config *c, const int64_t *cap)
     if (c->push_merge != 0 && c->push_merge != 2 && c->push_merge != 4)
         return "push_merge must be 0, 2 or 4";
     if (push_lds_bytes(tx, ty, H) > 64 * 1024) return "tile + halo window exceeds 64 KiB of LDS";
-    if (cap && (cap[0] < 0 || cap[1] < 0 || cap[0] > 0x7fffffffLL || cap[1] > 0x7fffffffLL))
-        return "capacity out of range";
+    if (cap && (cap[0] < 0 || cap[1] < 0)) return "capacity out of range";
+    if (cap && (cap[0] > 0x7fffffffLL || cap[1] > 0x7fffffffLL))
+        return "charge overflow: a capacity above 2^31 - 1 particles could exceed the int64 charge of a node "
+               "(2^32 units per particle)";
     if (c->hitlog_capacity < 0) return "hitlog_capacity must be >= 0";
     if (c->warm_start < 0 || c->warm_start > 1) return "warm_start must be 0 or 1";
     if (c->recycle_rows < 0 || c->recycle_rows > c->nx) return "recycle_rows must be in 0 .. nx";
@@ -244,6 +254,7 @@ constexpr int kContinueChunk = 64; // inner iterations per graph between stop te
 
 struct pic_ctx {
     int n = 0;
+    bool device_error = false;      // a device error bit was seen: every later call fails
     std::vector<InstHost> in;
     hipStream_t stream = nullptr;
     // shared device objects
@@ -718,6 +729,16 @@ pic_status read_flags(pic_ctx *c, std::vector<double> &S, std::vector<int> &F)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     memcpy(S.data(), c->h_flags, S.size() * sizeof(double));
     memcpy(F.data(), c->h_flags + ((char *)c->d_F - (char *)c->d_S), F.size() * sizeof(int));
+    for (int k = 0; k < c->n; k++) {
+        const int e = F[(size_t)k * F_NFLAG + F_ERR];
+        if (e) {
+            c->device_error = true;
+            char msg[160];
+            snprintf(msg, sizeof msg, "instance %d: device error bits 0x%x%s", k, e,
+                     (e & kErrVWindow) ? " (step counter outside the window of conductor potentials)" : "");
+            return fail(c, PIC_ERR_STATE, msg);
+        }
+    }
     return PIC_OK;
 }
 
@@ -734,13 +755,18 @@ void record_solve_info(pic_ctx *c, const std::vector<double> &S, const std::vect
         si.iterations_first = f[F_ITER1];
         si.relres0 = std::sqrt(s[S_RELRES0] / bb);
         si.relres = std::sqrt(s[S_RR64] / bb);
+        si.unconverged_pushes = f[F_UNCONV];
+        si.worst_relres = s[S_WORST];
     }
 }
 
 // Start of a solve: starting potential and the float64 residual.
 void enqueue_solve_start(pic_ctx *c, int kind, const double *guess, hipStream_t s)
 {
-    if (kind == 0 || kind == 2) launch_set_guess(c->d_inst, c->t_l0, kind, guess, s);
+    // kind 4 keeps the time history of kind 3 (the current solution becomes
+    // the previous one) and then starts from the caller's guess
+    if (kind == 4) launch_extrapolate(c->d_inst, c->t_l0, 0, s);
+    if (kind == 0 || kind == 2 || kind == 4) launch_set_guess(c->d_inst, c->t_l0, kind == 0 ? 0 : 2, guess, s);
     if (kind == 3) launch_extrapolate(c->d_inst, c->t_l0, c->have_prev ? 1 : 0, s);
     launch_pin_shift(c->d_inst, c->t_per, s);
     launch_resid64(c->d_inst, c->t_l0, 0, part_of(c), s);
@@ -783,7 +809,7 @@ pic_status run_sweep_chunk(pic_ctx *c, int count)
 pic_status do_sweep_solve(pic_ctx *c, int kind, const double *guess)
 {
     enqueue_solve_start(c, kind, guess, c->stream);
-    c->have_prev = (kind == 3);
+    c->have_prev = (kind == 3 || kind == 4);
     std::vector<double> S;
     std::vector<int> F;
     pic_status st = read_flags(c, S, F);
@@ -833,7 +859,7 @@ pic_status do_solve(pic_ctx *c, int kind, const double *guess)
 {
     if (c->sweep_solver) return do_sweep_solve(c, kind, guess);
     enqueue_solve_start(c, kind, guess, c->stream);
-    c->have_prev = (kind == 3);
+    c->have_prev = (kind == 3 || kind == 4);
     std::vector<double> S;
     std::vector<int> F;
     pic_status st = PIC_OK;
@@ -963,6 +989,7 @@ pic_status do_push(pic_ctx *c)
 pic_status check(pic_ctx *c)
 {
     if (!c || !c->d_inst) return fail(c, PIC_ERR_STATE, "not initialised");
+    if (c->device_error) return PIC_ERR_STATE;     // the message of the first report stays
     return PIC_OK;
 }
 
@@ -1238,7 +1265,22 @@ pic_status batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, vo
         caps[2 * k] = b->sp[0].capacity;
         caps[2 * k + 1] = b->sp[1].capacity;
         std::string v = validate(&cfgs[k], &caps[2 * k]);
-        if (!v.empty()) return fail(c, PIC_ERR_ARG, "instance " + std::to_string(k) + ": " + v);
+        if (!v.empty()) return fail(c, validate_status(v), "instance " + std::to_string(k) + ": " + v);
+        {
+            // leapfrog stability of the electron plasma oscillation at the loaded
+            // mean density n (omega_pe^2 = |alpha_e| n in the units of Sec. II):
+            // omega_pe dt must stay below 2
+            long long plasma = 0;
+            for (long long q = 0; q < (long long)cfgs[k].nx * cfgs[k].ny; q++) plasma += cfgs[k].cell_cond[q] == 0;
+            const double dens = plasma > 0 ? cfgs[k].weight * (double)b->sp[0].count / (double)plasma : 0.0;
+            const double wdt = cfgs[k].dt * std::sqrt(std::fabs(cfgs[k].alpha[0]) * dens);
+            if (!(wdt < 2.0)) {
+                char msg[160];
+                snprintf(msg, sizeof msg, "instance %d: omega_pe dt = %.3g at the loaded mean density: the leapfrog "
+                         "is unstable (needs < 2)", k, wdt);
+                return fail(c, PIC_ERR_CFL, msg);
+            }
+        }
         for (int s = 0; s < 2; s++) {
             if (b->sp[s].count < 0 || b->sp[s].count > b->sp[s].capacity)
                 return fail(c, PIC_ERR_CAPACITY, "particle count exceeds capacity");
@@ -1352,8 +1394,10 @@ pic_status pic_node_map(pic_ctx *ctx, int32_t i, const uint8_t **node_cond, uint
 pic_status pic_batch_workspace_size(int32_t n, const pic_config *cfgs, const int64_t *capacity, size_t *bytes)
 {
     if (n < 1 || n > kMaxInst || !cfgs || !capacity || !bytes) return PIC_ERR_ARG;
-    for (int k = 0; k < n; k++)
-        if (!validate(&cfgs[k], capacity + 2 * k).empty()) return PIC_ERR_ARG;
+    for (int k = 0; k < n; k++) {
+        std::string v = validate(&cfgs[k], capacity + 2 * k);
+        if (!v.empty()) return validate_status(v);
+    }
     *bytes = carve_all(nullptr, n, cfgs, capacity, nullptr);
     return PIC_OK;
 }
@@ -1391,8 +1435,8 @@ pic_status pic_deposit(pic_ctx *c)
 pic_status pic_solve(pic_ctx *c, int32_t guess_kind, const double *guess, pic_solve_info *info)
 {
     if (check(c) != PIC_OK) return PIC_ERR_STATE;
-    if (guess_kind < 0 || guess_kind > 3 || (guess_kind == 2 && (!guess || c->n != 1)))
-        return fail(c, PIC_ERR_ARG, "guess_kind must be 0, 1, 2 (one instance, with a guess array) or 3");
+    if (guess_kind < 0 || guess_kind > 4 || ((guess_kind == 2 || guess_kind == 4) && (!guess || c->n != 1)))
+        return fail(c, PIC_ERR_ARG, "guess_kind must be 0, 1, 2 or 4 (one instance, with a guess array) or 3");
     pic_status st = do_solve(c, guess_kind, guess);
     if (info) *info = c->in[0].last;
     return st;
@@ -1433,16 +1477,27 @@ pic_status pic_batch_step(pic_ctx *c, int32_t nsteps, int32_t passes, int32_t it
     if (nsteps < 0 || passes < 1 || passes > 8 || iters < 1 || iters > 128 || iters_later < 1 || iters_later > 128)
         return fail(c, PIC_ERR_ARG, "nsteps >= 0, passes in 1..8, iters and iters_later in 1..128");
     if (c->sweep_solver) return fail(c, PIC_ERR_ARG, "pic_batch_step needs the CG solvers (solver 0 or 1)");
+    if (nsteps == 0) return PIC_OK;
+    // pushes made so far with an unconverged potential (sticky device count)
+    std::vector<double> S;
+    std::vector<int> F;
+    pic_status st = read_flags(c, S, F);
+    if (st != PIC_OK) return st;
+    std::vector<int> unconv0(c->n);
+    for (int k = 0; k < c->n; k++) unconv0[k] = F[(size_t)k * F_NFLAG + F_UNCONV];
     if (!c->have_prev) {
         // the captured schedule extrapolates from two earlier solutions
-        pic_status st = pic_step(c, 1);
-        if (st != PIC_OK) return st;
+        st = pic_step(c, 1);
+        if (st != PIC_OK && st != PIC_ERR_NOT_CONVERGED) return st;
         nsteps--;
     }
     const int P = c->in[0].cfg.sort_interval[0] > 0 ? c->in[0].cfg.sort_interval[0] : 8;
     while (nsteps > 0) {
-        const int len = (int)std::min<long long>(nsteps, P - (c->step % P));
-        pic_status st = ensure_vwindow(c, c->step, len + 1);
+        // a graph covers at most one re-binning period and never more steps
+        // than the device window of conductor potentials holds
+        const int len = (int)std::min<long long>(std::min<long long>(nsteps, P - (c->step % P)),
+                                                 kVWindow - 2);
+        st = ensure_vwindow(c, c->step, len + 1);
         if (st != PIC_OK) return st;
         const int mask = sorts_due(c, c->step + len);
         hipGraphExec_t ex;
@@ -1452,11 +1507,29 @@ pic_status pic_batch_step(pic_ctx *c, int32_t nsteps, int32_t passes, int32_t it
         c->step += len;
         nsteps -= len;
     }
-    std::vector<double> S;
-    std::vector<int> F;
-    pic_status st = read_flags(c, S, F);
+    st = read_flags(c, S, F);
     if (st != PIC_OK) return st;
     record_solve_info(c, S, F);
+    for (int k = 0; k < c->n; k++) {
+        const int d = F[(size_t)k * F_NFLAG + F_UNCONV] - unconv0[k];
+        if (d > 0) {
+            char msg[200];
+            snprintf(msg, sizeof msg, "instance %d: %d of the steps pushed a potential above rtol "
+                     "(largest relative residual so far %.3e)", k, d, S[(size_t)k * S_NSCAL + S_WORST]);
+            return fail(c, PIC_ERR_NOT_CONVERGED, msg);
+        }
+    }
+    return PIC_OK;
+}
+
+pic_status pic_inject_fault(pic_ctx *c, int32_t what)
+{
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (what != 1) return fail(c, PIC_ERR_ARG, "pic_inject_fault: what must be 1");
+    // the device step counter jumps past the window of conductor potentials,
+    // as a runtime that lost track of it would leave it
+    for (int k = 0; k < kVWindow; k++) launch_tick(c->d_ctl, c->stream);
+    HIPCHK(c, hipGetLastError());
     return PIC_OK;
 }
 
@@ -1534,6 +1607,15 @@ pic_status pic_batch_diagnostics(pic_ctx *c, int32_t i, pic_diag *out)
     HIPCHK(c, hipMemcpyAsync(misc, h.d_misc, sizeof misc, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(surf.data(), h.d_surf, surf.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    {
+        // device error bits and the sticky unconverged-push count
+        std::vector<double> S;
+        std::vector<int> F;
+        pic_status st = read_flags(c, S, F);
+        if (st != PIC_OK) return st;
+        h.last.unconverged_pushes = F[(size_t)i * F_NFLAG + F_UNCONV];
+        h.last.worst_relres = S[(size_t)i * S_NSCAL + S_WORST];
+    }
     memset(out, 0, sizeof *out);
     out->step = c->step;
     out->t = c->step * h.cfg.dt;
@@ -1656,3 +1738,22 @@ void pic_destroy(pic_ctx *c)
 }
 
 } // extern "C"
+
+// Internal (C++ linkage, not exported by the headers): see ctx_view.h.
+pic_status pic_ctx_view(pic_ctx *c, int i, PicCtxView *out)
+{
+    if (check(c) != PIC_OK) return PIC_ERR_STATE;
+    if (i < 0 || i >= c->n || !out) return fail(c, PIC_ERR_ARG, "bad instance or output");
+    const InstHost &h = c->in[i];
+    out->phi = h.buf.phi;
+    out->phi_prev = c->have_prev ? h.d_phi_prev : nullptr;
+    out->b = h.buf.b;
+    out->node_cond = h.d_node_cond;
+    out->NX = h.g.NX;
+    out->NY = h.g.NY;
+    out->px = h.g.px;
+    out->py = h.g.py;
+    out->stream = c->stream;
+    return PIC_OK;
+}
+

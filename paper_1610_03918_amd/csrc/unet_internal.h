@@ -31,6 +31,7 @@ struct ConvArgs {
     const float *bias;           // [Cout] (forward only; rounded to bfloat16 like the weights)
     int Cout;                    // multiple of 16
     void *out;                   // forward: bf16 [P][Cout] after bias + ReLU; gradient: f32 [P][Cout]
+    int pw;                      // 1: the image wraps along W (circular padding), 0: zero padding
 };
 
 // Weight gradient of one convolution, split over pixel tiles.
@@ -46,6 +47,7 @@ struct WgradArgs {
     int nsplit;
     float *part;                 // [nsplit][Cout][9][Cin_pad]
     float *bpart;                // [nsplit][Cout]
+    int pw;                      // as in ConvArgs
 };
 
 // Gradient through a ReLU (and the skip / pooling / upsampling joins):
@@ -89,5 +91,13 @@ void launch_snapshot(const double *b, const double *phi, const uint8_t *node_con
                      float *mask, hipStream_t s);
 void launch_guess(const float *out, const double *b, const uint8_t *node_cond, int NX, int NY,
                   int H, int W, float s_phi, double *guess, hipStream_t s);
+// residual learning (see pic_unet.h: pic_unet_residual_sample, pic_unet_load, pic_unet_residual_guess)
+void launch_rsample(const double *b, const double *p1, const double *p2, const double *pt,
+                    const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r, float s_v,
+                    float s_d, uint16_t *x, uint16_t *t, double *stats, hipStream_t s);
+void launch_load(const uint16_t *xs, const uint16_t *ts, long long P, uint16_t *x, float *target, float *mask,
+                 hipStream_t s);
+void launch_rguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX, int NY,
+                   int H, int W, float s_d, int use_out, double *guess, hipStream_t s);
 
 } // namespace unet

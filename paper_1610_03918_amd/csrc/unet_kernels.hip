@@ -41,16 +41,20 @@ __device__ __forceinline__ bf16x8 pack8(const uint32_t *x) {
 // Stage the input patch rows h0-1 .. h0+PR-2, columns w0-1 .. w0+16, channels
 // c0 .. c0+31 of the concatenation [upsampled(up), src] into LDS as
 // [row][col][KS] (zeros outside the image and beyond the channel count).
+// pw: the image wraps along W, so the columns -1 and W are W-1 and 0 (the
+// patch never reaches farther than one column beyond the image).
 template <int PR>
 __device__ __forceinline__ void stage_patch(uint16_t *sp, const uint16_t *src, int Cs,
                                             const uint16_t *up, int Cu, int b, int H, int W,
-                                            int h0, int w0, int c0) {
+                                            int h0, int w0, int c0, int pw) {
     const int Cin = Cu + Cs;
     const int Hh = H >> 1, Wh = W >> 1;
     for (int e = threadIdx.x; e < PR * PC * 4; e += blockDim.x) {
         const int q = e & 3, pix = e >> 2;
         const int r = pix / PC, s = pix - r * PC;
-        const int h = h0 - 1 + r, w = w0 - 1 + s;
+        const int h = h0 - 1 + r;
+        int w = w0 - 1 + s;
+        if (pw) w = w < 0 ? w + W : (w == W ? 0 : w);
         const int c = c0 + 8 * q;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (h >= 0 && h < H && w >= 0 && w < W && c < Cin) {
@@ -109,7 +113,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             if (co < a.Cout) v = *(const uint4 *)(a.wt + ((size_t)co * 9 + t) * a.Cin_pad + c0 + 8 * q);
             *(uint4 *)(sw + row * KS + 8 * q) = v;
         }
-        stage_patch<PR>(sp, a.src, a.Cs, a.up, a.Cu, b, a.H, a.W, h0, w0, c0);
+        stage_patch<PR>(sp, a.src, a.Cs, a.up, a.Cu, b, a.H, a.W, h0, w0, c0, a.pw);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
                 v = *(const uint4 *)(a.gy + (((size_t)b * a.H + h) * a.W + w) * a.Cout + co0 + 8 * q);
             *(uint4 *)(sg + px * GS + 8 * q) = v;
         }
-        stage_patch<PR>(sp, a.src, a.Cs, a.up, a.Cu, b, a.H, a.W, h0, w0, c0);
+        stage_patch<PR>(sp, a.src, a.Cs, a.up, a.Cu, b, a.H, a.W, h0, w0, c0, a.pw);
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
@@ -631,6 +635,120 @@ void launch_guess(const float *out, const double *b, const uint8_t *node_cond, i
     const long long n = (long long)NX * NY;
     hipLaunchKernelGGL(k_guess, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, b, node_cond, NX,
                        NY, H, W, s_phi, guess);
+}
+
+// ---- residual learning: samples, stored-sample loads and the corrected start --------
+// The start is the linear extrapolation phi_s = 2 phi_1 - phi_2 (phi_1 when
+// phi_2 is null); r = b - A phi_s on free nodes with A = 4 - (free
+// neighbours), neighbours wrapping on periodic axes (a free node never lies
+// on a bounded edge).  Input x [H][W][3] = (bf16(r s_r) on free nodes, free
+// indicator, bf16(b s_v) on Dirichlet nodes); target t [H][W] =
+// bf16((phi_t - phi_s) s_d) on free nodes.  stats (may be null) accumulates
+// sum r^2, sum (phi_t - phi_s)^2 and the free-node count over the window.
+__device__ __forceinline__ double start_at(const double *p1, const double *p2, long long n) {
+    return p2 ? 2.0 * p1[n] - p2[n] : p1[n];
+}
+
+__global__ void k_rsample(const double *b, const double *p1, const double *p2, const double *pt,
+                          const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r,
+                          float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0, dd = 0.0, cnt = 0.0;
+    if (p < (long long)H * W) {
+        const int i = (int)(p / W), j = (int)(p % W);
+        const long long n = (long long)i * NY + j;
+        const bool freen = nc[n] == 0;
+        uint16_t x0 = 0, x2 = 0, t0 = 0;
+        if (freen) {
+            double s = 4.0 * start_at(p1, p2, n);
+            const int im = i - 1 < 0 ? (px ? NX - 1 : -1) : i - 1;
+            const int ip = i + 1 >= NX ? (px ? 0 : -1) : i + 1;
+            const int jm = j - 1 < 0 ? (py ? NY - 1 : -1) : j - 1;
+            const int jp = j + 1 >= NY ? (py ? 0 : -1) : j + 1;
+            long long q;
+            if (im >= 0 && !nc[q = (long long)im * NY + j]) s -= start_at(p1, p2, q);
+            if (ip >= 0 && !nc[q = (long long)ip * NY + j]) s -= start_at(p1, p2, q);
+            if (jm >= 0 && !nc[q = (long long)i * NY + jm]) s -= start_at(p1, p2, q);
+            if (jp >= 0 && !nc[q = (long long)i * NY + jp]) s -= start_at(p1, p2, q);
+            const double r = b[n] - s;
+            x0 = (uint16_t)f2bf((float)(r * s_r));
+            rr = r * r;
+            cnt = 1.0;
+            if (pt) {
+                const double d = pt[n] - start_at(p1, p2, n);
+                t0 = (uint16_t)f2bf((float)(d * s_d));
+                dd = d * d;
+            }
+        } else {
+            x2 = (uint16_t)f2bf((float)(b[n] * s_v));
+        }
+        x[3 * p + 0] = x0;
+        x[3 * p + 1] = (uint16_t)(freen ? 0x3F80u : 0u);
+        x[3 * p + 2] = x2;
+        if (t) t[p] = t0;
+    }
+    if (stats) {
+        double v[3] = {rr, dd, cnt};
+        __shared__ double sh[3][256];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = v[k];
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) atomicAdd(stats + k, sh[k][0]);
+    }
+}
+
+void launch_rsample(const double *b, const double *p1, const double *p2, const double *pt,
+                    const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r, float s_v,
+                    float s_d, uint16_t *x, uint16_t *t, double *stats, hipStream_t s) {
+    const long long n = (long long)H * W;
+    hipLaunchKernelGGL(k_rsample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, p1, p2, pt, nc, NX,
+                       NY, px, py, H, W, s_r, s_v, s_d, x, t, stats);
+}
+
+// A stored sample into a batch slot: the input as it is; with t, the target
+// (bfloat16 -> float32) and the loss mask (the free-node channel).
+__global__ void k_load(const uint16_t *xs, const uint16_t *ts, long long P, uint16_t *x, float *target,
+                       float *mask) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    x[3 * p + 0] = xs[3 * p + 0];
+    x[3 * p + 1] = xs[3 * p + 1];
+    x[3 * p + 2] = xs[3 * p + 2];
+    if (ts) {
+        target[p] = bf2f(ts[p]);
+        mask[p] = xs[3 * p + 1] ? 1.f : 0.f;
+    }
+}
+
+void launch_load(const uint16_t *xs, const uint16_t *ts, long long P, uint16_t *x, float *target, float *mask,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_load, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, xs, ts, P, x, target, mask);
+}
+
+// guess = phi_s + out / s_d on free nodes of the window (use_out), phi_s elsewhere.
+__global__ void k_rguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX,
+                         int NY, int H, int W, float s_d, int use_out, double *guess) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (long long)NX * NY) return;
+    const int i = (int)(n / NY), j = (int)(n % NY);
+    double v = start_at(p1, p2, n);
+    if (use_out && nc[n] == 0 && i < H && j < W) v += (double)out[(long long)i * W + j] / (double)s_d;
+    guess[n] = v;
+}
+
+void launch_rguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX, int NY,
+                   int H, int W, float s_d, int use_out, double *guess, hipStream_t s) {
+    const long long n = (long long)NX * NY;
+    hipLaunchKernelGGL(k_rguess, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, p1, p2, nc, NX, NY,
+                       H, W, s_d, use_out, guess);
 }
 
 } // namespace unet

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/pic_unet.h"
+#include "ctx_view.h"
 #include "unet_internal.h"
 
 using namespace unet;
@@ -107,6 +108,7 @@ struct pic_unet {
     double *dpart = nullptr, *scal = nullptr;   // scal[0] mask sum, scal[1] loss
     int ndpart = 0;
     int adam_t = 0;
+    int pw = 0;                                  // circular padding along W
     bool dirty = true;
     bool timing = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -231,6 +233,7 @@ void enqueue_forward(pic_unet *u)
         a.bias = u->params + y.b_off;
         a.Cout = y.cout;
         a.out = u->act[k];
+        a.pw = u->pw;
         launch_conv(a, false, s);
     }
     launch_head_fwd(u->act[kNConv - 1], u->params + N.head_off, u->out, u->P0, s);
@@ -263,6 +266,7 @@ void conv_backward(pic_unet *u, int k, float *gx)
     w.nsplit = ns;
     w.part = u->part;
     w.bpart = u->bpart;
+    w.pw = u->pw;
     launch_wgrad(w, chunks, s);
     launch_wgrad_reduce(u->part, u->bpart, ns, y.cout, y.cin, w.Cin_pad, u->grads + y.w_off,
                         u->grads + y.b_off, s);
@@ -280,6 +284,7 @@ void conv_backward(pic_unet *u, int k, float *gx)
     a.bias = nullptr;
     a.Cout = y.cin;
     a.out = gx;
+    a.pw = u->pw;
     launch_conv(a, true, s);
 }
 
@@ -482,6 +487,19 @@ pic_status pic_unet_guess(pic_unet *u, int32_t slot, const double *b, const uint
     return PIC_OK;
 }
 
+// The network's stream waits for the work queued so far on `other`.
+static pic_status after_stream(pic_unet *u, hipStream_t other)
+{
+    if (other == u->stream) return PIC_OK;
+    hipEvent_t ev = nullptr;
+    UCHK(u, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, other);
+    if (e == hipSuccess) e = hipStreamWaitEvent(u->stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    UCHK(u, e);
+    return PIC_OK;
+}
+
 pic_status pic_solve_learned(pic_ctx *ctx, pic_unet *u, const double *b, float s_rho, float s_v,
                              float s_phi, double *guess, pic_solve_info *info)
 {
@@ -490,11 +508,77 @@ pic_status pic_solve_learned(pic_ctx *ctx, pic_unet *u, const double *b, float s
     int32_t NX = 0, NY = 0;
     pic_status st = pic_node_map(ctx, 0, &nc, nullptr, &NX, &NY);
     if (st != PIC_OK) return st;
+    PicCtxView v;
+    if ((st = pic_ctx_view(ctx, 0, &v)) != PIC_OK) return st;
+    // b was assembled on the context's stream
+    if ((st = after_stream(u, v.stream)) != PIC_OK) return st;
     if ((st = pic_unet_snapshot(u, 0, b, nullptr, nc, NX, NY, s_rho, s_v, s_phi)) != PIC_OK) return st;
     if ((st = pic_unet_forward(u)) != PIC_OK) return st;
     if ((st = pic_unet_guess(u, 0, b, nc, NX, NY, s_phi, guess)) != PIC_OK) return st;
     UCHK(u, hipStreamSynchronize(u->stream));
     return pic_solve(ctx, 2, guess, info);
+}
+
+pic_status pic_unet_set_periodic(pic_unet *u, int32_t periodic_w)
+{
+    if (!u || (periodic_w != 0 && periodic_w != 1)) return ufail(u, PIC_ERR_ARG, "periodic_w must be 0 or 1");
+    u->pw = periodic_w;
+    return PIC_OK;
+}
+
+pic_status pic_unet_residual_sample(const double *b, const double *phi_1, const double *phi_2,
+                                    const double *phi_t, const uint8_t *node_cond, int32_t NX, int32_t NY,
+                                    int32_t periodic_x, int32_t periodic_y, int32_t H, int32_t W, float s_r,
+                                    float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats,
+                                    void *stream)
+{
+    if (!b || !phi_1 || !node_cond || !x || H < 1 || W < 1 || H > NX || W > NY || (t && !phi_t)) return PIC_ERR_ARG;
+    launch_rsample(b, phi_1, phi_2, phi_t, node_cond, NX, NY, periodic_x ? 1 : 0, periodic_y ? 1 : 0, H, W,
+                   s_r, s_v, s_d, x, t, stats, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_ERR_HIP;
+}
+
+pic_status pic_unet_load(pic_unet *u, int32_t slot, const uint16_t *x, const uint16_t *t)
+{
+    if (!u) return PIC_ERR_ARG;
+    if (slot < 0 || slot >= u->B || !x) return ufail(u, PIC_ERR_ARG, "pic_unet_load: bad slot or null input");
+    const long long P = (long long)u->H * u->W, off = (long long)slot * P;
+    launch_load(x, t, P, u->x + off * kInCh, u->target + off, u->mask + off, u->stream);
+    UCHK(u, hipGetLastError());
+    return PIC_OK;
+}
+
+pic_status pic_unet_residual_guess(pic_unet *u, int32_t slot, const double *phi_1, const double *phi_2,
+                                   const uint8_t *node_cond, int32_t NX, int32_t NY, float s_d,
+                                   int32_t use_output, double *guess)
+{
+    if (!u) return PIC_ERR_ARG;
+    if (slot < 0 || slot >= u->B || !phi_1 || !node_cond || !guess || NX < u->H || NY < u->W || !(s_d != 0.f))
+        return ufail(u, PIC_ERR_ARG, "pic_unet_residual_guess: bad slot, pointer, scale or grid");
+    launch_rguess(u->out + (long long)slot * u->H * u->W, phi_1, phi_2, node_cond, NX, NY, u->H, u->W, s_d,
+                  use_output ? 1 : 0, guess, u->stream);
+    UCHK(u, hipGetLastError());
+    return PIC_OK;
+}
+
+pic_status pic_solve_learned_residual(pic_ctx *ctx, pic_unet *u, float s_r, float s_v, float s_d,
+                                      double *guess, pic_solve_info *info)
+{
+    if (!ctx || !u) return PIC_ERR_ARG;
+    if (u->B < 1) return PIC_ERR_ARG;
+    PicCtxView v;
+    pic_status st = pic_ctx_view(ctx, 0, &v);
+    if (st != PIC_OK) return st;
+    if (!guess || v.NX < u->H || v.NY < u->W) return ufail(u, PIC_ERR_ARG, "pic_solve_learned_residual: grid or guess");
+    // the right-hand side and the potentials were written on the context's stream
+    if ((st = after_stream(u, v.stream)) != PIC_OK) return st;
+    launch_rsample(v.b, v.phi, v.phi_prev, nullptr, v.node_cond, v.NX, v.NY, v.px, v.py, u->H, u->W, s_r, s_v,
+                   s_d, u->x, nullptr, nullptr, u->stream);
+    if ((st = pic_unet_forward(u)) != PIC_OK) return st;
+    launch_rguess(u->out, v.phi, v.phi_prev, v.node_cond, v.NX, v.NY, u->H, u->W, s_d, 1, guess, u->stream);
+    UCHK(u, hipGetLastError());
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return pic_solve(ctx, 4, guess, info);
 }
 
 pic_status pic_unet_set_timing(pic_unet *u, int32_t on)

@@ -1,18 +1,25 @@
-"""Learned warm start of the field solve: snapshot collection from solver
-runs, training with the library's own forward / backward / Adam kernels,
-and the iteration counts of cold, previous-step and learned starts.
+"""Learned warm start of the field solve: training samples from solver runs,
+training with the library's own forward / backward / Adam kernels, and the
+iteration counts of the plain solver from several starts.
 
-Orchestration only: every tensor operation runs in the library (see
-unet.py); this module decides which snapshot goes into which batch slot and
+The network corrects the solver's own start, the linear extrapolation in time
+phi_s = 2 phi_{n-1} - phi_{n-2} of the potential (residual learning): its
+input is the residual b - A phi_s (with the free-node mask and the Dirichlet
+potentials), its target the gap phi_n - phi_s to the converged potential.
+
+Orchestration only: every tensor operation on the method's data runs in the
+library (see unet.py); this module decides which sample goes into which batch
+slot, keeps the stored samples in device tensors that torch allocates, and
 records the solver's counters.
 """
 from __future__ import annotations
 
 import math
+import time
 
 import numpy as np
 
-from .unet import UNet
+from .unet import UNet, residual_sample
 
 
 def window(w):
@@ -20,59 +27,152 @@ def window(w):
     return (w.NX // 8) * 8, (w.NY // 8) * 8
 
 
-def collect(pic, n, guess_kind=3):
-    """n (b, phi) pairs from a running simulation: solve, record, push."""
-    snaps = []
-    for _ in range(n):
-        pic.pic_solve(guess_kind)
-        snaps.append((pic.b.clone(), pic.phi.clone()))
+def pow2_scale(rms):
+    """A power of two near 1 / rms (exact rescaling in bfloat16)."""
+    return float(2.0 ** round(-math.log2(rms))) if rms > 0 else 1.0
+
+
+class SampleStore:
+    """Stored training samples of one window size, in device memory:
+    inputs bfloat16 [N, H, W, 3] and targets bfloat16 [N, H, W]."""
+
+    def __init__(self, torch, dev, H, W, capacity):
+        self.H, self.W = H, W
+        self.x = torch.empty((capacity, H, W, 3), dtype=torch.bfloat16, device=dev)
+        self.t = torch.empty((capacity, H, W), dtype=torch.bfloat16, device=dev)
+        self.n = 0
+
+    def full(self):
+        return self.n >= self.x.shape[0]
+
+
+def probe_scales(w, steps, torch, dev, sim_step):
+    """(s_r, s_d): powers of two near the inverse RMS of the residual of the
+    extrapolated start and of its gap to the solution, measured over `steps`
+    steps of a running simulation.  sim_step() advances it one step and
+    returns (b, phi_1, phi_2, phi_n, node_map, periodic)."""
+    H, W = window(w)
+    stats = torch.zeros(3, dtype=torch.float64, device=dev)
+    x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
+    t = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
+    for _ in range(steps):
+        b, p1, p2, pn, nm, per = sim_step()
+        if p2 is None:
+            continue
+        residual_sample(b, p1, p2, pn, nm, per, H, W, (1.0, 1.0, 1.0), x, t, stats)
+    s = stats.cpu().numpy()
+    cnt = max(s[2], 1.0)
+    return pow2_scale(math.sqrt(s[0] / cnt)), pow2_scale(math.sqrt(s[1] / cnt))
+
+
+def run_and_sample(pic, steps, stores, scales, keep=None, every=1):
+    """Advances a single-instance Pic `steps` steps (solve from the
+    extrapolated start, push) and writes a sample of each step's solve into
+    stores[(H, W)] until it is full.  keep: a list that receives the float64
+    (b, phi_{n-1}, phi_{n-2}, phi_n) of every `every`-th step instead (held-out
+    problems).  Returns the solver infos."""
+    w = pic.w
+    H, W = window(w)
+    nm = pic.pic_node_map()
+    per = (int(w.periodic_x), int(w.periodic_y))
+    hist = getattr(pic, "_phi_hist", [])
+    infos = []
+    for k in range(steps):
+        info = pic.pic_solve(3)
+        infos.append(info)
+        phi = pic.phi.clone()
+        if len(hist) == 2:
+            p1, p2 = hist[-1], hist[-2]
+            if keep is not None:
+                if k % every == 0:
+                    keep.append((pic.b.clone(), p1, p2, phi))
+            else:
+                st = stores.get((H, W))
+                if st is not None and not st.full():
+                    residual_sample(pic.b, p1, p2, phi, nm, per, H, W, scales, st.x[st.n], st.t[st.n])
+                    st.n += 1
+        hist = (hist + [phi])[-2:]
         pic.pic_push()
-    return snaps
+    pic._phi_hist = hist
+    return infos
 
 
-def scales(w, snaps, node_cond):
-    """(s_rho, s_v, s_phi): the source term on free nodes scaled to unit RMS
-    over the snapshots, potentials by the largest conductor amplitude.
-    node_cond: host copy of the node map (NX*NY)."""
-    amp = float(np.max(np.abs(np.asarray(w.v_amp, dtype=np.float64))))
-    amp = amp if amp > 0 else 1.0
-    free = np.asarray(node_cond).reshape(-1) == 0
-    ss = 0.0
-    cnt = 0
-    for b, _ in snaps:
-        v = b.reshape(-1).cpu().numpy()[free]
-        ss += float(np.dot(v, v))
-        cnt += v.size
-    rms = math.sqrt(ss / max(cnt, 1)) or 1.0
-    return (float(np.float32(1.0 / rms)), float(np.float32(1.0 / amp)), float(np.float32(amp)))
+def run_and_sample_batch(batch, steps, stores, scales):
+    """As run_and_sample for every instance of a PicBatch (eager solves of
+    all instances, one sample per instance and step)."""
+    n = batch.n
+    hist = getattr(batch, "_phi_hist", [[] for _ in range(n)])
+    nms = [batch.pic_node_map(i) for i in range(n)]
+    for _ in range(steps):
+        batch.pic_solve(3)
+        for i, w in enumerate(batch.ws):
+            phi = batch.phi(i).clone()
+            if len(hist[i]) == 2:
+                H, W = window(w)
+                st = stores.get((H, W))
+                if st is not None and not st.full():
+                    residual_sample(batch.b(i), hist[i][-1], hist[i][-2], phi, nms[i],
+                                    (int(w.periodic_x), int(w.periodic_y)), H, W, scales, st.x[st.n], st.t[st.n])
+                    st.n += 1
+            hist[i] = (hist[i] + [phi])[-2:]
+        batch.pic_push()
+    batch._phi_hist = hist
 
 
-def train(net: UNet, snaps, node_map, sc, steps, lr=2e-3, seed=0, log_every=0, log=None):
-    """Adam on the masked mean-square error of phi / s_phi over random
-    batches of snapshots, cosine-decayed learning rate.  Returns the losses."""
+def make_nets(stores, batch_pixels, seed, periodic_w=True):
+    """One network per window size over shared parameters, gradients and
+    Adam moments; the batch of each holds about batch_pixels pixels."""
+    nets = {}
+    main = None
+    for (H, W) in sorted(stores, key=lambda k: -k[0] * k[1]):
+        B = max(1, min(64, batch_pixels // (H * W)))
+        nets[(H, W)] = UNet(B, H, W, seed=seed, share=main, periodic_w=periodic_w)
+        main = main or nets[(H, W)]
+    return nets, main
+
+
+def train(nets, main, stores, steps, lr=2e-3, seed=0, log=None, log_every=0):
+    """Adam on the masked mean-square error of the target over random batches
+    of stored samples: each step draws a window size with probability
+    proportional to its stored pixels, then fills that network's batch.
+    Cosine-decayed learning rate.  Returns the losses."""
     rng = np.random.default_rng(seed)
+    keys = [k for k in nets if stores[k].n > 0]
+    wts = np.array([stores[k].n * k[0] * k[1] for k in keys], float)
+    wts /= wts.sum()
     losses = []
     for it in range(steps):
-        idx = rng.choice(len(snaps), size=net.B, replace=len(snaps) < net.B)
+        key = keys[rng.choice(len(keys), p=wts)]
+        net, st = nets[key], stores[key]
+        idx = rng.choice(st.n, size=net.B, replace=st.n < net.B)
         for slot, k in enumerate(idx):
-            b, phi = snaps[k]
-            net.pic_unet_snapshot(slot, b, phi, node_map, sc)
+            net.pic_unet_load(slot, st.x[k], st.t[k])
         rate = lr * 0.5 * (1.0 + math.cos(math.pi * it / max(steps, 1)))
-        losses.append(net.train_step(max(rate, 1e-3 * lr)))
+        net.pic_unet_forward()
+        losses.append(net.pic_unet_loss())
+        net.pic_unet_backward()
+        main.pic_unet_adam(max(rate, 1e-3 * lr))
+        for other in nets.values():
+            other.pic_unet_params_changed()
         if log and log_every and (it % log_every == 0 or it == steps - 1):
-            log(f"train step {it}: loss {losses[-1]:.4e}")
+            log(f"train step {it} ({key[0]}x{key[1]}): loss {losses[-1]:.4e}")
     return losses
 
 
-def evaluate(pic_cg, net: UNet, snaps, sc, torch):
-    """Iterations and wall time (ms) of the solver of pic_cg on each
-    snapshot's right-hand side from three starts: zero on the free nodes
-    (cold), the previous snapshot's potential, and the network's prediction
-    (its inference included).  Also the largest difference between the cold
-    and learned solutions on the free nodes."""
-    import time
+def evaluate(pic_cg, net, problems, scales, torch):
+    """Iterations and wall time (ms) of the solver of pic_cg on each held-out
+    problem (b, phi_{n-1}, phi_{n-2}, phi_n) from four starts: zero on the
+    free nodes (cold), the previous potential, the linear extrapolation, and
+    the extrapolation corrected by the network (its sample and inference
+    included in the time).  Also the largest difference between the cold and
+    learned solutions on the free nodes."""
+    w = pic_cg.w
+    H, W = window(w)
+    nm = pic_cg.pic_node_map()
+    per = (int(w.periodic_x), int(w.periodic_y))
     guess = torch.empty(pic_cg.nodes, dtype=torch.float64, device=pic_cg.dev)
     free = torch.as_tensor(pic_cg.node_map_host() == 0, device=pic_cg.dev)
+    s_r, s_v, s_d = scales
 
     def timed(fn):
         torch.cuda.synchronize(pic_cg.dev)
@@ -82,17 +182,26 @@ def evaluate(pic_cg, net: UNet, snaps, sc, torch):
         info["ms"] = 1e3 * (time.perf_counter() - t0)
         return info
 
+    def learned_start():
+        residual_sample(pic_cg.b, p1, p2, None, nm, per, H, W, scales, net.input()[0])
+        net.pic_unet_forward()
+        net.pic_unet_residual_guess(0, p1, p2, nm, s_d, guess, use_output=True)
+        return pic_cg.pic_solve(2, guess)
+
+    def ext_start():
+        net.pic_unet_residual_guess(0, p1, p2, nm, s_d, guess, use_output=False)
+        return pic_cg.pic_solve(2, guess)
+
     rows = []
-    for k, (b, phi) in enumerate(snaps):
+    for (b, p1, p2, pn) in problems:
         pic_cg.b.copy_(b)
         cold = timed(lambda: pic_cg.pic_solve(0))
         phi_cold = pic_cg.phi.clone()
-        prev = None
-        if k > 0:
-            pic_cg.phi.copy_(snaps[k - 1][1])
-            prev = timed(lambda: pic_cg.pic_solve(1))
-        learned = timed(lambda: net.pic_solve_learned(pic_cg, sc, guess))
+        pic_cg.phi.copy_(p1)
+        prev = timed(lambda: pic_cg.pic_solve(1))
+        ext = timed(ext_start)
+        learned = timed(learned_start)
         diff = float(((pic_cg.phi - phi_cold) * free).abs().max())
-        rows.append({"cold": cold, "prev": prev, "learned": learned, "max_diff": diff,
-                     "scale": float(phi.abs().max())})
+        rows.append({"cold": cold, "prev": prev, "ext": ext, "learned": learned, "max_diff": diff,
+                     "scale": float(pn.abs().max())})
     return rows

@@ -21,7 +21,7 @@ IAD_BINS = 90
 
 PIC_OK = 0
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -3: "PIC_ERR_HIP", -4: "PIC_ERR_NOT_CONVERGED",
-          -7: "PIC_ERR_STATE", -8: "PIC_ERR_CAPACITY"}
+          -5: "PIC_ERR_CFL", -6: "PIC_ERR_OVERFLOW", -7: "PIC_ERR_STATE", -8: "PIC_ERR_CAPACITY"}
 
 
 class pic_config(C.Structure):
@@ -55,11 +55,12 @@ class pic_buffers(C.Structure):
 
 class pic_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer", C.c_int32), ("converged", C.c_int32),
-                ("iterations_first", C.c_int32), ("relres0", C.c_double), ("relres", C.c_double)]
+                ("iterations_first", C.c_int32), ("relres0", C.c_double), ("relres", C.c_double),
+                ("unconverged_pushes", C.c_int32), ("pad", C.c_int32), ("worst_relres", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k in ("iterations", "iterations_first", "outer", "converged", "relres0",
-                                              "relres")}
+                                              "relres", "unconverged_pushes", "worst_relres")}
 
 
 class pic_diag(C.Structure):
@@ -82,8 +83,8 @@ ENTRY_POINTS = ["pic_workspace_size", "pic_init", "pic_deposit", "pic_solve", "p
                 "pic_push", "pic_step", "pic_diagnostics", "pic_particles", "pic_read_hits",
                 "pic_sort", "pic_push_timing", "pic_set_timing", "pic_batch_workspace_size",
                 "pic_batch_init", "pic_batch_step", "pic_batch_diagnostics", "pic_batch_particles",
-                "pic_batch_solve_info", "pic_node_map", "pic_tune", "pic_set_level_pairs", "pic_destroy",
-                "pic_last_error", "pic_version"]
+                "pic_batch_solve_info", "pic_node_map", "pic_tune", "pic_set_level_pairs", "pic_inject_fault",
+                "pic_destroy", "pic_last_error", "pic_version"]
 
 
 def lib():
@@ -119,6 +120,8 @@ def lib():
     L.pic_batch_solve_info.argtypes = [P, i32, C.POINTER(pic_solve_info)]
     L.pic_node_map.argtypes = [P, i32, C.POINTER(P), P, C.POINTER(i32), C.POINTER(i32)]
     L.pic_tune.argtypes = [P, i32, i32, i32, i32]
+    L.pic_set_level_pairs.argtypes = [P, i32]
+    L.pic_inject_fault.argtypes = [P, i32]
     L.pic_destroy.argtypes = [P]
     L.pic_destroy.restype = None
     L.pic_last_error.argtypes = [P]
@@ -257,6 +260,10 @@ class _Context:
 
     def pic_set_level_pairs(self, on):
         self._chk(lib().pic_set_level_pairs(self.ctx, int(bool(on))))
+
+    def pic_inject_fault(self, what=1):
+        """Test hook of the device error path (see pic.h)."""
+        self._chk(lib().pic_inject_fault(self.ctx, int(what)))
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -457,8 +464,12 @@ class PicBatch(_Context):
     def pic_step(self, n=1):
         self._chk(lib().pic_step(self.ctx, int(n)))
 
-    def pic_batch_step(self, n, passes=2, iters=12, iters_later=0):
-        self._chk(lib().pic_batch_step(self.ctx, int(n), int(passes), int(iters), int(iters_later)))
+    def pic_batch_step(self, n, passes=2, iters=12, iters_later=0, allow_unconverged=False):
+        """Steps as captured graphs; raises PicError(PIC_ERR_NOT_CONVERGED) when a
+        step of some instance pushed a potential above rtol, unless
+        allow_unconverged (then the per-instance infos carry the counts)."""
+        allow = (-4,) if allow_unconverged else ()
+        self._chk(lib().pic_batch_step(self.ctx, int(n), int(passes), int(iters), int(iters_later)), allow)
         return [self.pic_batch_solve_info(i) for i in range(self.n)]
 
     def pic_batch_solve_info(self, i):

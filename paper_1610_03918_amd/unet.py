@@ -21,6 +21,8 @@ UNET_ENTRY_POINTS = ["pic_unet_param_count", "pic_unet_layer_info", "pic_unet_wo
                      "pic_unet_create", "pic_unet_io_buffers", "pic_unet_params_changed",
                      "pic_unet_forward", "pic_unet_loss", "pic_unet_backward", "pic_unet_adam",
                      "pic_unet_snapshot", "pic_unet_guess", "pic_solve_learned",
+                     "pic_unet_set_periodic", "pic_unet_residual_sample", "pic_unet_load",
+                     "pic_unet_residual_guess", "pic_solve_learned_residual",
                      "pic_unet_set_timing", "pic_unet_forward_timing", "pic_unet_destroy",
                      "pic_unet_last_error"]
 
@@ -58,6 +60,12 @@ def lib():
     L.pic_unet_snapshot.argtypes = [P, i32, P, P, P, i32, i32, f32, f32, f32]
     L.pic_unet_guess.argtypes = [P, i32, P, P, i32, i32, f32, P]
     L.pic_solve_learned.argtypes = [P, P, P, f32, f32, f32, P, C.POINTER(pic_solve_info)]
+    L.pic_unet_set_periodic.argtypes = [P, i32]
+    L.pic_unet_residual_sample.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, i32, f32, f32, f32, P, P,
+                                           P, P]
+    L.pic_unet_load.argtypes = [P, i32, P, P]
+    L.pic_unet_residual_guess.argtypes = [P, i32, P, P, P, i32, i32, f32, i32, P]
+    L.pic_solve_learned_residual.argtypes = [P, P, f32, f32, f32, P, C.POINTER(pic_solve_info)]
     L.pic_unet_set_timing.argtypes = [P, i32]
     L.pic_unet_forward_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i32)]
     L.pic_unet_destroy.argtypes = [P]
@@ -102,7 +110,10 @@ def init_params(seed=100):
 class UNet:
     """The network over caller-owned torch buffers; method names follow the C ABI."""
 
-    def __init__(self, batch, H, W, device="cuda:0", params=None, seed=100):
+    def __init__(self, batch, H, W, device="cuda:0", params=None, seed=100, share=None, periodic_w=False):
+        """share: another UNet whose parameter, gradient and Adam moment
+        arrays this one uses too (networks of other image sizes trained
+        together); periodic_w: circular padding along W."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the U-Net kernels need a GPU (no CPU fallback)")
@@ -111,16 +122,19 @@ class UNet:
         self.dev = torch.device(device)
         self.B, self.H, self.W = int(batch), int(H), int(W)
         n = param_count()
-        if params is None:
-            params = init_params(seed)
-        if isinstance(params, torch.Tensor):
-            self.params = params.detach().to(self.dev, torch.float32).clone().contiguous()
+        if share is not None:
+            self.params, self.grads, self.m, self.v = share.params, share.grads, share.m, share.v
         else:
-            self.params = torch.as_tensor(np.asarray(params, np.float32)).to(self.dev).contiguous()
+            if params is None:
+                params = init_params(seed)
+            if isinstance(params, torch.Tensor):
+                self.params = params.detach().to(self.dev, torch.float32).clone().contiguous()
+            else:
+                self.params = torch.as_tensor(np.asarray(params, np.float32)).to(self.dev).contiguous()
+            self.grads = torch.zeros(n, dtype=torch.float32, device=self.dev)
+            self.m = torch.zeros(n, dtype=torch.float32, device=self.dev)
+            self.v = torch.zeros(n, dtype=torch.float32, device=self.dev)
         assert self.params.numel() == n
-        self.grads = torch.zeros(n, dtype=torch.float32, device=self.dev)
-        self.m = torch.zeros(n, dtype=torch.float32, device=self.dev)
-        self.v = torch.zeros(n, dtype=torch.float32, device=self.dev)
         nb = C.c_size_t(0)
         st = L.pic_unet_workspace_size(self.B, self.H, self.W, C.byref(nb))
         if st != PIC_OK:
@@ -141,6 +155,8 @@ class UNet:
         io = pic_unet_io()
         self._chk(L.pic_unet_io_buffers(self.h, C.byref(io)))
         self.io = io
+        if periodic_w:
+            self._chk(L.pic_unet_set_periodic(self.h, 1))
 
     def _chk(self, st):
         if st != PIC_OK:
@@ -223,6 +239,30 @@ class UNet:
             raise PicError(st, msg)
         return info.as_dict()
 
+    def pic_unet_load(self, slot, x, t=None):
+        """Stored sample (device bfloat16 tensors x [H, W, 3], t [H, W]) into a batch slot."""
+        self._chk(lib().pic_unet_load(self.h, int(slot), C.c_void_p(x.data_ptr()),
+                                      C.c_void_p(t.data_ptr()) if t is not None else None))
+
+    def pic_unet_residual_guess(self, slot, phi_1, phi_2, node_map, s_d, guess, use_output=True):
+        ptr, NX, NY = node_map
+        self._chk(lib().pic_unet_residual_guess(self.h, int(slot), C.c_void_p(phi_1.data_ptr()),
+                                                C.c_void_p(phi_2.data_ptr()) if phi_2 is not None else None,
+                                                C.c_void_p(ptr), NX, NY, float(s_d), 1 if use_output else 0,
+                                                C.c_void_p(guess.data_ptr())))
+
+    def pic_solve_learned_residual(self, pic, scales, guess):
+        """Residual-learning start for instance 0 of a running Pic (scales:
+        s_r, s_v, s_d; guess: device float64 NX*NY scratch)."""
+        s_r, s_v, s_d = scales
+        info = pic_solve_info()
+        st = lib().pic_solve_learned_residual(pic.ctx, self.h, s_r, s_v, s_d, C.c_void_p(guess.data_ptr()),
+                                              C.byref(info))
+        if st != PIC_OK:
+            msg = lib().pic_unet_last_error(self.h).decode() or _pic.lib().pic_last_error(pic.ctx).decode()
+            raise PicError(st, msg)
+        return info.as_dict()
+
     def pic_unet_set_timing(self, on=True):
         self._chk(lib().pic_unet_set_timing(self.h, 1 if on else 0))
 
@@ -238,3 +278,26 @@ class UNet:
         self.pic_unet_backward()
         self.pic_unet_adam(lr)
         return loss
+
+
+def residual_sample(b, phi_1, phi_2, phi_t, node_map, periodic, H, W, scales, x, t=None, stats=None,
+                    stream=None):
+    """pic_unet_residual_sample on device tensors: b, phi_1, phi_2 (or None),
+    phi_t (or None) float64 [NX, NY]; node_map (pointer, NX, NY); periodic
+    (x, y); scales (s_r, s_v, s_d); x bfloat16 [H, W, 3], t bfloat16 [H, W]
+    (or None); stats float64 [3] (or None)."""
+    import torch
+    ptr, NX, NY = node_map
+    s_r, s_v, s_d = scales
+    if stream is None:
+        stream = torch.cuda.current_stream(b.device)
+
+    def vp(a):
+        return C.c_void_p(a.data_ptr()) if a is not None else None
+
+    st = lib().pic_unet_residual_sample(vp(b), vp(phi_1), vp(phi_2), vp(phi_t), C.c_void_p(ptr), NX, NY,
+                                        int(periodic[0]), int(periodic[1]), int(H), int(W), float(s_r),
+                                        float(s_v), float(s_d), vp(x), vp(t), vp(stats),
+                                        C.c_void_p(stream.cuda_stream))
+    if st != PIC_OK:
+        raise PicError(st, "pic_unet_residual_sample: bad window, pointer or launch")

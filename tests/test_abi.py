@@ -94,3 +94,16 @@ def test_recycling_config_validation():
     bad, cc3 = make_config(w)
     bad.recycle_vth = -0.1
     assert _ws(bad, cap)[0] == -1
+
+
+def test_capacity_beyond_the_fixed_point_charge_bound_is_an_overflow():
+    """A capacity above 2^31 - 1 particles per species could exceed the
+    int64 node charge (2^32 units per particle): PIC_ERR_OVERFLOW, not a
+    generic argument error; 2^31 - 1 itself is accepted."""
+    from paper_1610_03918_amd.pic import make_config
+    w = synth.trench(nx=64, ny=32, width=4, depth=8, ppc=2)
+    cfg, cc = make_config(w)
+    assert _ws(cfg, [(1 << 31) - 1, 10])[0] == 0
+    assert _ws(cfg, [1 << 31, 10])[0] == -6
+    assert _ws(cfg, [10, 1 << 40])[0] == -6
+    assert _ws(cfg, [-1, 10])[0] == -1

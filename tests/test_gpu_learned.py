@@ -1,17 +1,16 @@
-"""GPU test of the learned warm start end to end: snapshots (b, phi) from one
-run of a small trench, training with the library's own forward / backward /
-Adam kernels, and plain masked CG on snapshots of a second run (another
-particle load) started from zero, from the previous step, and from the
-network.
+"""GPU test of the learned warm start end to end (residual learning): samples
+from one run of a small y-periodic trench, training with the library's own
+forward / backward / Adam kernels, and plain masked CG to 1e-8 on held-out
+problems of a second run (another particle load) from four starts: zero on
+the free nodes (cold), the previous potential, the linear extrapolation in
+time, and the extrapolation corrected by the network.
 
-What is asserted is what the trained network reliably gains: the training
-loss falls by two orders of magnitude, the predicted start cuts the initial
-residual at least in half against the cold start, and the solve finished
-from it reaches the same potential at the same tolerance.  The iteration
-counts of the three starts are printed; on this problem the learned start
-does not reduce the iterations of unrestarted CG appreciably (see the
-learned-start section of the design notes), and the test only bounds the
-extra cost."""
+Asserted: the training loss falls, every solve converges to the same
+potential, the network cuts the residual of the extrapolated start, and it
+saves iterations against both the cold start and the extrapolation alone
+(the method without the network).  The measured factors are printed.  The
+the benchmark spec's >= 3x cut is pinned as an expected failure at the full
+1024 x 512 size in the benchmark's figures, not here."""
 import numpy as np
 import pytest
 
@@ -24,43 +23,98 @@ def _trench(seed):
     return synth.trench(nx=96, ny=56, width=6, depth=24, ppc=12, seed=seed, rtol=1e-8)
 
 
-def test_learned_start_saves_cg_iterations():
+def _train(seed=41, steps=1500):
+    import torch
+    from paper_1610_03918_amd import Pic, learned
+    w = _trench(seed)
+    a = Pic(w, synth.load(w))
+    a.start()
+    a.pic_step(40)                                   # the sheath forms
+    H, W = learned.window(w)
+    dev = torch.device("cuda:0")
+    # probe the scales on a few steps
+    probe = []
+    learned.run_and_sample(a, 12, {}, (1.0, 1.0, 1.0), keep=probe)
+    from paper_1610_03918_amd.unet import residual_sample
+    stats = torch.zeros(3, dtype=torch.float64, device=dev)
+    x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
+    t = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
+    for b, p1, p2, pn in probe:
+        residual_sample(b, p1, p2, pn, a.pic_node_map(), (0, 1), H, W, (1.0, 1.0, 1.0), x, t, stats)
+    s = stats.cpu().numpy()
+    sc = (learned.pow2_scale(np.sqrt(s[0] / s[2])), float(np.float32(1 / 50)),
+          learned.pow2_scale(np.sqrt(s[1] / s[2])))
+    stores = {(H, W): learned.SampleStore(torch, dev, H, W, 400)}
+    learned.run_and_sample(a, 402, stores, sc)
+    a.close()
+    assert stores[(H, W)].n == 400
+    nets, main = learned.make_nets(stores, 8 * H * W, seed=3)
+    losses = learned.train(nets, main, stores, steps, lr=2e-3, seed=1)
+    return w, nets[(H, W)], sc, losses
+
+
+def test_learned_start_cuts_cg_iterations():
     import torch
     from paper_1610_03918_amd import Pic, learned
     from paper_1610_03918_amd.unet import UNet
-    wa, wb = _trench(41), _trench(42)
-    a = Pic(wa, synth.load(wa))
-    a.start()
-    train = learned.collect(a, 160)
-    nm_host = a.node_map_host()
-    sc = learned.scales(wa, train, nm_host)
-    H, W = learned.window(wa)
-    net = UNet(8, H, W, seed=3)
-    losses = learned.train(net, train, a.pic_node_map(), sc, steps=3000, lr=2e-3, seed=1)
-    a.close()
+    wa, net, sc, losses = _train()
     assert np.all(np.isfinite(losses))
-    assert np.mean(losses[-20:]) < 0.01 * np.mean(losses[:5]), (losses[:5], losses[-20:])
-
+    assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:5]), (losses[:5], losses[-20:])
+    wb = _trench(42)
     b = Pic(wb, synth.load(wb))
     b.start()
-    learned.collect(b, 60)
-    evals = learned.collect(b, 12)
+    b.pic_step(40)
+    learned.run_and_sample(b, 60, {}, sc)
+    problems = []
+    learned.run_and_sample(b, 24, {}, sc, keep=problems, every=2)
     b.close()
+    u1 = UNet(1, net.H, net.W, params=net.params, periodic_w=True)
     cg = Pic(wb, synth.load(wb), solver=1, max_iter=20000)
-    assert np.array_equal(cg.node_map_host(), nm_host)
-    rows = learned.evaluate(cg, net, evals, sc, torch)
+    rows = learned.evaluate(cg, u1, problems, sc, torch)
     cg.close()
-    net.close()
-    cold = np.array([r["cold"]["iterations"] for r in rows], float)
-    lrn = np.array([r["learned"]["iterations"] for r in rows], float)
-    print("loss", losses[0], np.mean(losses[:5]), np.mean(losses[-20:]))
+    u1.close()
+    its = {k: np.array([r[k]["iterations"] for r in rows], float) for k in ("cold", "prev", "ext", "learned")}
+    r0 = {k: np.median([r[k]["relres0"] for r in rows]) for k in ("cold", "prev", "ext", "learned")}
+    print("loss", np.mean(losses[:5]), "->", np.mean(losses[-20:]))
+    print({k: float(v.mean()) for k, v in its.items()}, r0,
+          "cold/learned", its["cold"].mean() / its["learned"].mean(),
+          "ext/learned", its["ext"].mean() / its["learned"].mean())
     for r in rows:
-        print({k: (r[k]["iterations"], r[k]["relres0"]) if isinstance(r[k], dict) else r[k] for k in r})
-    print("cold", cold.mean(), "learned", lrn.mean(),
-          "prev", np.mean([r["prev"]["iterations"] for r in rows[1:]]),
-          "relres0 learned", np.median([r["learned"]["relres0"] for r in rows]))
-    for r in rows:
-        assert r["cold"]["converged"] and r["learned"]["converged"]
+        for k in ("cold", "prev", "ext", "learned"):
+            assert r[k]["converged"], (k, r)
         assert r["max_diff"] <= 1e-4 * r["scale"], r
-        assert r["learned"]["relres0"] < 0.5 * r["cold"]["relres0"], r
-    assert lrn.mean() < 1.15 * cold.mean(), (cold, lrn)
+    assert r0["learned"] < 0.5 * r0["ext"], r0
+    assert its["learned"].mean() < its["ext"].mean() < its["cold"].mean(), its
+    assert its["cold"].mean() / its["learned"].mean() > 1.5, its
+
+
+def test_learned_start_inside_a_running_simulation():
+    """pic_solve_learned_residual on the live context: the corrected start of
+    the context's own b and potentials, finished by the solver to rtol; the
+    time history carries on (the next extrapolated, kind-3, solve converges
+    in a few multigrid iterations), and the potential equals the one a cold
+    solve of the same b reaches."""
+    import torch
+    from paper_1610_03918_amd import Pic
+    from paper_1610_03918_amd.unet import UNet
+    wa, net, sc, _ = _train(steps=300)
+    u1 = UNet(1, net.H, net.W, params=net.params, periodic_w=True)
+    p = Pic(wa, synth.load(wa))
+    p.start()
+    p.pic_step(30)
+    guess = torch.empty(p.nodes, dtype=torch.float64, device=p.dev)
+    free = torch.as_tensor(p.node_map_host() == 0, device=p.dev)
+    for k in range(3):
+        info = u1.pic_solve_learned_residual(p, sc, guess)
+        assert info["converged"] and info["relres"] <= wa.rtol, info
+        p.pic_push()
+        info3 = p.pic_solve(3)
+        assert info3["converged"] and info3["iterations"] <= 12, info3
+        p.pic_push()
+    info = u1.pic_solve_learned_residual(p, sc, guess)
+    phi_l = p.phi.clone()
+    cold = p.pic_solve(0)
+    assert cold["converged"] and cold["iterations"] > info["iterations"], (cold, info)
+    assert float(((p.phi - phi_l) * free).abs().max()) <= 1e-4 * float(phi_l.abs().max())
+    u1.close()
+    p.close()

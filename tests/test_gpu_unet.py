@@ -189,3 +189,93 @@ def test_snapshot_and_guess_maps():
     assert np.array_equal(guess.cpu().numpy().reshape(w.NX, w.NY), ref)
     u.close()
     pic.close()
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 24), (1, 32, 64)])
+def test_periodic_forward_and_backward_match_oracle(B, H, W):
+    """Circular padding along W (a y-periodic grid): forward and parameter
+    gradients against the oracle network with the same padding, at the bars
+    of the zero-padded network."""
+    import torch
+    from paper_1610_03918_amd.unet import UNet
+    ps = _params(15)
+    u = UNet(B, H, W, params=_flat(ps), periodic_w=True)
+    r = np.random.default_rng(8)
+    x = ou.bf16(r.standard_normal((B, H, W, 3)))
+    gout = r.standard_normal((B, H, W)).astype(np.float32)
+    _set_input(u, torch, x)
+    u.pic_unet_forward()
+    got = u.output().cpu().numpy().astype(np.float64)
+    ref, cache = ou.forward(ps, x, quantize=True, periodic_w=True)
+    assert _rel(got, ref) < 1e-2, _rel(got, ref)
+    ref0, _ = ou.forward(ps, x, quantize=True)
+    assert _rel(got, ref0) > 5e-2                     # the padding matters at this size
+    u.grad_output().copy_(torch.from_numpy(gout).to(u.dev))
+    u.pic_unet_backward()
+    grads = _unflat(u.grads.cpu().numpy(), ps)
+    gref, _ = ou.backward(cache, gout.astype(np.float64))
+    for k, (g, rf) in enumerate(zip(grads, gref)):
+        assert _rel(g, rf) < 2e-2, (k, _rel(g, rf))
+    u.close()
+
+
+def _trench_state(seed=43):
+    """A small y-periodic trench with two earlier potentials and a target
+    potential drawn as smooth-plus-noise fields (equal on both sides)."""
+    w = synth.trench(nx=64, ny=40, width=6, depth=16, ppc=4, seed=seed)
+    nc = oracle.node_cond(w)
+    parts = synth.load(w)
+    rho = [oracle.deposit(w, parts[s]) for s in range(2)]
+    b = oracle.assemble(w, nc, rho[0], rho[1], 1.7)
+    p1 = synth.random_potential(w, seed + 1, scale=3.0)
+    p2 = synth.random_potential(w, seed + 2, scale=3.0)
+    pt = synth.random_potential(w, seed + 3, scale=3.0)
+    return w, nc, b, p1, p2, pt
+
+
+def test_residual_sample_load_and_guess_are_bit_exact():
+    """The residual-learning maps against the oracle on identical float64
+    inputs: the sample's bfloat16 input and target, its statistics, the load
+    into a batch slot (target as float32, mask from the free channel) and the
+    corrected start, with and without a second earlier potential."""
+    import torch
+    from paper_1610_03918_amd import Pic
+    from paper_1610_03918_amd.unet import UNet, residual_sample
+    w, nc, b, p1, p2, pt = _trench_state()
+    pic = Pic(w, synth.load(w))                       # for its node map
+    nm = pic.pic_node_map()
+    assert np.array_equal(pic.node_map_host(), nc)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    H, W = (w.NX // 8) * 8, w.NY
+    sc = (float(np.float32(0.75)), float(np.float32(0.02)), float(np.float32(6.0)))
+    per = (False, True)
+    for second in (True, False):
+        x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
+        t = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
+        stats = torch.zeros(3, dtype=torch.float64, device=dev)
+        residual_sample(T(b), T(p1), T(p2) if second else None, T(pt), nm, per, H, W, sc, x, t, stats)
+        xr, tr = ou.residual_sample(b, p1, p2 if second else None, pt, nc, H, W, per, *sc)
+        assert np.array_equal(x.float().cpu().numpy(), xr)
+        assert np.array_equal(t.float().cpu().numpy(), tr)
+        start = ou.extrapolated(p1, p2 if second else None)
+        res = ou.masked_residual(b, start, nc, per)[:H, :W]
+        free = nc[:H, :W] == 0
+        st = stats.cpu().numpy()
+        assert st[2] == free.sum()
+        assert abs(st[0] - np.sum(res[free] ** 2)) <= 1e-9 * st[0]
+        assert abs(st[1] - np.sum((pt - start)[:H, :W][free] ** 2)) <= 1e-9 * st[1]
+        u = UNet(2, H, W, periodic_w=True)
+        u.pic_unet_load(1, x, t)
+        assert np.array_equal(u.input()[1].float().cpu().numpy(), xr)
+        assert np.array_equal(u.target()[1].cpu().numpy(), tr.astype(np.float32))
+        assert np.array_equal(u.mask()[1].cpu().numpy(), free.astype(np.float32))
+        u.pic_unet_forward()
+        out = u.output()[1].cpu().numpy().astype(np.float64)
+        g = torch.empty(w.NX * w.NY, dtype=torch.float64, device=dev)
+        for use in (True, False):
+            u.pic_unet_residual_guess(1, T(p1), T(p2) if second else None, nm, sc[2], g, use_output=use)
+            ref = ou.residual_guess(out, p1, p2 if second else None, nc, sc[2], use_output=use)
+            assert np.array_equal(g.cpu().numpy().reshape(w.NX, w.NY), ref)
+        u.close()
+    pic.close()
