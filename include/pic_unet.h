@@ -138,21 +138,27 @@ pic_status pic_solve_learned(pic_ctx *ctx, pic_unet *u, const double *b, float s
  * (the default) pads with zeros.  PIC_ERR_ARG for other values. */
 pic_status pic_unet_set_periodic(pic_unet *u, int32_t periodic_w);
 
+/* Bytes of the work array pic_unet_residual_sample needs for an H x W
+ * window when it returns statistics: 3 float64 per block of 256 pixels. */
+pic_status pic_unet_residual_sample_work_bytes(int32_t H, int32_t W, size_t *bytes);
+
 /* One training sample of the H x W window of a Poisson problem (no network
  * needed): x (device bfloat16 [H][W][3]) receives the input channels above,
  * t (device bfloat16 [H][W], or NULL) the target with phi_t the converged
- * potential; stats (device float64[3], or NULL) accumulates, with atomics
- * (so its last bits depend on the order of the blocks), the sums over the
- * window's free nodes of r^2 and of (phi_t - phi_s)^2 and their count.
- * b, phi_1, phi_2 (may be NULL), phi_t: device float64 NX x NY; node_cond:
- * device NX x NY node map (0 free); periodic_x / periodic_y: the grid's
- * periodic axes (neighbours wrap).  Enqueued on stream.  PIC_ERR_ARG for a
- * window larger than the grid or a missing pointer. */
+ * potential.  stats (device float64[3], or NULL) accumulates the sums over
+ * the window's free nodes of r^2 and of (phi_t - phi_s)^2 and their count,
+ * added in a fixed order (deterministic); with stats, work (device, at
+ * least pic_unet_residual_sample_work_bytes) holds the per-block partial
+ * sums.  b, phi_1, phi_2 (may be NULL), phi_t: device float64 NX x NY;
+ * node_cond: device NX x NY node map (0 free); periodic_x / periodic_y: the
+ * grid's periodic axes (neighbours wrap).  Enqueued on stream.  PIC_ERR_ARG
+ * for a window larger than the grid, a missing pointer or a short work
+ * array. */
 pic_status pic_unet_residual_sample(const double *b, const double *phi_1, const double *phi_2,
                                     const double *phi_t, const uint8_t *node_cond, int32_t NX, int32_t NY,
                                     int32_t periodic_x, int32_t periodic_y, int32_t H, int32_t W, float s_r,
                                     float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats,
-                                    void *stream);
+                                    void *work, size_t work_bytes, void *stream);
 
 /* Copies a stored sample (x, t as written by pic_unet_residual_sample for
  * this network's H x W) into batch slot `slot`: the input, and with t the

@@ -92,9 +92,12 @@ void launch_snapshot(const double *b, const double *phi, const uint8_t *node_con
 void launch_guess(const float *out, const double *b, const uint8_t *node_cond, int NX, int NY,
                   int H, int W, float s_phi, double *guess, hipStream_t s);
 // residual learning (see pic_unet.h: pic_unet_residual_sample, pic_unet_load, pic_unet_residual_guess)
+// stats (may be null) += deterministic sums over the window; part: 3 doubles per
+// block of rsample_blocks(H, W) (needed only with stats)
+long long rsample_blocks(int H, int W);
 void launch_rsample(const double *b, const double *p1, const double *p2, const double *pt,
                     const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r, float s_v,
-                    float s_d, uint16_t *x, uint16_t *t, double *stats, hipStream_t s);
+                    float s_d, uint16_t *x, uint16_t *t, double *stats, double *part, hipStream_t s);
 void launch_load(const uint16_t *xs, const uint16_t *ts, long long P, uint16_t *x, float *target, float *mask,
                  hipStream_t s);
 void launch_rguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX, int NY,

@@ -643,16 +643,20 @@ void launch_guess(const float *out, const double *b, const uint8_t *node_cond, i
 // neighbours), neighbours wrapping on periodic axes (a free node never lies
 // on a bounded edge).  Input x [H][W][3] = (bf16(r s_r) on free nodes, free
 // indicator, bf16(b s_v) on Dirichlet nodes); target t [H][W] =
-// bf16((phi_t - phi_s) s_d) on free nodes.  stats (may be null) accumulates
-// sum r^2, sum (phi_t - phi_s)^2 and the free-node count over the window.
+// bf16((phi_t - phi_s) s_d) on free nodes.  part (may be null): per-block
+// sums of r^2, (phi_t - phi_s)^2 and the free-node count, summed in block
+// order by k_rsample_sum into stats.
 __device__ __forceinline__ double start_at(const double *p1, const double *p2, long long n) {
     return p2 ? 2.0 * p1[n] - p2[n] : p1[n];
 }
 
-__global__ void k_rsample(const double *b, const double *p1, const double *p2, const double *pt,
-                          const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r,
-                          float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats) {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kRsBlock = 256;
+
+__global__ __launch_bounds__(kRsBlock) void k_rsample(const double *b, const double *p1, const double *p2,
+                                                      const double *pt, const uint8_t *nc, int NX, int NY,
+                                                      int px, int py, int H, int W, float s_r, float s_v,
+                                                      float s_d, uint16_t *x, uint16_t *t, double *part) {
+    const long long p = (long long)blockIdx.x * kRsBlock + threadIdx.x;
     double rr = 0.0, dd = 0.0, cnt = 0.0;
     if (p < (long long)H * W) {
         const int i = (int)(p / W), j = (int)(p % W);
@@ -687,13 +691,13 @@ __global__ void k_rsample(const double *b, const double *p1, const double *p2, c
         x[3 * p + 2] = x2;
         if (t) t[p] = t0;
     }
-    if (stats) {
+    if (part) {
         double v[3] = {rr, dd, cnt};
-        __shared__ double sh[3][256];
+        __shared__ double sh[3][kRsBlock];
 #pragma unroll
         for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = v[k];
         __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
+        for (int off = kRsBlock / 2; off > 0; off >>= 1) {
             if ((int)threadIdx.x < off)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
@@ -701,16 +705,42 @@ __global__ void k_rsample(const double *b, const double *p1, const double *p2, c
         }
         if (threadIdx.x == 0)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) atomicAdd(stats + k, sh[k][0]);
+            for (int k = 0; k < 3; ++k) part[3 * (long long)blockIdx.x + k] = sh[k][0];
     }
 }
 
+// stats[k] += the sum of the nblk partials of quantity k, in block order
+// (one wavefront: lane l sums blocks l, l + 64, ...; the 64 lane sums are
+// then added in lane order by lane 0).
+__global__ void k_rsample_sum(const double *part, int nblk, double *stats) {
+    __shared__ double sh[3][64];
+    const int l = threadIdx.x;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = l; b < nblk; b += 64)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s[k] += part[3 * (long long)b + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sh[k][l] = s[k];
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double a = 0.0;
+            for (int q = 0; q < 64; ++q) a += sh[k][q];
+            stats[k] += a;
+        }
+    }
+}
+
+long long rsample_blocks(int H, int W) { return ((long long)H * W + kRsBlock - 1) / kRsBlock; }
+
 void launch_rsample(const double *b, const double *p1, const double *p2, const double *pt,
                     const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r, float s_v,
-                    float s_d, uint16_t *x, uint16_t *t, double *stats, hipStream_t s) {
-    const long long n = (long long)H * W;
-    hipLaunchKernelGGL(k_rsample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, p1, p2, pt, nc, NX,
-                       NY, px, py, H, W, s_r, s_v, s_d, x, t, stats);
+                    float s_d, uint16_t *x, uint16_t *t, double *stats, double *part, hipStream_t s) {
+    const long long nb = rsample_blocks(H, W);
+    hipLaunchKernelGGL(k_rsample, dim3((unsigned)nb), dim3(kRsBlock), 0, s, b, p1, p2, pt, nc, NX, NY, px, py,
+                       H, W, s_r, s_v, s_d, x, t, stats ? part : nullptr);
+    if (stats) hipLaunchKernelGGL(k_rsample_sum, dim3(1), dim3(64), 0, s, part, (int)nb, stats);
 }
 
 // A stored sample into a batch slot: the input as it is; with t, the target

@@ -526,15 +526,23 @@ pic_status pic_unet_set_periodic(pic_unet *u, int32_t periodic_w)
     return PIC_OK;
 }
 
+pic_status pic_unet_residual_sample_work_bytes(int32_t H, int32_t W, size_t *bytes)
+{
+    if (!bytes || H < 1 || W < 1) return PIC_ERR_ARG;
+    *bytes = (size_t)rsample_blocks(H, W) * 3 * sizeof(double);
+    return PIC_OK;
+}
+
 pic_status pic_unet_residual_sample(const double *b, const double *phi_1, const double *phi_2,
                                     const double *phi_t, const uint8_t *node_cond, int32_t NX, int32_t NY,
                                     int32_t periodic_x, int32_t periodic_y, int32_t H, int32_t W, float s_r,
                                     float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats,
-                                    void *stream)
+                                    void *work, size_t work_bytes, void *stream)
 {
     if (!b || !phi_1 || !node_cond || !x || H < 1 || W < 1 || H > NX || W > NY || (t && !phi_t)) return PIC_ERR_ARG;
+    if (stats && (!work || work_bytes < (size_t)rsample_blocks(H, W) * 3 * sizeof(double))) return PIC_ERR_ARG;
     launch_rsample(b, phi_1, phi_2, phi_t, node_cond, NX, NY, periodic_x ? 1 : 0, periodic_y ? 1 : 0, H, W,
-                   s_r, s_v, s_d, x, t, stats, static_cast<hipStream_t>(stream));
+                   s_r, s_v, s_d, x, t, stats, static_cast<double *>(work), static_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? PIC_OK : PIC_ERR_HIP;
 }
 
@@ -573,7 +581,7 @@ pic_status pic_solve_learned_residual(pic_ctx *ctx, pic_unet *u, float s_r, floa
     // the right-hand side and the potentials were written on the context's stream
     if ((st = after_stream(u, v.stream)) != PIC_OK) return st;
     launch_rsample(v.b, v.phi, v.phi_prev, nullptr, v.node_cond, v.NX, v.NY, v.px, v.py, u->H, u->W, s_r, s_v,
-                   s_d, u->x, nullptr, nullptr, u->stream);
+                   s_d, u->x, nullptr, nullptr, nullptr, u->stream);
     if ((st = pic_unet_forward(u)) != PIC_OK) return st;
     launch_rguess(u->out, v.phi, v.phi_prev, v.node_cond, v.NX, v.NY, u->H, u->W, s_d, 1, guess, u->stream);
     UCHK(u, hipGetLastError());

@@ -21,7 +21,8 @@ UNET_ENTRY_POINTS = ["pic_unet_param_count", "pic_unet_layer_info", "pic_unet_wo
                      "pic_unet_create", "pic_unet_io_buffers", "pic_unet_params_changed",
                      "pic_unet_forward", "pic_unet_loss", "pic_unet_backward", "pic_unet_adam",
                      "pic_unet_snapshot", "pic_unet_guess", "pic_solve_learned",
-                     "pic_unet_set_periodic", "pic_unet_residual_sample", "pic_unet_load",
+                     "pic_unet_set_periodic", "pic_unet_residual_sample_work_bytes",
+                     "pic_unet_residual_sample", "pic_unet_load",
                      "pic_unet_residual_guess", "pic_solve_learned_residual",
                      "pic_unet_set_timing", "pic_unet_forward_timing", "pic_unet_destroy",
                      "pic_unet_last_error"]
@@ -61,8 +62,9 @@ def lib():
     L.pic_unet_guess.argtypes = [P, i32, P, P, i32, i32, f32, P]
     L.pic_solve_learned.argtypes = [P, P, P, f32, f32, f32, P, C.POINTER(pic_solve_info)]
     L.pic_unet_set_periodic.argtypes = [P, i32]
+    L.pic_unet_residual_sample_work_bytes.argtypes = [i32, i32, C.POINTER(C.c_size_t)]
     L.pic_unet_residual_sample.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, i32, f32, f32, f32, P, P,
-                                           P, P]
+                                           P, P, C.c_size_t, P]
     L.pic_unet_load.argtypes = [P, i32, P, P]
     L.pic_unet_residual_guess.argtypes = [P, i32, P, P, P, i32, i32, f32, i32, P]
     L.pic_solve_learned_residual.argtypes = [P, P, f32, f32, f32, P, C.POINTER(pic_solve_info)]
@@ -295,9 +297,15 @@ def residual_sample(b, phi_1, phi_2, phi_t, node_map, periodic, H, W, scales, x,
     def vp(a):
         return C.c_void_p(a.data_ptr()) if a is not None else None
 
+    work, nbytes = None, 0
+    if stats is not None:
+        nb = C.c_size_t(0)
+        lib().pic_unet_residual_sample_work_bytes(int(H), int(W), C.byref(nb))
+        nbytes = nb.value
+        work = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
     st = lib().pic_unet_residual_sample(vp(b), vp(phi_1), vp(phi_2), vp(phi_t), C.c_void_p(ptr), NX, NY,
                                         int(periodic[0]), int(periodic[1]), int(H), int(W), float(s_r),
-                                        float(s_v), float(s_d), vp(x), vp(t), vp(stats),
+                                        float(s_v), float(s_d), vp(x), vp(t), vp(stats), vp(work), nbytes,
                                         C.c_void_p(stream.cuda_stream))
     if st != PIC_OK:
         raise PicError(st, "pic_unet_residual_sample: bad window, pointer or launch")
