@@ -160,6 +160,23 @@ pic_status pic_unet_residual_sample(const double *b, const double *phi_1, const 
                                     float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats,
                                     void *work, size_t work_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sample and statistics as pic_unet_residual_sample, bit for bit, without
+ * the work array.  The per-block partial sums live in a static device array
+ * of the library (384 KiB per device, held until the process ends), so
+ * with stats the window may hold at most 4,194,304 pixels (H * W; 16384
+ * blocks of 256): larger windows return PIC_ERR_CAPACITY and launch
+ * nothing.  The stream must belong to the current device (PIC_ERR_ARG
+ * otherwise).  Allocates nothing.  Every call on a device shares that
+ * device's array: calls that overlap on one device (two streams, or two
+ * host threads) race and must be serialised by the caller. */
+pic_status pic_unet_residual_sample_noalloc(const double *b, const double *phi_1, const double *phi_2,
+                                            const double *phi_t, const uint8_t *node_cond, int32_t NX,
+                                            int32_t NY, int32_t periodic_x, int32_t periodic_y, int32_t H,
+                                            int32_t W, float s_r, float s_v, float s_d, uint16_t *x, uint16_t *t,
+                                            double *stats, void *stream);
+
 /* Copies a stored sample (x, t as written by pic_unet_residual_sample for
  * this network's H x W) into batch slot `slot`: the input, and with t the
  * training target (as float32) and the loss mask (the free-node channel). */

@@ -98,6 +98,12 @@ long long rsample_blocks(int H, int W);
 void launch_rsample(const double *b, const double *p1, const double *p2, const double *pt,
                     const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r, float s_v,
                     float s_d, uint16_t *x, uint16_t *t, double *stats, double *part, hipStream_t s);
+// The same with the partial sums in the library's static device scratch
+// (no work array); with stats, windows of at most rsample_static_max_pixels().
+long long rsample_static_max_pixels();
+hipError_t launch_rsample_static(const double *b, const double *p1, const double *p2, const double *pt,
+                                 const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r,
+                                 float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats, hipStream_t s);
 void launch_load(const uint16_t *xs, const uint16_t *ts, long long P, uint16_t *x, float *target, float *mask,
                  hipStream_t s);
 void launch_rguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX, int NY,

@@ -13,6 +13,8 @@
 // added in a fixed order (deterministic).
 #include "unet_internal.h"
 
+#include <mutex>
+
 namespace unet {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -741,6 +743,51 @@ void launch_rsample(const double *b, const double *p1, const double *p2, const d
     hipLaunchKernelGGL(k_rsample, dim3((unsigned)nb), dim3(kRsBlock), 0, s, b, p1, p2, pt, nc, NX, NY, px, py,
                        H, W, s_r, s_v, s_d, x, t, stats ? part : nullptr);
     if (stats) hipLaunchKernelGGL(k_rsample_sum, dim3(1), dim3(64), 0, s, part, (int)nb, stats);
+}
+
+// ---- the residual sample without a caller work array ------------------------
+// Its per-block partial sums live in `scratch`, a file-scope device array that
+// every call on a device shares (each device holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel: the
+// device address comes from hipGetSymbolAddress, looked up once per device
+// with that device current.  Every block writes its three partials before
+// they are summed, so nothing needs clearing between calls; calls that
+// overlap on one device race on the array.
+constexpr long long kScratchBlocks = 16384;                 // 4,194,304 pixels of 256-pixel blocks
+static __device__ __align__(256) double scratch[3 * kScratchBlocks];   // 384 KiB
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double *g_scratch_ptr[kMaxDevices] = {};
+}
+
+long long rsample_static_max_pixels() { return kScratchBlocks * kRsBlock; }
+
+hipError_t launch_rsample_static(const double *b, const double *p1, const double *p2, const double *pt,
+                                 const uint8_t *nc, int NX, int NY, int px, int py, int H, int W, float s_r,
+                                 float s_v, float s_d, uint16_t *x, uint16_t *t, double *stats, hipStream_t s) {
+    double *part = nullptr;
+    if (stats) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (s) {
+            hipDevice_t sd = 0;
+            if ((e = hipStreamGetDevice(s, &sd)) != hipSuccess) return e;
+            if (sd != dev) return hipErrorInvalidDevice;      // the lookup needs the stream's device current
+        }
+        if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void *ptr = nullptr;
+            if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+            g_scratch_ptr[dev] = static_cast<double *>(ptr);
+        }
+        part = g_scratch_ptr[dev];
+    }
+    launch_rsample(b, p1, p2, pt, nc, NX, NY, px, py, H, W, s_r, s_v, s_d, x, t, stats, part, s);
+    return hipGetLastError();
 }
 
 // A stored sample into a batch slot: the input as it is; with t, the target

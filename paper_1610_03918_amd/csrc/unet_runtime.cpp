@@ -546,6 +546,21 @@ pic_status pic_unet_residual_sample(const double *b, const double *phi_1, const 
     return hipGetLastError() == hipSuccess ? PIC_OK : PIC_ERR_HIP;
 }
 
+pic_status pic_unet_residual_sample_noalloc(const double *b, const double *phi_1, const double *phi_2,
+                                            const double *phi_t, const uint8_t *node_cond, int32_t NX,
+                                            int32_t NY, int32_t periodic_x, int32_t periodic_y, int32_t H,
+                                            int32_t W, float s_r, float s_v, float s_d, uint16_t *x, uint16_t *t,
+                                            double *stats, void *stream)
+{
+    if (!b || !phi_1 || !node_cond || !x || H < 1 || W < 1 || H > NX || W > NY || (t && !phi_t)) return PIC_ERR_ARG;
+    if (stats && (long long)H * W > rsample_static_max_pixels()) return PIC_ERR_CAPACITY;
+    hipError_t e = launch_rsample_static(b, phi_1, phi_2, phi_t, node_cond, NX, NY, periodic_x ? 1 : 0,
+                                         periodic_y ? 1 : 0, H, W, s_r, s_v, s_d, x, t, stats,
+                                         static_cast<hipStream_t>(stream));
+    if (e == hipErrorInvalidDevice) return PIC_ERR_ARG;
+    return e == hipSuccess ? PIC_OK : PIC_ERR_HIP;
+}
+
 pic_status pic_unet_load(pic_unet *u, int32_t slot, const uint16_t *x, const uint16_t *t)
 {
     if (!u) return PIC_ERR_ARG;

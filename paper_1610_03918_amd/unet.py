@@ -22,7 +22,7 @@ UNET_ENTRY_POINTS = ["pic_unet_param_count", "pic_unet_layer_info", "pic_unet_wo
                      "pic_unet_forward", "pic_unet_loss", "pic_unet_backward", "pic_unet_adam",
                      "pic_unet_snapshot", "pic_unet_guess", "pic_solve_learned",
                      "pic_unet_set_periodic", "pic_unet_residual_sample_work_bytes",
-                     "pic_unet_residual_sample", "pic_unet_load",
+                     "pic_unet_residual_sample", "pic_unet_residual_sample_noalloc", "pic_unet_load",
                      "pic_unet_residual_guess", "pic_solve_learned_residual",
                      "pic_unet_set_timing", "pic_unet_forward_timing", "pic_unet_destroy",
                      "pic_unet_last_error"]
@@ -65,6 +65,8 @@ def lib():
     L.pic_unet_residual_sample_work_bytes.argtypes = [i32, i32, C.POINTER(C.c_size_t)]
     L.pic_unet_residual_sample.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, i32, f32, f32, f32, P, P,
                                            P, P, C.c_size_t, P]
+    L.pic_unet_residual_sample_noalloc.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, i32, f32, f32, f32,
+                                                   P, P, P, P]
     L.pic_unet_load.argtypes = [P, i32, P, P]
     L.pic_unet_residual_guess.argtypes = [P, i32, P, P, P, i32, i32, f32, i32, P]
     L.pic_solve_learned_residual.argtypes = [P, P, f32, f32, f32, P, C.POINTER(pic_solve_info)]
