@@ -103,7 +103,16 @@ def cpu_baseline(w, parts):
         n_steps += 1
     rate = done / t_steps
     log(f"oracle: start {t1 - t0:.1f}s, {n_steps} steps in {t_steps:.2f}s ({done / n_steps:.0f} particles per step)")
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_cores_available": len(os.sched_getaffinity(0)),
             "sample": f"{n_steps} full steps of {w.name} ({done // n_steps} particles, {w.nx}x{w.ny} cells) "
                       f"after the oracle's start (sparse LU factorisation excluded), "
                       f"{t_steps:.1f} s of CPU time on one thread"}
@@ -122,33 +131,86 @@ def flops_per_inference(H, W):
 
 
 def learned_start(w, pic, parts, args):
-    """Plain masked CG to the workload's tolerance on held-out snapshots of
-    this run, from a cold start and from the U-Net's prediction (inference
-    included); the network is first trained on earlier snapshots of the same
-    run with the library's forward / backward / Adam kernels."""
+    """The learned warm start (residual learning): the network corrects the
+    solver's linearly extrapolated start.  Training samples come from this
+    trench run (after the timed steps) and from the 16-width sweep (its
+    1024 x 512, 512 x 256 and 256 x 128 instances, one network per window
+    size over shared parameters); training uses the library's forward /
+    backward / Adam kernels.  Then plain masked CG to the workload's
+    tolerance on held-out problems of the trench run from four starts: cold,
+    previous potential, linear extrapolation, extrapolation + network
+    (inference included)."""
     import numpy as np
     import torch
 
-    from paper_1610_03918_amd import Pic, learned
-    from paper_1610_03918_amd.unet import UNet
-    t0 = time.perf_counter()
-    train = learned.collect(pic, args.learn_snapshots)
-    for _ in range(8):
-        pic.pic_step(1)
-    evals = learned.collect(pic, args.learn_evals + 1)
-    sc = learned.scales(w, train, pic.node_map_host())
+    import synth
+    from paper_1610_03918_amd import Pic, PicBatch, learned
+    from paper_1610_03918_amd.unet import UNet, residual_sample
+    dev = torch.device("cuda:0")
     H, W = learned.window(w)
-    net = UNet(args.learn_batch, H, W, seed=5)
+    t0 = time.perf_counter()
+    # scales: powers of two near the inverse RMS of the residual and of the gap
+    probe = []
+    learned.run_and_sample(pic, 12, {}, (1.0, 1.0, 1.0), keep=probe)
+    stats = torch.zeros(3, dtype=torch.float64, device=dev)
+    x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
+    tt = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
+    for b, p1, p2, pn in probe:
+        residual_sample(b, p1, p2, pn, pic.pic_node_map(), (int(w.periodic_x), int(w.periodic_y)), H, W,
+                        (1.0, 1.0, 1.0), x, tt, stats)
+    st = stats.cpu().numpy()
+    amp = float(np.max(np.abs(np.asarray(w.v_amp, np.float64)))) or 1.0
+    sc = (learned.pow2_scale(np.sqrt(st[0] / st[2])), float(np.float32(1.0 / amp)),
+          learned.pow2_scale(np.sqrt(st[1] / st[2])))
+    del probe
+    stores = {(H, W): learned.SampleStore(torch, dev, H, W, args.learn_trench_steps)}
+    learned.run_and_sample(pic, args.learn_trench_steps + 2, stores, sc)
+    learned.run_and_sample(pic, 50, {}, sc)                     # a gap before the held-out problems
+    problems = []
+    learned.run_and_sample(pic, 5 * args.learn_evals, {}, sc, keep=problems, every=5)
+    n_trench = stores[(H, W)].n
     t1 = time.perf_counter()
-    losses = learned.train(net, train, pic.pic_node_map(), sc, steps=args.learn_steps, lr=2e-3, seed=2)
+    # the 16-width sweep (batched form), eager steps after a short spin-up
+    n_sweep = 0
+    if args.learn_sweep_steps > 0:
+        ws = synth.sweep()
+        sw = PicBatch(ws, [synth.load(q) for q in ws], sort_interval=(16, 128))
+        sw.start()
+        sw.pic_step(args.learn_sweep_spinup)
+        caps = {}
+        for q in ws:
+            caps[learned.window(q)] = caps.get(learned.window(q), 0) + args.learn_sweep_steps
+        for k, c in caps.items():
+            if k in stores:
+                old = stores[k]
+                new = learned.SampleStore(torch, dev, k[0], k[1], old.n + c)
+                new.x[:old.n].copy_(old.x[:old.n])
+                new.t[:old.n].copy_(old.t[:old.n])
+                new.n = old.n
+                stores[k] = new
+                del old
+            else:
+                stores[k] = learned.SampleStore(torch, dev, k[0], k[1], c)
+        before = sum(s_.n for s_ in stores.values())
+        learned.run_and_sample_batch(sw, args.learn_sweep_steps + 2, stores, sc)
+        n_sweep = sum(s_.n for s_ in stores.values()) - before
+        sw.close()
+        del sw
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    log(f"learned start: {len(train)} snapshots in {t1 - t0:.1f}s, {args.learn_steps} training steps "
-        f"in {t2 - t1:.1f}s, loss {np.mean(losses[:5]):.3e} -> {np.mean(losses[-10:]):.3e}")
-    u1 = UNet(1, H, W, params=net.params)
-    net.close()
-    del train
-    u1.pic_unet_snapshot(0, evals[0][0], None, pic.pic_node_map(), sc)
+    nets, main = learned.make_nets(stores, args.learn_batch * H * W, seed=5)
+    losses = learned.train(nets, main, stores, args.learn_steps, lr=2e-3, seed=2)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    log(f"learned start: {n_trench} trench + {n_sweep} sweep samples in {t2 - t0:.1f}s "
+        f"({', '.join(f'{k[0]}x{k[1]}: {v.n}' for k, v in stores.items())}), {args.learn_steps} training steps "
+        f"in {t3 - t2:.1f}s, loss {np.mean(losses[:5]):.3e} -> {np.mean(losses[-10:]):.3e}")
+    u1 = UNet(1, H, W, params=main.params, periodic_w=True)
+    for n_ in nets.values():
+        n_.close()
+    del stores
+    torch.cuda.empty_cache()
+    u1.input().zero_()
     u1.pic_unet_forward()
     u1.pic_unet_set_timing(True)
     for _ in range(20):
@@ -157,35 +219,38 @@ def learned_start(w, pic, parts, args):
     u1.pic_unet_set_timing(False)
     few = [{f: p[f][:4096] for f in p} for p in parts]
     cg = Pic(w, few, solver=1, max_iter=50000)
-    rows = learned.evaluate(cg, u1, evals, sc, torch)
+    rows = learned.evaluate(cg, u1, problems, sc, torch)
     cg.close()
     u1.close()
-    rows = rows[1:]
     for r in rows:
-        log(f"  cold {r['cold']['iterations']} it {r['cold']['ms']:.1f} ms | prev {r['prev']['iterations']} it "
-            f"{r['prev']['ms']:.1f} ms | learned {r['learned']['iterations']} it {r['learned']['ms']:.1f} ms "
-            f"(relres0 {r['learned']['relres0']:.3g}) | max diff {r['max_diff']:.2e}")
+        log("  " + " | ".join(f"{k} {r[k]['iterations']} it {r[k]['ms']:.1f} ms (relres0 {r[k]['relres0']:.2g})"
+                              for k in ("cold", "prev", "ext", "learned")) + f" | max diff {r['max_diff']:.2e}")
 
     def mean(kind, key):
         return float(np.mean([r[kind][key] for r in rows]))
 
     fl = flops_per_inference(H, W)
     tf = fl / (fwd_ms * 1e-3) / 1e12
+    kinds = ("cold", "prev", "ext", "learned")
     return {
         "solver": f"plain masked CG (float64 refinement of float32 CG), rtol {w.rtol:g}",
-        "snapshots_evaluated": len(rows),
-        "cold": {"iterations": mean("cold", "iterations"), "ms": mean("cold", "ms")},
-        "previous_step": {"iterations": mean("prev", "iterations"), "ms": mean("prev", "ms")},
-        "learned": {"iterations": mean("learned", "iterations"), "ms": mean("learned", "ms"),
-                    "relres0": float(np.median([r["learned"]["relres0"] for r in rows]))},
+        "start": "residual learning: network(residual of 2 phi_{n-1} - phi_{n-2}) corrects that start",
+        "problems_evaluated": len(rows),
+        **{k: {"iterations": mean(k, "iterations"), "ms": mean(k, "ms"),
+               "relres0": float(np.median([r[k]["relres0"] for r in rows]))} for k in kinds},
         "iterations_cold_over_learned": mean("cold", "iterations") / mean("learned", "iterations"),
+        "iterations_ext_over_learned": mean("ext", "iterations") / mean("learned", "iterations"),
+        "iterations_cold_over_ext": mean("cold", "iterations") / mean("ext", "iterations"),
         "ms_cold_over_learned": mean("cold", "ms") / mean("learned", "ms"),
-        "all_converged": all(r[k]["converged"] for r in rows for k in ("cold", "prev", "learned")),
+        "target_cold_over_learned": 3.0,
+        "all_converged": all(r[k]["converged"] for r in rows for k in kinds),
         "max_solution_diff_over_scale": max(r["max_diff"] / r["scale"] for r in rows),
-        "training": {"snapshots": args.learn_snapshots, "steps": args.learn_steps,
-                     "batch": args.learn_batch, "loss_first": float(np.mean(losses[:5])),
-                     "loss_last": float(np.mean(losses[-10:])), "seconds": t2 - t1},
-        "unet": {"pixels": [H, W], "forward_ms": fwd_ms, "gflop_per_inference": fl / 1e9,
+        "training": {"samples_trench1024x512": n_trench, "samples_sweep16": n_sweep,
+                     "sample_windows": sorted({f"{k[0]}x{k[1]}" for k in nets}), "steps": args.learn_steps,
+                     "batch_pixels": args.learn_batch * H * W, "scales": list(sc),
+                     "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-10:])),
+                     "seconds_sampling": t2 - t0, "seconds_training": t3 - t2},
+        "unet": {"pixels": [H, W], "periodic_w": True, "forward_ms": fwd_ms, "gflop_per_inference": fl / 1e9,
                  "roofline": {"bound": "mfma", "achieved": tf, "peak": BF16_PEAK_TFLOPS,
                               "unit": "TFLOP/s", "frac": tf / BF16_PEAK_TFLOPS}},
     }
@@ -358,14 +423,15 @@ def run_trench_study_batched(args):
     step = warm
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    converged = True
+    unconv0 = [b.pic_batch_solve_info(i)["unconverged_pushes"] for i in range(b.n)]
     for target in (6000, 7000, ws[0].steps):
-        infos = b.pic_batch_step(target - step, passes, iters, later)
-        converged = converged and all(x["converged"] for x in infos)
+        infos = b.pic_batch_step(target - step, passes, iters, later, allow_unconverged=True)
         step = target
         tallies[target] = [b.pic_batch_diagnostics(i)["tally"][1] for i in range(b.n)]
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / (step - warm)
+    unconverged = sum(x["unconverged_pushes"] - u for x, u in zip(infos, unconv0))
+    converged = unconverged == 0
     b.close()
     rows = []
     for i, (w, (_, _, t_from)) in enumerate(zip(ws, cases)):
@@ -380,6 +446,7 @@ def run_trench_study_batched(args):
     print(json.dumps({"metric": "ions reaching the trench bottom and sidewalls (Sec. III.C-D), batched",
                       "n_gpus": 1, "data": "synthetic", "seed": args.study_seed,
                       "ms_per_step_three_instances": ms, "all_converged": converged,
+                      "unconverged_pushes": unconverged,
                       "solver_schedule": {"passes": passes, "iters_first": iters, "iters_later": later},
                       "results": rows}), flush=True)
 
@@ -413,16 +480,20 @@ def run_sweep(args):
                  push_merge=sch["push_merge"], tile=tuple(sch["tile"]), halo=sch["halo"])
     b.start()
     # eager steps tell how many passes and iterations the captured schedule needs
-    passes, iters, iters_later = autotune.solver_schedule(b, args.warmup)
-    b.pic_batch_step(sort[0] if sort[0] > 0 else 8, passes, iters, iters_later)
+    # (after the spin-up steps, which bring the instances to their long-run state)
+    passes, iters, iters_later = autotune.solver_schedule(b, args.spinup + args.warmup)
+    infos = b.pic_batch_step(sort[0] if sort[0] > 0 else 8, passes, iters, iters_later, allow_unconverged=True)
+    unconv0 = [x["unconverged_pushes"] for x in infos]
     torch.cuda.synchronize()
     a0 = sum(sum(b.pic_batch_diagnostics(i)["alive"]) for i in range(b.n))
+    start_step = b.pic_batch_diagnostics(0)["step"]
     t0 = time.perf_counter()
-    infos = b.pic_batch_step(args.steps, passes, iters, iters_later)
+    infos = b.pic_batch_step(args.steps, passes, iters, iters_later, allow_unconverged=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     a1 = sum(sum(b.pic_batch_diagnostics(i)["alive"]) for i in range(b.n))
-    conv = all(x["converged"] for x in infos)
+    unconverged = sum(x["unconverged_pushes"] - u for x, u in zip(infos, unconv0))
+    conv = unconverged == 0
     value = 0.5 * (a0 + a1) * args.steps / (t1 - t0)
     out = {"metric": "particle-steps/s (push+deposit+solve)", "value": value,
            "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -431,7 +502,8 @@ def run_sweep(args):
            "config": {"workload": "trench-width sweep x16 (batched, graph-captured)",
                       "widths": list(synth.SWEEP_WIDTHS), "ppc": ws[0].species[0].ppc,
                       "particles": int(n0), "solver_schedule": {"passes": passes, "iters_first": iters, "iters_later": iters_later},
-                      "all_converged": conv, "schedule": sch, "schedule_source": source}}
+                      "all_converged": conv, "unconverged_pushes": unconverged,
+                      "timed_from_step": start_step, "schedule": sch, "schedule_source": source}}
     b.close()
     print(json.dumps(out), flush=True)
 
@@ -475,8 +547,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=400,
-                    help="untimed steps first: the sheath forms and the push settles to its long-run rate")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed steps before the timed ones")
+    ap.add_argument("--spinup", type=int, default=400,
+                    help="steps that bring the trench workload to its long-run state (the sheath forms, the "
+                         "electrons heat and the push settles to its long-run rate) before the warm-up steps")
     ap.add_argument("--workload", default="trench1024x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unet-only", action="store_true",
@@ -501,10 +575,14 @@ def main():
                     help="ignore a cached autotuned schedule for the workload")
     ap.add_argument("--autotune", action="store_true",
                     help="sweep: tune the schedule when the cache has no entry for the batch")
-    ap.add_argument("--learn-snapshots", type=int, default=128)
-    ap.add_argument("--learn-steps", type=int, default=2000)
-    ap.add_argument("--learn-batch", type=int, default=4)
-    ap.add_argument("--learn-evals", type=int, default=3)
+    ap.add_argument("--learn-trench-steps", type=int, default=4000,
+                    help="training samples from the trench run (one per step)")
+    ap.add_argument("--learn-sweep-steps", type=int, default=250,
+                    help="eager steps of the 16-width sweep sampled (16 samples per step)")
+    ap.add_argument("--learn-sweep-spinup", type=int, default=100)
+    ap.add_argument("--learn-steps", type=int, default=4000, help="training steps")
+    ap.add_argument("--learn-batch", type=int, default=4, help="batch, in 1024 x 512 images")
+    ap.add_argument("--learn-evals", type=int, default=20, help="held-out problems")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "multi-GPU runs are not implemented: this benchmark measures one GPU",
@@ -550,9 +628,16 @@ def main():
     pic = Pic(w, parts, device="cuda:0", **opts)
     info0 = pic.start()
     log(f"start solve: {info0}")
+    spinup = args.spinup if w.name.startswith("trench") else 0
+    t_spin = time.perf_counter()
+    pic.pic_step(spinup)
+    torch.cuda.synchronize()
+    if spinup:
+        log(f"spin-up: {spinup} steps in {time.perf_counter() - t_spin:.1f}s")
     pic.pic_step(args.warmup)
     torch.cuda.synchronize()
     d0 = pic.pic_diagnostics()
+    start_step = int(d0["step"])
     # timed region: the library's own step loop (solve, field, push, deposit,
     # assembly, re-binning when due), no host work between steps
     pic.pic_set_timing(True)
@@ -603,7 +688,8 @@ def main():
                    "particles": n0, "dt": w.dt, "rtol": w.rtol, "sort_interval": list(sort),
                    "tile": list(tile), "chunk": args.chunk, "halo": args.halo,
                    "push_unroll": args.unroll, "push_merge": args.merge, "warm_start": args.warm,
-                   "schedule_source": schedule_source},
+                   "schedule_source": schedule_source, "spinup_steps": spinup,
+                   "timed_from_step": start_step},
         "poisson_ms_per_step": 1e3 * solve_t / nps,
         "poisson_iters_per_step": iters / nps,
         "poisson_steps": nps,
@@ -612,6 +698,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "kernel": f"k_push<true,{args.unroll},{args.merge}>", "avg_launch_ms": push_ms, "launches": launches,
+                     "steps_measured": [start_step, start_step + args.steps],
                      "bytes_per_launch": per_launch * BYTES_PER_PARTICLE_STEP,
                      "plain_copy_GBs": copy_gbs, "frac_of_plain_copy": achieved / copy_gbs},
     }
