@@ -44,3 +44,38 @@ def gpu_state(pic, s):
 def live(p):
     m = p["cell"] >= 0
     return {k: v[m] for k, v in p.items()}
+
+
+_M1, _M2 = np.uint64(0xBF58476D1CE4E5B9), np.uint64(0x94D049BB133111EB)
+
+
+def _mix64(z):
+    """splitmix64's finaliser (Steele, Lea and Flood, OOPSLA 2014), wrapping uint64."""
+    z = (z ^ (z >> np.uint64(30))) * _M1
+    z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def multiset_hash(p, chunk=1 << 23):
+    """Order-free digest of the rows of the five state arrays: the wrapping
+    uint64 sum and the wrapping sum of squares of a 64-bit hash of each row
+    (cell code and the float32 bits of ox, oy, vx, vy; every NaN counted as
+    one canonical NaN).  Equal multisets give equal digests; a row that
+    differs in any bit changes them except with probability ~2^-64."""
+    n = int(p["cell"].size)
+    s1 = np.uint64(0)
+    s2 = np.uint64(0)
+    with np.errstate(over="ignore"):
+        for a in range(0, n, chunk):
+            cols = []
+            for f in FIELDS:
+                x = np.ascontiguousarray(p[f][a:a + chunk])
+                if x.dtype != np.int32:
+                    x = np.where(np.isnan(x), np.float32(np.nan), x).astype(np.float32).view(np.int32)
+                cols.append(x.view(np.uint32).astype(np.uint64))
+            h = _mix64(cols[0] | (cols[1] << np.uint64(32)))
+            h = _mix64(h ^ (cols[2] | (cols[3] << np.uint64(32))))
+            h = _mix64(h + cols[4] + np.uint64(0x9E3779B97F4A7C15))
+            s1 = s1 + h.sum(dtype=np.uint64)
+            s2 = s2 + (h * h).sum(dtype=np.uint64)
+    return n, int(s1), int(s2)

@@ -107,3 +107,38 @@ def test_graph_steps_track_eager_steps():
         assert np.max(np.abs(pg - pe)) <= 1e-4 * max(1.0, np.max(np.abs(pe)))
     g.close()
     e.close()
+
+
+def test_batched_push_matches_oracle_on_identical_potential():
+    """One batched push (the launch a batched step makes after its solve) on
+    a potential given to both sides: every instance's particles, charge,
+    wall tallies and trench-bottom counts equal the oracle's float32 push
+    bit for bit (Sec. II eqs. 1-4, the wall test of Sec. III.A)."""
+    from paper_1610_03918_amd import PicBatch
+    ws = mixed_batch()
+    parts = [synth.load(w) for w in ws]
+    b = PicBatch(ws, parts, sort_interval=(4, 8))
+    fields = []
+    for i, w in enumerate(ws):
+        nc = oracle.node_cond(w)
+        phi = synth.random_potential(w, 60 + i, scale=2.0)
+        phi[nc != 0] = oracle.voltages(w, 0.0)[nc[nc != 0]]
+        b.phi(i).copy_(b.torch.from_numpy(phi))
+        fields.append(oracle.field(w, nc, phi))
+    b.pic_push()
+    for i, w in enumerate(ws):
+        Ex, Ey = fields[i]
+        tally = np.zeros((2, 9), np.int64)
+        surf = np.zeros(w.ny, np.int64)
+        d = b.pic_batch_diagnostics(i)
+        for s in range(2):
+            q = {k: v.copy() for k, v in parts[i][s].items()}
+            oracle.push(w, s, q, Ex, Ey, "f32", tally[s], surf if (w.charge_mode == 2 and s == 1) else None)
+            got = b.particles_numpy(i, s)
+            assert np.array_equal(canonical(live(got)), canonical(live(q))), f"instance {i} species {s}"
+            assert np.array_equal(b.rho(i, s).cpu().numpy(), oracle.deposit(w, q)), f"instance {i} species {s}"
+            assert d["alive"][s] == int(np.count_nonzero(q["cell"] >= 0))
+        assert np.array_equal(np.array(d["tally"]), tally), (i, d["tally"], tally)
+        assert d["surf_hits"] == int(surf.sum())
+    assert sum(sum(map(sum, b.pic_batch_diagnostics(i)["tally"])) for i in range(len(ws))) > 0
+    b.close()

@@ -6,13 +6,17 @@ Every integer result is compared in full, bit for bit: the charge of both
 species at load, the assembled right-hand side, and, after one push on the
 oracle's exact potential, the wall tallies, the trench-bottom counts and
 the charge of the pushed particles (which sums every particle's new cell and
-quantised offsets).  The potential is compared with the exact sparse-direct
-solution of the same right-hand side."""
+quantised offsets).  All five state arrays of every particle still alive are
+compared as multisets through an order-free 64-bit digest (the device keeps
+its own order), so an error in a velocity or below the 2^-16 offset quantum
+of the charge is seen too.  The potential is compared with the exact
+sparse-direct solution of the same right-hand side."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from gpu_util import live, multiset_hash
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -51,7 +55,10 @@ def test_full_size_trench_load_solve_and_push_match_oracle():
         rho_new.append(oracle.deposit(w, q))
         assert np.array_equal(pic.rho(s).cpu().numpy(), rho_new[s]), f"species {s} charge after push"
         assert d["alive"][s] == int(np.count_nonzero(q["cell"] >= 0))
+        want = multiset_hash(live(q))
         del q
+        got = multiset_hash(live(pic.particles_numpy(s)))
+        assert got == want, f"species {s} particle states after push"
     assert np.array_equal(np.array(d["tally"]), tally)
     assert d["surf_hits"] == int(surf.sum())
     assert np.array_equal(pic.b.cpu().numpy(), oracle.assemble(w, nc, rho_new[0], rho_new[1], w.dt, surf))
