@@ -288,3 +288,89 @@ def residual_guess(out, phi_1, phi_2, node_cond, s_d, use_output=True):
         free = node_cond[:H, :W] == 0
         g[:H, :W] = np.where(free, g[:H, :W] + out / s_d, g[:H, :W])
     return g
+
+
+# ---------------------------------------------------------------------------
+# coarse residual learning: the network works on f x f blocks of nodes, so
+# that its receptive field spans the whole grid.  The smooth part of the
+# start's error is what the solver spends its iterations on; the prolonged
+# coarse correction supplies it.
+# ---------------------------------------------------------------------------
+
+def _block_sum(a, f, H, W):
+    """Sum over the f x f block of nodes (h f + p, w f + q), p, q < f, of every
+    pixel (h, w), added in the order p outer, q inner (row-major)."""
+    s = np.zeros((H, W))
+    for p in range(f):
+        for q in range(f):
+            s = s + a[p:H * f:f, q:W * f:f]
+    return s
+
+
+def coarse_residual_sample(b, phi_1, phi_2, phi_t, node_cond, f, H, W, periodic, s_r, s_v, s_d):
+    """Training sample of the coarse residual-learning start: pixel (h, w)
+    stands for the f x f block of nodes (h f .. h f + f - 1, w f .. w f + f - 1)
+    (H f <= NX, W f <= NY).  Input [H, W, 3] = (block mean of r, zero on
+    Dirichlet nodes, times s_r; fraction of free nodes; block mean of the
+    Dirichlet values, zero on free nodes, times s_v); target [H, W] = block
+    mean of (phi_t - start) on free nodes times s_d (None without phi_t).
+    Sums in the order of _block_sum, one multiply by 1/f^2, then the scale,
+    rounded to bfloat16 (the stored precision).  f = 1 gives
+    residual_sample."""
+    start = extrapolated(phi_1, phi_2)
+    r = masked_residual(b, start, node_cond, periodic)
+    free = node_cond == 0
+    inv = 1.0 / (f * f)
+    x = np.zeros((H, W, 3))
+    x[..., 0] = bf16(_block_sum(np.where(free, r, 0.0), f, H, W) * inv * s_r)
+    x[..., 1] = bf16(_block_sum(free.astype(np.float64), f, H, W) * inv)
+    x[..., 2] = bf16(_block_sum(np.where(free, 0.0, b), f, H, W) * inv * s_v)
+    t = None
+    if phi_t is not None:
+        t = bf16(_block_sum(np.where(free, phi_t - start, 0.0), f, H, W) * inv * s_d)
+    return x, t
+
+
+def _axis_weights(i, f, n, wrap):
+    """Lower pixel, upper pixel and the upper weight of node index i on an
+    axis of n pixels of f nodes: the node lies at pixel coordinate
+    (i + 1/2)/f - 1/2 (pixel centres at integers); outside [0, n - 1] the
+    pixel index wraps (wrap) or is clamped to the edge."""
+    u = (i + 0.5) / f - 0.5
+    lo = int(np.floor(u))
+    a = u - lo
+    hi = lo + 1
+    if wrap:
+        lo, hi = lo % n, hi % n
+    else:
+        lo, hi = min(max(lo, 0), n - 1), min(max(hi, 0), n - 1)
+    return lo, hi, a
+
+
+def coarse_residual_guess(out, phi_1, phi_2, node_cond, f, periodic, s_d, use_output=True):
+    """Start potential: the extrapolated start plus c / s_d on the free nodes
+    of the covered region (H f x W f nodes), c the bilinear interpolation of
+    the coarse output at the node, weights (1-a)(1-b), a(1-b), (1-a)b, ab on
+    pixels (lo_x, lo_y), (hi_x, lo_y), (lo_x, hi_y), (hi_x, hi_y) added in that
+    order; an axis wraps when it is periodic and covered exactly (n f nodes),
+    else is clamped.  Elsewhere the extrapolation alone."""
+    g = extrapolated(phi_1, phi_2)
+    if not use_output:
+        return g
+    H, W = out.shape
+    NX, NY = g.shape
+    wx = bool(periodic[0]) and H * f == NX
+    wy = bool(periodic[1]) and W * f == NY
+    o = np.asarray(out, np.float64)
+    for i in range(H * f):
+        h0, h1, a = _axis_weights(i, f, H, wx)
+        for j in range(W * f):
+            if node_cond[i, j] != 0:
+                continue
+            v0, v1, bq = _axis_weights(j, f, W, wy)
+            c = (1 - a) * (1 - bq) * o[h0, v0]
+            c = c + a * (1 - bq) * o[h1, v0]
+            c = c + (1 - a) * bq * o[h0, v1]
+            c = c + a * bq * o[h1, v1]
+            g[i, j] = g[i, j] + c / s_d
+    return g

@@ -395,3 +395,97 @@ def test_residual_sample_and_guess_by_hand():
     # no earlier pair: the start is phi_1
     x1, _ = unet.residual_sample(b, exact, None, None, nc, H, W, per, 1.0, 1.0, 1.0)
     assert np.max(np.abs(x1[..., 0])) < 1e-9 * np.max(np.abs(b))
+
+
+def test_coarse_sample_and_guess_reduce_to_the_full_resolution_ones_at_f1():
+    """f = 1 (one node per pixel) gives the residual-learning sample and
+    start of the full-resolution network, bit for bit."""
+    import oracle
+    w, nc, b = _trench_problem()
+    per = (False, True)
+    exact = oracle.solve_direct(w, nc, b)
+    r = _rng(21)
+    phi_1 = exact + 0.01 * r.standard_normal(exact.shape)
+    phi_2 = exact + 0.02 * r.standard_normal(exact.shape)
+    H, W = 16, 8
+    x, t = unet.residual_sample(b, phi_1, phi_2, exact, nc, H, W, per, 2.0, 0.5, 8.0)
+    xc, tc = unet.coarse_residual_sample(b, phi_1, phi_2, exact, nc, 1, H, W, per, 2.0, 0.5, 8.0)
+    assert np.array_equal(x, xc) and np.array_equal(t, tc)
+    out = r.standard_normal((H, W)).astype(np.float32)
+    assert np.array_equal(unet.residual_guess(out, phi_1, phi_2, nc, 8.0),
+                          unet.coarse_residual_guess(out, phi_1, phi_2, nc, 1, per, 8.0))
+
+
+def test_coarse_sample_by_brute_force():
+    """Block means against a per-pixel loop over the block's nodes, on values
+    that are small dyadic numbers (every sum exact, so the order of addition
+    cannot matter): a 9 x 8 grid with a Dirichlet edge row and a conductor
+    notch, 2 x 2 blocks, start zero (so r = b on free nodes)."""
+    NX, NY, f, H, W = 9, 8, 2, 4, 3
+    nc = np.zeros((NX, NY), np.uint8)
+    nc[0, :] = 1
+    nc[5:7, 2:4] = 2
+    r = _rng(22)
+    b = r.integers(-64, 64, (NX, NY)) / 8.0
+    phi_t = r.integers(-64, 64, (NX, NY)) / 16.0
+    zero = np.zeros((NX, NY))
+    x, t = unet.coarse_residual_sample(b, zero, None, phi_t, nc, f, H, W, (False, False), 0.5, 2.0, 4.0)
+    for h in range(H):
+        for q in range(W):
+            blk = (slice(h * f, h * f + f), slice(q * f, q * f + f))
+            free = nc[blk] == 0
+            assert x[h, q, 0] == unet.bf16(0.5 * np.sum(np.where(free, b[blk], 0)) / 4)
+            assert x[h, q, 1] == np.count_nonzero(free) / 4
+            assert x[h, q, 2] == unet.bf16(2.0 * np.sum(np.where(free, 0, b[blk])) / 4)
+            assert t[h, q] == unet.bf16(4.0 * np.sum(np.where(free, phi_t[blk], 0)) / 4)
+    # the pixel of rows 0-1, columns 0-1 holds two Dirichlet nodes (row 0)
+    assert x[0, 0, 1] == 0.5
+    # the notch: nodes (5..6, 2..3) are all Dirichlet, spread over pixels (2, 1) and (3, 1)
+    assert x[2, 1, 1] == 0.5 and x[3, 1, 1] == 0.5
+
+
+def test_coarse_guess_reproduces_linear_functions_and_wraps_by_shifts():
+    """Bilinear prolongation with pixel centres at node (h + 1/2) f - 1/2:
+    a coarse output linear in (h, w) gives the same linear function of the
+    node's pixel coordinate, held at the edge pixel beyond the first and
+    last centres (clamped axis); a constant gives that constant on every
+    free node; on an axis that is periodic and covered exactly, rolling the
+    coarse output by one pixel rolls the start by f nodes."""
+    NX, NY, f, H, W = 33, 24, 4, 8, 6
+    nc = np.zeros((NX, NY), np.uint8)
+    nc[0, :] = 1
+    nc[NX - 1, :] = 2
+    nc[20:, 10:13] = 2
+    zero = np.zeros((NX, NY))
+    hh, ww = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    lin = (3.0 * hh - 2.0 * ww + 1.0).astype(np.float32)
+    g = unet.coarse_residual_guess(lin, zero, None, nc, f, (False, False), 1.0)
+    u = np.clip((np.arange(NX) + 0.5) / f - 0.5, 0, H - 1)
+    v = np.clip((np.arange(NY) + 0.5) / f - 0.5, 0, W - 1)
+    want = 3.0 * u[:, None] - 2.0 * v[None, :] + 1.0
+    cover = np.zeros((NX, NY), bool)
+    cover[:H * f, :W * f] = True
+    m = cover & (nc == 0)
+    assert np.array_equal(g[m], want[m])
+    assert np.array_equal(g[~m], zero[~m])                 # Dirichlet and uncovered nodes: the start
+    # partition of unity, also at clamped and wrapped edges
+    phi_1 = _rng(23).standard_normal((NX, NY))
+    gc = unet.coarse_residual_guess(np.full((H, W), 0.75, np.float32), phi_1, None, nc, f, (False, True), 2.0)
+    assert np.array_equal(gc[m], phi_1[m] + 0.375)
+    # periodic y (W f == NY): shift equivariance on a problem without y structure
+    nc2 = np.zeros((NX, NY), np.uint8)
+    nc2[0, :] = 1
+    nc2[NX - 1, :] = 2
+    out = _rng(24).standard_normal((H, W)).astype(np.float32)
+    g1 = unet.coarse_residual_guess(out, zero, None, nc2, f, (False, True), 1.0)
+    g2 = unet.coarse_residual_guess(np.roll(out, 1, axis=1), zero, None, nc2, f, (False, True), 1.0)
+    assert np.array_equal(np.roll(g1, f, axis=1), g2)
+    # node 0 of the periodic axis lies between the last pixel and the first:
+    # pixel coordinate 1/(2f) - 1/2 in y (weight 1/2 + 1/(2f) on pixel 0), and
+    # node 8 at 8.5/f - 1/2 in x
+    o = out.astype(np.float64)
+    a = 0.5 + 0.5 / f
+    ax = (8.5 / f - 0.5) % 1
+    row = lambda h: (1 - a) * o[h, W - 1] + a * o[h, 0]
+    h0 = int(8.5 / f - 0.5)
+    assert np.isclose(g1[8, 0], (1 - ax) * row(h0) + ax * row(h0 + 1), rtol=0, atol=1e-12)
