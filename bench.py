@@ -131,43 +131,47 @@ def flops_per_inference(H, W):
 
 
 def learned_start(w, pic, parts, args):
-    """The learned warm start (residual learning): the network corrects the
-    solver's linearly extrapolated start.  Training samples come from this
-    trench run (after the timed steps) and from the 16-width sweep (its
-    1024 x 512, 512 x 256 and 256 x 128 instances, one network per window
-    size over shared parameters); training uses the library's forward /
-    backward / Adam kernels.  Then plain masked CG to the workload's
-    tolerance on held-out problems of the trench run from four starts: cold,
-    previous potential, linear extrapolation, extrapolation + network
-    (inference included)."""
+    """The learned warm start (coarse residual learning): the network corrects
+    the solver's linearly extrapolated start on f x f blocks of nodes
+    (block means of the residual in, a block-mean correction out, prolonged
+    bilinearly onto the nodes; f = 1 is the full-resolution form).  Training
+    samples come from this trench run (after the timed steps) and from the
+    16-width sweep (its 1024 x 512, 512 x 256 and 256 x 128 instances, one
+    network per window size over shared parameters); training uses the
+    library's forward / backward / Adam kernels.  Then plain masked CG to the
+    workload's tolerance on held-out problems of the trench run from four
+    starts: cold, previous potential, linear extrapolation, extrapolation +
+    network (sample, inference and prolongation included)."""
     import numpy as np
     import torch
 
     import synth
     from paper_1610_03918_amd import Pic, PicBatch, learned
-    from paper_1610_03918_amd.unet import UNet, residual_sample
+    from paper_1610_03918_amd.unet import UNet
     dev = torch.device("cuda:0")
-    H, W = learned.window(w)
+    f = args.learn_factor
+    H, W = learned.window(w, f)
+    per = (int(w.periodic_x), int(w.periodic_y))
     t0 = time.perf_counter()
     # scales: powers of two near the inverse RMS of the residual and of the gap
     probe = []
-    learned.run_and_sample(pic, 12, {}, (1.0, 1.0, 1.0), keep=probe)
+    learned.run_and_sample(pic, 12, {}, (1.0, 1.0, 1.0), keep=probe, f=f)
     stats = torch.zeros(3, dtype=torch.float64, device=dev)
     x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
     tt = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
     for b, p1, p2, pn in probe:
-        residual_sample(b, p1, p2, pn, pic.pic_node_map(), (int(w.periodic_x), int(w.periodic_y)), H, W,
-                        (1.0, 1.0, 1.0), x, tt, stats)
+        learned.sample(f, b, p1, p2, pn, pic.pic_node_map(), per, H, W, (1.0, 1.0, 1.0), x, tt, stats)
     st = stats.cpu().numpy()
     amp = float(np.max(np.abs(np.asarray(w.v_amp, np.float64)))) or 1.0
     sc = (learned.pow2_scale(np.sqrt(st[0] / st[2])), float(np.float32(1.0 / amp)),
           learned.pow2_scale(np.sqrt(st[1] / st[2])))
     del probe
-    stores = {(H, W): learned.SampleStore(torch, dev, H, W, args.learn_trench_steps)}
-    learned.run_and_sample(pic, args.learn_trench_steps + 2, stores, sc)
-    learned.run_and_sample(pic, 50, {}, sc)                     # a gap before the held-out problems
+    stores = {(H, W): learned.SampleStore(torch, dev, H, W, args.learn_trench_samples)}
+    learned.run_and_sample(pic, args.learn_every * (args.learn_trench_samples + 2), stores, sc,
+                           every=args.learn_every, f=f)
+    learned.run_and_sample(pic, 50, {}, sc, f=f)                # a gap before the held-out problems
     problems = []
-    learned.run_and_sample(pic, 5 * args.learn_evals, {}, sc, keep=problems, every=5)
+    learned.run_and_sample(pic, 5 * args.learn_evals, {}, sc, keep=problems, every=5, f=f)
     n_trench = stores[(H, W)].n
     t1 = time.perf_counter()
     # the 16-width sweep (batched form), eager steps after a short spin-up
@@ -179,7 +183,7 @@ def learned_start(w, pic, parts, args):
         sw.pic_step(args.learn_sweep_spinup)
         caps = {}
         for q in ws:
-            caps[learned.window(q)] = caps.get(learned.window(q), 0) + args.learn_sweep_steps
+            caps[learned.window(q, f)] = caps.get(learned.window(q, f), 0) + args.learn_sweep_steps
         for k, c in caps.items():
             if k in stores:
                 old = stores[k]
@@ -192,17 +196,17 @@ def learned_start(w, pic, parts, args):
             else:
                 stores[k] = learned.SampleStore(torch, dev, k[0], k[1], c)
         before = sum(s_.n for s_ in stores.values())
-        learned.run_and_sample_batch(sw, args.learn_sweep_steps + 2, stores, sc)
+        learned.run_and_sample_batch(sw, args.learn_sweep_steps + 2, stores, sc, f=f)
         n_sweep = sum(s_.n for s_ in stores.values()) - before
         sw.close()
         del sw
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     nets, main = learned.make_nets(stores, args.learn_batch * H * W, seed=5)
-    losses = learned.train(nets, main, stores, args.learn_steps, lr=2e-3, seed=2)
+    losses = learned.train(nets, main, stores, args.learn_steps, lr=args.learn_rate, seed=2)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    log(f"learned start: {n_trench} trench + {n_sweep} sweep samples in {t2 - t0:.1f}s "
+    log(f"learned start (f = {f}): {n_trench} trench + {n_sweep} sweep samples in {t2 - t0:.1f}s "
         f"({', '.join(f'{k[0]}x{k[1]}: {v.n}' for k, v in stores.items())}), {args.learn_steps} training steps "
         f"in {t3 - t2:.1f}s, loss {np.mean(losses[:5]):.3e} -> {np.mean(losses[-10:]):.3e}")
     u1 = UNet(1, H, W, params=main.params, periodic_w=True)
@@ -217,11 +221,13 @@ def learned_start(w, pic, parts, args):
         u1.pic_unet_forward()
     fwd_ms, _ = u1.pic_unet_forward_timing()
     u1.pic_unet_set_timing(False)
-    few = [{f: p[f][:4096] for f in p} for p in parts]
+    few = [{k: p[k][:4096] for k in p} for p in parts]
     cg = Pic(w, few, solver=1, max_iter=50000)
-    rows = learned.evaluate(cg, u1, problems, sc, torch)
-    cg.close()
+    rows = learned.evaluate(cg, u1, problems, sc, torch, f=f)
     u1.close()
+    bound = learned.coarse_bound(cg, problems[:args.learn_bound_problems], (4, 8, 16), torch)
+    cg.close()
+    log(f"  exact coarse targets (mean iterations): {bound}")
     for r in rows:
         log("  " + " | ".join(f"{k} {r[k]['iterations']} it {r[k]['ms']:.1f} ms (relres0 {r[k]['relres0']:.2g})"
                               for k in ("cold", "prev", "ext", "learned")) + f" | max diff {r['max_diff']:.2e}")
@@ -234,7 +240,11 @@ def learned_start(w, pic, parts, args):
     kinds = ("cold", "prev", "ext", "learned")
     return {
         "solver": f"plain masked CG (float64 refinement of float32 CG), rtol {w.rtol:g}",
-        "start": "residual learning: network(residual of 2 phi_{n-1} - phi_{n-2}) corrects that start",
+        "start": (f"coarse residual learning: the network maps block means ({f}x{f} nodes) of the residual of "
+                  f"2 phi_(n-1) - phi_(n-2) to a block-mean correction, prolonged bilinearly onto the free nodes"
+                  if f > 1 else "residual learning: network(residual of 2 phi_(n-1) - phi_(n-2)) corrects that "
+                                "start"),
+        "factor": f,
         "problems_evaluated": len(rows),
         **{k: {"iterations": mean(k, "iterations"), "ms": mean(k, "ms"),
                "relres0": float(np.median([r[k]["relres0"] for r in rows]))} for k in kinds},
@@ -243,9 +253,15 @@ def learned_start(w, pic, parts, args):
         "iterations_cold_over_ext": mean("cold", "iterations") / mean("ext", "iterations"),
         "ms_cold_over_learned": mean("cold", "ms") / mean("learned", "ms"),
         "target_cold_over_learned": 3.0,
+        "coarse_exact_target_iterations": {
+            "what": "extrapolation + the exact f x f block means of the true correction (a perfect coarse network), "
+                    "and the same with a 1 % uniform error",
+            "problems": min(len(problems), args.learn_bound_problems),
+            **{f"f{k}": v for k, v in bound.items()}},
         "all_converged": all(r[k]["converged"] for r in rows for k in kinds),
         "max_solution_diff_over_scale": max(r["max_diff"] / r["scale"] for r in rows),
         "training": {"samples_trench1024x512": n_trench, "samples_sweep16": n_sweep,
+                     "trench_sample_every": args.learn_every,
                      "sample_windows": sorted({f"{k[0]}x{k[1]}" for k in nets}), "steps": args.learn_steps,
                      "batch_pixels": args.learn_batch * H * W, "scales": list(sc),
                      "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-10:])),
@@ -575,13 +591,19 @@ def main():
                     help="ignore a cached autotuned schedule for the workload")
     ap.add_argument("--autotune", action="store_true",
                     help="sweep: tune the schedule when the cache has no entry for the batch")
-    ap.add_argument("--learn-trench-steps", type=int, default=4000,
-                    help="training samples from the trench run (one per step)")
+    ap.add_argument("--learn-bound-problems", type=int, default=5,
+                    help="held-out problems of the exact-coarse-target bound")
+    ap.add_argument("--learn-factor", type=int, default=1,
+                    help="nodes per network pixel along each axis (1, 2, 4, 8 or 16)")
+    ap.add_argument("--learn-trench-samples", type=int, default=4000,
+                    help="training samples from the trench run")
+    ap.add_argument("--learn-every", type=int, default=1, help="steps of the trench run per sample")
     ap.add_argument("--learn-sweep-steps", type=int, default=250,
                     help="eager steps of the 16-width sweep sampled (16 samples per step)")
     ap.add_argument("--learn-sweep-spinup", type=int, default=100)
     ap.add_argument("--learn-steps", type=int, default=4000, help="training steps")
-    ap.add_argument("--learn-batch", type=int, default=4, help="batch, in 1024 x 512 images")
+    ap.add_argument("--learn-batch", type=int, default=4, help="batch, in trench-window images")
+    ap.add_argument("--learn-rate", type=float, default=2e-3, help="Adam's initial learning rate")
     ap.add_argument("--learn-evals", type=int, default=20, help="held-out problems")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -201,6 +201,53 @@ pic_status pic_unet_residual_guess(pic_unet *u, int32_t slot, const double *phi_
 pic_status pic_solve_learned_residual(pic_ctx *ctx, pic_unet *u, float s_r, float s_v, float s_d,
                                       double *guess, pic_solve_info *info);
 
+/* ---- coarse residual learning: the start the benchmark's learned solve uses ----
+ * The solver's iteration count is set by the smooth part of its start's
+ * error, whose extent is the whole grid; a network that sees one node per
+ * pixel reaches only its receptive field (tens of nodes).  Here pixel
+ * (h, w) stands for the f x f block of nodes (h f + p, w f + q), p, q < f,
+ * f one of 1, 2, 4, 8, 16, covering H f <= NX by W f <= NY nodes.  Input
+ * channels: 0 the mean over the block of the residual r = b - A phi_s of
+ * the extrapolated start (zero on Dirichlet nodes) times s_r, 1 the
+ * fraction of free nodes in the block, 2 the mean of the Dirichlet values
+ * (zero on free nodes) times s_v.  Target: the block mean of (phi - phi_s)
+ * on free nodes times s_d.  Each mean adds the block's nodes in row-major
+ * order from zero, then multiplies by 1/f^2; values are rounded to bfloat16.
+ * The start adds to phi_s, on every free node of the covered region, c / s_d
+ * with c the bilinear interpolation of the output at the node's pixel
+ * coordinate ((i + 1/2)/f - 1/2, (j + 1/2)/f - 1/2): an axis that is
+ * periodic and covered exactly (H f = NX, W f = NY) wraps, any other is held
+ * at its edge pixels; nodes outside the covered region start from phi_s.
+ * f = 1 gives pic_unet_residual_sample / pic_unet_residual_guess. */
+/* Bytes of the work array of pic_unet_coarse_sample with statistics. */
+pic_status pic_unet_coarse_sample_work_bytes(int32_t f, int32_t H, int32_t W, size_t *bytes);
+/* One coarse training sample (no network needed): x (device bfloat16
+ * [H][W][3]) the input above, t (device bfloat16 [H][W], or NULL) the
+ * target for the converged potential phi_t.  stats (device float64[3], or
+ * NULL) accumulates the sums over pixels of (block mean of r)^2 and of
+ * (block mean of phi_t - phi_s)^2 and the count of pixels holding a free
+ * node, in a fixed order; with stats, work (device, at least
+ * pic_unet_coarse_sample_work_bytes) holds per-block partial sums.  Other
+ * arguments as pic_unet_residual_sample.  Enqueued on stream.  PIC_ERR_ARG
+ * for a factor not listed, a window that does not fit the grid, a missing
+ * pointer or a short work array. */
+pic_status pic_unet_coarse_sample(const double *b, const double *phi_1, const double *phi_2, const double *phi_t,
+                                  const uint8_t *node_cond, int32_t NX, int32_t NY, int32_t periodic_x,
+                                  int32_t periodic_y, int32_t f, int32_t H, int32_t W, float s_r, float s_v,
+                                  float s_d, uint16_t *x, uint16_t *t, double *stats, void *work,
+                                  size_t work_bytes, void *stream);
+/* Writes guess (device float64 NX x NY): the start above from the output of
+ * batch slot `slot` of a network of H x W pixels (use_output = 0: phi_s
+ * alone), a start for pic_solve(ctx, 2 or 4, guess, ...). */
+pic_status pic_unet_coarse_guess(pic_unet *u, int32_t slot, const double *phi_1, const double *phi_2,
+                                 const uint8_t *node_cond, int32_t NX, int32_t NY, int32_t periodic_x,
+                                 int32_t periodic_y, int32_t f, float s_d, int32_t use_output, double *guess);
+/* As pic_solve_learned_residual with the coarse sample and start of factor
+ * f: the sample of the context's current b and potentials, a forward pass,
+ * the prolonged start into guess, then pic_solve(ctx, 4, guess, info).
+ * Waits (as pic_solve). */
+pic_status pic_solve_learned_coarse(pic_ctx *ctx, pic_unet *u, int32_t f, float s_r, float s_v, float s_d,
+                                    double *guess, pic_solve_info *info);
 /* HIP-event timing of pic_unet_forward on the library stream (default off);
  * average ms per forward pass since the last read, then reset. */
 pic_status pic_unet_set_timing(pic_unet *u, int32_t on);

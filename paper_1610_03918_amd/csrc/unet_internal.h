@@ -108,5 +108,14 @@ void launch_load(const uint16_t *xs, const uint16_t *ts, long long P, uint16_t *
                  hipStream_t s);
 void launch_rguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX, int NY,
                    int H, int W, float s_d, int use_out, double *guess, hipStream_t s);
+// coarse residual learning (pixel = f x f block of nodes, f divides 16):
+// the sample (part: 3 float64 per block of csample_blocks(f, H, W), needed
+// only with stats) and the prolonged start
+long long csample_blocks(int f, int H, int W);
+void launch_csample(const double *b, const double *p1, const double *p2, const double *pt, const uint8_t *nc,
+                    int NX, int NY, int px, int py, int f, int H, int W, float s_r, float s_v, float s_d,
+                    uint16_t *x, uint16_t *t, double *stats, double *part, hipStream_t s);
+void launch_cguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX, int NY,
+                   int px, int py, int f, int H, int W, float s_d, int use_out, double *guess, hipStream_t s);
 
 } // namespace unet

@@ -828,4 +828,169 @@ void launch_rguess(const float *out, const double *p1, const double *p2, const u
                        H, W, s_d, use_out, guess);
 }
 
+// ---- coarse residual learning -----------------------------------------------
+// Pixel (h, w) of the network stands for the f x f block of nodes
+// (h f + p, w f + q), p, q < f (f divides 16), so the network's receptive
+// field spans the whole grid.  Input x [H][W][3] = (bf16(R/f^2 s_r),
+// bf16(F/f^2), bf16(V/f^2 s_v)) and target t [H][W] = bf16(D/f^2 s_d), with
+// R, D, F the sums over the block's free nodes of the residual r of the
+// extrapolated start, of (phi_t - phi_s) and of 1, and V the sum of the
+// Dirichlet values of its conductor nodes; every sum adds the block's nodes
+// in row-major order (p outer, q inner), starting from 0.  One block of 256
+// threads covers a 16 x 16 tile of nodes: each thread computes one node's
+// terms into LDS, then one thread per pixel of the tile adds its block.
+// part (may be null): per-block sums, in pixel order, of (R/f^2)^2,
+// (D/f^2)^2 and the count of pixels with a free node.
+constexpr int kCsTile = 16;
+
+__global__ __launch_bounds__(256) void k_csample(const double *b, const double *p1, const double *p2,
+                                                 const double *pt, const uint8_t *nc, int NX, int NY, int px,
+                                                 int py, int f, int H, int W, float s_r, float s_v, float s_d,
+                                                 uint16_t *x, uint16_t *t, double *part) {
+    __shared__ double sr[kCsTile * kCsTile], sv[kCsTile * kCsTile], sd[kCsTile * kCsTile];
+    __shared__ unsigned char sf[kCsTile * kCsTile];
+    __shared__ double st[3][kCsTile * kCsTile];
+    const int tid = threadIdx.x;
+    const int tiles_w = (W * f + kCsTile - 1) / kCsTile;
+    const int bi = blockIdx.x / tiles_w, bj = blockIdx.x % tiles_w;
+    const int i = bi * kCsTile + tid / kCsTile, j = bj * kCsTile + tid % kCsTile;
+    double r = 0.0, v = 0.0, d = 0.0;
+    unsigned char fr = 0;
+    if (i < H * f && j < W * f) {
+        const long long n = (long long)i * NY + j;
+        if (nc[n] == 0) {
+            double s = 4.0 * start_at(p1, p2, n);
+            const int im = i - 1 < 0 ? (px ? NX - 1 : -1) : i - 1;
+            const int ip = i + 1 >= NX ? (px ? 0 : -1) : i + 1;
+            const int jm = j - 1 < 0 ? (py ? NY - 1 : -1) : j - 1;
+            const int jp = j + 1 >= NY ? (py ? 0 : -1) : j + 1;
+            long long q;
+            if (im >= 0 && !nc[q = (long long)im * NY + j]) s -= start_at(p1, p2, q);
+            if (ip >= 0 && !nc[q = (long long)ip * NY + j]) s -= start_at(p1, p2, q);
+            if (jm >= 0 && !nc[q = (long long)i * NY + jm]) s -= start_at(p1, p2, q);
+            if (jp >= 0 && !nc[q = (long long)i * NY + jp]) s -= start_at(p1, p2, q);
+            r = b[n] - s;
+            if (pt) d = pt[n] - start_at(p1, p2, n);
+            fr = 1;
+        } else {
+            v = b[n];
+        }
+    }
+    sr[tid] = r;
+    sv[tid] = v;
+    sd[tid] = d;
+    sf[tid] = fr;
+    __syncthreads();
+    const int per = kCsTile / f;                 // pixels per tile edge
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    if (tid < per * per) {
+        const int a = tid / per, c = tid % per;
+        const int h = bi * per + a, w = bj * per + c;
+        if (h < H && w < W) {
+            double R = 0.0, V = 0.0, D = 0.0, F = 0.0;
+            for (int pp = 0; pp < f; ++pp)
+                for (int qq = 0; qq < f; ++qq) {
+                    const int l = (a * f + pp) * kCsTile + (c * f + qq);
+                    if (sf[l]) {
+                        R += sr[l];
+                        D += sd[l];
+                        F += 1.0;
+                    } else {
+                        V += sv[l];
+                    }
+                }
+            const double inv = 1.0 / (double)(f * f);
+            const long long p = (long long)h * W + w;
+            const double rm = R * inv, dm = D * inv;
+            x[3 * p + 0] = (uint16_t)f2bf((float)(rm * (double)s_r));
+            x[3 * p + 1] = (uint16_t)f2bf((float)(F * inv));
+            x[3 * p + 2] = (uint16_t)f2bf((float)(V * inv * (double)s_v));
+            if (t) t[p] = (uint16_t)f2bf((float)(dm * (double)s_d));
+            q0 = rm * rm;
+            q1 = dm * dm;
+            q2 = F > 0.0 ? 1.0 : 0.0;
+        }
+    }
+    if (part) {
+        st[0][tid] = q0;
+        st[1][tid] = q1;
+        st[2][tid] = q2;
+        __syncthreads();
+        if (tid == 0) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int k = 0; k < per * per; ++k) {
+                a0 += st[0][k];
+                a1 += st[1][k];
+                a2 += st[2][k];
+            }
+            part[3 * (long long)blockIdx.x + 0] = a0;
+            part[3 * (long long)blockIdx.x + 1] = a1;
+            part[3 * (long long)blockIdx.x + 2] = a2;
+        }
+    }
+}
+
+long long csample_blocks(int f, int H, int W) {
+    return (long long)((H * f + kCsTile - 1) / kCsTile) * ((W * f + kCsTile - 1) / kCsTile);
+}
+
+void launch_csample(const double *b, const double *p1, const double *p2, const double *pt, const uint8_t *nc,
+                    int NX, int NY, int px, int py, int f, int H, int W, float s_r, float s_v, float s_d,
+                    uint16_t *x, uint16_t *t, double *stats, double *part, hipStream_t s) {
+    const long long nb = csample_blocks(f, H, W);
+    hipLaunchKernelGGL(k_csample, dim3((unsigned)nb), dim3(kCsTile * kCsTile), 0, s, b, p1, p2, pt, nc, NX, NY,
+                       px, py, f, H, W, s_r, s_v, s_d, x, t, stats ? part : nullptr);
+    if (stats) hipLaunchKernelGGL(k_rsample_sum, dim3(1), dim3(64), 0, s, part, (int)nb, stats);
+}
+
+// Lower and upper pixel of node index i on an axis of n pixels of f nodes and
+// the upper pixel's weight: the node lies at pixel coordinate (i + 1/2)/f - 1/2
+// (pixel centres at integers); beyond [0, n - 1] the index wraps (wrap) or is
+// clamped to the edge pixel.
+__device__ __forceinline__ void axis_weights(int i, int f, int n, bool wrap, int &lo, int &hi, double &a) {
+    const double u = ((double)i + 0.5) / (double)f - 0.5;
+    const double fl = floor(u);
+    a = u - fl;
+    lo = (int)fl;
+    hi = lo + 1;
+    if (wrap) {
+        lo = lo < 0 ? lo + n : lo;
+        hi = hi >= n ? hi - n : hi;
+    } else {
+        lo = min(max(lo, 0), n - 1);
+        hi = min(max(hi, 0), n - 1);
+    }
+}
+
+// guess = phi_s + c / s_d on the free nodes of the covered H f x W f region
+// (use_out), c the bilinear interpolation of the coarse output, weights
+// (1-a)(1-b), a(1-b), (1-a)b, ab added in that order; phi_s elsewhere.  An
+// axis wraps when it is periodic and covered exactly.
+__global__ void k_cguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX,
+                         int NY, int px, int py, int f, int H, int W, float s_d, int use_out, double *guess) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (long long)NX * NY) return;
+    const int i = (int)(n / NY), j = (int)(n % NY);
+    double v = start_at(p1, p2, n);
+    if (use_out && nc[n] == 0 && i < H * f && j < W * f) {
+        int h0, h1, w0, w1;
+        double a, bq;
+        axis_weights(i, f, H, px && H * f == NX, h0, h1, a);
+        axis_weights(j, f, W, py && W * f == NY, w0, w1, bq);
+        double c = (1.0 - a) * (1.0 - bq) * (double)out[(long long)h0 * W + w0];
+        c = c + a * (1.0 - bq) * (double)out[(long long)h1 * W + w0];
+        c = c + (1.0 - a) * bq * (double)out[(long long)h0 * W + w1];
+        c = c + a * bq * (double)out[(long long)h1 * W + w1];
+        v = v + c / (double)s_d;
+    }
+    guess[n] = v;
+}
+
+void launch_cguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX, int NY,
+                   int px, int py, int f, int H, int W, float s_d, int use_out, double *guess, hipStream_t s) {
+    const long long n = (long long)NX * NY;
+    hipLaunchKernelGGL(k_cguess, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, p1, p2, nc, NX, NY, px,
+                       py, f, H, W, s_d, use_out, guess);
+}
+
 } // namespace unet

@@ -604,6 +604,66 @@ pic_status pic_solve_learned_residual(pic_ctx *ctx, pic_unet *u, float s_r, floa
     return pic_solve(ctx, 4, guess, info);
 }
 
+static bool coarse_factor_ok(int f) { return f == 1 || f == 2 || f == 4 || f == 8 || f == 16; }
+
+pic_status pic_unet_coarse_sample_work_bytes(int32_t f, int32_t H, int32_t W, size_t *bytes)
+{
+    if (!bytes || !coarse_factor_ok(f) || H < 1 || W < 1) return PIC_ERR_ARG;
+    *bytes = (size_t)csample_blocks(f, H, W) * 3 * sizeof(double);
+    return PIC_OK;
+}
+
+pic_status pic_unet_coarse_sample(const double *b, const double *phi_1, const double *phi_2, const double *phi_t,
+                                  const uint8_t *node_cond, int32_t NX, int32_t NY, int32_t periodic_x,
+                                  int32_t periodic_y, int32_t f, int32_t H, int32_t W, float s_r, float s_v,
+                                  float s_d, uint16_t *x, uint16_t *t, double *stats, void *work,
+                                  size_t work_bytes, void *stream)
+{
+    if (!b || !phi_1 || !node_cond || !x || !coarse_factor_ok(f) || H < 1 || W < 1 || (long long)H * f > NX ||
+        (long long)W * f > NY || (t && !phi_t))
+        return PIC_ERR_ARG;
+    if (stats && (!work || work_bytes < (size_t)csample_blocks(f, H, W) * 3 * sizeof(double))) return PIC_ERR_ARG;
+    launch_csample(b, phi_1, phi_2, phi_t, node_cond, NX, NY, periodic_x ? 1 : 0, periodic_y ? 1 : 0, f, H, W, s_r,
+                   s_v, s_d, x, t, stats, static_cast<double *>(work), static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_ERR_HIP;
+}
+
+pic_status pic_unet_coarse_guess(pic_unet *u, int32_t slot, const double *phi_1, const double *phi_2,
+                                 const uint8_t *node_cond, int32_t NX, int32_t NY, int32_t periodic_x,
+                                 int32_t periodic_y, int32_t f, float s_d, int32_t use_output, double *guess)
+{
+    if (!u) return PIC_ERR_ARG;
+    if (slot < 0 || slot >= u->B || !phi_1 || !node_cond || !guess || !coarse_factor_ok(f) ||
+        (long long)u->H * f > NX || (long long)u->W * f > NY || !(s_d != 0.f))
+        return ufail(u, PIC_ERR_ARG, "pic_unet_coarse_guess: bad slot, pointer, factor, scale or grid");
+    launch_cguess(u->out + (long long)slot * u->H * u->W, phi_1, phi_2, node_cond, NX, NY, periodic_x ? 1 : 0,
+                  periodic_y ? 1 : 0, f, u->H, u->W, s_d, use_output ? 1 : 0, guess, u->stream);
+    UCHK(u, hipGetLastError());
+    return PIC_OK;
+}
+
+pic_status pic_solve_learned_coarse(pic_ctx *ctx, pic_unet *u, int32_t f, float s_r, float s_v, float s_d,
+                                    double *guess, pic_solve_info *info)
+{
+    if (!ctx || !u) return PIC_ERR_ARG;
+    if (u->B < 1) return PIC_ERR_ARG;
+    PicCtxView v;
+    pic_status st = pic_ctx_view(ctx, 0, &v);
+    if (st != PIC_OK) return st;
+    if (!guess || !coarse_factor_ok(f) || (long long)u->H * f > v.NX || (long long)u->W * f > v.NY)
+        return ufail(u, PIC_ERR_ARG, "pic_solve_learned_coarse: factor, grid or guess");
+    // the right-hand side and the potentials were written on the context's stream
+    if ((st = after_stream(u, v.stream)) != PIC_OK) return st;
+    launch_csample(v.b, v.phi, v.phi_prev, nullptr, v.node_cond, v.NX, v.NY, v.px, v.py, f, u->H, u->W, s_r, s_v,
+                   s_d, u->x, nullptr, nullptr, nullptr, u->stream);
+    if ((st = pic_unet_forward(u)) != PIC_OK) return st;
+    launch_cguess(u->out, v.phi, v.phi_prev, v.node_cond, v.NX, v.NY, v.px, v.py, f, u->H, u->W, s_d, 1, guess,
+                  u->stream);
+    UCHK(u, hipGetLastError());
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return pic_solve(ctx, 4, guess, info);
+}
+
 pic_status pic_unet_set_timing(pic_unet *u, int32_t on)
 {
     if (!u) return PIC_ERR_ARG;

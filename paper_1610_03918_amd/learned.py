@@ -6,6 +6,10 @@ The network corrects the solver's own start, the linear extrapolation in time
 phi_s = 2 phi_{n-1} - phi_{n-2} of the potential (residual learning): its
 input is the residual b - A phi_s (with the free-node mask and the Dirichlet
 potentials), its target the gap phi_n - phi_s to the converged potential.
+With a coarsening factor f > 1 a network pixel stands for an f x f block of
+nodes (block means in, a block-mean correction out, prolonged bilinearly
+onto the nodes), so that the network sees the whole grid: the smooth part of
+the start's error is what the solver spends its iterations on.
 
 Orchestration only: every tensor operation on the method's data runs in the
 library (see unet.py); this module decides which sample goes into which batch
@@ -19,12 +23,29 @@ import time
 
 import numpy as np
 
-from .unet import UNet, residual_sample
+from .unet import UNet, coarse_sample, residual_sample
 
 
-def window(w):
-    """Network window over the node grid: the largest multiples of 8."""
-    return (w.NX // 8) * 8, (w.NY // 8) * 8
+def window(w, f=1):
+    """Network window (pixels) over the node grid at coarsening factor f:
+    the largest multiples of 8 of the node counts over f."""
+    return (w.NX // f // 8) * 8, (w.NY // f // 8) * 8
+
+
+def sample(f, b, phi_1, phi_2, phi_t, node_map, periodic, H, W, scales, x, t=None, stats=None):
+    """One training sample (or network input) at coarsening factor f."""
+    if f == 1:
+        residual_sample(b, phi_1, phi_2, phi_t, node_map, periodic, H, W, scales, x, t, stats)
+    else:
+        coarse_sample(b, phi_1, phi_2, phi_t, node_map, periodic, f, H, W, scales, x, t, stats)
+
+
+def start_guess(f, net, slot, phi_1, phi_2, node_map, periodic, s_d, guess, use_output=True):
+    """The corrected start (use_output) or the extrapolation alone into guess."""
+    if f == 1:
+        net.pic_unet_residual_guess(slot, phi_1, phi_2, node_map, s_d, guess, use_output=use_output)
+    else:
+        net.pic_unet_coarse_guess(slot, phi_1, phi_2, node_map, periodic, f, s_d, guess, use_output=use_output)
 
 
 def pow2_scale(rms):
@@ -46,12 +67,13 @@ class SampleStore:
         return self.n >= self.x.shape[0]
 
 
-def probe_scales(w, steps, torch, dev, sim_step):
+def probe_scales(w, steps, torch, dev, sim_step, f=1):
     """(s_r, s_d): powers of two near the inverse RMS of the residual of the
-    extrapolated start and of its gap to the solution, measured over `steps`
-    steps of a running simulation.  sim_step() advances it one step and
-    returns (b, phi_1, phi_2, phi_n, node_map, periodic)."""
-    H, W = window(w)
+    extrapolated start and of its gap to the solution (block means at
+    factor f), measured over `steps` steps of a running simulation.
+    sim_step() advances it one step and returns (b, phi_1, phi_2, phi_n,
+    node_map, periodic)."""
+    H, W = window(w, f)
     stats = torch.zeros(3, dtype=torch.float64, device=dev)
     x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
     t = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
@@ -59,20 +81,20 @@ def probe_scales(w, steps, torch, dev, sim_step):
         b, p1, p2, pn, nm, per = sim_step()
         if p2 is None:
             continue
-        residual_sample(b, p1, p2, pn, nm, per, H, W, (1.0, 1.0, 1.0), x, t, stats)
+        sample(f, b, p1, p2, pn, nm, per, H, W, (1.0, 1.0, 1.0), x, t, stats)
     s = stats.cpu().numpy()
     cnt = max(s[2], 1.0)
     return pow2_scale(math.sqrt(s[0] / cnt)), pow2_scale(math.sqrt(s[1] / cnt))
 
 
-def run_and_sample(pic, steps, stores, scales, keep=None, every=1):
+def run_and_sample(pic, steps, stores, scales, keep=None, every=1, f=1):
     """Advances a single-instance Pic `steps` steps (solve from the
-    extrapolated start, push) and writes a sample of each step's solve into
-    stores[(H, W)] until it is full.  keep: a list that receives the float64
-    (b, phi_{n-1}, phi_{n-2}, phi_n) of every `every`-th step instead (held-out
-    problems).  Returns the solver infos."""
+    extrapolated start, push) and writes a sample (factor f) of each
+    `every`-th step's solve into stores[(H, W)] until it is full.  keep: a
+    list that receives the float64 (b, phi_{n-1}, phi_{n-2}, phi_n) of every
+    `every`-th step instead (held-out problems).  Returns the solver infos."""
     w = pic.w
-    H, W = window(w)
+    H, W = window(w, f)
     nm = pic.pic_node_map()
     per = (int(w.periodic_x), int(w.periodic_y))
     hist = getattr(pic, "_phi_hist", [])
@@ -86,10 +108,10 @@ def run_and_sample(pic, steps, stores, scales, keep=None, every=1):
             if keep is not None:
                 if k % every == 0:
                     keep.append((pic.b.clone(), p1, p2, phi))
-            else:
+            elif k % every == 0:
                 st = stores.get((H, W))
                 if st is not None and not st.full():
-                    residual_sample(pic.b, p1, p2, phi, nm, per, H, W, scales, st.x[st.n], st.t[st.n])
+                    sample(f, pic.b, p1, p2, phi, nm, per, H, W, scales, st.x[st.n], st.t[st.n])
                     st.n += 1
         hist = (hist + [phi])[-2:]
         pic.pic_push()
@@ -97,7 +119,7 @@ def run_and_sample(pic, steps, stores, scales, keep=None, every=1):
     return infos
 
 
-def run_and_sample_batch(batch, steps, stores, scales):
+def run_and_sample_batch(batch, steps, stores, scales, f=1):
     """As run_and_sample for every instance of a PicBatch (eager solves of
     all instances, one sample per instance and step)."""
     n = batch.n
@@ -108,11 +130,11 @@ def run_and_sample_batch(batch, steps, stores, scales):
         for i, w in enumerate(batch.ws):
             phi = batch.phi(i).clone()
             if len(hist[i]) == 2:
-                H, W = window(w)
+                H, W = window(w, f)
                 st = stores.get((H, W))
                 if st is not None and not st.full():
-                    residual_sample(batch.b(i), hist[i][-1], hist[i][-2], phi, nms[i],
-                                    (int(w.periodic_x), int(w.periodic_y)), H, W, scales, st.x[st.n], st.t[st.n])
+                    sample(f, batch.b(i), hist[i][-1], hist[i][-2], phi, nms[i],
+                           (int(w.periodic_x), int(w.periodic_y)), H, W, scales, st.x[st.n], st.t[st.n])
                     st.n += 1
             hist[i] = (hist[i] + [phi])[-2:]
         batch.pic_push()
@@ -159,7 +181,7 @@ def train(nets, main, stores, steps, lr=2e-3, seed=0, log=None, log_every=0):
     return losses
 
 
-def evaluate(pic_cg, net, problems, scales, torch):
+def evaluate(pic_cg, net, problems, scales, torch, f=1):
     """Iterations and wall time (ms) of the solver of pic_cg on each held-out
     problem (b, phi_{n-1}, phi_{n-2}, phi_n) from four starts: zero on the
     free nodes (cold), the previous potential, the linear extrapolation, and
@@ -167,7 +189,7 @@ def evaluate(pic_cg, net, problems, scales, torch):
     included in the time).  Also the largest difference between the cold and
     learned solutions on the free nodes."""
     w = pic_cg.w
-    H, W = window(w)
+    H, W = window(w, f)
     nm = pic_cg.pic_node_map()
     per = (int(w.periodic_x), int(w.periodic_y))
     guess = torch.empty(pic_cg.nodes, dtype=torch.float64, device=pic_cg.dev)
@@ -183,13 +205,13 @@ def evaluate(pic_cg, net, problems, scales, torch):
         return info
 
     def learned_start():
-        residual_sample(pic_cg.b, p1, p2, None, nm, per, H, W, scales, net.input()[0])
+        sample(f, pic_cg.b, p1, p2, None, nm, per, H, W, scales, net.input()[0])
         net.pic_unet_forward()
-        net.pic_unet_residual_guess(0, p1, p2, nm, s_d, guess, use_output=True)
+        start_guess(f, net, 0, p1, p2, nm, per, s_d, guess, use_output=True)
         return pic_cg.pic_solve(2, guess)
 
     def ext_start():
-        net.pic_unet_residual_guess(0, p1, p2, nm, s_d, guess, use_output=False)
+        start_guess(f, net, 0, p1, p2, nm, per, s_d, guess, use_output=False)
         return pic_cg.pic_solve(2, guess)
 
     rows = []
@@ -205,3 +227,36 @@ def evaluate(pic_cg, net, problems, scales, torch):
         rows.append({"cold": cold, "prev": prev, "ext": ext, "learned": learned, "max_diff": diff,
                      "scale": float(pn.abs().max())})
     return rows
+
+
+def coarse_bound(pic_cg, problems, factors, torch, scale_errors=(0.99,)):
+    """What a perfect coarse network would give: plain-solver iterations from
+    the extrapolated start corrected by the exact block means (f x f) of the
+    true correction phi_n - phi_s (the training target itself, bfloat16),
+    prolonged as the network's output would be; and from the same correction
+    with a uniform relative error (times each of scale_errors).  Mean
+    iterations per factor over the problems."""
+    w = pic_cg.w
+    nm = pic_cg.pic_node_map()
+    per = (int(w.periodic_x), int(w.periodic_y))
+    guess = torch.empty(pic_cg.nodes, dtype=torch.float64, device=pic_cg.dev)
+    out = {}
+    for f in factors:
+        H, W = window(w, f)
+        net = UNet(1, H, W, device=pic_cg.dev, periodic_w=bool(per[1]) and W * f == w.NY)
+        x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=pic_cg.dev)
+        t = torch.empty((H, W), dtype=torch.bfloat16, device=pic_cg.dev)
+        its = {"exact": []}
+        its.update({f"scaled_{s:g}": [] for s in scale_errors})
+        for (b, p1, p2, pn) in problems:
+            pic_cg.b.copy_(b)
+            sample(f, b, p1, p2, pn, nm, per, H, W, (1.0, 1.0, 1.0), x, t)
+            net.output()[0].copy_(t)
+            start_guess(f, net, 0, p1, p2, nm, per, 1.0, guess)
+            its["exact"].append(pic_cg.pic_solve(2, guess)["iterations"])
+            for s in scale_errors:
+                start_guess(f, net, 0, p1, p2, nm, per, 1.0 / s, guess)
+                its[f"scaled_{s:g}"].append(pic_cg.pic_solve(2, guess)["iterations"])
+        net.close()
+        out[f] = {k: float(np.mean(v)) for k, v in its.items()}
+    return out

@@ -24,6 +24,8 @@ UNET_ENTRY_POINTS = ["pic_unet_param_count", "pic_unet_layer_info", "pic_unet_wo
                      "pic_unet_set_periodic", "pic_unet_residual_sample_work_bytes",
                      "pic_unet_residual_sample", "pic_unet_residual_sample_noalloc", "pic_unet_load",
                      "pic_unet_residual_guess", "pic_solve_learned_residual",
+                     "pic_unet_coarse_sample_work_bytes", "pic_unet_coarse_sample", "pic_unet_coarse_guess",
+                     "pic_solve_learned_coarse",
                      "pic_unet_set_timing", "pic_unet_forward_timing", "pic_unet_destroy",
                      "pic_unet_last_error"]
 
@@ -70,6 +72,11 @@ def lib():
     L.pic_unet_load.argtypes = [P, i32, P, P]
     L.pic_unet_residual_guess.argtypes = [P, i32, P, P, P, i32, i32, f32, i32, P]
     L.pic_solve_learned_residual.argtypes = [P, P, f32, f32, f32, P, C.POINTER(pic_solve_info)]
+    L.pic_unet_coarse_sample_work_bytes.argtypes = [i32, i32, i32, C.POINTER(C.c_size_t)]
+    L.pic_unet_coarse_sample.argtypes = [P, P, P, P, P, i32, i32, i32, i32, i32, i32, i32, f32, f32, f32, P, P,
+                                         P, P, C.c_size_t, P]
+    L.pic_unet_coarse_guess.argtypes = [P, i32, P, P, P, i32, i32, i32, i32, i32, f32, i32, P]
+    L.pic_solve_learned_coarse.argtypes = [P, P, i32, f32, f32, f32, P, C.POINTER(pic_solve_info)]
     L.pic_unet_set_timing.argtypes = [P, i32]
     L.pic_unet_forward_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i32)]
     L.pic_unet_destroy.argtypes = [P]
@@ -267,6 +274,26 @@ class UNet:
             raise PicError(st, msg)
         return info.as_dict()
 
+    def pic_unet_coarse_guess(self, slot, phi_1, phi_2, node_map, periodic, f, s_d, guess, use_output=True):
+        ptr, NX, NY = node_map
+        self._chk(lib().pic_unet_coarse_guess(self.h, int(slot), C.c_void_p(phi_1.data_ptr()),
+                                              C.c_void_p(phi_2.data_ptr()) if phi_2 is not None else None,
+                                              C.c_void_p(ptr), NX, NY, int(periodic[0]), int(periodic[1]),
+                                              int(f), float(s_d), 1 if use_output else 0,
+                                              C.c_void_p(guess.data_ptr())))
+
+    def pic_solve_learned_coarse(self, pic, f, scales, guess):
+        """Coarse residual-learning start (factor f) for instance 0 of a
+        running Pic (scales: s_r, s_v, s_d; guess: device float64 NX*NY scratch)."""
+        s_r, s_v, s_d = scales
+        info = pic_solve_info()
+        st = lib().pic_solve_learned_coarse(pic.ctx, self.h, int(f), s_r, s_v, s_d, C.c_void_p(guess.data_ptr()),
+                                            C.byref(info))
+        if st != PIC_OK:
+            msg = lib().pic_unet_last_error(self.h).decode() or _pic.lib().pic_last_error(pic.ctx).decode()
+            raise PicError(st, msg)
+        return info.as_dict()
+
     def pic_unet_set_timing(self, on=True):
         self._chk(lib().pic_unet_set_timing(self.h, 1 if on else 0))
 
@@ -311,3 +338,32 @@ def residual_sample(b, phi_1, phi_2, phi_t, node_map, periodic, H, W, scales, x,
                                         C.c_void_p(stream.cuda_stream))
     if st != PIC_OK:
         raise PicError(st, "pic_unet_residual_sample: bad window, pointer or launch")
+
+
+def coarse_sample(b, phi_1, phi_2, phi_t, node_map, periodic, f, H, W, scales, x, t=None, stats=None,
+                  stream=None):
+    """pic_unet_coarse_sample on device tensors: as residual_sample, with the
+    network pixel standing for an f x f block of nodes."""
+    import torch
+    ptr, NX, NY = node_map
+    s_r, s_v, s_d = scales
+    if stream is None:
+        stream = torch.cuda.current_stream(b.device)
+
+    def vp(a):
+        return C.c_void_p(a.data_ptr()) if a is not None else None
+
+    work, nbytes = None, 0
+    if stats is not None:
+        nb = C.c_size_t(0)
+        st = lib().pic_unet_coarse_sample_work_bytes(int(f), int(H), int(W), C.byref(nb))
+        if st != PIC_OK:
+            raise PicError(st, "pic_unet_coarse_sample_work_bytes: bad factor or window")
+        nbytes = nb.value
+        work = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    st = lib().pic_unet_coarse_sample(vp(b), vp(phi_1), vp(phi_2), vp(phi_t), C.c_void_p(ptr), NX, NY,
+                                      int(periodic[0]), int(periodic[1]), int(f), int(H), int(W), float(s_r),
+                                      float(s_v), float(s_d), vp(x), vp(t), vp(stats), vp(work), nbytes,
+                                      C.c_void_p(stream.cuda_stream))
+    if st != PIC_OK:
+        raise PicError(st, "pic_unet_coarse_sample: bad factor, window, pointer or launch")

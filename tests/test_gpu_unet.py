@@ -279,3 +279,57 @@ def test_residual_sample_load_and_guess_are_bit_exact():
             assert np.array_equal(g.cpu().numpy().reshape(w.NX, w.NY), ref)
         u.close()
     pic.close()
+
+
+@pytest.mark.parametrize("f,nx,ny", [(4, 64, 40), (8, 64, 64), (2, 64, 64), (16, 128, 128)])
+def test_coarse_sample_and_guess_are_bit_exact(f, nx, ny):
+    """The coarse residual-learning maps (network pixel = f x f block of
+    nodes) against the oracle on identical float64 inputs: the sample's
+    bfloat16 input and target and its statistics, and the prolonged start
+    from the network's output, on grids whose periodic axis is covered
+    exactly (wrapped prolongation) or not (held at the edge pixels)."""
+    import torch
+    from paper_1610_03918_amd import Pic
+    from paper_1610_03918_amd.unet import UNet, coarse_sample
+    w = synth.trench(nx=nx, ny=ny, width=6, depth=16, ppc=2, seed=44)
+    nc = oracle.node_cond(w)
+    parts = synth.load(w)
+    rho = [oracle.deposit(w, parts[s]) for s in range(2)]
+    b = oracle.assemble(w, nc, rho[0], rho[1], 1.7)
+    p1, p2, pt = (synth.random_potential(w, 45 + k, scale=3.0) for k in range(3))
+    pic = Pic(w, parts)                               # for its node map
+    nm = pic.pic_node_map()
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    H, W = (w.NX // f // 8) * 8, (w.NY // f // 8) * 8
+    sc = (float(np.float32(0.75)), float(np.float32(0.02)), float(np.float32(6.0)))
+    per = (False, True)
+    for second in (True, False):
+        q2 = p2 if second else None
+        x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
+        t = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
+        stats = torch.zeros(3, dtype=torch.float64, device=dev)
+        coarse_sample(T(b), T(p1), T(q2) if second else None, T(pt), nm, per, f, H, W, sc, x, t, stats)
+        xr, tr = ou.coarse_residual_sample(b, p1, q2, pt, nc, f, H, W, per, *sc)
+        assert np.array_equal(x.float().cpu().numpy(), xr)
+        assert np.array_equal(t.float().cpu().numpy(), tr)
+        start = ou.extrapolated(p1, q2)
+        res = np.where(nc == 0, ou.masked_residual(b, start, nc, per), 0.0)
+        bs = lambda a: a[:H * f, :W * f].reshape(H, f, W, f).sum(axis=(1, 3)) / (f * f)
+        rm, dm = bs(res), bs(np.where(nc == 0, pt - start, 0.0))
+        has = bs((nc == 0).astype(float)) > 0
+        st = stats.cpu().numpy()
+        assert st[2] == has.sum()
+        assert abs(st[0] - np.sum(rm ** 2)) <= 1e-9 * st[0]
+        assert abs(st[1] - np.sum(dm ** 2)) <= 1e-9 * st[1]
+        u = UNet(1, H, W, periodic_w=(W * f == w.NY))
+        u.pic_unet_load(0, x, t)
+        u.pic_unet_forward()
+        out = u.output()[0].cpu().numpy().astype(np.float64)
+        g = torch.empty(w.NX * w.NY, dtype=torch.float64, device=dev)
+        for use in (True, False):
+            u.pic_unet_coarse_guess(0, T(p1), T(q2) if second else None, nm, per, f, sc[2], g, use_output=use)
+            ref = ou.coarse_residual_guess(out, p1, q2, nc, f, per, sc[2], use_output=use)
+            assert np.array_equal(g.cpu().numpy().reshape(w.NX, w.NY), ref)
+        u.close()
+    pic.close()
