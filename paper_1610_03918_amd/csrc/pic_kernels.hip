@@ -1587,14 +1587,18 @@ __device__ __forceinline__ void wave_sum4_f32(float &a, float &b, float &c, floa
 // triangle T of the inverse the host factorised (row r: columns 0 .. r padded
 // to a multiple of 4, diagonal halved, zero rows and columns at fixed nodes).
 // Wavefront w takes rows w, w + 16, ...; its lanes read 16-byte pieces of the
-// row.  Each stored entry serves twice: its row's dot product with g (the
-// lower part of u[r] and half its diagonal term, summed across the wave) and
-// T[r][c] g[r] added to the lane's partial sum for column c (the upper part
-// and the other half).  The column partials of the 16 wavefronts meet in LDS
-// (part, 16 x n floats) and are summed in a fixed order.  Every stored float
-// is read once.
+// row (Q pieces per lane and row), R rows per pass with every load of a pass
+// issued before any is used.  Each stored entry serves twice: its row's dot
+// product with g (the lower part of u[r] and half its diagonal term, summed
+// across the wave) and T[r][c] g[r] added to the lane's partial sum for
+// column c (the upper part and the other half).  The column partials of the
+// 16 wavefronts meet in LDS (part, 16 x n floats) and are summed in a fixed
+// order.  Every stored float is read once.  Small levels (n <= 256: one piece
+// per lane and row, 8 rows of a wave per pass) pay one or two memory latencies.
+template <int Q, int R>
 __device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__ T, int n, float *part, int tid)
 {
+    static_assert(R == 2 || R % 4 == 0, "rows per pass: 2 or a multiple of 4 (four-way wave sums)");
     const int lane = tid & 63, w = tid >> 6;
     const int npc = (n + 3) >> 2;                 // 16-byte pieces of the longest row
     // g is read in 16-byte pieces: its padding up to a multiple of 4 (inside
@@ -1602,13 +1606,9 @@ __device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__
     if (tid < 4 && n + tid < 4 * npc) L.g[n + tid] = 0.0f;
     __syncthreads();
     const float4 *g4 = (const float4 *)L.g;
-    constexpr int Q = (kDenseMaxNodes + 255) / 256;  // 16-byte pieces per lane and row
     float4 acc[Q];
 #pragma unroll
     for (int q = 0; q < Q; q++) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-    // two rows per pass, all their loads issued before any is used (the
-    // wave's requests overlap instead of paying the latency row by row)
-    constexpr int R = 2;
     for (int r0 = w; r0 < n; r0 += R * kCoarseWaves) {
         float4 t[R][Q];
 #pragma unroll
@@ -1622,6 +1622,12 @@ __device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__
                 t[i][q] = k < len ? row[k] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
+        float4 gq[Q];
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            const int k = lane + 64 * q;
+            gq[q] = k < npc ? g4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         float dot[R];
 #pragma unroll
         for (int i = 0; i < R; i++) {
@@ -1630,17 +1636,20 @@ __device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__
             dot[i] = 0.0f;
 #pragma unroll
             for (int q = 0; q < Q; q++) {
-                const int k = lane + 64 * q;
-                const float4 gq = k < npc ? g4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
-                dot[i] += t[i][q].x * gq.x + t[i][q].y * gq.y + t[i][q].z * gq.z + t[i][q].w * gq.w;
+                dot[i] += t[i][q].x * gq[q].x + t[i][q].y * gq[q].y + t[i][q].z * gq[q].z + t[i][q].w * gq[q].w;
                 acc[q].x += t[i][q].x * gr;
                 acc[q].y += t[i][q].y * gr;
                 acc[q].z += t[i][q].z * gr;
                 acc[q].w += t[i][q].w * gr;
             }
         }
-        float d2 = 0.0f, d3 = 0.0f;
-        wave_sum4_f32(dot[0], dot[1], d2, d3);
+        if constexpr (R == 2) {
+            float d2 = 0.0f, d3 = 0.0f;
+            wave_sum4_f32(dot[0], dot[1], d2, d3);
+        } else {
+#pragma unroll
+            for (int i = 0; i < R; i += 4) wave_sum4_f32(dot[i], dot[i + 1], dot[i + 2], dot[i + 3]);
+        }
         if (lane == 63) {
 #pragma unroll
             for (int i = 0; i < R; i++) {
@@ -1669,6 +1678,16 @@ __device__ __forceinline__ void c_dense(const CLev &L, const float *__restrict__
     }
 }
 
+constexpr int kDenseOnePass = 256;   // coarsest levels up to this size: one piece per lane, 8 rows per pass
+
+__device__ __forceinline__ void c_dense_any(const CLev &L, const float *__restrict__ T, int n, float *part, int tid)
+{
+    if (n <= kDenseOnePass) c_dense<1, 8>(L, T, n, part, tid);
+    else c_dense<(kDenseMaxNodes + 255) / 256, 2>(L, T, n, part, tid);
+}
+
+constexpr int kCoarsePre = 4;   // 16-byte pieces per thread loaded before the level-0 reduction (fetch calls)
+
 // The levels from lg on: one 1024-thread work-group per instance, every level
 // in LDS.  Per level on the way down a black half-sweep, the red residuals,
 // their restriction to the next level with its red-from-zero start; on the
@@ -1686,7 +1705,59 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t, Tab t
 {
     const Inst &I = insts[t.id[blockIdx.x]];
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (!fuse && I.F[F_DONE]) return;
+    const CoarseArgs &a = I.coarse;
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int tab[3][kMaxLev];
+    __shared__ int dims[2][kMaxLev];
+    // 16-byte pieces to stage: the masks of every level, then the first
+    // level's g (the global arrays are 256-byte aligned and padded, the LDS
+    // ones 16-byte rounded, so whole pieces stay inside both)
+    __shared__ const unsigned char *src[kMaxLev + 1];
+    __shared__ int dst[kMaxLev + 1], cum[kMaxLev + 2];
+    if (tid == 0) {
+        int c = 0;
+        for (int l = 0; l < a.nlev; l++) {
+            tab[0][l] = a.off_u[l];
+            tab[1][l] = a.off_g[l];
+            tab[2][l] = a.off_f[l];
+            dims[0][l] = a.NX[l];
+            dims[1][l] = a.NY[l];
+            src[l] = a.fix[l];
+            dst[l] = a.off_f[l];
+            cum[l] = c;
+            c += (a.NX[l] * a.NY[l] + 15) >> 4;
+        }
+        src[a.nlev] = (const unsigned char *)a.g_top;
+        dst[a.nlev] = a.off_g[0];
+        cum[a.nlev] = c;
+        cum[a.nlev + 1] = c + ((a.NX[0] * a.NY[0] + 3) >> 2);
+    }
+    __syncthreads();
+    const int nlev = a.nlev, px = a.px, py = a.py, npieces = cum[nlev + 1];
+    // every thread issues its first pieces' loads before the level-0
+    // reduction below, so their latencies overlap
+    auto fetch = [&](int m, uint4 &v, int &d) {
+        const int p = tid + m * nt;
+        d = -1;
+        if (p < npieces) {
+            int k = 0;
+            while (p >= cum[k + 1]) k++;
+            const int q = p - cum[k];
+            v = ((const uint4 *)src[k])[q];
+            d = dst[k] + 16 * q;
+        }
+    };
+    uint4 pv0, pv1, pv2, pv3;
+    int pd0, pd1, pd2, pd3;
+    fetch(0, pv0, pd0);
+    fetch(1, pv1, pd1);
+    fetch(2, pv2, pd2);
+    fetch(3, pv3, pd3);
     if (fuse) {
+        // what k_finalize(OP_UPDATE) does after the level-0 CG step (t0: that
+        // launch's units, in the same order as t): the totals of its partials
+        // in the same order, the iteration count and the inner stop test
         __shared__ double fsh[2][4];
         __shared__ int fdone;
         partial_sums_256(pt, t0.boff[blockIdx.x], t0.boff[blockIdx.x + 1], 2, fsh, tid);
@@ -1698,21 +1769,17 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t, Tab t
         }
         __syncthreads();
         if (fdone) return;
-    } else if (I.F[F_DONE]) {
-        return;
     }
-    const CoarseArgs &a = I.coarse;
-    extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int tab[3][kMaxLev];
-    __shared__ int dims[2][kMaxLev];
-    if (tid < a.nlev) {
-        tab[0][tid] = a.off_u[tid];
-        tab[1][tid] = a.off_g[tid];
-        tab[2][tid] = a.off_f[tid];
-        dims[0][tid] = a.NX[tid];
-        dims[1][tid] = a.NY[tid];
+    if (pd0 >= 0) *(uint4 *)(lds + pd0) = pv0;
+    if (pd1 >= 0) *(uint4 *)(lds + pd1) = pv1;
+    if (pd2 >= 0) *(uint4 *)(lds + pd2) = pv2;
+    if (pd3 >= 0) *(uint4 *)(lds + pd3) = pv3;
+    for (int p = tid + kCoarsePre * nt; p < npieces; p += nt) {
+        int k = 0;
+        while (p >= cum[k + 1]) k++;
+        const int q = p - cum[k];
+        *(uint4 *)(lds + dst[k] + 16 * q) = ((const uint4 *)src[k])[q];
     }
-    __syncthreads();
     auto lev = [&](int l) {
         CLev L;
         L.u = (float *)(lds + tab[0][l]);
@@ -1723,25 +1790,6 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t, Tab t
         return L;
     };
     float *sr = (float *)(lds + a.off_s);
-    const int nlev = a.nlev, px = a.px, py = a.py;
-    // masks of every level and the first level's g, in 16-byte pieces (the
-    // global arrays are 256-byte aligned, the LDS ones 16-byte), bytes for the
-    // tails; then the first level's red start from them
-    for (int l = 0; l < nlev; l++) {
-        const int N = dims[0][l] * dims[1][l], N16 = N >> 4;
-        const uint4 *src = (const uint4 *)a.fix[l];
-        uint4 *dst = (uint4 *)(lds + tab[2][l]);
-        for (int k = tid; k < N16; k += nt) dst[k] = src[k];
-        for (int k = (N16 << 4) + tid; k < N; k += nt) lds[tab[2][l] + k] = a.fix[l][k];
-    }
-    {
-        const int N = dims[0][0] * dims[1][0], N4 = N >> 2;
-        const float4 *src = (const float4 *)a.g_top;
-        float4 *dst = (float4 *)(lds + tab[1][0]);
-        for (int k = tid; k < N4; k += nt) dst[k] = src[k];
-        float *dg = (float *)(lds + tab[1][0]);
-        for (int k = (N4 << 2) + tid; k < N; k += nt) dg[k] = a.g_top[k];
-    }
     __syncthreads();
     {
         const CLev L = lev(0);
@@ -1780,7 +1828,7 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t, Tab t
         }
         if (a.dense_n) {
             __syncthreads();
-            c_dense(lev(nlev - 1), a.ainv, a.dense_n, (float *)(lds + a.off_p), tid);
+            c_dense_any(lev(nlev - 1), a.ainv, a.dense_n, (float *)(lds + a.off_p), tid);
             __syncthreads();
         }
         if (tid < 64) {
@@ -1806,7 +1854,7 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t, Tab t
         }
         __syncthreads();
     } else if (a.dense_n) {
-        c_dense(lev(nlev - 1), a.ainv, a.dense_n, (float *)(lds + a.off_p), tid);
+        c_dense_any(lev(nlev - 1), a.ainv, a.dense_n, (float *)(lds + a.off_p), tid);
         __syncthreads();
     } else {
         const CLev L = lev(nlev - 1);

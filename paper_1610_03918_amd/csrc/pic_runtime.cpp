@@ -24,6 +24,7 @@ namespace {
 
 constexpr int kCoarseMaxNodes = 12288;  // largest level solved inside one work-group
 constexpr int kCoarseMaxLds = 159 * 1024;   // dynamic LDS of the coarse kernel (160 KiB per work-group)
+constexpr int kDenseTruncNodes = 256;       // coarsest level at most this size (see make_layout)
 constexpr int kMaxTiming = 512;
 
 struct Layout {
@@ -172,6 +173,16 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
     L.lg = 1;
     while (L.lg < L.nlev && (L.NXl[L.lg] * L.NYl[L.lg] > kCoarseMaxNodes || lds_from(L.lg) > kCoarseMaxLds)) L.lg++;
     L.mg = (c->solver == 0) && L.nlev >= 2 && L.lg < L.nlev;
+    // the hierarchy stops at the first level below the coarse kernel's first
+    // that has at most kDenseTruncNodes nodes: solved exactly (below), it costs
+    // one memory latency, where each further level costs a chain of
+    // single-wavefront passes
+    if (L.mg)
+        for (int l = L.lg + 1; l < L.nlev; l++)
+            if (L.NXl[l] * L.NYl[l] <= kDenseTruncNodes) {
+                L.nlev = l + 1;
+                break;
+            }
     // the coarsest level is solved exactly with its inverse rather than swept
     // (a periodic axis with an odd factor stops the coarsening early, and a
     // large coarsest level needs many sweeps) when it is small enough and its
