@@ -68,9 +68,11 @@ def lib():
         L.or_field.restype = None
         for nm in ("or_push_f32", "or_push_f64"):
             f = getattr(L, nm)
-            f.argtypes = [i, i, i, i, P, i, i, i, d, d, P, P, i64, P, P, P, P, P, P, P, P]
+            f.argtypes = [i, i, i, i, P, i, i, i, d, d, P, P, i64, P, P, P, P, P, P, P, P, P]
             f.restype = i64
         L.or_philox4x32_10.argtypes = [P, P, P]
+        L.or_emit.restype = i64
+        L.or_emit.argtypes = [i64, P, P, i64, C.c_uint32, C.c_uint32, P, d, P, P, P, P, P]
         L.or_philox4x32_10.restype = None
         L.or_recycled_ion.argtypes = [P, C.c_float, C.c_float, C.c_float, i, P, P, P, P, P]
         L.or_recycled_ion.restype = None
@@ -340,11 +342,29 @@ def recycled_ion(w, step, ux, ox0, oy0):
     return code.value, ox.value, oy.value, vx.value, vy.value
 
 
-def push(w, s: int, p: dict, Ex, Ey, precision="f32", tally=None, surf=None, step=None) -> int:
+class _Hits(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("n", C.c_int64), ("rec", C.c_void_p)]
+
+
+class HitRecords:
+    """Removals recorded by one push: rows (class, packed last cell, bits of
+    the kicked float32 v_x, v_y)."""
+
+    def __init__(self, capacity: int):
+        self.rec = np.zeros((max(int(capacity), 1), 4), np.int32)
+        self.h = _Hits(self.rec.shape[0], 0, self.rec.ctypes.data)
+
+    def rows(self):
+        assert self.h.n <= self.h.cap, "hit record buffer too small"
+        return self.rec[:self.h.n]
+
+
+def push(w, s: int, p: dict, Ex, Ey, precision="f32", tally=None, surf=None, step=None, hits=None) -> int:
     """In-place push of species s.  precision 'f32' needs float32 state,
     'f64' float64 state.  Returns the number of particles removed.  With
     w.recycle_rows > 0 and the step index given, lost ions (species 1) are
-    replaced by recycled ones (Sec. III.A)."""
+    replaced by recycled ones (Sec. III.A).  hits: a HitRecords that receives
+    every removal."""
     sp = w.species[s]
     rc = None
     if s == 1 and w.recycle_rows > 0 and step is not None:
@@ -361,7 +381,31 @@ def push(w, s: int, p: dict, Ex, Ey, precision="f32", tally=None, surf=None, ste
              int(w.box_i_top), int(w.box_j_lo), int(w.box_j_hi), float(w.dt), float(sp.alpha),
              _p(_c(Ex, np.float64)), _p(_c(Ey, np.float64)), p["cell"].size, _p(p["cell"]),
              _p(p["ox"]), _p(p["oy"]), _p(p["vx"]), _p(p["vy"]), _p(tally), surf_p,
-             C.cast(C.pointer(rc), C.c_void_p) if rc is not None else None)
+             C.cast(C.pointer(rc), C.c_void_p) if rc is not None else None,
+             C.cast(C.pointer(hits.h), C.c_void_p) if hits is not None else None)
+
+
+def see_thresholds(w):
+    """Integer emission thresholds floor(yield_s 2^24) of the two species."""
+    return np.array([int(np.floor(float(y) * 16777216.0)) for y in w.see_yield], np.uint32)
+
+
+def emit(w, removals, step):
+    """Secondary electrons freed by the removals of one step (Sec. IV;
+    constant-yield reading, see or_emit): removals is a list of (species,
+    rows) with rows as HitRecords.rows() gives them.  Returns the new
+    electrons as float32 state arrays."""
+    sp = np.concatenate([np.full(len(r), s, np.int32) for s, r in removals]) if removals else np.zeros(0, np.int32)
+    rec = np.ascontiguousarray(np.concatenate([r for _, r in removals]) if removals else np.zeros((0, 4), np.int32),
+                               dtype=np.int32)
+    n = sp.size
+    out = {"cell": np.zeros(max(n, 1), np.int32),
+           **{k: np.zeros(max(n, 1), np.float32) for k in ("ox", "oy", "vx", "vy")}}
+    k0, k1 = w.see_key()
+    th = see_thresholds(w)
+    m = lib().or_emit(n, _p(sp), _p(rec), int(step), k0, k1, _p(th), float(w.see_vth), _p(out["cell"]),
+                      _p(out["ox"]), _p(out["oy"]), _p(out["vx"]), _p(out["vy"]))
+    return {k: v[:m].copy() for k, v in out.items()}
 
 
 def rewind(w, s: int, p: dict, Ex, Ey, precision="f32"):
@@ -385,6 +429,7 @@ class Sim:
         self.p = [_state(q, dt) for q in particles]
         self.nc = node_cond(w)
         self.step_index = 0
+        self.emitted = 0
         self.tally = np.zeros((len(self.p), 9), np.int64)
         self.surf = np.zeros(w.ny, np.int64)
         self.phi = None
@@ -418,9 +463,22 @@ class Sim:
         self.deposit_assemble()
         self.solve()
         Ex, Ey = field(w, self.nc, self.phi)
+        see = any(float(y) > 0.0 for y in w.see_yield)
+        removals = []
         for s, q in enumerate(self.p):
             surf = self.surf if (w.charge_mode == 2 and w.species[s].sign > 0) else None
-            push(w, s, q, Ex, Ey, self.prec, self.tally[s], surf, step=self.step_index)
+            hits = HitRecords(min(q["cell"].size, 1 << 20)) if see else None
+            push(w, s, q, Ex, Ey, self.prec, self.tally[s], surf, step=self.step_index, hits=hits)
+            if see:
+                removals.append((s, hits.rows()))
+        if see:
+            # secondary electrons of this step's trench-surface impacts join the
+            # electrons after both pushes (pushed from the next step on)
+            new = emit(w, removals, self.step_index)
+            self.emitted += int(new["cell"].size)
+            dt = self.p[0]["ox"].dtype
+            self.p[0] = {k: np.concatenate([self.p[0][k], new[k].astype(self.p[0][k].dtype if k == "cell" else dt)])
+                         for k in self.p[0]}
         self.step_index += 1
 
     def alive(self, s):

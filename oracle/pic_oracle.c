@@ -352,6 +352,26 @@ void or_recycled_ion(const or_recycle *rc, float ux, float ox0, float oy0, int n
     *vy = rc->vth * rad * sin(ang);
 }
 
+/* Optional record of every removal of the push: (class, last cell occupied
+ * as a packed code, bits of the kicked float32 velocity), cap rows. */
+typedef struct {
+    int64_t cap, n;
+    int32_t *rec;                 /* cap x 4 */
+} or_hits;
+
+static void hit_record(or_hits *h, int cls, int ci, int cj, float ux, float uy)
+{
+    if (!h) return;
+    if (h->n < h->cap) {
+        int32_t *r = h->rec + 4 * h->n;
+        r[0] = cls;
+        r[1] = (int32_t)(((uint32_t)ci << 16) | (uint32_t)cj);
+        memcpy(&r[2], &ux, 4);
+        memcpy(&r[3], &uy, 4);
+    }
+    h->n++;
+}
+
 #define PUSH_BODY(T, FLOOR)                                                          \
     int NY = py ? ny : ny + 1;                                                       \
     T qdt = (T)(alpha * dt), dtt = (T)dt;                                            \
@@ -384,6 +404,7 @@ void or_recycled_ion(const or_recycle *rc, float ux, float ox0, float oy0, int n
         if (!(fabs((double)fsx) < 1.0e6 && fabs((double)fsy) < 1.0e6)) {            \
             cell[p] = -1 - 8; lost++;                                                \
             if (tally) tally[8]++;                                                   \
+            hit_record(hits, 8, i, j, (float)ux, (float)uy);                         \
             continue;                                                                \
         }                                                                            \
         int sx = (int)fsx, sy = (int)fsy;                                            \
@@ -418,6 +439,7 @@ void or_recycled_ion(const or_recycle *rc, float ux, float ox0, float oy0, int n
             lost++;                                                                  \
             if (tally) tally[dead]++;                                                \
             if (surf && dead == 4) surf[cj]++;                                       \
+            hit_record(hits, dead, ci, cj, (float)ux, (float)uy);                    \
             if (rc && rc->rows > 0) {                                                \
                 int32_t code; float nox, noy; double nvx, nvy;                       \
                 or_recycled_ion(rc, (float)ux, (float)x0, (float)y0, ny, &code,      \
@@ -443,7 +465,7 @@ int64_t or_push_f32(int nx, int ny, int px, int py, const uint8_t *cell_cond,
                     int box_i_top, int box_j_lo, int box_j_hi, double dt, double alpha,
                     const double *Ex, const double *Ey, int64_t n, int32_t *cell,
                     float *ox, float *oy, float *vx, float *vy, int64_t *tally,
-                    int64_t *surf, const or_recycle *rc)
+                    int64_t *surf, const or_recycle *rc, or_hits *hits)
 {
     PUSH_BODY(float, floorf)
 }
@@ -452,7 +474,7 @@ int64_t or_push_f64(int nx, int ny, int px, int py, const uint8_t *cell_cond,
                     int box_i_top, int box_j_lo, int box_j_hi, double dt, double alpha,
                     const double *Ex, const double *Ey, int64_t n, int32_t *cell,
                     double *ox, double *oy, double *vx, double *vy, int64_t *tally,
-                    int64_t *surf, const or_recycle *rc)
+                    int64_t *surf, const or_recycle *rc, or_hits *hits)
 {
     PUSH_BODY(double, floor)
 }
@@ -499,4 +521,63 @@ void or_rewind_f64(int nx, int ny, int px, int py, double dt, double alpha,
                    const double *ox, const double *oy, double *vx, double *vy)
 {
     REWIND_BODY(double)
+}
+
+/* ------------------------------------------------------------------------
+ * Secondary electron emission at the trench surfaces.  The paper names it
+ * as future work (Sec. IV: emission through ion and through electron
+ * bombardment) and gives no yield model.  Reading taken: a particle of
+ * species s removed at a trench surface (the bottom, class 4; the
+ * sidewalls, classes 6 and 7) frees one electron with the constant
+ * probability yield_s.  The electron starts in the cell the particle last
+ * occupied, on the struck face (normal offset at the face: the largest float
+ * below 1 on a cell's high side, 0 on its low side), uniformly along it, and
+ * leaves the surface with a flux-weighted half-Maxwellian of thermal speed
+ * vth: normal speed vth sqrt(-2 ln u) away from the wall, tangential
+ * velocity vth sqrt(-2 ln u') cos(2 pi u'').  Its velocity is taken as the
+ * half-step velocity of the step that created it (as for recycled ions).
+ * Draws: Philox4x32-10 (Salmon et al., SC 2011) keyed by (k0, k1), counter
+ * (step, packed cell, bits of the kicked float32 velocity (ux, uy)):
+ *   r = Philox(ctr, (k0, k1)):     emitted iff (r0 >> 8) < thresh_s
+ *                                  (thresh_s = floor(yield_s 2^24));
+ *                                  along-face offset (r1 >> 8) 2^-24
+ *   q = Philox(ctr, (k0, k1 + 1)): u = ((q0 >> 8) + 1) 2^-24,
+ *                                  u' = ((q1 >> 8) + 1) 2^-24, u'' = (q2 >> 8) 2^-24
+ * in double, the velocity rounded to float.  Input: nh removals (species
+ * and a 4-word record each, as or_hits writes them); output: the emitted
+ * electrons (at most nh).  Returns their number.
+ * ---------------------------------------------------------------------- */
+int64_t or_emit(int64_t nh, const int32_t *species, const int32_t *rec, int64_t step, uint32_t k0, uint32_t k1,
+                const uint32_t *thresh, double vth, int32_t *cell, float *ox, float *oy, float *vx, float *vy)
+{
+    int64_t m = 0;
+    const float below1 = nextafterf(1.0f, 0.0f);
+    for (int64_t h = 0; h < nh; h++) {
+        const int32_t *r4 = rec + 4 * h;
+        const int cls = r4[0];
+        if (cls != 4 && cls != 6 && cls != 7) continue;
+        const int s = species[h];
+        if (s < 0 || s > 1 || thresh[s] == 0) continue;
+        uint32_t ctr[4] = {(uint32_t)step, (uint32_t)r4[1], (uint32_t)r4[2], (uint32_t)r4[3]};
+        uint32_t key[2] = {k0, k1}, r[4], q[4];
+        or_philox4x32_10(ctr, key, r);
+        if ((r[0] >> 8) >= thresh[s]) continue;
+        key[1] += 1u;
+        or_philox4x32_10(ctr, key, q);
+        const float a = (float)(r[1] >> 8) * 0x1p-24f;
+        const double u1 = (double)((q[0] >> 8) + 1u) * 0x1p-24, u2 = (double)((q[1] >> 8) + 1u) * 0x1p-24;
+        const double u3 = (double)(q[2] >> 8) * 0x1p-24;
+        const double vn = vth * sqrt(-2.0 * log(u1));
+        const double vt = vth * sqrt(-2.0 * log(u2)) * cos(6.283185307179586 * u3);
+        cell[m] = r4[1];
+        if (cls == 4) {                 /* +x face (the bottom): back along -x */
+            ox[m] = below1; oy[m] = a; vx[m] = (float)(-vn); vy[m] = (float)vt;
+        } else if (cls == 6) {          /* +y face: back along -y */
+            ox[m] = a; oy[m] = below1; vx[m] = (float)vt; vy[m] = (float)(-vn);
+        } else {                        /* -y face: back along +y */
+            ox[m] = a; oy[m] = 0.0f; vx[m] = (float)vt; vy[m] = (float)vn;
+        }
+        m++;
+    }
+    return m;
 }

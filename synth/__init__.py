@@ -67,11 +67,20 @@ class Workload:
     # ion recycling (Sec. III.A, III.C): a lost ion is replaced by a thermal ion
     # in the bulk cell rows 0 .. recycle_rows-1 (0: off)
     recycle_rows: int = 0
+    # secondary electron emission at the trench surfaces (Sec. IV): electrons
+    # freed per impact of an electron / an ion (0: off), and the thermal
+    # speed of the emitted electrons (electron thermal speed units)
+    see_yield: tuple = (0.0, 0.0)
+    see_vth: float = 0.0
     extra: dict = field(default_factory=dict)
 
     def recycle_key(self) -> tuple:
         """Key of the recycling generator (two 32-bit words)."""
         return (int(self.seed) & 0xFFFFFFFF, 0x1610D3F1)
+
+    def see_key(self) -> tuple:
+        """Key of the secondary-emission generator (two 32-bit words)."""
+        return (int(self.seed) & 0xFFFFFFFF, 0x5EE0E1EC)
 
     @property
     def NX(self) -> int:
