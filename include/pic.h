@@ -117,6 +117,28 @@ typedef struct {
     int32_t recycle_rows;
     uint32_t recycle_key[2];
     double recycle_vth;          /* Gaussian sigma of each velocity component of a new ion */
+    /* secondary electron emission at the trench surfaces (Sec. IV names it as
+     * future work, through ion and through electron bombardment, and gives no
+     * yield model; the reading here is a constant yield per impact).  A
+     * particle of species s removed at the trench bottom or a sidewall
+     * (classes 4, 6, 7) frees one electron with probability see_yield[s]:
+     * the electron starts in the cell the particle last occupied, on the
+     * struck face (offset along it uniform), with a flux-weighted
+     * half-Maxwellian of thermal speed see_vth away from the wall (normal
+     * speed see_vth sqrt(-2 ln u), tangential velocity Gaussian), taken as
+     * the half-step velocity of the step that freed it.  Draws: Philox4x32-10
+     * with key see_key, counter (step, packed cell, bits of the removed
+     * particle's kicked velocity); emitted iff (r0 >> 8) < floor(yield 2^24).
+     * The new electrons are appended to species 0 (up to its capacity; the
+     * excess is counted in pic_diag.see_dropped) within the same pic_push,
+     * their charge added to rho[0], and pushed from the next step on.  The
+     * emission reads the removals from the hit ring, so hitlog_capacity must
+     * hold one step's removals of the logged species (at least 65536) and
+     * hitlog_species_mask must log every species with a yield > 0.
+     * 0 = off. */
+    double see_yield[2];         /* electrons freed per impact of species s (0 .. 1) */
+    double see_vth;              /* thermal speed of the emitted electrons (> 0 with a yield) */
+    uint32_t see_key[2];
 } pic_config;
 
 typedef struct {
@@ -165,6 +187,9 @@ typedef struct {
     double field_energy;         /* 0.5 sum over nodes of |E|^2 (node field of the current phi) */
     int64_t iad[PIC_IAD_BINS];   /* ions absorbed by the trench bottom per 2-degree bin of the
                                     impact angle atan2(v_y, v_x) in [-90, 90) degrees (Sec. III.C) */
+    int64_t see_emitted;         /* secondary electrons appended so far (counted in alive[0]) */
+    int64_t see_dropped;         /* freed electrons beyond species 0's capacity, plus removal records
+                                    overwritten in the hit ring before the emission read them */
 } pic_diag;
 
 typedef struct {

@@ -168,6 +168,29 @@ struct PushArgs {
     double recycle_vth;
 };
 
+// Secondary electron emission of one instance (k_emit, k_emit_finish):
+// the removals logged in the hit ring since the last call free electrons
+// that are appended to species 0 (the set in use), after its binned slots.
+struct SeeArgs {
+    Geom g;
+    const int32_t *rec;                 // hit ring, capacity x 6 int32 (pic_hit layout)
+    const unsigned long long *log_count;// records written so far
+    long long log_capacity;
+    unsigned long long *misc;           // [0] records consumed, [1] slots asked this step,
+                                        // [2] electrons appended, [3] dropped
+    unsigned thresh[2];                 // floor(yield_s 2^24)
+    double vth;
+    unsigned key[2];
+    int32_t *cell[2];                   // species 0, both storage sets; info[7] selects
+    float *ox[2], *oy[2], *vx[2], *vy[2];
+    long long *info;                    // species 0: [1] push blocks, [2 + set] slots,
+                                        // [4] slots binned, [5] blocks of the binned slots, [7] set
+    int4 *table;                        // species 0 push table
+    long long capacity;
+    int chunk;
+    unsigned long long *rho;            // charge of species 0
+};
+
 struct BinArgs {
     int nx, ny;
     int lx, ly, tiles_y, ntiles, chunk;
@@ -239,6 +262,9 @@ void launch_tick(long long *step, hipStream_t s);
 // summed in block order into out[0] (kinetic) / out[0] (field)
 void launch_kinetic(const PushArgs *A, int unit, double *part, double *out, hipStream_t s);
 void launch_recycle(const PushArgs *A, const Tab &t, hipStream_t s);
+// secondary electron emission: t has kEmitBlocks blocks per unit, t1 one
+constexpr int kEmitBlocks = 32;
+void launch_emit(const SeeArgs *A, const Tab &t, const Tab &t1, hipStream_t s);
 void launch_field_energy(const Inst *I, int inst, double *part, double *out, hipStream_t s);
 int bin_per_block();
 

@@ -2880,6 +2880,10 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const BinArgs *B, Tab t)
         a.info[0] = (long long)sp[tid];
         a.info[1] = (long long)sb[tid];
         a.info[2 + (1 - (int)a.info[7])] = (long long)sp[tid];
+        // the binned slots and their push blocks: particles appended later
+        // (secondary emission) get push blocks after these
+        a.info[4] = (long long)sp[tid];
+        a.info[5] = (long long)sb[tid];
     }
 }
 
@@ -3067,6 +3071,115 @@ void launch_rho_sum(const unsigned long long *rho, long long n, unsigned long lo
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_rho_sum, dim3((unsigned)nb), dim3(256), 0, s, rho, n, out);
+}
+
+// ---------------------------------------------------------------------------
+// secondary electron emission at the trench surfaces (Sec. IV; constant
+// yield per impact, see pic_config.see_yield)
+// ---------------------------------------------------------------------------
+
+// The removals logged since the last call (grid-stride over the ring):
+// every trench-surface removal (classes 4, 6, 7) of a species with a yield
+// draws from Philox4x32-10, counter (step, packed cell, bits of the kicked
+// velocity), key (k0, k1), and with (r0 >> 8) < thresh frees an electron:
+// on the struck face of the cell (normal offset the largest float below 1
+// on the cell's high side, 0 on its low side; along it (r1 >> 8) 2^-24),
+// normal speed vth sqrt(-2 ln u) away from the wall and tangential velocity
+// vth sqrt(-2 ln u') cos(2 pi u'') from the draw with key (k0, k1 + 1)
+// (u = ((q0 >> 8) + 1) 2^-24, u' = ((q1 >> 8) + 1) 2^-24, u'' = (q2 >> 8)
+// 2^-24, in double, rounded to float).  Each takes a slot after species 0's
+// slots (a counter; beyond the capacity it is dropped and counted) and adds
+// its charge to rho.  Records overwritten before this call are counted as
+// dropped.
+__global__ __launch_bounds__(256) void k_emit(const SeeArgs *A, Tab t)
+{
+    const int ku = unit_of(t, (int)blockIdx.x);
+    const SeeArgs &a = A[t.id[ku]];
+    const int lb = (int)blockIdx.x - t.boff[ku];
+    const unsigned long long total = *a.log_count, done = a.misc[0];
+    const unsigned long long cap = (unsigned long long)a.log_capacity;
+    const unsigned long long first = total - done > cap ? total - cap : done;
+    if (lb == 0 && threadIdx.x == 0 && first > done) atomicAdd(&a.misc[3], first - done);
+    const int set = (int)a.info[7];
+    const long long slots0 = a.info[2 + set];
+    GLOBAL int32_t *cell = to_global(a.cell[set]);
+    GLOBAL float *ox = to_global(a.ox[set]), *oy = to_global(a.oy[set]);
+    GLOBAL float *vx = to_global(a.vx[set]), *vy = to_global(a.vy[set]);
+    const float below1 = 0x1.fffffep-1f;
+    for (unsigned long long k = first + (unsigned long long)lb * 256 + threadIdx.x; k < total;
+         k += (unsigned long long)kEmitBlocks * 256) {
+        const int32_t *r = a.rec + 6 * (long long)(k % cap);
+        const int sc = r[0], cls = sc & 0xFF, sp = sc >> 8;
+        if ((cls != 4 && cls != 6 && cls != 7) || sp < 0 || sp > 1 || a.thresh[sp] == 0u) continue;
+        const unsigned c0 = (unsigned)r[4], c1 = (unsigned)r[1], c2 = (unsigned)r[2], c3 = (unsigned)r[3];
+        const Philox4 d = philox4x32_10(c0, c1, c2, c3, a.key[0], a.key[1]);
+        if ((d.x >> 8) >= a.thresh[sp]) continue;
+        const Philox4 q = philox4x32_10(c0, c1, c2, c3, a.key[0], a.key[1] + 1u);
+        const float along = (float)(d.y >> 8) * 0x1p-24f;
+        const double u1 = (double)((q.x >> 8) + 1u) * 0x1p-24, u2 = (double)((q.y >> 8) + 1u) * 0x1p-24;
+        const double u3 = (double)(q.z >> 8) * 0x1p-24;
+        const double vn = a.vth * sqrt(-2.0 * log(u1));
+        const double vt = a.vth * sqrt(-2.0 * log(u2)) * cos(6.283185307179586 * u3);
+        float nox, noy, nvx, nvy;
+        if (cls == 4) {             // +x face (the bottom): back along -x
+            nox = below1; noy = along; nvx = (float)(-vn); nvy = (float)vt;
+        } else if (cls == 6) {      // +y face: back along -y
+            nox = along; noy = below1; nvx = (float)vt; nvy = (float)(-vn);
+        } else {                    // -y face: back along +y
+            nox = along; noy = 0.0f; nvx = (float)vt; nvy = (float)vn;
+        }
+        const long long slot = slots0 + (long long)atomicAdd(&a.misc[1], 1ull);
+        if (slot >= a.capacity) {
+            atomicAdd(&a.misc[3], 1ull);
+            continue;
+        }
+        cell[slot] = r[1];
+        ox[slot] = nox;
+        oy[slot] = noy;
+        vx[slot] = nvx;
+        vy[slot] = nvy;
+        const int ci = (int)((unsigned)r[1] >> 16), cj = r[1] & 0xFFFF;
+        deposit_global(to_global(a.rho), a.g, ci, cj, (unsigned)floorf(nox * 65536.0f),
+                       (unsigned)floorf(noy * 65536.0f));
+    }
+}
+
+// After k_emit: the slots of species 0 grow by the electrons that found
+// room, the push table gets blocks of `chunk` slots over everything past the
+// binned slots (on tile 0's window; the push reads other cells' fields and
+// deposits their charge through its global paths), and the ring position
+// and counters move on.
+__global__ void k_emit_finish(const SeeArgs *A, Tab t)
+{
+    const SeeArgs &a = A[t.id[unit_of(t, (int)blockIdx.x)]];
+    const int set = (int)a.info[7];
+    const long long slots0 = a.info[2 + set];
+    const long long want = (long long)a.misc[1];
+    const long long room = a.capacity > slots0 ? a.capacity - slots0 : 0;
+    const long long got = want < room ? want : room;
+    const long long slots = slots0 + got;
+    const long long t0 = a.info[4], nb0 = a.info[5];
+    const long long nb = slots > t0 ? (slots - t0 + a.chunk - 1) / a.chunk : 0;
+    for (long long k = threadIdx.x; k < nb; k += blockDim.x) {
+        const long long s0 = t0 + k * a.chunk;
+        const long long s1 = s0 + a.chunk < slots ? s0 + a.chunk : slots;
+        a.table[nb0 + k] = make_int4(0, (int)s0, (int)s1, 0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.info[2 + set] = slots;
+        a.info[1] = nb0 + nb;
+        a.misc[0] = *a.log_count;
+        a.misc[1] = 0ull;
+        a.misc[2] += (unsigned long long)got;
+    }
+}
+
+void launch_emit(const SeeArgs *A, const Tab &t, const Tab &t1, hipStream_t s)
+{
+    if (!t.n) return;
+    hipLaunchKernelGGL(k_emit, dim3(tab_blocks(t)), dim3(256), 0, s, A, t);
+    hipLaunchKernelGGL(k_emit_finish, dim3(tab_blocks(t1)), dim3(64), 0, s, A, t1);
 }
 
 } // namespace pic

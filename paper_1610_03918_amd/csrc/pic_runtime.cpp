@@ -62,6 +62,9 @@ pic_status validate_status(const std::string &v)
     return v.rfind("charge overflow", 0) == 0 ? PIC_ERR_OVERFLOW : PIC_ERR_ARG;
 }
 
+// Secondary electron emission at the trench surfaces is on.
+bool see_on(const pic_config *c) { return c->see_yield[0] > 0.0 || c->see_yield[1] > 0.0; }
+
 std::string validate(const pic_config *c, const int64_t *cap)
 {
     if (!c) return "null config";
@@ -105,6 +108,16 @@ std::string validate(const pic_config *c, const int64_t *cap)
     if (c->cell_cond)
         for (size_t q = 0; q < (size_t)c->recycle_rows * c->ny; q++)
             if (c->cell_cond[q]) return "the recycling rows must hold no solid cell";
+    for (int s = 0; s < 2; s++)
+        if (!(c->see_yield[s] >= 0.0 && c->see_yield[s] <= 1.0)) return "see_yield must be in 0 .. 1";
+    if (see_on(c)) {
+        if (!(c->see_vth > 0.0)) return "see_vth must be positive with a secondary-emission yield";
+        if (c->hitlog_capacity < 65536)
+            return "secondary emission reads the hit ring: hitlog_capacity must be at least 65536";
+        for (int s = 0; s < 2; s++)
+            if (c->see_yield[s] > 0.0 && !((c->hitlog_species_mask >> s) & 1))
+                return "secondary emission: hitlog_species_mask must log every species with a yield";
+    }
     return "";
 }
 
@@ -204,6 +217,9 @@ Layout make_layout(const pic_config *c, const int64_t *cap)
     L.unroll = c->push_unroll ? c->push_unroll : 4;
     L.merge = c->push_merge;
     for (int s = 0; s < 2; s++) L.max_blocks[s] = L.ntiles + (cap[s] + L.chunk - 1) / L.chunk;
+    // appended electrons (secondary emission) get blocks of their own after
+    // the binned ones: at most two more than a full binning would need
+    if (see_on(c)) L.max_blocks[0] += 2;
     int maxrows = std::max(L.NX, L.nx), maxcols = std::max(L.NY, L.ny);
     L.grid_blocks = ((maxcols + kGridBX - 1) / kGridBX) * ((maxrows + kGridBY - 1) / kGridBY);
     return L;
@@ -285,6 +301,8 @@ struct pic_ctx {
     // launch tables
     Tab t_l0{}, t_field{}, t_per{}, t_coarse{}, t_push{}, t_rewind{};
     Tab t_recycle{};                // ion units with recycling: one thread per slot
+    Tab t_see{}, t_see1{};          // instances with secondary emission: kEmitBlocks blocks / one
+    SeeArgs *d_see = nullptr;
     Tab t_plain{};                 // level-0 grid of the instances solved by plain CG
     Tab t_fine[kMaxLev] = {};      // 32 x 32 tiles of the fine multigrid levels handled one at a time
     Tab t_pair[kMaxLev] = {};      // 32 x 32 tiles of level l + 1 for levels l, l + 1 in one launch
@@ -510,6 +528,7 @@ size_t carve_all(pic_ctx *c, int n, const pic_config *cfgs, const int64_t *caps,
     Inst *di = w.take<Inst>(n);
     PushArgs *dp = w.take<PushArgs>(2 * n);
     BinArgs *db = w.take<BinArgs>(2 * n);
+    SeeArgs *dse = w.take<SeeArgs>(n);
     double *part = w.take<double>((size_t)2 * stride);
     double *S = w.take<double>((size_t)n * S_NSCAL);
     int *F = w.take<int>((size_t)n * F_NFLAG);
@@ -519,6 +538,7 @@ size_t carve_all(pic_ctx *c, int n, const pic_config *cfgs, const int64_t *caps,
         c->d_inst = di;
         c->d_push = dp;
         c->d_bin = db;
+        c->d_see = dse;
         c->d_part = part;
         c->part_stride = stride;
         c->d_S = S;
@@ -971,6 +991,7 @@ void enqueue_push(pic_ctx *c, hipStream_t s, bool timed)
         for (auto &h : c->in) c->timed_particles += h.slots_ub[0] + h.slots_ub[1];
     }
     launch_recycle(c->d_push, c->t_recycle, s);     // before the step counter moves on
+    launch_emit(c->d_see, c->t_see, c->t_see1, s);  // its charge joins rho before the assembly
     launch_tick(c->d_ctl, s);
     enqueue_assemble(c, s);
 }
@@ -1023,6 +1044,8 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
         h.loaded[s] = buf->sp[s].count;
         h.slots_ub[s] = buf->sp[s].count;
     }
+    // emitted electrons are appended to species 0, up to its capacity
+    if (see_on(cfg)) h.slots_ub[0] = buf->sp[0].capacity;
     // masks of every level: level 0 = Dirichlet nodes (plus node 0 pinned on a
     // fully periodic grid); coarse node fixed iff its coincident fine node is
     h.fixh.assign(L.nlev, {});
@@ -1191,9 +1214,37 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
         b.table = h.d_table[sp];
         b.info = h.d_info[sp];
         HIPCHK(c, hipMemcpyAsync(c->d_bin + 2 * k + sp, &b, sizeof b, hipMemcpyHostToDevice, s));
-        long long info[8] = {0, 0, buf->sp[sp].count, 0, 0, 0, 0, 0};
+        long long info[8] = {0, 0, buf->sp[sp].count, 0, buf->sp[sp].count, 0, 0, 0};
         HIPCHK(c, hipMemcpyAsync(h.d_info[sp], info, sizeof info, hipMemcpyHostToDevice, s));
         HIPCHK(c, hipStreamSynchronize(s));   // the small host structs above go out of scope
+    }
+    {
+        SeeArgs e;
+        memset(&e, 0, sizeof e);
+        e.g = h.g;
+        e.rec = h.d_hits;
+        e.log_count = h.d_misc + 1;
+        e.log_capacity = std::max<int64_t>(h.cfg.hitlog_capacity, 1);
+        e.misc = h.d_misc + 8;
+        for (int sp = 0; sp < 2; sp++)
+            e.thresh[sp] = (unsigned)std::floor(h.cfg.see_yield[sp] * 16777216.0);
+        e.vth = h.cfg.see_vth;
+        e.key[0] = h.cfg.see_key[0];
+        e.key[1] = h.cfg.see_key[1];
+        for (int q = 0; q < 2; q++) {
+            e.cell[q] = buf->sp[0].cell[q];
+            e.ox[q] = buf->sp[0].ox[q];
+            e.oy[q] = buf->sp[0].oy[q];
+            e.vx[q] = buf->sp[0].vx[q];
+            e.vy[q] = buf->sp[0].vy[q];
+        }
+        e.info = h.d_info[0];
+        e.table = h.d_table[0];
+        e.capacity = buf->sp[0].capacity;
+        e.chunk = L.chunk;
+        e.rho = reinterpret_cast<unsigned long long *>(buf->rho[0]);
+        HIPCHK(c, hipMemcpyAsync(c->d_see + k, &e, sizeof e, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));
     }
     HIPCHK(c, hipMemsetAsync(h.d_tally, 0, sizeof(unsigned long long) * 2 * kNClass, s));
     HIPCHK(c, hipMemsetAsync(h.d_surf, 0, sizeof(unsigned long long) * (L.ny + 1), s));
@@ -1215,6 +1266,7 @@ pic_status init_instance(pic_ctx *c, int k, const pic_config *cfg, const pic_buf
 void build_tabs(pic_ctx *c)
 {
     c->t_l0 = c->t_field = c->t_per = c->t_coarse = c->t_push = c->t_rewind = c->t_plain = c->t_recycle = Tab{};
+    c->t_see = c->t_see1 = Tab{};
     for (int l = 0; l < kMaxLev; l++) c->t_fine[l] = c->t_pair[l] = Tab{};
     c->maxlg = 0;
     c->coarse_lds = 0;
@@ -1253,6 +1305,10 @@ void build_tabs(pic_ctx *c)
                 tab_add(c->t_recycle, 2 * k + s, (int)std::max<long long>(1, (h.slots_ub[s] + 255) / 256));
         }
         c->push_lds = std::max(c->push_lds, push_lds_bytes(L.TX, L.TY, L.H));
+        if (see_on(&h.cfg)) {
+            tab_add(c->t_see, k, kEmitBlocks);
+            tab_add(c->t_see1, k, 1);
+        }
     }
     c->unroll = c->in[0].L.unroll;
     c->merge = c->in[0].L.merge;
@@ -1639,7 +1695,7 @@ pic_status pic_batch_diagnostics(pic_ctx *c, int32_t i, pic_diag *out)
             if (!recycled || k == kNClass - 1) lost += (long long)tally[sp * kNClass + k];
         }
         out->loaded[sp] = h.loaded[sp];
-        out->alive[sp] = h.loaded[sp] - lost;
+        out->alive[sp] = h.loaded[sp] - lost + (sp == 0 ? (long long)misc[10] : 0);
         out->charge[sp] = (int64_t)misc[4 + sp];
     }
     long long sh = 0;
@@ -1652,6 +1708,8 @@ pic_status pic_batch_diagnostics(pic_ctx *c, int32_t i, pic_diag *out)
         out->kinetic[sp] = 0.5 * h.cfg.weight * dsum[sp] / std::fabs(h.cfg.alpha[sp]);
     out->field_energy = dsum[2];
     for (int k = 0; k < kIadBins; k++) out->iad[k] = (int64_t)iad[k];
+    out->see_emitted = (int64_t)misc[10];
+    out->see_dropped = (int64_t)misc[11];
     return PIC_OK;
 }
 

@@ -38,7 +38,8 @@ class pic_config(C.Structure):
         ("push_unroll", C.c_int32), ("push_merge", C.c_int32),
         ("hitlog_capacity", C.c_int64), ("hitlog_species_mask", C.c_int32),
         ("warm_start", C.c_int32), ("recycle_rows", C.c_int32), ("recycle_key", C.c_uint32 * 2),
-        ("recycle_vth", C.c_double),
+        ("recycle_vth", C.c_double), ("see_yield", C.c_double * 2), ("see_vth", C.c_double),
+        ("see_key", C.c_uint32 * 2),
     ]
 
 
@@ -69,7 +70,8 @@ class pic_diag(C.Structure):
                 ("tally", (C.c_int64 * NCLASS) * 2), ("surf_hits", C.c_int64),
                 ("hits_logged", C.c_int64), ("deposit_fallbacks", C.c_int64),
                 ("last_solve", pic_solve_info), ("kinetic", C.c_double * 2),
-                ("field_energy", C.c_double), ("iad", C.c_int64 * IAD_BINS)]
+                ("field_energy", C.c_double), ("iad", C.c_int64 * IAD_BINS),
+                ("see_emitted", C.c_int64), ("see_dropped", C.c_int64)]
 
 
 class pic_hit(C.Structure):
@@ -180,6 +182,14 @@ def make_config(w, *, solver=0, max_iter=2000, sort_interval=(8, 64), tile=(16, 
         k0, k1 = w.recycle_key()
         cfg.recycle_key[0], cfg.recycle_key[1] = k0, k1
         cfg.recycle_vth = float(w.species[1].vth)
+    see = tuple(float(y) for y in getattr(w, "see_yield", (0.0, 0.0)))
+    if any(y > 0.0 for y in see):
+        cfg.see_yield[0], cfg.see_yield[1] = see
+        cfg.see_vth = float(w.see_vth)
+        cfg.see_key[0], cfg.see_key[1] = w.see_key()
+        # the emission reads every removal of the emitting species from the hit ring
+        cfg.hitlog_capacity = max(int(cfg.hitlog_capacity), 1 << 20)
+        cfg.hitlog_species_mask |= (1 if see[0] > 0.0 else 0) | (2 if see[1] > 0.0 else 0)
     return cfg, cc
 
 
@@ -351,7 +361,7 @@ class Pic(_Context):
             "tally": [list(d.tally[s]) for s in range(2)], "surf_hits": d.surf_hits,
             "hits_logged": d.hits_logged, "deposit_fallbacks": d.deposit_fallbacks,
             "kinetic": list(d.kinetic), "field_energy": d.field_energy, "iad": list(d.iad),
-            "last_solve": d.last_solve.as_dict(),
+            "last_solve": d.last_solve.as_dict(), "see_emitted": d.see_emitted, "see_dropped": d.see_dropped,
         }
 
     def pic_particles(self, s):
@@ -423,7 +433,9 @@ class PicBatch(_Context):
     """Several independent instances (e.g. a trench-width sweep) in one
     context; every kernel launch covers all of them (pic_batch_* calls)."""
 
-    def __init__(self, workloads, particles, device="cuda:0", **opts):
+    def __init__(self, workloads, particles, device="cuda:0", capacities=None, **opts):
+        """capacities: per instance (electron, ion) slot counts, or None for
+        the loaded counts."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
@@ -432,7 +444,8 @@ class PicBatch(_Context):
         self.dev = torch.device(device)
         self.ws = list(workloads)
         self.n = len(self.ws)
-        self.insts = [_Instance(torch, self.dev, w, p, None, opts) for w, p in zip(self.ws, particles)]
+        caps = capacities if capacities is not None else [None] * self.n
+        self.insts = [_Instance(torch, self.dev, w, p, c, opts) for w, p, c in zip(self.ws, particles, caps)]
         cfgs = (pic_config * self.n)(*[x.cfg for x in self.insts])
         bufs = (pic_buffers * self.n)(*[x.bufs for x in self.insts])
         caps = (C.c_int64 * (2 * self.n))(*[c for x in self.insts for c in x.capacity])
@@ -486,6 +499,7 @@ class PicBatch(_Context):
             "surf_hits": d.surf_hits, "hits_logged": d.hits_logged,
             "deposit_fallbacks": d.deposit_fallbacks,
             "kinetic": list(d.kinetic), "field_energy": d.field_energy, "iad": list(d.iad), "last_solve": d.last_solve.as_dict(),
+            "see_emitted": d.see_emitted, "see_dropped": d.see_dropped,
         }
 
     def pic_batch_particles(self, i, s):

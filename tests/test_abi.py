@@ -107,3 +107,47 @@ def test_capacity_beyond_the_fixed_point_charge_bound_is_an_overflow():
     assert _ws(cfg, [1 << 31, 10])[0] == -6
     assert _ws(cfg, [10, 1 << 40])[0] == -6
     assert _ws(cfg, [-1, 10])[0] == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the C structs have the header's size and field
+    offsets (compiled with the host C compiler)."""
+    import subprocess
+    from paper_1610_03918_amd import pic
+    structs = [pic.pic_config, pic.pic_species_buffers, pic.pic_buffers, pic.pic_solve_info, pic.pic_diag,
+               pic.pic_hit]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void) {"]
+    want = []
+    for st in structs:
+        lines.append(f'    printf("%zu\\n", sizeof({st.__name__}));')
+        want.append(C.sizeof(st))
+        for name, *_ in st._fields_:
+            lines.append(f'    printf("%zu\\n", offsetof({st.__name__}, {name}));')
+            want.append(getattr(st, name).offset)
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == want
+
+
+def test_secondary_emission_configuration_is_validated():
+    """Yields outside 0..1, a missing emission speed, a short hit ring or a
+    species with a yield that the ring does not log are refused."""
+    from paper_1610_03918_amd import pic
+    w = synth.trench(nx=48, ny=40, width=6, depth=12, ppc=1, seed=3)
+    w.see_yield, w.see_vth = (0.0, 0.5), 0.3
+    cfg, cc = pic.make_config(w)
+    cap = (C.c_int64 * 2)(1000, 1000)
+    nb = C.c_size_t(0)
+    assert pic.lib().pic_workspace_size(C.byref(cfg), cap, C.byref(nb)) == 0
+    assert cfg.hitlog_capacity >= 65536 and cfg.hitlog_species_mask & 2
+    for field, value in (("see_vth", 0.0), ("hitlog_capacity", 1000), ("hitlog_species_mask", 1)):
+        bad, _ = pic.make_config(w)
+        setattr(bad, field, value)
+        assert pic.lib().pic_workspace_size(C.byref(bad), cap, C.byref(nb)) == -1, field
+    bad, _ = pic.make_config(w)
+    bad.see_yield[1] = 1.5
+    assert pic.lib().pic_workspace_size(C.byref(bad), cap, C.byref(nb)) == -1
