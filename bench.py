@@ -360,21 +360,33 @@ def run_trench_study(args):
     ratio, the same with only the sidewall hits at least 5 cells below the
     trench mouth (the paper draws its sidewalls from x = 65 to 80), the
     cumulative counts every 50 time units, and the mean impact angle of the
-    bottom and sidewall hits."""
+    bottom and sidewall hits.  With --see GI,GE the trench surfaces emit
+    secondary electrons (Sec. IV; constant yields per ion / electron impact,
+    emission speed --see-vth): the same counts, the electrons emitted, and the
+    potential at the trench's mid-depth centre averaged over the window."""
     import numpy as np
     import torch
 
     import synth
     from paper_1610_03918_amd import Pic
+    see = tuple(float(x) for x in args.see.split(",")) if args.see else None
     rows = []
     for width, charged, t_from in ((15, False, 600), (4, False, 600), (15, True, 700)):
         w = synth.paper_trench(width, charged, seed=args.study_seed)
-        pic = Pic(w, synth.load(w), hitlog_capacity=1 << 21, hitlog_species_mask=2)
+        if see:
+            w.see_yield = (see[1], see[0])            # species 0 electrons, 1 ions
+            w.see_vth = args.see_vth
+        cap = 1 << (22 if see else 21)
+        pic = Pic(w, synth.load(w), hitlog_capacity=cap, hitlog_species_mask=2,
+                  capacity=None if not see else (2 * w.n_particles(0), w.n_particles(1)))
         pic.start()
         k_from = int(round(t_from / w.dt))
         every = int(round(50 / w.dt))
         curve = []
         base = None
+        im = (w.box_i_top + w.nx) // 2
+        jc = (w.box_j_lo + w.box_j_hi) // 2
+        phi_mid = []
         t0 = time.perf_counter()
         for k in range(0, w.steps, every):
             pic.pic_step(every)
@@ -382,6 +394,8 @@ def run_trench_study(args):
             curve.append([round((k + every) * w.dt, 3), tal[4], tal[6] + tal[7]])
             if k + every == k_from:
                 base = (tal[4], tal[6] + tal[7])
+            if k + every > k_from:
+                phi_mid.append(float(pic.phi[im, jc]))
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         d = pic.pic_diagnostics()
@@ -392,7 +406,7 @@ def run_trench_study(args):
         cls = h["species_class"] & 0xFF
         ang = np.degrees(np.arctan2(np.abs(h["vy"]), np.abs(h["vx"])))
         pic.close()
-        assert d["hits_logged"] <= 1 << 21, "hit log wrapped"
+        assert d["hits_logged"] <= cap, "hit log wrapped"
         side = (cls == 6) | (cls == 7)
         deep = side & ((h["cell"] >> 16) >= w.extra["electrode_top"] + 5)
         pb, ps = PAPER_TRENCH_COUNTS[w.name]
@@ -409,6 +423,9 @@ def run_trench_study(args):
                "angle_hist_bottom_10deg": np.histogram(ang[cls == 4], bins=9, range=(0, 90))[0].tolist(),
                "angle_hist_sidewall_10deg": np.histogram(90.0 - ang[side], bins=9, range=(0, 90))[0].tolist(),
                "electrons_alive": d["alive"][0], "ions_alive": d["alive"][1],
+               "phi_trench_mid_depth_mean": float(np.mean(phi_mid)),
+               "secondary_emission": ({"yield_ion": see[0], "yield_electron": see[1], "vth": args.see_vth,
+                                       "emitted": d["see_emitted"], "dropped": d["see_dropped"]} if see else None),
                "ms_per_step": 1e3 * secs / w.steps, "cumulative_t_bottom_side": curve}
         rows.append(row)
         log(f"{w.name:26s} bottom {nb:6d} sidewalls {ns:6d} ratio {row['ratio']:.2f} "
@@ -577,6 +594,10 @@ def main():
                     help="the paper's trench runs: bottom and sidewall ion counts")
     ap.add_argument("--study-seed", type=int, default=5)
     ap.add_argument("--batched", action="store_true", help="with --trench-study: the three runs as one batch")
+    ap.add_argument("--see", default="", help="with --trench-study: secondary emission yields per ion and per "
+                    "electron impact on the trench surfaces, e.g. 0.2,0.2")
+    ap.add_argument("--see-vth", type=float, default=0.4472,
+                    help="thermal speed of the emitted electrons (sqrt(T_se / T_e); 0.4472: 2 eV at T_e = 10 eV)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sort", default="8,64")
