@@ -149,8 +149,12 @@ def forward(params, x, quantize=False, periodic_w=False):
     return out, cache
 
 
-def backward(cache, gout):
-    """Gradients (same order as the parameters) and the input gradient."""
+def backward(cache, gout, quantize_grad=False):
+    """Gradients (same order as the parameters) and the input gradient.
+    quantize_grad: round the gradient entering each convolution (after the
+    ReLU mask) to bfloat16, the storage precision of the device network's
+    backward pass; the sums stay float64."""
+    qg = bf16 if quantize_grad else (lambda a: a)
     P = cache["P"]
     pw = cache.get("periodic_w", False)
     grads = [None] * len(P)
@@ -165,7 +169,7 @@ def backward(cache, gout):
     for lev in range(0, len(CH) - 1):    # decoder in reverse: finest level first
         for _ in range(2):
             inp, out = cache["acts"][k]
-            gy = g * (out > 0)
+            gy = qg(g * (out > 0))
             gx, grads[2 * k], grads[2 * k + 1] = conv3x3_grads(inp, P[2 * k], gy, pw)
             g = gx
             k -= 1
@@ -177,7 +181,7 @@ def backward(cache, gout):
             g = pool_grad(g) + skip_grads[lev]
         for _ in range(2):
             inp, out = cache["acts"][k]
-            gy = g * (out > 0)
+            gy = qg(g * (out > 0))
             gx, grads[2 * k], grads[2 * k + 1] = conv3x3_grads(inp, P[2 * k], gy, pw)
             g = gx
             k -= 1

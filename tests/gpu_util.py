@@ -79,3 +79,25 @@ def multiset_hash(p, chunk=1 << 23):
             s1 = s1 + h.sum(dtype=np.uint64)
             s2 = s2 + (h * h).sum(dtype=np.uint64)
     return n, int(s1), int(s2)
+
+
+def unet_params(seed, conv_shapes):
+    """Seeded network parameters in the flat layout's order: He-normal
+    weights and small random biases per convolution (float32), then the 1 x 1
+    head's 16 weights and its bias."""
+    r = np.random.default_rng(seed)
+    ps = []
+    for cin, cout in conv_shapes:
+        ps.append((r.standard_normal((cout, 3, 3, cin)) * np.sqrt(2.0 / (9 * cin))).astype(np.float32))
+        ps.append((r.standard_normal(cout) * 0.05).astype(np.float32))
+    ps.append((r.standard_normal(16) * 0.25).astype(np.float32))
+    ps.append(np.array([0.1], np.float32))
+    return ps
+
+
+# forward cases of the device network tests: (parameter seed, input seed,
+# shape, periodic along W); the crops of the 1024 x 512 case are 192 x 192
+UNET_FORWARD_CASES = [(11, 3, (2, 16, 24, 3), False), (11, 3, (1, 64, 48, 3), False),
+                      (15, 8, (2, 16, 24, 3), True), (15, 8, (1, 32, 64, 3), True)]
+UNET_STEPS = 8.0
+

@@ -4,16 +4,24 @@ Forward: the device network (bfloat16 weights and activations, float32
 accumulation on the matrix cores) against the float64 oracle with the same
 bfloat16 rounding of inputs, weights and stored activations.  The two differ
 only by float32 versus float64 accumulation, which moves an activation by
-one bfloat16 step (2^-8 relative) where it lands next to a rounding
-boundary, and 14 layers of random weights amplify such flips: perturbing
-the oracle's sums by float32-sized relative noise moves its output by up to
-about 3e-3 (relative L2; pinned on the CPU in test_oracle_unet).  The bar is
-1e-2.
+one bfloat16 step (2^-8 relative) where it lies next to a rounding boundary,
+and the layers carry such flips to the output.  The bar is per element:
+every output lies within UNET_STEPS = 8 bfloat16 steps of its own magnitude
+plus the output's RMS, |got - ref| <= 8 * 2^-8 * (|ref| + rms(ref)).  On the
+CPU (test_oracle_unet) the same networks and inputs, with every convolution
+sum given a random error of up to 2^-20 of the sum of its terms'
+magnitudes, move by at most 1.7 - 3.7 such steps; the device's largest
+element deviation is about one step.  The relative L2 error is held to 1e-2
+as well.
 
-Backward: parameter gradients against the oracle's float64 backward pass on
-the oracle's own (quantised) forward activations.  The device rounds the
-gradient entering every convolution to bfloat16 (relative 2^-9 per value),
-so each gradient tensor is held to a relative L2 error of 2e-2.
+Backward: parameter gradients against the oracle's float64 backward pass
+with the device's rounding of the gradient entering each convolution to
+bfloat16, on the oracle's own forward activations; each gradient tensor is
+held to a relative L2 error of 2e-2.  The bar is not per element: a weight
+gradient element sums over every pixel with heavy cancellation, and one
+flipped ReLU mask in the forward pass adds or removes a whole term of it, so
+single elements move by many bfloat16 steps of their size while the tensor
+moves by well under one percent.
 """
 import ctypes as C
 
@@ -23,20 +31,13 @@ import pytest
 import oracle
 import synth
 from oracle import unet as ou
+from gpu_util import UNET_STEPS, unet_params
 
 pytestmark = pytest.mark.gpu
 
 
 def _params(seed):
-    """Seeded parameters in the flat layout (He-normal weights, small random biases)."""
-    r = np.random.default_rng(seed)
-    ps = []
-    for cin, cout in ou.conv_shapes():
-        ps.append((r.standard_normal((cout, 3, 3, cin)) * np.sqrt(2.0 / (9 * cin))).astype(np.float32))
-        ps.append((r.standard_normal(cout) * 0.05).astype(np.float32))
-    ps.append((r.standard_normal(16) * 0.25).astype(np.float32))
-    ps.append(np.array([0.1], np.float32))
-    return ps
+    return unet_params(seed, ou.conv_shapes())
 
 
 def _flat(ps):
@@ -65,6 +66,19 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+BF16_STEP = 2.0 ** -8
+
+
+def _within(got, ref, what):
+    """Per-element bar: |got - ref| <= UNET_STEPS * 2^-8 * (|ref| + rms(ref))."""
+    rms = float(np.sqrt(np.mean(ref * ref)))
+    ratio = np.abs(got - ref) / (UNET_STEPS * BF16_STEP * (np.abs(ref) + rms))
+    print(f"{what}: rel L2 {_rel(got, ref):.2e}, largest ratio to the bar {ratio.max():.3f}, "
+          f"99.9 % {np.quantile(ratio, 0.999):.3f}")
+    assert np.all(np.isfinite(got)), what
+    assert ratio.max() <= 1.0, (what, float(ratio.max()), np.unravel_index(int(np.argmax(ratio)), ratio.shape))
+
+
 @pytest.mark.parametrize("B,H,W", [(2, 16, 24), (1, 64, 48)])
 def test_forward_matches_oracle(B, H, W):
     ps = _params(11)
@@ -76,7 +90,7 @@ def test_forward_matches_oracle(B, H, W):
     got = u.output().cpu().numpy().astype(np.float64)
     ref, _ = ou.forward(ps, x, quantize=True)
     assert got.shape == ref.shape
-    assert np.all(np.isfinite(got))
+    _within(got, ref, f"forward {B}x{H}x{W}")
     assert _rel(got, ref) < 1e-2, _rel(got, ref)
     u.close()
 
@@ -98,6 +112,7 @@ def test_forward_full_size_on_crops():
         hs = slice(0 if h0 == 0 else M, 192 if h0 + 192 == H else 192 - M)
         ws = slice(0 if w0 == 0 else M, 192 if w0 + 192 == W else 192 - M)
         g = got[:, h0:h0 + 192, w0:w0 + 192][:, hs, ws]
+        _within(g, ref[:, hs, ws], f"forward 1024x512 crop at {h0},{w0}")
         assert _rel(g, ref[:, hs, ws]) < 1e-2, (h0, w0, _rel(g, ref[:, hs, ws]))
     u.close()
 
@@ -115,10 +130,12 @@ def test_backward_matches_oracle(B, H, W):
     u.pic_unet_backward()
     grads = _unflat(u.grads.cpu().numpy(), ps)
     _, cache = ou.forward(ps, x, quantize=True)
-    ref, _ = ou.backward(cache, gout.astype(np.float64))
+    ref, _ = ou.backward(cache, gout.astype(np.float64), quantize_grad=True)
+    rels = [_rel(g, rf) for g, rf in zip(grads, ref)]
+    print(f"gradients {B}x{H}x{W}: largest relative L2 {max(rels):.2e}")
     for k, (g, rf) in enumerate(zip(grads, ref)):
         assert np.all(np.isfinite(g)), k
-        assert _rel(g, rf) < 2e-2, (k, _rel(g, rf))
+        assert rels[k] < 2e-2, (k, rels[k])
     u.close()
 
 
@@ -207,15 +224,19 @@ def test_periodic_forward_and_backward_match_oracle(B, H, W):
     u.pic_unet_forward()
     got = u.output().cpu().numpy().astype(np.float64)
     ref, cache = ou.forward(ps, x, quantize=True, periodic_w=True)
+    _within(got, ref, f"periodic forward {B}x{H}x{W}")
     assert _rel(got, ref) < 1e-2, _rel(got, ref)
     ref0, _ = ou.forward(ps, x, quantize=True)
     assert _rel(got, ref0) > 5e-2                     # the padding matters at this size
     u.grad_output().copy_(torch.from_numpy(gout).to(u.dev))
     u.pic_unet_backward()
     grads = _unflat(u.grads.cpu().numpy(), ps)
-    gref, _ = ou.backward(cache, gout.astype(np.float64))
+    gref, _ = ou.backward(cache, gout.astype(np.float64), quantize_grad=True)
+    rels = [_rel(g, rf) for g, rf in zip(grads, gref)]
+    print(f"periodic gradients {B}x{H}x{W}: largest relative L2 {max(rels):.2e}")
     for k, (g, rf) in enumerate(zip(grads, gref)):
-        assert _rel(g, rf) < 2e-2, (k, _rel(g, rf))
+        assert np.all(np.isfinite(g)), k
+        assert rels[k] < 2e-2, (k, rels[k])
     u.close()
 
 

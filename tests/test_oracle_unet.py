@@ -142,6 +142,38 @@ def test_backward_matches_finite_differences():
     assert checked >= 100
 
 
+def test_backward_with_bfloat16_gradients():
+    """quantize_grad rounds the gradient entering every one of the 14
+    convolutions (after the ReLU mask) to bfloat16 and nothing else: the
+    convolution gradients see bfloat16 values only, the unrounded pass does
+    not, and the parameter gradients stay within the rounding's size (2^-9
+    per value, relative L2 below 2^-7) of the float64 ones."""
+    r = _rng(17)
+    ps = [p.astype(np.float64) for p in unet.init_params(seed=5)]
+    x = unet.bf16(r.standard_normal((1, 16, 24, 3)))
+    c = r.standard_normal((1, 16, 24))
+    _, cache = unet.forward(ps, x, quantize=True)
+    seen = []
+    orig = unet.conv3x3_grads
+
+    def spy(xx, w, gy, periodic_w=False):
+        seen.append(np.array_equal(gy, unet.bf16(gy)))
+        return orig(xx, w, gy, periodic_w)
+
+    unet.conv3x3_grads = spy
+    try:
+        gq, _ = unet.backward(cache, c, quantize_grad=True)
+        assert len(seen) == 14 and all(seen)
+        seen.clear()
+        g, _ = unet.backward(cache, c)
+        assert len(seen) == 14 and not all(seen)
+    finally:
+        unet.conv3x3_grads = orig
+    for a, b in zip(gq, g):
+        assert np.linalg.norm(a - b) <= 2.0 ** -7 * np.linalg.norm(b)
+    assert any(not np.array_equal(a, b) for a, b in zip(gq, g))
+
+
 def test_mse_gradient():
     r = _rng(8)
     p, t = r.standard_normal((2, 8, 8)), r.standard_normal((2, 8, 8))
@@ -186,6 +218,43 @@ def test_forward_sensitivity_to_float32_sums():
             unet.conv3x3 = orig
         rel = np.linalg.norm(alt - ref) / np.linalg.norm(ref)
         assert 1e-5 < rel < 5e-3, rel
+
+
+def test_float32_sized_sum_errors_stay_within_the_device_bar():
+    """Calibration of the per-element bar of the device network's forward
+    test, on the very networks and inputs that test uses: with every
+    convolution sum carrying a uniform random error of up to 2^-20 of the sum
+    of its terms' magnitudes (float32 accumulation over up to 54 partial sums,
+    with margin), which flips the bfloat16 rounding of activations that lie
+    next to a rounding boundary, no output element moves by more than
+    UNET_STEPS bfloat16 steps of its magnitude plus the output's RMS,
+    2^-8 (|ref| + rms), over six draws; and the errors do reach the
+    rounding (some element moves)."""
+    from gpu_util import UNET_FORWARD_CASES, UNET_STEPS, unet_params
+    oc = unet.conv3x3
+    noise = np.random.default_rng(2)
+
+    def conv(x, w, b, periodic_w=False):
+        mag = oc(np.abs(x), np.abs(w), np.zeros_like(b), periodic_w)
+        return oc(x, w, b, periodic_w) + 2.0 ** -20 * mag * noise.uniform(-1.0, 1.0, mag.shape)
+
+    full = np.random.default_rng(4).standard_normal((1, 1024, 512, 3))
+    crops = [(12, unet.bf16(full[:, h0:h0 + 192, w0:w0 + 192]), False) for h0, w0 in [(0, 0), (448, 192), (832, 320)]]
+    cases = [(ps, unet.bf16(np.random.default_rng(xs).standard_normal(shape)), per)
+             for ps, xs, shape, per in UNET_FORWARD_CASES] + crops
+    for seed, x, periodic in cases:
+        ps = unet_params(seed, unet.conv_shapes())
+        ref, _ = unet.forward(ps, x, quantize=True, periodic_w=periodic)
+        rms = np.sqrt(np.mean(ref * ref))
+        worst = 0.0
+        for _ in range(6):
+            unet.conv3x3 = conv
+            try:
+                alt, _ = unet.forward(ps, x, quantize=True, periodic_w=periodic)
+            finally:
+                unet.conv3x3 = oc
+            worst = max(worst, float(np.max(np.abs(alt - ref) / (2.0 ** -8 * (np.abs(ref) + rms)))))
+        assert 0.0 < worst < UNET_STEPS, (seed, x.shape, worst)
 
 
 def test_adam_two_steps_closed_form():
