@@ -47,7 +47,10 @@ enum {
     S_CG_BETA,   // direction coefficient of the next CG step
     S_CG_GAMMA,  // r.z of the last V-cycle
     S_WORST,     // largest relative residual of a potential that was pushed with unconverged
-    S_NSCAL = 16
+    S_CG_NALPHA, // alpha, beta and r.z of the step in progress (multigrid form): written by
+    S_CG_NBETA,  //   the level-0 down kernel that computes them, moved to S_CG_* by the
+    S_CG_NGAMMA, //   step's update (the kernel's other blocks still read the old ones)
+    S_NSCAL = 20
 };
 enum {
     F_DONE = 0,  // inner solve finished (kernels of the pass return at once)
@@ -218,7 +221,7 @@ enum {
     OP_PQ,           // S_PQ
     OP_UPDATE,       // S_RR, iteration count, inner stop test
     OP_RZ,           // rz rotation
-    OP_CG_DOTS       // r.z and w.z of a V-cycle: the next step's alpha and beta
+    OP_UNUSED        // (the multigrid form's alpha and beta come from the level-0 down kernel)
 };
 
 // ---- launchers (pic_kernels.hip) --------------------------------------

@@ -88,7 +88,7 @@ __device__ void apply_op(const Inst &I, int op, double t0, double t1)
 {
     double *S = I.S;
     int *F = I.F;
-    if ((op == OP_PQ || op == OP_UPDATE || op == OP_RZ || op == OP_CG_DOTS) && F[F_DONE]) return;
+    if ((op == OP_PQ || op == OP_UPDATE || op == OP_RZ) && F[F_DONE]) return;
     if (op == OP_RR64_PASS && F[F_SKIP]) return;
     if (op == OP_INIT && F[F_CONV]) {
         F[F_SKIP] = 1;
@@ -138,32 +138,25 @@ __device__ void apply_op(const Inst &I, int op, double t0, double t1)
     }
     case OP_PQ: S[S_PQ] = t0; break;
     case OP_UPDATE:
+        if (I.mg && !(S[S_CG_NALPHA] > 0.0 && S[S_CG_NALPHA] < INFINITY && S[S_CG_NBETA] < INFINITY)) {
+            // the step had no usable length (the level-0 down kernel skipped it)
+            F[F_DONE] = 1;
+            break;
+        }
         S[S_RR] = t0;
         F[F_ITER] += 1;
         F[F_ITER_TOT] += 1;
         if (F[F_PASSES] == 1) F[F_ITER1] = F[F_ITER];
         if (t0 <= S[S_ETA2] * S[S_RR0]) F[F_DONE] = 1;
         if (!I.mg) { S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t1; }
+        else {
+            // the step's alpha, beta and r.z, computed by the level-0 down kernel
+            S[S_CG_ALPHA] = S[S_CG_NALPHA];
+            S[S_CG_BETA] = S[S_CG_NBETA];
+            S[S_CG_GAMMA] = S[S_CG_NGAMMA];
+        }
         break;
     case OP_RZ: S[S_RZOLD] = S[S_RZ]; S[S_RZ] = t0; break;
-    case OP_CG_DOTS: {
-        // Chronopoulos-Gear recurrences: gamma = r.z, delta = (A z).z;
-        // beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old)
-        // (= r.z / p.Ap); a step length that is not positive and finite
-        // ends the inner solve (the float64 refinement carries on)
-        double alpha, beta = 0.0;
-        if (F[F_ITER] == 0) {
-            alpha = t0 / t1;
-        } else {
-            beta = t0 / S[S_CG_GAMMA];
-            alpha = t0 / (t1 - beta * t0 / S[S_CG_ALPHA]);
-        }
-        if (!(alpha > 0.0) || !(alpha < INFINITY) || !(beta < INFINITY)) F[F_DONE] = 1;
-        S[S_CG_ALPHA] = alpha;
-        S[S_CG_BETA] = beta;
-        S[S_CG_GAMMA] = t0;
-        break;
-    }
     }
 }
 
@@ -199,11 +192,30 @@ __device__ __forceinline__ void partial_sums_256(const Part &pt, int b0, int b1,
     }
 }
 
+// Chronopoulos-Gear recurrences of the multigrid-preconditioned CG from
+// gamma = r.z and delta = (A z).z of the last V-cycle: beta = gamma /
+// gamma_old, alpha = gamma / (delta - beta gamma / alpha_old) (= r.z / p.Ap);
+// on the first step alpha = gamma / delta, beta = 0.  False when the step
+// length is not positive and finite (the inner solve ends there; the float64
+// refinement carries on).
+__device__ __forceinline__ bool cg_coefficients(const double *S, int iter, double gamma, double delta,
+                                                double &alpha, double &beta)
+{
+    beta = 0.0;
+    if (iter == 0) {
+        alpha = gamma / delta;
+    } else {
+        beta = gamma / S[S_CG_GAMMA];
+        alpha = gamma / (delta - beta * gamma / S[S_CG_ALPHA]);
+    }
+    return alpha > 0.0 && alpha < INFINITY && beta < INFINITY;
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part pt, int op)
 {
     const Inst &I = insts[t.id[blockIdx.x]];
     const int *F = I.F;
-    const bool inner = op == OP_PQ || op == OP_UPDATE || op == OP_RZ || op == OP_CG_DOTS;
+    const bool inner = op == OP_PQ || op == OP_UPDATE || op == OP_RZ;
     if (inner && F[F_DONE]) return;
     if (op == OP_RR64_PASS && F[F_SKIP]) return;
     if (op == OP_INIT && F[F_CONV]) {
@@ -212,7 +224,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Inst *insts, Tab t, Part
     }
     __shared__ double sh[2][4];
     const int tid = threadIdx.x;
-    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE || op == OP_RR64_START || op == OP_CG_DOTS) ? 2 : 1;
+    const int nq = (op == OP_ASM || op == OP_INIT || op == OP_UPDATE || op == OP_RR64_START) ? 2 : 1;
     partial_sums_256(pt, t.boff[blockIdx.x], t.boff[blockIdx.x + 1], nq, sh, tid);
     __syncthreads();
     if (tid != 0) return;
@@ -919,12 +931,14 @@ __device__ __forceinline__ void win_sweep(float *su, const float *sg, const uint
 // MODE 0: level l >= 1 (start staged from u).
 // MODE 1: level 0 at the start of an inner pass: r = R[0], e = 0, ||r||^2
 //         (inner stop ratio and counters in the last block).
-// MODE 2: level 0 after a CG step: s' = w + beta s, r' = r - alpha s',
+// MODE 2: level 0 after a CG step: alpha and beta from the last V-cycle's
+//         dot products (partials pq), s' = w + beta s, r' = r - alpha s',
 //         p = z + beta p, e += alpha p (beta = 0 on the first step), r' and
-//         s' to the other buffers of the pair, ||r'||^2 and the inner stop
-//         test in the last block.  par: buffer of the pair holding r and s.
+//         s' to the other buffers of the pair, ||r'||^2 partials (pt) for
+//         the inner stop test.  par: buffer of the pair holding r and s.
 template <int NU, int MODE>
-__global__ __launch_bounds__(kMgThreads) void k_mg_down(const Inst *insts, Tab t, int level, int par, Part pt)
+__global__ __launch_bounds__(kMgThreads) void k_mg_down(const Inst *insts, Tab t, int level, int par, Part pt,
+                                                        Part pq)
 {
     constexpr int HD = 2 * NU + 1, W = kMgTile + 2 * HD - 1;
     const int ku = unit_of(t, (int)blockIdx.x);
@@ -944,13 +958,34 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_down(const Inst *insts, Tab t
     } else {
         if (F[F_DONE]) return;
     }
+    float alpha = 0.0f, beta = 0.0f;
+    if (MODE == 2) {
+        // this step's alpha and beta from the last V-cycle's r.z and (A z).z
+        // partials (pq): every block adds them in the same order, so all
+        // blocks agree.  Block 0 records them for the step's update, which
+        // also ends the inner solve when they are not usable (no block of
+        // this launch writes a flag the others read).
+        __shared__ double shq[2][4];
+        partial_sums_256(pq, t.boff[ku], t.boff[ku + 1], 2, shq, (int)threadIdx.x);
+        __syncthreads();
+        const double gamma = shq[0][0] + shq[0][1] + shq[0][2] + shq[0][3];
+        const double delta = shq[1][0] + shq[1][1] + shq[1][2] + shq[1][3];
+        double a, b;
+        const bool ok = cg_coefficients(S, F[F_ITER], gamma, delta, a, b);
+        if (lb == 0 && threadIdx.x == 0) {
+            S[S_CG_NALPHA] = a;
+            S[S_CG_NBETA] = b;
+            S[S_CG_NGAMMA] = gamma;
+        }
+        if (!ok) return;
+        alpha = (float)a;
+        beta = (float)b;
+    }
     if (work) {
         if (MODE == 0) {
             mg_stage<W>(F0, F0.u, F0.g, I.g.px, I.g.py, i0 - HD, j0 - HD, su, sg, sf);
         } else {
             const int first = MODE == 2 ? F[F_ITER] == 0 : 1;
-            const float alpha = MODE == 2 ? (float)S[S_CG_ALPHA] : 0.0f;
-            const float beta = MODE == 2 && !first ? (float)S[S_CG_BETA] : 0.0f;
             const float *r = par ? I.cg_r1 : F0.g;
             mg_stage_l0<W>(I, MODE == 2, first, alpha, beta, r, I.cg_s[par], I.cg_w, i0 - HD, j0 - HD, su, sg, sf);
             __syncthreads();
@@ -1141,18 +1176,25 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_up(const Inst *insts, Tab t, 
 
 constexpr int kMgSmooth = 1;     // pre- and post-smoothing steps on the fine levels
 
+// The level-0 up kernel's r.z and (A z).z partials: a range of their own
+// after the two the other reductions use, so that they survive until the
+// next level-0 down kernel reads them (plain-CG instances of a batch reduce
+// in between).
+static Part cg_dot_part(Part pt) { return Part{pt.p + 2 * (size_t)pt.stride, pt.stride}; }
+
 void launch_mg_down(const Inst *I, const Tab &t, int level, int mode, int par, Part pt, hipStream_t s)
 {
     if (!t.n) return;
     const dim3 g(tab_blocks(t)), b(kMgThreads);
+    const Part pq = cg_dot_part(pt);
     if (mode == 0) {
-        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 0>), g, b, 0, s, I, t, level, par, pt);
+        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 0>), g, b, 0, s, I, t, level, par, pt, pq);
     } else if (mode == 1) {
-        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 1>), g, b, 0, s, I, t, level, par, pt);
+        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 1>), g, b, 0, s, I, t, level, par, pt, pq);
         finalize(I, t, pt, OP_INIT, s);
     } else {
         // mode 3: the coarse kernel reduces the partials (fused update)
-        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 2>), g, b, 0, s, I, t, level, par, pt);
+        hipLaunchKernelGGL((k_mg_down<kMgSmooth, 2>), g, b, 0, s, I, t, level, par, pt, pq);
         if (mode == 2) finalize(I, t, pt, OP_UPDATE, s);
     }
 }
@@ -1162,8 +1204,8 @@ void launch_mg_up(const Inst *I, const Tab &t, int level, int par, Part pt, hipS
     if (!t.n) return;
     const dim3 g(tab_blocks(t)), b(kMgThreads);
     if (level == 0) {
-        hipLaunchKernelGGL((k_mg_up<kMgSmooth, 1>), g, b, 0, s, I, t, level, par, pt);
-        finalize(I, t, pt, OP_CG_DOTS, s);
+        // the next level-0 down kernel turns the partials into alpha and beta
+        hipLaunchKernelGGL((k_mg_up<kMgSmooth, 1>), g, b, 0, s, I, t, level, par, cg_dot_part(pt));
     } else {
         hipLaunchKernelGGL((k_mg_up<kMgSmooth, 0>), g, b, 0, s, I, t, level, par, pt);
     }

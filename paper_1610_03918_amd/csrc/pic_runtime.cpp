@@ -529,7 +529,9 @@ size_t carve_all(pic_ctx *c, int n, const pic_config *cfgs, const int64_t *caps,
     PushArgs *dp = w.take<PushArgs>(2 * n);
     BinArgs *db = w.take<BinArgs>(2 * n);
     SeeArgs *dse = w.take<SeeArgs>(n);
-    double *part = w.take<double>((size_t)2 * stride);
+    // partials of block reductions: two quantities, then the level-0 up
+    // kernel's two (kept for the next level-0 down kernel)
+    double *part = w.take<double>((size_t)4 * stride);
     double *S = w.take<double>((size_t)n * S_NSCAL);
     int *F = w.take<int>((size_t)n * F_NFLAG);
     double *V = w.take<double>((size_t)kVWindow * n * 8);
