@@ -1802,6 +1802,17 @@ __global__ __launch_bounds__(1024) void k_coarse(const Inst *insts, Tab t, Tab t
         // in the same order, the iteration count and the inner stop test
         __shared__ double fsh[2][4];
         __shared__ int fdone;
+        if (tid == 256) {
+            // a wavefront outside the sums reads the scalars and flags the
+            // update uses (just written by other kernels, on other XCDs), so
+            // that thread 0 finds them in the caches after the barrier (the
+            // empty asm keeps the loads)
+            const double *ws = I.S;
+            const int *wf = I.F;
+            const double warm = ws[S_ETA2] + ws[S_RR0] + ws[S_CG_NALPHA] + ws[S_CG_NBETA] + ws[S_CG_NGAMMA] +
+                                (double)(wf[F_ITER] + wf[F_ITER_TOT] + wf[F_PASSES]);
+            asm volatile("" ::"v"(warm));
+        }
         partial_sums_256(pt, t0.boff[blockIdx.x], t0.boff[blockIdx.x + 1], 2, fsh, tid);
         __syncthreads();
         if (tid == 0) {
