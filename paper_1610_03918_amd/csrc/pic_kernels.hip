@@ -2797,14 +2797,20 @@ __device__ __forceinline__ bool live_code(int c, int nx, int ny)
     return c >= 0 && (int)((unsigned)c >> 16) < nx && (c & 0xFFFF) < ny;
 }
 
-// Count and scatter work in blocks of kBinPer consecutive slots: a block
-// first counts its live particles per tile in LDS (one LDS atomic per
-// distinct tile per wavefront), then adds each non-zero count to the global
-// counters (count pass) or reserves that many consecutive destination slots
-// with one global atomic per tile (scatter pass) and hands them out in LDS.
-// Tiles beyond kBinLds fall back to global wavefront-aggregated atomics.
+// Count and scatter work in blocks of kBinPer consecutive slots.  Between
+// re-binnings particles drift less than a tile, so a block's particles lie
+// in a 5 x 5 box of tiles centred on its home tile (the tile of the first
+// live particle among thread 0's slots, which may itself have moved a tile;
+// tile indices taken modulo the tile grid, so the box is an index map
+// whatever the boundaries).  A block counts its
+// particles per box tile in LDS (one LDS atomic per distinct tile per
+// wavefront), then adds each non-zero count to the global counters (count
+// pass) or reserves that many consecutive destination slots with one global
+// atomic per tile (scatter pass) and hands them out in LDS.  Particles
+// outside the box use global wavefront-aggregated atomics.
 constexpr int kBinPer = 2048;
-constexpr int kBinLds = 2048;
+constexpr int kBox = 5;
+constexpr int kBoxN = kBox * kBox;
 
 // Source (info[7]) and destination sets of a re-binning.
 struct BView {
@@ -2835,53 +2841,81 @@ __device__ __forceinline__ BView bview(const BinArgs &a)
     return v;
 }
 
-// Loads the block's cell codes (all loads issued before use) and counts the
-// live ones per tile: tiles below kBinLds in LDS, the rest in global counts
-// (count pass only).
-constexpr int kBinRP = kBinPer / 256;
-__device__ __forceinline__ void bin_local_count(const BinArgs &a, const BView &v, long long lo, long long hi,
-                                                unsigned *hist, bool count_bad, int (&cv)[kBinRP])
+// A block's box: tile rows ti .. ti+kBox-1 and columns tj .. tj+kBox-1 (modulo tx, ty).
+struct TileBox {
+    int ti, tj, tx, ty;
+    bool on;
+};
+
+// Local index of the tile of live code c in the box, or -1.
+__device__ __forceinline__ int box_index(const TileBox &b, int c, int lx, int ly)
 {
-    const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
+    if (!b.on) return -1;
+    int di = (int)(((unsigned)c >> 16) >> lx) - b.ti, dj = (int)((unsigned)(c & 0xFFFF) >> ly) - b.tj;
+    if (di < 0) di += b.tx;
+    else if (di >= b.tx) di -= b.tx;
+    if (dj < 0) dj += b.ty;
+    else if (dj >= b.ty) dj -= b.ty;
+    return (di < kBox && dj < kBox) ? di * kBox + dj : -1;
+}
+
+// Global tile of local index k of the box.
+__device__ __forceinline__ int box_tile(const TileBox &b, int k)
+{
+    int ti = b.ti + k / kBox, tj = b.tj + k % kBox;
+    if (ti < 0) ti += b.tx;
+    else if (ti >= b.tx) ti -= b.tx;
+    if (tj < 0) tj += b.ty;
+    else if (tj >= b.ty) tj -= b.ty;
+    return ti * b.ty + tj;
+}
+
+// Loads the block's cell codes (all loads issued before use), sets up its
+// box (shared home), counts the live ones per box tile in hist (zeroed
+// here) and, in the count pass, the others in the global counts and the bad
+// codes.
+constexpr int kBinRP = kBinPer / 256;
+__device__ __forceinline__ TileBox bin_local_count(const BinArgs &a, const BView &v, long long lo, long long hi,
+                                                   unsigned *hist, int *home, bool count_pass, int (&cv)[kBinRP])
+{
 #pragma unroll
     for (int r8 = 0; r8 < kBinRP; r8++) {
         const long long p = lo + r8 * 256 + threadIdx.x;
         cv[r8] = p < hi ? v.cell[p] : -1;
     }
-    for (int k = threadIdx.x; k < nl; k += 256) hist[k] = 0u;
+    if (threadIdx.x < kBoxN) hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        int h = -1;
+#pragma unroll
+        for (int r8 = 0; r8 < kBinRP; r8++)
+            if (h < 0 && live_code(cv[r8], a.nx, a.ny)) h = cv[r8];
+        *home = h;
+    }
     __syncthreads();
+    TileBox b;
+    const int h = *home;
+    b.on = h >= 0;
+    b.ty = a.tiles_y;
+    b.tx = a.ntiles / a.tiles_y;
+    b.ti = b.on ? (int)(((unsigned)h >> 16) >> a.lx) - kBox / 2 : 0;
+    b.tj = b.on ? (int)((unsigned)(h & 0xFFFF) >> a.ly) - kBox / 2 : 0;
 #pragma unroll
     for (int r8 = 0; r8 < kBinRP; r8++) {
         const int c = cv[r8];
         const bool act = live_code(c, a.nx, a.ny);
-        if (count_bad && c >= 0 && !act) atomicAdd(a.bad, 1ull);
-        const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
-        wave_add(hist, key, act && key < kBinLds);
-        if (count_bad) wave_add(a.counts, key, act && key >= kBinLds);
+        if (count_pass && c >= 0 && !act) atomicAdd(a.bad, 1ull);
+        const int k = act ? box_index(b, c, a.lx, a.ly) : -1;
+        wave_add(hist, k < 0 ? 0 : k, act && k >= 0);
+        if (count_pass) wave_add(a.counts, act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0, act && k < 0);
     }
     __syncthreads();
-}
-
-// Exclusive prefix sum of one value per thread over a 256-thread block.
-__device__ __forceinline__ unsigned block_exclusive_scan(unsigned x, unsigned *wsum)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    unsigned inc = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned y = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += y;
-    }
-    if (lane == 63) wsum[wid] = inc;
-    __syncthreads();
-    unsigned before = 0;
-    for (int w = 0; w < wid; w++) before += wsum[w];
-    return before + inc - x;
+    return b;
 }
 
 __global__ __launch_bounds__(256) void k_bin_count(const BinArgs *B, Tab t)
 {
-    __shared__ unsigned hist[kBinLds];
+    __shared__ unsigned hist[kBoxN];
+    __shared__ int home;
     const int ku = unit_of(t, (int)blockIdx.x);
     const BinArgs &a = B[t.id[ku]];
     const BView v = bview(a);
@@ -2890,10 +2924,8 @@ __global__ __launch_bounds__(256) void k_bin_count(const BinArgs *B, Tab t)
     if (lo >= n) return;
     const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
     int cv[kBinRP];
-    bin_local_count(a, v, lo, hi, hist, true, cv);
-    const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
-    for (int k = threadIdx.x; k < nl; k += 256)
-        if (hist[k]) atomicAdd(&a.counts[k], hist[k]);
+    const TileBox b = bin_local_count(a, v, lo, hi, hist, &home, true, cv);
+    if (threadIdx.x < kBoxN && hist[threadIdx.x]) atomicAdd(&a.counts[box_tile(b, threadIdx.x)], hist[threadIdx.x]);
 }
 // Single work-group: exclusive scans of the tile counts and of the blocks
 // per tile; writes the cursor for the scatter and the totals.
@@ -2978,28 +3010,38 @@ __device__ __forceinline__ unsigned gcd_u(unsigned x, unsigned y)
 // consecutive destination slots.
 // One array of the block through LDS: values (in registers, slot order) to
 // their staging positions, then the staged runs to their destination slots.
-__device__ __forceinline__ void bin_move(const float (&vals)[kBinRP], float *dst_arr, const int (&qv)[kBinRP],
-                                         const unsigned *dst, float *buf, unsigned total)
+// Staged moves of two arrays at a time (the cell codes travel as float
+// bits): each thread puts its particles' values at their staging positions,
+// then consecutive threads write consecutive destinations (the tile ranges
+// are contiguous).  c0: the first array holds cell codes.  d1 null: one array.
+__device__ __forceinline__ void bin_move2(const float (&v0)[kBinRP], float *d0, int32_t *c0, const float (&v1)[kBinRP],
+                                          float *d1, const int (&qv)[kBinRP], const unsigned *dst, float *buf0,
+                                          float *buf1, unsigned total)
 {
 #pragma unroll
     for (int r8 = 0; r8 < kBinRP; r8++)
-        if (qv[r8] >= 0) buf[qv[r8]] = vals[r8];
+        if (qv[r8] >= 0) {
+            buf0[qv[r8]] = v0[r8];
+            if (d1) buf1[qv[r8]] = v1[r8];
+        }
     __syncthreads();
-    for (unsigned q = threadIdx.x; q < total; q += 256) dst_arr[dst[q]] = buf[q];
+    for (unsigned q = threadIdx.x; q < total; q += 256) {
+        const unsigned d = dst[q];
+        if (c0) c0[d] = __float_as_int(buf0[q]);
+        else d0[d] = buf0[q];
+        if (d1) d1[d] = buf1[q];
+    }
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_bin_scatter(const BinArgs *B, Tab tb)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_bin_scatter(const BinArgs *B, Tab tb)
 {
     constexpr int RP = kBinPer / 256;
-    // tile tables until the staging positions are known, then the staging
-    // buffer in the same LDS
-    __shared__ unsigned tabs[4 * kBinLds];
-    __shared__ unsigned dst[kBinPer];
-    __shared__ unsigned wsum[4];
-    static_assert(kBinPer <= 4 * kBinLds, "staging buffer inside the tile tables");
-    unsigned *hist = tabs, *base = tabs + kBinLds, *loff = tabs + 2 * kBinLds, *mstr = tabs + 3 * kBinLds;
-    float *buf = reinterpret_cast<float *>(tabs);
+    __shared__ float buf0[kBinPer], buf1[kBinPer];       // staging of two arrays
+    __shared__ unsigned dst[kBinPer];                    // destination slot per staging position
+    __shared__ unsigned hist[kBoxN], base[kBoxN], loff[kBoxN], mstr[kBoxN];
+    __shared__ unsigned total;
+    __shared__ int home;
     const int ku = unit_of(tb, (int)blockIdx.x);
     const BinArgs &a = B[tb.id[ku]];
     const BView v = bview(a);
@@ -3018,43 +3060,47 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const BinArgs *B, Tab tb)
             fv[f][r8] = p < hi ? fsrc[f][p] : 0.0f;
         }
     int cv[RP];
-    bin_local_count(a, v, lo, hi, hist, false, cv);
-    const int nl = a.ntiles < kBinLds ? a.ntiles : kBinLds;
-    const int per = (nl + 255) / 256;
-    const int t0 = threadIdx.x * per, t1 = min(nl, t0 + per);
-    unsigned sum = 0;
-    for (int k = t0; k < t1; k++) {
+    const TileBox bx = bin_local_count(a, v, lo, hi, hist, &home, false, cv);
+    // per box tile: a destination range, the staging offset, and a stride
+    // coprime to the count that spreads runs of particles from one cell over
+    // the tile's range (runs would serialise a wavefront's LDS atomics in the
+    // push)
+    if (threadIdx.x < kBoxN) {
+        const int k = threadIdx.x;
         const unsigned m = hist[k];
         if (m) {
-            base[k] = atomicAdd(&a.cursor[k], m);
+            base[k] = atomicAdd(&a.cursor[box_tile(bx, k)], m);
             unsigned st = (unsigned)(0.618034f * (float)m) | 1u;
             while (gcd_u(st, m) != 1u) st++;
             mstr[k] = (m << 16) | (st % m);
         }
-        sum += m;
     }
-    unsigned off = block_exclusive_scan(sum, wsum);
-    for (int k = t0; k < t1; k++) {
-        loff[k] = off;
-        off += hist[k];
-        hist[k] = 0u;
+    if (threadIdx.x == 0) {
+        unsigned off = 0;
+        for (int k = 0; k < kBoxN; k++) {
+            loff[k] = off;
+            off += hist[k];
+        }
+        total = off;
     }
+    __syncthreads();
+    if (threadIdx.x < kBoxN) hist[threadIdx.x] = 0u;     // the rank counters of the pass below
     __syncthreads();
     int qv[RP];                                           // staging position of each own slot, or -1
 #pragma unroll
     for (int r8 = 0; r8 < RP; r8++) {
         const int c = cv[r8];
         const bool act = live_code(c, a.nx, a.ny);
-        const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
-        const bool loc = act && key < kBinLds;
-        const unsigned r = wave_add(hist, key, loc);
-        const unsigned d1 = wave_add(a.cursor, key, act && key >= kBinLds);
+        const int k = act ? box_index(bx, c, a.lx, a.ly) : -1;
+        const bool loc = act && k >= 0;
+        const unsigned r = wave_add(hist, loc ? k : 0, loc);
+        const unsigned d1 = wave_add(a.cursor, act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0, act && !loc);
         int qp = -1;
         if (loc) {
-            const unsigned ms = mstr[key];
-            const unsigned q = loff[key] + (r * (ms & 0xFFFFu)) % (ms >> 16);
+            const unsigned ms = mstr[k];
+            const unsigned q = loff[k] + (r * (ms & 0xFFFFu)) % (ms >> 16);
             qp = (int)q;
-            dst[q] = base[key] + (q - loff[key]);
+            dst[q] = base[k] + (q - loff[k]);
         } else if (act) {
             v.cell2[d1] = c;
             v.ox2[d1] = fv[0][r8];
@@ -3065,20 +3111,13 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const BinArgs *B, Tab tb)
         qv[r8] = qp;
     }
     __syncthreads();
-    // staged total: offset of the last bin plus its count (its rank counter);
-    // read by every thread before the tables become the staging buffer
-    const unsigned total = (nl > 0) ? loff[nl - 1] + hist[nl - 1] : 0u;
-    __syncthreads();
+    const unsigned nq = total;
+    float cf[RP];
 #pragma unroll
-    for (int r8 = 0; r8 < RP; r8++)
-        if (qv[r8] >= 0) buf[qv[r8]] = __int_as_float(cv[r8]);
-    __syncthreads();
-    for (unsigned q = threadIdx.x; q < total; q += 256) v.cell2[dst[q]] = __float_as_int(buf[q]);
-    __syncthreads();
-    bin_move(fv[0], v.ox2, qv, dst, buf, total);
-    bin_move(fv[1], v.oy2, qv, dst, buf, total);
-    bin_move(fv[2], v.vx2, qv, dst, buf, total);
-    bin_move(fv[3], v.vy2, qv, dst, buf, total);
+    for (int r8 = 0; r8 < RP; r8++) cf[r8] = __int_as_float(cv[r8]);
+    bin_move2(cf, nullptr, v.cell2, fv[0], v.ox2, qv, dst, buf0, buf1, nq);
+    bin_move2(fv[1], v.oy2, nullptr, fv[2], v.vx2, qv, dst, buf0, buf1, nq);
+    bin_move2(fv[3], v.vy2, nullptr, fv[3], nullptr, qv, dst, buf0, buf1, nq);
 }
 
 // The destination set becomes the set in use.
