@@ -2802,12 +2802,11 @@ __device__ __forceinline__ bool live_code(int c, int nx, int ny)
 // in a 5 x 5 box of tiles centred on its home tile (the tile of the first
 // live particle among thread 0's slots, which may itself have moved a tile;
 // tile indices taken modulo the tile grid, so the box is an index map
-// whatever the boundaries).  A block counts its
-// particles per box tile in LDS (one LDS atomic per distinct tile per
-// wavefront), then adds each non-zero count to the global counters (count
-// pass) or reserves that many consecutive destination slots with one global
-// atomic per tile (scatter pass) and hands them out in LDS.  Particles
-// outside the box use global wavefront-aggregated atomics.
+// whatever the boundaries).  The scatter counts its particles per box tile
+// in LDS (one LDS atomic per distinct tile per wavefront), reserves that
+// many consecutive destination slots with one global atomic per tile and
+// hands them out in LDS; particles outside the box use global
+// wavefront-aggregated atomics.
 constexpr int kBinPer = 2048;
 constexpr int kBox = 5;
 constexpr int kBoxN = kBox * kBox;
@@ -2870,13 +2869,12 @@ __device__ __forceinline__ int box_tile(const TileBox &b, int k)
     return ti * b.ty + tj;
 }
 
-// Loads the block's cell codes (all loads issued before use), sets up its
-// box (shared home), counts the live ones per box tile in hist (zeroed
-// here) and, in the count pass, the others in the global counts and the bad
-// codes.
+// Scatter pass: loads the block's cell codes (all loads issued before
+// use), sets up its box (shared home) and counts the live ones per box tile
+// in hist (zeroed here).
 constexpr int kBinRP = kBinPer / 256;
 __device__ __forceinline__ TileBox bin_local_count(const BinArgs &a, const BView &v, long long lo, long long hi,
-                                                   unsigned *hist, int *home, bool count_pass, int (&cv)[kBinRP])
+                                                   unsigned *hist, int *home, int (&cv)[kBinRP])
 {
 #pragma unroll
     for (int r8 = 0; r8 < kBinRP; r8++) {
@@ -2903,19 +2901,24 @@ __device__ __forceinline__ TileBox bin_local_count(const BinArgs &a, const BView
     for (int r8 = 0; r8 < kBinRP; r8++) {
         const int c = cv[r8];
         const bool act = live_code(c, a.nx, a.ny);
-        if (count_pass && c >= 0 && !act) atomicAdd(a.bad, 1ull);
         const int k = act ? box_index(b, c, a.lx, a.ly) : -1;
         wave_add(hist, k < 0 ? 0 : k, act && k >= 0);
-        if (count_pass) wave_add(a.counts, act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0, act && k < 0);
     }
     __syncthreads();
     return b;
 }
 
+// Count pass: the block's live particles per tile in an LDS histogram over
+// the whole tile grid (tiles beyond kCountLds in global counts), added to
+// the global counts once per non-zero tile; codes outside the grid in bad.
+// (No box here: the count has no home tile to wait for, and the scatter
+// places every particle counted for a tile in that tile's range whichever
+// path counted it.)
+constexpr int kCountLds = 2048;
+
 __global__ __launch_bounds__(256) void k_bin_count(const BinArgs *B, Tab t)
 {
-    __shared__ unsigned hist[kBoxN];
-    __shared__ int home;
+    __shared__ unsigned hist[kCountLds];
     const int ku = unit_of(t, (int)blockIdx.x);
     const BinArgs &a = B[t.id[ku]];
     const BView v = bview(a);
@@ -2923,10 +2926,29 @@ __global__ __launch_bounds__(256) void k_bin_count(const BinArgs *B, Tab t)
     const long long lo = (long long)((int)blockIdx.x - t.boff[ku]) * kBinPer;
     if (lo >= n) return;
     const long long hi = lo + kBinPer < n ? lo + kBinPer : n;
+    const int nl = a.ntiles < kCountLds ? a.ntiles : kCountLds;
     int cv[kBinRP];
-    const TileBox b = bin_local_count(a, v, lo, hi, hist, &home, true, cv);
-    if (threadIdx.x < kBoxN && hist[threadIdx.x]) atomicAdd(&a.counts[box_tile(b, threadIdx.x)], hist[threadIdx.x]);
+#pragma unroll
+    for (int r8 = 0; r8 < kBinRP; r8++) {
+        const long long p = lo + r8 * 256 + threadIdx.x;
+        cv[r8] = p < hi ? v.cell[p] : -1;
+    }
+    for (int k = threadIdx.x; k < nl; k += 256) hist[k] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int r8 = 0; r8 < kBinRP; r8++) {
+        const int c = cv[r8];
+        const bool act = live_code(c, a.nx, a.ny);
+        if (c >= 0 && !act) atomicAdd(a.bad, 1ull);
+        const int key = act ? tile_of(c, a.lx, a.ly, a.tiles_y) : 0;
+        wave_add(hist, key, act && key < kCountLds);
+        wave_add(a.counts, key, act && key >= kCountLds);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nl; k += 256)
+        if (hist[k]) atomicAdd(&a.counts[k], hist[k]);
 }
+
 // Single work-group: exclusive scans of the tile counts and of the blocks
 // per tile; writes the cursor for the scatter and the totals.
 __global__ __launch_bounds__(1024) void k_bin_scan(const BinArgs *B, Tab t)
@@ -3060,7 +3082,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
             fv[f][r8] = p < hi ? fsrc[f][p] : 0.0f;
         }
     int cv[RP];
-    const TileBox bx = bin_local_count(a, v, lo, hi, hist, &home, false, cv);
+    const TileBox bx = bin_local_count(a, v, lo, hi, hist, &home, cv);
     // per box tile: a destination range, the staging offset, and a stride
     // coprime to the count that spreads runs of particles from one cell over
     // the tile's range (runs would serialise a wavefront's LDS atomics in the
