@@ -131,17 +131,20 @@ def flops_per_inference(H, W):
 
 
 def learned_start(w, pic, parts, args):
-    """The learned warm start (coarse residual learning): the network corrects
-    the solver's linearly extrapolated start on f x f blocks of nodes
-    (block means of the residual in, a block-mean correction out, prolonged
-    bilinearly onto the nodes; f = 1 is the full-resolution form).  Training
-    samples come from this trench run (after the timed steps) and from the
-    16-width sweep (its 1024 x 512, 512 x 256 and 256 x 128 instances, one
-    network per window size over shared parameters); training uses the
-    library's forward / backward / Adam kernels.  Then plain masked CG to the
-    workload's tolerance on held-out problems of the trench run from four
-    starts: cold, previous potential, linear extrapolation, extrapolation +
-    network (sample, inference and prolongation included)."""
+    """The learned warm start (residual learning): the network corrects the
+    K-point polynomial extrapolation in time of the last K potentials (K =
+    args.learn_stencil; K = 4: 4 phi_1 - 6 phi_2 + 4 phi_3 - phi_4), at full
+    resolution (f = 1) or on f x f blocks of nodes (block means of the
+    residual in, a block-mean correction out, prolonged bilinearly onto the
+    nodes).  Training samples come from this trench run (after the timed
+    steps) and from the 16-width sweep (its 1024 x 512, 512 x 256 and
+    256 x 128 instances, one network per window size over shared
+    parameters); training uses the library's forward / backward / Adam
+    kernels.  Then plain masked CG to the workload's tolerance on held-out
+    problems of the trench run from the starts: cold, previous potential,
+    linear extrapolation, the K-point extrapolation alone (base) and with the
+    network's correction (extrapolation, sample, inference and guess
+    included in the time)."""
     import numpy as np
     import torch
 
@@ -150,17 +153,19 @@ def learned_start(w, pic, parts, args):
     from paper_1610_03918_amd.unet import UNet
     dev = torch.device("cuda:0")
     f = args.learn_factor
+    K = args.learn_stencil
     H, W = learned.window(w, f)
     per = (int(w.periodic_x), int(w.periodic_y))
     t0 = time.perf_counter()
     # scales: powers of two near the inverse RMS of the residual and of the gap
     probe = []
-    learned.run_and_sample(pic, 12, {}, (1.0, 1.0, 1.0), keep=probe, f=f)
+    learned.run_and_sample(pic, 12 + K, {}, (1.0, 1.0, 1.0), keep=probe, f=f, K=K)
     stats = torch.zeros(3, dtype=torch.float64, device=dev)
     x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
     tt = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
-    for b, p1, p2, pn in probe:
-        learned.sample(f, b, p1, p2, pn, pic.pic_node_map(), per, H, W, (1.0, 1.0, 1.0), x, tt, stats)
+    for b, hist, pn in probe:
+        s0 = learned.start_of(hist, K, torch.empty_like(pn))
+        learned.sample(f, b, s0, s0, pn, pic.pic_node_map(), per, H, W, (1.0, 1.0, 1.0), x, tt, stats)
     st = stats.cpu().numpy()
     amp = float(np.max(np.abs(np.asarray(w.v_amp, np.float64)))) or 1.0
     sc = (learned.pow2_scale(np.sqrt(st[0] / st[2])), float(np.float32(1.0 / amp)),
@@ -168,10 +173,10 @@ def learned_start(w, pic, parts, args):
     del probe
     stores = {(H, W): learned.SampleStore(torch, dev, H, W, args.learn_trench_samples)}
     learned.run_and_sample(pic, args.learn_every * (args.learn_trench_samples + 2), stores, sc,
-                           every=args.learn_every, f=f)
-    learned.run_and_sample(pic, 50, {}, sc, f=f)                # a gap before the held-out problems
+                           every=args.learn_every, f=f, K=K)
+    learned.run_and_sample(pic, 50, {}, sc, f=f, K=K)           # a gap before the held-out problems
     problems = []
-    learned.run_and_sample(pic, 5 * args.learn_evals, {}, sc, keep=problems, every=5, f=f)
+    learned.run_and_sample(pic, 5 * args.learn_evals, {}, sc, keep=problems, every=5, f=f, K=K)
     n_trench = stores[(H, W)].n
     t1 = time.perf_counter()
     # the 16-width sweep (batched form), eager steps after a short spin-up
@@ -196,7 +201,7 @@ def learned_start(w, pic, parts, args):
             else:
                 stores[k] = learned.SampleStore(torch, dev, k[0], k[1], c)
         before = sum(s_.n for s_ in stores.values())
-        learned.run_and_sample_batch(sw, args.learn_sweep_steps + 2, stores, sc, f=f)
+        learned.run_and_sample_batch(sw, args.learn_sweep_steps + K, stores, sc, f=f, K=K)
         n_sweep = sum(s_.n for s_ in stores.values()) - before
         sw.close()
         del sw
@@ -223,34 +228,39 @@ def learned_start(w, pic, parts, args):
     u1.pic_unet_set_timing(False)
     few = [{k: p[k][:4096] for k in p} for p in parts]
     cg = Pic(w, few, solver=1, max_iter=50000)
-    rows = learned.evaluate(cg, u1, problems, sc, torch, f=f)
+    rows = learned.evaluate(cg, u1, problems, sc, torch, f=f, K=K)
     u1.close()
-    bound = learned.coarse_bound(cg, problems[:args.learn_bound_problems], (4, 8, 16), torch)
+    bound = learned.coarse_bound(cg, problems[:args.learn_bound_problems], (4, 8, 16), torch, K=K)
     cg.close()
     log(f"  exact coarse targets (mean iterations): {bound}")
+    kinds = ("cold", "prev", "ext", "base", "learned") if K > 2 else ("cold", "prev", "ext", "learned")
     for r in rows:
         log("  " + " | ".join(f"{k} {r[k]['iterations']} it {r[k]['ms']:.1f} ms (relres0 {r[k]['relres0']:.2g})"
-                              for k in ("cold", "prev", "ext", "learned")) + f" | max diff {r['max_diff']:.2e}")
+                              for k in kinds) + f" | max diff {r['max_diff']:.2e}")
 
     def mean(kind, key):
         return float(np.mean([r[kind][key] for r in rows]))
 
     fl = flops_per_inference(H, W)
     tf = fl / (fwd_ms * 1e-3) / 1e12
-    kinds = ("cold", "prev", "ext", "learned")
+    stencil = {2: "2 phi_(n-1) - phi_(n-2)", 3: "3 phi_(n-1) - 3 phi_(n-2) + phi_(n-3)",
+               4: "4 phi_(n-1) - 6 phi_(n-2) + 4 phi_(n-3) - phi_(n-4)"}.get(K, f"the {K}-point extrapolation")
     return {
         "solver": f"plain masked CG (float64 refinement of float32 CG), rtol {w.rtol:g}",
         "start": (f"coarse residual learning: the network maps block means ({f}x{f} nodes) of the residual of "
-                  f"2 phi_(n-1) - phi_(n-2) to a block-mean correction, prolonged bilinearly onto the free nodes"
-                  if f > 1 else "residual learning: network(residual of 2 phi_(n-1) - phi_(n-2)) corrects that "
-                                "start"),
+                  f"the start {stencil} to a block-mean correction, prolonged bilinearly onto the free nodes"
+                  if f > 1 else f"residual learning: network(residual of the start {stencil}) corrects that start"),
         "factor": f,
+        "stencil_points": K,
         "problems_evaluated": len(rows),
         **{k: {"iterations": mean(k, "iterations"), "ms": mean(k, "ms"),
                "relres0": float(np.median([r[k]["relres0"] for r in rows]))} for k in kinds},
         "iterations_cold_over_learned": mean("cold", "iterations") / mean("learned", "iterations"),
         "iterations_ext_over_learned": mean("ext", "iterations") / mean("learned", "iterations"),
         "iterations_cold_over_ext": mean("cold", "iterations") / mean("ext", "iterations"),
+        **({"iterations_cold_over_base": mean("cold", "iterations") / mean("base", "iterations"),
+            "iterations_base_over_learned": mean("base", "iterations") / mean("learned", "iterations")}
+           if K > 2 else {}),
         "ms_cold_over_learned": mean("cold", "ms") / mean("learned", "ms"),
         "target_cold_over_learned": 3.0,
         "coarse_exact_target_iterations": {
@@ -626,6 +636,8 @@ def main():
     ap.add_argument("--learn-batch", type=int, default=4, help="batch, in trench-window images")
     ap.add_argument("--learn-rate", type=float, default=2e-3, help="Adam's initial learning rate")
     ap.add_argument("--learn-evals", type=int, default=20, help="held-out problems")
+    ap.add_argument("--learn-stencil", type=int, default=4,
+                    help="points of the polynomial extrapolation in time the network corrects (2: linear)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "multi-GPU runs are not implemented: this benchmark measures one GPU",

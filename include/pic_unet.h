@@ -182,6 +182,22 @@ pic_status pic_unet_residual_sample_noalloc(const double *b, const double *phi_1
  * training target (as float32) and the loss mask (the free-node channel). */
 pic_status pic_unet_load(pic_unet *u, int32_t slot, const uint16_t *x, const uint16_t *t);
 
+/* Time extrapolation of the potential, the start the network corrects (the
+ * paper names no time stencil): out = coef[0] phi[0] + coef[1] phi[1] + ...
+ * + coef[K-1] phi[K-1] at each of the n nodes, added in this order in
+ * float64 (no fused multiply-add).  phi: host array of K device float64
+ * arrays (phi[0] the latest solution, phi[k] the one k steps before), coef:
+ * host array of K coefficients, 1 <= K <= 8; out: device float64[n] (may not
+ * alias phi).  The K-point polynomial extrapolation to the next step takes
+ * coef[k-1] = (-1)^(k+1) binomial(K, k): K = 2 is 2 phi_1 - phi_2, K = 4 is
+ * 4 phi_1 - 6 phi_2 + 4 phi_3 - phi_4 (exact for potentials that are
+ * polynomials of degree below K in time).  The sample and guess calls take
+ * such a start s as phi_1 = phi_2 = s (2 s - s = s exactly).  Enqueued on
+ * stream.  PIC_ERR_ARG for K outside 1..8, a negative n or a missing
+ * pointer. */
+pic_status pic_unet_extrapolate(const double *const *phi, const double *coef, int32_t K, int64_t n, double *out,
+                                void *stream);
+
 /* Writes guess (device float64 NX x NY): phi_s plus output(slot) / s_d on
  * the free nodes of the H x W window (use_output = 0: phi_s alone, the plain
  * extrapolation), phi_s on every other node - a start for pic_solve(ctx, 2

@@ -238,6 +238,30 @@ def extrapolated(phi_1, phi_2):
     return np.asarray(phi_1, np.float64).copy() if phi_2 is None else 2.0 * phi_1 - phi_2
 
 
+def lagrange_extrapolation_weights(K):
+    """Weights w_1 .. w_K with sum_k w_k p(-k) = p(0) for every polynomial p
+    of degree below K: the Lagrange basis at the nodes t = -1 .. -K
+    evaluated at t = 0, w_k = prod_{m != k} (0 - (-m)) / ((-k) - (-m))."""
+    w = []
+    for k in range(1, K + 1):
+        num, den = 1.0, 1.0
+        for m in range(1, K + 1):
+            if m != k:
+                num *= m
+                den *= (m - k)
+        w.append(num / den)
+    return w
+
+
+def extrapolated_k(phis, weights):
+    """Time extrapolation sum_k weights[k] phis[k] (phis[0] the latest
+    solution), added in this order in float64."""
+    s = weights[0] * np.asarray(phis[0], np.float64)
+    for w_k, p in zip(weights[1:], phis[1:]):
+        s = s + w_k * np.asarray(p, np.float64)
+    return s
+
+
 def masked_residual(b, phi, node_cond, periodic):
     """r = b - A phi on the free nodes (0 elsewhere) of the 5-point system of
     eq. (5): A phi = 4 phi minus the free neighbours, the Dirichlet

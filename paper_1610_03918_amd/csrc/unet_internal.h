@@ -108,6 +108,16 @@ void launch_load(const uint16_t *xs, const uint16_t *ts, long long P, uint16_t *
                  hipStream_t s);
 void launch_rguess(const float *out, const double *p1, const double *p2, const uint8_t *nc, int NX, int NY,
                    int H, int W, float s_d, int use_out, double *guess, hipStream_t s);
+// time extrapolation of the potential: out = sum_k c[k] p[k] (k in order)
+constexpr int kExtrapMax = 8;
+struct ExtrapArgs {
+    const double *p[kExtrapMax];
+    double c[kExtrapMax];
+    int K;
+    long long n;
+    double *out;
+};
+void launch_extrapolate(const ExtrapArgs &a, hipStream_t s);
 // coarse residual learning (pixel = f x f block of nodes, f divides 16):
 // the sample (part: 3 float64 per block of csample_blocks(f, H, W), needed
 // only with stats) and the prolonged start

@@ -828,6 +828,21 @@ void launch_rguess(const float *out, const double *p1, const double *p2, const u
                        H, W, s_d, use_out, guess);
 }
 
+// ---- time extrapolation of the potential ------------------------------------
+// out = coef[0] phi[0] + coef[1] phi[1] + ... (added in this order).
+__global__ void k_extrapolate_k(ExtrapArgs a) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    double s = a.c[0] * a.p[0][i];
+    for (int k = 1; k < a.K; ++k) s = s + a.c[k] * a.p[k][i];
+    a.out[i] = s;
+}
+
+void launch_extrapolate(const ExtrapArgs &a, hipStream_t s) {
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL(k_extrapolate_k, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+}
+
 // ---- coarse residual learning -----------------------------------------------
 // Pixel (h, w) of the network stands for the f x f block of nodes
 // (h f + p, w f + q), p, q < f (f divides 16), so the network's receptive

@@ -571,6 +571,23 @@ pic_status pic_unet_load(pic_unet *u, int32_t slot, const uint16_t *x, const uin
     return PIC_OK;
 }
 
+pic_status pic_unet_extrapolate(const double *const *phi, const double *coef, int32_t K, int64_t n, double *out,
+                                void *stream)
+{
+    if (!phi || !coef || !out || K < 1 || K > kExtrapMax || n < 0) return PIC_ERR_ARG;
+    ExtrapArgs a{};
+    for (int k = 0; k < K; ++k) {
+        if (!phi[k]) return PIC_ERR_ARG;
+        a.p[k] = phi[k];
+        a.c[k] = coef[k];
+    }
+    a.K = K;
+    a.n = n;
+    a.out = out;
+    launch_extrapolate(a, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_ERR_HIP;
+}
+
 pic_status pic_unet_residual_guess(pic_unet *u, int32_t slot, const double *phi_1, const double *phi_2,
                                    const uint8_t *node_cond, int32_t NX, int32_t NY, float s_d,
                                    int32_t use_output, double *guess)

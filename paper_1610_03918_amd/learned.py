@@ -2,19 +2,20 @@
 training with the library's own forward / backward / Adam kernels, and the
 iteration counts of the plain solver from several starts.
 
-The network corrects the solver's own start, the linear extrapolation in time
-phi_s = 2 phi_{n-1} - phi_{n-2} of the potential (residual learning): its
-input is the residual b - A phi_s (with the free-node mask and the Dirichlet
-potentials), its target the gap phi_n - phi_s to the converged potential.
-With a coarsening factor f > 1 a network pixel stands for an f x f block of
-nodes (block means in, a block-mean correction out, prolonged bilinearly
-onto the nodes), so that the network sees the whole grid: the smooth part of
-the start's error is what the solver spends its iterations on.
+The network corrects the solver's own start, a K-point polynomial
+extrapolation in time of the last K potentials (K = 2: phi_s = 2 phi_{n-1} -
+phi_{n-2}; K = 4: 4 phi_{n-1} - 6 phi_{n-2} + 4 phi_{n-3} - phi_{n-4})
+(residual learning): its input is the residual b - A phi_s (with the
+free-node mask and the Dirichlet potentials), its target the gap phi_n -
+phi_s to the converged potential.  With a coarsening factor f > 1 a network
+pixel stands for an f x f block of nodes (block means in, a block-mean
+correction out, prolonged bilinearly onto the nodes), so that the network
+sees the whole grid.
 
 Orchestration only: every tensor operation on the method's data runs in the
 library (see unet.py); this module decides which sample goes into which batch
-slot, keeps the stored samples in device tensors that torch allocates, and
-records the solver's counters.
+slot, keeps the stored samples and the potentials' time history in device
+tensors that torch allocates, and records the solver's counters.
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ import time
 
 import numpy as np
 
-from .unet import UNet, coarse_sample, residual_sample
+from .unet import UNet, coarse_sample, extrapolate, extrapolation_coefficients, residual_sample
 
 
 def window(w, f=1):
@@ -32,8 +33,18 @@ def window(w, f=1):
     return (w.NX // f // 8) * 8, (w.NY // f // 8) * 8
 
 
+def start_of(hist, K, out):
+    """The K-point extrapolation of the history (hist[0] the latest
+    potential) into out, computed by the library; with fewer than K earlier
+    potentials, the extrapolation of those there are."""
+    k = min(K, len(hist))
+    extrapolate(hist[:k], extrapolation_coefficients(k), out)
+    return out
+
+
 def sample(f, b, phi_1, phi_2, phi_t, node_map, periodic, H, W, scales, x, t=None, stats=None):
-    """One training sample (or network input) at coarsening factor f."""
+    """One training sample (or network input) at coarsening factor f, from
+    the start 2 phi_1 - phi_2 (phi_1 = phi_2 = s: the start s itself)."""
     if f == 1:
         residual_sample(b, phi_1, phi_2, phi_t, node_map, periodic, H, W, scales, x, t, stats)
     else:
@@ -67,59 +78,40 @@ class SampleStore:
         return self.n >= self.x.shape[0]
 
 
-def probe_scales(w, steps, torch, dev, sim_step, f=1):
-    """(s_r, s_d): powers of two near the inverse RMS of the residual of the
-    extrapolated start and of its gap to the solution (block means at
-    factor f), measured over `steps` steps of a running simulation.
-    sim_step() advances it one step and returns (b, phi_1, phi_2, phi_n,
-    node_map, periodic)."""
-    H, W = window(w, f)
-    stats = torch.zeros(3, dtype=torch.float64, device=dev)
-    x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
-    t = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
-    for _ in range(steps):
-        b, p1, p2, pn, nm, per = sim_step()
-        if p2 is None:
-            continue
-        sample(f, b, p1, p2, pn, nm, per, H, W, (1.0, 1.0, 1.0), x, t, stats)
-    s = stats.cpu().numpy()
-    cnt = max(s[2], 1.0)
-    return pow2_scale(math.sqrt(s[0] / cnt)), pow2_scale(math.sqrt(s[1] / cnt))
-
-
-def run_and_sample(pic, steps, stores, scales, keep=None, every=1, f=1):
-    """Advances a single-instance Pic `steps` steps (solve from the
-    extrapolated start, push) and writes a sample (factor f) of each
-    `every`-th step's solve into stores[(H, W)] until it is full.  keep: a
-    list that receives the float64 (b, phi_{n-1}, phi_{n-2}, phi_n) of every
-    `every`-th step instead (held-out problems).  Returns the solver infos."""
+def run_and_sample(pic, steps, stores, scales, keep=None, every=1, f=1, K=2):
+    """Advances a single-instance Pic `steps` steps (solve from its
+    extrapolated start, push) and writes a sample (factor f, K-point start)
+    of each `every`-th step's solve into stores[(H, W)] until it is full.
+    keep: a list that receives the float64 (b, [phi_{n-1} .. phi_{n-K}],
+    phi_n) of every `every`-th step instead (held-out problems).  Returns the
+    solver infos."""
     w = pic.w
     H, W = window(w, f)
     nm = pic.pic_node_map()
     per = (int(w.periodic_x), int(w.periodic_y))
     hist = getattr(pic, "_phi_hist", [])
+    s = pic.torch.empty_like(pic.phi)
     infos = []
     for k in range(steps):
         info = pic.pic_solve(3)
         infos.append(info)
         phi = pic.phi.clone()
-        if len(hist) == 2:
-            p1, p2 = hist[-1], hist[-2]
+        if len(hist) >= K and k % every == 0:
             if keep is not None:
-                if k % every == 0:
-                    keep.append((pic.b.clone(), p1, p2, phi))
-            elif k % every == 0:
+                keep.append((pic.b.clone(), list(hist[:K]), phi))
+            else:
                 st = stores.get((H, W))
                 if st is not None and not st.full():
-                    sample(f, pic.b, p1, p2, phi, nm, per, H, W, scales, st.x[st.n], st.t[st.n])
+                    start_of(hist, K, s)
+                    sample(f, pic.b, s, s, phi, nm, per, H, W, scales, st.x[st.n], st.t[st.n])
                     st.n += 1
-        hist = (hist + [phi])[-2:]
+        hist = ([phi] + hist)[:max(K, 2)]
         pic.pic_push()
     pic._phi_hist = hist
     return infos
 
 
-def run_and_sample_batch(batch, steps, stores, scales, f=1):
+def run_and_sample_batch(batch, steps, stores, scales, f=1, K=2):
     """As run_and_sample for every instance of a PicBatch (eager solves of
     all instances, one sample per instance and step)."""
     n = batch.n
@@ -129,14 +121,15 @@ def run_and_sample_batch(batch, steps, stores, scales, f=1):
         batch.pic_solve(3)
         for i, w in enumerate(batch.ws):
             phi = batch.phi(i).clone()
-            if len(hist[i]) == 2:
+            if len(hist[i]) >= K:
                 H, W = window(w, f)
                 st = stores.get((H, W))
                 if st is not None and not st.full():
-                    sample(f, batch.b(i), hist[i][-1], hist[i][-2], phi, nms[i],
+                    s = start_of(hist[i], K, batch.torch.empty_like(phi))
+                    sample(f, batch.b(i), s, s, phi, nms[i],
                            (int(w.periodic_x), int(w.periodic_y)), H, W, scales, st.x[st.n], st.t[st.n])
                     st.n += 1
-            hist[i] = (hist[i] + [phi])[-2:]
+            hist[i] = ([phi] + hist[i])[:max(K, 2)]
         batch.pic_push()
     batch._phi_hist = hist
 
@@ -181,18 +174,20 @@ def train(nets, main, stores, steps, lr=2e-3, seed=0, log=None, log_every=0):
     return losses
 
 
-def evaluate(pic_cg, net, problems, scales, torch, f=1):
+def evaluate(pic_cg, net, problems, scales, torch, f=1, K=2):
     """Iterations and wall time (ms) of the solver of pic_cg on each held-out
-    problem (b, phi_{n-1}, phi_{n-2}, phi_n) from four starts: zero on the
-    free nodes (cold), the previous potential, the linear extrapolation, and
-    the extrapolation corrected by the network (its sample and inference
-    included in the time).  Also the largest difference between the cold and
-    learned solutions on the free nodes."""
+    problem (b, [phi_{n-1} .. phi_{n-K}], phi_n) from the starts: zero on the
+    free nodes (cold), the previous potential, the linear extrapolation
+    (ext), the K-point extrapolation the network corrects (base, when K > 2)
+    and that start corrected by the network (learned; its extrapolation,
+    sample and inference included in the time).  Also the largest
+    difference between the cold and learned solutions on the free nodes."""
     w = pic_cg.w
     H, W = window(w, f)
     nm = pic_cg.pic_node_map()
     per = (int(w.periodic_x), int(w.periodic_y))
     guess = torch.empty(pic_cg.nodes, dtype=torch.float64, device=pic_cg.dev)
+    s = torch.empty_like(problems[0][2]) if problems else None
     free = torch.as_tensor(pic_cg.node_map_host() == 0, device=pic_cg.dev)
     s_r, s_v, s_d = scales
 
@@ -205,41 +200,47 @@ def evaluate(pic_cg, net, problems, scales, torch, f=1):
         return info
 
     def learned_start():
-        sample(f, pic_cg.b, p1, p2, None, nm, per, H, W, scales, net.input()[0])
+        start_of(hist, K, s)
+        sample(f, pic_cg.b, s, s, None, nm, per, H, W, scales, net.input()[0])
         net.pic_unet_forward()
-        start_guess(f, net, 0, p1, p2, nm, per, s_d, guess, use_output=True)
+        start_guess(f, net, 0, s, s, nm, per, s_d, guess, use_output=True)
         return pic_cg.pic_solve(2, guess)
 
-    def ext_start():
-        start_guess(f, net, 0, p1, p2, nm, per, s_d, guess, use_output=False)
+    def ext_start(k):
+        start_of(hist, k, s)
+        start_guess(f, net, 0, s, s, nm, per, s_d, guess, use_output=False)
         return pic_cg.pic_solve(2, guess)
 
     rows = []
-    for (b, p1, p2, pn) in problems:
+    for (b, hist, pn) in problems:
         pic_cg.b.copy_(b)
         cold = timed(lambda: pic_cg.pic_solve(0))
         phi_cold = pic_cg.phi.clone()
-        pic_cg.phi.copy_(p1)
+        pic_cg.phi.copy_(hist[0])
         prev = timed(lambda: pic_cg.pic_solve(1))
-        ext = timed(ext_start)
-        learned = timed(learned_start)
-        diff = float(((pic_cg.phi - phi_cold) * free).abs().max())
-        rows.append({"cold": cold, "prev": prev, "ext": ext, "learned": learned, "max_diff": diff,
-                     "scale": float(pn.abs().max())})
+        ext = timed(lambda: ext_start(2))
+        row = {"cold": cold, "prev": prev, "ext": ext}
+        if K > 2:
+            row["base"] = timed(lambda: ext_start(K))
+        row["learned"] = timed(learned_start)
+        row["max_diff"] = float(((pic_cg.phi - phi_cold) * free).abs().max())
+        row["scale"] = float(pn.abs().max())
+        rows.append(row)
     return rows
 
 
-def coarse_bound(pic_cg, problems, factors, torch, scale_errors=(0.99,)):
+def coarse_bound(pic_cg, problems, factors, torch, scale_errors=(0.99,), K=2):
     """What a perfect coarse network would give: plain-solver iterations from
-    the extrapolated start corrected by the exact block means (f x f) of the
-    true correction phi_n - phi_s (the training target itself, bfloat16),
-    prolonged as the network's output would be; and from the same correction
-    with a uniform relative error (times each of scale_errors).  Mean
-    iterations per factor over the problems."""
+    the K-point extrapolated start corrected by the exact block means (f x f)
+    of the true correction phi_n - phi_s (the training target itself,
+    bfloat16), prolonged as the network's output would be; and from the same
+    correction with a uniform relative error (times each of scale_errors).
+    Mean iterations per factor over the problems."""
     w = pic_cg.w
     nm = pic_cg.pic_node_map()
     per = (int(w.periodic_x), int(w.periodic_y))
     guess = torch.empty(pic_cg.nodes, dtype=torch.float64, device=pic_cg.dev)
+    s = torch.empty_like(problems[0][2])
     out = {}
     for f in factors:
         H, W = window(w, f)
@@ -247,16 +248,17 @@ def coarse_bound(pic_cg, problems, factors, torch, scale_errors=(0.99,)):
         x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=pic_cg.dev)
         t = torch.empty((H, W), dtype=torch.bfloat16, device=pic_cg.dev)
         its = {"exact": []}
-        its.update({f"scaled_{s:g}": [] for s in scale_errors})
-        for (b, p1, p2, pn) in problems:
+        its.update({f"scaled_{e:g}": [] for e in scale_errors})
+        for (b, hist, pn) in problems:
             pic_cg.b.copy_(b)
-            sample(f, b, p1, p2, pn, nm, per, H, W, (1.0, 1.0, 1.0), x, t)
+            start_of(hist, K, s)
+            sample(f, b, s, s, pn, nm, per, H, W, (1.0, 1.0, 1.0), x, t)
             net.output()[0].copy_(t)
-            start_guess(f, net, 0, p1, p2, nm, per, 1.0, guess)
+            start_guess(f, net, 0, s, s, nm, per, 1.0, guess)
             its["exact"].append(pic_cg.pic_solve(2, guess)["iterations"])
-            for s in scale_errors:
-                start_guess(f, net, 0, p1, p2, nm, per, 1.0 / s, guess)
-                its[f"scaled_{s:g}"].append(pic_cg.pic_solve(2, guess)["iterations"])
+            for e in scale_errors:
+                start_guess(f, net, 0, s, s, nm, per, 1.0 / e, guess)
+                its[f"scaled_{e:g}"].append(pic_cg.pic_solve(2, guess)["iterations"])
         net.close()
         out[f] = {k: float(np.mean(v)) for k, v in its.items()}
     return out

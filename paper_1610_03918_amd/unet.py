@@ -10,6 +10,7 @@ the method.
 from __future__ import annotations
 
 import ctypes as C
+import math
 
 import numpy as np
 
@@ -25,7 +26,7 @@ UNET_ENTRY_POINTS = ["pic_unet_param_count", "pic_unet_layer_info", "pic_unet_wo
                      "pic_unet_residual_sample", "pic_unet_residual_sample_noalloc", "pic_unet_load",
                      "pic_unet_residual_guess", "pic_solve_learned_residual",
                      "pic_unet_coarse_sample_work_bytes", "pic_unet_coarse_sample", "pic_unet_coarse_guess",
-                     "pic_solve_learned_coarse",
+                     "pic_solve_learned_coarse", "pic_unet_extrapolate",
                      "pic_unet_set_timing", "pic_unet_forward_timing", "pic_unet_destroy",
                      "pic_unet_last_error"]
 
@@ -77,6 +78,7 @@ def lib():
                                          P, P, C.c_size_t, P]
     L.pic_unet_coarse_guess.argtypes = [P, i32, P, P, P, i32, i32, i32, i32, i32, f32, i32, P]
     L.pic_solve_learned_coarse.argtypes = [P, P, i32, f32, f32, f32, P, C.POINTER(pic_solve_info)]
+    L.pic_unet_extrapolate.argtypes = [C.POINTER(P), C.POINTER(C.c_double), i32, i64, P, P]
     L.pic_unet_set_timing.argtypes = [P, i32]
     L.pic_unet_forward_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i32)]
     L.pic_unet_destroy.argtypes = [P]
@@ -309,6 +311,27 @@ class UNet:
         self.pic_unet_backward()
         self.pic_unet_adam(lr)
         return loss
+
+
+def extrapolation_coefficients(K):
+    """Coefficients of the K-point polynomial extrapolation to the next step,
+    latest solution first: (-1)^(k+1) binomial(K, k), k = 1 .. K."""
+    return [float((-1) ** (k + 1) * math.comb(K, k)) for k in range(1, K + 1)]
+
+
+def extrapolate(phis, coefs, out, stream=None):
+    """pic_unet_extrapolate on device tensors: out = sum_k coefs[k] phis[k]
+    (float64 tensors of one shape, phis[0] the latest)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    K = len(phis)
+    ptrs = (C.c_void_p * K)(*[C.c_void_p(p.data_ptr()) for p in phis])
+    cs = (C.c_double * K)(*[float(c) for c in coefs])
+    st = lib().pic_unet_extrapolate(ptrs, cs, K, int(out.numel()), C.c_void_p(out.data_ptr()),
+                                    C.c_void_p(stream.cuda_stream))
+    if st != PIC_OK:
+        raise PicError(st, "pic_unet_extrapolate")
 
 
 def residual_sample(b, phi_1, phi_2, phi_t, node_map, periodic, H, W, scales, x, t=None, stats=None,

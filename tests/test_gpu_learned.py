@@ -1,16 +1,19 @@
 """GPU test of the learned warm start end to end (residual learning): samples
 from one run of a small y-periodic trench, training with the library's own
 forward / backward / Adam kernels, and plain masked CG to 1e-8 on held-out
-problems of a second run (another particle load) from four starts: zero on
+problems of a second run (another particle load) from these starts: zero on
 the free nodes (cold), the previous potential, the linear extrapolation in
-time, and the extrapolation corrected by the network.
+time (ext), the K-point extrapolation the network corrects (base, K = 4), and
+that start corrected by the network.
 
-Asserted: the training loss falls, every solve converges to the same
-potential, the network cuts the residual of the extrapolated start, and it
-saves iterations against both the cold start and the extrapolation alone
-(the method without the network).  The measured factors are printed.  The
-target of a >= 3x cut against the cold start is kept as a strict expected
-failure with the measured factor."""
+Asserted, for the network on the linear start: the training loss falls, every
+solve converges to the same potential, the network cuts the residual of the
+extrapolated start, and it saves iterations against both the cold start and
+the extrapolation alone.  For the network on the 4-point start: every solve
+converges to the same potential and the corrected start beats both the
+4-point start and the linear one.  The target of a >= 3x cut against the
+cold start is kept as a strict expected failure at this size, with the
+measured factor.  The measured factors are printed."""
 import numpy as np
 import pytest
 
@@ -23,7 +26,7 @@ def _trench(seed):
     return synth.trench(nx=96, ny=56, width=6, depth=24, ppc=12, seed=seed, rtol=1e-8)
 
 
-def _train(seed=41, steps=1500):
+def _train(seed=41, steps=1500, K=2):
     import torch
     from paper_1610_03918_amd import Pic, learned
     w = _trench(seed)
@@ -34,18 +37,19 @@ def _train(seed=41, steps=1500):
     dev = torch.device("cuda:0")
     # probe the scales on a few steps
     probe = []
-    learned.run_and_sample(a, 12, {}, (1.0, 1.0, 1.0), keep=probe)
+    learned.run_and_sample(a, 12 + K, {}, (1.0, 1.0, 1.0), keep=probe, K=K)
     from paper_1610_03918_amd.unet import residual_sample
     stats = torch.zeros(3, dtype=torch.float64, device=dev)
     x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
     t = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
-    for b, p1, p2, pn in probe:
-        residual_sample(b, p1, p2, pn, a.pic_node_map(), (0, 1), H, W, (1.0, 1.0, 1.0), x, t, stats)
+    for b, hist, pn in probe:
+        s0 = learned.start_of(hist, K, torch.empty_like(pn))
+        residual_sample(b, s0, s0, pn, a.pic_node_map(), (0, 1), H, W, (1.0, 1.0, 1.0), x, t, stats)
     s = stats.cpu().numpy()
     sc = (learned.pow2_scale(np.sqrt(s[0] / s[2])), float(np.float32(1 / 50)),
           learned.pow2_scale(np.sqrt(s[1] / s[2])))
     stores = {(H, W): learned.SampleStore(torch, dev, H, W, 400)}
-    learned.run_and_sample(a, 402, stores, sc)
+    learned.run_and_sample(a, 400 + K, stores, sc, K=K)
     a.close()
     assert stores[(H, W)].n == 400
     nets, main = learned.make_nets(stores, 8 * H * W, seed=3)
@@ -53,33 +57,45 @@ def _train(seed=41, steps=1500):
     return w, nets[(H, W)], sc, losses
 
 
-@pytest.fixture(scope="module")
-def evaluated():
-    """Train on run A, evaluate on 12 held-out problems of run B (once)."""
+def _evaluate(K):
+    """Train on run A, evaluate on 12 held-out problems of run B."""
     import torch
     from paper_1610_03918_amd import Pic, learned
     from paper_1610_03918_amd.unet import UNet
-    wa, net, sc, losses = _train()
+    wa, net, sc, losses = _train(K=K)
     wb = _trench(42)
     b = Pic(wb, synth.load(wb))
     b.start()
     b.pic_step(40)
-    learned.run_and_sample(b, 60, {}, sc)
+    learned.run_and_sample(b, 60, {}, sc, K=K)
     problems = []
-    learned.run_and_sample(b, 24, {}, sc, keep=problems, every=2)
+    learned.run_and_sample(b, 24, {}, sc, keep=problems, every=2, K=K)
     b.close()
     u1 = UNet(1, net.H, net.W, params=net.params, periodic_w=True)
     cg = Pic(wb, synth.load(wb), solver=1, max_iter=20000)
-    rows = learned.evaluate(cg, u1, problems, sc, torch)
+    rows = learned.evaluate(cg, u1, problems, sc, torch, K=K)
     cg.close()
     u1.close()
-    its = {k: np.array([r[k]["iterations"] for r in rows], float) for k in ("cold", "prev", "ext", "learned")}
-    r0 = {k: np.median([r[k]["relres0"] for r in rows]) for k in ("cold", "prev", "ext", "learned")}
-    print("loss", np.mean(losses[:5]), "->", np.mean(losses[-20:]))
+    kinds = [k for k in ("cold", "prev", "ext", "base", "learned") if k in rows[0]]
+    its = {k: np.array([r[k]["iterations"] for r in rows], float) for k in kinds}
+    r0 = {k: np.median([r[k]["relres0"] for r in rows]) for k in kinds}
+    print(f"K = {K}: loss", np.mean(losses[:5]), "->", np.mean(losses[-20:]))
     print({k: float(v.mean()) for k, v in its.items()}, r0,
           "cold/learned", its["cold"].mean() / its["learned"].mean(),
           "ext/learned", its["ext"].mean() / its["learned"].mean())
     return losses, rows, its, r0
+
+
+@pytest.fixture(scope="module")
+def evaluated():
+    """The network correcting the linear extrapolation."""
+    return _evaluate(2)
+
+
+@pytest.fixture(scope="module")
+def evaluated4():
+    """The network correcting the 4-point extrapolation."""
+    return _evaluate(4)
 
 
 def test_learned_start_cuts_cg_iterations(evaluated):
@@ -98,11 +114,31 @@ def test_learned_start_cuts_cg_iterations(evaluated):
     assert its["cold"].mean() / its["learned"].mean() > 1.4, its
 
 
-@pytest.mark.xfail(strict=True, reason="the >= 3x cut is not reached: measured 1.56x here "
-                                       "(1.53x at 1024 x 512), bounded by the smooth part of the start's error, "
-                                       "which the network does not predict on held-out steps")
-def test_learned_start_meets_the_threefold_target(evaluated):
-    _, _, its, _ = evaluated
+def test_network_corrects_the_four_point_start(evaluated4):
+    """The network trained on the 4-point start: every solve reaches the same
+    potential, and the corrected start beats both the 4-point start it
+    corrects and the linear extrapolation.  On this small, noisy problem
+    (12 particles per cell) the 4-point start alone is worse than the linear
+    one, since its weights amplify the particle noise of the potentials
+    (sum of squared weights 69 against 5); measured: cold 275, ext 182,
+    base 216, learned 163 iterations, start residual 0.018 -> 0.001."""
+    losses, rows, its, r0 = evaluated4
+    assert np.all(np.isfinite(losses))
+    assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:5]), (losses[:5], losses[-20:])
+    for r in rows:
+        for k in ("cold", "prev", "ext", "base", "learned"):
+            assert r[k]["converged"], (k, r)
+        assert r["max_diff"] <= 1e-4 * r["scale"], r
+    assert r0["learned"] < 0.25 * r0["base"], r0
+    assert its["learned"].mean() < its["base"].mean(), its
+    assert its["learned"].mean() < its["ext"].mean(), its
+
+
+@pytest.mark.xfail(strict=True, reason="at 96x56 with 12 particles per cell the corrected "
+                   "4-point start needs 1.68x fewer iterations than the cold start; the "
+                   "3x cut holds on the 1024x512 trench (3.66x, measured by the benchmark)")
+def test_threefold_target_on_the_small_trench(evaluated4):
+    losses, rows, its, r0 = evaluated4
     assert its["cold"].mean() / its["learned"].mean() >= 3.0, its
 
 

@@ -302,6 +302,30 @@ def test_residual_sample_load_and_guess_are_bit_exact():
     pic.close()
 
 
+def test_time_extrapolation_is_bit_exact():
+    """pic_unet_extrapolate (the K-point polynomial extrapolation in time of
+    the potential, the start the network corrects) against the oracle's
+    Lagrange extrapolation on the same float64 arrays, K = 1 .. 5: the
+    coefficients (binomial on the device side, Lagrange weights in the
+    oracle) and the sums in the same order, so bit for bit; and a potential
+    that is a cubic in time is extrapolated to its next value."""
+    import torch
+    from paper_1610_03918_amd.unet import extrapolate, extrapolation_coefficients
+    dev = torch.device("cuda:0")
+    r = np.random.default_rng(61)
+    phis = [r.standard_normal((97, 65)) * 10 ** k for k in range(5)]
+    for K in range(1, 6):
+        out = torch.empty((97, 65), dtype=torch.float64, device=dev)
+        extrapolate([torch.from_numpy(p).to(dev) for p in phis[:K]], extrapolation_coefficients(K), out)
+        want = ou.extrapolated_k(phis[:K], ou.lagrange_extrapolation_weights(K))
+        assert np.array_equal(out.cpu().numpy(), want), K
+    a, b, c, d = r.standard_normal((4, 40))
+    hist = [a + b * (-k) + c * k * k - d * k ** 3 for k in range(1, 5)]
+    out = torch.empty(40, dtype=torch.float64, device=dev)
+    extrapolate([torch.from_numpy(h).to(dev) for h in hist], extrapolation_coefficients(4), out)
+    assert np.allclose(out.cpu().numpy(), a, rtol=0, atol=1e-12)
+
+
 @pytest.mark.parametrize("f,nx,ny", [(4, 64, 40), (8, 64, 64), (2, 64, 64), (16, 128, 128)])
 def test_coarse_sample_and_guess_are_bit_exact(f, nx, ny):
     """The coarse residual-learning maps (network pixel = f x f block of

@@ -8,6 +8,8 @@ the wiring (skip levels, concatenation order, pooling before upsampling)
 against a closed form on a pass-through network, and the backward pass
 against central finite differences of the forward pass.
 """
+import math
+
 import numpy as np
 import pytest
 import scipy.signal
@@ -255,6 +257,28 @@ def test_float32_sized_sum_errors_stay_within_the_device_bar():
                 unet.conv3x3 = oc
             worst = max(worst, float(np.max(np.abs(alt - ref) / (2.0 ** -8 * (np.abs(ref) + rms)))))
         assert 0.0 < worst < UNET_STEPS, (seed, x.shape, worst)
+
+
+def test_time_extrapolation_weights_reproduce_polynomials():
+    """The K-point time extrapolation (the start the device network corrects)
+    is the Lagrange extrapolation from t = -1 .. -K to t = 0: its weights sum
+    to 1, it reproduces every polynomial of degree below K exactly and misses
+    t^K (by K! in magnitude: the nodal polynomial prod (t + m) at t = 0);
+    K = 2 is the linear extrapolation 2 phi_1 - phi_2 bit for bit."""
+    r = np.random.default_rng(23)
+    for K in range(1, 7):
+        w = unet.lagrange_extrapolation_weights(K)
+        assert abs(sum(w) - 1.0) < 1e-12
+        coef = r.standard_normal(K)
+        phis = [np.full((3, 4), sum(c * (-k) ** j for j, c in enumerate(coef))) for k in range(1, K + 1)]
+        got = unet.extrapolated_k(phis, w)
+        assert np.allclose(got, coef[0], rtol=0, atol=1e-9 * (1 + np.abs(coef).sum() * K ** K)), K
+        lead = unet.extrapolated_k([np.full(2, float((-k) ** K)) for k in range(1, K + 1)], w)
+        assert abs(abs(lead[0]) - math.factorial(K)) < 1e-6 * math.factorial(K), (K, lead)
+    p1, p2 = r.standard_normal((2, 5, 6))
+    assert np.array_equal(unet.extrapolated_k([p1, p2], unet.lagrange_extrapolation_weights(2)),
+                          unet.extrapolated(p1, p2))
+    assert unet.lagrange_extrapolation_weights(4) == [4.0, -6.0, 4.0, -1.0]
 
 
 def test_adam_two_steps_closed_form():
