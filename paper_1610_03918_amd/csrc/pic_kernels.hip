@@ -2051,6 +2051,52 @@ __device__ __forceinline__ PK resolve(const PushArgs &a)
     return k;
 }
 
+// Cell-by-cell walk of the straight segment (Dx, Dy) from offsets (x0, y0)
+// in cell (ci, cj) across sx, sy faces (not both 0): the earlier face first,
+// compared as (fx + kx)|Dy| <= (fy + ky)|Dx| (ties cross x).  Stops at the
+// first cell outside a bounded axis or inside a conductor: dead = direction
+// (0 +x, 1 -x, 2 +y, 3 -y) + 4 when the last cell occupied (ei, ej) lies in the
+// trench box; else dead stays -1 and (ei, ej) is the final cell.
+__device__ __forceinline__ void walk_cells(const PK &a, float x0, float y0, float Dx, float Dy, int sx, int sy,
+                                           int &dead, int &ei, int &ej)
+{
+    const Geom &g = a.g;
+    const float ax = fabsf(Dx), ay = fabsf(Dy);
+    const float fx = sx > 0 ? 1.0f - x0 : x0, fy = sy > 0 ? 1.0f - y0 : y0;
+    const int nxs = abs(sx), nys = abs(sy);
+    const int di = sx > 0 ? 1 : -1, dj = sy > 0 ? 1 : -1;
+    int kx = 0, ky = 0;
+    while (kx < nxs || ky < nys) {
+        bool gox;
+        if (ky >= nys) gox = true;
+        else if (kx >= nxs) gox = false;
+        else gox = ((fx + (float)kx) * ay <= (fy + (float)ky) * ax);
+        int ni = ei, nj = ej, dir;
+        if (gox) { ni = ei + di; kx++; dir = di > 0 ? 0 : 1; }
+        else { nj = ej + dj; ky++; dir = dj > 0 ? 2 : 3; }
+        bool out = false;
+        if (g.px) ni = wrap_hi(wrap_lo(ni, g.nx), g.nx);
+        else if (ni < 0 || ni >= g.nx) out = true;
+        if (g.py) nj = wrap_hi(wrap_lo(nj, g.ny), g.ny);
+        else if (nj < 0 || nj >= g.ny) out = true;
+        if (!out) {
+            // conductor test from the block's LDS map when the cell lies in it
+            int li = ni - a.c0i, lj = nj - a.c0j;
+            if (g.px) { if (li < 0) li += g.nx; else if (li >= g.nx) li -= g.nx; }
+            if (g.py) { if (lj < 0) lj += g.ny; else if (lj >= g.ny) lj -= g.ny; }
+            const bool loc = li >= 0 && li < a.CW && lj >= 0 && lj < a.CH;
+            if (loc ? a.scc[li * a.CH + lj] : a.cell_cond[(long long)ni * g.ny + nj]) out = true;
+        }
+        if (out) {
+            const bool inbox = ei >= a.box_i_top && ej >= a.box_j_lo && ej < a.box_j_hi;
+            dead = dir + (inbox ? 4 : 0);
+            break;
+        }
+        ei = ni;
+        ej = nj;
+    }
+}
+
 // Leapfrog push of one particle with the bilinear gather of its cell's
 // corner fields and the cell-by-cell wall test (eqs. 1-4).  Computes the new
 // velocity (ux, uy), offsets (nxo, nyo) and cell (ei, ej); returns false when
@@ -2059,7 +2105,6 @@ __device__ __forceinline__ bool push_core(const PK &a, float x0, float y0, float
                                           float4 ea, float4 eb, int ci, int cj, int &dead, int &ei,
                                           int &ej, float &ux, float &uy, float &nxo, float &nyo)
 {
-    const Geom &g = a.g;
     const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
     const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
     float ex = w00 * ea.x;
@@ -2084,44 +2129,7 @@ __device__ __forceinline__ bool push_core(const PK &a, float x0, float y0, float
     } else {
         sx = (int)fsx;
         sy = (int)fsy;
-        if (sx != 0 || sy != 0) {
-            // walk the straight segment cell by cell; the earlier face first,
-            // compared as (fx + kx)|Dy| <= (fy + ky)|Dx| (ties cross x)
-            const float ax = fabsf(Dx), ay = fabsf(Dy);
-            const float fx = sx > 0 ? 1.0f - x0 : x0, fy = sy > 0 ? 1.0f - y0 : y0;
-            const int nxs = abs(sx), nys = abs(sy);
-            const int di = sx > 0 ? 1 : -1, dj = sy > 0 ? 1 : -1;
-            int kx = 0, ky = 0;
-            while (kx < nxs || ky < nys) {
-                bool gox;
-                if (ky >= nys) gox = true;
-                else if (kx >= nxs) gox = false;
-                else gox = ((fx + (float)kx) * ay <= (fy + (float)ky) * ax);
-                int ni = ei, nj = ej, dir;
-                if (gox) { ni = ei + di; kx++; dir = di > 0 ? 0 : 1; }
-                else { nj = ej + dj; ky++; dir = dj > 0 ? 2 : 3; }
-                bool out = false;
-                if (g.px) ni = wrap_hi(wrap_lo(ni, g.nx), g.nx);
-                else if (ni < 0 || ni >= g.nx) out = true;
-                if (g.py) nj = wrap_hi(wrap_lo(nj, g.ny), g.ny);
-                else if (nj < 0 || nj >= g.ny) out = true;
-                if (!out) {
-                    // conductor test from the block's LDS map when the cell lies in it
-                    int li = ni - a.c0i, lj = nj - a.c0j;
-                    if (g.px) { if (li < 0) li += g.nx; else if (li >= g.nx) li -= g.nx; }
-                    if (g.py) { if (lj < 0) lj += g.ny; else if (lj >= g.ny) lj -= g.ny; }
-                    const bool loc = li >= 0 && li < a.CW && lj >= 0 && lj < a.CH;
-                    if (loc ? a.scc[li * a.CH + lj] : a.cell_cond[(long long)ni * g.ny + nj]) out = true;
-                }
-                if (out) {
-                    const bool inbox = ei >= a.box_i_top && ej >= a.box_j_lo && ej < a.box_j_hi;
-                    dead = dir + (inbox ? 4 : 0);
-                    break;
-                }
-                ei = ni;
-                ej = nj;
-            }
-        }
+        if (sx != 0 || sy != 0) walk_cells(a, x0, y0, Dx, Dy, sx, sy, dead, ei, ej);
     }
     nxo = x0;
     nyo = y0;
@@ -2260,6 +2268,11 @@ __device__ __forceinline__ void st_nt_f4(GLOBAL float *p, float a, float b, floa
     nt_f4 v = {a, b, c, d};
     __builtin_nontemporal_store(v, (GLOBAL nt_f4 *)p);
 }
+__device__ __forceinline__ void st_nt_i4(GLOBAL int32_t *p, int a, int b, int c, int d)
+{
+    nt_i4 v = {a, b, c, d};
+    __builtin_nontemporal_store(v, (GLOBAL nt_i4 *)p);
+}
 
 // Corner fields of the particle's cell (packed code c >= 0): from the
 // block's LDS copy of the tile + 1-cell frame (origin e0i, e0j; EW x EH
@@ -2324,6 +2337,178 @@ __device__ __forceinline__ void deposit_lane(const PK &a, unsigned long long *mA
         }
     }
     // wavefront merge of equal cells (all lanes take part)
+    const unsigned m3 = ux * uy;
+    if (MERGE > 0) {
+        unsigned long long pend = __ballot(key >= 0);
+        for (int it = 0; it < MERGE && pend; it++) {
+            const int leader = __builtin_ctzll(pend);
+            const int lk = __builtin_amdgcn_readlane(key, leader);
+            const bool m = key == lk;
+            const unsigned long long mask = __ballot(m);
+            unsigned sx = m ? ux : 0u, sy = m ? uy : 0u;
+            unsigned sh = m ? (m3 >> 16) : 0u, sl = m ? (m3 & 0xFFFFu) : 0u;
+            wave_sum4_u32(sx, sy, sh, sl);
+            if (lane == leader) {
+                const unsigned long long cnt = (unsigned long long)__popcll(mask);
+                const unsigned long long s3 = ((unsigned long long)sh << 16) + sl;
+                atomicAdd(&mA[lk], (cnt << 45) + s3);
+                atomicAdd(&mB[lk], (unsigned long long)sx | ((unsigned long long)sy << 29));
+            }
+            if (m) key = -1;
+            pend &= ~mask;
+        }
+    }
+    if (key >= 0) {
+        atomicAdd(&mA[key], (1ull << 45) + (unsigned long long)m3);
+        atomicAdd(&mB[key], (unsigned long long)ux | ((unsigned long long)uy << 29));
+    }
+}
+
+// ---- block-local cell coordinates -------------------------------------------
+// A particle's cell relative to the origin (c0i, c0j) of the block's conductor
+// map, taken into [0, n) on a periodic axis.  The field frame and the deposit
+// window are fixed shifts of the same origin, so one wrapped coordinate serves
+// all three LDS copies, and a step of the walk is one add.  An LDS copy holds
+// the cell (origin + l) mod n at index l, so any representative of the cell
+// modulo n that lands inside a copy reads the right entry.
+__device__ __forceinline__ int map_rel(int c, int c0, int n, int per)
+{
+    int l = c - c0;
+    if (per) { if (l < 0) l += n; else if (l >= n) l -= n; }
+    return l;
+}
+
+__device__ __forceinline__ int wrap_step(int c, int n, int per)
+{
+    if (per) { if (c < 0) c += n; else if (c >= n) c -= n; }
+    return c;
+}
+
+// Whether the cell a step of the walk enters stops the particle (a conductor
+// cell, or outside a bounded axis).  (lx, ly): its conductor-map coordinates;
+// (gi, gj): its global ones, one cell from a valid cell, not yet wrapped.  The
+// LDS map holds 1 for cells outside a bounded axis, so both tests agree.
+__device__ __forceinline__ bool step_blocked(const PK &a, int lx, int ly, int gi, int gj)
+{
+    if ((unsigned)lx < (unsigned)a.CW && (unsigned)ly < (unsigned)a.CH) return a.scc[lx * a.CH + ly] != 0;
+    const Geom &g = a.g;
+    if (g.px) gi = wrap_step(gi, g.nx, 1);
+    else if (gi < 0 || gi >= g.nx) return true;
+    if (g.py) gj = wrap_step(gj, g.ny, 1);
+    else if (gj < 0 || gj >= g.ny) return true;
+    return a.cell_cond[(long long)gi * g.ny + gj] != 0;
+}
+
+// push_core with the particle's cell also in conductor-map coordinates
+// (lx, ly; moved with the particle).  The same arithmetic in the same order;
+// a move of at most one face per axis (all but a few particles per million)
+// is walked in straight-line code: for a diagonal move the earlier face first,
+// compared as fx |Dy| <= fy |Dx| (ties cross x), then the other one.  Longer
+// moves take the cell-by-cell walk of push_core.
+__device__ __forceinline__ bool push_core_l(const PK &a, float x0, float y0, float vx0, float vy0,
+                                            float4 ea, float4 eb, int ci, int cj, int &lx, int &ly,
+                                            int &dead, int &ei, int &ej, float &ux, float &uy,
+                                            float &nxo, float &nyo)
+{
+    const Geom &g = a.g;
+    const float wx0 = 1.0f - x0, wy0 = 1.0f - y0;
+    const float w00 = wx0 * wy0, w10 = x0 * wy0, w01 = wx0 * y0, w11 = x0 * y0;
+    float ex = w00 * ea.x;
+    ex = ex + w10 * ea.z;
+    ex = ex + w01 * eb.x;
+    ex = ex + w11 * eb.z;
+    float ey = w00 * ea.y;
+    ey = ey + w10 * ea.w;
+    ey = ey + w01 * eb.y;
+    ey = ey + w11 * eb.w;
+    ux = vx0 + a.qdt * ex;
+    uy = vy0 + a.qdt * ey;
+    const float Dx = ux * a.dtf, Dy = uy * a.dtf;
+    const float x1 = x0 + Dx, y1 = y0 + Dy;
+    const float fsx = floorf(x1), fsy = floorf(y1);
+    dead = -1;
+    ei = ci;
+    ej = cj;
+    nxo = x0;
+    nyo = y0;
+    if (!(fabsf(fsx) < 1.0e6f && fabsf(fsy) < 1.0e6f)) {
+        dead = 8;
+        return false;
+    }
+    const int sx = (int)fsx, sy = (int)fsy;
+    if (sx != 0 || sy != 0) {
+        if ((unsigned)(sx + 1) <= 2u && (unsigned)(sy + 1) <= 2u) {
+            const bool both = sx != 0 && sy != 0;
+            bool gox = sy == 0;
+            if (both) {
+                const float fx = sx > 0 ? 1.0f - x0 : x0, fy = sy > 0 ? 1.0f - y0 : y0;
+                gox = fx * fabsf(Dy) <= fy * fabsf(Dx);
+            }
+            const int d1x = gox ? sx : 0, d1y = gox ? 0 : sy;
+            if (step_blocked(a, lx + d1x, ly + d1y, ci + d1x, cj + d1y)) {
+                dead = gox ? (sx > 0 ? 0 : 1) : (sy > 0 ? 2 : 3);
+            } else if (both && step_blocked(a, lx + sx, ly + sy, ci + sx, cj + sy)) {
+                dead = gox ? (sy > 0 ? 2 : 3) : (sx > 0 ? 0 : 1);
+                ei = wrap_step(ci + d1x, g.nx, g.px);
+                ej = wrap_step(cj + d1y, g.ny, g.py);
+            }
+            if (dead >= 0) {
+                const bool inbox = ei >= a.box_i_top && ej >= a.box_j_lo && ej < a.box_j_hi;
+                dead += inbox ? 4 : 0;
+                return false;
+            }
+            ei = wrap_step(ci + sx, g.nx, g.px);
+            ej = wrap_step(cj + sy, g.ny, g.py);
+        } else {
+            walk_cells(a, x0, y0, Dx, Dy, sx, sy, dead, ei, ej);
+            if (dead >= 0) return false;
+        }
+        lx += sx;
+        ly += sy;
+    }
+    nxo = x1 - (float)sx;
+    nyo = y1 - (float)sy;
+    if (nxo >= 1.0f) nxo = 0x1.fffffep-1f;
+    if (nyo >= 1.0f) nyo = 0x1.fffffep-1f;
+    return true;
+}
+
+// Corner fields from conductor-map coordinates (lx, ly): the field frame's
+// origin is the map's shifted by halo + 1 - kFieldFrame cells.
+__device__ __forceinline__ void cell_fields_l(const PK &a, const float4 *sE, int sh, int EW, int EH, int lx,
+                                              int ly, int ci, int cj, float4 &ea, float4 &eb)
+{
+    const int li = lx - sh, lj = ly - sh;
+    if ((unsigned)li < (unsigned)EW && (unsigned)lj < (unsigned)EH) {
+        const int m = 2 * (li * EH + lj);
+        ea = sE[m];
+        eb = sE[m + 1];
+    } else {
+        const long long cc = (long long)ci * a.g.ny + cj;
+        ea = ld_f4(a.E4 + 2 * cc);
+        eb = ld_f4(a.E4 + 2 * cc + 1);
+    }
+}
+
+// deposit_lane with the deposit-window coordinates given (wi, wj: the
+// conductor-map ones less 1).
+template <int MERGE>
+__device__ __forceinline__ void deposit_lane_l(const PK &a, unsigned long long *mA, unsigned long long *mB,
+                                               int lane, bool alive, int ci, int cj, float x0, float y0,
+                                               int wi, int wj, int WX, int WY, unsigned long long &nfb)
+{
+    int key = -1;
+    unsigned ux = 0, uy = 0;
+    if (alive) {
+        ux = (unsigned)floorf(x0 * 65536.0f);
+        uy = (unsigned)floorf(y0 * 65536.0f);
+        if ((unsigned)wi < (unsigned)WX && (unsigned)wj < (unsigned)WY) {
+            key = wi * WY + wj;
+        } else {
+            deposit_global(a.rho, a.g, ci, cj, ux, uy);
+            nfb++;
+        }
+    }
     const unsigned m3 = ux * uy;
     if (MERGE > 0) {
         unsigned long long pend = __ballot(key >= 0);
@@ -2455,32 +2640,38 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                 }
             }
             bool alv[4];
+            // slots holding a live particle on entry (cv[k] becomes its new code)
+            unsigned live0 = 0u;
+            // the field frame's origin relative to the conductor map's
+            const int fsh = a.H + 1 - kFieldFrame;
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 const int c = cv[k];
                 bool alive = false;
-                int ci = 0, cj = 0;
+                int ci = 0, cj = 0, lx = -1, ly = -1;
                 if (c >= 0) {
                     ci = (int)((unsigned)c >> 16);
                     cj = c & 0xFFFF;
+                    lx = map_rel(ci, a.c0i, g.nx, g.px);
+                    ly = map_rel(cj, a.c0j, g.ny, g.py);
                     alive = true;
+                    live0 |= 1u << k;
                     if (PUSH) {
                         // the corner fields of this particle's cell only (fewer
                         // live registers than gathering all four first)
                         float4 ea, eb;
-                        cell_fields(a, sE, e0i, e0j, EW, EH, c, ea, eb);
+                        cell_fields_l(a, sE, fsh, EW, EH, lx, ly, ci, cj, ea, eb);
                         int dead, ei, ej;
                         float ux, uy, nxo, nyo;
-                        alive = push_core(a, xv[k], yv[k], uxv[k], uyv[k], ea, eb, ci, cj, dead,
-                                          ei, ej, ux, uy, nxo, nyo);
+                        alive = push_core_l(a, xv[k], yv[k], uxv[k], uyv[k], ea, eb, ci, cj, lx, ly,
+                                            dead, ei, ej, ux, uy, nxo, nyo);
                         uxv[k] = ux;
                         uyv[k] = uy;
                         if (!alive) {
-                            a.cell[v + k] = -1 - dead;
+                            cv[k] = -1 - dead;
                             record_hit(a, tl, dead, ei, ej, ux, uy);
                         } else {
-                            const int nc = (int)(((unsigned)ei << 16) | (unsigned)ej);
-                            if (nc != c) a.cell[v + k] = nc;
+                            cv[k] = (int)(((unsigned)ei << 16) | (unsigned)ej);
                             xv[k] = nxo;
                             yv[k] = nyo;
                             ci = ei;
@@ -2489,10 +2680,13 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                     }
                 }
                 alv[k] = alive;
-                deposit_lane<MERGE>(a, mA, mB, lane, alive, ci, cj, xv[k], yv[k], i0, j0, WX, WY, nfb);
+                deposit_lane_l<MERGE>(a, mA, mB, lane, alive, ci, cj, xv[k], yv[k], lx - 1, ly - 1, WX, WY,
+                                      nfb);
             }
             if (PUSH) {
                 if (full) {
+                    // every code of the vector (unchanged ones rewritten as read)
+                    st_nt_i4(a.cell + v, cv[0], cv[1], cv[2], cv[3]);
                     st_nt_f4(a.vx + v, uxv[0], uxv[1], uxv[2], uxv[3]);
                     st_nt_f4(a.vy + v, uyv[0], uyv[1], uyv[2], uyv[3]);
                     st_nt_f4(a.ox + v, xv[0], xv[1], xv[2], xv[3]);
@@ -2500,7 +2694,8 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                 } else {
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
-                        if (cv[k] < 0) continue;          // outside the range, or removed earlier
+                        if (!((live0 >> k) & 1u)) continue;   // outside the range, or removed earlier
+                        a.cell[v + k] = cv[k];
                         a.vx[v + k] = uxv[k];
                         a.vy[v + k] = uyv[k];
                         if (alv[k]) {
