@@ -2014,6 +2014,9 @@ struct PK {
     // (the block's deposit window and a one-cell frame; CW = 0: none)
     const uint8_t *scc;
     int c0i, c0j, CW, CH;
+    // the same origin taken into [0, n) on a periodic axis, and the wrap
+    // length of each axis (n when periodic, 0 when bounded)
+    int c0wi, c0wj, nwx, nwy;
 };
 
 __device__ __forceinline__ PK resolve(const PushArgs &a)
@@ -2021,6 +2024,7 @@ __device__ __forceinline__ PK resolve(const PushArgs &a)
     PK k;
     k.scc = nullptr;
     k.c0i = k.c0j = k.CW = k.CH = 0;
+    k.c0wi = k.c0wj = k.nwx = k.nwy = 0;
     const int set = (int)a.info[7];
     k.g = a.g;
     k.TX = a.TX;
@@ -2365,22 +2369,27 @@ __device__ __forceinline__ void deposit_lane(const PK &a, unsigned long long *mA
 }
 
 // ---- block-local cell coordinates -------------------------------------------
-// A particle's cell relative to the origin (c0i, c0j) of the block's conductor
-// map, taken into [0, n) on a periodic axis.  The field frame and the deposit
-// window are fixed shifts of the same origin, so one wrapped coordinate serves
-// all three LDS copies, and a step of the walk is one add.  An LDS copy holds
-// the cell (origin + l) mod n at index l, so any representative of the cell
-// modulo n that lands inside a copy reads the right entry.
-__device__ __forceinline__ int map_rel(int c, int c0, int n, int per)
+// A particle's cell relative to the origin of the block's conductor map,
+// taken into [0, n) on a periodic axis (c0w: the origin already in [0, n)
+// there, nw = n; on a bounded axis c0w is the origin and nw = 0).  The field
+// frame and the deposit window are fixed shifts of the same origin, so one
+// wrapped coordinate serves all three LDS copies, and a step of the walk is
+// one add.  An LDS copy holds the cell (origin + l) mod n at index l, so any
+// representative of the cell modulo n that lands inside a copy reads the
+// right entry.  Selects, not branches: the wrap costs the same on every lane.
+__device__ __forceinline__ int map_rel(int c, int c0w, int nw)
 {
-    int l = c - c0;
-    if (per) { if (l < 0) l += n; else if (l >= n) l -= n; }
+    int l = c - c0w;
+    l += l < 0 ? nw : 0;
     return l;
 }
 
-__device__ __forceinline__ int wrap_step(int c, int n, int per)
+// A cell index one step from a valid one, back into [0, n) on a periodic
+// axis (nw = n; nw = 0 leaves a bounded axis's index as it is).
+__device__ __forceinline__ int wrap_step(int c, int n, int nw)
 {
-    if (per) { if (c < 0) c += n; else if (c >= n) c -= n; }
+    c += c < 0 ? nw : 0;
+    c -= c >= n ? nw : 0;
     return c;
 }
 
@@ -2390,11 +2399,12 @@ __device__ __forceinline__ int wrap_step(int c, int n, int per)
 // LDS map holds 1 for cells outside a bounded axis, so both tests agree.
 __device__ __forceinline__ bool step_blocked(const PK &a, int lx, int ly, int gi, int gj)
 {
-    if ((unsigned)lx < (unsigned)a.CW && (unsigned)ly < (unsigned)a.CH) return a.scc[lx * a.CH + ly] != 0;
+    if ((unsigned)lx < (unsigned)a.CW && (unsigned)ly < (unsigned)a.CH)
+        return a.scc[__umul24((unsigned)lx, (unsigned)a.CH) + ly] != 0;
     const Geom &g = a.g;
-    if (g.px) gi = wrap_step(gi, g.nx, 1);
+    if (g.px) gi = wrap_step(gi, g.nx, g.nx);
     else if (gi < 0 || gi >= g.nx) return true;
-    if (g.py) gj = wrap_step(gj, g.ny, 1);
+    if (g.py) gj = wrap_step(gj, g.ny, g.ny);
     else if (gj < 0 || gj >= g.ny) return true;
     return a.cell_cond[(long long)gi * g.ny + gj] != 0;
 }
@@ -2449,16 +2459,16 @@ __device__ __forceinline__ bool push_core_l(const PK &a, float x0, float y0, flo
                 dead = gox ? (sx > 0 ? 0 : 1) : (sy > 0 ? 2 : 3);
             } else if (both && step_blocked(a, lx + sx, ly + sy, ci + sx, cj + sy)) {
                 dead = gox ? (sy > 0 ? 2 : 3) : (sx > 0 ? 0 : 1);
-                ei = wrap_step(ci + d1x, g.nx, g.px);
-                ej = wrap_step(cj + d1y, g.ny, g.py);
+                ei = wrap_step(ci + d1x, g.nx, a.nwx);
+                ej = wrap_step(cj + d1y, g.ny, a.nwy);
             }
             if (dead >= 0) {
                 const bool inbox = ei >= a.box_i_top && ej >= a.box_j_lo && ej < a.box_j_hi;
                 dead += inbox ? 4 : 0;
                 return false;
             }
-            ei = wrap_step(ci + sx, g.nx, g.px);
-            ej = wrap_step(cj + sy, g.ny, g.py);
+            ei = wrap_step(ci + sx, g.nx, a.nwx);
+            ej = wrap_step(cj + sy, g.ny, a.nwy);
         } else {
             walk_cells(a, x0, y0, Dx, Dy, sx, sy, dead, ei, ej);
             if (dead >= 0) return false;
@@ -2480,7 +2490,7 @@ __device__ __forceinline__ void cell_fields_l(const PK &a, const float4 *sE, int
 {
     const int li = lx - sh, lj = ly - sh;
     if ((unsigned)li < (unsigned)EW && (unsigned)lj < (unsigned)EH) {
-        const int m = 2 * (li * EH + lj);
+        const int m = 2 * (int)(__umul24((unsigned)li, (unsigned)EH) + lj);
         ea = sE[m];
         eb = sE[m + 1];
     } else {
@@ -2500,16 +2510,18 @@ __device__ __forceinline__ void deposit_lane_l(const PK &a, unsigned long long *
     int key = -1;
     unsigned ux = 0, uy = 0;
     if (alive) {
-        ux = (unsigned)floorf(x0 * 65536.0f);
-        uy = (unsigned)floorf(y0 * 65536.0f);
+        // offsets lie in [0, 1): truncation is the floor
+        ux = (unsigned)(x0 * 65536.0f);
+        uy = (unsigned)(y0 * 65536.0f);
         if ((unsigned)wi < (unsigned)WX && (unsigned)wj < (unsigned)WY) {
-            key = wi * WY + wj;
+            key = (int)__umul24((unsigned)wi, (unsigned)WY) + wj;
         } else {
             deposit_global(a.rho, a.g, ci, cj, ux, uy);
             nfb++;
         }
     }
-    const unsigned m3 = ux * uy;
+    // both factors below 2^16: the 24-bit product is exact
+    const unsigned m3 = __umul24(ux, uy);
     if (MERGE > 0) {
         unsigned long long pend = __ballot(key >= 0);
         for (int it = 0; it < MERGE && pend; it++) {
@@ -2574,6 +2586,10 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
     a.scc = scc;
     a.c0i = i0 - 1;
     a.c0j = j0 - 1;
+    a.nwx = aa.g.px ? aa.g.nx : 0;
+    a.nwy = aa.g.py ? aa.g.ny : 0;
+    a.c0wi = a.nwx ? ((a.c0i % a.nwx) + a.nwx) % a.nwx : a.c0i;
+    a.c0wj = a.nwy ? ((a.c0j % a.nwy) + a.nwy) % a.nwy : a.c0j;
     a.CW = PUSH ? WX + 2 : 0;
     a.CH = WY + 2;
     const int tid = threadIdx.x;
@@ -2652,8 +2668,8 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                 if (c >= 0) {
                     ci = (int)((unsigned)c >> 16);
                     cj = c & 0xFFFF;
-                    lx = map_rel(ci, a.c0i, g.nx, g.px);
-                    ly = map_rel(cj, a.c0j, g.ny, g.py);
+                    lx = map_rel(ci, a.c0wi, a.nwx);
+                    ly = map_rel(cj, a.c0wj, a.nwy);
                     alive = true;
                     live0 |= 1u << k;
                     if (PUSH) {
