@@ -2556,13 +2556,29 @@ __device__ __forceinline__ void deposit_lane_l(const PK &a, unsigned long long *
 // so runs of particles in one cell cost one LDS atomic per cell.
 // Particles that drifted beyond the window add their four corner weights to
 // global memory directly.  The window is flushed to the node charge at the end.
+// The dispatcher hands blocks to the 8 XCDs in turn (block b to XCD b mod 8),
+// each with its own L2.  In every group of 8 K blocks this gives XCD x the K
+// consecutive table entries x K .. x K + K - 1 (a bijection on [0, G); a last,
+// partial group is split the same way), so the blocks of one tile, which read
+// the same field frame and conductor map, mostly share an L2, while every XCD
+// still gets an equal share of each group.
+__device__ __forceinline__ int xcd_swizzle(int b, int G)
+{
+    constexpr int K = 16;
+    const int base = b / (8 * K) * (8 * K);
+    const int n = min(8 * K, G - base);
+    const int o = b - base, x = o & 7, q = n >> 3, r = n & 7;
+    return base + (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (o >> 3);
+}
+
 template <bool PUSH, int U, int MERGE>
 __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_push(const PushArgs *A, Tab t)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int ku = unit_of(t, (int)blockIdx.x);
+    const int bid = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
+    const int ku = unit_of(t, bid);
     const PushArgs &aa = A[t.id[ku]];
-    const int lb = (int)blockIdx.x - t.boff[ku];
+    const int lb = bid - t.boff[ku];
     if ((long long)lb >= aa.info[1]) return;
     const int4 ent = aa.table[lb];
     PK a = resolve(aa);
