@@ -313,6 +313,12 @@ struct pic_ctx {
     // solver control
     bool have_prev = false;
     int pass_chunk[2] = {12, 12};   // inner iterations per pass (first pass, later passes)
+    // re-binning inside pic_step: queued on a stream of its own behind the
+    // push, so that it runs beside the next step's solve (which leaves most
+    // CUs idle); the next push, and every entry point, waits for it
+    hipStream_t bin_stream = nullptr;
+    hipEvent_t ev_bin_go = nullptr, ev_bin_done = nullptr;
+    bool bin_pending = false;
     // graphs
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> outer_graphs;   // CG passes by K; sweep chunks by kSweepKey + count
@@ -998,6 +1004,15 @@ void enqueue_push(pic_ctx *c, hipStream_t s, bool timed)
     enqueue_assemble(c, s);
 }
 
+// The caller's stream waits for a re-binning still running on the side
+// stream (no host wait).
+void join_bin(pic_ctx *c)
+{
+    if (!c->bin_pending) return;
+    (void)hipStreamWaitEvent(c->stream, c->ev_bin_done, 0);
+    c->bin_pending = false;
+}
+
 int sorts_due(pic_ctx *c, long long step_after)
 {
     int mask = 0;
@@ -1008,14 +1023,30 @@ int sorts_due(pic_ctx *c, long long step_after)
     return mask;
 }
 
-pic_status do_push(pic_ctx *c)
+// side: a re-binning that falls due may run on the side stream until the
+// next push (pic_step's loop, whose solve in between touches no particle).
+pic_status do_push(pic_ctx *c, bool side = false)
 {
     pic_status st = ensure_vwindow(c, c->step + 1, 1);
     if (st != PIC_OK) return st;
+    join_bin(c);
     enqueue_push(c, c->stream, true);
     c->step++;
     const int mask = sorts_due(c, c->step);
-    if (mask) enqueue_bin(c, mask, c->stream);
+    if (mask && side) {
+        if (!c->bin_stream) {
+            HIPCHK(c, hipStreamCreateWithFlags(&c->bin_stream, hipStreamNonBlocking));
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_bin_go, hipEventDisableTiming));
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_bin_done, hipEventDisableTiming));
+        }
+        HIPCHK(c, hipEventRecord(c->ev_bin_go, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->bin_stream, c->ev_bin_go, 0));
+        enqueue_bin(c, mask, c->bin_stream);
+        HIPCHK(c, hipEventRecord(c->ev_bin_done, c->bin_stream));
+        c->bin_pending = true;
+    } else if (mask) {
+        enqueue_bin(c, mask, c->stream);
+    }
     HIPCHK(c, hipGetLastError());
     return PIC_OK;
 }
@@ -1024,6 +1055,7 @@ pic_status check(pic_ctx *c)
 {
     if (!c || !c->d_inst) return fail(c, PIC_ERR_STATE, "not initialised");
     if (c->device_error) return PIC_ERR_STATE;     // the message of the first report stays
+    join_bin(c);
     return PIC_OK;
 }
 
@@ -1532,10 +1564,14 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps)
     if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps < 0");
     for (int k = 0; k < nsteps; k++) {
         pic_status st = do_solve(c, c->in[0].cfg.warm_start == 1 ? 3 : 1, nullptr);
-        if (st != PIC_OK) return st;
-        st = do_push(c);
-        if (st != PIC_OK) return st;
+        if (st == PIC_OK) st = do_push(c, true);
+        if (st != PIC_OK) {
+            join_bin(c);
+            return st;
+        }
     }
+    // work the caller queues next (particle views included) follows the re-binning
+    join_bin(c);
     return PIC_OK;
 }
 
@@ -1798,10 +1834,14 @@ void pic_destroy(pic_ctx *c)
 {
     if (!c) return;
     if (c->d_inst) (void)hipStreamSynchronize(c->stream);
+    if (c->bin_stream) (void)hipStreamSynchronize(c->bin_stream);
     for (auto &kv : c->outer_graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : c->chunk_graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->bin_stream) (void)hipStreamDestroy(c->bin_stream);
+    if (c->ev_bin_go) (void)hipEventDestroy(c->ev_bin_go);
+    if (c->ev_bin_done) (void)hipEventDestroy(c->ev_bin_done);
     for (auto e : c->ev0) if (e) (void)hipEventDestroy(e);
     for (auto e : c->ev1) if (e) (void)hipEventDestroy(e);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
