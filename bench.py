@@ -133,7 +133,9 @@ def flops_per_inference(H, W):
 def learned_start(w, pic, parts, args):
     """The learned warm start (residual learning): the network corrects the
     K-point polynomial extrapolation in time of the last K potentials (K =
-    args.learn_stencil; K = 4: 4 phi_1 - 6 phi_2 + 4 phi_3 - phi_4), at full
+    args.learn_stencil; K = 4: 4 phi_1 - 6 phi_2 + 4 phi_3 - phi_4; with
+    args.learn_fit = D the least-squares polynomial of degree D through
+    them), at full
     resolution (f = 1) or on f x f blocks of nodes (block means of the
     residual in, a block-mean correction out, prolonged bilinearly onto the
     nodes).  Training samples come from this trench run (after the timed
@@ -153,13 +155,13 @@ def learned_start(w, pic, parts, args):
     from paper_1610_03918_amd.unet import UNet
     dev = torch.device("cuda:0")
     f = args.learn_factor
-    K = args.learn_stencil
+    K = args.learn_stencil if args.learn_fit is None else (args.learn_stencil, args.learn_fit)
     H, W = learned.window(w, f)
     per = (int(w.periodic_x), int(w.periodic_y))
     t0 = time.perf_counter()
     # scales: powers of two near the inverse RMS of the residual and of the gap
     probe = []
-    learned.run_and_sample(pic, 12 + K, {}, (1.0, 1.0, 1.0), keep=probe, f=f, K=K)
+    learned.run_and_sample(pic, 12 + learned.points_of(K), {}, (1.0, 1.0, 1.0), keep=probe, f=f, K=K)
     stats = torch.zeros(3, dtype=torch.float64, device=dev)
     x = torch.empty((H, W, 3), dtype=torch.bfloat16, device=dev)
     tt = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
@@ -201,7 +203,7 @@ def learned_start(w, pic, parts, args):
             else:
                 stores[k] = learned.SampleStore(torch, dev, k[0], k[1], c)
         before = sum(s_.n for s_ in stores.values())
-        learned.run_and_sample_batch(sw, args.learn_sweep_steps + K, stores, sc, f=f, K=K)
+        learned.run_and_sample_batch(sw, args.learn_sweep_steps + learned.points_of(K), stores, sc, f=f, K=K)
         n_sweep = sum(s_.n for s_ in stores.values()) - before
         sw.close()
         del sw
@@ -233,7 +235,7 @@ def learned_start(w, pic, parts, args):
     bound = learned.coarse_bound(cg, problems[:args.learn_bound_problems], (4, 8, 16), torch, K=K)
     cg.close()
     log(f"  exact coarse targets (mean iterations): {bound}")
-    kinds = ("cold", "prev", "ext", "base", "learned") if K > 2 else ("cold", "prev", "ext", "learned")
+    kinds = ("cold", "prev", "ext", "base", "learned") if K != 2 else ("cold", "prev", "ext", "learned")
     for r in rows:
         log("  " + " | ".join(f"{k} {r[k]['iterations']} it {r[k]['ms']:.1f} ms (relres0 {r[k]['relres0']:.2g})"
                               for k in kinds) + f" | max diff {r['max_diff']:.2e}")
@@ -243,15 +245,19 @@ def learned_start(w, pic, parts, args):
 
     fl = flops_per_inference(H, W)
     tf = fl / (fwd_ms * 1e-3) / 1e12
-    stencil = {2: "2 phi_(n-1) - phi_(n-2)", 3: "3 phi_(n-1) - 3 phi_(n-2) + phi_(n-3)",
-               4: "4 phi_(n-1) - 6 phi_(n-2) + 4 phi_(n-3) - phi_(n-4)"}.get(K, f"the {K}-point extrapolation")
+    if isinstance(K, tuple):
+        stencil = f"the least-squares polynomial of degree {K[1]} through the last {K[0]} potentials"
+    else:
+        stencil = {2: "2 phi_(n-1) - phi_(n-2)", 3: "3 phi_(n-1) - 3 phi_(n-2) + phi_(n-3)",
+                   4: "4 phi_(n-1) - 6 phi_(n-2) + 4 phi_(n-3) - phi_(n-4)"}.get(K, f"the {K}-point extrapolation")
     return {
         "solver": f"plain masked CG (float64 refinement of float32 CG), rtol {w.rtol:g}",
         "start": (f"coarse residual learning: the network maps block means ({f}x{f} nodes) of the residual of "
                   f"the start {stencil} to a block-mean correction, prolonged bilinearly onto the free nodes"
                   if f > 1 else f"residual learning: network(residual of the start {stencil}) corrects that start"),
         "factor": f,
-        "stencil_points": K,
+        "stencil_points": learned.points_of(K),
+        "stencil_degree": K[1] if isinstance(K, tuple) else K - 1,
         "problems_evaluated": len(rows),
         **{k: {"iterations": mean(k, "iterations"), "ms": mean(k, "ms"),
                "relres0": float(np.median([r[k]["relres0"] for r in rows]))} for k in kinds},
@@ -260,7 +266,7 @@ def learned_start(w, pic, parts, args):
         "iterations_cold_over_ext": mean("cold", "iterations") / mean("ext", "iterations"),
         **({"iterations_cold_over_base": mean("cold", "iterations") / mean("base", "iterations"),
             "iterations_base_over_learned": mean("base", "iterations") / mean("learned", "iterations")}
-           if K > 2 else {}),
+           if K != 2 else {}),
         "ms_cold_over_learned": mean("cold", "ms") / mean("learned", "ms"),
         "target_cold_over_learned": 3.0,
         "coarse_exact_target_iterations": {
@@ -636,6 +642,9 @@ def main():
     ap.add_argument("--learn-batch", type=int, default=4, help="batch, in trench-window images")
     ap.add_argument("--learn-rate", type=float, default=2e-3, help="Adam's initial learning rate")
     ap.add_argument("--learn-evals", type=int, default=20, help="held-out problems")
+    ap.add_argument("--learn-fit", type=int, default=None,
+                    help="degree of a least-squares polynomial through the --learn-stencil points "
+                         "(default: the polynomial through all of them)")
     ap.add_argument("--learn-stencil", type=int, default=4,
                     help="points of the polynomial extrapolation in time the network corrects (2: linear)")
     args = ap.parse_args()

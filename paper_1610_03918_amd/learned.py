@@ -33,12 +33,24 @@ def window(w, f=1):
     return (w.NX // f // 8) * 8, (w.NY // f // 8) * 8
 
 
+def points_of(K):
+    """Past potentials a start stencil reads: K, or the first entry of a
+    (points, degree) pair."""
+    return K[0] if isinstance(K, tuple) else K
+
+
 def start_of(hist, K, out):
-    """The K-point extrapolation of the history (hist[0] the latest
-    potential) into out, computed by the library; with fewer than K earlier
-    potentials, the extrapolation of those there are."""
-    k = min(K, len(hist))
-    extrapolate(hist[:k], extrapolation_coefficients(k), out)
+    """The extrapolation of the history (hist[0] the latest potential) into
+    out, computed by the library.  K: the points of the polynomial through
+    the last K potentials, or (points, degree) for the least-squares
+    polynomial of that degree through more points.  With fewer potentials
+    than the stencil reads, the interpolation through those there are."""
+    n = points_of(K)
+    if len(hist) < n or not isinstance(K, tuple):
+        k = min(n, len(hist))
+        extrapolate(hist[:k], extrapolation_coefficients(k), out)
+    else:
+        extrapolate(hist[:n], extrapolation_coefficients(n, K[1]), out)
     return out
 
 
@@ -96,16 +108,16 @@ def run_and_sample(pic, steps, stores, scales, keep=None, every=1, f=1, K=2):
         info = pic.pic_solve(3)
         infos.append(info)
         phi = pic.phi.clone()
-        if len(hist) >= K and k % every == 0:
+        if len(hist) >= points_of(K) and k % every == 0:
             if keep is not None:
-                keep.append((pic.b.clone(), list(hist[:K]), phi))
+                keep.append((pic.b.clone(), list(hist[:points_of(K)]), phi))
             else:
                 st = stores.get((H, W))
                 if st is not None and not st.full():
                     start_of(hist, K, s)
                     sample(f, pic.b, s, s, phi, nm, per, H, W, scales, st.x[st.n], st.t[st.n])
                     st.n += 1
-        hist = ([phi] + hist)[:max(K, 2)]
+        hist = ([phi] + hist)[:max(points_of(K), 2)]
         pic.pic_push()
     pic._phi_hist = hist
     return infos
@@ -121,7 +133,7 @@ def run_and_sample_batch(batch, steps, stores, scales, f=1, K=2):
         batch.pic_solve(3)
         for i, w in enumerate(batch.ws):
             phi = batch.phi(i).clone()
-            if len(hist[i]) >= K:
+            if len(hist[i]) >= points_of(K):
                 H, W = window(w, f)
                 st = stores.get((H, W))
                 if st is not None and not st.full():
@@ -129,7 +141,7 @@ def run_and_sample_batch(batch, steps, stores, scales, f=1, K=2):
                     sample(f, batch.b(i), s, s, phi, nms[i],
                            (int(w.periodic_x), int(w.periodic_y)), H, W, scales, st.x[st.n], st.t[st.n])
                     st.n += 1
-            hist[i] = ([phi] + hist[i])[:max(K, 2)]
+            hist[i] = ([phi] + hist[i])[:max(points_of(K), 2)]
         batch.pic_push()
     batch._phi_hist = hist
 
@@ -220,7 +232,7 @@ def evaluate(pic_cg, net, problems, scales, torch, f=1, K=2):
         prev = timed(lambda: pic_cg.pic_solve(1))
         ext = timed(lambda: ext_start(2))
         row = {"cold": cold, "prev": prev, "ext": ext}
-        if K > 2:
+        if K != 2:
             row["base"] = timed(lambda: ext_start(K))
         row["learned"] = timed(learned_start)
         row["max_diff"] = float(((pic_cg.phi - phi_cold) * free).abs().max())

@@ -313,10 +313,21 @@ class UNet:
         return loss
 
 
-def extrapolation_coefficients(K):
-    """Coefficients of the K-point polynomial extrapolation to the next step,
-    latest solution first: (-1)^(k+1) binomial(K, k), k = 1 .. K."""
-    return [float((-1) ** (k + 1) * math.comb(K, k)) for k in range(1, K + 1)]
+def extrapolation_coefficients(K, degree=None):
+    """Coefficients of the extrapolation to the next step from the last K
+    solutions, latest first.  degree None (or K - 1): the polynomial through
+    all K, (-1)^(k+1) binomial(K, k), k = 1 .. K.  A lower degree: the value
+    at the next step of the least-squares polynomial of that degree through
+    the K solutions at steps -1 .. -K, e0^T (V^T V)^-1 V^T with V the
+    Vandermonde matrix of those steps."""
+    if degree is None or degree == K - 1:
+        return [float((-1) ** (k + 1) * math.comb(K, k)) for k in range(1, K + 1)]
+    if not 0 <= degree < K:
+        raise ValueError("degree must lie in 0 .. K - 1")
+    import numpy as np
+    t = -np.arange(1, K + 1, dtype=np.float64)
+    V = np.vander(t, degree + 1, increasing=True)
+    return [float(x) for x in np.linalg.solve(V.T @ V, V.T)[0]]
 
 
 def extrapolate(phis, coefs, out, stream=None):
