@@ -182,6 +182,34 @@ def test_sorting_does_not_change_results():
     b.close()
 
 
+def test_overlapped_rebinning_matches_one_stream_steps():
+    """pic_step queues a re-binning that falls due on a stream of its own,
+    beside the next step's solve; stepping with pic_solve and pic_push keeps
+    one stream.  From identical loads both give the same particle multisets,
+    charge, potential and counters, read right after each call (the views
+    follow the re-binning), with re-binnings every 2 and 3 steps falling
+    inside and at the end of the pic_step calls."""
+    w = synth.workload_for_tests("trench")
+    parts = synth.load(w)
+    a = make(w, parts, rtol=1e-10, sort_interval=(2, 3))
+    b = make(w, parts, rtol=1e-10, sort_interval=(2, 3))
+    a.start()
+    b.start()
+    for n in (1, 2, 3, 5):
+        a.pic_step(n)
+        for _ in range(n):
+            b.pic_solve(3)
+            b.pic_push()
+        for s in range(2):
+            assert np.array_equal(canonical(live(a.particles_numpy(s))), canonical(live(b.particles_numpy(s)))), (n, s)
+            assert np.array_equal(a.rho(s).cpu().numpy(), b.rho(s).cpu().numpy()), (n, s)
+        assert np.array_equal(a.phi.cpu().numpy(), b.phi.cpu().numpy()), n
+        da, db = a.pic_diagnostics(), b.pic_diagnostics()
+        assert da["tally"] == db["tally"] and da["alive"] == db["alive"] and da["step"] == db["step"], n
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("kind", ["bounded", "trench"])
 def test_short_run_tracks_oracle(kind):
     """Ten full steps on both sides (GPU iterative solve to 1e-12 vs exact
