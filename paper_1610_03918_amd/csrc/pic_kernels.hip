@@ -304,7 +304,8 @@ __device__ __forceinline__ float2 node_field(const Geom g, const uint8_t *nc, co
     return make_float2((float)ex, (float)ey);
 }
 
-// One thread per cell; writes the cell's four corner fields (float32) and,
+// One thread per cell; writes the cell's four corner fields (float32, each
+// node's computed once per block) and,
 // when requested (the field of a push), clears both species' node charge for
 // the coming deposit.  The field of a push also counts, in F_UNCONV, a
 // potential whose last residual test failed, and keeps the largest such
@@ -324,15 +325,23 @@ __global__ void k_field(const Inst *insts, Tab t, int zero_rho)
         I.rho[0][n] = 0ull;
         I.rho[1][n] = 0ull;
     }
-    if (i >= g.nx || j >= g.ny) return;
-    const int i1 = g.px ? wrap_hi(i + 1, g.nx) : i + 1;
-    const int j1 = g.py ? wrap_hi(j + 1, g.ny) : j + 1;
+    // the field of each node of the block's (kGridBY + 1) x (kGridBX + 1)
+    // corner set, once, in LDS; a periodic axis wraps the far row / column
     const uint8_t *nc = I.node_cond;
     const double *phi = I.phi;
-    float2 e00 = node_field(g, nc, phi, i, j);
-    float2 e10 = node_field(g, nc, phi, i1, j);
-    float2 e01 = node_field(g, nc, phi, i, j1);
-    float2 e11 = node_field(g, nc, phi, i1, j1);
+    __shared__ float2 sn[kGridBY + 1][kGridBX + 1];
+    const int ti = (int)threadIdx.y, tj = (int)threadIdx.x;
+    auto node_at = [&](int a, int b) {
+        if (g.px && a >= g.NX) a %= g.NX;
+        if (g.py && b >= g.NY) b %= g.NY;
+        return (a < g.NX && b < g.NY) ? node_field(g, nc, phi, a, b) : make_float2(0.f, 0.f);
+    };
+    sn[ti][tj] = node_at(i, j);
+    if (ti == 0) sn[kGridBY][tj] = node_at(i - ti + kGridBY, j);
+    if (ti == 1 && tj <= kGridBY) sn[tj][kGridBX] = node_at(i - ti + tj, j - tj + kGridBX);
+    __syncthreads();
+    if (i >= g.nx || j >= g.ny) return;
+    const float2 e00 = sn[ti][tj], e10 = sn[ti + 1][tj], e01 = sn[ti][tj + 1], e11 = sn[ti + 1][tj + 1];
     const long long c = (long long)i * g.ny + j;
     I.E4[2 * c] = make_float4(e00.x, e00.y, e10.x, e10.y);
     I.E4[2 * c + 1] = make_float4(e01.x, e01.y, e11.x, e11.y);
