@@ -2658,16 +2658,22 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
             int cv[4];
             float xv[4], yv[4], uxv[4], uyv[4];
             if (full) {
+                // the wave issues its loads at raised priority, so that they
+                // leave before other waves' arithmetic
+                __builtin_amdgcn_s_setprio(3);
                 const nt_i4 c4 = ld_nt_i4(a.cell + v);
                 const nt_f4 x4 = ld_nt_f4(a.ox + v), y4 = ld_nt_f4(a.oy + v);
+                nt_f4 u4 = {0.f, 0.f, 0.f, 0.f}, w4 = u4;
+                if (PUSH) {
+                    u4 = ld_nt_f4(a.vx + v);
+                    w4 = ld_nt_f4(a.vy + v);
+                }
+                __builtin_amdgcn_s_setprio(0);
                 cv[0] = c4.x; cv[1] = c4.y; cv[2] = c4.z; cv[3] = c4.w;
                 xv[0] = x4.x; xv[1] = x4.y; xv[2] = x4.z; xv[3] = x4.w;
                 yv[0] = y4.x; yv[1] = y4.y; yv[2] = y4.z; yv[3] = y4.w;
-                if (PUSH) {
-                    const nt_f4 u4 = ld_nt_f4(a.vx + v), w4 = ld_nt_f4(a.vy + v);
-                    uxv[0] = u4.x; uxv[1] = u4.y; uxv[2] = u4.z; uxv[3] = u4.w;
-                    uyv[0] = w4.x; uyv[1] = w4.y; uyv[2] = w4.z; uyv[3] = w4.w;
-                }
+                uxv[0] = u4.x; uxv[1] = u4.y; uxv[2] = u4.z; uxv[3] = u4.w;
+                uyv[0] = w4.x; uyv[1] = w4.y; uyv[2] = w4.z; uyv[3] = w4.w;
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
