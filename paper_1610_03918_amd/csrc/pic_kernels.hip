@@ -2652,23 +2652,39 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
         // loads and stores where the 4 slots lie inside [start, end) (the
         // head and tail of the range go element by element).  Slots of
         // removed particles in a full vector are written back unchanged.
+        // A pass's full vectors are loaded at the end of the pass before it,
+        // ahead of that pass's stores: the wait at the top of a pass is then
+        // for the loads alone, and their registers are not those of the
+        // stores still in flight.  The wave issues them at raised priority,
+        // so that they leave before other waves' arithmetic.
+        nt_i4 c4 = {-1, -1, -1, -1};
+        nt_f4 x4 = {0.f, 0.f, 0.f, 0.f}, y4 = x4, u4 = x4, w4 = x4;
+        auto no_pass = [&]() {
+            c4 = nt_i4{-1, -1, -1, -1};
+            x4 = y4 = u4 = w4 = nt_f4{0.f, 0.f, 0.f, 0.f};
+        };
+        auto load_pass = [&](int v) {
+            __builtin_amdgcn_s_setprio(3);
+            c4 = ld_nt_i4(a.cell + v);
+            x4 = ld_nt_f4(a.ox + v);
+            y4 = ld_nt_f4(a.oy + v);
+            if (PUSH) {
+                u4 = ld_nt_f4(a.vx + v);
+                w4 = ld_nt_f4(a.vy + v);
+            }
+            __builtin_amdgcn_s_setprio(0);
+        };
+        {
+            const int v = (start & ~3) + 4 * tid;
+            if (v >= start && v + 4 <= end) load_pass(v);
+            else no_pass();
+        }
         for (int vb = start & ~3; vb < end; vb += 4 * kPushThreads) {
             const int v = vb + 4 * tid;
             const bool full = v >= start && v + 4 <= end;
             int cv[4];
             float xv[4], yv[4], uxv[4], uyv[4];
             if (full) {
-                // the wave issues its loads at raised priority, so that they
-                // leave before other waves' arithmetic
-                __builtin_amdgcn_s_setprio(3);
-                const nt_i4 c4 = ld_nt_i4(a.cell + v);
-                const nt_f4 x4 = ld_nt_f4(a.ox + v), y4 = ld_nt_f4(a.oy + v);
-                nt_f4 u4 = {0.f, 0.f, 0.f, 0.f}, w4 = u4;
-                if (PUSH) {
-                    u4 = ld_nt_f4(a.vx + v);
-                    w4 = ld_nt_f4(a.vy + v);
-                }
-                __builtin_amdgcn_s_setprio(0);
                 cv[0] = c4.x; cv[1] = c4.y; cv[2] = c4.z; cv[3] = c4.w;
                 xv[0] = x4.x; xv[1] = x4.y; xv[2] = x4.z; xv[3] = x4.w;
                 yv[0] = y4.x; yv[1] = y4.y; yv[2] = y4.z; yv[3] = y4.w;
@@ -2729,6 +2745,13 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(6)
                 alv[k] = alive;
                 deposit_lane_l<MERGE>(a, mA, mB, lane, alive, ci, cj, xv[k], yv[k], lx - 1, ly - 1, WX, WY,
                                       nfb);
+            }
+            {
+                // the next pass's vectors (slots v + 1024 .. v + 1027 lie at or
+                // after start, so full means inside [start, end))
+                const int vn = v + 4 * kPushThreads;
+                if (vn + 4 <= end) load_pass(vn);
+                else no_pass();
             }
             if (PUSH) {
                 if (full) {
