@@ -239,7 +239,11 @@ pic_status pic_rewind(pic_ctx *ctx);
 pic_status pic_push(pic_ctx *ctx);
 
 /* nsteps x (pic_solve started as cfg.warm_start selects; pic_push).  Stops
- * at the first failing solve and returns its status. */
+ * at the first failing solve and returns its status.  A re-binning that falls
+ * due inside the loop runs on a stream the library owns (default priority),
+ * beside the next step's solve; the next push waits for it, and on return
+ * the context's stream is ordered after it (no host wait), so work the caller
+ * queues on that stream, particle reads included, sees the re-binned state. */
 pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
 
 /* Waits for the stream and copies counters to the host. */
