@@ -340,6 +340,9 @@ pic_status pic_node_map(pic_ctx *ctx, int32_t i, const uint8_t **node_cond, uint
  * pic_diagnostics) returns PIC_ERR_STATE, and every later call does too. */
 pic_status pic_inject_fault(pic_ctx *ctx, int32_t what);
 
+/* Waits for the context's stream and the library's own streams, then frees
+ * the context's host objects and graphs.  The caller frees the buffers and
+ * workspace it passed in afterwards.  NULL is ignored. */
 void pic_destroy(pic_ctx *ctx);
 const char *pic_last_error(const pic_ctx *ctx);
 const char *pic_version(void);
