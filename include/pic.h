@@ -31,7 +31,10 @@
  *
  * Streams: every call is enqueued on the stream given to pic_init and
  * returns without waiting, except where stated (pic_solve, pic_step and
- * pic_diagnostics wait for the convergence test / copy-back).
+ * pic_diagnostics wait for the convergence test / copy-back).  The library
+ * also owns two streams of default priority: one to capture HIP graphs, and
+ * one on which pic_step runs a re-binning beside the next solve (joined to
+ * the context's stream before pic_step returns, see there).
  *
  * Errors: every call returns a pic_status; on failure pic_last_error gives
  * a message.  No exception or abort crosses this boundary.  A context is not
